@@ -1,0 +1,75 @@
+"""Closed-form integrals of the test integrands -- TEST INFRASTRUCTURE ONLY.
+
+I_d(f) of (2.1), on the unit cube, for the three families, in mpmath at 40
+significant digits.  These are the exact integrals, not the Smolyak values:
+they pin the quadrature only where its truncation error is small.
+"""
+from __future__ import annotations
+
+import mpmath as mp
+import numpy as np
+
+mp.mp.dps = 40
+
+
+def exact_exp_sum(c) -> float:
+    """prod_i (e^{c_i} - 1)/c_i  (factor 1 when c_i = 0)."""
+    r = mp.mpf(1)
+    for ci in np.asarray(c, dtype=np.float64):
+        ci = mp.mpf(float(ci))
+        r *= mp.expm1(ci) / ci if ci != 0 else mp.mpf(1)
+    return r
+
+
+def exact_oscillatory(w, a):
+    """Re( e^{2 pi i w} prod_i (e^{i a_i} - 1)/(i a_i) )."""
+    z = mp.expj(2 * mp.pi * mp.mpf(float(w)))
+    for ai in np.asarray(a, dtype=np.float64):
+        ai = mp.mpf(float(ai))
+        z *= (mp.expj(ai) - 1) / (1j * ai) if ai != 0 else mp.mpf(1)
+    return mp.re(z)
+
+
+def exact_product_peak(b, u):
+    """prod_i b_i (atan(b_i (1-u_i)) + atan(b_i u_i))."""
+    r = mp.mpf(1)
+    for bi, ui in zip(np.asarray(b, dtype=np.float64), np.asarray(u, dtype=np.float64)):
+        bi = mp.mpf(float(bi))
+        ui = mp.mpf(float(ui))
+        r *= bi * (mp.atan(bi * (1 - ui)) + mp.atan(bi * ui))
+    return r
+
+
+def exact(family: str, d: int, params):
+    params = np.asarray(params, dtype=np.float64)
+    if family == "exp_sum":
+        return exact_exp_sum(params[:d])
+    if family == "oscillatory":
+        return exact_oscillatory(params[0], params[1:1 + d])
+    if family == "product_peak":
+        return exact_product_peak(params[:d], params[d:2 * d])
+    raise ValueError(family)
+
+
+def exact_grad_oscillatory(w, a) -> np.ndarray:
+    """Gradient of the exact oscillatory integral with respect to (w, a)."""
+    a = [mp.mpf(float(x)) for x in np.asarray(a, dtype=np.float64)]
+    rot = mp.expj(2 * mp.pi * mp.mpf(float(w)))
+    facs = [(mp.expj(ai) - 1) / (1j * ai) for ai in a]
+    dfacs = []
+    for ai in a:
+        # d/da (e^{ia}-1)/(ia) = (i a e^{ia} i - i (e^{ia} - 1)) / (i a)^2 ... written out:
+        # g(a) = (e^{ia} - 1)/(ia);  g'(a) = e^{ia}/a - (e^{ia} - 1)/(i a^2)
+        dfacs.append(mp.expj(ai) / ai - (mp.expj(ai) - 1) / (1j * ai * ai))
+    total = rot
+    for f in facs:
+        total *= f
+    g = np.zeros(len(a) + 1)
+    g[0] = float(mp.re(2j * mp.pi * total))
+    for t in range(len(a)):
+        z = rot * dfacs[t]
+        for s, f in enumerate(facs):
+            if s != t:
+                z *= f
+        g[1 + t] = float(mp.re(z))
+    return g

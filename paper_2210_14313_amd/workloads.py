@@ -1,0 +1,236 @@
+"""Seeded synthetic workloads: integrand batches and their parameters.
+
+This module only draws random inputs.  It holds none of the quadrature's
+arithmetic (no rules, no counts, no sums), so that the GPU path and the CPU
+oracle can both be fed from it without sharing any part of the method.
+
+Integrand families (all on the unit cube [0,1]^d, a rescaling of the paper's
+[-1,1]^d in (2.1)):
+
+* ``exp_sum``      f(x) = exp(sum_i c_i x_i)            params: c[d]
+* ``oscillatory``  f(x) = cos(2 pi w + sum_i a_i x_i)    params: w, a[d]
+* ``product_peak`` f(x) = prod_i 1/(b_i^-2 + (x_i-u_i)^2) params: b[d], u[d]
+
+The product-peak family is the integrand of Test 4 (4.4) and Table 5.8 with
+free widths and centres; exp-sum generalises (4.5)/(5.1); oscillatory
+generalises the cosine integrand of Table 5.7.
+
+A batch is a list of problems ``(d, q, rule, family, param_offset)`` plus one
+flat float64 parameter array.  Rules are named ``"cc"`` (Clenshaw-Curtis,
+(2.11)), ``"tr"`` (trapezoidal, (2.10)), ``"gl"`` (Gauss-Legendre with 2l-1
+points at level l) and ``"gl_paper"`` (Gauss-Legendre with l points at level
+l, (2.13)).  The level q is the q of (2.6); the excess budget is K = q - d.
+
+Random numbers come from ``numpy.random.default_rng(seed)`` (PCG64) and are
+drawn per integrand in a fixed order: shape choices first, then the scalar
+parameter (w), then the vectors in coordinate order (a; or b then u; or c).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Sequence
+
+import numpy as np
+
+RULES = ("tr", "cc", "gl", "gl_paper")
+FAMILIES = ("exp_sum", "oscillatory", "product_peak")
+
+#: seeds used for the five standard workloads (workload k uses SEED_BASE + k)
+SEED_BASE = 14313
+
+
+def n_params(family: str, d: int) -> int:
+    """Number of float64 parameters one integrand of ``family`` takes."""
+    if family == "exp_sum":
+        return d
+    if family == "oscillatory":
+        return d + 1
+    if family == "product_peak":
+        return 2 * d
+    raise ValueError(f"unknown family {family!r}")
+
+
+@dataclass
+class Problem:
+    d: int
+    q: int
+    rule: str
+    family: str
+    param_offset: int
+
+    @property
+    def K(self) -> int:
+        return self.q - self.d
+
+
+@dataclass
+class Batch:
+    """A batch of integrands sharing one flat parameter array."""
+
+    name: str
+    problems: List[Problem] = field(default_factory=list)
+    params: np.ndarray = field(default_factory=lambda: np.zeros(0))
+
+    def __len__(self) -> int:
+        return len(self.problems)
+
+    def param_slice(self, i: int) -> np.ndarray:
+        p = self.problems[i]
+        return self.params[p.param_offset:p.param_offset + n_params(p.family, p.d)]
+
+    def subset(self, idx: Sequence[int], name: str | None = None) -> "Batch":
+        """A new batch holding problems ``idx`` with compacted parameters."""
+        probs, chunks, off = [], [], 0
+        for i in idx:
+            p = self.problems[i]
+            v = self.param_slice(i)
+            probs.append(Problem(p.d, p.q, p.rule, p.family, off))
+            chunks.append(v)
+            off += len(v)
+        params = np.concatenate(chunks) if chunks else np.zeros(0)
+        return Batch(name or f"{self.name}[subset]", probs, params.astype(np.float64))
+
+
+class _Builder:
+    def __init__(self, name: str):
+        self.name = name
+        self.problems: List[Problem] = []
+        self.chunks: List[np.ndarray] = []
+        self.off = 0
+
+    def add(self, d: int, q: int, rule: str, family: str, params: np.ndarray):
+        assert rule in RULES and family in FAMILIES
+        params = np.asarray(params, dtype=np.float64).ravel()
+        assert params.size == n_params(family, d)
+        self.problems.append(Problem(int(d), int(q), rule, family, self.off))
+        self.chunks.append(params)
+        self.off += params.size
+
+    def build(self) -> Batch:
+        params = np.concatenate(self.chunks) if self.chunks else np.zeros(0)
+        return Batch(self.name, self.problems, params.astype(np.float64))
+
+
+def draw_params(rng: np.random.Generator, family: str, d: int,
+                osc_scale: float = 9.0, exp_scale: float = 1.0) -> np.ndarray:
+    """Draw one integrand's parameters with the standard distributions.
+
+    exp_sum: c_i ~ U(0,1) * exp_scale.  oscillatory: w ~ U(0,1),
+    a_i ~ U(0,1) * osc_scale / d.  product_peak: b_i ~ U(0.5, 2),
+    u_i ~ U(0, 1).
+    """
+    if family == "exp_sum":
+        return rng.uniform(0.0, 1.0, d) * exp_scale
+    if family == "oscillatory":
+        w = rng.uniform(0.0, 1.0)
+        a = rng.uniform(0.0, 1.0, d) * (osc_scale / d)
+        return np.concatenate([[w], a])
+    if family == "product_peak":
+        b = rng.uniform(0.5, 2.0, d)
+        u = rng.uniform(0.0, 1.0, d)
+        return np.concatenate([b, u])
+    raise ValueError(family)
+
+
+def plain_exp_d10(seed: int = SEED_BASE + 1) -> Batch:
+    """One exp-sum integrand, d=10, q=d+4, Clenshaw-Curtis, c_i ~ U(0,1)."""
+    rng = np.random.default_rng(seed)
+    b = _Builder("plain_exp_d10_q14_cc")
+    b.add(10, 14, "cc", "exp_sum", rng.uniform(0.0, 1.0, 10))
+    return b.build()
+
+
+def precision_d100(seed: int = SEED_BASE + 2) -> Batch:
+    """d=100, q=d+5, Clenshaw-Curtis: one oscillatory (w ~ U(0,1),
+    a_i ~ U(0,1)*9/d) and one product-peak (b_i ~ U(0.5,2), u_i ~ U(0,1))."""
+    rng = np.random.default_rng(seed)
+    b = _Builder("precision_d100_q105_cc")
+    d = 100
+    b.add(d, d + 5, "cc", "oscillatory", draw_params(rng, "oscillatory", d))
+    b.add(d, d + 5, "cc", "product_peak", draw_params(rng, "product_peak", d))
+    return b.build()
+
+
+def high_dim_d1000(seed: int = SEED_BASE + 3, rules: Sequence[str] = ("gl", "tr")) -> Batch:
+    """d=1000, q=d+3: exp(sum c_i x_i / d) with c_i ~ U(-1,1), once per rule.
+
+    The same c vector is used for every rule; the parameter passed to the
+    exp-sum family is c_i / d.
+    """
+    rng = np.random.default_rng(seed)
+    d = 1000
+    c = rng.uniform(-1.0, 1.0, d) / d
+    b = _Builder("high_dim_d1000_q1003")
+    for r in rules:
+        b.add(d, d + 3, r, "exp_sum", c)
+    return b.build()
+
+
+def batched_uneven(n: int = 4096, seed: int = SEED_BASE + 4,
+                   d_lo: int = 8, d_hi: int = 256, k_lo: int = 2, k_hi: int = 6,
+                   rules: Sequence[str] = ("cc", "gl"),
+                   families: Sequence[str] = ("oscillatory", "exp_sum")) -> Batch:
+    """Batch of ``n`` integrands of uneven size.
+
+    Per integrand, in this order: d ~ U{d_lo..d_hi}, K = q-d ~ U{k_lo..k_hi},
+    rule uniform over ``rules``, family uniform over ``families``, then the
+    parameters (exp-sum c_i ~ U(0,1); oscillatory w ~ U(0,1),
+    a_i ~ U(0,1)*9/d).
+    """
+    rng = np.random.default_rng(seed)
+    b = _Builder(f"batched_uneven_n{n}")
+    for _ in range(n):
+        d = int(rng.integers(d_lo, d_hi + 1))
+        K = int(rng.integers(k_lo, k_hi + 1))
+        rule = rules[int(rng.integers(0, len(rules)))]
+        fam = families[int(rng.integers(0, len(families)))]
+        b.add(d, d + K, rule, fam, draw_params(rng, fam, d))
+    return b.build()
+
+
+def gradient_osc_d200(n: int = 256, seed: int = SEED_BASE + 5, d: int = 200, K: int = 5) -> Batch:
+    """``n`` oscillatory integrands, d=200, q=d+5, Clenshaw-Curtis."""
+    rng = np.random.default_rng(seed)
+    b = _Builder(f"gradient_osc_d{d}_n{n}")
+    for _ in range(n):
+        b.add(d, d + K, "cc", "oscillatory", draw_params(rng, "oscillatory", d))
+    return b.build()
+
+
+def random_small(seed: int, n: int, d_range=(1, 6), k_range=(0, 4),
+                 rules: Sequence[str] = RULES, families: Sequence[str] = FAMILIES,
+                 osc_scale: float = 9.0, exp_scale: float = 1.0) -> Batch:
+    """Small mixed batch for parity tests (sizes the point oracle finishes fast)."""
+    rng = np.random.default_rng(seed)
+    b = _Builder(f"random_small_s{seed}")
+    for _ in range(n):
+        d = int(rng.integers(d_range[0], d_range[1] + 1))
+        K = int(rng.integers(k_range[0], k_range[1] + 1))
+        rule = rules[int(rng.integers(0, len(rules)))]
+        fam = families[int(rng.integers(0, len(families)))]
+        b.add(d, d + K, rule, fam, draw_params(rng, fam, d, osc_scale, exp_scale))
+    return b.build()
+
+
+def single(d: int, q: int, rule: str, family: str, params) -> Batch:
+    """A one-integrand batch with explicit parameters."""
+    b = _Builder(f"single_{family}_{rule}_d{d}_q{q}")
+    b.add(d, q, rule, family, np.asarray(params, dtype=np.float64))
+    return b.build()
+
+
+def concat(batches: Sequence[Batch], name: str = "concat") -> Batch:
+    b = _Builder(name)
+    for bt in batches:
+        for i, p in enumerate(bt.problems):
+            b.add(p.d, p.q, p.rule, p.family, bt.param_slice(i))
+    return b.build()
+
+
+STANDARD = {
+    "plain_exp_d10": plain_exp_d10,
+    "precision_d100": precision_d100,
+    "high_dim_d1000": high_dim_d1000,
+    "batched_uneven": batched_uneven,
+    "gradient_osc_d200": gradient_osc_d200,
+}
