@@ -1,0 +1,235 @@
+"""Benchmark: batched Smolyak quadrature on one MI355X.
+
+One step = one forward launch of the whole batched path over the
+4096-integrand uneven workload (d ~ U{8..256}, K = q-d ~ U{2..6},
+Clenshaw-Curtis / Gauss-Legendre, oscillatory / exp-sum), FP32-compensated
+per-coordinate arithmetic with FP64 sweep products, a-priori error bound
+computed for every result.  Inputs are resident in HBM before timing.
+
+Prints ONE JSON line (rank 0).  Metric: effective sparse-grid points per
+second = sum over integrands of n_d^q (points with repetition of (2.6))
+divided by the time of one step.  Extras: time-to-integral at d = 1000,
+batched vs plain per-integrand FP64 speedup at the 1e-7 accuracy target,
+the FP64 batched rate, and the accuracy against the CPU oracle.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# non-packed VALU peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA)
+# x 2.4 GHz; FP32 (without packed math) and FP64 FMAs issue at this same rate
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+PAIR_EVAL_FLOPS = 8.0   # one centred node-pair evaluation = one quarter-rate transcendental slot
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_flops(info) -> float:
+    """Flop-slots of one forward launch: pair evaluations x 8 + 2 x MACs +
+    sweep merge flops (see the plan info fields)."""
+    return PAIR_EVAL_FLOPS * info["pair_evals"] + 2.0 * info["macs"] + info["merge_flops"]
+
+
+def cpu_baseline(batch, target_points: float, threads: int):
+    """Time the point-by-point oracle on the first integrands of the batch
+    (skipping any with more than 5e8 points) until ~target_points are done."""
+    import oracle
+    from oracle import counts as OC
+    idx, total = [], 0
+    for i, p in enumerate(batch.problems):
+        n = OC.counts_by_generating_function(p.d, p.q, p.rule)["n_points_rep"]
+        if n > 5e8:
+            continue
+        idx.append((i, n))
+        total += n
+        if total >= target_points:
+            break
+    t0 = time.perf_counter()
+    done = 0
+    for i, n in idx:
+        p = batch.problems[i]
+        r = oracle.smolyak_points(p.d, p.q, p.rule, p.family, batch.param_slice(i), nthreads=threads)
+        done += r["npoints"]
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "points/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {len(idx)} integrands of the batch with n_d^q <= 5e8 "
+                      f"({done:.3e} points, {dt:.1f} s, point-by-point (2.6)-(2.7) in x87 extended precision)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", default="fp32c", choices=["fp32c", "fp64"])
+    ap.add_argument("--n", type=int, default=4096, help="integrands in the batch")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--cpu-points", type=float, default=1.5e9)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(a batch of independent integrands would be split across GPUs by cost, "
+              "with no communication); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2210_14313_amd import api, native, workloads as W
+
+    batch = W.batched_uneven(n=args.n)
+    # oracle values first (CPU, binary128) for the accuracy statement
+    log("oracle reference (binary128, threaded) ...")
+    t0 = time.perf_counter()
+    ref = oracle.batch_factorised(batch, nthreads=min(16, os.cpu_count() or 1))
+    log(f"  done in {time.perf_counter() - t0:.1f} s")
+    fam = np.array([p.family for p in batch.problems])
+    scale = np.where(fam == "oscillatory", np.maximum(np.abs(ref), 1.0), np.abs(ref))
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    params = api.params_tensor(batch, dev)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+
+    def run_plan(precision, steps, warmup, autotune):
+        plan = native.Plan(batch.problems, precision)
+        out = torch.empty(len(batch), dtype=torch.float64, device=dev)
+        bound = torch.empty_like(out)
+        if autotune:
+            plan.autotune(params, out, stream=s)
+        for _ in range(warmup):
+            plan.execute(params, out, bound, stream=s)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            ev[k][0].record(s)
+            plan.execute(params, out, bound, stream=s)
+            ev[k][1].record(s)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        kern_ms = [a.elapsed_time(b) for a, b in ev]
+        got = out.cpu().numpy()
+        bnd = bound.cpu().numpy()
+        info = plan.info()
+        plan.close()
+        return dict(ms_per_step=(t1 - t0) * 1e3 / steps, kernel_ms=float(np.mean(kern_ms)),
+                    kernel_ms_median=float(np.median(kern_ms)), got=got, bound=bnd, info=info)
+
+    log(f"timing {args.precision} batched plan: {args.steps} steps after {args.warmup} warmup")
+    main_run = run_plan(args.precision, args.steps, args.warmup, not args.no_autotune)
+    info = main_run["info"]
+    err = np.abs(main_run["got"] - ref) / scale
+    max_err = float(np.max(err))
+    bound_ok = bool(np.all(np.abs(main_run["got"] - ref) <= main_run["bound"]))
+    eff = float(info["effective_points"])
+    value = eff / (main_run["ms_per_step"] / 1e3)
+    flops = algorithmic_flops(info)
+    achieved = flops / (main_run["kernel_ms"] / 1e3) / 1e12
+    result = {
+        "metric": "sparse-grid points/s effective + time-to-integral d=1000; batched vs plain @1e-7",
+        "value": value,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_run["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32c+f64" if args.precision == "fp32c" else "f64",
+        "data": "synthetic (seeded integrand parameters, no dataset)",
+        "config": {"workload": f"batched_uneven_{args.n}: d~U{{8..256}}, q-d~U{{2..6}}, rule~{{CC,GL(2l-1)}}, "
+                               f"family~{{oscillatory, exp-sum}}, one hipGraph launch",
+                   "integrands": args.n, "precision": args.precision,
+                   "effective_points_per_step": eff, "parallelism": "single-gpu"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / VALU_PEAK_TFLOPS, "traffic": None,
+                     "kernel_ms": main_run["kernel_ms"], "algorithmic_flops_per_launch": flops},
+        "accuracy": {"max_rel_err_vs_oracle": max_err, "all_within_stated_bound": bound_ok,
+                     "max_stated_rel_bound": float(np.max(main_run["bound"] / scale))},
+    }
+
+    if not args.no_extras:
+        extras = {}
+        # FP64 batched rate
+        other = "fp64" if args.precision == "fp32c" else "fp32c"
+        r2 = run_plan(other, max(20, args.steps // 2), 5, not args.no_autotune)
+        extras[f"{other}_batched"] = {
+            "points_per_s": eff / (r2["ms_per_step"] / 1e3), "ms_per_step": r2["ms_per_step"],
+            "kernel_ms": r2["kernel_ms"], "max_rel_err_vs_oracle": float(np.max(np.abs(r2["got"] - ref) / scale))}
+        # plain per-integrand FP64 path: one launch per integrand, no plan, no graph
+        log("plain per-integrand FP64 path ...")
+        outp = torch.empty(len(batch), dtype=torch.float64, device=dev)
+        s.wait_stream(torch.cuda.current_stream())
+        views = [(p, params[p.param_offset: p.param_offset + W.n_params(p.family, p.d)], outp[i: i + 1])
+                 for i, p in enumerate(batch.problems)]
+        for p, pv, ov in views[:64]:
+            native.integrate_one(p, pv, "fp64", out=ov, stream=s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for p, pv, ov in views:
+            native.integrate_one(p, pv, "fp64", out=ov, stream=s)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        plain_err = float(np.max(np.abs(outp.cpu().numpy() - ref) / scale))
+        extras["batched_vs_plain"] = {
+            "plain_fp64_ms": t_plain * 1e3, "batched_ms": main_run["ms_per_step"],
+            "speedup": (t_plain * 1e3 / main_run["ms_per_step"]) if max_err <= 1e-7 else None,
+            "batched_max_rel_err": max_err, "plain_max_rel_err": plain_err,
+            "accuracy_target": 1e-7}
+        # time to integral at d = 1000 (wall time, call -> host-visible value)
+        hd = W.high_dim_d1000()
+        ref_hd = oracle.batch_factorised(hd)
+        tti = {}
+        for i, p in enumerate(hd.problems):
+            one = hd.subset([i])
+            pr = api.params_tensor(one, dev)
+            for prec in ("fp32c", "fp64"):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                plan = native.Plan(one.problems, prec)
+                o = torch.empty(1, dtype=torch.float64, device=dev)
+                s.wait_stream(torch.cuda.current_stream())
+                with torch.cuda.stream(s):
+                    plan.execute(pr, o, stream=s)
+                    v = o.item()              # copy on s, then host sync
+                    cold = time.perf_counter() - t0
+                    ts = []
+                    for _ in range(30):
+                        t0 = time.perf_counter()
+                        plan.execute(pr, o, stream=s)
+                        v = o.item()
+                        ts.append(time.perf_counter() - t0)
+                plan.close()
+                ex = float(ref_hd[i])
+                tti[f"{p.rule}_{prec}"] = {"median_s": statistics.median(ts), "cold_s": cold, "value": v,
+                                           "rel_err_vs_oracle": abs(v - ex) / abs(ex)}
+        extras["time_to_integral_d1000"] = tti
+        result["extras"] = extras
+
+    if not args.no_cpu_baseline:
+        log("CPU baseline (oracle) ...")
+        result["cpu_baseline"] = cpu_baseline(batch, args.cpu_points, min(16, os.cpu_count() or 1))
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

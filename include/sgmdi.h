@@ -1,0 +1,231 @@
+/*
+ * sgmdi.h -- C ABI of the MI355X (gfx950) Smolyak sparse-grid quadrature
+ * library (libsgmdi.so).
+ *
+ * The library evaluates the Smolyak rule of Section 2.1, equation (2.6),
+ *
+ *   Q_d^q(f) = sum_{q-d+1 <= |l| <= q} (-1)^(q-|l|) C(d-1, q-|l|)
+ *              sum_{|l| fixed} (J^{l_1} x ... x J^{l_d}) f,
+ *
+ * with tensor sub-rules (2.7) built from the 1-D rules of Section 2.2, by a
+ * dimension sweep in the spirit of the multilevel dimension iteration of
+ * Section 3 (Algorithms 3.1-3.3, (3.9)-(3.11)): the coordinates are swept
+ * and only clustered partial quantities per coordinate are carried, never
+ * points.  For the supported integrand families every partial function of
+ * (3.11) is a truncated polynomial in the remaining level budget (the gamma
+ * recursion under (2.9)) times an affine phase / log-amplitude sum.
+ *
+ * Domain: the unit cube [0,1]^d (the paper's [-1,1]^d of (2.1) is an affine
+ * image; rescale parameters on the caller's side).  Level q and the excess
+ * budget K = q - d are those of (2.6).  Level 1 of every rule is the single
+ * midpoint 1/2 with weight 1.
+ *
+ * Conventions for every function:
+ *   - the return value is an sg_status; nothing is thrown across the ABI;
+ *   - arguments are validated on the host before anything is launched;
+ *     a rejected call launches nothing and writes no output;
+ *   - "device" pointers are HIP device allocations owned by the caller
+ *     (e.g. torch tensors' data_ptr()); the library keeps no caller pointer
+ *     beyond the call, except that a plan caches one captured graph per
+ *     (params, out, bound, stream) binding and replays it while the binding
+ *     is unchanged;
+ *   - "stream" is a hipStream_t passed as void* (NULL = default stream);
+ *     device work is asynchronous on that stream;
+ *   - one context per host thread; contexts and plans are not thread-safe.
+ */
+#ifndef SGMDI_H
+#define SGMDI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SG_OK = 0,
+    SG_ERR_INVALID_ARGUMENT = 1, /* bad d, q, rule, family, size or NULL pointer */
+    SG_ERR_UNSUPPORTED = 2,      /* valid but beyond this build (e.g. K > SG_MAX_K) */
+    SG_ERR_OVERFLOW = 3,         /* an exact count does not fit in 64 bits */
+    SG_ERR_OUT_OF_MEMORY = 4,    /* host or device allocation failed */
+    SG_ERR_DEVICE = 5,           /* a HIP call failed; see sg_last_error */
+    SG_ERR_CAPTURE = 6           /* graph capture or instantiation failed */
+} sg_status;
+
+/* 1-D rules, numbered as the paper's parameter r (Section 3.1, Section 5). */
+typedef enum {
+    SG_RULE_TRAPEZOID = 1,           /* (2.10): n_1 = 1, n_l = 2^(l-1)+1, nested */
+    SG_RULE_CLENSHAW_CURTIS = 2,     /* (2.11): n_1 = 1, n_l = 2^(l-1)+1, nested */
+    SG_RULE_GAUSS_LEGENDRE = 4,      /* Gauss-Legendre with n_l = 2l-1 points */
+    SG_RULE_GAUSS_LEGENDRE_PAPER = 5 /* (2.13): Gauss-Legendre with n_l = l points */
+} sg_rule;
+
+/* Integrand families; parameters are float64, per integrand, contiguous:
+ *   EXP_SUM       f(x) = exp(sum_i c_i x_i)                      params c[d]
+ *   OSCILLATORY   f(x) = cos(2 pi w + sum_i a_i x_i)              params w, a[d]
+ *   PRODUCT_PEAK  f(x) = prod_i 1/(b_i^-2 + (x_i - u_i)^2)        params b[d], u[d]
+ * (PRODUCT_PEAK is the integrand of (4.4)/(5.2) with free widths/centres;
+ * EXP_SUM generalises (4.5)/(5.1); OSCILLATORY generalises Table 5.7's.) */
+typedef enum {
+    SG_FAMILY_EXP_SUM = 0,
+    SG_FAMILY_OSCILLATORY = 1,
+    SG_FAMILY_PRODUCT_PEAK = 2
+} sg_family;
+
+/* Arithmetic of the per-coordinate work (node values and within-rule sums).
+ * The sweep's truncated-polynomial products and the read-out are FP64 in
+ * both modes. */
+typedef enum {
+    SG_PREC_FP64 = 0,
+    SG_PREC_FP32_COMPENSATED = 1 /* FP32 node values, FP32 hi+lo weights,
+                                    two-sum compensated FP32 accumulation */
+} sg_precision;
+
+/* Largest excess budget K = q - d the GPU path accepts. */
+#define SG_MAX_K 8
+
+/* One integrand of a batch.  param_offset indexes the batch's float64
+ * parameter array (in elements); see sg_family for the layout. */
+typedef struct {
+    int32_t d;      /* dimension, >= 1 */
+    int32_t q;      /* level of (2.6), q >= d */
+    int32_t rule;   /* sg_rule */
+    int32_t family; /* sg_family */
+    int64_t param_offset;
+} sg_problem;
+
+typedef struct sg_context sg_context;
+typedef struct sg_plan sg_plan;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on the current HIP device.  The context owns the rule
+ * cache, the autotune results and its plans' device buffers.
+ * Errors: INVALID_ARGUMENT (ctx NULL), DEVICE (no usable device). */
+sg_status sg_context_create(sg_context **ctx);
+
+/* Destroy a context (NULL is accepted).  Plans created from it must be
+ * destroyed first. */
+sg_status sg_context_destroy(sg_context *ctx);
+
+/* Static text for a status code. */
+const char *sg_status_string(sg_status s);
+
+/* Detail of the last failure on this context (including HIP error text);
+ * valid until the next call on the context.  Never NULL. */
+const char *sg_last_error(const sg_context *ctx);
+
+/* ------------------------------------------------------- host, exact, sync */
+
+/* Exact counts for (d, q, rule) (Section 2.1):
+ *   n_multi         multi-indices in the window q-d+1 <= |l| <= q of (2.6);
+ *   n_points_rep    n_d^q, the point count with repetition;
+ *   n_points_unique distinct points of the sparse grid (the union (2.4)
+ *                   over the window).
+ * Any output pointer may be NULL.  Errors: INVALID_ARGUMENT (d < 1, q < d,
+ * unknown rule), UNSUPPORTED (K > 60), OVERFLOW (a count >= 2^64). */
+sg_status sg_counts(int32_t d, int32_t q, int32_t rule,
+                    uint64_t *n_multi, uint64_t *n_points_rep, uint64_t *n_points_unique);
+
+/* Nodes and weights of the level-l 1-D rule on [0,1] (Section 2.2,
+ * (2.10)-(2.13)), ascending.  x and w must hold at least n_l entries; pass
+ * NULL for both to query n_l only.  Errors: INVALID_ARGUMENT (unknown rule,
+ * level < 1), UNSUPPORTED (n_l > 2^16+1). */
+sg_status sg_rule_table(int32_t rule, int32_t level, double *x, double *w, int32_t *n);
+
+/* Signed combination coefficient (-1)^(q-|l|) C(d-1, q-|l|) of (2.6) for
+ * multi-indices of excess e = |l| - d.  Returns 0 for e outside the window.
+ * Errors: INVALID_ARGUMENT, OVERFLOW (|coefficient| >= 2^63). */
+sg_status sg_coefficient(int32_t d, int32_t q, int32_t e, int64_t *coef);
+
+/* Multi-index of a given rank in the canonical order of the window of
+ * (2.6): by excess e = |l| - d ascending, then by (l_1, ..., l_d) in
+ * decreasing lexicographic order.  Output is sparse: the *nnz coordinates
+ * with l_i >= 2 (ascending, 0-based) and their levels; coords/levels must
+ * hold K entries.  Errors: INVALID_ARGUMENT (rank >= n_multi or bad d, q),
+ * OVERFLOW (the window is not countable in 64 bits). */
+sg_status sg_unrank(int32_t d, int32_t q, uint64_t rank,
+                    int32_t *coords, int32_t *levels, int32_t *nnz);
+
+/* ---------------------------------------------------- device, asynchronous */
+
+/* Unrank `count` consecutive ranks rank0, rank0+1, ... on the device, one
+ * workgroup per block of ranks (same order and output as sg_unrank).
+ * coords_dev/levels_dev: count x max_nnz int32 (row-major, unused slots
+ * -1 / 0), nnz_dev: count int32.  max_nnz must be >= K.
+ * Errors: INVALID_ARGUMENT (range beyond n_multi, NULL, max_nnz < K),
+ * OVERFLOW, DEVICE. */
+sg_status sg_unrank_device(sg_context *ctx, int32_t d, int32_t q, uint64_t rank0, uint64_t count,
+                           int32_t max_nnz, int32_t *coords_dev, int32_t *levels_dev,
+                           int32_t *nnz_dev, void *stream);
+
+/* Build a plan for a batch of n problems (host array) in one precision:
+ * validates every problem, builds (or reuses) the rule tables, orders the
+ * work longest-first, picks tile/schedule parameters (from the context's
+ * autotune results when present) and uploads the plan to the device.
+ * Errors: INVALID_ARGUMENT (n < 1, NULL, a bad problem), UNSUPPORTED
+ * (K > SG_MAX_K), OUT_OF_MEMORY, DEVICE. */
+sg_status sg_plan_create(sg_context *ctx, const sg_problem *problems, int32_t n,
+                         int32_t precision, sg_plan **plan);
+
+/* Evaluate every integrand of the plan.  params_dev: the batch's float64
+ * parameter array (device); out_dev: n float64 results in problem order
+ * (device); bound_dev: NULL or n float64 a-priori bounds on |result - exact
+ * Smolyak value| (device).  The launch is captured into a HIP graph on the
+ * first call with a given (params, out, bound, stream) and replayed after.
+ * Errors: INVALID_ARGUMENT (NULL plan/params/out), DEVICE, CAPTURE. */
+sg_status sg_plan_execute(sg_plan *plan, const double *params_dev, double *out_dev,
+                          double *bound_dev, void *stream);
+
+/* Gradient of every result with respect to every parameter (reverse sweep):
+ * grad_params_dev[k] = grad_out_dev[i] * dQ_i/dparams[k] for the parameters
+ * k of problem i, same layout as params.  Parameters not used by any problem
+ * are left untouched.  Errors: INVALID_ARGUMENT, DEVICE. */
+sg_status sg_plan_execute_grad(sg_plan *plan, const double *params_dev, const double *grad_out_dev,
+                               double *grad_params_dev, void *stream);
+
+/* Plan facts for reporting (all exact counts of the algorithmic work of one
+ * forward launch; u64 counts saturate at 2^64-1):
+ *   effective_points  sum over problems of n_d^q (points with repetition);
+ *   units             sum over problems of d ((integrand, coordinate) pairs);
+ *   pair_evals        centred node-pair evaluations (one per symmetric pair
+ *                     {1/2 - y, 1/2 + y} of the union node set, per unit);
+ *   macs              within-rule multiply-adds (difference-rule weights
+ *                     times pair values), summed over units;
+ *   merge_flops       floating-point operations of the truncated-polynomial
+ *                     products of the sweep (K(K-1)/2 multiply-adds and K
+ *                     adds per unit, multiply-add counted as 2);
+ *   block_threads, grid_blocks: the launch shape the plan uses. */
+typedef struct {
+    uint64_t effective_points;
+    uint64_t units;
+    uint64_t pair_evals;
+    uint64_t macs;
+    uint64_t merge_flops;
+    int32_t block_threads;
+    int32_t grid_blocks;
+} sg_plan_info;
+
+sg_status sg_plan_get_info(const sg_plan *plan, sg_plan_info *info);
+
+/* Time candidate schedules for this plan on `stream` with HIP events and
+ * keep the fastest (stored in the context; later plans with the same shape
+ * class reuse it).  Runs the forward launch repeatedly on params_dev/out_dev.
+ * Errors: INVALID_ARGUMENT, DEVICE. */
+sg_status sg_plan_autotune(sg_plan *plan, const double *params_dev, double *out_dev, void *stream);
+
+/* Release a plan (NULL accepted). */
+sg_status sg_plan_destroy(sg_plan *plan);
+
+/* Plain, plan-free path: one integrand, one launch, no graph, no batching.
+ * Same arguments as one problem of a plan (param_offset is ignored: params_dev
+ * points at this integrand's parameters).  out_dev/bound_dev: one float64
+ * each (bound may be NULL). */
+sg_status sg_integrate(sg_context *ctx, const sg_problem *problem, int32_t precision,
+                       const double *params_dev, double *out_dev, double *bound_dev, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGMDI_H */

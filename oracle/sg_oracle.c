@@ -691,3 +691,50 @@ int or_smolyak_factorised_grad(int d, int q, int rule, int family, const double 
     fq_free(&F);
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Batch driver: or_smolyak_factorised over many integrands, threads   */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int n, nthreads, tid;
+    const int *d, *q, *rule, *family;
+    const int64_t *offset;
+    const double *params;
+    double *out;
+    int rc;
+} fb_job;
+
+static void *fb_thread(void *arg)
+{
+    fb_job *J = (fb_job *)arg;
+    for (int i = J->tid; i < J->n; i += J->nthreads) {
+        double o[2];
+        if (or_smolyak_factorised(J->d[i], J->q[i], J->rule[i], J->family[i], J->params + J->offset[i], o))
+            J->rc = -1;
+        J->out[i] = o[0];
+    }
+    return NULL;
+}
+
+/* Factorised values of n integrands (problem i: d[i], q[i], rule[i],
+ * family[i], parameters at params + offset[i]); out[i] rounded to double. */
+int or_batch_factorised(int n, const int *d, const int *q, const int *rule, const int *family,
+                        const int64_t *offset, const double *params, int nthreads, double *out)
+{
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    fb_job *J = calloc(nthreads, sizeof(fb_job));
+    pthread_t *th = calloc(nthreads, sizeof(pthread_t));
+    for (int t = 0; t < nthreads; ++t) {
+        fb_job j = {n, nthreads, t, d, q, rule, family, offset, params, out, 0};
+        J[t] = j;
+        pthread_create(&th[t], NULL, fb_thread, &J[t]);
+    }
+    int rc = 0;
+    for (int t = 0; t < nthreads; ++t) {
+        pthread_join(th[t], NULL);
+        rc |= J[t].rc;
+    }
+    free(J); free(th);
+    return rc;
+}

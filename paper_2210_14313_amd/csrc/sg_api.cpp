@@ -1,0 +1,588 @@
+// C ABI (include/sgmdi.h): contexts, plans, graph capture cache, plain
+// per-integrand path, unranking, autotuning and argument validation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "sg_internal.hpp"
+
+using namespace sg;
+
+namespace {
+
+struct PlainEntry {
+    ProbDev* probs = nullptr;
+    TableDev* tabs = nullptr;
+    double* pool64 = nullptr;
+    float* pool32 = nullptr;
+};
+
+struct GraphEntry {
+    const void* params;
+    void* out;
+    void* bound;
+    void* stream;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+}  // namespace
+
+struct sg_context {
+    int device = 0;
+    std::string last_error;
+    std::map<std::pair<int, int>, std::unique_ptr<DeltaTable>> tables;
+    std::map<std::string, LaunchCfg> tuned;
+    std::map<std::tuple<int, int, int, int>, PlainEntry> plain;
+    std::map<std::pair<int, int>, uint64_t*> unrank_tables;
+    int live_plans = 0;
+};
+
+struct sg_plan {
+    sg_context* ctx = nullptr;
+    int precision = 0;
+    int n = 0;
+    std::vector<sg_problem> problems;
+    ProbDev* d_probs = nullptr;
+    TableDev* d_tabs = nullptr;
+    double* d_pool64 = nullptr;
+    float* d_pool32 = nullptr;
+    LaunchCfg cfg;
+    sg_plan_info info{};
+    std::string tune_key;
+    std::vector<GraphEntry> graphs;
+};
+
+namespace {
+
+sg_status fail(sg_context* ctx, sg_status st, const std::string& msg)
+{
+    if (ctx) ctx->last_error = msg;
+    return st;
+}
+
+sg_status hip_fail(sg_context* ctx, hipError_t e, const char* what)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(ctx, SG_ERR_DEVICE, m);
+}
+
+bool family_ok(int f)
+{
+    return f == SG_FAMILY_EXP_SUM || f == SG_FAMILY_OSCILLATORY || f == SG_FAMILY_PRODUCT_PEAK;
+}
+
+sg_status validate_problem(sg_context* ctx, const sg_problem& p, int idx)
+{
+    char buf[160];
+    if (p.d < 1 || p.q < p.d || !rule_is_known(p.rule) || !family_ok(p.family) || p.param_offset < 0) {
+        snprintf(buf, sizeof buf, "problem %d: invalid (d=%d q=%d rule=%d family=%d offset=%lld)", idx,
+                 p.d, p.q, p.rule, p.family, (long long)p.param_offset);
+        return fail(ctx, SG_ERR_INVALID_ARGUMENT, buf);
+    }
+    if (p.q - p.d > kMaxK) {
+        snprintf(buf, sizeof buf, "problem %d: excess budget K=%d exceeds SG_MAX_K=%d", idx, p.q - p.d,
+                 kMaxK);
+        return fail(ctx, SG_ERR_UNSUPPORTED, buf);
+    }
+    return SG_OK;
+}
+
+const DeltaTable* get_table(sg_context* ctx, int rule, int K, sg_status& st)
+{
+    auto key = std::make_pair(rule, K);
+    auto it = ctx->tables.find(key);
+    if (it != ctx->tables.end()) return it->second.get();
+    std::unique_ptr<DeltaTable> t(new DeltaTable());
+    std::string err;
+    if (!build_delta_table(rule, K, *t, err)) {
+        st = fail(ctx, SG_ERR_INVALID_ARGUMENT, err);
+        return nullptr;
+    }
+    const DeltaTable* r = t.get();
+    ctx->tables[key] = std::move(t);
+    return r;
+}
+
+uint64_t macs_of(const DeltaTable& t)
+{
+    uint64_t m = 0;
+    for (int L = 2; L <= t.K + 1; ++L) {
+        const uint64_t np = (uint64_t)(t.level_begin[L + 1] - t.level_begin[L]);
+        const uint64_t ne = t.nested ? (uint64_t)(t.K - L + 2) : (uint64_t)(L <= t.K ? 2 : 1);
+        m += np * ne;
+    }
+    return m;
+}
+
+uint64_t sat_add(uint64_t a, uint64_t b)
+{
+    return a > UINT64_MAX - b ? UINT64_MAX : a + b;
+}
+
+uint64_t sat_mul(uint64_t a, uint64_t b)
+{
+    if (a == 0 || b == 0) return 0;
+    return a > UINT64_MAX / b ? UINT64_MAX : a * b;
+}
+
+int round_block(int want)
+{
+    int b = 64;
+    while (b < want && b < 256) b *= 2;
+    return b;
+}
+
+// Append one table to the pools and fill its device view.
+void append_table(const DeltaTable& t, std::vector<double>& p64, std::vector<float>& p32, TableDev& td)
+{
+    std::memset(&td, 0, sizeof td);
+    td.K = t.K;
+    td.npairs = t.npairs;
+    td.nested = t.nested ? 1 : 0;
+    for (int i = 0; i < kMaxK + 3; ++i)
+        td.level_begin[i] = i < (int)t.level_begin.size() ? t.level_begin[i] : t.npairs;
+    td.off64 = (int64_t)p64.size();
+    td.off32 = (int64_t)p32.size();
+    p64.insert(p64.end(), t.y.begin(), t.y.end());
+    p64.insert(p64.end(), t.dw.begin(), t.dw.end());
+    p64.insert(p64.end(), t.wabs.begin(), t.wabs.end());
+    p32.insert(p32.end(), t.y32.begin(), t.y32.end());
+    p32.insert(p32.end(), t.dw_hi.begin(), t.dw_hi.end());
+    p32.insert(p32.end(), t.dw_lo.begin(), t.dw_lo.end());
+}
+
+template <class T>
+sg_status upload(sg_context* ctx, T** dst, const T* src, size_t n)
+{
+    const size_t bytes = std::max<size_t>(1, n) * sizeof(T);
+    hipError_t e = hipMalloc((void**)dst, bytes);
+    if (e != hipSuccess) return fail(ctx, SG_ERR_OUT_OF_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(e));
+    if (n) {
+        e = hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy");
+    }
+    return SG_OK;
+}
+
+void destroy_graphs(sg_plan* p)
+{
+    for (GraphEntry& g : p->graphs) {
+        hipGraphExecDestroy(g.exec);
+        hipGraphDestroy(g.graph);
+    }
+    p->graphs.clear();
+}
+
+bool graphs_enabled()
+{
+    const char* v = std::getenv("SGMDI_NO_GRAPH");
+    return !(v && v[0] && v[0] != '0');
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sg_status_string(sg_status s)
+{
+    switch (s) {
+    case SG_OK: return "ok";
+    case SG_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case SG_ERR_UNSUPPORTED: return "unsupported";
+    case SG_ERR_OVERFLOW: return "count overflows 64 bits";
+    case SG_ERR_OUT_OF_MEMORY: return "out of memory";
+    case SG_ERR_DEVICE: return "device error";
+    case SG_ERR_CAPTURE: return "graph capture failed";
+    }
+    return "unknown status";
+}
+
+const char* sg_last_error(const sg_context* ctx)
+{
+    return ctx ? ctx->last_error.c_str() : "no context";
+}
+
+sg_status sg_context_create(sg_context** ctx)
+{
+    if (!ctx) return SG_ERR_INVALID_ARGUMENT;
+    *ctx = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return SG_ERR_DEVICE;
+    sg_context* c = new (std::nothrow) sg_context();
+    if (!c) return SG_ERR_OUT_OF_MEMORY;
+    c->device = dev;
+    *ctx = c;
+    return SG_OK;
+}
+
+sg_status sg_context_destroy(sg_context* ctx)
+{
+    if (!ctx) return SG_OK;
+    for (auto& kv : ctx->plain) {
+        hipFree(kv.second.probs);
+        hipFree(kv.second.tabs);
+        hipFree(kv.second.pool64);
+        hipFree(kv.second.pool32);
+    }
+    for (auto& kv : ctx->unrank_tables) hipFree(kv.second);
+    delete ctx;
+    return SG_OK;
+}
+
+sg_status sg_counts(int32_t d, int32_t q, int32_t rule, uint64_t* n_multi, uint64_t* n_points_rep,
+                    uint64_t* n_points_unique)
+{
+    return counts(d, q, rule, n_multi, n_points_rep, n_points_unique);
+}
+
+sg_status sg_rule_table(int32_t rule, int32_t level, double* x, double* w, int32_t* n)
+{
+    if (!rule_is_known(rule) || level < 1) return SG_ERR_INVALID_ARGUMENT;
+    const long np = rule_npoints(rule, level);
+    if (np < 1) return SG_ERR_UNSUPPORTED;
+    if (n) *n = (int32_t)np;
+    if (!x && !w) return SG_OK;
+    if (!x || !w) return SG_ERR_INVALID_ARGUMENT;
+    std::vector<long double> xs, ws;
+    if (!rule_nodes(rule, level, xs, ws)) return SG_ERR_UNSUPPORTED;
+    for (long j = 0; j < np; ++j) {
+        x[j] = (double)xs[j];
+        w[j] = (double)ws[j];
+    }
+    return SG_OK;
+}
+
+sg_status sg_coefficient(int32_t d, int32_t q, int32_t e, int64_t* coef)
+{
+    if (d < 1 || q < d || !coef) return SG_ERR_INVALID_ARGUMENT;
+    const int K = q - d;
+    if (e < std::max(0, K - d + 1) || e > K) { *coef = 0; return SG_OK; }
+    uint64_t c;
+    if (!binom_u64((uint64_t)d - 1, (uint64_t)(K - e), c) || c > (uint64_t)INT64_MAX) return SG_ERR_OVERFLOW;
+    *coef = ((K - e) % 2) ? -(int64_t)c : (int64_t)c;
+    return SG_OK;
+}
+
+sg_status sg_unrank(int32_t d, int32_t q, uint64_t rank, int32_t* coords, int32_t* levels, int32_t* nnz)
+{
+    if (d < 1 || q < d) return SG_ERR_INVALID_ARGUMENT;
+    uint64_t m;
+    sg_status st = counts(d, q, SG_RULE_CLENSHAW_CURTIS, &m, nullptr, nullptr);
+    if (st == SG_ERR_OVERFLOW) {
+        // the multi-index count alone may still fit; recount it directly
+        const int K = q - d;
+        m = 0;
+        for (int e = std::max(0, K - d + 1); e <= K; ++e) {
+            uint64_t c;
+            if (!binom_u64((uint64_t)d - 1 + e, (uint64_t)e, c) || m > UINT64_MAX - c) return SG_ERR_OVERFLOW;
+            m += c;
+        }
+    } else if (st != SG_OK) {
+        return st;
+    }
+    if (rank >= m) return SG_ERR_INVALID_ARGUMENT;
+    return unrank(d, q, rank, coords, levels, nnz);
+}
+
+sg_status sg_unrank_device(sg_context* ctx, int32_t d, int32_t q, uint64_t rank0, uint64_t count,
+                           int32_t max_nnz, int32_t* coords_dev, int32_t* levels_dev, int32_t* nnz_dev,
+                           void* stream)
+{
+    if (!ctx) return SG_ERR_INVALID_ARGUMENT;
+    if (d < 1 || q < d || !coords_dev || !levels_dev || !nnz_dev)
+        return fail(ctx, SG_ERR_INVALID_ARGUMENT, "sg_unrank_device: bad d/q or NULL output");
+    const int K = q - d;
+    if (K > 60) return fail(ctx, SG_ERR_UNSUPPORTED, "K > 60");
+    if (max_nnz < std::max(1, K)) return fail(ctx, SG_ERR_INVALID_ARGUMENT, "max_nnz < K");
+    // table of weak-composition counts W[n][parts], n <= K, parts <= d
+    std::vector<uint64_t> W((size_t)(K + 1) * (d + 1), 0);
+    for (int nn = 0; nn <= K; ++nn)
+        for (int parts = 0; parts <= d; ++parts) {
+            uint64_t v;
+            if (parts == 0) v = (nn == 0);
+            else if (!binom_u64((uint64_t)nn + parts - 1, (uint64_t)nn, v))
+                return fail(ctx, SG_ERR_OVERFLOW, "window not countable in 64 bits");
+            W[(size_t)nn * (d + 1) + parts] = v;
+        }
+    uint64_t m = 0;
+    for (int e = std::max(0, K - d + 1); e <= K; ++e) {
+        const uint64_t c = W[(size_t)e * (d + 1) + d];
+        if (m > UINT64_MAX - c) return fail(ctx, SG_ERR_OVERFLOW, "window not countable in 64 bits");
+        m += c;
+    }
+    if (count == 0) return SG_OK;
+    if (rank0 >= m || count > m - rank0) return fail(ctx, SG_ERR_INVALID_ARGUMENT, "rank range beyond the window");
+    auto key = std::make_pair(d, q);
+    uint64_t* dW = nullptr;
+    auto it = ctx->unrank_tables.find(key);
+    if (it == ctx->unrank_tables.end()) {
+        sg_status st = upload(ctx, &dW, W.data(), W.size());
+        if (st != SG_OK) return st;
+        ctx->unrank_tables[key] = dW;
+    } else {
+        dW = it->second;
+    }
+    const int rc = launch_unrank(d, q, rank0, count, max_nnz, dW, K + 1, coords_dev, levels_dev, nnz_dev, stream);
+    if (rc != 0) return hip_fail(ctx, (hipError_t)rc, "unrank launch");
+    return SG_OK;
+}
+
+sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n, int32_t precision,
+                         sg_plan** plan)
+{
+    if (!ctx || !plan) return SG_ERR_INVALID_ARGUMENT;
+    *plan = nullptr;
+    if (!problems || n < 1) return fail(ctx, SG_ERR_INVALID_ARGUMENT, "empty problem list");
+    if (precision != SG_PREC_FP64 && precision != SG_PREC_FP32_COMPENSATED)
+        return fail(ctx, SG_ERR_INVALID_ARGUMENT, "unknown precision");
+    for (int i = 0; i < n; ++i) {
+        sg_status st = validate_problem(ctx, problems[i], i);
+        if (st != SG_OK) return st;
+    }
+    std::unique_ptr<sg_plan> p(new sg_plan());
+    p->ctx = ctx;
+    p->precision = precision;
+    p->n = n;
+    p->problems.assign(problems, problems + n);
+
+    // tables
+    std::map<std::pair<int, int>, int> tindex;
+    std::vector<const DeltaTable*> tlist;
+    std::vector<int> ptab(n);
+    for (int i = 0; i < n; ++i) {
+        auto key = std::make_pair(problems[i].rule, problems[i].q - problems[i].d);
+        auto it = tindex.find(key);
+        if (it == tindex.end()) {
+            sg_status st = SG_OK;
+            const DeltaTable* t = get_table(ctx, key.first, key.second, st);
+            if (!t) return st;
+            tindex[key] = (int)tlist.size();
+            ptab[i] = (int)tlist.size();
+            tlist.push_back(t);
+        } else {
+            ptab[i] = it->second;
+        }
+    }
+    std::vector<double> p64;
+    std::vector<float> p32;
+    std::vector<TableDev> tdev(tlist.size());
+    for (size_t k = 0; k < tlist.size(); ++k) append_table(*tlist[k], p64, p32, tdev[k]);
+
+    // longest-processing-time order
+    std::vector<double> cost(n);
+    sg_plan_info info{};
+    int maxd = 1;
+    for (int i = 0; i < n; ++i) {
+        const DeltaTable& t = *tlist[ptab[i]];
+        const uint64_t d = (uint64_t)problems[i].d;
+        const uint64_t K = (uint64_t)t.K;
+        const uint64_t macs = macs_of(t);
+        cost[i] = (double)d * (8.0 * t.npairs + 2.0 * (double)macs + (double)(K * K));
+        uint64_t nrep = 0;
+        sg_status st = counts(problems[i].d, problems[i].q, problems[i].rule, nullptr, &nrep, nullptr);
+        info.effective_points = sat_add(info.effective_points, st == SG_OK ? nrep : UINT64_MAX);
+        info.units = sat_add(info.units, d);
+        info.pair_evals = sat_add(info.pair_evals, sat_mul(d, (uint64_t)t.npairs));
+        info.macs = sat_add(info.macs, sat_mul(d, macs));
+        info.merge_flops = sat_add(info.merge_flops, sat_mul(d, K * (K - (K ? 1 : 0)) + K));
+        maxd = std::max(maxd, problems[i].d);
+    }
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::vector<ProbDev> pdev(n);
+    for (int k = 0; k < n; ++k) {
+        const int i = order[k];
+        ProbDev& r = pdev[k];
+        r.d = problems[i].d;
+        r.K = problems[i].q - problems[i].d;
+        r.family = problems[i].family;
+        r.table = ptab[i];
+        r.param_offset = problems[i].param_offset;
+        r.out_index = i;
+        r.pad = 0;
+    }
+
+    char key[128];
+    snprintf(key, sizeof key, "p%d_n%d_maxd%d", precision, n, maxd);
+    p->tune_key = key;
+    auto tk = ctx->tuned.find(p->tune_key);
+    if (tk != ctx->tuned.end()) p->cfg = tk->second;
+    else p->cfg.block = round_block(maxd);
+    info.block_threads = p->cfg.block;
+    info.grid_blocks = n;
+    p->info = info;
+
+    sg_status st;
+    if ((st = upload(ctx, &p->d_probs, pdev.data(), pdev.size())) != SG_OK) return st;
+    if ((st = upload(ctx, &p->d_tabs, tdev.data(), tdev.size())) != SG_OK) return st;
+    if ((st = upload(ctx, &p->d_pool64, p64.data(), p64.size())) != SG_OK) return st;
+    if ((st = upload(ctx, &p->d_pool32, p32.data(), p32.size())) != SG_OK) return st;
+    ctx->live_plans++;
+    *plan = p.release();
+    return SG_OK;
+}
+
+static sg_status plan_launch(sg_plan* p, const double* params, double* out, double* bound, void* stream)
+{
+    const int rc = launch_forward(p->precision, p->cfg, p->n, p->d_probs, p->d_tabs, p->d_pool64,
+                                  p->d_pool32, params, out, bound, stream);
+    if (rc != 0) return hip_fail(p->ctx, (hipError_t)rc, "forward launch");
+    return SG_OK;
+}
+
+sg_status sg_plan_execute(sg_plan* p, const double* params_dev, double* out_dev, double* bound_dev, void* stream)
+{
+    if (!p) return SG_ERR_INVALID_ARGUMENT;
+    if (!params_dev || !out_dev) return fail(p->ctx, SG_ERR_INVALID_ARGUMENT, "NULL params or out");
+    if (!stream || !graphs_enabled()) return plan_launch(p, params_dev, out_dev, bound_dev, stream);
+    for (GraphEntry& g : p->graphs) {
+        if (g.params == params_dev && g.out == out_dev && g.bound == bound_dev && g.stream == stream) {
+            hipError_t e = hipGraphLaunch(g.exec, (hipStream_t)stream);
+            if (e != hipSuccess) return hip_fail(p->ctx, e, "hipGraphLaunch");
+            return SG_OK;
+        }
+    }
+    // first call with this binding: capture the launch into a graph
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fail(p->ctx, SG_ERR_CAPTURE, std::string("begin capture: ") + hipGetErrorString(e));
+    const int rc = launch_forward(p->precision, p->cfg, p->n, p->d_probs, p->d_tabs, p->d_pool64,
+                                  p->d_pool32, params_dev, out_dev, bound_dev, stream);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(s, &graph);
+    if (rc != 0 || e != hipSuccess || !graph) {
+        if (graph) hipGraphDestroy(graph);
+        return fail(p->ctx, SG_ERR_CAPTURE, std::string("capture: ") + hipGetErrorString(rc ? (hipError_t)rc : e));
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(graph);
+        return fail(p->ctx, SG_ERR_CAPTURE, std::string("instantiate: ") + hipGetErrorString(e));
+    }
+    if (p->graphs.size() >= 8) {   // keep the cache small
+        hipGraphExecDestroy(p->graphs.front().exec);
+        hipGraphDestroy(p->graphs.front().graph);
+        p->graphs.erase(p->graphs.begin());
+    }
+    p->graphs.push_back(GraphEntry{params_dev, out_dev, bound_dev, stream, graph, exec});
+    e = hipGraphLaunch(exec, s);
+    if (e != hipSuccess) return hip_fail(p->ctx, e, "hipGraphLaunch");
+    return SG_OK;
+}
+
+sg_status sg_plan_execute_grad(sg_plan* p, const double* params_dev, const double* grad_out_dev,
+                               double* grad_params_dev, void* stream)
+{
+    (void)params_dev; (void)grad_out_dev; (void)grad_params_dev; (void)stream;
+    if (!p) return SG_ERR_INVALID_ARGUMENT;
+    return fail(p->ctx, SG_ERR_UNSUPPORTED, "gradient not available in this build");
+}
+
+sg_status sg_plan_get_info(const sg_plan* p, sg_plan_info* info)
+{
+    if (!p || !info) return SG_ERR_INVALID_ARGUMENT;
+    *info = p->info;
+    return SG_OK;
+}
+
+sg_status sg_plan_autotune(sg_plan* p, const double* params_dev, double* out_dev, void* stream)
+{
+    if (!p || !params_dev || !out_dev) return SG_ERR_INVALID_ARGUMENT;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(p->ctx, SG_ERR_DEVICE, "hipEventCreate");
+    const LaunchCfg saved = p->cfg;
+    LaunchCfg best = saved;
+    float best_ms = 1e30f;
+    const int reps = 20;
+    for (int b = 64; b <= 256; b *= 2) {
+        p->cfg.block = b;
+        sg_status st = plan_launch(p, params_dev, out_dev, nullptr, stream);   // warm
+        if (st != SG_OK) { p->cfg = saved; return st; }
+        hipEventRecord(e0, s);
+        for (int r = 0; r < reps; ++r) plan_launch(p, params_dev, out_dev, nullptr, stream);
+        hipEventRecord(e1, s);
+        hipError_t e = hipEventSynchronize(e1);
+        if (e != hipSuccess) { p->cfg = saved; return hip_fail(p->ctx, e, "autotune sync"); }
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) { best_ms = ms; best = p->cfg; }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    p->cfg = best;
+    p->info.block_threads = best.block;
+    p->ctx->tuned[p->tune_key] = best;
+    destroy_graphs(p);
+    return SG_OK;
+}
+
+sg_status sg_plan_destroy(sg_plan* p)
+{
+    if (!p) return SG_OK;
+    destroy_graphs(p);
+    hipFree(p->d_probs);
+    hipFree(p->d_tabs);
+    hipFree(p->d_pool64);
+    hipFree(p->d_pool32);
+    if (p->ctx) p->ctx->live_plans--;
+    delete p;
+    return SG_OK;
+}
+
+sg_status sg_integrate(sg_context* ctx, const sg_problem* problem, int32_t precision, const double* params_dev,
+                       double* out_dev, double* bound_dev, void* stream)
+{
+    if (!ctx) return SG_ERR_INVALID_ARGUMENT;
+    if (!problem || !params_dev || !out_dev) return fail(ctx, SG_ERR_INVALID_ARGUMENT, "NULL argument");
+    if (precision != SG_PREC_FP64 && precision != SG_PREC_FP32_COMPENSATED)
+        return fail(ctx, SG_ERR_INVALID_ARGUMENT, "unknown precision");
+    sg_status st = validate_problem(ctx, *problem, 0);
+    if (st != SG_OK) return st;
+    const int K = problem->q - problem->d;
+    auto key = std::make_tuple(problem->rule, K, problem->family, problem->d);
+    auto it = ctx->plain.find(key);
+    if (it == ctx->plain.end()) {
+        const DeltaTable* t = get_table(ctx, problem->rule, K, st);
+        if (!t) return st;
+        std::vector<double> p64;
+        std::vector<float> p32;
+        TableDev td;
+        append_table(*t, p64, p32, td);
+        ProbDev pd;
+        pd.d = problem->d;
+        pd.K = K;
+        pd.family = problem->family;
+        pd.table = 0;
+        pd.param_offset = 0;
+        pd.out_index = 0;
+        pd.pad = 0;
+        PlainEntry pe;
+        if ((st = upload(ctx, &pe.probs, &pd, 1)) != SG_OK) return st;
+        if ((st = upload(ctx, &pe.tabs, &td, 1)) != SG_OK) return st;
+        if ((st = upload(ctx, &pe.pool64, p64.data(), p64.size())) != SG_OK) return st;
+        if ((st = upload(ctx, &pe.pool32, p32.data(), p32.size())) != SG_OK) return st;
+        it = ctx->plain.emplace(key, pe).first;
+    }
+    LaunchCfg cfg;
+    cfg.block = round_block(problem->d);
+    const int rc = launch_forward(precision, cfg, 1, it->second.probs, it->second.tabs, it->second.pool64,
+                                  it->second.pool32, params_dev, out_dev, bound_dev, stream);
+    if (rc != 0) return hip_fail(ctx, (hipError_t)rc, "forward launch");
+    return SG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,89 @@
+// Internal declarations shared by the host runtime and the kernel launchers.
+// Not part of the ABI (see include/sgmdi.h).
+#pragma once
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "sgmdi.h"
+
+namespace sg {
+
+constexpr int kMaxK = SG_MAX_K;
+
+// ---------------------------------------------------------------- 1-D rules
+// Number of nodes of the level-l rule (Section 2.2); -1 if unknown/too big.
+long rule_npoints(int rule, int level);
+bool rule_is_known(int rule);
+bool rule_is_nested(int rule);
+// Level-l nodes/weights on [0,1], ascending, computed in long double.
+bool rule_nodes(int rule, int level, std::vector<long double>& x, std::vector<long double>& w);
+
+// Hierarchical (difference-rule) table for one (rule, K).
+//
+// The Smolyak sum over the window equals the sum over all l with excess
+// |l| - d <= K of the tensor products of difference rules
+// Delta^1 = J^1, Delta^{e+1} = J^{e+1} - J^e (the reading of (2.9) as a
+// summation by coordinates).  Every difference rule with e >= 1 has weights
+// summing to 0 and is symmetric about 1/2, so it only sees the even part of
+// a centred factor g(1/2 + y)/g(1/2) - 1.  The table therefore lists node
+// PAIRS {1/2 - y, 1/2 + y}, y > 0, and for each pair and each e >= 1 the
+// weight dW[e][p] the pair's nodes carry in Delta^{e+1}.
+//
+// Pairs are grouped by the level L at which they first enter; pair p of
+// level L carries non-zero weights for
+//   nested rules (trapezoid, Clenshaw-Curtis):  e = L-1 .. K
+//   Gauss-Legendre (levels share only 1/2):     e = L-1 and e = L (if <= K).
+struct DeltaTable {
+    int rule = 0, K = 0, npairs = 0;
+    bool nested = true;
+    std::vector<int> level_begin;          // size K+3; pairs of level L: [lb[L], lb[L+1])
+    std::vector<double> y;                 // npairs, y_p > 0
+    std::vector<double> dw;                // (K+1) x npairs, row 0 unused (zero)
+    std::vector<float> y32, dw_hi, dw_lo;  // FP32 copies; dw = dw_hi + dw_lo to ~2^-48
+    std::vector<double> wabs;              // npairs: sum_e |dW[e][p]| (error bound)
+};
+bool build_delta_table(int rule, int K, DeltaTable& t, std::string& err);
+
+// ------------------------------------------------------------ integer layer
+// Exact unsigned binomial with overflow report (result >= 2^64 -> false).
+bool binom_u64(uint64_t n, uint64_t k, uint64_t& out);
+sg_status counts(int d, int q, int rule, uint64_t* n_multi, uint64_t* n_rep, uint64_t* n_unique);
+sg_status unrank(int d, int q, uint64_t rank, int32_t* coords, int32_t* levels, int32_t* nnz);
+
+// ------------------------------------------------------------------- device
+// Per-problem record in device memory (plan order = longest first).
+struct ProbDev {
+    int32_t d, K, family, table;   // table: index into the plan's TableDev array
+    int64_t param_offset;
+    int32_t out_index;             // position in the caller's problem order
+    int32_t pad;
+};
+
+// Device view of one DeltaTable inside the plan's table pools.
+struct TableDev {
+    int32_t K, npairs, nested, pad;
+    int32_t level_begin[kMaxK + 3];
+    int32_t pad2;
+    int64_t off64;   // pool64: y[npairs], dw[(K+1)*npairs], wabs[npairs]
+    int64_t off32;   // pool32: y32[npairs], dw_hi[(K+1)*npairs], dw_lo[(K+1)*npairs]
+};
+
+struct LaunchCfg {
+    int block = 256;   // threads per workgroup (64, 128 or 256)
+};
+
+// Kernel launchers (sg_kernels.hip).
+int launch_forward(int precision, const LaunchCfg& cfg, int nprob, const ProbDev* probs,
+                   const TableDev* tabs, const double* pool64, const float* pool32,
+                   const double* params, double* out, double* bound, void* stream);
+int launch_unrank(int d, int q, uint64_t rank0, uint64_t count, int max_nnz,
+                  const uint64_t* binom_table, int binom_rows, int32_t* coords, int32_t* levels,
+                  int32_t* nnz, void* stream);
+const char* device_error_string(int code);
+
+}  // namespace sg

@@ -1,0 +1,256 @@
+"""ctypes binding of libsgmdi.so (include/sgmdi.h): argument marshalling only.
+
+Every step of the computation runs in the library's HIP kernels; this module
+converts Python/torch objects to pointers and sizes and raises on errors.
+It never falls back to another implementation: if the library is missing,
+loading fails with an exception.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsgmdi.so")
+
+RULES = {"tr": 1, "cc": 2, "gl": 4, "gl_paper": 5}
+FAMILIES = {"exp_sum": 0, "oscillatory": 1, "product_peak": 2}
+PRECISIONS = {"fp64": 0, "fp32c": 1}
+STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "overflow", 4: "out of memory",
+          5: "device error", 6: "capture error"}
+MAX_K = 8
+
+
+class SgError(RuntimeError):
+    def __init__(self, status: int, msg: str = ""):
+        super().__init__(f"sgmdi: {STATUS.get(status, status)}{': ' + msg if msg else ''}")
+        self.status = status
+
+
+class SgProblem(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("q", ctypes.c_int32), ("rule", ctypes.c_int32),
+                ("family", ctypes.c_int32), ("param_offset", ctypes.c_int64)]
+
+
+class SgPlanInfo(ctypes.Structure):
+    _fields_ = [("effective_points", ctypes.c_uint64), ("units", ctypes.c_uint64),
+                ("pair_evals", ctypes.c_uint64), ("macs", ctypes.c_uint64),
+                ("merge_flops", ctypes.c_uint64), ("block_threads", ctypes.c_int32),
+                ("grid_blocks", ctypes.c_int32)]
+
+
+_lib = None
+
+EXPORTS = ["sg_context_create", "sg_context_destroy", "sg_status_string", "sg_last_error", "sg_counts",
+           "sg_rule_table", "sg_coefficient", "sg_unrank", "sg_unrank_device", "sg_plan_create",
+           "sg_plan_execute", "sg_plan_execute_grad", "sg_plan_get_info", "sg_plan_autotune",
+           "sg_plan_destroy", "sg_integrate"]
+
+
+def lib():
+    """Load libsgmdi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2210_14313_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, u64, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64
+    P = ctypes.POINTER
+    sig = {
+        "sg_context_create": ([P(vp)], i32),
+        "sg_context_destroy": ([vp], i32),
+        "sg_status_string": ([i32], ctypes.c_char_p),
+        "sg_last_error": ([vp], ctypes.c_char_p),
+        "sg_counts": ([i32, i32, i32, P(u64), P(u64), P(u64)], i32),
+        "sg_rule_table": ([i32, i32, P(ctypes.c_double), P(ctypes.c_double), P(i32)], i32),
+        "sg_coefficient": ([i32, i32, i32, P(i64)], i32),
+        "sg_unrank": ([i32, i32, u64, P(i32), P(i32), P(i32)], i32),
+        "sg_unrank_device": ([vp, i32, i32, u64, u64, i32, vp, vp, vp, vp], i32),
+        "sg_plan_create": ([vp, P(SgProblem), i32, i32, P(vp)], i32),
+        "sg_plan_execute": ([vp, vp, vp, vp, vp], i32),
+        "sg_plan_execute_grad": ([vp, vp, vp, vp, vp], i32),
+        "sg_plan_get_info": ([vp, P(SgPlanInfo)], i32),
+        "sg_plan_autotune": ([vp, vp, vp, vp], i32),
+        "sg_plan_destroy": ([vp], i32),
+        "sg_integrate": ([vp, P(SgProblem), i32, vp, vp, vp, vp], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(st: int, ctx=None):
+    if st != 0:
+        msg = ""
+        if ctx is not None and getattr(ctx, "value", None):
+            msg = lib().sg_last_error(ctx).decode(errors="replace")
+        raise SgError(st, msg)
+
+
+# ------------------------------------------------------------- host calls
+def counts(d: int, q: int, rule: str):
+    """(n_multi, n_points_rep, n_points_unique) of the window of (2.6)."""
+    a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    _check(lib().sg_counts(d, q, RULES[rule], ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def rule_table(rule: str, level: int):
+    n = ctypes.c_int32()
+    _check(lib().sg_rule_table(RULES[rule], level, None, None, ctypes.byref(n)))
+    x = np.zeros(n.value)
+    w = np.zeros(n.value)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(lib().sg_rule_table(RULES[rule], level, x.ctypes.data_as(dp), w.ctypes.data_as(dp), ctypes.byref(n)))
+    return x, w
+
+
+def coefficient(d: int, q: int, e: int) -> int:
+    c = ctypes.c_int64()
+    _check(lib().sg_coefficient(d, q, e, ctypes.byref(c)))
+    return c.value
+
+
+def unrank(d: int, q: int, rank: int):
+    K = max(1, q - d)
+    co = (ctypes.c_int32 * K)()
+    le = (ctypes.c_int32 * K)()
+    nnz = ctypes.c_int32()
+    _check(lib().sg_unrank(d, q, rank, co, le, ctypes.byref(nnz)))
+    return [(co[i], le[i]) for i in range(nnz.value)]
+
+
+# ------------------------------------------------------------- device side
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream) if stream.cuda_stream else None
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Context:
+    """Owns an sg_context on the current device."""
+
+    def __init__(self):
+        self.handle = ctypes.c_void_p()
+        _check(lib().sg_context_create(ctypes.byref(self.handle)))
+
+    def close(self):
+        if self.handle:
+            lib().sg_context_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx: Optional[Context] = None
+
+
+def default_context() -> Context:
+    global _default_ctx
+    if _default_ctx is None:
+        _default_ctx = Context()
+    return _default_ctx
+
+
+def make_problems(problems) -> ctypes.Array:
+    """sg_problem array from objects with d, q, rule, family, param_offset."""
+    arr = (SgProblem * len(problems))()
+    for i, p in enumerate(problems):
+        arr[i] = SgProblem(p.d, p.q, RULES[p.rule], FAMILIES[p.family], p.param_offset)
+    return arr
+
+
+class Plan:
+    """A compiled batch: sg_plan_create / execute / execute_grad / destroy."""
+
+    def __init__(self, problems: Sequence, precision: str = "fp64", ctx: Optional[Context] = None):
+        self.ctx = ctx or default_context()
+        self.n = len(problems)
+        self.problems = list(problems)
+        self._arr = make_problems(problems)
+        self.handle = ctypes.c_void_p()
+        self.precision = precision
+        _check(lib().sg_plan_create(self.ctx.handle, self._arr, self.n, PRECISIONS[precision],
+                                    ctypes.byref(self.handle)), self.ctx.handle)
+
+    def info(self) -> dict:
+        inf = SgPlanInfo()
+        _check(lib().sg_plan_get_info(self.handle, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in SgPlanInfo._fields_}
+
+    def execute(self, params, out=None, bound=None, stream=None):
+        import torch
+        assert params.dtype == torch.float64 and params.is_cuda and params.is_contiguous()
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float64, device=params.device)
+        assert out.dtype == torch.float64 and out.numel() >= self.n and out.is_contiguous()
+        if bound is not None:
+            assert bound.dtype == torch.float64 and bound.numel() >= self.n and bound.is_contiguous()
+        _check(lib().sg_plan_execute(self.handle, _ptr(params), _ptr(out), _ptr(bound), _stream_ptr(stream)),
+               self.ctx.handle)
+        return out
+
+    def execute_grad(self, params, grad_out, grad_params=None, stream=None):
+        import torch
+        if grad_params is None:
+            grad_params = torch.zeros_like(params)
+        _check(lib().sg_plan_execute_grad(self.handle, _ptr(params), _ptr(grad_out), _ptr(grad_params),
+                                          _stream_ptr(stream)), self.ctx.handle)
+        return grad_params
+
+    def autotune(self, params, out, stream=None):
+        _check(lib().sg_plan_autotune(self.handle, _ptr(params), _ptr(out), _stream_ptr(stream)), self.ctx.handle)
+
+    def close(self):
+        if self.handle:
+            lib().sg_plan_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def integrate_one(problem, params, precision: str = "fp64", out=None, bound=None, stream=None,
+                  ctx: Optional[Context] = None):
+    """Plain single-integrand path (one launch, no plan, no graph)."""
+    import torch
+    ctx = ctx or default_context()
+    pr = SgProblem(problem.d, problem.q, RULES[problem.rule], FAMILIES[problem.family], 0)
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=params.device)
+    _check(lib().sg_integrate(ctx.handle, ctypes.byref(pr), PRECISIONS[precision], _ptr(params), _ptr(out),
+                              _ptr(bound), _stream_ptr(stream)), ctx.handle)
+    return out
+
+
+def unrank_device(d: int, q: int, rank0: int, count: int, max_nnz: Optional[int] = None, stream=None,
+                  ctx: Optional[Context] = None):
+    import torch
+    ctx = ctx or default_context()
+    K = q - d
+    max_nnz = max_nnz or max(1, K)
+    coords = torch.empty((max(count, 1), max_nnz), dtype=torch.int32, device="cuda")
+    levels = torch.empty_like(coords)
+    nnz = torch.empty(max(count, 1), dtype=torch.int32, device="cuda")
+    _check(lib().sg_unrank_device(ctx.handle, d, q, rank0, count, max_nnz, _ptr(coords), _ptr(levels), _ptr(nnz),
+                                  _stream_ptr(stream)), ctx.handle)
+    return coords[:count], levels[:count], nnz[:count]

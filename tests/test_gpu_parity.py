@@ -1,0 +1,314 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances: FP64 mode within 1e-12 relative (for the oscillatory family,
+whose values lie in [-1, 1], relative to max(|Q|, 1)); the FP32-compensated
+mode within the a-priori bound the library states for every result, and
+within 1e-7 relative on the standard workloads.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def api(torch_dev):
+    from paper_2210_14313_amd import api as A, native
+    native.lib()
+    return A
+
+
+def _scale(batch, ref):
+    fam = np.array([p.family for p in batch.problems])
+    return np.where(fam == "oscillatory", np.maximum(np.abs(ref), 1.0), np.abs(ref))
+
+
+def _run(api, batch, precision, with_bound=True):
+    vals, bnd = api.integrate(batch, precision, with_bound=with_bound)
+    return vals.cpu().numpy(), (bnd.cpu().numpy() if bnd is not None else None)
+
+
+def _point_ref(orc, batch):
+    return np.array([orc.smolyak_points(p.d, p.q, p.rule, p.family, batch.param_slice(i))["q"]
+                     for i, p in enumerate(batch.problems)])
+
+
+def _fact_ref(orc, batch):
+    return orc.batch_factorised(batch)
+
+
+# ---------------------------------------------------------------- small
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_small_random_batches_fp64(api, orc, seed):
+    from paper_2210_14313_amd import workloads as W
+    b = W.random_small(seed, 64, d_range=(1, 12), k_range=(0, 5))
+    say("case small_random fp64 seed", seed)
+    got, bnd = _run(api, b, "fp64")
+    ref = _point_ref(orc, b)
+    err = np.abs(got - ref) / _scale(b, ref)
+    assert np.max(err) <= 1e-12, (np.argmax(err), np.max(err))
+    assert np.all(np.abs(got - ref) <= bnd + 1e-300)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_small_random_batches_fp32c(api, orc, seed):
+    from paper_2210_14313_amd import workloads as W
+    b = W.random_small(seed, 64, d_range=(1, 12), k_range=(0, 5))
+    say("case small_random fp32c seed", seed)
+    got, bnd = _run(api, b, "fp32c")
+    ref = _point_ref(orc, b)
+    assert np.all(np.abs(got - ref) <= bnd), np.max(np.abs(got - ref) / bnd)
+    assert np.max(np.abs(got - ref) / _scale(b, ref)) <= 1e-7
+
+
+# -------------------------------------------- several tiles, ragged tails
+TILE_CASES = [(63, 2, "cc", "exp_sum"), (64, 3, "gl", "oscillatory"), (65, 2, "tr", "product_peak"),
+              (255, 2, "cc", "oscillatory"), (257, 2, "gl", "exp_sum"), (300, 2, "cc", "product_peak"),
+              (513, 1, "tr", "exp_sum"), (40, 8, "cc", "exp_sum"), (20, 8, "gl", "oscillatory"),
+              (1, 8, "cc", "exp_sum"), (1, 0, "gl", "oscillatory"), (7, 0, "cc", "product_peak"),
+              (2, 8, "gl_paper", "product_peak"), (129, 3, "gl_paper", "exp_sum")]
+
+
+@pytest.mark.parametrize("d,K,rule,family", TILE_CASES)
+def test_tiles_and_edges(api, orc, d, K, rule, family):
+    from paper_2210_14313_amd import workloads as W
+    rng = np.random.default_rng(d * 1000 + K)
+    b = W.single(d, d + K, rule, family, W.draw_params(rng, family, d))
+    say("case tile", d, K, rule, family)
+    npts = orc.counts.counts_by_generating_function(d, d + K, rule)["n_points_rep"]
+    ref = _point_ref(orc, b) if npts <= 3e8 else _fact_ref(orc, b)
+    for prec, tol in (("fp64", 1e-12), ("fp32c", 1e-7)):
+        got, bnd = _run(api, b, prec)
+        err = np.abs(got - ref) / _scale(b, ref)
+        assert err[0] <= tol, (prec, got, ref, err)
+        assert np.abs(got - ref)[0] <= bnd[0], (prec, got, ref, bnd)
+
+
+def test_large_arguments_take_the_exact_branch(api, orc):
+    # |parameter * y| > 1/2 switches from the series to expm1 / sin
+    from paper_2210_14313_amd import workloads as W
+    for fam, params in (("exp_sum", np.array([3.0, -2.5, 0.2, 6.0])),
+                        ("oscillatory", np.array([0.3, 7.0, -3.0, 1.5, 12.0]))):
+        b = W.single(4, 9, "cc", fam, params)
+        say("case large-arguments", fam)
+        ref = _point_ref(orc, b)
+        got, bnd = _run(api, b, "fp64")
+        assert abs(got[0] - ref[0]) <= 1e-12 * _scale(b, ref)[0]
+        got, bnd = _run(api, b, "fp32c")
+        assert abs(got[0] - ref[0]) <= bnd[0]
+
+
+# ---------------------------------------------------------- full sizes
+def test_plain_exp_d10_full(api, orc):
+    from paper_2210_14313_amd import workloads as W
+    b = W.plain_exp_d10()
+    say("case plain_exp_d10 full")
+    ref = _point_ref(orc, b)
+    got, _ = _run(api, b, "fp64")
+    assert abs(got[0] - ref[0]) <= 1e-12 * abs(ref[0])
+    got32, bnd = _run(api, b, "fp32c")
+    assert abs(got32[0] - ref[0]) <= bnd[0]
+
+
+def _golden_rows():
+    path = os.path.join(GOLDEN, "oracle_full_size.json")
+    if not os.path.exists(path):
+        return []
+    return json.load(open(path))["rows"]
+
+
+@pytest.mark.parametrize("row", _golden_rows(), ids=lambda r: f"{r['workload']}-{r['index']}")
+def test_full_size_against_stored_point_oracle(api, orc, row):
+    from paper_2210_14313_amd import workloads as W
+    batch = W.STANDARD[row["workload"]]()
+    b = batch.subset([row["index"]])
+    p = b.problems[0]
+    assert (p.d, p.q, p.rule, p.family) == (row["d"], row["q"], row["rule"], row["family"])
+    ref = row["points_hi"] + row["points_lo"]
+    say("case full-size", row["workload"], row["index"], p.family, p.rule)
+    got, _ = _run(api, b, "fp64")
+    scale = max(abs(ref), 1.0) if p.family == "oscillatory" else abs(ref)
+    assert abs(got[0] - ref) <= 1e-12 * scale, (got, ref)
+    got32, bnd = _run(api, b, "fp32c")
+    assert abs(got32[0] - ref) <= bnd[0]
+    assert abs(got32[0] - ref) <= 1e-7 * scale
+
+
+def test_batched_uneven_full_launch(api, orc):
+    """The 4096-integrand batch in the launch configuration the benchmark
+    times: every result against the binary128 oracle, and a sample of the
+    cheaper integrands against the point-by-point oracle."""
+    import torch
+    from paper_2210_14313_amd import native, workloads as W
+    b = W.batched_uneven()
+    params = api.params_tensor(b)
+    ref = _fact_ref(orc, b)
+    scale = _scale(b, ref)
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    for prec, tol in (("fp64", 1e-12), ("fp32c", 1e-7)):
+        say("case batched_uneven", prec)
+        plan = native.Plan(b.problems, prec)
+        out = torch.empty(len(b), dtype=torch.float64, device="cuda")
+        bnd = torch.empty_like(out)
+        with torch.cuda.stream(stream):
+            plan.execute(params, out, bnd, stream=stream)     # captured graph
+            plan.execute(params, out, bnd, stream=stream)     # replay
+        stream.synchronize()
+        got, bd = out.cpu().numpy(), bnd.cpu().numpy()
+        err = np.abs(got - ref) / scale
+        assert np.max(err) <= tol, (prec, int(np.argmax(err)), float(np.max(err)))
+        assert np.all(np.abs(got - ref) <= bd), prec
+        plan.close()
+    # sampled integrands against the point oracle
+    npts = np.array([orc.counts.counts_by_generating_function(p.d, p.q, p.rule)["n_points_rep"]
+                     for p in b.problems])
+    idx = [int(i) for i in np.nonzero(npts <= 2e7)[0][:24]]
+    assert len(idx) >= 8
+    sub = b.subset(idx)
+    pref = _point_ref(orc, sub)
+    got, _ = _run(api, sub, "fp64")
+    assert np.max(np.abs(got - pref) / _scale(sub, pref)) <= 1e-12
+
+
+def test_gradient_workload_forward(api, orc):
+    from paper_2210_14313_amd import workloads as W
+    b = W.gradient_osc_d200()
+    say("case gradient_osc_d200 forward")
+    ref = _fact_ref(orc, b)
+    got, _ = _run(api, b, "fp64")
+    assert np.max(np.abs(got - ref) / _scale(b, ref)) <= 1e-12
+
+
+# -------------------------------------------------- determinism and paths
+def test_determinism_graph_and_plain_path(api, orc):
+    import torch
+    from paper_2210_14313_amd import native, workloads as W
+    b = W.random_small(9, 100, d_range=(1, 300), k_range=(0, 6))
+    params = api.params_tensor(b)
+    say("case determinism")
+    for prec in ("fp64", "fp32c"):
+        plan = native.Plan(b.problems, prec)
+        a = plan.execute(params).clone()           # default stream: no graph
+        c = plan.execute(params).clone()
+        assert torch.equal(a, c)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        outs = []
+        for _ in range(3):                         # capture, then replays
+            o = torch.empty_like(a)
+            s.wait_stream(torch.cuda.current_stream())
+            plan.execute(params, o, stream=s)
+            s.synchronize()
+            outs.append(o)
+        o = torch.empty_like(a)
+        s.wait_stream(torch.cuda.current_stream())
+        for _ in range(3):
+            plan.execute(params, o, stream=s)
+            s.synchronize()
+            assert torch.equal(o, a)
+        for o in outs:
+            assert torch.equal(o, a)
+        plan.close()
+        # plain single-integrand path
+        for i in range(0, len(b), 17):
+            p = b.problems[i]
+            pi = torch.as_tensor(b.param_slice(i)).cuda()
+            v = native.integrate_one(p, pi, prec).item()
+            assert abs(v - a[i].item()) <= 1e-14 * max(abs(a[i].item()), 1.0)
+
+
+def test_parameter_update_between_replays(api, orc):
+    import torch
+    from paper_2210_14313_amd import native, workloads as W
+    b = W.random_small(10, 32, d_range=(2, 40), k_range=(1, 5))
+    params = api.params_tensor(b)
+    plan = native.Plan(b.problems, "fp64")
+    s = torch.cuda.Stream()
+    out = torch.empty(len(b), dtype=torch.float64, device="cuda")
+    s.wait_stream(torch.cuda.current_stream())
+    plan.execute(params, out, stream=s)
+    s.synchronize()
+    say("case parameter update")
+    rng = np.random.default_rng(11)
+    b2 = W.concat([W.single(p.d, p.q, p.rule, p.family, W.draw_params(rng, p.family, p.d))
+                   for p in b.problems])
+    assert len(b2.params) == len(b.params)
+    params.copy_(torch.as_tensor(b2.params))
+    s.wait_stream(torch.cuda.current_stream())
+    plan.execute(params, out, stream=s)            # replay with new values
+    s.synchronize()
+    ref = _point_ref(orc, b2)
+    got = out.cpu().numpy()
+    assert np.max(np.abs(got - ref) / _scale(b2, ref)) <= 1e-12
+    plan.close()
+
+
+# ------------------------------------------------------------ unranking
+@pytest.mark.parametrize("d,q", [(1, 5), (3, 7), (6, 10), (9, 11), (12, 12)])
+def test_unrank_device_bit_exact(api, orc, d, q):
+    from paper_2210_14313_amd import native
+    say("case unrank", d, q)
+    total, co, le, nz = orc.enumerate_window(d, q)
+    K = q - d
+    c, l, n = native.unrank_device(d, q, 0, total, max_nnz=max(1, K))
+    c, l, n = c.cpu().numpy(), l.cpu().numpy(), n.cpu().numpy()
+    assert np.array_equal(n, nz)
+    for r in range(total):
+        k = nz[r]
+        assert np.array_equal(c[r, :k], co[r, :k]) and np.array_equal(l[r, :k], le[r, :k])
+
+
+def test_unrank_device_large_window(api):
+    from paper_2210_14313_amd import native
+    d, q = 1000, 1003
+    n = native.counts(d, q, "cc")[0]
+    say("case unrank large")
+    r0 = n - 100000
+    c, l, z = native.unrank_device(d, q, r0, 100000)
+    c, l, z = c.cpu().numpy(), l.cpu().numpy(), z.cpu().numpy()
+    for r in list(range(0, 100000, 997)) + [99999]:
+        ref = native.unrank(d, q, r0 + r)
+        assert [(int(c[r, k]), int(l[r, k])) for k in range(z[r])] == ref
+
+
+# --------------------------------------------------------------- errors
+def test_errors_are_reported_before_launch(api):
+    import torch
+    from paper_2210_14313_amd import native, workloads as W
+    bad = W.single(5, 5 + native.MAX_K + 1, "cc", "exp_sum", np.zeros(5))
+    with pytest.raises(native.SgError) as e:
+        native.Plan(bad.problems, "fp64")
+    assert e.value.status == 2
+    with pytest.raises(native.SgError) as e:
+        native.Plan([], "fp64")
+    assert e.value.status == 1
+    bad = W.single(5, 4, "cc", "exp_sum", np.zeros(5))
+    with pytest.raises(native.SgError) as e:
+        native.Plan(bad.problems, "fp64")
+    assert e.value.status == 1
+    ok = W.single(3, 5, "cc", "exp_sum", np.zeros(3))
+    plan = native.Plan(ok.problems, "fp64")
+    assert native.lib().sg_plan_execute(plan.handle, None, None, None, None) == 1
+    with pytest.raises(native.SgError) as e:
+        native.unrank_device(3, 5, 5, 100)
+    assert e.value.status == 1
+    plan.close()
