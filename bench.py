@@ -129,6 +129,7 @@ def main():
         got = out.cpu().numpy()
         bnd = bound.cpu().numpy()
         info = plan.info()
+        log(f"  {precision}: block {info['block_threads']}, kernel {np.mean(kern_ms) * 1e3:.2f} us")
         plan.close()
         return dict(ms_per_step=(t1 - t0) * 1e3 / steps, kernel_ms=float(np.mean(kern_ms)),
                     kernel_ms_median=float(np.median(kern_ms)), got=got, bound=bnd, info=info)

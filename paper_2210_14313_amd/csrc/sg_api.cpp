@@ -419,6 +419,10 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
     auto tk = ctx->tuned.find(p->tune_key);
     if (tk != ctx->tuned.end()) p->cfg = tk->second;
     else p->cfg.block = round_block(maxd);
+    if (const char* fb = std::getenv("SGMDI_BLOCK")) {   // debug / profiling override
+        const int b = std::atoi(fb);
+        if (b == 64 || b == 128 || b == 256) p->cfg.block = b;
+    }
     info.block_threads = p->cfg.block;
     info.grid_blocks = n;
     p->info = info;

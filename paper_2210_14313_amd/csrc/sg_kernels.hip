@@ -117,15 +117,11 @@ __device__ __forceinline__ float pair32(const CoordParam& cp, double y)
             return -4.0f * sn * sn;
         }
     } else {
-        const float beta = (float)cp.p0, hv = (float)cp.p1, yf = (float)y;
-        const float y2 = yf * yf;
-        const float dp = yf + hv, dm = yf - hv;
-        const float Dp = fmaf(dp, dp, beta), Dm = fmaf(dm, dm, beta);
-        const float num = 2.0f * y2 * (fmaf(3.0f * hv, hv, -beta) - y2);
-        const float den = Dp * Dm;
-        float r = __builtin_amdgcn_rcpf(den);
-        r = fmaf(r, fmaf(-den, r, 1.0f), r);       // one Newton step
-        return num * r;
+        // The product-peak pair value is a rational function with no
+        // transcendental; its cancellation-prone parts (y^2, the bracket and
+        // the two denominators) are formed in FP64 and the value is rounded
+        // once, which keeps it within half an FP32 ulp of the exact value.
+        return (float)pair64<FAM_PEAK>(cp, y);
     }
 }
 
