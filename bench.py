@@ -129,7 +129,8 @@ def main():
         got = out.cpu().numpy()
         bnd = bound.cpu().numpy()
         info = plan.info()
-        log(f"  {precision}: block {info['block_threads']}, kernel {np.mean(kern_ms) * 1e3:.2f} us")
+        log(f"  {precision}: waves_cap {info['waves_cap']} graph {info['graph']} grid {info['grid_blocks']}, "
+            f"kernel {np.mean(kern_ms) * 1e3:.2f} us, step {(t1 - t0) * 1e6 / steps:.2f} us")
         plan.close()
         return dict(ms_per_step=(t1 - t0) * 1e3 / steps, kernel_ms=float(np.mean(kern_ms)),
                     kernel_ms_median=float(np.median(kern_ms)), got=got, bound=bnd, info=info)
@@ -224,6 +225,45 @@ def main():
                 tti[f"{p.rule}_{prec}"] = {"median_s": statistics.median(ts), "cold_s": cold, "value": v,
                                            "rel_err_vs_oracle": abs(v - ex) / abs(ex)}
         extras["time_to_integral_d1000"] = tti
+        # reverse sweep on the gradient workload (256 oscillatory, d = 200, q = 205)
+        gb = W.gradient_osc_d200()
+        gref = np.zeros_like(gb.params)
+        for i, p in enumerate(gb.problems):
+            gref[p.param_offset:p.param_offset + p.d + 1] = oracle.smolyak_factorised_grad(
+                p.d, p.q, p.rule, p.family, gb.param_slice(i))
+        gparams = api.params_tensor(gb, dev)
+        gout = torch.ones(len(gb), dtype=torch.float64, device=dev)
+        adj = {}
+        for prec in ("fp32c", "fp64"):
+            plan = native.Plan(gb.problems, prec)
+            gp = torch.zeros_like(gparams)
+            s.wait_stream(torch.cuda.current_stream())
+            for _ in range(3):
+                plan.execute_grad(gparams, gout, gp, stream=s)
+            torch.cuda.synchronize()
+            reps = 50
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            for _ in range(reps):
+                plan.execute_grad(gparams, gout, gp, stream=s)
+            e1.record(s)
+            torch.cuda.synchronize()
+            fwd = torch.empty(len(gb), dtype=torch.float64, device=dev)
+            f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            f0.record(s)
+            for _ in range(reps):
+                plan.execute(gparams, fwd, stream=s)
+            f1.record(s)
+            torch.cuda.synchronize()
+            g = gp.cpu().numpy()
+            errs = []
+            for i, p in enumerate(gb.problems):
+                sl = slice(p.param_offset, p.param_offset + p.d + 1)
+                errs.append(np.max(np.abs(g[sl] - gref[sl])) / np.max(np.abs(gref[sl])))
+            adj[prec] = {"grad_ms": e0.elapsed_time(e1) / reps, "forward_ms": f0.elapsed_time(f1) / reps,
+                         "max_rel_err_vs_oracle_grad": float(np.max(errs))}
+            plan.close()
+        extras["adjoint_gradient_osc_d200_n256"] = adj
         result["extras"] = extras
 
     if not args.no_cpu_baseline:

@@ -171,7 +171,8 @@ sg_status sg_plan_create(sg_context *ctx, const sg_problem *problems, int32_t n,
 /* Evaluate every integrand of the plan.  params_dev: the batch's float64
  * parameter array (device); out_dev: n float64 results in problem order
  * (device); bound_dev: NULL or n float64 a-priori bounds on |result - exact
- * Smolyak value| (device).  The launch is captured into a HIP graph on the
+ * Smolyak value| (device).  On a non-default stream, unless the autotuner
+ * chose direct launches, the launch is captured into a HIP graph on the
  * first call with a given (params, out, bound, stream) and replayed after.
  * Errors: INVALID_ARGUMENT (NULL plan/params/out), DEVICE, CAPTURE. */
 sg_status sg_plan_execute(sg_plan *plan, const double *params_dev, double *out_dev,
@@ -195,7 +196,10 @@ sg_status sg_plan_execute_grad(sg_plan *plan, const double *params_dev, const do
  *   merge_flops       floating-point operations of the truncated-polynomial
  *                     products of the sweep (K(K-1)/2 multiply-adds and K
  *                     adds per unit, multiply-add counted as 2);
- *   block_threads, grid_blocks: the launch shape the plan uses. */
+ *   block_threads, grid_blocks: the launch shape the plan uses;
+ *   waves_cap: most waves one integrand spans; graph: 1 if executions on a
+ *   non-default stream replay a captured graph, 0 if they launch directly
+ *   (both knobs are chosen by sg_plan_autotune). */
 typedef struct {
     uint64_t effective_points;
     uint64_t units;
@@ -204,13 +208,17 @@ typedef struct {
     uint64_t merge_flops;
     int32_t block_threads;
     int32_t grid_blocks;
+    int32_t waves_cap;
+    int32_t graph;
 } sg_plan_info;
 
 sg_status sg_plan_get_info(const sg_plan *plan, sg_plan_info *info);
 
 /* Time candidate schedules for this plan on `stream` with HIP events and
  * keep the fastest (stored in the context; later plans with the same shape
- * class reuse it).  Runs the forward launch repeatedly on params_dev/out_dev.
+ * class reuse it): the most waves one integrand may span (1, 2, 4) and, on a
+ * non-default stream, graph replay versus direct launch.  Runs the forward
+ * launch repeatedly on params_dev/out_dev (their contents are overwritten).
  * Errors: INVALID_ARGUMENT, DEVICE. */
 sg_status sg_plan_autotune(sg_plan *plan, const double *params_dev, double *out_dev, void *stream);
 

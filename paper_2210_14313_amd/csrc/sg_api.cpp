@@ -20,9 +20,14 @@ namespace {
 
 struct PlainEntry {
     ProbDev* probs = nullptr;
-    TableDev* tabs = nullptr;
+    WGDesc* wgs = nullptr;
     double* pool64 = nullptr;
     float* pool32 = nullptr;
+};
+
+struct Records {
+    std::vector<double> r64;
+    std::vector<float> r32;
 };
 
 struct GraphEntry {
@@ -40,7 +45,8 @@ struct sg_context {
     int device = 0;
     std::string last_error;
     std::map<std::pair<int, int>, std::unique_ptr<DeltaTable>> tables;
-    std::map<std::string, LaunchCfg> tuned;
+    std::map<std::pair<int, int>, std::unique_ptr<Records>> records;
+    std::map<std::string, std::pair<int, bool>> tuned;   // plan shape -> (waves cap, graph)
     std::map<std::tuple<int, int, int, int>, PlainEntry> plain;
     std::map<std::pair<int, int>, uint64_t*> unrank_tables;
     int live_plans = 0;
@@ -52,10 +58,17 @@ struct sg_plan {
     int n = 0;
     std::vector<sg_problem> problems;
     ProbDev* d_probs = nullptr;
-    TableDev* d_tabs = nullptr;
+    WGDesc* d_wgs = nullptr;
     double* d_pool64 = nullptr;
     float* d_pool32 = nullptr;
-    LaunchCfg cfg;
+    std::vector<ProbDev> probs;     // plan order (longest first)
+    int wmax = 4;                   // waves-per-problem cap
+    bool use_graph = true;          // replay a captured graph (else direct launch)
+    bool params_disjoint = true;    // problems' parameter ranges do not overlap
+    double* d_ws = nullptr;         // reverse-sweep workspace (sum d*K doubles), lazy
+    size_t ws_elems = 0;
+    int nwg = 0;
+    size_t wg_capacity = 0;
     sg_plan_info info{};
     std::string tune_key;
     std::vector<GraphEntry> graphs;
@@ -112,6 +125,65 @@ const DeltaTable* get_table(sg_context* ctx, int rule, int K, sg_status& st)
     return r;
 }
 
+const Records* get_records(sg_context* ctx, int rule, int K, sg_status& st)
+{
+    auto key = std::make_pair(rule, K);
+    auto it = ctx->records.find(key);
+    if (it != ctx->records.end()) return it->second.get();
+    const DeltaTable* t = get_table(ctx, rule, K, st);
+    if (!t) return nullptr;
+    std::unique_ptr<Records> r(new Records());
+    std::string err;
+    if (!build_records(*t, r->r64, r->r32, err)) {
+        st = fail(ctx, SG_ERR_INVALID_ARGUMENT, err);
+        return nullptr;
+    }
+    const Records* out = r.get();
+    ctx->records[key] = std::move(r);
+    return out;
+}
+
+int waves_for(int d, int wmax)
+{
+    int w = (d + 63) / 64;
+    if (w > wmax) w = wmax;
+    if (w == 3) w = 4;
+    return w < 1 ? 1 : w;
+}
+
+// Pack problems (in plan order) into 4-wave workgroups, first fit.  A
+// problem of w waves takes w consecutive slots of one workgroup.
+std::vector<WGDesc> pack_workgroups(const std::vector<ProbDev>& probs, int wmax)
+{
+    std::vector<WGDesc> wgs;
+    std::vector<int> used;
+    std::vector<int> open;   // indices of workgroups with free slots
+    for (size_t k = 0; k < probs.size(); ++k) {
+        const int w = waves_for(probs[k].d, wmax);
+        int target = -1;
+        for (size_t o = 0; o < open.size(); ++o) {
+            if (4 - used[open[o]] >= w) { target = open[o]; break; }
+        }
+        if (target < 0) {
+            WGDesc e;
+            for (int i = 0; i < 4; ++i) { e.slot[i].prob = -1; e.slot[i].rank = 0; e.slot[i].group = 1; }
+            wgs.push_back(e);
+            used.push_back(0);
+            target = (int)wgs.size() - 1;
+            open.push_back(target);
+        }
+        for (int r = 0; r < w; ++r) {
+            WaveSlot& sl = wgs[target].slot[used[target] + r];
+            sl.prob = (int32_t)k;
+            sl.rank = (int16_t)r;
+            sl.group = (int16_t)w;
+        }
+        used[target] += w;
+        if (used[target] == 4) open.erase(std::find(open.begin(), open.end(), target));
+    }
+    return wgs;
+}
+
 uint64_t macs_of(const DeltaTable& t)
 {
     uint64_t m = 0;
@@ -132,32 +204,6 @@ uint64_t sat_mul(uint64_t a, uint64_t b)
 {
     if (a == 0 || b == 0) return 0;
     return a > UINT64_MAX / b ? UINT64_MAX : a * b;
-}
-
-int round_block(int want)
-{
-    int b = 64;
-    while (b < want && b < 256) b *= 2;
-    return b;
-}
-
-// Append one table to the pools and fill its device view.
-void append_table(const DeltaTable& t, std::vector<double>& p64, std::vector<float>& p32, TableDev& td)
-{
-    std::memset(&td, 0, sizeof td);
-    td.K = t.K;
-    td.npairs = t.npairs;
-    td.nested = t.nested ? 1 : 0;
-    for (int i = 0; i < kMaxK + 3; ++i)
-        td.level_begin[i] = i < (int)t.level_begin.size() ? t.level_begin[i] : t.npairs;
-    td.off64 = (int64_t)p64.size();
-    td.off32 = (int64_t)p32.size();
-    p64.insert(p64.end(), t.y.begin(), t.y.end());
-    p64.insert(p64.end(), t.dw.begin(), t.dw.end());
-    p64.insert(p64.end(), t.wabs.begin(), t.wabs.end());
-    p32.insert(p32.end(), t.y32.begin(), t.y32.end());
-    p32.insert(p32.end(), t.dw_hi.begin(), t.dw_hi.end());
-    p32.insert(p32.end(), t.dw_lo.begin(), t.dw_lo.end());
 }
 
 template <class T>
@@ -230,7 +276,7 @@ sg_status sg_context_destroy(sg_context* ctx)
     if (!ctx) return SG_OK;
     for (auto& kv : ctx->plain) {
         hipFree(kv.second.probs);
-        hipFree(kv.second.tabs);
+        hipFree(kv.second.wgs);
         hipFree(kv.second.pool64);
         hipFree(kv.second.pool32);
     }
@@ -355,35 +401,33 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
     p->n = n;
     p->problems.assign(problems, problems + n);
 
-    // tables
-    std::map<std::pair<int, int>, int> tindex;
-    std::vector<const DeltaTable*> tlist;
-    std::vector<int> ptab(n);
-    for (int i = 0; i < n; ++i) {
-        auto key = std::make_pair(problems[i].rule, problems[i].q - problems[i].d);
-        auto it = tindex.find(key);
-        if (it == tindex.end()) {
-            sg_status st = SG_OK;
-            const DeltaTable* t = get_table(ctx, key.first, key.second, st);
-            if (!t) return st;
-            tindex[key] = (int)tlist.size();
-            ptab[i] = (int)tlist.size();
-            tlist.push_back(t);
-        } else {
-            ptab[i] = it->second;
-        }
-    }
+    // record tables, one per distinct (rule, K), in two pools
+    std::map<std::pair<int, int>, std::pair<int64_t, int64_t>> toff;
     std::vector<double> p64;
     std::vector<float> p32;
-    std::vector<TableDev> tdev(tlist.size());
-    for (size_t k = 0; k < tlist.size(); ++k) append_table(*tlist[k], p64, p32, tdev[k]);
+    std::vector<const DeltaTable*> ptab(n);
+    for (int i = 0; i < n; ++i) {
+        auto key = std::make_pair(problems[i].rule, problems[i].q - problems[i].d);
+        sg_status st = SG_OK;
+        const DeltaTable* t = get_table(ctx, key.first, key.second, st);
+        if (!t) return st;
+        ptab[i] = t;
+        if (toff.count(key)) continue;
+        const Records* r = get_records(ctx, key.first, key.second, st);
+        if (!r) return st;
+        toff[key] = std::make_pair((int64_t)p64.size(), (int64_t)p32.size());
+        p64.insert(p64.end(), r->r64.begin(), r->r64.end());
+        p32.insert(p32.end(), r->r32.begin(), r->r32.end());
+        while (p64.size() % 8) p64.push_back(0.0);     // 64-byte aligned tables
+        while (p32.size() % 16) p32.push_back(0.0f);
+    }
 
     // longest-processing-time order
     std::vector<double> cost(n);
     sg_plan_info info{};
     int maxd = 1;
     for (int i = 0; i < n; ++i) {
-        const DeltaTable& t = *tlist[ptab[i]];
+        const DeltaTable& t = *ptab[i];
         const uint64_t d = (uint64_t)problems[i].d;
         const uint64_t K = (uint64_t)t.K;
         const uint64_t macs = macs_of(t);
@@ -394,42 +438,67 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
         info.units = sat_add(info.units, d);
         info.pair_evals = sat_add(info.pair_evals, sat_mul(d, (uint64_t)t.npairs));
         info.macs = sat_add(info.macs, sat_mul(d, macs));
-        info.merge_flops = sat_add(info.merge_flops, sat_mul(d, K * (K - (K ? 1 : 0)) + K));
+        info.merge_flops = sat_add(info.merge_flops, sat_mul(d, K * K));
         maxd = std::max(maxd, problems[i].d);
     }
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-    std::vector<ProbDev> pdev(n);
+    p->probs.resize(n);
     for (int k = 0; k < n; ++k) {
         const int i = order[k];
-        ProbDev& r = pdev[k];
+        ProbDev& r = p->probs[k];
+        const int K = problems[i].q - problems[i].d;
         r.d = problems[i].d;
-        r.K = problems[i].q - problems[i].d;
+        r.K = K;
         r.family = problems[i].family;
-        r.table = ptab[i];
+        r.rclass = rule_class_of(problems[i].rule);
         r.param_offset = problems[i].param_offset;
+        const auto& o = toff[std::make_pair(problems[i].rule, K)];
+        r.off64 = o.first;
+        r.off32 = o.second;
         r.out_index = i;
-        r.pad = 0;
+        r.waves = 0;
+        r.ws_off = (int64_t)p->ws_elems;
+        p->ws_elems += (size_t)r.d * (size_t)(K > 0 ? K : 1);
+    }
+    {
+        // parameter ranges must be disjoint for the reverse sweep to write them
+        std::vector<std::pair<int64_t, int64_t>> rg(n);
+        for (int i = 0; i < n; ++i) {
+            const int64_t len = problems[i].family == SG_FAMILY_EXP_SUM ? problems[i].d
+                                : problems[i].family == SG_FAMILY_OSCILLATORY ? (int64_t)problems[i].d + 1
+                                                                              : 2 * (int64_t)problems[i].d;
+            rg[i] = std::make_pair(problems[i].param_offset, problems[i].param_offset + len);
+        }
+        std::sort(rg.begin(), rg.end());
+        for (int i = 1; i < n; ++i)
+            if (rg[i].first < rg[i - 1].second) p->params_disjoint = false;
     }
 
     char key[128];
     snprintf(key, sizeof key, "p%d_n%d_maxd%d", precision, n, maxd);
     p->tune_key = key;
     auto tk = ctx->tuned.find(p->tune_key);
-    if (tk != ctx->tuned.end()) p->cfg = tk->second;
-    else p->cfg.block = round_block(maxd);
-    if (const char* fb = std::getenv("SGMDI_BLOCK")) {   // debug / profiling override
-        const int b = std::atoi(fb);
-        if (b == 64 || b == 128 || b == 256) p->cfg.block = b;
+    p->wmax = tk != ctx->tuned.end() ? tk->second.first : 4;
+    p->use_graph = tk != ctx->tuned.end() ? tk->second.second : true;
+    if (const char* fw = std::getenv("SGMDI_WMAX")) {   // debug / profiling override
+        const int w = std::atoi(fw);
+        if (w == 1 || w == 2 || w == 4) p->wmax = w;
     }
-    info.block_threads = p->cfg.block;
-    info.grid_blocks = n;
+    std::vector<WGDesc> wgs = pack_workgroups(p->probs, p->wmax);
+    for (auto& pr : p->probs) pr.waves = waves_for(pr.d, p->wmax);
+    p->nwg = (int)wgs.size();
+    info.block_threads = 256;
+    info.grid_blocks = p->nwg;
+    info.waves_cap = p->wmax;
+    info.graph = p->use_graph ? 1 : 0;
     p->info = info;
 
     sg_status st;
-    if ((st = upload(ctx, &p->d_probs, pdev.data(), pdev.size())) != SG_OK) return st;
-    if ((st = upload(ctx, &p->d_tabs, tdev.data(), tdev.size())) != SG_OK) return st;
+    if ((st = upload(ctx, &p->d_probs, p->probs.data(), p->probs.size())) != SG_OK) return st;
+    if ((st = upload(ctx, &p->d_wgs, wgs.data(), wgs.size())) != SG_OK) return st;
+    p->wg_capacity = wgs.size();
     if ((st = upload(ctx, &p->d_pool64, p64.data(), p64.size())) != SG_OK) return st;
     if ((st = upload(ctx, &p->d_pool32, p32.data(), p32.size())) != SG_OK) return st;
     ctx->live_plans++;
@@ -439,9 +508,31 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
 
 static sg_status plan_launch(sg_plan* p, const double* params, double* out, double* bound, void* stream)
 {
-    const int rc = launch_forward(p->precision, p->cfg, p->n, p->d_probs, p->d_tabs, p->d_pool64,
-                                  p->d_pool32, params, out, bound, stream);
+    const int rc = launch_forward(p->precision, p->nwg, p->d_wgs, p->d_probs, p->d_pool64, p->d_pool32, params,
+                                  out, bound, stream);
     if (rc != 0) return hip_fail(p->ctx, (hipError_t)rc, "forward launch");
+    return SG_OK;
+}
+
+// Re-pack the plan's workgroups for another waves-per-problem cap.
+static sg_status plan_repack(sg_plan* p, int wmax)
+{
+    std::vector<WGDesc> wgs = pack_workgroups(p->probs, wmax);
+    if (wgs.size() > p->wg_capacity) {
+        hipFree(p->d_wgs);
+        p->d_wgs = nullptr;
+        sg_status st = upload(p->ctx, &p->d_wgs, wgs.data(), wgs.size());
+        if (st != SG_OK) return st;
+        p->wg_capacity = wgs.size();
+    } else {
+        hipError_t e = hipMemcpy(p->d_wgs, wgs.data(), wgs.size() * sizeof(WGDesc), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(p->ctx, e, "hipMemcpy");
+    }
+    p->wmax = wmax;
+    p->nwg = (int)wgs.size();
+    p->info.grid_blocks = p->nwg;
+    p->info.waves_cap = wmax;
+    for (auto& pr : p->probs) pr.waves = waves_for(pr.d, wmax);
     return SG_OK;
 }
 
@@ -449,7 +540,7 @@ sg_status sg_plan_execute(sg_plan* p, const double* params_dev, double* out_dev,
 {
     if (!p) return SG_ERR_INVALID_ARGUMENT;
     if (!params_dev || !out_dev) return fail(p->ctx, SG_ERR_INVALID_ARGUMENT, "NULL params or out");
-    if (!stream || !graphs_enabled()) return plan_launch(p, params_dev, out_dev, bound_dev, stream);
+    if (!stream || !p->use_graph || !graphs_enabled()) return plan_launch(p, params_dev, out_dev, bound_dev, stream);
     for (GraphEntry& g : p->graphs) {
         if (g.params == params_dev && g.out == out_dev && g.bound == bound_dev && g.stream == stream) {
             hipError_t e = hipGraphLaunch(g.exec, (hipStream_t)stream);
@@ -461,8 +552,8 @@ sg_status sg_plan_execute(sg_plan* p, const double* params_dev, double* out_dev,
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return fail(p->ctx, SG_ERR_CAPTURE, std::string("begin capture: ") + hipGetErrorString(e));
-    const int rc = launch_forward(p->precision, p->cfg, p->n, p->d_probs, p->d_tabs, p->d_pool64,
-                                  p->d_pool32, params_dev, out_dev, bound_dev, stream);
+    const int rc = launch_forward(p->precision, p->nwg, p->d_wgs, p->d_probs, p->d_pool64, p->d_pool32,
+                                  params_dev, out_dev, bound_dev, stream);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(s, &graph);
     if (rc != 0 || e != hipSuccess || !graph) {
@@ -489,9 +580,23 @@ sg_status sg_plan_execute(sg_plan* p, const double* params_dev, double* out_dev,
 sg_status sg_plan_execute_grad(sg_plan* p, const double* params_dev, const double* grad_out_dev,
                                double* grad_params_dev, void* stream)
 {
-    (void)params_dev; (void)grad_out_dev; (void)grad_params_dev; (void)stream;
     if (!p) return SG_ERR_INVALID_ARGUMENT;
-    return fail(p->ctx, SG_ERR_UNSUPPORTED, "gradient not available in this build");
+    if (!params_dev || !grad_out_dev || !grad_params_dev)
+        return fail(p->ctx, SG_ERR_INVALID_ARGUMENT, "NULL params, grad_out or grad_params");
+    if (!p->params_disjoint)
+        return fail(p->ctx, SG_ERR_INVALID_ARGUMENT,
+                    "problems share parameters: the reverse sweep needs disjoint parameter ranges");
+    if (!p->d_ws) {
+        hipError_t e = hipMalloc((void**)&p->d_ws, std::max<size_t>(1, p->ws_elems) * sizeof(double));
+        if (e != hipSuccess) {
+            p->d_ws = nullptr;
+            return fail(p->ctx, SG_ERR_OUT_OF_MEMORY, std::string("workspace: ") + hipGetErrorString(e));
+        }
+    }
+    const int rc = launch_adjoint(p->precision, p->nwg, p->d_wgs, p->d_probs, p->d_pool64, p->d_pool32, params_dev,
+                                  grad_out_dev, grad_params_dev, p->d_ws, stream);
+    if (rc != 0) return hip_fail(p->ctx, (hipError_t)rc, "adjoint launch");
+    return SG_OK;
 }
 
 sg_status sg_plan_get_info(const sg_plan* p, sg_plan_info* info)
@@ -508,29 +613,42 @@ sg_status sg_plan_autotune(sg_plan* p, const double* params_dev, double* out_dev
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(p->ctx, SG_ERR_DEVICE, "hipEventCreate");
-    const LaunchCfg saved = p->cfg;
-    LaunchCfg best = saved;
+    const int saved_w = p->wmax;
+    const bool saved_g = p->use_graph;
+    int best_w = saved_w;
+    bool best_g = saved_g;
     float best_ms = 1e30f;
     const int reps = 20;
-    for (int b = 64; b <= 256; b *= 2) {
-        p->cfg.block = b;
-        sg_status st = plan_launch(p, params_dev, out_dev, nullptr, stream);   // warm
-        if (st != SG_OK) { p->cfg = saved; return st; }
-        hipEventRecord(e0, s);
-        for (int r = 0; r < reps; ++r) plan_launch(p, params_dev, out_dev, nullptr, stream);
-        hipEventRecord(e1, s);
-        hipError_t e = hipEventSynchronize(e1);
-        if (e != hipSuccess) { p->cfg = saved; return hip_fail(p->ctx, e, "autotune sync"); }
-        float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
-        if (ms < best_ms) { best_ms = ms; best = p->cfg; }
+    const int cands[3] = {1, 2, 4};
+    sg_status st = SG_OK;
+    // candidates: waves-per-problem cap x (graph replay | direct launch);
+    // the graph variant is only timed on a non-default stream
+    for (int c : cands) {
+        if ((st = plan_repack(p, c)) != SG_OK) break;
+        destroy_graphs(p);
+        for (int g = 0; g < (stream ? 2 : 1); ++g) {
+            p->use_graph = g == 1;
+            if ((st = sg_plan_execute(p, params_dev, out_dev, nullptr, stream)) != SG_OK) break;   // warm / capture
+            hipEventRecord(e0, s);
+            for (int r = 0; r < reps; ++r) sg_plan_execute(p, params_dev, out_dev, nullptr, stream);
+            hipEventRecord(e1, s);
+            hipError_t e = hipEventSynchronize(e1);
+            if (e != hipSuccess) { st = hip_fail(p->ctx, e, "autotune sync"); break; }
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best_ms) { best_ms = ms; best_w = c; best_g = p->use_graph; }
+        }
+        if (st != SG_OK) break;
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
-    p->cfg = best;
-    p->info.block_threads = best.block;
-    p->ctx->tuned[p->tune_key] = best;
     destroy_graphs(p);
+    sg_status st2 = plan_repack(p, st == SG_OK ? best_w : saved_w);
+    p->use_graph = st == SG_OK ? best_g : saved_g;
+    if (st != SG_OK) return st;
+    if (st2 != SG_OK) return st2;
+    p->ctx->tuned[p->tune_key] = std::make_pair(best_w, best_g);
+    p->info.graph = p->use_graph ? 1 : 0;
     return SG_OK;
 }
 
@@ -539,7 +657,8 @@ sg_status sg_plan_destroy(sg_plan* p)
     if (!p) return SG_OK;
     destroy_graphs(p);
     hipFree(p->d_probs);
-    hipFree(p->d_tabs);
+    hipFree(p->d_wgs);
+    hipFree(p->d_ws);
     hipFree(p->d_pool64);
     hipFree(p->d_pool32);
     if (p->ctx) p->ctx->live_plans--;
@@ -560,30 +679,29 @@ sg_status sg_integrate(sg_context* ctx, const sg_problem* problem, int32_t preci
     auto key = std::make_tuple(problem->rule, K, problem->family, problem->d);
     auto it = ctx->plain.find(key);
     if (it == ctx->plain.end()) {
-        const DeltaTable* t = get_table(ctx, problem->rule, K, st);
-        if (!t) return st;
-        std::vector<double> p64;
-        std::vector<float> p32;
-        TableDev td;
-        append_table(*t, p64, p32, td);
-        ProbDev pd;
+        const Records* r = get_records(ctx, problem->rule, K, st);
+        if (!r) return st;
+        std::vector<ProbDev> pv(1);
+        ProbDev& pd = pv[0];
         pd.d = problem->d;
         pd.K = K;
         pd.family = problem->family;
-        pd.table = 0;
+        pd.rclass = rule_class_of(problem->rule);
         pd.param_offset = 0;
+        pd.off64 = 0;
+        pd.off32 = 0;
         pd.out_index = 0;
-        pd.pad = 0;
+        pd.waves = waves_for(pd.d, 4);
+        pd.ws_off = 0;
+        std::vector<WGDesc> wgs = pack_workgroups(pv, 4);
         PlainEntry pe;
-        if ((st = upload(ctx, &pe.probs, &pd, 1)) != SG_OK) return st;
-        if ((st = upload(ctx, &pe.tabs, &td, 1)) != SG_OK) return st;
-        if ((st = upload(ctx, &pe.pool64, p64.data(), p64.size())) != SG_OK) return st;
-        if ((st = upload(ctx, &pe.pool32, p32.data(), p32.size())) != SG_OK) return st;
+        if ((st = upload(ctx, &pe.probs, pv.data(), 1)) != SG_OK) return st;
+        if ((st = upload(ctx, &pe.wgs, wgs.data(), wgs.size())) != SG_OK) return st;
+        if ((st = upload(ctx, &pe.pool64, r->r64.data(), r->r64.size())) != SG_OK) return st;
+        if ((st = upload(ctx, &pe.pool32, r->r32.data(), r->r32.size())) != SG_OK) return st;
         it = ctx->plain.emplace(key, pe).first;
     }
-    LaunchCfg cfg;
-    cfg.block = round_block(problem->d);
-    const int rc = launch_forward(precision, cfg, 1, it->second.probs, it->second.tabs, it->second.pool64,
+    const int rc = launch_forward(precision, 1, it->second.wgs, it->second.probs, it->second.pool64,
                                   it->second.pool32, params_dev, out_dev, bound_dev, stream);
     if (rc != 0) return hip_fail(ctx, (hipError_t)rc, "forward launch");
     return SG_OK;

@@ -55,35 +55,81 @@ bool binom_u64(uint64_t n, uint64_t k, uint64_t& out);
 sg_status counts(int d, int q, int rule, uint64_t* n_multi, uint64_t* n_rep, uint64_t* n_unique);
 sg_status unrank(int d, int q, uint64_t rank, int32_t* coords, int32_t* levels, int32_t* nnz);
 
+// ------------------------------------------------------- static rule layout
+// Structure classes of the difference-rule tables, fixed per (class, K):
+// pairs entering at level L and the e-range [elo, ehi] their nodes carry
+// weights in.  The kernels unroll over this structure at compile time; the
+// host writes the tables in exactly this order (and checks the counts).
+enum { RC_NESTED = 0, RC_GL2 = 1, RC_GLP = 2 };
+
+constexpr int rule_class_of(int rule)
+{
+    return (rule == SG_RULE_TRAPEZOID || rule == SG_RULE_CLENSHAW_CURTIS) ? RC_NESTED
+           : rule == SG_RULE_GAUSS_LEGENDRE ? RC_GL2 : RC_GLP;
+}
+constexpr int rc_pairs(int rc, int L)
+{
+    return L < 2 ? 0 : rc == RC_NESTED ? (L == 2 ? 1 : (1 << (L - 3))) : rc == RC_GL2 ? L - 1 : L / 2;
+}
+constexpr int rc_elo(int L) { return L - 1; }
+constexpr int rc_ehi(int rc, int K, int L) { return rc == RC_NESTED ? K : (L < K ? L : K); }
+// FP64 record of one pair: y, dW[elo..ehi], sum_e |dW|
+constexpr int rc_rec64(int rc, int K, int L) { return rc_ehi(rc, K, L) - rc_elo(L) + 3; }
+// FP32 record of one pair: (dW_hi, dW_lo) for e = elo..ehi
+constexpr int rc_rec32(int rc, int K, int L) { return 2 * (rc_ehi(rc, K, L) - rc_elo(L) + 1); }
+constexpr int rc_off64(int rc, int K, int L)
+{
+    int o = 0;
+    for (int l = 2; l < L; ++l) o += rc_pairs(rc, l) * rc_rec64(rc, K, l);
+    return o;
+}
+constexpr int rc_off32(int rc, int K, int L)
+{
+    int o = 0;
+    for (int l = 2; l < L; ++l) o += rc_pairs(rc, l) * rc_rec32(rc, K, l);
+    return o;
+}
+
 // ------------------------------------------------------------------- device
 // Per-problem record in device memory (plan order = longest first).
 struct ProbDev {
-    int32_t d, K, family, table;   // table: index into the plan's TableDev array
+    int32_t d, K, family, rclass;
     int64_t param_offset;
+    int64_t off64;                 // record table in pool64
+    int64_t off32;                 // record table in pool32
     int32_t out_index;             // position in the caller's problem order
-    int32_t pad;
+    int32_t waves;                 // waves this problem spans inside its workgroup (1, 2 or 4)
+    int64_t ws_off;                // reverse sweep: this problem's d*K slots in the workspace
 };
 
-// Device view of one DeltaTable inside the plan's table pools.
-struct TableDev {
-    int32_t K, npairs, nested, pad;
-    int32_t level_begin[kMaxK + 3];
-    int32_t pad2;
-    int64_t off64;   // pool64: y[npairs], dw[(K+1)*npairs], wabs[npairs]
-    int64_t off32;   // pool32: y32[npairs], dw_hi[(K+1)*npairs], dw_lo[(K+1)*npairs]
+// One workgroup = 4 waves; wave w works on problem slot[w].prob (or idles
+// when prob < 0) as wave `rank` of a group of `group` waves.
+struct WaveSlot {
+    int32_t prob;
+    int16_t rank, group;
+};
+struct WGDesc {
+    WaveSlot slot[4];
 };
 
 struct LaunchCfg {
-    int block = 256;   // threads per workgroup (64, 128 or 256)
+    int block = 256;   // threads per workgroup (always 4 waves)
 };
 
 // Kernel launchers (sg_kernels.hip).
-int launch_forward(int precision, const LaunchCfg& cfg, int nprob, const ProbDev* probs,
-                   const TableDev* tabs, const double* pool64, const float* pool32,
-                   const double* params, double* out, double* bound, void* stream);
+int launch_forward(int precision, int nwg, const WGDesc* wgs, const ProbDev* probs,
+                   const double* pool64, const float* pool32, const double* params, double* out,
+                   double* bound, void* stream);
+int launch_adjoint(int precision, int nwg, const WGDesc* wgs, const ProbDev* probs, const double* pool64,
+                   const float* pool32, const double* params, const double* gout, double* grad, double* ws,
+                   void* stream);
 int launch_unrank(int d, int q, uint64_t rank0, uint64_t count, int max_nnz,
                   const uint64_t* binom_table, int binom_rows, int32_t* coords, int32_t* levels,
                   int32_t* nnz, void* stream);
 const char* device_error_string(int code);
+
+// Record tables (FP64 and FP32 pools) of one (rule, K) in the static layout.
+bool build_records(const DeltaTable& t, std::vector<double>& rec64, std::vector<float>& rec32,
+                   std::string& err);
 
 }  // namespace sg

@@ -32,6 +32,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "sg_internal.hpp"
 
 namespace sg {
@@ -153,76 +155,103 @@ __device__ __forceinline__ void pmul(double (&a)[MAXK + 1], const double (&b)[MA
 }
 
 // ------------------------------------------------ per-coordinate surplus
-struct TableView {
-    int np;
-    const int* lb;          // level_begin
-    const double* y;
-    const double* dw;       // (K+1) x np
-    const double* wabs;
-    const float* dwh;
-    const float* dwl;
-};
-
-template <int K, bool NESTED, int FAM>
-__device__ __forceinline__ void surplus64(const TableView& T, const CoordParam& cp, bool want_bound,
-                                          double (&del)[MAXK + 1], double& eps)
+// Compile-time loop over the levels L = B .. E-1.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f)
 {
-#pragma unroll
-    for (int e = 0; e <= MAXK; ++e) del[e] = 0.0;
-#pragma unroll
-    for (int L = 2; L <= K + 1; ++L) {
-        const int pb = T.lb[L], pe = T.lb[L + 1];
-        for (int p = pb; p < pe; ++p) {
-            const double s = pair64<FAM>(cp, T.y[p]);
-            if (want_bound) eps = fma(T.wabs[p], fabs(s), eps);
-            if constexpr (NESTED) {
-#pragma unroll
-                for (int e = L - 1; e <= K; ++e) del[e] = fma(T.dw[e * T.np + p], s, del[e]);
-            } else {
-                del[L - 1] = fma(T.dw[(L - 1) * T.np + p], s, del[L - 1]);
-                if (L <= K) del[L] = fma(T.dw[L * T.np + p], s, del[L]);
-            }
-        }
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
     }
 }
 
-template <int K, bool NESTED, int FAM>
-__device__ __forceinline__ void surplus32(const TableView& T, const CoordParam& cp, bool want_bound,
-                                          double (&del)[MAXK + 1], double& eps)
+// delta_t[e] for one coordinate, FP64.  The table is a sequence of per-pair
+// records (y, dW[elo..ehi], sum|dW|) whose layout is fixed by (RC, K), so
+// every load has a compile-time offset from the table base.  `pf` maps the
+// pair's y to its (even-part) value.
+template <int K, int RC, class PF>
+__device__ __forceinline__ void surplus64g(const double* __restrict__ r64, PF&& pf, bool want_bound,
+                                           double (&del)[MAXK + 1], double& eps)
+{
+#pragma unroll
+    for (int e = 0; e <= MAXK; ++e) del[e] = 0.0;
+    static_for<2, K + 2>([&](auto Lc) {
+        constexpr int L = decltype(Lc)::value;
+        constexpr int np = rc_pairs(RC, L), lo = rc_elo(L), hi = rc_ehi(RC, K, L);
+        constexpr int rl = rc_rec64(RC, K, L), off = rc_off64(RC, K, L);
+#pragma unroll 2
+        for (int j = 0; j < np; ++j) {
+            const double* r = r64 + off + j * rl;
+            const double s = pf(r[0]);
+#pragma unroll
+            for (int e = lo; e <= hi; ++e) del[e] = fma(r[1 + e - lo], s, del[e]);
+            if (want_bound) eps = fma(r[rl - 1], fabs(s), eps);
+        }
+    });
+}
+
+// Same with FP32 pair values and two-sum compensated FP32 accumulation
+// against hi+lo weights; emitted as FP64 hi + lo.
+template <int K, int RC, class PF>
+__device__ __forceinline__ void surplus32g(const double* __restrict__ r64, const float* __restrict__ r32,
+                                           PF&& pf, bool want_bound, double (&del)[MAXK + 1], double& eps)
 {
     float hi[MAXK + 1], lo[MAXK + 1];
 #pragma unroll
     for (int e = 0; e <= MAXK; ++e) { hi[e] = 0.0f; lo[e] = 0.0f; }
     float epsf = 0.0f;
+    static_for<2, K + 2>([&](auto Lc) {
+        constexpr int L = decltype(Lc)::value;
+        constexpr int np = rc_pairs(RC, L), elo = rc_elo(L), ehi = rc_ehi(RC, K, L);
+        constexpr int rl = rc_rec64(RC, K, L), off = rc_off64(RC, K, L);
+        constexpr int rl32 = rc_rec32(RC, K, L), off32 = rc_off32(RC, K, L);
+#pragma unroll 2
+        for (int j = 0; j < np; ++j) {
+            const double* r = r64 + off + j * rl;
+            const float* w = r32 + off32 + j * rl32;
+            const float s = pf(r[0]);
 #pragma unroll
-    for (int L = 2; L <= K + 1; ++L) {
-        const int pb = T.lb[L], pe = T.lb[L + 1];
-        for (int p = pb; p < pe; ++p) {
-            const float s = pair32<FAM>(cp, T.y[p]);
-            if (want_bound) epsf = fmaf((float)T.wabs[p], fabsf(s), epsf);
-            if constexpr (NESTED) {
-#pragma unroll
-                for (int e = L - 1; e <= K; ++e)
-                    acc2(hi[e], lo[e], T.dwh[e * T.np + p], T.dwl[e * T.np + p], s);
-            } else {
-                acc2(hi[L - 1], lo[L - 1], T.dwh[(L - 1) * T.np + p], T.dwl[(L - 1) * T.np + p], s);
-                if (L <= K) acc2(hi[L], lo[L], T.dwh[L * T.np + p], T.dwl[L * T.np + p], s);
-            }
+            for (int e = elo; e <= ehi; ++e)
+                acc2(hi[e], lo[e], w[2 * (e - elo)], w[2 * (e - elo) + 1], s);
+            if (want_bound) epsf = fmaf((float)r[rl - 1], fabsf(s), epsf);
         }
-    }
+    });
 #pragma unroll
     for (int e = 0; e <= MAXK; ++e) del[e] = (double)hi[e] + (double)lo[e];
     eps += (double)epsf;
 }
 
-// -------------------------------------------------------- block reduction
-// Merge state: running polynomial a, its absolute-value twin ab (for the
-// error bound), the affine partial sum ls, sum |terms of ls|, and eps.
+template <int K, int RC, int FAM>
+__device__ __forceinline__ void surplus64(const double* __restrict__ r64, const CoordParam& cp, bool want_bound,
+                                          double (&del)[MAXK + 1], double& eps)
+{
+    surplus64g<K, RC>(r64, [&](double y) { return pair64<FAM>(cp, y); }, want_bound, del, eps);
+}
+
+template <int K, int RC, int FAM>
+__device__ __forceinline__ void surplus32(const double* __restrict__ r64, const float* __restrict__ r32,
+                                          const CoordParam& cp, bool want_bound, double (&del)[MAXK + 1],
+                                          double& eps)
+{
+    surplus32g<K, RC>(r64, r32, [&](double y) { return pair32<FAM>(cp, y); }, want_bound, del, eps);
+}
+
+// ----------------------------------------------------------- merge state
+// Running polynomial a, its absolute-value twin ab (error bound), the
+// affine partial sum ls, sum |terms of ls|, and the bound accumulator eps.
 struct Acc {
     double a[MAXK + 1];
     double ab[MAXK + 1];
     double ls, lsabs, eps;
 };
+
+template <int K>
+__device__ __forceinline__ void acc_identity(Acc& x)
+{
+#pragma unroll
+    for (int k = 0; k <= MAXK; ++k) { x.a[k] = 0.0; x.ab[k] = 0.0; }
+    x.ls = x.lsabs = x.eps = 0.0;
+}
 
 template <int K>
 __device__ __forceinline__ void merge(Acc& x, const Acc& y, bool want_bound)
@@ -250,73 +279,99 @@ __device__ __forceinline__ void shfl_acc(Acc& o, const Acc& x, int mask, bool wa
 
 constexpr int ACC_WORDS = 2 * MAXK + 3;   // doubles per wave in LDS
 
-// Reduce the block's per-thread states into thread 0 (deterministic tree:
-// xor butterflies inside each wave, then the wave results in wave order).
 template <int K>
-__device__ __forceinline__ void block_reduce(Acc& x, bool want_bound, double* smem)
+__device__ __forceinline__ void acc_store(const Acc& x, double* s)
 {
-    for (int m = 32; m >= 1; m >>= 1) {
-        Acc o;
-        shfl_acc<K>(o, x, m, want_bound);
-        merge<K>(x, o, want_bound);
-    }
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    if (nw == 1) return;
-    if (lane == 0) {
-        double* s = smem + wid * ACC_WORDS;
 #pragma unroll
-        for (int k = 1; k <= K; ++k) { s[k - 1] = x.a[k]; s[MAXK + k - 1] = x.ab[k]; }
-        s[2 * MAXK] = x.ls;
-        s[2 * MAXK + 1] = x.lsabs;
-        s[2 * MAXK + 2] = x.eps;
-    }
-    __syncthreads();
-    if (wid == 0) {
-        if (lane < nw) {
-            const double* s = smem + lane * ACC_WORDS;
-#pragma unroll
-            for (int k = 1; k <= K; ++k) { x.a[k] = s[k - 1]; x.ab[k] = s[MAXK + k - 1]; }
-            x.ls = s[2 * MAXK];
-            x.lsabs = s[2 * MAXK + 1];
-            x.eps = s[2 * MAXK + 2];
-        } else {
-#pragma unroll
-            for (int k = 1; k <= K; ++k) { x.a[k] = 0.0; x.ab[k] = 0.0; }
-            x.ls = x.lsabs = x.eps = 0.0;
-        }
-        for (int m = 2; m >= 1; m >>= 1) {
-            Acc o;
-            shfl_acc<K>(o, x, m, want_bound);
-            merge<K>(x, o, want_bound);
-        }
-    }
+    for (int k = 1; k <= K; ++k) { s[k - 1] = x.a[k]; s[MAXK + k - 1] = x.ab[k]; }
+    s[2 * MAXK] = x.ls;
+    s[2 * MAXK + 1] = x.lsabs;
+    s[2 * MAXK + 2] = x.eps;
 }
 
-// ------------------------------------------------------------ integrand
-template <int PREC, int K, bool NESTED, int FAM>
-__device__ __forceinline__ void integrand_body(const ProbDev& P, const TableDev& TD, const double* pool64,
-                               const float* pool32, const double* __restrict__ params, double* out,
-                               double* bound, double* smem)
+template <int K>
+__device__ __forceinline__ void acc_load(Acc& x, const double* s)
 {
-    TableView T;
-    T.np = TD.npairs;
-    T.lb = TD.level_begin;
-    T.y = pool64 + TD.off64;
-    T.dw = T.y + T.np;
-    T.wabs = T.dw + (size_t)(K + 1) * T.np;
-    T.dwh = pool32 + TD.off32 + T.np;
-    T.dwl = T.dwh + (size_t)(K + 1) * T.np;
+#pragma unroll
+    for (int k = 1; k <= K; ++k) { x.a[k] = s[k - 1]; x.ab[k] = s[MAXK + k - 1]; }
+    x.ls = s[2 * MAXK];
+    x.lsabs = s[2 * MAXK + 1];
+    x.eps = s[2 * MAXK + 2];
+}
+
+// ------------------------------------------------------------ read-out
+// Q = A * (1 + sum_k a_k) with the affine partial sum giving A, and the
+// a-priori bound on |Q - exact Smolyak value| from rounding.
+template <int PREC, int K, int FAM>
+__device__ void readout(const Acc& x, const ProbDev& P, const double* __restrict__ prm, int rl_pairs,
+                        double* out, double* bound)
+{
     const bool want_bound = bound != nullptr;
+    double s = 0.0, sabs = 0.0;
+#pragma unroll
+    for (int k = K; k >= 1; --k) { s += x.a[k]; sabs += x.ab[k]; }
+    s += 1.0;
+    sabs += 1.0;
+    const double u64 = 1.1102230246251565e-16;
+    const double ls_err = u64 * (double)P.d * x.lsabs;   // rounding of the affine sum
+    // relative error of one surplus: pair value + within-rule sum
+    const double rel = PREC == SG_PREC_FP64 ? u64 * (4.0 + (double)rl_pairs) : 5.9604644775390625e-08 * 4.0;
+    // products of the sweep: (K+2) roundings per merge level
+    const double levels = (double)((P.d + 63) / 64 + 10);
+    double Q;
+    if constexpr (FAM == FAM_OSC) {
+        const double phase = 2.0 * 3.141592653589793 * prm[0] + x.ls;
+        Q = cos(phase) * s;
+        if (want_bound) {
+            const double dsum = sabs * (rel * x.eps + (K + 2) * levels * u64);
+            bound[P.out_index] = dsum + fabs(s) * (ls_err + u64 * (fabs(phase) + 4.0)) + fabs(Q) * 4.0 * u64;
+        }
+    } else {
+        const double A = exp(FAM == FAM_EXP ? x.ls : -x.ls);
+        Q = A * s;
+        if (want_bound) {
+            const double dsum = sabs * (rel * x.eps + (K + 2) * levels * u64);
+            bound[P.out_index] = A * dsum + fabs(Q) * (ls_err + 4.0 * u64 + u64 * fabs(x.ls));
+        }
+    }
+    out[P.out_index] = Q;
+}
+
+// Number of node pairs of a (class, K) table (for the bound's sum length).
+template <int RC, int K>
+constexpr int total_pairs()
+{
+    int n = 0;
+    for (int L = 2; L <= K + 1; ++L) n += rc_pairs(RC, L);
+    return n;
+}
+
+// ----------------------------------------------------------- wave sweep
+// One wave sweeps the coordinates t = rank*64 + lane + j*64*group of its
+// problem, reduces across its lanes, and either reads out (group of one
+// wave) or leaves its partial state in LDS for the group leader.
+template <int PREC, int K, int RC, int FAM>
+__device__ __forceinline__ void wave_sweep(const ProbDev& P, int rank, int group, const double* pool64,
+                                           const float* pool32, const double* __restrict__ params,
+                                           double* out, double* bound, double* lds_slot)
+{
+    const bool want_bound = bound != nullptr;
+    const int lane = threadIdx.x & 63;
     const int d = P.d;
-    const double* prm = params + P.param_offset;
+    const double* __restrict__ r64 = pool64 + P.off64;
+    const float* __restrict__ r32 = pool32 + P.off32;
+    const double* __restrict__ prm = params + P.param_offset;
 
     Acc x;
-#pragma unroll
-    for (int k = 0; k <= MAXK; ++k) { x.a[k] = 0.0; x.ab[k] = 0.0; }
-    x.ls = x.lsabs = x.eps = 0.0;
-
-    // the sweep: each thread walks its coordinates t = tid, tid + B, ...
-    for (int t = threadIdx.x; t < d; t += blockDim.x) {
+    acc_identity<K>(x);
+    for (int t = rank * 64 + lane; t < d; t += 64 * group) {
+        // The table addresses are loop-invariant; hiding them from the
+        // optimiser keeps the table in scalar loads issued per coordinate
+        // instead of hoisting hundreds of values into vector registers.
+        int opaque = 0;
+        asm volatile("" : "+s"(opaque));
+        const double* __restrict__ r64i = r64 + opaque;
+        const float* __restrict__ r32i = r32 + opaque;
         CoordParam cp;
         double lterm;
         if constexpr (FAM == FAM_EXP) {
@@ -335,8 +390,8 @@ __device__ __forceinline__ void integrand_body(const ProbDev& P, const TableDev&
         }
         double del[MAXK + 1];
         double eps_t = 0.0;
-        if constexpr (PREC == SG_PREC_FP64) surplus64<K, NESTED, FAM>(T, cp, want_bound, del, eps_t);
-        else surplus32<K, NESTED, FAM>(T, cp, want_bound, del, eps_t);
+        if constexpr (PREC == SG_PREC_FP64) surplus64<K, RC, FAM>(r64i, cp, want_bound, del, eps_t);
+        else surplus32<K, RC, FAM>(r64i, r32i, cp, want_bound, del, eps_t);
         pmul<K>(x.a, del);
         if (want_bound) {
             double dab[MAXK + 1];
@@ -348,83 +403,435 @@ __device__ __forceinline__ void integrand_body(const ProbDev& P, const TableDev&
         x.lsabs += fabs(lterm);
         x.eps += eps_t;
     }
-
-    block_reduce<K>(x, want_bound, smem);
-
-    if (threadIdx.x == 0) {
-        double s = 0.0, sabs = 0.0;
-#pragma unroll
-        for (int k = K; k >= 1; --k) { s += x.a[k]; sabs += x.ab[k]; }
-        s += 1.0;
-        sabs += 1.0;
-        double Q, scale, amp_rel;
-        const double u64 = 1.1102230246251565e-16;
-        const double ls_err = u64 * (double)d * x.lsabs;   // rounding of the affine sum
-        if constexpr (FAM == FAM_OSC) {
-            const double phase = 2.0 * 3.141592653589793 * prm[0] + x.ls;
-            const double cph = cos(phase);
-            Q = cph * s;
-            scale = 1.0;                                  // |cos| <= 1
-            amp_rel = 0.0;
-            if (want_bound) {
-                const double rel = (PREC == SG_PREC_FP64 ? u64 * (4.0 + (double)T.np)
-                                                         : 5.9604644775390625e-08 * 4.0);
-                const double dsum = sabs * (rel * x.eps + (K + 2) * (double)(d / (int)blockDim.x + 12) * u64);
-                bound[P.out_index] = dsum + fabs(s) * (ls_err + u64 * (fabs(phase) + 4.0)) + fabs(Q) * 4.0 * u64;
-            }
-        } else {
-            const double A = exp(FAM == FAM_EXP ? x.ls : -x.ls);
-            Q = A * s;
-            scale = A;
-            amp_rel = ls_err + 4.0 * u64 + u64 * fabs(x.ls);
-            if (want_bound) {
-                const double rel = (PREC == SG_PREC_FP64 ? u64 * (4.0 + (double)T.np)
-                                                         : 5.9604644775390625e-08 * 4.0);
-                const double dsum = sabs * (rel * x.eps + (K + 2) * (double)(d / (int)blockDim.x + 12) * u64);
-                bound[P.out_index] = scale * dsum + fabs(Q) * amp_rel;
-            }
-        }
-        out[P.out_index] = Q;
+    // butterfly over the lanes that hold coordinates (lane 0 ends with all)
+    const int nact = min(64, max(0, d - rank * 64));
+    for (int m = 1; m < nact; m <<= 1) {
+        Acc o;
+        shfl_acc<K>(o, x, m, want_bound);
+        merge<K>(x, o, want_bound);
+    }
+    if (group == 1) {
+        if (lane == 0) readout<PREC, K, FAM>(x, P, prm, total_pairs<RC, K>(), out, bound);
+    } else if (lane == 0) {
+        acc_store<K>(x, lds_slot);
     }
 }
 
 template <int PREC, int K>
-__device__ __forceinline__ void dispatch_rule_family(const ProbDev& P, const TableDev& T, const double* pool64,
-                                     const float* pool32, const double* params, double* out,
-                                     double* bound, double* smem)
+__device__ __forceinline__ void wave_dispatch_k(const ProbDev& P, int rank, int group, const double* pool64,
+                                                const float* pool32, const double* params, double* out,
+                                                double* bound, double* lds_slot)
 {
-    if (T.nested) {
-        if (P.family == FAM_EXP) integrand_body<PREC, K, true, FAM_EXP>(P, T, pool64, pool32, params, out, bound, smem);
-        else if (P.family == FAM_OSC) integrand_body<PREC, K, true, FAM_OSC>(P, T, pool64, pool32, params, out, bound, smem);
-        else integrand_body<PREC, K, true, FAM_PEAK>(P, T, pool64, pool32, params, out, bound, smem);
+#define SG_WAVE(RC, FAM) wave_sweep<PREC, K, RC, FAM>(P, rank, group, pool64, pool32, params, out, bound, lds_slot)
+    if (P.rclass == RC_NESTED) {
+        if (P.family == FAM_EXP) SG_WAVE(RC_NESTED, FAM_EXP);
+        else if (P.family == FAM_OSC) SG_WAVE(RC_NESTED, FAM_OSC);
+        else SG_WAVE(RC_NESTED, FAM_PEAK);
+    } else if (P.rclass == RC_GL2) {
+        if (P.family == FAM_EXP) SG_WAVE(RC_GL2, FAM_EXP);
+        else if (P.family == FAM_OSC) SG_WAVE(RC_GL2, FAM_OSC);
+        else SG_WAVE(RC_GL2, FAM_PEAK);
     } else {
-        if (P.family == FAM_EXP) integrand_body<PREC, K, false, FAM_EXP>(P, T, pool64, pool32, params, out, bound, smem);
-        else if (P.family == FAM_OSC) integrand_body<PREC, K, false, FAM_OSC>(P, T, pool64, pool32, params, out, bound, smem);
-        else integrand_body<PREC, K, false, FAM_PEAK>(P, T, pool64, pool32, params, out, bound, smem);
+        if (P.family == FAM_EXP) SG_WAVE(RC_GLP, FAM_EXP);
+        else if (P.family == FAM_OSC) SG_WAVE(RC_GLP, FAM_OSC);
+        else SG_WAVE(RC_GLP, FAM_PEAK);
     }
+#undef SG_WAVE
 }
 
-// One workgroup per integrand (plan order: most expensive first).
+// Group leader: merge the group's wave states in wave order, read out.
+template <int PREC, int K>
+__device__ __forceinline__ void group_finish_k(const ProbDev& P, int group, const double* lds_first,
+                                               const double* params, double* out, double* bound)
+{
+    const bool want_bound = bound != nullptr;
+    Acc x, y;
+    acc_identity<K>(x);
+    acc_identity<K>(y);
+    acc_load<K>(x, lds_first);
+    for (int g = 1; g < group; ++g) {
+        acc_load<K>(y, lds_first + g * ACC_WORDS);
+        merge<K>(x, y, want_bound);
+    }
+    const double* prm = params + P.param_offset;
+    const int np = P.rclass == RC_NESTED ? total_pairs<RC_NESTED, K>()
+                   : P.rclass == RC_GL2  ? total_pairs<RC_GL2, K>()
+                                         : total_pairs<RC_GLP, K>();
+    if (P.family == FAM_EXP) readout<PREC, K, FAM_EXP>(x, P, prm, np, out, bound);
+    else if (P.family == FAM_OSC) readout<PREC, K, FAM_OSC>(x, P, prm, np, out, bound);
+    else readout<PREC, K, FAM_PEAK>(x, P, prm, np, out, bound);
+}
+
+#define SG_SWITCH_K(K_, CALL)                      \
+    switch (K_) {                                  \
+    case 0: CALL(0); break;                        \
+    case 1: CALL(1); break;                        \
+    case 2: CALL(2); break;                        \
+    case 3: CALL(3); break;                        \
+    case 4: CALL(4); break;                        \
+    case 5: CALL(5); break;                        \
+    case 6: CALL(6); break;                        \
+    case 7: CALL(7); break;                        \
+    default: CALL(8); break;                       \
+    }
+
+// Each workgroup holds 4 waves; wave w works on wgs[blockIdx.x].slot[w].
+// Problems spanning several waves sit in consecutive slots of one
+// workgroup and are merged through LDS by their first wave.
 template <int PREC>
 __global__ void __launch_bounds__(256)
-k_forward(const ProbDev* __restrict__ probs, const TableDev* __restrict__ tabs,
+k_forward(const WGDesc* __restrict__ wgs, const ProbDev* __restrict__ probs,
           const double* __restrict__ pool64, const float* __restrict__ pool32,
           const double* __restrict__ params, double* __restrict__ out, double* __restrict__ bound)
 {
-    __shared__ double smem[4 * ACC_WORDS];
-    const ProbDev P = probs[blockIdx.x];
-    const TableDev& T = tabs[P.table];
-    switch (P.K) {
-    case 0: dispatch_rule_family<PREC, 0>(P, T, pool64, pool32, params, out, bound, smem); break;
-    case 1: dispatch_rule_family<PREC, 1>(P, T, pool64, pool32, params, out, bound, smem); break;
-    case 2: dispatch_rule_family<PREC, 2>(P, T, pool64, pool32, params, out, bound, smem); break;
-    case 3: dispatch_rule_family<PREC, 3>(P, T, pool64, pool32, params, out, bound, smem); break;
-    case 4: dispatch_rule_family<PREC, 4>(P, T, pool64, pool32, params, out, bound, smem); break;
-    case 5: dispatch_rule_family<PREC, 5>(P, T, pool64, pool32, params, out, bound, smem); break;
-    case 6: dispatch_rule_family<PREC, 6>(P, T, pool64, pool32, params, out, bound, smem); break;
-    case 7: dispatch_rule_family<PREC, 7>(P, T, pool64, pool32, params, out, bound, smem); break;
-    default: dispatch_rule_family<PREC, 8>(P, T, pool64, pool32, params, out, bound, smem); break;
+    __shared__ double lds[4 * ACC_WORDS];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+    const WGDesc* desc = wgs + blockIdx.x;
+    WaveSlot sl = desc->slot[w];
+    sl.prob = __builtin_amdgcn_readfirstlane(sl.prob);
+    sl.rank = (int16_t)__builtin_amdgcn_readfirstlane(sl.rank);
+    sl.group = (int16_t)__builtin_amdgcn_readfirstlane(sl.group);
+    const bool grouped = desc->slot[0].group > 1 || desc->slot[1].group > 1 || desc->slot[2].group > 1 ||
+                         desc->slot[3].group > 1;
+    ProbDev P;
+    if (sl.prob >= 0) {
+        P = probs[sl.prob];
+#define SG_CALL(KK) wave_dispatch_k<PREC, KK>(P, sl.rank, sl.group, pool64, pool32, params, out, bound, lds + w * ACC_WORDS)
+        SG_SWITCH_K(P.K, SG_CALL)
+#undef SG_CALL
     }
+    if (!grouped) return;
+    __syncthreads();
+    if (sl.prob >= 0 && sl.group > 1 && sl.rank == 0 && (threadIdx.x & 63) == 0) {
+#define SG_CALL(KK) group_finish_k<PREC, KK>(P, sl.group, lds + w * ACC_WORDS, params, out, bound)
+        SG_SWITCH_K(P.K, SG_CALL)
+#undef SG_CALL
+    }
+}
+
+// ================================================================ adjoint
+// Reverse sweep.  With S(z) = prod_t delta_t(z) (monic, truncated at z^K)
+// and s = sum_{b<=K} [z^b] S:
+//   ds/d delta_t[e] = sum_{j=0}^{K-e} [z^j] R_t,   R_t = prod_{t' != t} delta_t',
+// where R_t is formed from exclusive prefix and suffix products across the
+// sweep (no division by delta_t), and
+//   d delta_t[e] / d p_t = sum_p dW[e][p] ds_p/dp_t
+// is a within-rule sum of derivative pair values.  The affine partial sum
+// (log-amplitude or phase) contributes its own term.
+
+// sinh(v)/v = sum z^k/(2k+1)!, sin(v)/v = sum (-z)^k/(2k+1)!, z = v^2.
+__device__ __forceinline__ double series_s64(double z)
+{
+    double p = 1.0 / 355687428096000.0;                // 1/17!
+    p = fma(p, z, 1.0 / 1307674368000.0);              // 1/15!
+    p = fma(p, z, 1.0 / 6227020800.0);                 // 1/13!
+    p = fma(p, z, 1.0 / 39916800.0);                   // 1/11!
+    p = fma(p, z, 1.0 / 362880.0);                     // 1/9!
+    p = fma(p, z, 1.0 / 5040.0);                       // 1/7!
+    p = fma(p, z, 1.0 / 120.0);                        // 1/5!
+    p = fma(p, z, 1.0 / 6.0);                          // 1/3!
+    p = fma(p, z, 1.0);
+    return p;
+}
+
+__device__ __forceinline__ float series_s32(float z)
+{
+    float p = 1.0f / 362880.0f;
+    p = fmaf(p, z, 1.0f / 5040.0f);
+    p = fmaf(p, z, 1.0f / 120.0f);
+    p = fmaf(p, z, 1.0f / 6.0f);
+    p = fmaf(p, z, 1.0f);
+    return p;
+}
+
+// d s(y) / d parameter for exp-sum (d/dc: 2 y sinh(c y)) and oscillatory
+// (d/da: -2 y sin(a y)).
+template <int FAM>
+__device__ __forceinline__ double dpair64(const CoordParam& cp, double y)
+{
+    const double v = cp.p0 * y;
+    const double z = v * v;
+    if (fabs(v) <= 0.5) return FAM == FAM_EXP ? 2.0 * y * v * series_s64(z) : -2.0 * y * v * series_s64(-z);
+    return FAM == FAM_EXP ? 2.0 * y * sinh(v) : -2.0 * y * sin(v);
+}
+
+template <int FAM>
+__device__ __forceinline__ float dpair32(const CoordParam& cp, double y)
+{
+    const float v = (float)(cp.p0 * y);
+    const float yf = (float)y;
+    const float z = v * v;
+    if (fabsf(v) <= 0.5f) return FAM == FAM_EXP ? 2.0f * yf * v * series_s32(z) : -2.0f * yf * v * series_s32(-z);
+    return FAM == FAM_EXP ? 2.0f * yf * sinhf(v) : -2.0f * yf * sinf(v);
+}
+
+// Product-peak: s = 2 y^2 N / (Dp Dm), N = 3 hv^2 - beta - y^2,
+// Dp = beta + (y + hv)^2, Dm = beta + (y - hv)^2; derivatives in beta and hv.
+__device__ __forceinline__ void dpair_peak64(const CoordParam& cp, double y, double& ds_dbeta, double& ds_dhv)
+{
+    const double beta = cp.p0, hv = cp.p1;
+    const double y2 = y * y;
+    const double dp = y + hv, dm = y - hv;
+    const double Dp = fma(dp, dp, beta), Dm = fma(dm, dm, beta);
+    const double D = Dp * Dm;
+    const double N = fma(3.0 * hv, hv, -beta) - y2;
+    const double iD2 = 1.0 / (D * D);
+    // d(Dp Dm)/d beta = Dp + Dm;  d(Dp Dm)/d hv = 2 dp Dm - 2 dm Dp
+    ds_dbeta = 2.0 * y2 * (-D - N * (Dp + Dm)) * iD2;
+    ds_dhv = 2.0 * y2 * (6.0 * hv * D - N * (2.0 * dp * Dm - 2.0 * dm * Dp)) * iD2;
+}
+
+// Inclusive scans of monic truncated polynomials across the 64 lanes.
+template <int K>
+__device__ __forceinline__ void shfl_poly_up(double (&o)[MAXK + 1], const double (&x)[MAXK + 1], int off)
+{
+#pragma unroll
+    for (int k = 1; k <= K; ++k) o[k] = __shfl_up(x[k], off);
+}
+template <int K>
+__device__ __forceinline__ void shfl_poly_down(double (&o)[MAXK + 1], const double (&x)[MAXK + 1], int off)
+{
+#pragma unroll
+    for (int k = 1; k <= K; ++k) o[k] = __shfl_down(x[k], off);
+}
+template <int K>
+__device__ __forceinline__ void poly_one(double (&x)[MAXK + 1])
+{
+#pragma unroll
+    for (int k = 0; k <= MAXK; ++k) x[k] = 0.0;
+}
+
+constexpr int ADJ_WORDS = MAXK + 2;   // doubles per wave in LDS: wave product + affine sum
+
+template <int PREC, int K, int RC, int FAM>
+__device__ __forceinline__ void wave_adjoint(const ProbDev& P, int rank, int group, bool grouped,
+                                             const double* pool64, const float* pool32,
+                                             const double* __restrict__ params, const double* __restrict__ gout,
+                                             double* __restrict__ grad, double* __restrict__ ws, double* lds)
+{
+    const int lane = threadIdx.x & 63;
+    const int d = P.d;
+    const double* __restrict__ r64 = pool64 + P.off64;
+    const float* __restrict__ r32 = pool32 + P.off32;
+    const double* __restrict__ prm = params + P.param_offset;
+    double* __restrict__ wsp = ws + P.ws_off;
+    const int stride = 64 * group;
+
+    auto coord_param = [&](int t, CoordParam& cp) -> double {
+        if constexpr (FAM == FAM_EXP) {
+            cp.p0 = prm[t];
+            cp.p1 = 0.0;
+            return 0.5 * cp.p0;
+        } else if constexpr (FAM == FAM_OSC) {
+            cp.p0 = prm[1 + t];
+            cp.p1 = 0.0;
+            return 0.5 * cp.p0;
+        } else {
+            const double b = prm[t], u = prm[d + t];
+            cp.p0 = 1.0 / (b * b);
+            cp.p1 = 0.5 - u;
+            return log(fma(cp.p1, cp.p1, cp.p0));
+        }
+    };
+
+    // pass 1: surpluses of this lane's coordinates (kept in the workspace),
+    // the lane's product and affine sum
+    double L[MAXK + 1];
+    poly_one<K>(L);
+    double ls = 0.0;
+    for (int t = rank * 64 + lane; t < d; t += stride) {
+        int opaque = 0;
+        asm volatile("" : "+s"(opaque));
+        CoordParam cp;
+        ls += coord_param(t, cp);
+        double del[MAXK + 1], eps = 0.0;
+        if constexpr (PREC == SG_PREC_FP64) surplus64<K, RC, FAM>(r64 + opaque, cp, false, del, eps);
+        else surplus32<K, RC, FAM>(r64 + opaque, r32 + opaque, cp, false, del, eps);
+#pragma unroll
+        for (int k = 1; k <= K; ++k) wsp[(size_t)t * K + (k - 1)] = del[k];
+        pmul<K>(L, del);
+    }
+
+    // exclusive prefix / suffix products across the wave's lanes
+    double pre[MAXK + 1], suf[MAXK + 1], tmp[MAXK + 1];
+#pragma unroll
+    for (int k = 0; k <= MAXK; ++k) { pre[k] = L[k]; suf[k] = L[k]; }
+    for (int off = 1; off < 64; off <<= 1) {
+        shfl_poly_up<K>(tmp, pre, off);
+        if (lane >= off) pmul<K>(pre, tmp);
+        shfl_poly_down<K>(tmp, suf, off);
+        if (lane + off < 64) pmul<K>(suf, tmp);
+    }
+    double wave_tot[MAXK + 1];
+#pragma unroll
+    for (int k = 1; k <= K; ++k) wave_tot[k] = __shfl(pre[k], 63);
+    shfl_poly_up<K>(tmp, pre, 1);
+#pragma unroll
+    for (int k = 1; k <= K; ++k) pre[k] = lane == 0 ? 0.0 : tmp[k];
+    shfl_poly_down<K>(tmp, suf, 1);
+#pragma unroll
+    for (int k = 1; k <= K; ++k) suf[k] = lane == 63 ? 0.0 : tmp[k];
+    for (int m = 1; m < 64; m <<= 1) ls += __shfl_xor(ls, m);
+
+    // across the waves of the group: wave products in rank order
+    double total[MAXK + 1];
+#pragma unroll
+    for (int k = 0; k <= MAXK; ++k) total[k] = wave_tot[k];
+    if (grouped) {
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 1; k <= K; ++k) lds[k - 1] = wave_tot[k];
+            lds[MAXK] = ls;
+        }
+        __syncthreads();
+        if (group > 1) {
+            const double* base = lds - rank * ADJ_WORDS;
+            double wp[MAXK + 1], ws_[MAXK + 1], o[MAXK + 1];
+            poly_one<K>(wp);
+            poly_one<K>(ws_);
+            poly_one<K>(o);
+            double lsum = 0.0;
+            for (int r = 0; r < group; ++r) {
+#pragma unroll
+                for (int k = 1; k <= K; ++k) o[k] = base[r * ADJ_WORDS + k - 1];
+                lsum += base[r * ADJ_WORDS + MAXK];
+                if (r < rank) pmul<K>(wp, o);
+                if (r > rank) pmul<K>(ws_, o);
+            }
+            pmul<K>(pre, wp);
+            pmul<K>(suf, ws_);
+#pragma unroll
+            for (int k = 1; k <= K; ++k) total[k] = wave_tot[k];
+            pmul<K>(total, wp);
+            pmul<K>(total, ws_);
+            ls = lsum;
+        }
+    }
+
+    // read-out quantities
+    double s = 1.0;
+#pragma unroll
+    for (int k = K; k >= 1; --k) s += total[k];
+    const double g = gout[P.out_index];
+    double A = 1.0, cph = 0.0, sph = 0.0;
+    if constexpr (FAM == FAM_OSC) {
+        const double phase = 2.0 * 3.141592653589793 * prm[0] + ls;
+        sincos(phase, &sph, &cph);
+        if (rank == 0 && lane == 0) grad[P.param_offset] = g * (-2.0 * 3.141592653589793 * sph * s);
+    } else {
+        A = exp(FAM == FAM_EXP ? ls : -ls);
+    }
+
+    // pass 2: per coordinate, R_t from prefix, suffix and the lane's other
+    // coordinates; then the contraction with the derivative surpluses
+    for (int t = rank * 64 + lane; t < d; t += stride) {
+        int opaque = 0;
+        asm volatile("" : "+s"(opaque));
+        double R[MAXK + 1];
+#pragma unroll
+        for (int k = 0; k <= MAXK; ++k) R[k] = pre[k];
+        pmul<K>(R, suf);
+        for (int t2 = rank * 64 + lane; t2 < d; t2 += stride) {
+            if (t2 == t) continue;
+            double o[MAXK + 1];
+            o[0] = 1.0;
+#pragma unroll
+            for (int k = 1; k <= K; ++k) o[k] = wsp[(size_t)t2 * K + (k - 1)];
+            pmul<K>(R, o);
+        }
+        // G[e] = sum_{j <= K-e} R[j], R[0] = 1
+        double G[MAXK + 1];
+        {
+            double c = 1.0;
+            G[K] = 1.0;
+#pragma unroll
+            for (int e = K - 1; e >= 1; --e) { c += R[K - e]; G[e] = c; }
+        }
+        CoordParam cp;
+        coord_param(t, cp);
+        if constexpr (FAM == FAM_PEAK) {
+            double db[MAXK + 1], du[MAXK + 1], eps = 0.0;
+            surplus64g<K, RC>(r64 + opaque, [&](double y) { double a, b; dpair_peak64(cp, y, a, b); return a; },
+                              false, db, eps);
+            surplus64g<K, RC>(r64 + opaque, [&](double y) { double a, b; dpair_peak64(cp, y, a, b); return b; },
+                              false, du, eps);
+            double dsb = 0.0, dsh = 0.0;
+#pragma unroll
+            for (int e = 1; e <= K; ++e) { dsb = fma(G[e], db[e], dsb); dsh = fma(G[e], du[e], dsh); }
+            const double b = prm[t];
+            const double dbeta_db = -2.0 / (b * b * b);
+            const double Dc = fma(cp.p1, cp.p1, cp.p0);            // D_t(1/2)
+            // Q = A s, A = prod 1/D_t(1/2): dA/dbeta = -A/Dc, dA/dhv = -2 hv A/Dc
+            const double dQ_dbeta = A * dsb - A * s / Dc;
+            const double dQ_dhv = A * dsh - 2.0 * cp.p1 * A * s / Dc;
+            grad[P.param_offset + t] = g * dQ_dbeta * dbeta_db;
+            grad[P.param_offset + d + t] = g * (-dQ_dhv);         // hv = 1/2 - u
+        } else {
+            double dd[MAXK + 1], eps = 0.0;
+            if constexpr (PREC == SG_PREC_FP64)
+                surplus64g<K, RC>(r64 + opaque, [&](double y) { return dpair64<FAM>(cp, y); }, false, dd, eps);
+            else
+                surplus32g<K, RC>(r64 + opaque, r32 + opaque, [&](double y) { return dpair32<FAM>(cp, y); }, false,
+                                  dd, eps);
+            double ds = 0.0;
+#pragma unroll
+            for (int e = 1; e <= K; ++e) ds = fma(G[e], dd[e], ds);
+            if constexpr (FAM == FAM_EXP) {
+                grad[P.param_offset + t] = g * A * (ds + 0.5 * s);             // dA/dc_t = A/2
+            } else {
+                grad[P.param_offset + 1 + t] = g * (cph * ds - 0.5 * sph * s); // d phase/d a_t = 1/2
+            }
+        }
+    }
+}
+
+template <int PREC, int K>
+__device__ __forceinline__ void adjoint_dispatch_k(const ProbDev& P, int rank, int group, bool grouped,
+                                                   const double* pool64, const float* pool32, const double* params,
+                                                   const double* gout, double* grad, double* ws, double* lds)
+{
+#define SG_ADJ(RC, FAM) wave_adjoint<PREC, K, RC, FAM>(P, rank, group, grouped, pool64, pool32, params, gout, grad, ws, lds)
+    if (P.rclass == RC_NESTED) {
+        if (P.family == FAM_EXP) SG_ADJ(RC_NESTED, FAM_EXP);
+        else if (P.family == FAM_OSC) SG_ADJ(RC_NESTED, FAM_OSC);
+        else SG_ADJ(RC_NESTED, FAM_PEAK);
+    } else if (P.rclass == RC_GL2) {
+        if (P.family == FAM_EXP) SG_ADJ(RC_GL2, FAM_EXP);
+        else if (P.family == FAM_OSC) SG_ADJ(RC_GL2, FAM_OSC);
+        else SG_ADJ(RC_GL2, FAM_PEAK);
+    } else {
+        if (P.family == FAM_EXP) SG_ADJ(RC_GLP, FAM_EXP);
+        else if (P.family == FAM_OSC) SG_ADJ(RC_GLP, FAM_OSC);
+        else SG_ADJ(RC_GLP, FAM_PEAK);
+    }
+#undef SG_ADJ
+}
+
+// Same workgroup packing as the forward pass.  Every wave of a workgroup
+// that holds a multi-wave problem passes exactly one barrier.
+template <int PREC>
+__global__ void __launch_bounds__(256)
+k_adjoint(const WGDesc* __restrict__ wgs, const ProbDev* __restrict__ probs, const double* __restrict__ pool64,
+          const float* __restrict__ pool32, const double* __restrict__ params, const double* __restrict__ gout,
+          double* __restrict__ grad, double* __restrict__ ws)
+{
+    __shared__ double lds[4 * ADJ_WORDS];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const WGDesc* desc = wgs + blockIdx.x;
+    WaveSlot sl = desc->slot[w];
+    sl.prob = __builtin_amdgcn_readfirstlane(sl.prob);
+    sl.rank = (int16_t)__builtin_amdgcn_readfirstlane(sl.rank);
+    sl.group = (int16_t)__builtin_amdgcn_readfirstlane(sl.group);
+    const bool grouped = desc->slot[0].group > 1 || desc->slot[1].group > 1 || desc->slot[2].group > 1 ||
+                         desc->slot[3].group > 1;
+    if (sl.prob < 0) {
+        if (grouped) __syncthreads();
+        return;
+    }
+    const ProbDev P = probs[sl.prob];
+#define SG_CALL(KK) adjoint_dispatch_k<PREC, KK>(P, sl.rank, sl.group, grouped, pool64, pool32, params, gout, grad, ws, lds + w * ADJ_WORDS)
+    SG_SWITCH_K(P.K, SG_CALL)
+#undef SG_CALL
 }
 
 // ------------------------------------------------------------- unranking
@@ -479,17 +886,30 @@ k_unrank(int d, int q, uint64_t rank0, uint64_t count, int max_nnz, const uint64
 
 }  // namespace
 
-int launch_forward(int precision, const LaunchCfg& cfg, int nprob, const ProbDev* probs,
-                   const TableDev* tabs, const double* pool64, const float* pool32,
-                   const double* params, double* out, double* bound, void* stream)
+int launch_forward(int precision, int nwg, const WGDesc* wgs, const ProbDev* probs, const double* pool64,
+                   const float* pool32, const double* params, double* out, double* bound, void* stream)
 {
-    if (nprob <= 0) return 0;
-    const dim3 grid((unsigned)nprob), block((unsigned)cfg.block);
+    if (nwg <= 0) return 0;
+    const dim3 grid((unsigned)nwg), block(256);
     hipStream_t s = (hipStream_t)stream;
     if (precision == SG_PREC_FP64)
-        hipLaunchKernelGGL((k_forward<SG_PREC_FP64>), grid, block, 0, s, probs, tabs, pool64, pool32, params, out, bound);
+        hipLaunchKernelGGL((k_forward<SG_PREC_FP64>), grid, block, 0, s, wgs, probs, pool64, pool32, params, out, bound);
     else
-        hipLaunchKernelGGL((k_forward<SG_PREC_FP32_COMPENSATED>), grid, block, 0, s, probs, tabs, pool64, pool32, params, out, bound);
+        hipLaunchKernelGGL((k_forward<SG_PREC_FP32_COMPENSATED>), grid, block, 0, s, wgs, probs, pool64, pool32, params, out, bound);
+    return (int)hipGetLastError();
+}
+
+int launch_adjoint(int precision, int nwg, const WGDesc* wgs, const ProbDev* probs, const double* pool64,
+                   const float* pool32, const double* params, const double* gout, double* grad, double* ws,
+                   void* stream)
+{
+    if (nwg <= 0) return 0;
+    const dim3 grid((unsigned)nwg), block(256);
+    hipStream_t s = (hipStream_t)stream;
+    if (precision == SG_PREC_FP64)
+        hipLaunchKernelGGL((k_adjoint<SG_PREC_FP64>), grid, block, 0, s, wgs, probs, pool64, pool32, params, gout, grad, ws);
+    else
+        hipLaunchKernelGGL((k_adjoint<SG_PREC_FP32_COMPENSATED>), grid, block, 0, s, wgs, probs, pool64, pool32, params, gout, grad, ws);
     return (int)hipGetLastError();
 }
 

@@ -246,4 +246,31 @@ bool build_delta_table(int rule, int K, DeltaTable& t, std::string& err)
     return true;
 }
 
+bool build_records(const DeltaTable& t, std::vector<double>& r64, std::vector<float>& r32, std::string& err)
+{
+    const int rc = rule_class_of(t.rule);
+    const int K = t.K, P = t.npairs;
+    r64.clear();
+    r32.clear();
+    for (int L = 2; L <= K + 1; ++L) {
+        const int b = t.level_begin[L], e = t.level_begin[L + 1];
+        if (e - b != rc_pairs(rc, L) || (int)r64.size() != rc_off64(rc, K, L) ||
+            (int)r32.size() != rc_off32(rc, K, L)) {
+            err = "difference-rule table does not match the static layout of its rule class";
+            return false;
+        }
+        const int lo = rc_elo(L), hi = rc_ehi(rc, K, L);
+        for (int p = b; p < e; ++p) {
+            r64.push_back(t.y[p]);
+            for (int q = lo; q <= hi; ++q) {
+                r64.push_back(t.dw[(size_t)q * P + p]);
+                r32.push_back(t.dw_hi[(size_t)q * P + p]);
+                r32.push_back(t.dw_lo[(size_t)q * P + p]);
+            }
+            r64.push_back(t.wabs[p]);
+        }
+    }
+    return true;
+}
+
 }  // namespace sg

@@ -14,7 +14,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsgmdi.so")
+# SGMDI_LIB: developer override of the library file (kernel variants)
+LIB_PATH = os.environ.get("SGMDI_LIB") or os.path.join(_HERE, "libsgmdi.so")
 
 RULES = {"tr": 1, "cc": 2, "gl": 4, "gl_paper": 5}
 FAMILIES = {"exp_sum": 0, "oscillatory": 1, "product_peak": 2}
@@ -39,7 +40,8 @@ class SgPlanInfo(ctypes.Structure):
     _fields_ = [("effective_points", ctypes.c_uint64), ("units", ctypes.c_uint64),
                 ("pair_evals", ctypes.c_uint64), ("macs", ctypes.c_uint64),
                 ("merge_flops", ctypes.c_uint64), ("block_threads", ctypes.c_int32),
-                ("grid_blocks", ctypes.c_int32)]
+                ("grid_blocks", ctypes.c_int32), ("waves_cap", ctypes.c_int32),
+                ("graph", ctypes.c_int32)]
 
 
 _lib = None
