@@ -129,7 +129,7 @@ def main():
         got = out.cpu().numpy()
         bnd = bound.cpu().numpy()
         info = plan.info()
-        log(f"  {precision}: waves_cap {info['waves_cap']} graph {info['graph']} grid {info['grid_blocks']}, "
+        log(f"  {precision}: sched {info['waves_cap']} graph {info['graph']} grid {info['grid_blocks']}, "
             f"kernel {np.mean(kern_ms) * 1e3:.2f} us, step {(t1 - t0) * 1e6 / steps:.2f} us")
         plan.close()
         return dict(ms_per_step=(t1 - t0) * 1e3 / steps, kernel_ms=float(np.mean(kern_ms)),

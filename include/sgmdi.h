@@ -26,9 +26,9 @@
  *     a rejected call launches nothing and writes no output;
  *   - "device" pointers are HIP device allocations owned by the caller
  *     (e.g. torch tensors' data_ptr()); the library keeps no caller pointer
- *     beyond the call, except that a plan caches one captured graph per
- *     (params, out, bound, stream) binding and replays it while the binding
- *     is unchanged;
+ *     beyond the call, except that a plan using graph replay caches one
+ *     captured graph per (params, out, bound, stream) binding and replays
+ *     it while the binding is unchanged;
  *   - "stream" is a hipStream_t passed as void* (NULL = default stream);
  *     device work is asynchronous on that stream;
  *   - one context per host thread; contexts and plans are not thread-safe.
@@ -171,9 +171,10 @@ sg_status sg_plan_create(sg_context *ctx, const sg_problem *problems, int32_t n,
 /* Evaluate every integrand of the plan.  params_dev: the batch's float64
  * parameter array (device); out_dev: n float64 results in problem order
  * (device); bound_dev: NULL or n float64 a-priori bounds on |result - exact
- * Smolyak value| (device).  On a non-default stream, unless the autotuner
- * chose direct launches, the launch is captured into a HIP graph on the
- * first call with a given (params, out, bound, stream) and replayed after.
+ * Smolyak value| (device).  Launched directly by default; when the
+ * autotuner found graph replay faster (non-default streams only), the launch
+ * is captured into a HIP graph on the first call with a given
+ * (params, out, bound, stream) and replayed after.
  * Errors: INVALID_ARGUMENT (NULL plan/params/out), DEVICE, CAPTURE. */
 sg_status sg_plan_execute(sg_plan *plan, const double *params_dev, double *out_dev,
                           double *bound_dev, void *stream);
@@ -197,9 +198,12 @@ sg_status sg_plan_execute_grad(sg_plan *plan, const double *params_dev, const do
  *                     products of the sweep (K(K-1)/2 multiply-adds and K
  *                     adds per unit, multiply-add counted as 2);
  *   block_threads, grid_blocks: the launch shape the plan uses;
- *   waves_cap: most waves one integrand spans; graph: 1 if executions on a
- *   non-default stream replay a captured graph, 0 if they launch directly
- *   (both knobs are chosen by sg_plan_autotune). */
+ *   waves_cap: the schedule of integrands onto waves: > 0 caps every
+ *   integrand at that many waves (1, 2, 4); < 0 gives each integrand the
+ *   fewest waves in {1, 2, 4} that bring one wave's estimated work under
+ *   -waves_cap times the plan's largest per-coordinate cost;
+ *   graph: 1 if executions on a non-default stream replay a captured graph,
+ *   0 if they launch directly (both knobs are chosen by sg_plan_autotune). */
 typedef struct {
     uint64_t effective_points;
     uint64_t units;
@@ -216,8 +220,10 @@ sg_status sg_plan_get_info(const sg_plan *plan, sg_plan_info *info);
 
 /* Time candidate schedules for this plan on `stream` with HIP events and
  * keep the fastest (stored in the context; later plans with the same shape
- * class reuse it): the most waves one integrand may span (1, 2, 4) and, on a
- * non-default stream, graph replay versus direct launch.  Runs the forward
+ * class reuse it): the integrand-to-wave schedule (waves caps 1, 2, 4 and
+ * cost thresholds 1, 2, 4 times the largest per-coordinate cost; see
+ * sg_plan_info.waves_cap) and, on a non-default stream, graph replay versus
+ * direct launch.  Runs the forward
  * launch repeatedly on params_dev/out_dev (their contents are overwritten).
  * Errors: INVALID_ARGUMENT, DEVICE. */
 sg_status sg_plan_autotune(sg_plan *plan, const double *params_dev, double *out_dev, void *stream);

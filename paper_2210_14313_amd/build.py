@@ -5,6 +5,7 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -12,7 +13,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsgmdi.so")
 
-SOURCES = ["sg_kernels.hip", "sg_rules.cpp", "sg_counts.cpp", "sg_api.cpp"]
+SOURCES = ["sg_fwd0.hip", "sg_fwd1.hip", "sg_adj0.hip", "sg_adj1.hip", "sg_unrank.hip",
+           "sg_rules.cpp", "sg_counts.cpp", "sg_api.cpp"]
 
 # Packed FP32 instructions are disabled for every device pass; contraction of
 # a*b+c into FMAs is off so that compensated (two-sum) sequences keep their
@@ -33,8 +35,8 @@ def build(verbose: bool = False, extra_flags=None) -> str:
     """Compile every source and link libsgmdi.so next to this file."""
     objdir = os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
-    for src in SOURCES:
+
+    def compile_one(src):
         path = os.path.join(CSRC, src)
         obj = os.path.join(objdir, src + ".o")
         cmd = [hipcc()] + HIP_FLAGS + (extra_flags or []) + ["-I", INCLUDE, "-I", CSRC, "-c", path, "-o", obj]
@@ -44,7 +46,12 @@ def build(verbose: bool = False, extra_flags=None) -> str:
         if r.returncode != 0:
             sys.stderr.write(r.stdout + r.stderr)
             raise RuntimeError(f"compiling {src} failed")
-        objs.append(obj)
+        return obj
+
+    # the kernel units are independent: compile them in parallel
+    workers = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -46,7 +46,7 @@ struct sg_context {
     std::string last_error;
     std::map<std::pair<int, int>, std::unique_ptr<DeltaTable>> tables;
     std::map<std::pair<int, int>, std::unique_ptr<Records>> records;
-    std::map<std::string, std::pair<int, bool>> tuned;   // plan shape -> (waves cap, graph)
+    std::map<std::string, std::pair<int, bool>> tuned;   // plan shape -> (schedule, graph)
     std::map<std::tuple<int, int, int, int>, PlainEntry> plain;
     std::map<std::pair<int, int>, uint64_t*> unrank_tables;
     int live_plans = 0;
@@ -62,9 +62,12 @@ struct sg_plan {
     double* d_pool64 = nullptr;
     float* d_pool32 = nullptr;
     std::vector<ProbDev> probs;     // plan order (longest first)
-    int wmax = 4;                   // waves-per-problem cap
-    bool use_graph = true;          // replay a captured graph (else direct launch)
+    std::vector<double> unit_cost;  // per-coordinate cost estimate, plan order
+    double cmax = 1.0;              // largest unit cost of the plan
+    int wmax = 4;                   // schedule: > 0 waves cap, < 0 cost threshold (see waves_for)
+    bool use_graph = false;         // replay a captured graph (else direct launch)
     bool params_disjoint = true;    // problems' parameter ranges do not overlap
+    int kmax = 0;                   // largest K of the plan (kernel instantiation class)
     double* d_ws = nullptr;         // reverse-sweep workspace (sum d*K doubles), lazy
     size_t ws_elems = 0;
     int nwg = 0;
@@ -143,29 +146,41 @@ const Records* get_records(sg_context* ctx, int rule, int K, sg_status& st)
     return out;
 }
 
-int waves_for(int d, int wmax)
+// Waves assigned to one problem under a schedule: sched > 0 caps every
+// problem at `sched` waves (one coordinate per lane when possible); sched < 0
+// gives a problem the fewest waves in {1, 2, 4} that bring one wave's work,
+// ceil(d / (64 w)) * unit_cost, under -sched times the largest unit cost of
+// the plan (so expensive problems are split and cheap ones are not).
+int waves_for(int d, double unit_cost, int sched, double cmax)
 {
-    int w = (d + 63) / 64;
-    if (w > wmax) w = wmax;
-    if (w == 3) w = 4;
-    return w < 1 ? 1 : w;
+    const int full = std::max(1, (d + 63) / 64);
+    int w = 1;
+    if (sched > 0) {
+        w = std::min(full, sched);
+        if (w == 3) w = 4;
+    } else {
+        const double T = -(double)sched * cmax;
+        while (w < 4 && w < full && (double)((d + 64 * w - 1) / (64 * w)) * unit_cost > T) w *= 2;
+    }
+    return w;
 }
 
 // Pack problems (in plan order) into 4-wave workgroups, first fit.  A
 // problem of w waves takes w consecutive slots of one workgroup.
-std::vector<WGDesc> pack_workgroups(const std::vector<ProbDev>& probs, int wmax)
+std::vector<WGDesc> pack_workgroups(const std::vector<ProbDev>& probs, const std::vector<int>& waves)
 {
     std::vector<WGDesc> wgs;
     std::vector<int> used;
     std::vector<int> open;   // indices of workgroups with free slots
     for (size_t k = 0; k < probs.size(); ++k) {
-        const int w = waves_for(probs[k].d, wmax);
+        const int w = waves[k];
         int target = -1;
         for (size_t o = 0; o < open.size(); ++o) {
             if (4 - used[open[o]] >= w) { target = open[o]; break; }
         }
         if (target < 0) {
             WGDesc e;
+            std::memset(&e, 0, sizeof e);
             for (int i = 0; i < 4; ++i) { e.slot[i].prob = -1; e.slot[i].rank = 0; e.slot[i].group = 1; }
             wgs.push_back(e);
             used.push_back(0);
@@ -174,6 +189,8 @@ std::vector<WGDesc> pack_workgroups(const std::vector<ProbDev>& probs, int wmax)
         }
         for (int r = 0; r < w; ++r) {
             WaveSlot& sl = wgs[target].slot[used[target] + r];
+            sl.p = probs[k];
+            sl.p.waves = w;
             sl.prob = (int32_t)k;
             sl.rank = (int16_t)r;
             sl.group = (int16_t)w;
@@ -440,13 +457,17 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
         info.macs = sat_add(info.macs, sat_mul(d, macs));
         info.merge_flops = sat_add(info.merge_flops, sat_mul(d, K * K));
         maxd = std::max(maxd, problems[i].d);
+        p->kmax = std::max(p->kmax, (int)K);
     }
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
     p->probs.resize(n);
+    p->unit_cost.resize(n);
     for (int k = 0; k < n; ++k) {
         const int i = order[k];
+        p->unit_cost[k] = cost[i] / (double)problems[i].d;
+        p->cmax = std::max(p->cmax, p->unit_cost[k]);
         ProbDev& r = p->probs[k];
         const int K = problems[i].q - problems[i].d;
         r.d = problems[i].d;
@@ -480,14 +501,16 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
     snprintf(key, sizeof key, "p%d_n%d_maxd%d", precision, n, maxd);
     p->tune_key = key;
     auto tk = ctx->tuned.find(p->tune_key);
-    p->wmax = tk != ctx->tuned.end() ? tk->second.first : 4;
-    p->use_graph = tk != ctx->tuned.end() ? tk->second.second : true;
+    p->wmax = tk != ctx->tuned.end() ? tk->second.first : -1;
+    p->use_graph = tk != ctx->tuned.end() ? tk->second.second : false;
     if (const char* fw = std::getenv("SGMDI_WMAX")) {   // debug / profiling override
         const int w = std::atoi(fw);
-        if (w == 1 || w == 2 || w == 4) p->wmax = w;
+        if (w == 1 || w == 2 || w == 4 || w == -1 || w == -2 || w == -4) p->wmax = w;
     }
-    std::vector<WGDesc> wgs = pack_workgroups(p->probs, p->wmax);
-    for (auto& pr : p->probs) pr.waves = waves_for(pr.d, p->wmax);
+    std::vector<int> wv(n);
+    for (int k = 0; k < n; ++k) wv[k] = waves_for(p->probs[k].d, p->unit_cost[k], p->wmax, p->cmax);
+    std::vector<WGDesc> wgs = pack_workgroups(p->probs, wv);
+    for (int k = 0; k < n; ++k) p->probs[k].waves = wv[k];
     p->nwg = (int)wgs.size();
     info.block_threads = 256;
     info.grid_blocks = p->nwg;
@@ -508,16 +531,19 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
 
 static sg_status plan_launch(sg_plan* p, const double* params, double* out, double* bound, void* stream)
 {
-    const int rc = launch_forward(p->precision, p->nwg, p->d_wgs, p->d_probs, p->d_pool64, p->d_pool32, params,
-                                  out, bound, stream);
+    const int rc = launch_forward(p->precision, p->kmax, p->nwg, p->d_wgs, p->d_probs, p->d_pool64, p->d_pool32,
+                                  params, out, bound, stream);
     if (rc != 0) return hip_fail(p->ctx, (hipError_t)rc, "forward launch");
     return SG_OK;
 }
 
-// Re-pack the plan's workgroups for another waves-per-problem cap.
-static sg_status plan_repack(sg_plan* p, int wmax)
+// Re-pack the plan's workgroups for another schedule.
+static sg_status plan_repack(sg_plan* p, int sched)
 {
-    std::vector<WGDesc> wgs = pack_workgroups(p->probs, wmax);
+    std::vector<int> wv(p->probs.size());
+    for (size_t k = 0; k < p->probs.size(); ++k)
+        wv[k] = waves_for(p->probs[k].d, p->unit_cost[k], sched, p->cmax);
+    std::vector<WGDesc> wgs = pack_workgroups(p->probs, wv);
     if (wgs.size() > p->wg_capacity) {
         hipFree(p->d_wgs);
         p->d_wgs = nullptr;
@@ -528,11 +554,11 @@ static sg_status plan_repack(sg_plan* p, int wmax)
         hipError_t e = hipMemcpy(p->d_wgs, wgs.data(), wgs.size() * sizeof(WGDesc), hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(p->ctx, e, "hipMemcpy");
     }
-    p->wmax = wmax;
+    p->wmax = sched;
     p->nwg = (int)wgs.size();
     p->info.grid_blocks = p->nwg;
-    p->info.waves_cap = wmax;
-    for (auto& pr : p->probs) pr.waves = waves_for(pr.d, wmax);
+    p->info.waves_cap = sched;
+    for (size_t k = 0; k < p->probs.size(); ++k) p->probs[k].waves = wv[k];
     return SG_OK;
 }
 
@@ -552,7 +578,7 @@ sg_status sg_plan_execute(sg_plan* p, const double* params_dev, double* out_dev,
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return fail(p->ctx, SG_ERR_CAPTURE, std::string("begin capture: ") + hipGetErrorString(e));
-    const int rc = launch_forward(p->precision, p->nwg, p->d_wgs, p->d_probs, p->d_pool64, p->d_pool32,
+    const int rc = launch_forward(p->precision, p->kmax, p->nwg, p->d_wgs, p->d_probs, p->d_pool64, p->d_pool32,
                                   params_dev, out_dev, bound_dev, stream);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(s, &graph);
@@ -619,7 +645,7 @@ sg_status sg_plan_autotune(sg_plan* p, const double* params_dev, double* out_dev
     bool best_g = saved_g;
     float best_ms = 1e30f;
     const int reps = 20;
-    const int cands[3] = {1, 2, 4};
+    const int cands[6] = {1, 2, 4, -1, -2, -4};
     sg_status st = SG_OK;
     // candidates: waves-per-problem cap x (graph replay | direct launch);
     // the graph variant is only timed on a non-default stream
@@ -691,9 +717,10 @@ sg_status sg_integrate(sg_context* ctx, const sg_problem* problem, int32_t preci
         pd.off64 = 0;
         pd.off32 = 0;
         pd.out_index = 0;
-        pd.waves = waves_for(pd.d, 4);
         pd.ws_off = 0;
-        std::vector<WGDesc> wgs = pack_workgroups(pv, 4);
+        std::vector<int> wv(1, waves_for(pd.d, 1.0, 4, 1.0));
+        pd.waves = wv[0];
+        std::vector<WGDesc> wgs = pack_workgroups(pv, wv);
         PlainEntry pe;
         if ((st = upload(ctx, &pe.probs, pv.data(), 1)) != SG_OK) return st;
         if ((st = upload(ctx, &pe.wgs, wgs.data(), wgs.size())) != SG_OK) return st;
@@ -701,7 +728,7 @@ sg_status sg_integrate(sg_context* ctx, const sg_problem* problem, int32_t preci
         if ((st = upload(ctx, &pe.pool32, r->r32.data(), r->r32.size())) != SG_OK) return st;
         it = ctx->plain.emplace(key, pe).first;
     }
-    const int rc = launch_forward(precision, 1, it->second.wgs, it->second.probs, it->second.pool64,
+    const int rc = launch_forward(precision, K, 1, it->second.wgs, it->second.probs, it->second.pool64,
                                   it->second.pool32, params_dev, out_dev, bound_dev, stream);
     if (rc != 0) return hip_fail(ctx, (hipError_t)rc, "forward launch");
     return SG_OK;

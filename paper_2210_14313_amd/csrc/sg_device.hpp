@@ -1,4 +1,6 @@
-// HIP kernels (gfx950) for the Smolyak dimension sweep.
+#pragma once
+// Device code (gfx950) of the Smolyak dimension sweep, included by the
+// per-precision kernel units sg_fwd*.hip / sg_adj*.hip / sg_unrank.hip.
 //
 // Method (Section 2.1 (2.6), Section 3 (3.9)-(3.11)).  With K = q - d, the
 // Smolyak sum over the window equals the sum over all multi-indices of
@@ -37,7 +39,7 @@
 #include "sg_internal.hpp"
 
 namespace sg {
-namespace {
+namespace dev {
 
 constexpr int MAXK = kMaxK;
 constexpr int FAM_EXP = SG_FAMILY_EXP_SUM;
@@ -127,17 +129,19 @@ __device__ __forceinline__ float pair32(const CoordParam& cp, double y)
     }
 }
 
-// Compensated FP32 accumulation of w*s with w = wh + wl (two-sum on the
-// running sum, exact product error by FMA, low parts gathered in lo).
+// Compensated FP32 accumulation of w*s with w = wh + wl: two-sum of the
+// rounded product into the running sum (its error goes to lo, exactly), and
+// the low weight part w_l*s added to lo.  Each product keeps its own
+// rounding (half an ulp, independent between terms, the size of the pair
+// value's own rounding); the bound accounts for it.
 __device__ __forceinline__ void acc2(float& hi, float& lo, float wh, float wl, float s)
 {
     const float p = wh * s;
-    const float pe = fmaf(wh, s, -p);
     const float t = hi + p;
     const float bp = t - hi;
     const float err = (hi - (t - bp)) + (p - bp);
     hi = t;
-    lo = fmaf(wl, s, lo + (err + pe));
+    lo = fmaf(wl, s, lo + err);
 }
 
 // ------------------------------------------------- truncated polynomials
@@ -237,30 +241,32 @@ __device__ __forceinline__ void surplus32(const double* __restrict__ r64, const 
 }
 
 // ----------------------------------------------------------- merge state
-// Running polynomial a, its absolute-value twin ab (error bound), the
-// affine partial sum ls, sum |terms of ls|, and the bound accumulator eps.
+// Running polynomial a; for the error bound, m = sum_t sum_e |delta_t[e]| and
+// eps = sum_t sum_p sum_e |dW[e][p]| |s_p|; the affine partial sum ls and
+// sum |terms of ls|.
 struct Acc {
     double a[MAXK + 1];
-    double ab[MAXK + 1];
-    double ls, lsabs, eps;
+    double m, ls, lsabs, eps;
 };
 
 template <int K>
 __device__ __forceinline__ void acc_identity(Acc& x)
 {
 #pragma unroll
-    for (int k = 0; k <= MAXK; ++k) { x.a[k] = 0.0; x.ab[k] = 0.0; }
-    x.ls = x.lsabs = x.eps = 0.0;
+    for (int k = 0; k <= MAXK; ++k) x.a[k] = 0.0;
+    x.m = x.ls = x.lsabs = x.eps = 0.0;
 }
 
 template <int K>
 __device__ __forceinline__ void merge(Acc& x, const Acc& y, bool want_bound)
 {
     pmul<K>(x.a, y.a);
-    if (want_bound) pmul<K>(x.ab, y.ab);
+    if (want_bound) {
+        x.m += y.m;
+        x.eps += y.eps;
+    }
     x.ls += y.ls;
     x.lsabs += y.lsabs;
-    x.eps += y.eps;
 }
 
 template <int K>
@@ -269,34 +275,95 @@ __device__ __forceinline__ void shfl_acc(Acc& o, const Acc& x, int mask, bool wa
 #pragma unroll
     for (int k = 1; k <= K; ++k) o.a[k] = __shfl_xor(x.a[k], mask);
     if (want_bound) {
-#pragma unroll
-        for (int k = 1; k <= K; ++k) o.ab[k] = __shfl_xor(x.ab[k], mask);
+        o.m = __shfl_xor(x.m, mask);
+        o.eps = __shfl_xor(x.eps, mask);
     }
     o.ls = __shfl_xor(x.ls, mask);
     o.lsabs = __shfl_xor(x.lsabs, mask);
-    o.eps = __shfl_xor(x.eps, mask);
 }
 
-constexpr int ACC_WORDS = 2 * MAXK + 3;   // doubles per wave in LDS
+// DPP moves of a double (two 32-bit halves).  Lanes whose source is outside
+// the pattern, or whose row is masked off, receive `fill`.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v, double fill)
+{
+    const long long bv = __double_as_longlong(v), bf = __double_as_longlong(fill);
+    const int lo = __builtin_amdgcn_update_dpp((int)bf, (int)bv, CTRL, ROW_MASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(bf >> 32), (int)(bv >> 32), CTRL, ROW_MASK, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// One reduction step: x <- x (*) (state moved by the DPP pattern); lanes
+// without a source multiply by the identity.
+template <int K, int CTRL, int ROW_MASK>
+__device__ __forceinline__ void dpp_step(Acc& x, bool want_bound)
+{
+    Acc o;
+#pragma unroll
+    for (int k = 1; k <= K; ++k) o.a[k] = dpp_f64<CTRL, ROW_MASK>(x.a[k], 0.0);
+    if (want_bound) {
+        o.m = dpp_f64<CTRL, ROW_MASK>(x.m, 0.0);
+        o.eps = dpp_f64<CTRL, ROW_MASK>(x.eps, 0.0);
+    }
+    o.ls = dpp_f64<CTRL, ROW_MASK>(x.ls, 0.0);
+    o.lsabs = dpp_f64<CTRL, ROW_MASK>(x.lsabs, 0.0);
+    merge<K>(x, o, want_bound);
+}
+
+// Reduce the wave's lane states towards one lane with DPP row shifts and row
+// broadcasts (no LDS traffic).  Only lanes 0..nact-1 hold coordinates; the
+// fixed step pattern makes the result deterministic.  Returns the lane that
+// holds the whole wave's state (15, 31 or 63).
+template <int K>
+__device__ __forceinline__ int wave_reduce_dpp(Acc& x, int nact, bool want_bound)
+{
+    constexpr int ROW_SHR1 = 0x111, ROW_SHR2 = 0x112, ROW_SHR4 = 0x114, ROW_SHR8 = 0x118;
+    constexpr int ROW_BCAST15 = 0x142, ROW_BCAST31 = 0x143;
+    if (nact > 1) dpp_step<K, ROW_SHR1, 0xF>(x, want_bound);
+    if (nact > 2) dpp_step<K, ROW_SHR2, 0xF>(x, want_bound);
+    if (nact > 4) dpp_step<K, ROW_SHR4, 0xF>(x, want_bound);
+    if (nact > 8) dpp_step<K, ROW_SHR8, 0xF>(x, want_bound);
+    // after the shifts up to 2^j, lane 2^(j+1)-1 holds lanes 0 .. 2^(j+1)-1
+    if (nact <= 16) return nact <= 1 ? 0 : nact <= 2 ? 1 : nact <= 4 ? 3 : nact <= 8 ? 7 : 15;
+    // lane 15 of each row now holds its row; row 1 takes row 0's total, row 3 row 2's
+    dpp_step<K, ROW_BCAST15, 0xA>(x, want_bound);
+    if (nact <= 32) return 31;
+    dpp_step<K, ROW_BCAST31, 0xC>(x, want_bound);
+    return 63;
+}
+
+constexpr int ACC_WORDS = MAXK + 4;   // doubles per wave in LDS
 
 template <int K>
 __device__ __forceinline__ void acc_store(const Acc& x, double* s)
 {
 #pragma unroll
-    for (int k = 1; k <= K; ++k) { s[k - 1] = x.a[k]; s[MAXK + k - 1] = x.ab[k]; }
-    s[2 * MAXK] = x.ls;
-    s[2 * MAXK + 1] = x.lsabs;
-    s[2 * MAXK + 2] = x.eps;
+    for (int k = 1; k <= K; ++k) s[k - 1] = x.a[k];
+    s[MAXK] = x.m;
+    s[MAXK + 1] = x.ls;
+    s[MAXK + 2] = x.lsabs;
+    s[MAXK + 3] = x.eps;
 }
 
 template <int K>
 __device__ __forceinline__ void acc_load(Acc& x, const double* s)
 {
 #pragma unroll
-    for (int k = 1; k <= K; ++k) { x.a[k] = s[k - 1]; x.ab[k] = s[MAXK + k - 1]; }
-    x.ls = s[2 * MAXK];
-    x.lsabs = s[2 * MAXK + 1];
-    x.eps = s[2 * MAXK + 2];
+    for (int k = 1; k <= K; ++k) x.a[k] = s[k - 1];
+    x.m = s[MAXK];
+    x.ls = s[MAXK + 1];
+    x.lsabs = s[MAXK + 2];
+    x.eps = s[MAXK + 3];
+}
+
+// Upper bound on every |[z^b] prod_{t in T} delta_t| (any subset T) summed
+// over b <= K: the product of the absolute-value polynomials has
+// non-negative coefficients, 1 + x <= exp(x) coefficient-wise, and a sum of
+// non-negative coefficients is at most the value at z = 1, so the bound is
+// exp(m) with m = sum_t sum_e |delta_t[e]|.
+__device__ __forceinline__ double abs_product_bound(double m)
+{
+    return exp(m) * (1.0 + 1e-13);
 }
 
 // ------------------------------------------------------------ read-out
@@ -307,15 +374,17 @@ __device__ void readout(const Acc& x, const ProbDev& P, const double* __restrict
                         double* out, double* bound)
 {
     const bool want_bound = bound != nullptr;
-    double s = 0.0, sabs = 0.0;
+    double s = 0.0;
 #pragma unroll
-    for (int k = K; k >= 1; --k) { s += x.a[k]; sabs += x.ab[k]; }
+    for (int k = K; k >= 1; --k) s += x.a[k];
     s += 1.0;
-    sabs += 1.0;
+    const double sabs = want_bound ? abs_product_bound(x.m) : 0.0;
     const double u64 = 1.1102230246251565e-16;
     const double ls_err = u64 * (double)P.d * x.lsabs;   // rounding of the affine sum
-    // relative error of one surplus: pair value + within-rule sum
-    const double rel = PREC == SG_PREC_FP64 ? u64 * (4.0 + (double)rl_pairs) : 5.9604644775390625e-08 * 4.0;
+    // relative error of one surplus term: pair value (8 roundings) plus the
+    // within-rule sum (FP64: a plain FMA chain over at most rl_pairs terms;
+    // FP32: one rounding of the product, compensated accumulation)
+    const double rel = PREC == SG_PREC_FP64 ? u64 * (8.0 + (double)rl_pairs) : 5.9604644775390625e-08 * 10.0;
     // products of the sweep: (K+2) roundings per merge level
     const double levels = (double)((P.d + 63) / 64 + 10);
     double Q;
@@ -394,25 +463,21 @@ __device__ __forceinline__ void wave_sweep(const ProbDev& P, int rank, int group
         else surplus32<K, RC, FAM>(r64i, r32i, cp, want_bound, del, eps_t);
         pmul<K>(x.a, del);
         if (want_bound) {
-            double dab[MAXK + 1];
+            double mt = 0.0;
 #pragma unroll
-            for (int k = 0; k <= MAXK; ++k) dab[k] = fabs(del[k]);
-            pmul<K>(x.ab, dab);
+            for (int k = 1; k <= K; ++k) mt += fabs(del[k]);
+            x.m += mt;
+            x.eps += eps_t;
         }
         x.ls += lterm;
         x.lsabs += fabs(lterm);
-        x.eps += eps_t;
     }
-    // butterfly over the lanes that hold coordinates (lane 0 ends with all)
+    // reduce over the lanes that hold coordinates
     const int nact = min(64, max(0, d - rank * 64));
-    for (int m = 1; m < nact; m <<= 1) {
-        Acc o;
-        shfl_acc<K>(o, x, m, want_bound);
-        merge<K>(x, o, want_bound);
-    }
+    const int root = wave_reduce_dpp<K>(x, nact, want_bound);
     if (group == 1) {
-        if (lane == 0) readout<PREC, K, FAM>(x, P, prm, total_pairs<RC, K>(), out, bound);
-    } else if (lane == 0) {
+        if (lane == root) readout<PREC, K, FAM>(x, P, prm, total_pairs<RC, K>(), out, bound);
+    } else if (lane == root) {
         acc_store<K>(x, lds_slot);
     }
 }
@@ -462,23 +527,19 @@ __device__ __forceinline__ void group_finish_k(const ProbDev& P, int group, cons
     else readout<PREC, K, FAM_PEAK>(x, P, prm, np, out, bound);
 }
 
-#define SG_SWITCH_K(K_, CALL)                      \
-    switch (K_) {                                  \
-    case 0: CALL(0); break;                        \
-    case 1: CALL(1); break;                        \
-    case 2: CALL(2); break;                        \
-    case 3: CALL(3); break;                        \
-    case 4: CALL(4); break;                        \
-    case 5: CALL(5); break;                        \
-    case 6: CALL(6); break;                        \
-    case 7: CALL(7); break;                        \
-    default: CALL(8); break;                       \
-    }
+// Dispatch a runtime K in [0, KMAXP] to a compile-time K.
+template <int KMAXP, class F>
+__device__ __forceinline__ void switch_k(int K, F&& f)
+{
+    static_for<0, KMAXP + 1>([&](auto kc) {
+        if (K == decltype(kc)::value) f(kc);
+    });
+}
 
 // Each workgroup holds 4 waves; wave w works on wgs[blockIdx.x].slot[w].
 // Problems spanning several waves sit in consecutive slots of one
 // workgroup and are merged through LDS by their first wave.
-template <int PREC>
+template <int PREC, int KMAXP>
 __global__ void __launch_bounds__(256)
 k_forward(const WGDesc* __restrict__ wgs, const ProbDev* __restrict__ probs,
           const double* __restrict__ pool64, const float* __restrict__ pool32,
@@ -487,25 +548,26 @@ k_forward(const WGDesc* __restrict__ wgs, const ProbDev* __restrict__ probs,
     __shared__ double lds[4 * ACC_WORDS];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const WGDesc* desc = wgs + blockIdx.x;
-    WaveSlot sl = desc->slot[w];
-    sl.prob = __builtin_amdgcn_readfirstlane(sl.prob);
-    sl.rank = (int16_t)__builtin_amdgcn_readfirstlane(sl.rank);
-    sl.group = (int16_t)__builtin_amdgcn_readfirstlane(sl.group);
+    struct { int32_t prob; int16_t rank, group; } sl;
+    sl.prob = __builtin_amdgcn_readfirstlane(desc->slot[w].prob);
+    sl.rank = (int16_t)__builtin_amdgcn_readfirstlane(desc->slot[w].rank);
+    sl.group = (int16_t)__builtin_amdgcn_readfirstlane(desc->slot[w].group);
     const bool grouped = desc->slot[0].group > 1 || desc->slot[1].group > 1 || desc->slot[2].group > 1 ||
                          desc->slot[3].group > 1;
     ProbDev P;
     if (sl.prob >= 0) {
-        P = probs[sl.prob];
-#define SG_CALL(KK) wave_dispatch_k<PREC, KK>(P, sl.rank, sl.group, pool64, pool32, params, out, bound, lds + w * ACC_WORDS)
-        SG_SWITCH_K(P.K, SG_CALL)
-#undef SG_CALL
+        P = desc->slot[w].p;
+        switch_k<KMAXP>(P.K, [&](auto kc) {
+            wave_dispatch_k<PREC, decltype(kc)::value>(P, sl.rank, sl.group, pool64, pool32, params, out, bound,
+                                                      lds + w * ACC_WORDS);
+        });
     }
     if (!grouped) return;
     __syncthreads();
     if (sl.prob >= 0 && sl.group > 1 && sl.rank == 0 && (threadIdx.x & 63) == 0) {
-#define SG_CALL(KK) group_finish_k<PREC, KK>(P, sl.group, lds + w * ACC_WORDS, params, out, bound)
-        SG_SWITCH_K(P.K, SG_CALL)
-#undef SG_CALL
+        switch_k<KMAXP>(P.K, [&](auto kc) {
+            group_finish_k<PREC, decltype(kc)::value>(P, sl.group, lds + w * ACC_WORDS, params, out, bound);
+        });
     }
 }
 
@@ -818,115 +880,22 @@ k_adjoint(const WGDesc* __restrict__ wgs, const ProbDev* __restrict__ probs, con
     __shared__ double lds[4 * ADJ_WORDS];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const WGDesc* desc = wgs + blockIdx.x;
-    WaveSlot sl = desc->slot[w];
-    sl.prob = __builtin_amdgcn_readfirstlane(sl.prob);
-    sl.rank = (int16_t)__builtin_amdgcn_readfirstlane(sl.rank);
-    sl.group = (int16_t)__builtin_amdgcn_readfirstlane(sl.group);
+    struct { int32_t prob; int16_t rank, group; } sl;
+    sl.prob = __builtin_amdgcn_readfirstlane(desc->slot[w].prob);
+    sl.rank = (int16_t)__builtin_amdgcn_readfirstlane(desc->slot[w].rank);
+    sl.group = (int16_t)__builtin_amdgcn_readfirstlane(desc->slot[w].group);
     const bool grouped = desc->slot[0].group > 1 || desc->slot[1].group > 1 || desc->slot[2].group > 1 ||
                          desc->slot[3].group > 1;
     if (sl.prob < 0) {
         if (grouped) __syncthreads();
         return;
     }
-    const ProbDev P = probs[sl.prob];
-#define SG_CALL(KK) adjoint_dispatch_k<PREC, KK>(P, sl.rank, sl.group, grouped, pool64, pool32, params, gout, grad, ws, lds + w * ADJ_WORDS)
-    SG_SWITCH_K(P.K, SG_CALL)
-#undef SG_CALL
+    const ProbDev P = desc->slot[w].p;
+    switch_k<MAXK>(P.K, [&](auto kc) {
+        adjoint_dispatch_k<PREC, decltype(kc)::value>(P, sl.rank, sl.group, grouped, pool64, pool32, params, gout,
+                                                      grad, ws, lds + w * ADJ_WORDS);
+    });
 }
 
-// ------------------------------------------------------------- unranking
-// Canonical order of the window of (2.6): excess ascending, then
-// (l_1..l_d) in decreasing lexicographic order.  W[n * (d+1) + parts] holds
-// the number of weak compositions of n into `parts` parts (host-computed,
-// exact, n <= K).  One thread per rank, one workgroup per block of ranks.
-__global__ void __launch_bounds__(256)
-k_unrank(int d, int q, uint64_t rank0, uint64_t count, int max_nnz, const uint64_t* __restrict__ W,
-         int32_t* __restrict__ coords, int32_t* __restrict__ levels, int32_t* __restrict__ nnz)
-{
-    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= count) return;
-    const int K = q - d;
-    const int stride = d + 1;
-    auto weak = [&](int n, int parts) -> uint64_t { return W[(size_t)n * stride + parts]; };
-    uint64_t r = rank0 + g;
-    int e = K - d + 1 > 0 ? K - d + 1 : 0;
-    for (; e < K; ++e) {
-        const uint64_t c = weak(e, d);
-        if (r < c) break;
-        r -= c;
-    }
-    int32_t* co = coords + g * max_nnz;
-    int32_t* le = levels + g * max_nnz;
-    for (int k = 0; k < max_nnz; ++k) { co[k] = -1; le[k] = 0; }
-    int i = 0, rem = e, k = 0;
-    while (rem > 0 && k < max_nnz) {
-        const uint64_t total = weak(rem, d - i);
-        const uint64_t T = total - r;
-        int lo = i, hi = d - 1;
-        while (lo < hi) {
-            const int mid = lo + (hi - lo + 1) / 2;
-            if (weak(rem, d - mid) >= T) lo = mid; else hi = mid - 1;
-        }
-        const int j = lo;
-        r -= total - weak(rem, d - j);
-        int a = rem;
-        for (; a > 1; --a) {
-            const uint64_t cnt = weak(rem - a, d - j - 1);
-            if (r < cnt) break;
-            r -= cnt;
-        }
-        co[k] = j;
-        le[k] = a + 1;
-        ++k;
-        rem -= a;
-        i = j + 1;
-    }
-    nnz[g] = k;
-}
-
-}  // namespace
-
-int launch_forward(int precision, int nwg, const WGDesc* wgs, const ProbDev* probs, const double* pool64,
-                   const float* pool32, const double* params, double* out, double* bound, void* stream)
-{
-    if (nwg <= 0) return 0;
-    const dim3 grid((unsigned)nwg), block(256);
-    hipStream_t s = (hipStream_t)stream;
-    if (precision == SG_PREC_FP64)
-        hipLaunchKernelGGL((k_forward<SG_PREC_FP64>), grid, block, 0, s, wgs, probs, pool64, pool32, params, out, bound);
-    else
-        hipLaunchKernelGGL((k_forward<SG_PREC_FP32_COMPENSATED>), grid, block, 0, s, wgs, probs, pool64, pool32, params, out, bound);
-    return (int)hipGetLastError();
-}
-
-int launch_adjoint(int precision, int nwg, const WGDesc* wgs, const ProbDev* probs, const double* pool64,
-                   const float* pool32, const double* params, const double* gout, double* grad, double* ws,
-                   void* stream)
-{
-    if (nwg <= 0) return 0;
-    const dim3 grid((unsigned)nwg), block(256);
-    hipStream_t s = (hipStream_t)stream;
-    if (precision == SG_PREC_FP64)
-        hipLaunchKernelGGL((k_adjoint<SG_PREC_FP64>), grid, block, 0, s, wgs, probs, pool64, pool32, params, gout, grad, ws);
-    else
-        hipLaunchKernelGGL((k_adjoint<SG_PREC_FP32_COMPENSATED>), grid, block, 0, s, wgs, probs, pool64, pool32, params, gout, grad, ws);
-    return (int)hipGetLastError();
-}
-
-int launch_unrank(int d, int q, uint64_t rank0, uint64_t count, int max_nnz,
-                  const uint64_t* W, int /*rows*/, int32_t* coords, int32_t* levels, int32_t* nnz,
-                  void* stream)
-{
-    if (count == 0) return 0;
-    const unsigned blocks = (unsigned)((count + 255) / 256);
-    hipLaunchKernelGGL(k_unrank, dim3(blocks), dim3(256), 0, (hipStream_t)stream, d, q, rank0, count,
-                       max_nnz, W, coords, levels, nnz);
-    return (int)hipGetLastError();
-}
-
-const char* device_error_string(int code)
-{
-    return hipGetErrorString((hipError_t)code);
-}
-
+}  // namespace dev
 }  // namespace sg

@@ -105,7 +105,8 @@ struct ProbDev {
 // One workgroup = 4 waves; wave w works on problem slot[w].prob (or idles
 // when prob < 0) as wave `rank` of a group of `group` waves.
 struct WaveSlot {
-    int32_t prob;
+    ProbDev p;         // copy of the problem record (saves a dependent load)
+    int32_t prob;      // plan index of the problem, -1 for an idle wave
     int16_t rank, group;
 };
 struct WGDesc {
@@ -116,8 +117,9 @@ struct LaunchCfg {
     int block = 256;   // threads per workgroup (always 4 waves)
 };
 
-// Kernel launchers (sg_kernels.hip).
-int launch_forward(int precision, int nwg, const WGDesc* wgs, const ProbDev* probs,
+// Kernel launchers (sg_unrank.hip dispatches to sg_fwd*.hip / sg_adj*.hip).
+// kmax: the largest K of the launched problems (selects the instantiation).
+int launch_forward(int precision, int kmax, int nwg, const WGDesc* wgs, const ProbDev* probs,
                    const double* pool64, const float* pool32, const double* params, double* out,
                    double* bound, void* stream);
 int launch_adjoint(int precision, int nwg, const WGDesc* wgs, const ProbDev* probs, const double* pool64,
