@@ -31,15 +31,45 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+def host_cxx() -> str:
+    for c in (os.environ.get("CXX"), shutil.which("g++"), shutil.which("c++"), shutil.which("clang++")):
+        if c and os.path.exists(c):
+            return c
+    raise RuntimeError("no host C++ compiler found")
+
+
+def generate_tables(objdir: str, verbose: bool = False) -> None:
+    """Write sg_tables.inc: the difference-rule records of every (rule, K)
+    as C++ constants, produced by the library's own rule construction."""
+    exe = os.path.join(objdir, "gen_tables")
+    cmd = [host_cxx(), "-O2", "-std=c++17", "-I", INCLUDE, "-I", CSRC, os.path.join(CSRC, "gen_tables.cpp"),
+           os.path.join(CSRC, "sg_rules.cpp"), "-o", exe]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("compiling gen_tables failed")
+    r = subprocess.run([exe], capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stderr)
+        raise RuntimeError("gen_tables failed")
+    tmp = os.path.join(objdir, "sg_tables.inc.tmp")
+    with open(tmp, "w") as f:
+        f.write(r.stdout)
+    os.replace(tmp, os.path.join(objdir, "sg_tables.inc"))
+
+
 def build(verbose: bool = False, extra_flags=None) -> str:
     """Compile every source and link libsgmdi.so next to this file."""
     objdir = os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)
+    generate_tables(objdir, verbose)
 
     def compile_one(src):
         path = os.path.join(CSRC, src)
         obj = os.path.join(objdir, src + ".o")
-        cmd = [hipcc()] + HIP_FLAGS + (extra_flags or []) + ["-I", INCLUDE, "-I", CSRC, "-c", path, "-o", obj]
+        cmd = [hipcc()] + HIP_FLAGS + (extra_flags or []) + ["-I", INCLUDE, "-I", CSRC, "-I", objdir, "-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)

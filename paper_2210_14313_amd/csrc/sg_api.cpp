@@ -473,7 +473,7 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
         r.d = problems[i].d;
         r.K = K;
         r.family = problems[i].family;
-        r.rclass = rule_class_of(problems[i].rule);
+        r.rule = problems[i].rule;
         r.param_offset = problems[i].param_offset;
         const auto& o = toff[std::make_pair(problems[i].rule, K)];
         r.off64 = o.first;
@@ -712,7 +712,7 @@ sg_status sg_integrate(sg_context* ctx, const sg_problem* problem, int32_t preci
         pd.d = problem->d;
         pd.K = K;
         pd.family = problem->family;
-        pd.rclass = rule_class_of(problem->rule);
+        pd.rule = problem->rule;
         pd.param_offset = 0;
         pd.off64 = 0;
         pd.off32 = 0;

@@ -37,6 +37,7 @@
 #include <type_traits>
 
 #include "sg_internal.hpp"
+#include "sg_tables.inc"
 
 namespace sg {
 namespace dev {
@@ -67,6 +68,33 @@ __device__ __forceinline__ double series64(double z)
 __device__ __forceinline__ float series32(float z)
 {
     float p = 1.0f / 20160.0f;
+    p = fmaf(p, z, 1.0f / 360.0f);
+    p = fmaf(p, z, 1.0f / 12.0f);
+    p = fmaf(p, z, 1.0f);
+    return p;
+}
+
+// The same series on |v| <= 1 (z <= 1), used by the compiled-table path
+// whenever |parameter| <= 2 (every node has y <= 1/2).  First dropped term
+// relative to 1: 2/20! < 1e-18 (FP64, 9 terms) and 2/12! < 5e-9 (FP32, 5 terms).
+__device__ __forceinline__ double series64w(double z)
+{
+    double p = 1.0 / 3201186852864000.0;              // 2/18!
+    p = fma(p, z, 1.0 / 10461394944000.0);             // 2/16!
+    p = fma(p, z, 1.0 / 43589145600.0);                // 2/14!
+    p = fma(p, z, 1.0 / 239500800.0);                  // 2/12!
+    p = fma(p, z, 1.0 / 1814400.0);                    // 2/10!
+    p = fma(p, z, 1.0 / 20160.0);                      // 2/8!
+    p = fma(p, z, 1.0 / 360.0);                        // 2/6!
+    p = fma(p, z, 1.0 / 12.0);                         // 2/4!
+    p = fma(p, z, 1.0);                                // 2/2!
+    return p;
+}
+
+__device__ __forceinline__ float series32w(float z)
+{
+    float p = 1.0f / 1814400.0f;
+    p = fmaf(p, z, 1.0f / 20160.0f);
     p = fmaf(p, z, 1.0f / 360.0f);
     p = fmaf(p, z, 1.0f / 12.0f);
     p = fmaf(p, z, 1.0f);
@@ -110,23 +138,34 @@ __device__ __forceinline__ float pair32(const CoordParam& cp, double y)
 {
     if constexpr (FAM == FAM_EXP || FAM == FAM_OSC) {
         const float v = (float)(cp.p0 * y);       // one rounding of the argument
-        const float z = v * v;
-        const float av = fabsf(v);
-        if (av <= 0.5f) return FAM == FAM_EXP ? z * series32(z) : -z * series32(-z);
-        if constexpr (FAM == FAM_EXP) {
-            const float E = expm1f(av);
-            return E * (E / (1.0f + E));
-        } else {
-            const float sn = sinf(0.5f * v);
-            return -4.0f * sn * sn;
+        if (fabsf(v) <= 1.0f) {
+            const float z = FAM == FAM_EXP ? v * v : -(v * v);
+            return z * series32w(z);
         }
-    } else {
-        // The product-peak pair value is a rational function with no
-        // transcendental; its cancellation-prone parts (y^2, the bracket and
-        // the two denominators) are formed in FP64 and the value is rounded
-        // once, which keeps it within half an FP32 ulp of the exact value.
-        return (float)pair64<FAM_PEAK>(cp, y);
     }
+    // Outside the series range (and for the product-peak family, a rational
+    // function whose cancellation-prone parts need the wider format) the
+    // value is formed in FP64 and rounded once, so every pair value carries
+    // at most the series path's relative error whatever the parameter.
+    return (float)pair64<FAM>(cp, y);
+}
+
+// Pair values on the compiled-table path, |c| <= 2 so |v| <= 1: the node
+// is split as y = yh + yl (two FP32 constants), v = c32 * y in FP32.
+template <int FAM, bool SPLIT>
+__device__ __forceinline__ float pair32_series(float c32, float yh, float yl)
+{
+    const float v = SPLIT ? fmaf(c32, yh, c32 * yl) : c32 * yh;
+    const float z = FAM == FAM_EXP ? v * v : -(v * v);
+    return z * series32w(z);
+}
+
+template <int FAM>
+__device__ __forceinline__ double pair64_series(double c, double y)
+{
+    const double v = c * y;
+    const double z = FAM == FAM_EXP ? v * v : -(v * v);
+    return z * series64w(z);
 }
 
 // Compensated FP32 accumulation of w*s with w = wh + wl: two-sum of the
@@ -238,6 +277,117 @@ __device__ __forceinline__ void surplus32(const double* __restrict__ r64, const 
                                           double& eps)
 {
     surplus32g<K, RC>(r64, r32, [&](double y) { return pair32<FAM>(cp, y); }, want_bound, del, eps);
+}
+
+// ------------------------------------------- compiled-table surpluses
+// For K <= KCONST the record tables of every rule are compiled into the
+// kernels (sg_tables.inc, written at build time by the same host code that
+// builds the run-time tables), so each node and weight is an instruction
+// constant: no table loads and no waits on them in the coordinate loop.
+constexpr int KCONST = 6;
+
+// First pair index of level L in the pair order.
+template <int RC>
+constexpr int pair_base(int L)
+{
+    int n = 0;
+    for (int l = 2; l < L; ++l) n += rc_pairs(RC, l);
+    return n;
+}
+
+// Lowest level whose pairs carry weight in row e (rows are filled first by
+// that level's first pair).
+template <int RC, int K>
+constexpr int first_level(int e)
+{
+    for (int L = 2; L <= K + 1; ++L)
+        if (rc_pairs(RC, L) > 0 && rc_elo(L) <= e && e <= rc_ehi(RC, K, L)) return L;
+    return -1;
+}
+
+// FP64: delta_t[e] = sum_p dW[e][p] s_p with every (y, dW, sum|dW|) a
+// compile-time constant.  `fast` lanes (|c| <= 2, and every product-peak
+// lane) use the series / rational forms; the caller sends other lanes to
+// the table-driven path.
+template <int RULE, int K, int FAM>
+__device__ __forceinline__ void surplus64_const(const CoordParam& cp, double (&del)[MAXK + 1], double& eps)
+{
+    constexpr int RC = rule_class_of(RULE);
+    using R = tab::Rec<RULE, K>;
+#pragma unroll
+    for (int e = 0; e <= MAXK; ++e) del[e] = 0.0;
+    double et = 0.0;
+    static_for<2, K + 2>([&](auto Lc) {
+        constexpr int L = decltype(Lc)::value;
+        constexpr int off = rc_off64(RC, K, L), rl = rc_rec64(RC, K, L);
+        constexpr int lo = rc_elo(L), hi = rc_ehi(RC, K, L);
+        static_for<0, rc_pairs(RC, L)>([&](auto Jc) {
+            constexpr int J = decltype(Jc)::value;
+            constexpr double y = R::r64[off + J * rl];
+            double sv;
+            if constexpr (FAM == FAM_PEAK) sv = pair64<FAM_PEAK>(cp, y);
+            else sv = pair64_series<FAM>(cp.p0, y);
+            static_for<lo, hi + 1>([&](auto Ec) {
+                constexpr int E = decltype(Ec)::value;
+                constexpr double w = R::r64[off + J * rl + 1 + E - lo];
+                if constexpr (first_level<RC, K>(E) == L && J == 0) del[E] = w * sv;
+                else del[E] = fma(w, sv, del[E]);
+            });
+            constexpr double wa = R::r64[off + J * rl + rl - 1];
+            et = fma(wa, fabs(sv), et);
+        });
+    });
+    eps += et;
+}
+
+// FP32 pair values, two-sum compensated FP32 sums against hi+lo weights.
+template <int RULE, int K, int FAM>
+__device__ __forceinline__ void surplus32_const(const CoordParam& cp, double (&del)[MAXK + 1], double& eps)
+{
+    constexpr int RC = rule_class_of(RULE);
+    using R = tab::Rec<RULE, K>;
+    float hi[MAXK + 1], lo[MAXK + 1];
+#pragma unroll
+    for (int e = 0; e <= MAXK; ++e) { hi[e] = 0.0f; lo[e] = 0.0f; }
+    float epsf = 0.0f;
+    const float c32 = (float)cp.p0;
+    static_for<2, K + 2>([&](auto Lc) {
+        constexpr int L = decltype(Lc)::value;
+        constexpr int off = rc_off64(RC, K, L), rl = rc_rec64(RC, K, L);
+        constexpr int off32 = rc_off32(RC, K, L), rl32 = rc_rec32(RC, K, L);
+        constexpr int elo = rc_elo(L), ehi = rc_ehi(RC, K, L);
+        static_for<0, rc_pairs(RC, L)>([&](auto Jc) {
+            constexpr int J = decltype(Jc)::value;
+            constexpr double y = R::r64[off + J * rl];
+            float sv;
+            if constexpr (FAM == FAM_PEAK) {
+                sv = (float)pair64<FAM_PEAK>(cp, y);
+            } else {
+                constexpr float yh = (float)y;
+                constexpr float yl = (float)(y - (double)yh);
+                sv = pair32_series<FAM, yl != 0.0f>(c32, yh, yl);
+            }
+            static_for<elo, ehi + 1>([&](auto Ec) {
+                constexpr int E = decltype(Ec)::value;
+                constexpr float wh = R::r32[off32 + J * rl32 + 2 * (E - elo)];
+                constexpr float wl = R::r32[off32 + J * rl32 + 2 * (E - elo) + 1];
+                if constexpr (first_level<RC, K>(E) == L && J == 0) {
+                    hi[E] = wh * sv;
+                    lo[E] = wl * sv;
+                } else {
+                    acc2(hi[E], lo[E], wh, wl, sv);
+                }
+            });
+            constexpr float wa = (float)R::r64[off + J * rl + rl - 1];
+            // exp-sum pair values are >= 0 and oscillatory ones <= 0
+            if constexpr (FAM == FAM_EXP) epsf = fmaf(wa, sv, epsf);
+            else if constexpr (FAM == FAM_OSC) epsf = fmaf(-wa, sv, epsf);
+            else epsf = fmaf(wa, fabsf(sv), epsf);
+        });
+    });
+#pragma unroll
+    for (int e = 0; e <= MAXK; ++e) del[e] = (double)hi[e] + (double)lo[e];
+    eps += (double)epsf;
 }
 
 // ----------------------------------------------------------- merge state
@@ -416,14 +566,36 @@ constexpr int total_pairs()
 }
 
 // ----------------------------------------------------------- wave sweep
+// Per-coordinate inputs of a family: the pair-function parameters and the
+// coordinate's term of the affine partial sum (log-amplitude or phase).
+template <int FAM>
+__device__ __forceinline__ double coord_param(const double* __restrict__ prm, int d, int t, CoordParam& cp)
+{
+    if constexpr (FAM == FAM_EXP) {
+        cp.p0 = prm[t];
+        cp.p1 = 0.0;
+        return 0.5 * cp.p0;                       // log g_t(1/2) = c_t / 2
+    } else if constexpr (FAM == FAM_OSC) {
+        cp.p0 = prm[1 + t];
+        cp.p1 = 0.0;
+        return 0.5 * cp.p0;                       // phase of g_t(1/2) = a_t / 2
+    } else {
+        const double b = prm[t], u = prm[d + t];
+        cp.p0 = 1.0 / (b * b);
+        cp.p1 = 0.5 - u;
+        return log(fma(cp.p1, cp.p1, cp.p0));     // log D_t(1/2) = -log g_t(1/2)
+    }
+}
+
 // One wave sweeps the coordinates t = rank*64 + lane + j*64*group of its
 // problem, reduces across its lanes, and either reads out (group of one
 // wave) or leaves its partial state in LDS for the group leader.
-template <int PREC, int K, int RC, int FAM>
+template <int PREC, int K, int RULE, int FAM>
 __device__ __forceinline__ void wave_sweep(const ProbDev& P, int rank, int group, const double* pool64,
                                            const float* pool32, const double* __restrict__ params,
                                            double* out, double* bound, double* lds_slot)
 {
+    constexpr int RC = rule_class_of(RULE);
     const bool want_bound = bound != nullptr;
     const int lane = threadIdx.x & 63;
     const int d = P.d;
@@ -434,33 +606,28 @@ __device__ __forceinline__ void wave_sweep(const ProbDev& P, int rank, int group
     Acc x;
     acc_identity<K>(x);
     for (int t = rank * 64 + lane; t < d; t += 64 * group) {
-        // The table addresses are loop-invariant; hiding them from the
-        // optimiser keeps the table in scalar loads issued per coordinate
-        // instead of hoisting hundreds of values into vector registers.
-        int opaque = 0;
-        asm volatile("" : "+s"(opaque));
-        const double* __restrict__ r64i = r64 + opaque;
-        const float* __restrict__ r32i = r32 + opaque;
         CoordParam cp;
-        double lterm;
-        if constexpr (FAM == FAM_EXP) {
-            cp.p0 = prm[t];
-            cp.p1 = 0.0;
-            lterm = 0.5 * cp.p0;                      // log g_t(1/2) = c_t / 2
-        } else if constexpr (FAM == FAM_OSC) {
-            cp.p0 = prm[1 + t];
-            cp.p1 = 0.0;
-            lterm = 0.5 * cp.p0;                      // phase of g_t(1/2) = a_t / 2
-        } else {
-            const double b = prm[t], u = prm[d + t];
-            cp.p0 = 1.0 / (b * b);
-            cp.p1 = 0.5 - u;
-            lterm = log(fma(cp.p1, cp.p1, cp.p0));    // log D_t(1/2) = -log g_t(1/2)
-        }
+        const double lterm = coord_param<FAM>(prm, d, t, cp);
         double del[MAXK + 1];
         double eps_t = 0.0;
-        if constexpr (PREC == SG_PREC_FP64) surplus64<K, RC, FAM>(r64i, cp, want_bound, del, eps_t);
-        else surplus32<K, RC, FAM>(r64i, r32i, cp, want_bound, del, eps_t);
+        bool done = false;
+        if constexpr (K <= KCONST) {
+            if (FAM == FAM_PEAK || fabs(cp.p0) <= 2.0) {
+                if constexpr (PREC == SG_PREC_FP64) surplus64_const<RULE, K, FAM>(cp, del, eps_t);
+                else surplus32_const<RULE, K, FAM>(cp, del, eps_t);
+                done = true;
+            }
+        }
+        if (!done) {
+            // table-driven path: large parameters (any K) and K > KCONST.
+            // The table addresses are loop-invariant; hiding them from the
+            // optimiser keeps the table in scalar loads issued per coordinate
+            // instead of hoisting hundreds of values into vector registers.
+            int opaque = 0;
+            asm volatile("" : "+s"(opaque));
+            if constexpr (PREC == SG_PREC_FP64) surplus64<K, RC, FAM>(r64 + opaque, cp, true, del, eps_t);
+            else surplus32<K, RC, FAM>(r64 + opaque, r32 + opaque, cp, true, del, eps_t);
+        }
         pmul<K>(x.a, del);
         if (want_bound) {
             double mt = 0.0;
@@ -487,20 +654,27 @@ __device__ __forceinline__ void wave_dispatch_k(const ProbDev& P, int rank, int 
                                                 const float* pool32, const double* params, double* out,
                                                 double* bound, double* lds_slot)
 {
-#define SG_WAVE(RC, FAM) wave_sweep<PREC, K, RC, FAM>(P, rank, group, pool64, pool32, params, out, bound, lds_slot)
-    if (P.rclass == RC_NESTED) {
-        if (P.family == FAM_EXP) SG_WAVE(RC_NESTED, FAM_EXP);
-        else if (P.family == FAM_OSC) SG_WAVE(RC_NESTED, FAM_OSC);
-        else SG_WAVE(RC_NESTED, FAM_PEAK);
-    } else if (P.rclass == RC_GL2) {
-        if (P.family == FAM_EXP) SG_WAVE(RC_GL2, FAM_EXP);
-        else if (P.family == FAM_OSC) SG_WAVE(RC_GL2, FAM_OSC);
-        else SG_WAVE(RC_GL2, FAM_PEAK);
+#define SG_WAVE(RULE, FAM) wave_sweep<PREC, K, RULE, FAM>(P, rank, group, pool64, pool32, params, out, bound, lds_slot)
+#define SG_FAMS(RULE)                                   \
+    do {                                                \
+        if (P.family == FAM_EXP) SG_WAVE(RULE, FAM_EXP); \
+        else if (P.family == FAM_OSC) SG_WAVE(RULE, FAM_OSC); \
+        else SG_WAVE(RULE, FAM_PEAK);                   \
+    } while (0)
+    if constexpr (K <= KCONST) {
+        // compiled tables differ per rule
+        if (P.rule == SG_RULE_CLENSHAW_CURTIS) SG_FAMS(SG_RULE_CLENSHAW_CURTIS);
+        else if (P.rule == SG_RULE_TRAPEZOID) SG_FAMS(SG_RULE_TRAPEZOID);
+        else if (P.rule == SG_RULE_GAUSS_LEGENDRE) SG_FAMS(SG_RULE_GAUSS_LEGENDRE);
+        else SG_FAMS(SG_RULE_GAUSS_LEGENDRE_PAPER);
     } else {
-        if (P.family == FAM_EXP) SG_WAVE(RC_GLP, FAM_EXP);
-        else if (P.family == FAM_OSC) SG_WAVE(RC_GLP, FAM_OSC);
-        else SG_WAVE(RC_GLP, FAM_PEAK);
+        // table-driven only: one instantiation per structure class
+        const int rc = rule_class_of(P.rule);
+        if (rc == RC_NESTED) SG_FAMS(SG_RULE_CLENSHAW_CURTIS);
+        else if (rc == RC_GL2) SG_FAMS(SG_RULE_GAUSS_LEGENDRE);
+        else SG_FAMS(SG_RULE_GAUSS_LEGENDRE_PAPER);
     }
+#undef SG_FAMS
 #undef SG_WAVE
 }
 
@@ -519,9 +693,10 @@ __device__ __forceinline__ void group_finish_k(const ProbDev& P, int group, cons
         merge<K>(x, y, want_bound);
     }
     const double* prm = params + P.param_offset;
-    const int np = P.rclass == RC_NESTED ? total_pairs<RC_NESTED, K>()
-                   : P.rclass == RC_GL2  ? total_pairs<RC_GL2, K>()
-                                         : total_pairs<RC_GLP, K>();
+    const int rc = rule_class_of(P.rule);
+    const int np = rc == RC_NESTED ? total_pairs<RC_NESTED, K>()
+                   : rc == RC_GL2  ? total_pairs<RC_GL2, K>()
+                                   : total_pairs<RC_GLP, K>();
     if (P.family == FAM_EXP) readout<PREC, K, FAM_EXP>(x, P, prm, np, out, bound);
     else if (P.family == FAM_OSC) readout<PREC, K, FAM_OSC>(x, P, prm, np, out, bound);
     else readout<PREC, K, FAM_PEAK>(x, P, prm, np, out, bound);
@@ -853,11 +1028,12 @@ __device__ __forceinline__ void adjoint_dispatch_k(const ProbDev& P, int rank, i
                                                    const double* gout, double* grad, double* ws, double* lds)
 {
 #define SG_ADJ(RC, FAM) wave_adjoint<PREC, K, RC, FAM>(P, rank, group, grouped, pool64, pool32, params, gout, grad, ws, lds)
-    if (P.rclass == RC_NESTED) {
+    const int rc = rule_class_of(P.rule);
+    if (rc == RC_NESTED) {
         if (P.family == FAM_EXP) SG_ADJ(RC_NESTED, FAM_EXP);
         else if (P.family == FAM_OSC) SG_ADJ(RC_NESTED, FAM_OSC);
         else SG_ADJ(RC_NESTED, FAM_PEAK);
-    } else if (P.rclass == RC_GL2) {
+    } else if (rc == RC_GL2) {
         if (P.family == FAM_EXP) SG_ADJ(RC_GL2, FAM_EXP);
         else if (P.family == FAM_OSC) SG_ADJ(RC_GL2, FAM_OSC);
         else SG_ADJ(RC_GL2, FAM_PEAK);

@@ -93,7 +93,7 @@ constexpr int rc_off32(int rc, int K, int L)
 // ------------------------------------------------------------------- device
 // Per-problem record in device memory (plan order = longest first).
 struct ProbDev {
-    int32_t d, K, family, rclass;
+    int32_t d, K, family, rule;    // rule: sg_rule (the structure class follows from it)
     int64_t param_offset;
     int64_t off64;                 // record table in pool64
     int64_t off32;                 // record table in pool32
