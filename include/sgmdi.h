@@ -197,13 +197,16 @@ sg_status sg_plan_execute_grad(sg_plan *plan, const double *params_dev, const do
  *   merge_flops       floating-point operations of the truncated-polynomial
  *                     products of the sweep (K(K-1)/2 multiply-adds and K
  *                     adds per unit, multiply-add counted as 2);
- *   block_threads, grid_blocks: the launch shape the plan uses;
- *   waves_cap: the schedule of integrands onto waves: > 0 caps every
- *   integrand at that many waves (1, 2, 4); < 0 gives each integrand the
- *   fewest waves in {1, 2, 4} that bring one wave's estimated work under
- *   -waves_cap times the plan's largest per-coordinate cost;
+ *   block_threads, grid_blocks: the forward launch shape the plan uses;
+ *   coords_per_lane, max_group: the forward schedule.  Each wave runs one
+ *   class (K, rule, family) of integrands; an integrand of d coordinates
+ *   gets the fewest lanes (a power of two, 4..64) that keep every lane at
+ *   <= coords_per_lane coordinates, several integrands sharing a wave, or,
+ *   when d > 64 * coords_per_lane, 64 lanes on up to max_group (1, 2, 4)
+ *   waves of one workgroup;
  *   graph: 1 if executions on a non-default stream replay a captured graph,
- *   0 if they launch directly (both knobs are chosen by sg_plan_autotune). */
+ *   0 if they launch directly (the three knobs are chosen by
+ *   sg_plan_autotune). */
 typedef struct {
     uint64_t effective_points;
     uint64_t units;
@@ -212,18 +215,19 @@ typedef struct {
     uint64_t merge_flops;
     int32_t block_threads;
     int32_t grid_blocks;
-    int32_t waves_cap;
+    int32_t coords_per_lane;
+    int32_t max_group;
     int32_t graph;
+    int32_t reserved;
 } sg_plan_info;
 
 sg_status sg_plan_get_info(const sg_plan *plan, sg_plan_info *info);
 
 /* Time candidate schedules for this plan on `stream` with HIP events and
  * keep the fastest (stored in the context; later plans with the same shape
- * class reuse it): the integrand-to-wave schedule (waves caps 1, 2, 4 and
- * cost thresholds 1, 2, 4 times the largest per-coordinate cost; see
- * sg_plan_info.waves_cap) and, on a non-default stream, graph replay versus
- * direct launch.  Runs the forward
+ * class reuse it): the integrand-to-wave schedule (coordinates per lane
+ * 1, 2, 3, 4, 8 times waves per integrand 1, 2, 4; see sg_plan_info) and,
+ * on a non-default stream, graph replay versus direct launch.  Runs the forward
  * launch repeatedly on params_dev/out_dev (their contents are overwritten).
  * Errors: INVALID_ARGUMENT, DEVICE. */
 sg_status sg_plan_autotune(sg_plan *plan, const double *params_dev, double *out_dev, void *stream);

@@ -19,10 +19,17 @@ using namespace sg;
 namespace {
 
 struct PlainEntry {
-    ProbDev* probs = nullptr;
-    WGDesc* wgs = nullptr;
+    FwdWG* fwd = nullptr;
+    int nfwg = 0;
     double* pool64 = nullptr;
     float* pool32 = nullptr;
+};
+
+// Forward schedule: target coordinates per lane and the most waves one
+// problem may span.
+struct FwdSched {
+    int cpl = 2;
+    int gmax = 4;
 };
 
 struct Records {
@@ -46,7 +53,7 @@ struct sg_context {
     std::string last_error;
     std::map<std::pair<int, int>, std::unique_ptr<DeltaTable>> tables;
     std::map<std::pair<int, int>, std::unique_ptr<Records>> records;
-    std::map<std::string, std::pair<int, bool>> tuned;   // plan shape -> (schedule, graph)
+    std::map<std::string, std::pair<FwdSched, bool>> tuned;   // plan shape -> (schedule, graph)
     std::map<std::tuple<int, int, int, int>, PlainEntry> plain;
     std::map<std::pair<int, int>, uint64_t*> unrank_tables;
     int live_plans = 0;
@@ -64,7 +71,11 @@ struct sg_plan {
     std::vector<ProbDev> probs;     // plan order (longest first)
     std::vector<double> unit_cost;  // per-coordinate cost estimate, plan order
     double cmax = 1.0;              // largest unit cost of the plan
-    int wmax = 4;                   // schedule: > 0 waves cap, < 0 cost threshold (see waves_for)
+    int wmax = -1;                  // reverse sweep: > 0 waves cap, < 0 cost threshold (see waves_for)
+    FwdSched sched;                 // forward schedule (see pack_forward)
+    FwdWG* d_fwd = nullptr;         // forward workgroup descriptors
+    int nfwg = 0;
+    size_t fwd_capacity = 0;
     bool use_graph = false;         // replay a captured graph (else direct launch)
     bool params_disjoint = true;    // problems' parameter ranges do not overlap
     int kmax = 0;                   // largest K of the plan (kernel instantiation class)
@@ -201,6 +212,125 @@ std::vector<WGDesc> pack_workgroups(const std::vector<ProbDev>& probs, const std
     return wgs;
 }
 
+// Lanes (2^lw) and waves (group) one problem of d coordinates gets: the
+// fewest lanes that keep a lane at <= cpl coordinates, or, beyond 64*cpl
+// coordinates, 64 lanes on up to gmax waves of one workgroup.
+void fwd_shape(int d, int cpl, int gmax, int& lw, int& group)
+{
+    group = 1;
+    if (d > 64 * cpl) {
+        lw = 6;
+        const int need = (d + 64 * cpl - 1) / (64 * cpl);
+        group = std::min(need <= 2 ? need : 4, gmax);
+        return;
+    }
+    const int lanes = (d + cpl - 1) / cpl;
+    lw = 2;
+    while ((1 << lw) < lanes) ++lw;
+}
+
+// Forward workgroups for a schedule.  Problems are bucketed by class
+// (K, rule, family) and shape; a bucket's single-wave problems (plan order,
+// so longest first) fill waves side by side, multi-wave problems get their
+// own waves.  Wave sets are then placed longest-first (estimated cost:
+// per-lane coordinates times the class's per-coordinate cost) into 4-wave
+// workgroups, first fit; the hardware dispatches workgroups in that order.
+FwdSeg seg_of(const ProbDev& p)
+{
+    FwdSeg g;
+    g.d = p.d;
+    g.out_index = p.out_index;
+    g.param_offset = p.param_offset;
+    return g;
+}
+
+std::vector<FwdWG> pack_forward(const std::vector<ProbDev>& probs, const std::vector<double>& unit_cost,
+                                const FwdSched& sc)
+{
+    std::map<std::tuple<int, int, int, int, int>, std::vector<int>> buckets;
+    for (size_t k = 0; k < probs.size(); ++k) {
+        int lw, group;
+        fwd_shape(probs[k].d, sc.cpl, sc.gmax, lw, group);
+        buckets[std::make_tuple(probs[k].K, probs[k].rule, probs[k].family, lw, group)].push_back((int)k);
+    }
+    struct WaveSet {
+        double cost;
+        std::vector<FwdWave> waves;
+    };
+    std::vector<WaveSet> sets;
+    auto base = [&](const ProbDev& pd, int lw, int group) {
+        FwdWave w;
+        std::memset(&w, 0, sizeof w);
+        w.K = (int16_t)pd.K;
+        w.rule = (int16_t)pd.rule;
+        w.family = (int16_t)pd.family;
+        w.lw = (int16_t)lw;
+        w.group = (int16_t)group;
+        w.off64 = (int32_t)pd.off64;
+        w.off32 = (int32_t)pd.off32;
+        for (int i = 0; i < kWaveProbs; ++i) w.seg[i].out_index = -1;
+        return w;
+    };
+    for (auto& kv : buckets) {
+        const int lw = std::get<3>(kv.first), group = std::get<4>(kv.first);
+        const std::vector<int>& list = kv.second;
+        if (group == 1) {
+            const size_t per = (size_t)std::min(kWaveProbs, 64 >> lw);
+            for (size_t i = 0; i < list.size(); i += per) {
+                FwdWave w = base(probs[list[i]], lw, 1);
+                int maxd = 0;
+                for (size_t j = i; j < std::min(list.size(), i + per); ++j) {
+                    w.seg[j - i] = seg_of(probs[list[j]]);
+                    maxd = std::max(maxd, probs[list[j]].d);
+                }
+                w.nprob = (int16_t)(std::min(list.size(), i + per) - i);
+                const int span = 1 << lw;
+                const double c = unit_cost[list[i]] * (double)((maxd + span - 1) / span + 1);
+                sets.push_back(WaveSet{c, std::vector<FwdWave>(1, w)});
+            }
+        } else {
+            for (int k : list) {
+                WaveSet ws;
+                ws.cost = unit_cost[k] * (double)((probs[k].d + 64 * group - 1) / (64 * group) + 1);
+                for (int r = 0; r < group; ++r) {
+                    FwdWave w = base(probs[k], lw, group);
+                    w.rank = (int16_t)r;
+                    w.nprob = 1;
+                    w.seg[0] = seg_of(probs[k]);
+                    ws.waves.push_back(w);
+                }
+                sets.push_back(ws);
+            }
+        }
+    }
+    std::stable_sort(sets.begin(), sets.end(), [](const WaveSet& a, const WaveSet& b) { return a.cost > b.cost; });
+    std::vector<FwdWG> wgs;
+    std::vector<int> used, open;
+    for (const WaveSet& ws : sets) {
+        const int w = (int)ws.waves.size();
+        int target = -1;
+        for (int o : open)
+            if (4 - used[o] >= w) { target = o; break; }
+        if (target < 0) {
+            FwdWG e;
+            std::memset(&e, 0, sizeof e);
+            for (int i = 0; i < 4; ++i) {
+                e.w[i].group = 1;
+                e.w[i].lw = 6;
+                for (int j = 0; j < kWaveProbs; ++j) e.w[i].seg[j].out_index = -1;
+            }
+            wgs.push_back(e);
+            used.push_back(0);
+            target = (int)wgs.size() - 1;
+            open.push_back(target);
+        }
+        for (int r = 0; r < w; ++r) wgs[target].w[used[target] + r] = ws.waves[r];
+        used[target] += w;
+        if (used[target] == 4) open.erase(std::find(open.begin(), open.end(), target));
+    }
+    return wgs;
+}
+
 uint64_t macs_of(const DeltaTable& t)
 {
     uint64_t m = 0;
@@ -292,8 +422,7 @@ sg_status sg_context_destroy(sg_context* ctx)
 {
     if (!ctx) return SG_OK;
     for (auto& kv : ctx->plain) {
-        hipFree(kv.second.probs);
-        hipFree(kv.second.wgs);
+        hipFree(kv.second.fwd);
         hipFree(kv.second.pool64);
         hipFree(kv.second.pool32);
     }
@@ -501,20 +630,30 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
     snprintf(key, sizeof key, "p%d_n%d_maxd%d", precision, n, maxd);
     p->tune_key = key;
     auto tk = ctx->tuned.find(p->tune_key);
-    p->wmax = tk != ctx->tuned.end() ? tk->second.first : -1;
-    p->use_graph = tk != ctx->tuned.end() ? tk->second.second : false;
-    if (const char* fw = std::getenv("SGMDI_WMAX")) {   // debug / profiling override
-        const int w = std::atoi(fw);
-        if (w == 1 || w == 2 || w == 4 || w == -1 || w == -2 || w == -4) p->wmax = w;
+    if (tk != ctx->tuned.end()) {
+        p->sched = tk->second.first;
+        p->use_graph = tk->second.second;
     }
+    if (const char* fs = std::getenv("SGMDI_SCHED")) {   // profiling override: "cpl,gmax"
+        int c = 0, g = 0;
+        if (std::sscanf(fs, "%d,%d", &c, &g) == 2 && c >= 1 && c <= 64 && (g == 1 || g == 2 || g == 4)) {
+            p->sched.cpl = c;
+            p->sched.gmax = g;
+        }
+    }
+    // reverse sweep: one problem per wave slot, cost-threshold schedule
     std::vector<int> wv(n);
     for (int k = 0; k < n; ++k) wv[k] = waves_for(p->probs[k].d, p->unit_cost[k], p->wmax, p->cmax);
     std::vector<WGDesc> wgs = pack_workgroups(p->probs, wv);
     for (int k = 0; k < n; ++k) p->probs[k].waves = wv[k];
     p->nwg = (int)wgs.size();
+    // forward sweep: class-uniform waves, problems side by side
+    std::vector<FwdWG> fwd = pack_forward(p->probs, p->unit_cost, p->sched);
+    p->nfwg = (int)fwd.size();
     info.block_threads = 256;
-    info.grid_blocks = p->nwg;
-    info.waves_cap = p->wmax;
+    info.grid_blocks = p->nfwg;
+    info.coords_per_lane = p->sched.cpl;
+    info.max_group = p->sched.gmax;
     info.graph = p->use_graph ? 1 : 0;
     p->info = info;
 
@@ -522,6 +661,8 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
     if ((st = upload(ctx, &p->d_probs, p->probs.data(), p->probs.size())) != SG_OK) return st;
     if ((st = upload(ctx, &p->d_wgs, wgs.data(), wgs.size())) != SG_OK) return st;
     p->wg_capacity = wgs.size();
+    if ((st = upload(ctx, &p->d_fwd, fwd.data(), fwd.size())) != SG_OK) return st;
+    p->fwd_capacity = fwd.size();
     if ((st = upload(ctx, &p->d_pool64, p64.data(), p64.size())) != SG_OK) return st;
     if ((st = upload(ctx, &p->d_pool32, p32.data(), p32.size())) != SG_OK) return st;
     ctx->live_plans++;
@@ -531,34 +672,31 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
 
 static sg_status plan_launch(sg_plan* p, const double* params, double* out, double* bound, void* stream)
 {
-    const int rc = launch_forward(p->precision, p->kmax, p->nwg, p->d_wgs, p->d_probs, p->d_pool64, p->d_pool32,
-                                  params, out, bound, stream);
+    const int rc = launch_forward(p->precision, p->kmax, p->nfwg, p->d_fwd, p->d_pool64, p->d_pool32, params,
+                                  out, bound, stream);
     if (rc != 0) return hip_fail(p->ctx, (hipError_t)rc, "forward launch");
     return SG_OK;
 }
 
-// Re-pack the plan's workgroups for another schedule.
-static sg_status plan_repack(sg_plan* p, int sched)
+// Re-pack the plan's forward workgroups for another schedule.
+static sg_status plan_repack(sg_plan* p, const FwdSched& sc)
 {
-    std::vector<int> wv(p->probs.size());
-    for (size_t k = 0; k < p->probs.size(); ++k)
-        wv[k] = waves_for(p->probs[k].d, p->unit_cost[k], sched, p->cmax);
-    std::vector<WGDesc> wgs = pack_workgroups(p->probs, wv);
-    if (wgs.size() > p->wg_capacity) {
-        hipFree(p->d_wgs);
-        p->d_wgs = nullptr;
-        sg_status st = upload(p->ctx, &p->d_wgs, wgs.data(), wgs.size());
+    std::vector<FwdWG> fwd = pack_forward(p->probs, p->unit_cost, sc);
+    if (fwd.size() > p->fwd_capacity) {
+        hipFree(p->d_fwd);
+        p->d_fwd = nullptr;
+        sg_status st = upload(p->ctx, &p->d_fwd, fwd.data(), fwd.size());
         if (st != SG_OK) return st;
-        p->wg_capacity = wgs.size();
+        p->fwd_capacity = fwd.size();
     } else {
-        hipError_t e = hipMemcpy(p->d_wgs, wgs.data(), wgs.size() * sizeof(WGDesc), hipMemcpyHostToDevice);
+        hipError_t e = hipMemcpy(p->d_fwd, fwd.data(), fwd.size() * sizeof(FwdWG), hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(p->ctx, e, "hipMemcpy");
     }
-    p->wmax = sched;
-    p->nwg = (int)wgs.size();
-    p->info.grid_blocks = p->nwg;
-    p->info.waves_cap = sched;
-    for (size_t k = 0; k < p->probs.size(); ++k) p->probs[k].waves = wv[k];
+    p->sched = sc;
+    p->nfwg = (int)fwd.size();
+    p->info.grid_blocks = p->nfwg;
+    p->info.coords_per_lane = sc.cpl;
+    p->info.max_group = sc.gmax;
     return SG_OK;
 }
 
@@ -578,8 +716,8 @@ sg_status sg_plan_execute(sg_plan* p, const double* params_dev, double* out_dev,
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return fail(p->ctx, SG_ERR_CAPTURE, std::string("begin capture: ") + hipGetErrorString(e));
-    const int rc = launch_forward(p->precision, p->kmax, p->nwg, p->d_wgs, p->d_probs, p->d_pool64, p->d_pool32,
-                                  params_dev, out_dev, bound_dev, stream);
+    const int rc = launch_forward(p->precision, p->kmax, p->nfwg, p->d_fwd, p->d_pool64, p->d_pool32, params_dev,
+                                  out_dev, bound_dev, stream);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(s, &graph);
     if (rc != 0 || e != hipSuccess || !graph) {
@@ -639,41 +777,48 @@ sg_status sg_plan_autotune(sg_plan* p, const double* params_dev, double* out_dev
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(p->ctx, SG_ERR_DEVICE, "hipEventCreate");
-    const int saved_w = p->wmax;
+    const FwdSched saved = p->sched;
     const bool saved_g = p->use_graph;
-    int best_w = saved_w;
+    FwdSched best = saved;
     bool best_g = saved_g;
     float best_ms = 1e30f;
     const int reps = 20;
-    const int cands[6] = {1, 2, 4, -1, -2, -4};
+    const int cpls[5] = {1, 2, 3, 4, 8};
+    const int gmaxs[3] = {1, 2, 4};
     sg_status st = SG_OK;
-    // candidates: waves-per-problem cap x (graph replay | direct launch);
-    // the graph variant is only timed on a non-default stream
-    for (int c : cands) {
-        if ((st = plan_repack(p, c)) != SG_OK) break;
-        destroy_graphs(p);
-        for (int g = 0; g < (stream ? 2 : 1); ++g) {
-            p->use_graph = g == 1;
-            if ((st = sg_plan_execute(p, params_dev, out_dev, nullptr, stream)) != SG_OK) break;   // warm / capture
-            hipEventRecord(e0, s);
-            for (int r = 0; r < reps; ++r) sg_plan_execute(p, params_dev, out_dev, nullptr, stream);
-            hipEventRecord(e1, s);
-            hipError_t e = hipEventSynchronize(e1);
-            if (e != hipSuccess) { st = hip_fail(p->ctx, e, "autotune sync"); break; }
-            float ms = 0.f;
-            hipEventElapsedTime(&ms, e0, e1);
-            if (ms < best_ms) { best_ms = ms; best_w = c; best_g = p->use_graph; }
+    // candidates: coordinates per lane x waves per problem x (graph replay |
+    // direct launch); the graph variant is only timed on a non-default stream
+    for (int c : cpls) {
+        for (int gm : gmaxs) {
+            FwdSched sc;
+            sc.cpl = c;
+            sc.gmax = gm;
+            if ((st = plan_repack(p, sc)) != SG_OK) break;
+            destroy_graphs(p);
+            for (int g = 0; g < (stream ? 2 : 1); ++g) {
+                p->use_graph = g == 1;
+                if ((st = sg_plan_execute(p, params_dev, out_dev, nullptr, stream)) != SG_OK) break;   // warm / capture
+                hipEventRecord(e0, s);
+                for (int r = 0; r < reps; ++r) sg_plan_execute(p, params_dev, out_dev, nullptr, stream);
+                hipEventRecord(e1, s);
+                hipError_t e = hipEventSynchronize(e1);
+                if (e != hipSuccess) { st = hip_fail(p->ctx, e, "autotune sync"); break; }
+                float ms = 0.f;
+                hipEventElapsedTime(&ms, e0, e1);
+                if (ms < best_ms) { best_ms = ms; best = sc; best_g = p->use_graph; }
+            }
+            if (st != SG_OK) break;
         }
         if (st != SG_OK) break;
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     destroy_graphs(p);
-    sg_status st2 = plan_repack(p, st == SG_OK ? best_w : saved_w);
+    sg_status st2 = plan_repack(p, st == SG_OK ? best : saved);
     p->use_graph = st == SG_OK ? best_g : saved_g;
     if (st != SG_OK) return st;
     if (st2 != SG_OK) return st2;
-    p->ctx->tuned[p->tune_key] = std::make_pair(best_w, best_g);
+    p->ctx->tuned[p->tune_key] = std::make_pair(best, best_g);
     p->info.graph = p->use_graph ? 1 : 0;
     return SG_OK;
 }
@@ -684,6 +829,7 @@ sg_status sg_plan_destroy(sg_plan* p)
     destroy_graphs(p);
     hipFree(p->d_probs);
     hipFree(p->d_wgs);
+    hipFree(p->d_fwd);
     hipFree(p->d_ws);
     hipFree(p->d_pool64);
     hipFree(p->d_pool32);
@@ -718,18 +864,20 @@ sg_status sg_integrate(sg_context* ctx, const sg_problem* problem, int32_t preci
         pd.off32 = 0;
         pd.out_index = 0;
         pd.ws_off = 0;
-        std::vector<int> wv(1, waves_for(pd.d, 1.0, 4, 1.0));
-        pd.waves = wv[0];
-        std::vector<WGDesc> wgs = pack_workgroups(pv, wv);
+        // one problem: 64 lanes on up to 4 waves, a few coordinates per lane
+        FwdSched sc;
+        sc.cpl = 4;
+        sc.gmax = 4;
+        std::vector<FwdWG> fwd = pack_forward(pv, std::vector<double>(1, 1.0), sc);
         PlainEntry pe;
-        if ((st = upload(ctx, &pe.probs, pv.data(), 1)) != SG_OK) return st;
-        if ((st = upload(ctx, &pe.wgs, wgs.data(), wgs.size())) != SG_OK) return st;
+        pe.nfwg = (int)fwd.size();
+        if ((st = upload(ctx, &pe.fwd, fwd.data(), fwd.size())) != SG_OK) return st;
         if ((st = upload(ctx, &pe.pool64, r->r64.data(), r->r64.size())) != SG_OK) return st;
         if ((st = upload(ctx, &pe.pool32, r->r32.data(), r->r32.size())) != SG_OK) return st;
         it = ctx->plain.emplace(key, pe).first;
     }
-    const int rc = launch_forward(precision, K, 1, it->second.wgs, it->second.probs, it->second.pool64,
-                                  it->second.pool32, params_dev, out_dev, bound_dev, stream);
+    const int rc = launch_forward(precision, K, it->second.nfwg, it->second.fwd, it->second.pool64, it->second.pool32,
+                                  params_dev, out_dev, bound_dev, stream);
     if (rc != 0) return hip_fail(ctx, (hipError_t)rc, "forward launch");
     return SG_OK;
 }

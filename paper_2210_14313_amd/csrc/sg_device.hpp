@@ -460,26 +460,25 @@ __device__ __forceinline__ void dpp_step(Acc& x, bool want_bound)
     merge<K>(x, o, want_bound);
 }
 
-// Reduce the wave's lane states towards one lane with DPP row shifts and row
-// broadcasts (no LDS traffic).  Only lanes 0..nact-1 hold coordinates; the
-// fixed step pattern makes the result deterministic.  Returns the lane that
-// holds the whole wave's state (15, 31 or 63).
+// Segmented reduction of the lane states with DPP row shifts and row
+// broadcasts (no LDS traffic): lanes form segments of 2^lw consecutive lanes
+// (2^lw <= 64) and, after lw steps, the last lane of every segment holds
+// the product of its segment.  This is an inclusive Hillis-Steele scan
+// whose steps never reach past 2^lw - 1 lanes below, so a segment's last
+// lane sees only its own segment; lanes without a source multiply by the
+// identity.  The fixed step pattern makes the result deterministic.
 template <int K>
-__device__ __forceinline__ int wave_reduce_dpp(Acc& x, int nact, bool want_bound)
+__device__ __forceinline__ void wave_reduce_seg(Acc& x, int lw, bool want_bound)
 {
     constexpr int ROW_SHR1 = 0x111, ROW_SHR2 = 0x112, ROW_SHR4 = 0x114, ROW_SHR8 = 0x118;
     constexpr int ROW_BCAST15 = 0x142, ROW_BCAST31 = 0x143;
-    if (nact > 1) dpp_step<K, ROW_SHR1, 0xF>(x, want_bound);
-    if (nact > 2) dpp_step<K, ROW_SHR2, 0xF>(x, want_bound);
-    if (nact > 4) dpp_step<K, ROW_SHR4, 0xF>(x, want_bound);
-    if (nact > 8) dpp_step<K, ROW_SHR8, 0xF>(x, want_bound);
-    // after the shifts up to 2^j, lane 2^(j+1)-1 holds lanes 0 .. 2^(j+1)-1
-    if (nact <= 16) return nact <= 1 ? 0 : nact <= 2 ? 1 : nact <= 4 ? 3 : nact <= 8 ? 7 : 15;
+    if (lw >= 1) dpp_step<K, ROW_SHR1, 0xF>(x, want_bound);
+    if (lw >= 2) dpp_step<K, ROW_SHR2, 0xF>(x, want_bound);
+    if (lw >= 3) dpp_step<K, ROW_SHR4, 0xF>(x, want_bound);
+    if (lw >= 4) dpp_step<K, ROW_SHR8, 0xF>(x, want_bound);
     // lane 15 of each row now holds its row; row 1 takes row 0's total, row 3 row 2's
-    dpp_step<K, ROW_BCAST15, 0xA>(x, want_bound);
-    if (nact <= 32) return 31;
-    dpp_step<K, ROW_BCAST31, 0xC>(x, want_bound);
-    return 63;
+    if (lw >= 5) dpp_step<K, ROW_BCAST15, 0xA>(x, want_bound);
+    if (lw >= 6) dpp_step<K, ROW_BCAST31, 0xC>(x, want_bound);
 }
 
 constexpr int ACC_WORDS = MAXK + 4;   // doubles per wave in LDS
@@ -520,8 +519,8 @@ __device__ __forceinline__ double abs_product_bound(double m)
 // Q = A * (1 + sum_k a_k) with the affine partial sum giving A, and the
 // a-priori bound on |Q - exact Smolyak value| from rounding.
 template <int PREC, int K, int FAM>
-__device__ void readout(const Acc& x, const ProbDev& P, const double* __restrict__ prm, int rl_pairs,
-                        double* out, double* bound)
+__device__ void readout(const Acc& x, int d, int out_index, const double* __restrict__ prm, int rl_pairs,
+                        int depth, double* out, double* bound)
 {
     const bool want_bound = bound != nullptr;
     double s = 0.0;
@@ -530,30 +529,31 @@ __device__ void readout(const Acc& x, const ProbDev& P, const double* __restrict
     s += 1.0;
     const double sabs = want_bound ? abs_product_bound(x.m) : 0.0;
     const double u64 = 1.1102230246251565e-16;
-    const double ls_err = u64 * (double)P.d * x.lsabs;   // rounding of the affine sum
+    const double ls_err = u64 * (double)d * x.lsabs;   // rounding of the affine sum
     // relative error of one surplus term: pair value (8 roundings) plus the
     // within-rule sum (FP64: a plain FMA chain over at most rl_pairs terms;
     // FP32: one rounding of the product, compensated accumulation)
     const double rel = PREC == SG_PREC_FP64 ? u64 * (8.0 + (double)rl_pairs) : 5.9604644775390625e-08 * 10.0;
-    // products of the sweep: (K+2) roundings per merge level
-    const double levels = (double)((P.d + 63) / 64 + 10);
+    // products of the sweep: (K+2) roundings per level of the product tree
+    // (depth: the caller's bound on the tree depth)
+    const double levels = (double)depth;
     double Q;
     if constexpr (FAM == FAM_OSC) {
         const double phase = 2.0 * 3.141592653589793 * prm[0] + x.ls;
         Q = cos(phase) * s;
         if (want_bound) {
             const double dsum = sabs * (rel * x.eps + (K + 2) * levels * u64);
-            bound[P.out_index] = dsum + fabs(s) * (ls_err + u64 * (fabs(phase) + 4.0)) + fabs(Q) * 4.0 * u64;
+            bound[out_index] = dsum + fabs(s) * (ls_err + u64 * (fabs(phase) + 4.0)) + fabs(Q) * 4.0 * u64;
         }
     } else {
         const double A = exp(FAM == FAM_EXP ? x.ls : -x.ls);
         Q = A * s;
         if (want_bound) {
             const double dsum = sabs * (rel * x.eps + (K + 2) * levels * u64);
-            bound[P.out_index] = A * dsum + fabs(Q) * (ls_err + 4.0 * u64 + u64 * fabs(x.ls));
+            bound[out_index] = A * dsum + fabs(Q) * (ls_err + 4.0 * u64 + u64 * fabs(x.ls));
         }
     }
-    out[P.out_index] = Q;
+    out[out_index] = Q;
 }
 
 // Number of node pairs of a (class, K) table (for the bound's sum length).
@@ -566,48 +566,96 @@ constexpr int total_pairs()
 }
 
 // ----------------------------------------------------------- wave sweep
-// Per-coordinate inputs of a family: the pair-function parameters and the
+// Per-coordinate inputs of a family: the raw parameters (loaded one
+// coordinate ahead of their use), then the pair-function parameters and the
 // coordinate's term of the affine partial sum (log-amplitude or phase).
+struct RawParam {
+    double a, b;
+};
+
 template <int FAM>
-__device__ __forceinline__ double coord_param(const double* __restrict__ prm, int d, int t, CoordParam& cp)
+__device__ __forceinline__ RawParam load_param(const double* __restrict__ prm, int d, int t)
 {
+    RawParam r;
     if constexpr (FAM == FAM_EXP) {
-        cp.p0 = prm[t];
-        cp.p1 = 0.0;
-        return 0.5 * cp.p0;                       // log g_t(1/2) = c_t / 2
+        r.a = prm[t];
+        r.b = 0.0;
     } else if constexpr (FAM == FAM_OSC) {
-        cp.p0 = prm[1 + t];
-        cp.p1 = 0.0;
-        return 0.5 * cp.p0;                       // phase of g_t(1/2) = a_t / 2
+        r.a = prm[1 + t];
+        r.b = 0.0;
     } else {
-        const double b = prm[t], u = prm[d + t];
-        cp.p0 = 1.0 / (b * b);
-        cp.p1 = 0.5 - u;
+        r.a = prm[t];
+        r.b = prm[d + t];
+    }
+    return r;
+}
+
+template <int FAM>
+__device__ __forceinline__ double coord_param(const RawParam& r, CoordParam& cp)
+{
+    if constexpr (FAM == FAM_EXP || FAM == FAM_OSC) {
+        cp.p0 = r.a;
+        cp.p1 = 0.0;
+        return 0.5 * cp.p0;                       // exp: log g_t(1/2) = c_t/2; osc: phase a_t/2
+    } else {
+        cp.p0 = 1.0 / (r.a * r.a);                // beta = b^-2
+        cp.p1 = 0.5 - r.b;
         return log(fma(cp.p1, cp.p1, cp.p0));     // log D_t(1/2) = -log g_t(1/2)
     }
 }
 
-// One wave sweeps the coordinates t = rank*64 + lane + j*64*group of its
-// problem, reduces across its lanes, and either reads out (group of one
-// wave) or leaves its partial state in LDS for the group leader.
+// Wave-uniform description of one forward wave (from its descriptor).
+struct WaveInfo {
+    int lw, rank, group, nprob;
+    const double* r64;     // the class's record table (table-driven path)
+    const float* r32;
+    const FwdSeg* seg;     // the problems by lane segment
+};
+
+// Depth of the product tree behind one result: a lane's sequential chain of
+// ceil(d / (2^lw * group)) coordinates, lw DPP levels, up to 3 group merges.
+__device__ __forceinline__ int tree_depth(int d, int lw, int group)
+{
+    const int span = (1 << lw) * group;
+    return (d + span - 1) / span + lw + 4;
+}
+
+// One wave sweeps its problems: lane l works on problem seg[l >> lw] and
+// its coordinates t = rank*2^lw + (l & (2^lw - 1)) + j * 2^lw * group, then
+// the segments are reduced and every segment's last lane reads out (group of
+// one wave) or, for a multi-wave problem, leaves the wave's state in LDS for
+// the group leader.  The next coordinate's parameters are loaded before the
+// current coordinate is evaluated, so their latency overlaps the arithmetic.
 template <int PREC, int K, int RULE, int FAM>
-__device__ __forceinline__ void wave_sweep(const ProbDev& P, int rank, int group, const double* pool64,
-                                           const float* pool32, const double* __restrict__ params,
-                                           double* out, double* bound, double* lds_slot)
+__device__ __forceinline__ void wave_sweep(const WaveInfo& wi, const double* __restrict__ params, double* out,
+                                           double* bound, double* lds_slot)
 {
     constexpr int RC = rule_class_of(RULE);
     const bool want_bound = bound != nullptr;
     const int lane = threadIdx.x & 63;
-    const int d = P.d;
-    const double* __restrict__ r64 = pool64 + P.off64;
-    const float* __restrict__ r32 = pool32 + P.off32;
-    const double* __restrict__ prm = params + P.param_offset;
+    const int W = 1 << wi.lw;
+    const int sg = lane >> wi.lw, lis = lane & (W - 1);
+    int d = 0, out_index = -1;
+    const double* __restrict__ prm = params;
+    if (sg < wi.nprob) {
+        const FwdSeg rec = wi.seg[sg];
+        d = rec.d;
+        out_index = rec.out_index;
+        prm = params + rec.param_offset;
+    }
 
     Acc x;
     acc_identity<K>(x);
-    for (int t = rank * 64 + lane; t < d; t += 64 * group) {
+    const int stride = W * wi.group;
+    int t = wi.rank * W + lis;
+    RawParam nxt{0.0, 0.0};
+    if (t < d) nxt = load_param<FAM>(prm, d, t);
+    while (t < d) {
+        const RawParam cur = nxt;
+        const int tn = t + stride;
+        if (tn < d) nxt = load_param<FAM>(prm, d, tn);
         CoordParam cp;
-        const double lterm = coord_param<FAM>(prm, d, t, cp);
+        const double lterm = coord_param<FAM>(cur, cp);
         double del[MAXK + 1];
         double eps_t = 0.0;
         bool done = false;
@@ -625,8 +673,8 @@ __device__ __forceinline__ void wave_sweep(const ProbDev& P, int rank, int group
             // instead of hoisting hundreds of values into vector registers.
             int opaque = 0;
             asm volatile("" : "+s"(opaque));
-            if constexpr (PREC == SG_PREC_FP64) surplus64<K, RC, FAM>(r64 + opaque, cp, true, del, eps_t);
-            else surplus32<K, RC, FAM>(r64 + opaque, r32 + opaque, cp, true, del, eps_t);
+            if constexpr (PREC == SG_PREC_FP64) surplus64<K, RC, FAM>(wi.r64 + opaque, cp, true, del, eps_t);
+            else surplus32<K, RC, FAM>(wi.r64 + opaque, wi.r32 + opaque, cp, true, del, eps_t);
         }
         pmul<K>(x.a, del);
         if (want_bound) {
@@ -638,38 +686,38 @@ __device__ __forceinline__ void wave_sweep(const ProbDev& P, int rank, int group
         }
         x.ls += lterm;
         x.lsabs += fabs(lterm);
+        t = tn;
     }
-    // reduce over the lanes that hold coordinates
-    const int nact = min(64, max(0, d - rank * 64));
-    const int root = wave_reduce_dpp<K>(x, nact, want_bound);
-    if (group == 1) {
-        if (lane == root) readout<PREC, K, FAM>(x, P, prm, total_pairs<RC, K>(), out, bound);
-    } else if (lane == root) {
+    wave_reduce_seg<K>(x, wi.lw, want_bound);
+    if (lis != W - 1) return;
+    if (wi.group == 1) {
+        if (out_index >= 0)
+            readout<PREC, K, FAM>(x, d, out_index, prm, total_pairs<RC, K>(), tree_depth(d, wi.lw, 1), out, bound);
+    } else {
         acc_store<K>(x, lds_slot);
     }
 }
 
 template <int PREC, int K>
-__device__ __forceinline__ void wave_dispatch_k(const ProbDev& P, int rank, int group, const double* pool64,
-                                                const float* pool32, const double* params, double* out,
-                                                double* bound, double* lds_slot)
+__device__ __forceinline__ void wave_dispatch_k(int rule, int family, const WaveInfo& wi, const double* params,
+                                                double* out, double* bound, double* lds_slot)
 {
-#define SG_WAVE(RULE, FAM) wave_sweep<PREC, K, RULE, FAM>(P, rank, group, pool64, pool32, params, out, bound, lds_slot)
-#define SG_FAMS(RULE)                                   \
-    do {                                                \
-        if (P.family == FAM_EXP) SG_WAVE(RULE, FAM_EXP); \
-        else if (P.family == FAM_OSC) SG_WAVE(RULE, FAM_OSC); \
-        else SG_WAVE(RULE, FAM_PEAK);                   \
+#define SG_WAVE(RULE, FAM) wave_sweep<PREC, K, RULE, FAM>(wi, params, out, bound, lds_slot)
+#define SG_FAMS(RULE)                                         \
+    do {                                                      \
+        if (family == FAM_EXP) SG_WAVE(RULE, FAM_EXP);        \
+        else if (family == FAM_OSC) SG_WAVE(RULE, FAM_OSC);   \
+        else SG_WAVE(RULE, FAM_PEAK);                         \
     } while (0)
     if constexpr (K <= KCONST) {
         // compiled tables differ per rule
-        if (P.rule == SG_RULE_CLENSHAW_CURTIS) SG_FAMS(SG_RULE_CLENSHAW_CURTIS);
-        else if (P.rule == SG_RULE_TRAPEZOID) SG_FAMS(SG_RULE_TRAPEZOID);
-        else if (P.rule == SG_RULE_GAUSS_LEGENDRE) SG_FAMS(SG_RULE_GAUSS_LEGENDRE);
+        if (rule == SG_RULE_CLENSHAW_CURTIS) SG_FAMS(SG_RULE_CLENSHAW_CURTIS);
+        else if (rule == SG_RULE_TRAPEZOID) SG_FAMS(SG_RULE_TRAPEZOID);
+        else if (rule == SG_RULE_GAUSS_LEGENDRE) SG_FAMS(SG_RULE_GAUSS_LEGENDRE);
         else SG_FAMS(SG_RULE_GAUSS_LEGENDRE_PAPER);
     } else {
         // table-driven only: one instantiation per structure class
-        const int rc = rule_class_of(P.rule);
+        const int rc = rule_class_of(rule);
         if (rc == RC_NESTED) SG_FAMS(SG_RULE_CLENSHAW_CURTIS);
         else if (rc == RC_GL2) SG_FAMS(SG_RULE_GAUSS_LEGENDRE);
         else SG_FAMS(SG_RULE_GAUSS_LEGENDRE_PAPER);
@@ -680,8 +728,9 @@ __device__ __forceinline__ void wave_dispatch_k(const ProbDev& P, int rank, int 
 
 // Group leader: merge the group's wave states in wave order, read out.
 template <int PREC, int K>
-__device__ __forceinline__ void group_finish_k(const ProbDev& P, int group, const double* lds_first,
-                                               const double* params, double* out, double* bound)
+__device__ __forceinline__ void group_finish_k(int rule, int family, int group, const FwdSeg& lp,
+                                               const double* lds_first, const double* params, double* out,
+                                               double* bound)
 {
     const bool want_bound = bound != nullptr;
     Acc x, y;
@@ -692,14 +741,15 @@ __device__ __forceinline__ void group_finish_k(const ProbDev& P, int group, cons
         acc_load<K>(y, lds_first + g * ACC_WORDS);
         merge<K>(x, y, want_bound);
     }
-    const double* prm = params + P.param_offset;
-    const int rc = rule_class_of(P.rule);
+    const double* prm = params + lp.param_offset;
+    const int rc = rule_class_of(rule);
     const int np = rc == RC_NESTED ? total_pairs<RC_NESTED, K>()
                    : rc == RC_GL2  ? total_pairs<RC_GL2, K>()
                                    : total_pairs<RC_GLP, K>();
-    if (P.family == FAM_EXP) readout<PREC, K, FAM_EXP>(x, P, prm, np, out, bound);
-    else if (P.family == FAM_OSC) readout<PREC, K, FAM_OSC>(x, P, prm, np, out, bound);
-    else readout<PREC, K, FAM_PEAK>(x, P, prm, np, out, bound);
+    const int depth = tree_depth(lp.d, 6, group);
+    if (family == FAM_EXP) readout<PREC, K, FAM_EXP>(x, lp.d, lp.out_index, prm, np, depth, out, bound);
+    else if (family == FAM_OSC) readout<PREC, K, FAM_OSC>(x, lp.d, lp.out_index, prm, np, depth, out, bound);
+    else readout<PREC, K, FAM_PEAK>(x, lp.d, lp.out_index, prm, np, depth, out, bound);
 }
 
 // Dispatch a runtime K in [0, KMAXP] to a compile-time K.
@@ -711,37 +761,42 @@ __device__ __forceinline__ void switch_k(int K, F&& f)
     });
 }
 
-// Each workgroup holds 4 waves; wave w works on wgs[blockIdx.x].slot[w].
-// Problems spanning several waves sit in consecutive slots of one
-// workgroup and are merged through LDS by their first wave.
+// Each workgroup holds 4 waves; wave w runs wgs[blockIdx.x].w[w].  A
+// problem spanning several waves sits in consecutive waves of one
+// workgroup and is merged through LDS by its first wave.
 template <int PREC, int KMAXP>
 __global__ void __launch_bounds__(256)
-k_forward(const WGDesc* __restrict__ wgs, const ProbDev* __restrict__ probs,
-          const double* __restrict__ pool64, const float* __restrict__ pool32,
+k_forward(const FwdWG* __restrict__ wgs, const double* __restrict__ pool64, const float* __restrict__ pool32,
           const double* __restrict__ params, double* __restrict__ out, double* __restrict__ bound)
 {
     __shared__ double lds[4 * ACC_WORDS];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
-    const WGDesc* desc = wgs + blockIdx.x;
-    struct { int32_t prob; int16_t rank, group; } sl;
-    sl.prob = __builtin_amdgcn_readfirstlane(desc->slot[w].prob);
-    sl.rank = (int16_t)__builtin_amdgcn_readfirstlane(desc->slot[w].rank);
-    sl.group = (int16_t)__builtin_amdgcn_readfirstlane(desc->slot[w].group);
-    const bool grouped = desc->slot[0].group > 1 || desc->slot[1].group > 1 || desc->slot[2].group > 1 ||
-                         desc->slot[3].group > 1;
-    ProbDev P;
-    if (sl.prob >= 0) {
-        P = desc->slot[w].p;
-        switch_k<KMAXP>(P.K, [&](auto kc) {
-            wave_dispatch_k<PREC, decltype(kc)::value>(P, sl.rank, sl.group, pool64, pool32, params, out, bound,
-                                                      lds + w * ACC_WORDS);
+    const FwdWG* wg = wgs + blockIdx.x;
+    const FwdWave* wd = &wg->w[w];
+    const int K = __builtin_amdgcn_readfirstlane(wd->K);
+    const int rule = __builtin_amdgcn_readfirstlane(wd->rule);
+    const int family = __builtin_amdgcn_readfirstlane(wd->family);
+    WaveInfo wi;
+    wi.lw = __builtin_amdgcn_readfirstlane(wd->lw);
+    wi.rank = __builtin_amdgcn_readfirstlane(wd->rank);
+    wi.group = __builtin_amdgcn_readfirstlane(wd->group);
+    wi.nprob = __builtin_amdgcn_readfirstlane(wd->nprob);
+    wi.r64 = pool64 + __builtin_amdgcn_readfirstlane(wd->off64);
+    wi.r32 = pool32 + __builtin_amdgcn_readfirstlane(wd->off32);
+    wi.seg = wd->seg;
+    const bool grouped = wg->w[0].group > 1 || wg->w[1].group > 1 || wg->w[2].group > 1 || wg->w[3].group > 1;
+    if (wi.nprob > 0) {
+        switch_k<KMAXP>(K, [&](auto kc) {
+            wave_dispatch_k<PREC, decltype(kc)::value>(rule, family, wi, params, out, bound, lds + w * ACC_WORDS);
         });
     }
     if (!grouped) return;
     __syncthreads();
-    if (sl.prob >= 0 && sl.group > 1 && sl.rank == 0 && (threadIdx.x & 63) == 0) {
-        switch_k<KMAXP>(P.K, [&](auto kc) {
-            group_finish_k<PREC, decltype(kc)::value>(P, sl.group, lds + w * ACC_WORDS, params, out, bound);
+    if (wi.nprob > 0 && wi.group > 1 && wi.rank == 0 && (threadIdx.x & 63) == 0) {
+        const FwdSeg lp = wd->seg[0];
+        switch_k<KMAXP>(K, [&](auto kc) {
+            group_finish_k<PREC, decltype(kc)::value>(rule, family, wi.group, lp, lds + w * ACC_WORDS, params, out,
+                                                      bound);
         });
     }
 }

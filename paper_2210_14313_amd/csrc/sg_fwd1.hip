@@ -5,18 +5,18 @@
 
 namespace sg {
 
-int launch_forward_p1(int kmax, int nwg, const WGDesc* wgs, const ProbDev* probs, const double* pool64,
+int launch_forward_p1(int kmax, int nwg, const FwdWG* wgs, const double* pool64,
                        const float* pool32, const double* params, double* out, double* bound, void* stream)
 {
     if (nwg <= 0) return 0;
     const dim3 grid((unsigned)nwg), block(256);
     hipStream_t s = (hipStream_t)stream;
     if (kmax <= 4)
-        hipLaunchKernelGGL((dev::k_forward<1, 4>), grid, block, 0, s, wgs, probs, pool64, pool32, params, out, bound);
+        hipLaunchKernelGGL((dev::k_forward<1, 4>), grid, block, 0, s, wgs, pool64, pool32, params, out, bound);
     else if (kmax <= 6)
-        hipLaunchKernelGGL((dev::k_forward<1, 6>), grid, block, 0, s, wgs, probs, pool64, pool32, params, out, bound);
+        hipLaunchKernelGGL((dev::k_forward<1, 6>), grid, block, 0, s, wgs, pool64, pool32, params, out, bound);
     else
-        hipLaunchKernelGGL((dev::k_forward<1, 8>), grid, block, 0, s, wgs, probs, pool64, pool32, params, out, bound);
+        hipLaunchKernelGGL((dev::k_forward<1, 8>), grid, block, 0, s, wgs, pool64, pool32, params, out, bound);
     return (int)hipGetLastError();
 }
 

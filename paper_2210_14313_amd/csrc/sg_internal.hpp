@@ -113,13 +113,40 @@ struct WGDesc {
     WaveSlot slot[4];
 };
 
+// ----------------------------------------------------- forward schedule
+// One problem as a forward lane segment sees it.
+struct FwdSeg {
+    int32_t d;
+    int32_t out_index;             // position in the caller's problem order
+    int64_t param_offset;
+};
+
+// One wave of the forward sweep.  All its problems share one class
+// (K, rule, family), so the wave runs one code path.  Either up to
+// kWaveProbs problems sit side by side on 2^lw lanes each (group == 1), or
+// one problem spans `group` waves of 64 lanes (lw == 6) of one workgroup and
+// is merged through LDS.  A lane reads its segment record directly (one
+// load, no index indirection).
+constexpr int kWaveProbs = 16;
+struct FwdWave {
+    int16_t K, rule, family, lw;   // class; lw = log2(lanes per problem), 2..6
+    int16_t rank, group;           // wave rank inside its group; group size (1, 2, 4)
+    int16_t nprob, pad;            // problems in this wave (0: idle wave)
+    int32_t off64, off32;          // the class's record table in the pools
+    int32_t pad2[2];
+    FwdSeg seg[kWaveProbs];        // the problems, by lane segment
+};
+struct FwdWG {
+    FwdWave w[4];
+};
+
 struct LaunchCfg {
     int block = 256;   // threads per workgroup (always 4 waves)
 };
 
 // Kernel launchers (sg_unrank.hip dispatches to sg_fwd*.hip / sg_adj*.hip).
 // kmax: the largest K of the launched problems (selects the instantiation).
-int launch_forward(int precision, int kmax, int nwg, const WGDesc* wgs, const ProbDev* probs,
+int launch_forward(int precision, int kmax, int nwg, const FwdWG* wgs,
                    const double* pool64, const float* pool32, const double* params, double* out,
                    double* bound, void* stream);
 int launch_adjoint(int precision, int nwg, const WGDesc* wgs, const ProbDev* probs, const double* pool64,

@@ -61,21 +61,21 @@ k_unrank(int d, int q, uint64_t rank0, uint64_t count, int max_nnz, const uint64
 
 }  // namespace
 
-int launch_forward_p0(int, int, const WGDesc*, const ProbDev*, const double*, const float*, const double*, double*,
+int launch_forward_p0(int, int, const FwdWG*, const double*, const float*, const double*, double*,
                       double*, void*);
-int launch_forward_p1(int, int, const WGDesc*, const ProbDev*, const double*, const float*, const double*, double*,
+int launch_forward_p1(int, int, const FwdWG*, const double*, const float*, const double*, double*,
                       double*, void*);
 int launch_adjoint_p0(int, const WGDesc*, const ProbDev*, const double*, const float*, const double*, const double*,
                       double*, double*, void*);
 int launch_adjoint_p1(int, const WGDesc*, const ProbDev*, const double*, const float*, const double*, const double*,
                       double*, double*, void*);
 
-int launch_forward(int precision, int kmax, int nwg, const WGDesc* wgs, const ProbDev* probs, const double* pool64,
+int launch_forward(int precision, int kmax, int nwg, const FwdWG* wgs, const double* pool64,
                    const float* pool32, const double* params, double* out, double* bound, void* stream)
 {
     return precision == SG_PREC_FP64
-               ? launch_forward_p0(kmax, nwg, wgs, probs, pool64, pool32, params, out, bound, stream)
-               : launch_forward_p1(kmax, nwg, wgs, probs, pool64, pool32, params, out, bound, stream);
+               ? launch_forward_p0(kmax, nwg, wgs, pool64, pool32, params, out, bound, stream)
+               : launch_forward_p1(kmax, nwg, wgs, pool64, pool32, params, out, bound, stream);
 }
 
 int launch_adjoint(int precision, int nwg, const WGDesc* wgs, const ProbDev* probs, const double* pool64,

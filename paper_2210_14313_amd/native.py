@@ -40,8 +40,8 @@ class SgPlanInfo(ctypes.Structure):
     _fields_ = [("effective_points", ctypes.c_uint64), ("units", ctypes.c_uint64),
                 ("pair_evals", ctypes.c_uint64), ("macs", ctypes.c_uint64),
                 ("merge_flops", ctypes.c_uint64), ("block_threads", ctypes.c_int32),
-                ("grid_blocks", ctypes.c_int32), ("waves_cap", ctypes.c_int32),
-                ("graph", ctypes.c_int32)]
+                ("grid_blocks", ctypes.c_int32), ("coords_per_lane", ctypes.c_int32),
+                ("max_group", ctypes.c_int32), ("graph", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -134,7 +134,7 @@ def _stream_ptr(stream):
     import torch
     if stream is None:
         stream = torch.cuda.current_stream()
-    return ctypes.c_void_p(stream.cuda_stream) if stream.cuda_stream else None
+    return stream.cuda_stream or None
 
 
 def _ptr(t):
@@ -190,6 +190,7 @@ class Plan:
         self.precision = precision
         _check(lib().sg_plan_create(self.ctx.handle, self._arr, self.n, PRECISIONS[precision],
                                     ctypes.byref(self.handle)), self.ctx.handle)
+        self._exec = lib().sg_plan_execute
 
     def info(self) -> dict:
         inf = SgPlanInfo()
@@ -198,14 +199,21 @@ class Plan:
 
     def execute(self, params, out=None, bound=None, stream=None):
         import torch
-        assert params.dtype == torch.float64 and params.is_cuda and params.is_contiguous()
+        f64 = torch.float64
+        if params.dtype != f64 or not params.is_cuda or not params.is_contiguous():
+            raise ValueError("params must be a contiguous float64 device tensor")
         if out is None:
-            out = torch.empty(self.n, dtype=torch.float64, device=params.device)
-        assert out.dtype == torch.float64 and out.numel() >= self.n and out.is_contiguous()
+            out = torch.empty(self.n, dtype=f64, device=params.device)
+        elif out.dtype != f64 or out.numel() < self.n or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous float64 tensor of >= {self.n} elements")
+        bptr = None
         if bound is not None:
-            assert bound.dtype == torch.float64 and bound.numel() >= self.n and bound.is_contiguous()
-        _check(lib().sg_plan_execute(self.handle, _ptr(params), _ptr(out), _ptr(bound), _stream_ptr(stream)),
-               self.ctx.handle)
+            if bound.dtype != f64 or bound.numel() < self.n or not bound.is_contiguous():
+                raise ValueError(f"bound must be a contiguous float64 tensor of >= {self.n} elements")
+            bptr = bound.data_ptr()
+        st = self._exec(self.handle, params.data_ptr(), out.data_ptr(), bptr, _stream_ptr(stream))
+        if st != 0:
+            _check(st, self.ctx.handle)
         return out
 
     def execute_grad(self, params, grad_out, grad_params=None, stream=None):
