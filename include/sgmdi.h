@@ -74,11 +74,16 @@ typedef enum {
 
 /* Arithmetic of the per-coordinate work (node values and within-rule sums).
  * The sweep's truncated-polynomial products and the read-out are FP64 in
- * both modes. */
+ * every mode.  Node values of integrands whose parameters leave the FP32
+ * series range (|parameter| > 2) are formed in FP64 and rounded once in the
+ * FP32 modes. */
 typedef enum {
     SG_PREC_FP64 = 0,
-    SG_PREC_FP32_COMPENSATED = 1 /* FP32 node values, FP32 hi+lo weights,
-                                    two-sum compensated FP32 accumulation */
+    SG_PREC_FP32_COMPENSATED = 1, /* FP32 node values, FP32 hi+lo weights,
+                                     two-sum compensated FP32 accumulation */
+    SG_PREC_FP32_FP64_SUM = 2     /* FP32 node values, FP64 weights and
+                                     FP64 accumulation (the reverse sweep of
+                                     such a plan runs in mode 1) */
 } sg_precision;
 
 /* Largest excess budget K = q - d the GPU path accepts. */
@@ -231,6 +236,13 @@ sg_status sg_plan_get_info(const sg_plan *plan, sg_plan_info *info);
  * launch repeatedly on params_dev/out_dev (their contents are overwritten).
  * Errors: INVALID_ARGUMENT, DEVICE. */
 sg_status sg_plan_autotune(sg_plan *plan, const double *params_dev, double *out_dev, void *stream);
+
+/* Set the forward schedule and launch mode directly (the knobs
+ * sg_plan_autotune chooses; see sg_plan_info): coords_per_lane in 1..64,
+ * max_group in {1, 2, 4}, graph 0 (direct launch) or 1 (graph replay on
+ * non-default streams).  Re-packs the plan's workgroups; synchronous.
+ * Errors: INVALID_ARGUMENT, OUT_OF_MEMORY, DEVICE. */
+sg_status sg_plan_set_schedule(sg_plan *plan, int32_t coords_per_lane, int32_t max_group, int32_t graph);
 
 /* Release a plan (NULL accepted). */
 sg_status sg_plan_destroy(sg_plan *plan);

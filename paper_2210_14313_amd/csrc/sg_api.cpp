@@ -535,7 +535,7 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
     if (!ctx || !plan) return SG_ERR_INVALID_ARGUMENT;
     *plan = nullptr;
     if (!problems || n < 1) return fail(ctx, SG_ERR_INVALID_ARGUMENT, "empty problem list");
-    if (precision != SG_PREC_FP64 && precision != SG_PREC_FP32_COMPENSATED)
+    if (precision != SG_PREC_FP64 && precision != SG_PREC_FP32_COMPENSATED && precision != SG_PREC_FP32_FP64_SUM)
         return fail(ctx, SG_ERR_INVALID_ARGUMENT, "unknown precision");
     for (int i = 0; i < n; ++i) {
         sg_status st = validate_problem(ctx, problems[i], i);
@@ -823,6 +823,23 @@ sg_status sg_plan_autotune(sg_plan* p, const double* params_dev, double* out_dev
     return SG_OK;
 }
 
+sg_status sg_plan_set_schedule(sg_plan* p, int32_t coords_per_lane, int32_t max_group, int32_t graph)
+{
+    if (!p) return SG_ERR_INVALID_ARGUMENT;
+    if (coords_per_lane < 1 || coords_per_lane > 64 || (max_group != 1 && max_group != 2 && max_group != 4) ||
+        (graph != 0 && graph != 1))
+        return fail(p->ctx, SG_ERR_INVALID_ARGUMENT, "schedule out of range");
+    FwdSched sc;
+    sc.cpl = coords_per_lane;
+    sc.gmax = max_group;
+    destroy_graphs(p);
+    sg_status st = plan_repack(p, sc);
+    if (st != SG_OK) return st;
+    p->use_graph = graph == 1;
+    p->info.graph = graph;
+    return SG_OK;
+}
+
 sg_status sg_plan_destroy(sg_plan* p)
 {
     if (!p) return SG_OK;
@@ -843,7 +860,7 @@ sg_status sg_integrate(sg_context* ctx, const sg_problem* problem, int32_t preci
 {
     if (!ctx) return SG_ERR_INVALID_ARGUMENT;
     if (!problem || !params_dev || !out_dev) return fail(ctx, SG_ERR_INVALID_ARGUMENT, "NULL argument");
-    if (precision != SG_PREC_FP64 && precision != SG_PREC_FP32_COMPENSATED)
+    if (precision != SG_PREC_FP64 && precision != SG_PREC_FP32_COMPENSATED && precision != SG_PREC_FP32_FP64_SUM)
         return fail(ctx, SG_ERR_INVALID_ARGUMENT, "unknown precision");
     sg_status st = validate_problem(ctx, *problem, 0);
     if (st != SG_OK) return st;

@@ -390,6 +390,49 @@ __device__ __forceinline__ void surplus32_const(const CoordParam& cp, double (&d
     eps += (double)epsf;
 }
 
+// FP32 pair values accumulated against FP64 weights in FP64 (on CDNA4 an
+// FP64 FMA issues at the FP32 rate, so the wider accumulator costs one
+// instruction per term where the two-sum costs eight).
+template <int RULE, int K, int FAM>
+__device__ __forceinline__ void surplus32e_const(const CoordParam& cp, double (&del)[MAXK + 1], double& eps)
+{
+    constexpr int RC = rule_class_of(RULE);
+    using R = tab::Rec<RULE, K>;
+#pragma unroll
+    for (int e = 0; e <= MAXK; ++e) del[e] = 0.0;
+    float epsf = 0.0f;
+    const float c32 = (float)cp.p0;
+    static_for<2, K + 2>([&](auto Lc) {
+        constexpr int L = decltype(Lc)::value;
+        constexpr int off = rc_off64(RC, K, L), rl = rc_rec64(RC, K, L);
+        constexpr int lo = rc_elo(L), hi = rc_ehi(RC, K, L);
+        static_for<0, rc_pairs(RC, L)>([&](auto Jc) {
+            constexpr int J = decltype(Jc)::value;
+            constexpr double y = R::r64[off + J * rl];
+            float sv;
+            if constexpr (FAM == FAM_PEAK) {
+                sv = (float)pair64<FAM_PEAK>(cp, y);
+            } else {
+                constexpr float yh = (float)y;
+                constexpr float yl = (float)(y - (double)yh);
+                sv = pair32_series<FAM, yl != 0.0f>(c32, yh, yl);
+            }
+            const double sd = (double)sv;
+            static_for<lo, hi + 1>([&](auto Ec) {
+                constexpr int E = decltype(Ec)::value;
+                constexpr double w = R::r64[off + J * rl + 1 + E - lo];
+                if constexpr (first_level<RC, K>(E) == L && J == 0) del[E] = w * sd;
+                else del[E] = fma(w, sd, del[E]);
+            });
+            constexpr float wa = (float)R::r64[off + J * rl + rl - 1];
+            if constexpr (FAM == FAM_EXP) epsf = fmaf(wa, sv, epsf);
+            else if constexpr (FAM == FAM_OSC) epsf = fmaf(-wa, sv, epsf);
+            else epsf = fmaf(wa, fabsf(sv), epsf);
+        });
+    });
+    eps += (double)epsf;
+}
+
 // ----------------------------------------------------------- merge state
 // Running polynomial a; for the error bound, m = sum_t sum_e |delta_t[e]| and
 // eps = sum_t sum_p sum_e |dW[e][p]| |s_p|; the affine partial sum ls and
@@ -532,8 +575,11 @@ __device__ void readout(const Acc& x, int d, int out_index, const double* __rest
     const double ls_err = u64 * (double)d * x.lsabs;   // rounding of the affine sum
     // relative error of one surplus term: pair value (8 roundings) plus the
     // within-rule sum (FP64: a plain FMA chain over at most rl_pairs terms;
-    // FP32: one rounding of the product, compensated accumulation)
-    const double rel = PREC == SG_PREC_FP64 ? u64 * (8.0 + (double)rl_pairs) : 5.9604644775390625e-08 * 10.0;
+    // FP32 compensated: one rounding of the product, compensated
+    // accumulation; FP32 values with FP64 sums: the FP32 value's error, the
+    // FP64 chain adding a negligible rl_pairs * 2^-53)
+    const double rel = PREC == SG_PREC_FP64 ? u64 * (8.0 + (double)rl_pairs)
+                                            : 5.9604644775390625e-08 * 10.0 + u64 * (double)rl_pairs;
     // products of the sweep: (K+2) roundings per level of the product tree
     // (depth: the caller's bound on the tree depth)
     const double levels = (double)depth;
@@ -662,7 +708,8 @@ __device__ __forceinline__ void wave_sweep(const WaveInfo& wi, const double* __r
         if constexpr (K <= KCONST) {
             if (FAM == FAM_PEAK || fabs(cp.p0) <= 2.0) {
                 if constexpr (PREC == SG_PREC_FP64) surplus64_const<RULE, K, FAM>(cp, del, eps_t);
-                else surplus32_const<RULE, K, FAM>(cp, del, eps_t);
+                else if constexpr (PREC == SG_PREC_FP32_COMPENSATED) surplus32_const<RULE, K, FAM>(cp, del, eps_t);
+                else surplus32e_const<RULE, K, FAM>(cp, del, eps_t);
                 done = true;
             }
         }
@@ -673,7 +720,8 @@ __device__ __forceinline__ void wave_sweep(const WaveInfo& wi, const double* __r
             // instead of hoisting hundreds of values into vector registers.
             int opaque = 0;
             asm volatile("" : "+s"(opaque));
-            if constexpr (PREC == SG_PREC_FP64) surplus64<K, RC, FAM>(wi.r64 + opaque, cp, true, del, eps_t);
+            // (FP32 node values with FP64 sums fall back to FP64 values here)
+            if constexpr (PREC != SG_PREC_FP32_COMPENSATED) surplus64<K, RC, FAM>(wi.r64 + opaque, cp, true, del, eps_t);
             else surplus32<K, RC, FAM>(wi.r64 + opaque, wi.r32 + opaque, cp, true, del, eps_t);
         }
         pmul<K>(x.a, del);

@@ -65,6 +65,8 @@ int launch_forward_p0(int, int, const FwdWG*, const double*, const float*, const
                       double*, void*);
 int launch_forward_p1(int, int, const FwdWG*, const double*, const float*, const double*, double*,
                       double*, void*);
+int launch_forward_p2(int, int, const FwdWG*, const double*, const float*, const double*, double*,
+                      double*, void*);
 int launch_adjoint_p0(int, const WGDesc*, const ProbDev*, const double*, const float*, const double*, const double*,
                       double*, double*, void*);
 int launch_adjoint_p1(int, const WGDesc*, const ProbDev*, const double*, const float*, const double*, const double*,
@@ -73,9 +75,10 @@ int launch_adjoint_p1(int, const WGDesc*, const ProbDev*, const double*, const f
 int launch_forward(int precision, int kmax, int nwg, const FwdWG* wgs, const double* pool64,
                    const float* pool32, const double* params, double* out, double* bound, void* stream)
 {
-    return precision == SG_PREC_FP64
-               ? launch_forward_p0(kmax, nwg, wgs, pool64, pool32, params, out, bound, stream)
-               : launch_forward_p1(kmax, nwg, wgs, pool64, pool32, params, out, bound, stream);
+    if (precision == SG_PREC_FP64) return launch_forward_p0(kmax, nwg, wgs, pool64, pool32, params, out, bound, stream);
+    if (precision == SG_PREC_FP32_COMPENSATED)
+        return launch_forward_p1(kmax, nwg, wgs, pool64, pool32, params, out, bound, stream);
+    return launch_forward_p2(kmax, nwg, wgs, pool64, pool32, params, out, bound, stream);
 }
 
 int launch_adjoint(int precision, int nwg, const WGDesc* wgs, const ProbDev* probs, const double* pool64,

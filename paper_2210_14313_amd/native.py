@@ -19,7 +19,7 @@ LIB_PATH = os.environ.get("SGMDI_LIB") or os.path.join(_HERE, "libsgmdi.so")
 
 RULES = {"tr": 1, "cc": 2, "gl": 4, "gl_paper": 5}
 FAMILIES = {"exp_sum": 0, "oscillatory": 1, "product_peak": 2}
-PRECISIONS = {"fp64": 0, "fp32c": 1}
+PRECISIONS = {"fp64": 0, "fp32c": 1, "fp32e": 2}
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "overflow", 4: "out of memory",
           5: "device error", 6: "capture error"}
 MAX_K = 8
@@ -49,7 +49,7 @@ _lib = None
 EXPORTS = ["sg_context_create", "sg_context_destroy", "sg_status_string", "sg_last_error", "sg_counts",
            "sg_rule_table", "sg_coefficient", "sg_unrank", "sg_unrank_device", "sg_plan_create",
            "sg_plan_execute", "sg_plan_execute_grad", "sg_plan_get_info", "sg_plan_autotune",
-           "sg_plan_destroy", "sg_integrate"]
+           "sg_plan_set_schedule", "sg_plan_destroy", "sg_integrate"]
 
 
 def lib():
@@ -77,6 +77,7 @@ def lib():
         "sg_plan_execute_grad": ([vp, vp, vp, vp, vp], i32),
         "sg_plan_get_info": ([vp, P(SgPlanInfo)], i32),
         "sg_plan_autotune": ([vp, vp, vp, vp], i32),
+        "sg_plan_set_schedule": ([vp, i32, i32, i32], i32),
         "sg_plan_destroy": ([vp], i32),
         "sg_integrate": ([vp, P(SgProblem), i32, vp, vp, vp, vp], i32),
     }
@@ -226,6 +227,10 @@ class Plan:
 
     def autotune(self, params, out, stream=None):
         _check(lib().sg_plan_autotune(self.handle, _ptr(params), _ptr(out), _stream_ptr(stream)), self.ctx.handle)
+
+    def set_schedule(self, coords_per_lane: int, max_group: int, graph: bool = False):
+        _check(lib().sg_plan_set_schedule(self.handle, coords_per_lane, max_group, int(graph)),
+               self.ctx.handle)
 
     def close(self):
         if self.handle:

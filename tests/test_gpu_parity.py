@@ -68,12 +68,13 @@ def test_small_random_batches_fp64(api, orc, seed):
     assert np.all(np.abs(got - ref) <= bnd + 1e-300)
 
 
+@pytest.mark.parametrize("prec", ["fp32c", "fp32e"])
 @pytest.mark.parametrize("seed", [1, 2])
-def test_small_random_batches_fp32c(api, orc, seed):
+def test_small_random_batches_fp32(api, orc, seed, prec):
     from paper_2210_14313_amd import workloads as W
     b = W.random_small(seed, 64, d_range=(1, 12), k_range=(0, 5))
-    say("case small_random fp32c seed", seed)
-    got, bnd = _run(api, b, "fp32c")
+    say("case small_random", prec, "seed", seed)
+    got, bnd = _run(api, b, prec)
     ref = _point_ref(orc, b)
     assert np.all(np.abs(got - ref) <= bnd), np.max(np.abs(got - ref) / bnd)
     # the 1e-7 target is stated for the oscillatory and exp-sum families
@@ -97,7 +98,8 @@ def test_tiles_and_edges(api, orc, d, K, rule, family):
     say("case tile", d, K, rule, family)
     npts = orc.counts.counts_by_generating_function(d, d + K, rule)["n_points_rep"]
     ref = _point_ref(orc, b) if npts <= 3e8 else _fact_ref(orc, b)
-    for prec, tol in (("fp64", 1e-12), ("fp32c", 1e-7 if family != "product_peak" else 1.0)):
+    tol32 = 1e-7 if family != "product_peak" else 1.0
+    for prec, tol in (("fp64", 1e-12), ("fp32c", tol32), ("fp32e", tol32)):
         got, bnd = _run(api, b, prec)
         err = np.abs(got - ref) / _scale(b, ref)
         assert err[0] <= tol, (prec, got, ref, err)
@@ -114,8 +116,9 @@ def test_large_arguments_take_the_exact_branch(api, orc):
         ref = _point_ref(orc, b)
         got, bnd = _run(api, b, "fp64")
         assert abs(got[0] - ref[0]) <= 1e-12 * _scale(b, ref)[0]
-        got, bnd = _run(api, b, "fp32c")
-        assert abs(got[0] - ref[0]) <= bnd[0]
+        for prec in ("fp32c", "fp32e"):
+            got, bnd = _run(api, b, prec)
+            assert abs(got[0] - ref[0]) <= bnd[0], prec
 
 
 # ---------------------------------------------------------- full sizes
@@ -126,8 +129,9 @@ def test_plain_exp_d10_full(api, orc):
     ref = _point_ref(orc, b)
     got, _ = _run(api, b, "fp64")
     assert abs(got[0] - ref[0]) <= 1e-12 * abs(ref[0])
-    got32, bnd = _run(api, b, "fp32c")
-    assert abs(got32[0] - ref[0]) <= bnd[0]
+    for prec in ("fp32c", "fp32e"):
+        got32, bnd = _run(api, b, prec)
+        assert abs(got32[0] - ref[0]) <= bnd[0], prec
 
 
 def _golden_rows():
@@ -149,10 +153,11 @@ def test_full_size_against_stored_point_oracle(api, orc, row):
     got, _ = _run(api, b, "fp64")
     scale = max(abs(ref), 1.0) if p.family == "oscillatory" else abs(ref)
     assert abs(got[0] - ref) <= 1e-12 * scale, (got, ref)
-    got32, bnd = _run(api, b, "fp32c")
-    assert abs(got32[0] - ref) <= bnd[0]
-    if p.family != "product_peak":
-        assert abs(got32[0] - ref) <= 1e-7 * scale
+    for prec in ("fp32c", "fp32e"):
+        got32, bnd = _run(api, b, prec)
+        assert abs(got32[0] - ref) <= bnd[0], prec
+        if p.family != "product_peak":
+            assert abs(got32[0] - ref) <= 1e-7 * scale, prec
 
 
 def test_batched_uneven_full_launch(api, orc):
@@ -167,9 +172,10 @@ def test_batched_uneven_full_launch(api, orc):
     scale = _scale(b, ref)
     stream = torch.cuda.Stream()
     stream.wait_stream(torch.cuda.current_stream())
-    for prec, tol in (("fp64", 1e-12), ("fp32c", 1e-7)):
+    for prec, tol in (("fp64", 1e-12), ("fp32c", 1e-7), ("fp32e", 1e-7)):
         say("case batched_uneven", prec)
         plan = native.Plan(b.problems, prec)
+        plan.set_schedule(3, 4, graph=True)
         out = torch.empty(len(b), dtype=torch.float64, device="cuda")
         bnd = torch.empty_like(out)
         with torch.cuda.stream(stream):
@@ -208,8 +214,9 @@ def test_determinism_graph_and_plain_path(api, orc):
     b = W.random_small(9, 100, d_range=(1, 300), k_range=(0, 6))
     params = api.params_tensor(b)
     say("case determinism")
-    for prec in ("fp64", "fp32c"):
+    for prec in ("fp64", "fp32c", "fp32e"):
         plan = native.Plan(b.problems, prec)
+        plan.set_schedule(2, 4, graph=True)
         a = plan.execute(params).clone()           # default stream: no graph
         c = plan.execute(params).clone()
         assert torch.equal(a, c)
@@ -314,4 +321,24 @@ def test_errors_are_reported_before_launch(api):
     with pytest.raises(native.SgError) as e:
         native.unrank_device(3, 5, 5, 100)
     assert e.value.status == 1
+    plan.close()
+
+
+def test_set_schedule_validation_and_equivalence(api, orc):
+    import torch
+    from paper_2210_14313_amd import native, workloads as W
+    b = W.random_small(12, 40, d_range=(1, 400), k_range=(0, 6))
+    params = api.params_tensor(b)
+    say("case set_schedule")
+    plan = native.Plan(b.problems, "fp64")
+    for bad in ((0, 4, 0), (65, 4, 0), (2, 3, 0), (2, 4, 2)):
+        with pytest.raises(native.SgError) as e:
+            plan.set_schedule(bad[0], bad[1], bad[2])
+        assert e.value.status == 1
+    ref = _fact_ref(orc, b)
+    outs = []
+    for cpl, gm in ((1, 1), (2, 4), (5, 2), (64, 1)):
+        plan.set_schedule(cpl, gm)
+        outs.append(plan.execute(params).cpu().numpy())
+        assert np.max(np.abs(outs[-1] - ref) / _scale(b, ref)) <= 1e-12, (cpl, gm)
     plan.close()
