@@ -210,8 +210,13 @@ sg_status sg_plan_execute_grad(sg_plan *plan, const double *params_dev, const do
  *   when d > 64 * coords_per_lane, 64 lanes on up to max_group (1, 2, 4)
  *   waves of one workgroup;
  *   graph: 1 if executions on a non-default stream replay a captured graph,
- *   0 if they launch directly (the three knobs are chosen by
- *   sg_plan_autotune). */
+ *   0 if they launch directly;
+ *   persistent: 1 if the forward launch is the persistent work-queue kernel
+ *   (a grid of the device's resident capacity popping workgroup
+ *   descriptors, longest first, from a per-plan queue that each launch
+ *   leaves reset; executions of such a plan must not overlap in time), 0 if
+ *   the hardware dispatches one workgroup per descriptor (the four knobs are
+ *   chosen by sg_plan_autotune). */
 typedef struct {
     uint64_t effective_points;
     uint64_t units;
@@ -223,7 +228,7 @@ typedef struct {
     int32_t coords_per_lane;
     int32_t max_group;
     int32_t graph;
-    int32_t reserved;
+    int32_t persistent;
 } sg_plan_info;
 
 sg_status sg_plan_get_info(const sg_plan *plan, sg_plan_info *info);
@@ -231,18 +236,20 @@ sg_status sg_plan_get_info(const sg_plan *plan, sg_plan_info *info);
 /* Time candidate schedules for this plan on `stream` with HIP events and
  * keep the fastest (stored in the context; later plans with the same shape
  * class reuse it): the integrand-to-wave schedule (coordinates per lane
- * 1, 2, 3, 4, 8 times waves per integrand 1, 2, 4; see sg_plan_info) and,
- * on a non-default stream, graph replay versus direct launch.  Runs the forward
+ * 1, 2, 3, 4, 8 times waves per integrand 1, 2, 4; see sg_plan_info),
+ * hardware dispatch versus the persistent work-queue kernel and, on a
+ * non-default stream, graph replay versus direct launch.  Runs the forward
  * launch repeatedly on params_dev/out_dev (their contents are overwritten).
  * Errors: INVALID_ARGUMENT, DEVICE. */
 sg_status sg_plan_autotune(sg_plan *plan, const double *params_dev, double *out_dev, void *stream);
 
 /* Set the forward schedule and launch mode directly (the knobs
  * sg_plan_autotune chooses; see sg_plan_info): coords_per_lane in 1..64,
- * max_group in {1, 2, 4}, graph 0 (direct launch) or 1 (graph replay on
- * non-default streams).  Re-packs the plan's workgroups; synchronous.
- * Errors: INVALID_ARGUMENT, OUT_OF_MEMORY, DEVICE. */
-sg_status sg_plan_set_schedule(sg_plan *plan, int32_t coords_per_lane, int32_t max_group, int32_t graph);
+ * max_group in {1, 2, 4}, persistent 0/1, graph 0 (direct launch) or 1
+ * (graph replay on non-default streams).  Re-packs the plan's workgroups;
+ * synchronous.  Errors: INVALID_ARGUMENT, OUT_OF_MEMORY, DEVICE. */
+sg_status sg_plan_set_schedule(sg_plan *plan, int32_t coords_per_lane, int32_t max_group,
+                               int32_t persistent, int32_t graph);
 
 /* Release a plan (NULL accepted). */
 sg_status sg_plan_destroy(sg_plan *plan);

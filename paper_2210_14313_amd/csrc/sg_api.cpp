@@ -30,6 +30,7 @@ struct PlainEntry {
 struct FwdSched {
     int cpl = 2;
     int gmax = 4;
+    bool persistent = false;   // work-queue kernel instead of one workgroup per descriptor
 };
 
 struct Records {
@@ -76,6 +77,8 @@ struct sg_plan {
     FwdWG* d_fwd = nullptr;         // forward workgroup descriptors
     int nfwg = 0;
     size_t fwd_capacity = 0;
+    unsigned int* d_queue = nullptr; // persistent kernel: next-descriptor and exit counters
+    int qgrid = 0;                  // persistent kernel: workgroups launched
     bool use_graph = false;         // replay a captured graph (else direct launch)
     bool params_disjoint = true;    // problems' parameter ranges do not overlap
     int kmax = 0;                   // largest K of the plan (kernel instantiation class)
@@ -529,6 +532,8 @@ sg_status sg_unrank_device(sg_context* ctx, int32_t d, int32_t q, uint64_t rank0
     return SG_OK;
 }
 
+static sg_status plan_repack(sg_plan* p, const FwdSched& sc);
+
 sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n, int32_t precision,
                          sg_plan** plan)
 {
@@ -634,11 +639,13 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
         p->sched = tk->second.first;
         p->use_graph = tk->second.second;
     }
-    if (const char* fs = std::getenv("SGMDI_SCHED")) {   // profiling override: "cpl,gmax"
-        int c = 0, g = 0;
-        if (std::sscanf(fs, "%d,%d", &c, &g) == 2 && c >= 1 && c <= 64 && (g == 1 || g == 2 || g == 4)) {
+    if (const char* fs = std::getenv("SGMDI_SCHED")) {   // profiling override: "cpl,gmax[,persistent]"
+        int c = 0, g = 0, q = 0;
+        const int nf = std::sscanf(fs, "%d,%d,%d", &c, &g, &q);
+        if (nf >= 2 && c >= 1 && c <= 64 && (g == 1 || g == 2 || g == 4)) {
             p->sched.cpl = c;
             p->sched.gmax = g;
+            p->sched.persistent = nf == 3 && q == 1;
         }
     }
     // reverse sweep: one problem per wave slot, cost-threshold schedule
@@ -647,13 +654,7 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
     std::vector<WGDesc> wgs = pack_workgroups(p->probs, wv);
     for (int k = 0; k < n; ++k) p->probs[k].waves = wv[k];
     p->nwg = (int)wgs.size();
-    // forward sweep: class-uniform waves, problems side by side
-    std::vector<FwdWG> fwd = pack_forward(p->probs, p->unit_cost, p->sched);
-    p->nfwg = (int)fwd.size();
     info.block_threads = 256;
-    info.grid_blocks = p->nfwg;
-    info.coords_per_lane = p->sched.cpl;
-    info.max_group = p->sched.gmax;
     info.graph = p->use_graph ? 1 : 0;
     p->info = info;
 
@@ -661,8 +662,12 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
     if ((st = upload(ctx, &p->d_probs, p->probs.data(), p->probs.size())) != SG_OK) return st;
     if ((st = upload(ctx, &p->d_wgs, wgs.data(), wgs.size())) != SG_OK) return st;
     p->wg_capacity = wgs.size();
-    if ((st = upload(ctx, &p->d_fwd, fwd.data(), fwd.size())) != SG_OK) return st;
-    p->fwd_capacity = fwd.size();
+    {
+        hipError_t e = hipMalloc((void**)&p->d_queue, 2 * sizeof(unsigned int));
+        if (e != hipSuccess) return fail(ctx, SG_ERR_OUT_OF_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    // forward sweep: class-uniform waves, problems side by side
+    if ((st = plan_repack(p.get(), p->sched)) != SG_OK) return st;
     if ((st = upload(ctx, &p->d_pool64, p64.data(), p64.size())) != SG_OK) return st;
     if ((st = upload(ctx, &p->d_pool32, p32.data(), p32.size())) != SG_OK) return st;
     ctx->live_plans++;
@@ -672,8 +677,8 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
 
 static sg_status plan_launch(sg_plan* p, const double* params, double* out, double* bound, void* stream)
 {
-    const int rc = launch_forward(p->precision, p->kmax, p->nfwg, p->d_fwd, p->d_pool64, p->d_pool32, params,
-                                  out, bound, stream);
+    const int rc = launch_forward(p->precision, p->kmax, p->nfwg, p->d_fwd, p->sched.persistent ? p->d_queue : nullptr,
+                                  p->qgrid, p->d_pool64, p->d_pool32, params, out, bound, stream);
     if (rc != 0) return hip_fail(p->ctx, (hipError_t)rc, "forward launch");
     return SG_OK;
 }
@@ -694,9 +699,18 @@ static sg_status plan_repack(sg_plan* p, const FwdSched& sc)
     }
     p->sched = sc;
     p->nfwg = (int)fwd.size();
-    p->info.grid_blocks = p->nfwg;
+    const int cap = forward_capacity(p->precision, p->kmax);
+    if (cap <= 0) p->sched.persistent = false;
+    p->qgrid = std::max(1, std::min(p->nfwg, cap));
+    if (p->sched.persistent) {
+        // counters start at zero; each launch leaves them at zero
+        hipError_t e = hipMemset(p->d_queue, 0, 2 * sizeof(unsigned int));
+        if (e != hipSuccess) return hip_fail(p->ctx, e, "hipMemset");
+    }
+    p->info.grid_blocks = p->sched.persistent ? p->qgrid : p->nfwg;
     p->info.coords_per_lane = sc.cpl;
     p->info.max_group = sc.gmax;
+    p->info.persistent = p->sched.persistent ? 1 : 0;
     return SG_OK;
 }
 
@@ -716,8 +730,8 @@ sg_status sg_plan_execute(sg_plan* p, const double* params_dev, double* out_dev,
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return fail(p->ctx, SG_ERR_CAPTURE, std::string("begin capture: ") + hipGetErrorString(e));
-    const int rc = launch_forward(p->precision, p->kmax, p->nfwg, p->d_fwd, p->d_pool64, p->d_pool32, params_dev,
-                                  out_dev, bound_dev, stream);
+    const int rc = launch_forward(p->precision, p->kmax, p->nfwg, p->d_fwd, p->sched.persistent ? p->d_queue : nullptr,
+                                  p->qgrid, p->d_pool64, p->d_pool32, params_dev, out_dev, bound_dev, stream);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(s, &graph);
     if (rc != 0 || e != hipSuccess || !graph) {
@@ -786,13 +800,16 @@ sg_status sg_plan_autotune(sg_plan* p, const double* params_dev, double* out_dev
     const int cpls[5] = {1, 2, 3, 4, 8};
     const int gmaxs[3] = {1, 2, 4};
     sg_status st = SG_OK;
-    // candidates: coordinates per lane x waves per problem x (graph replay |
-    // direct launch); the graph variant is only timed on a non-default stream
+    // candidates: coordinates per lane x waves per problem x (hardware
+    // dispatch | persistent work queue) x (graph replay | direct launch); the
+    // graph variant is only timed on a non-default stream
     for (int c : cpls) {
-        for (int gm : gmaxs) {
+        for (int gq = 0; gq < 6; ++gq) {
+            const int gm = gmaxs[gq % 3];
             FwdSched sc;
             sc.cpl = c;
             sc.gmax = gm;
+            sc.persistent = gq >= 3;
             if ((st = plan_repack(p, sc)) != SG_OK) break;
             destroy_graphs(p);
             for (int g = 0; g < (stream ? 2 : 1); ++g) {
@@ -823,15 +840,17 @@ sg_status sg_plan_autotune(sg_plan* p, const double* params_dev, double* out_dev
     return SG_OK;
 }
 
-sg_status sg_plan_set_schedule(sg_plan* p, int32_t coords_per_lane, int32_t max_group, int32_t graph)
+sg_status sg_plan_set_schedule(sg_plan* p, int32_t coords_per_lane, int32_t max_group, int32_t persistent,
+                               int32_t graph)
 {
     if (!p) return SG_ERR_INVALID_ARGUMENT;
     if (coords_per_lane < 1 || coords_per_lane > 64 || (max_group != 1 && max_group != 2 && max_group != 4) ||
-        (graph != 0 && graph != 1))
+        (persistent != 0 && persistent != 1) || (graph != 0 && graph != 1))
         return fail(p->ctx, SG_ERR_INVALID_ARGUMENT, "schedule out of range");
     FwdSched sc;
     sc.cpl = coords_per_lane;
     sc.gmax = max_group;
+    sc.persistent = persistent == 1;
     destroy_graphs(p);
     sg_status st = plan_repack(p, sc);
     if (st != SG_OK) return st;
@@ -847,6 +866,7 @@ sg_status sg_plan_destroy(sg_plan* p)
     hipFree(p->d_probs);
     hipFree(p->d_wgs);
     hipFree(p->d_fwd);
+    hipFree(p->d_queue);
     hipFree(p->d_ws);
     hipFree(p->d_pool64);
     hipFree(p->d_pool32);
@@ -893,8 +913,8 @@ sg_status sg_integrate(sg_context* ctx, const sg_problem* problem, int32_t preci
         if ((st = upload(ctx, &pe.pool32, r->r32.data(), r->r32.size())) != SG_OK) return st;
         it = ctx->plain.emplace(key, pe).first;
     }
-    const int rc = launch_forward(precision, K, it->second.nfwg, it->second.fwd, it->second.pool64, it->second.pool32,
-                                  params_dev, out_dev, bound_dev, stream);
+    const int rc = launch_forward(precision, K, it->second.nfwg, it->second.fwd, nullptr, 0, it->second.pool64,
+                                  it->second.pool32, params_dev, out_dev, bound_dev, stream);
     if (rc != 0) return hip_fail(ctx, (hipError_t)rc, "forward launch");
     return SG_OK;
 }

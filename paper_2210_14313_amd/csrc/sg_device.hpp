@@ -809,17 +809,16 @@ __device__ __forceinline__ void switch_k(int K, F&& f)
     });
 }
 
-// Each workgroup holds 4 waves; wave w runs wgs[blockIdx.x].w[w].  A
-// problem spanning several waves sits in consecutive waves of one
-// workgroup and is merged through LDS by its first wave.
+// One workgroup descriptor: 4 waves; wave w runs wg->w[w].  A problem
+// spanning several waves sits in consecutive waves of the workgroup and is
+// merged through LDS by its first wave.  Every thread of the workgroup must
+// call this (it may synchronise the workgroup).
 template <int PREC, int KMAXP>
-__global__ void __launch_bounds__(256)
-k_forward(const FwdWG* __restrict__ wgs, const double* __restrict__ pool64, const float* __restrict__ pool32,
-          const double* __restrict__ params, double* __restrict__ out, double* __restrict__ bound)
+__device__ __forceinline__ void run_workgroup(const FwdWG* wg, const double* __restrict__ pool64,
+                                              const float* __restrict__ pool32, const double* __restrict__ params,
+                                              double* __restrict__ out, double* __restrict__ bound, double* lds)
 {
-    __shared__ double lds[4 * ACC_WORDS];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
-    const FwdWG* wg = wgs + blockIdx.x;
     const FwdWave* wd = &wg->w[w];
     const int K = __builtin_amdgcn_readfirstlane(wd->K);
     const int rule = __builtin_amdgcn_readfirstlane(wd->rule);
@@ -846,6 +845,47 @@ k_forward(const FwdWG* __restrict__ wgs, const double* __restrict__ pool64, cons
             group_finish_k<PREC, decltype(kc)::value>(rule, family, wi.group, lp, lds + w * ACC_WORDS, params, out,
                                                       bound);
         });
+    }
+}
+
+// Hardware-dispatched form: workgroup b runs descriptor b.
+template <int PREC, int KMAXP>
+__global__ void __launch_bounds__(256)
+k_forward(const FwdWG* __restrict__ wgs, const double* __restrict__ pool64, const float* __restrict__ pool32,
+          const double* __restrict__ params, double* __restrict__ out, double* __restrict__ bound)
+{
+    __shared__ double lds[4 * ACC_WORDS];
+    run_workgroup<PREC, KMAXP>(wgs + blockIdx.x, pool64, pool32, params, out, bound, lds);
+}
+
+// Persistent form: a grid sized to the resident capacity pops descriptors
+// (longest first) from a work queue, queue[0] being the next index.  Every
+// workgroup leaves once the queue is exhausted; the last one to leave
+// (counted in queue[1]) resets both counters, so the next launch on the
+// stream starts from zero without a memset (graph-safe).  Launches of one
+// queue must not overlap.
+template <int PREC, int KMAXP>
+__global__ void __launch_bounds__(256)
+k_forward_queue(const FwdWG* __restrict__ wgs, int nwg, unsigned int* __restrict__ queue,
+                const double* __restrict__ pool64, const float* __restrict__ pool32,
+                const double* __restrict__ params, double* __restrict__ out, double* __restrict__ bound)
+{
+    __shared__ double lds[4 * ACC_WORDS];
+    __shared__ int next;
+    for (;;) {
+        if (threadIdx.x == 0) next = (int)atomicAdd(&queue[0], 1u);
+        __syncthreads();
+        const int idx = __builtin_amdgcn_readfirstlane(next);
+        __syncthreads();   // every thread has read `next` before it is overwritten
+        if (idx >= nwg) break;
+        run_workgroup<PREC, KMAXP>(wgs + idx, pool64, pool32, params, out, bound, lds);
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&queue[1], 1u) == gridDim.x - 1) {
+            atomicExch(&queue[0], 0u);
+            atomicExch(&queue[1], 0u);
+        }
     }
 }
 

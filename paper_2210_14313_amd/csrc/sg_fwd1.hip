@@ -5,12 +5,26 @@
 
 namespace sg {
 
-int launch_forward_p1(int kmax, int nwg, const FwdWG* wgs, const double* pool64,
-                       const float* pool32, const double* params, double* out, double* bound, void* stream)
+int launch_forward_p1(int kmax, int nwg, const FwdWG* wgs, unsigned int* queue, int qgrid, const double* pool64,
+                      const float* pool32, const double* params, double* out, double* bound, void* stream)
 {
     if (nwg <= 0) return 0;
-    const dim3 grid((unsigned)nwg), block(256);
+    const dim3 block(256);
     hipStream_t s = (hipStream_t)stream;
+    if (queue) {
+        const dim3 grid((unsigned)qgrid);
+        if (kmax <= 4)
+            hipLaunchKernelGGL((dev::k_forward_queue<1, 4>), grid, block, 0, s, wgs, nwg, queue, pool64, pool32, params,
+                               out, bound);
+        else if (kmax <= 6)
+            hipLaunchKernelGGL((dev::k_forward_queue<1, 6>), grid, block, 0, s, wgs, nwg, queue, pool64, pool32, params,
+                               out, bound);
+        else
+            hipLaunchKernelGGL((dev::k_forward_queue<1, 8>), grid, block, 0, s, wgs, nwg, queue, pool64, pool32, params,
+                               out, bound);
+        return (int)hipGetLastError();
+    }
+    const dim3 grid((unsigned)nwg);
     if (kmax <= 4)
         hipLaunchKernelGGL((dev::k_forward<1, 4>), grid, block, 0, s, wgs, pool64, pool32, params, out, bound);
     else if (kmax <= 6)
@@ -18,6 +32,20 @@ int launch_forward_p1(int kmax, int nwg, const FwdWG* wgs, const double* pool64,
     else
         hipLaunchKernelGGL((dev::k_forward<1, 8>), grid, block, 0, s, wgs, pool64, pool32, params, out, bound);
     return (int)hipGetLastError();
+}
+
+// Workgroups of the persistent forward kernel the current device holds at
+// once (resident capacity), 0 on error.
+int forward_capacity_p1(int kmax)
+{
+    const void* f = kmax <= 4   ? reinterpret_cast<const void*>(&dev::k_forward_queue<1, 4>)
+                    : kmax <= 6 ? reinterpret_cast<const void*>(&dev::k_forward_queue<1, 6>)
+                                : reinterpret_cast<const void*>(&dev::k_forward_queue<1, 8>);
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 256, 0) != hipSuccess) return 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return per_cu * cus;
 }
 
 }  // namespace sg

@@ -146,9 +146,13 @@ struct LaunchCfg {
 
 // Kernel launchers (sg_unrank.hip dispatches to sg_fwd*.hip / sg_adj*.hip).
 // kmax: the largest K of the launched problems (selects the instantiation).
-int launch_forward(int precision, int kmax, int nwg, const FwdWG* wgs,
+// queue == nullptr: one workgroup per descriptor; else the persistent
+// work-queue kernel on qgrid workgroups (queue: two zeroed counters).
+int launch_forward(int precision, int kmax, int nwg, const FwdWG* wgs, unsigned int* queue, int qgrid,
                    const double* pool64, const float* pool32, const double* params, double* out,
                    double* bound, void* stream);
+// Resident workgroups of the persistent forward kernel on the current device.
+int forward_capacity(int precision, int kmax);
 int launch_adjoint(int precision, int nwg, const WGDesc* wgs, const ProbDev* probs, const double* pool64,
                    const float* pool32, const double* params, const double* gout, double* grad, double* ws,
                    void* stream);

@@ -61,24 +61,36 @@ k_unrank(int d, int q, uint64_t rank0, uint64_t count, int max_nnz, const uint64
 
 }  // namespace
 
-int launch_forward_p0(int, int, const FwdWG*, const double*, const float*, const double*, double*,
-                      double*, void*);
-int launch_forward_p1(int, int, const FwdWG*, const double*, const float*, const double*, double*,
-                      double*, void*);
-int launch_forward_p2(int, int, const FwdWG*, const double*, const float*, const double*, double*,
-                      double*, void*);
+int launch_forward_p0(int, int, const FwdWG*, unsigned int*, int, const double*, const float*, const double*,
+                      double*, double*, void*);
+int launch_forward_p1(int, int, const FwdWG*, unsigned int*, int, const double*, const float*, const double*,
+                      double*, double*, void*);
+int launch_forward_p2(int, int, const FwdWG*, unsigned int*, int, const double*, const float*, const double*,
+                      double*, double*, void*);
+int forward_capacity_p0(int);
+int forward_capacity_p1(int);
+int forward_capacity_p2(int);
 int launch_adjoint_p0(int, const WGDesc*, const ProbDev*, const double*, const float*, const double*, const double*,
                       double*, double*, void*);
 int launch_adjoint_p1(int, const WGDesc*, const ProbDev*, const double*, const float*, const double*, const double*,
                       double*, double*, void*);
 
-int launch_forward(int precision, int kmax, int nwg, const FwdWG* wgs, const double* pool64,
-                   const float* pool32, const double* params, double* out, double* bound, void* stream)
+int launch_forward(int precision, int kmax, int nwg, const FwdWG* wgs, unsigned int* queue, int qgrid,
+                   const double* pool64, const float* pool32, const double* params, double* out, double* bound,
+                   void* stream)
 {
-    if (precision == SG_PREC_FP64) return launch_forward_p0(kmax, nwg, wgs, pool64, pool32, params, out, bound, stream);
+    if (precision == SG_PREC_FP64)
+        return launch_forward_p0(kmax, nwg, wgs, queue, qgrid, pool64, pool32, params, out, bound, stream);
     if (precision == SG_PREC_FP32_COMPENSATED)
-        return launch_forward_p1(kmax, nwg, wgs, pool64, pool32, params, out, bound, stream);
-    return launch_forward_p2(kmax, nwg, wgs, pool64, pool32, params, out, bound, stream);
+        return launch_forward_p1(kmax, nwg, wgs, queue, qgrid, pool64, pool32, params, out, bound, stream);
+    return launch_forward_p2(kmax, nwg, wgs, queue, qgrid, pool64, pool32, params, out, bound, stream);
+}
+
+int forward_capacity(int precision, int kmax)
+{
+    if (precision == SG_PREC_FP64) return forward_capacity_p0(kmax);
+    if (precision == SG_PREC_FP32_COMPENSATED) return forward_capacity_p1(kmax);
+    return forward_capacity_p2(kmax);
 }
 
 int launch_adjoint(int precision, int nwg, const WGDesc* wgs, const ProbDev* probs, const double* pool64,

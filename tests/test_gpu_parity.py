@@ -214,9 +214,9 @@ def test_determinism_graph_and_plain_path(api, orc):
     b = W.random_small(9, 100, d_range=(1, 300), k_range=(0, 6))
     params = api.params_tensor(b)
     say("case determinism")
-    for prec in ("fp64", "fp32c", "fp32e"):
+    for prec, pq in (("fp64", False), ("fp32c", True), ("fp32e", False)):
         plan = native.Plan(b.problems, prec)
-        plan.set_schedule(2, 4, graph=True)
+        plan.set_schedule(2, 4, graph=True, persistent=pq)
         a = plan.execute(params).clone()           # default stream: no graph
         c = plan.execute(params).clone()
         assert torch.equal(a, c)
@@ -331,14 +331,40 @@ def test_set_schedule_validation_and_equivalence(api, orc):
     params = api.params_tensor(b)
     say("case set_schedule")
     plan = native.Plan(b.problems, "fp64")
-    for bad in ((0, 4, 0), (65, 4, 0), (2, 3, 0), (2, 4, 2)):
+    for bad in ((0, 4, 0, 0), (65, 4, 0, 0), (2, 3, 0, 0), (2, 4, 2, 0), (2, 4, 0, 2)):
         with pytest.raises(native.SgError) as e:
-            plan.set_schedule(bad[0], bad[1], bad[2])
+            plan.set_schedule(bad[0], bad[1], graph=bad[2], persistent=bad[3])
         assert e.value.status == 1
     ref = _fact_ref(orc, b)
-    outs = []
-    for cpl, gm in ((1, 1), (2, 4), (5, 2), (64, 1)):
-        plan.set_schedule(cpl, gm)
-        outs.append(plan.execute(params).cpu().numpy())
-        assert np.max(np.abs(outs[-1] - ref) / _scale(b, ref)) <= 1e-12, (cpl, gm)
+    for cpl, gm, pq in ((1, 1, 0), (2, 4, 0), (5, 2, 0), (64, 1, 0), (1, 4, 1), (3, 2, 1), (64, 4, 1)):
+        plan.set_schedule(cpl, gm, persistent=bool(pq))
+        assert plan.info()["persistent"] == pq
+        for rep in range(3):   # the work queue must come back reset after every launch
+            got = plan.execute(params).cpu().numpy()
+            assert np.max(np.abs(got - ref) / _scale(b, ref)) <= 1e-12, (cpl, gm, pq, rep)
     plan.close()
+
+
+def test_persistent_queue_in_graph_replays(api, orc):
+    import torch
+    from paper_2210_14313_amd import native, workloads as W
+    b = W.batched_uneven(n=512)
+    params = api.params_tensor(b)
+    ref = _fact_ref(orc, b)
+    say("case persistent queue graph replays")
+    for prec, tol in (("fp64", 1e-12), ("fp32e", 1e-7)):
+        plan = native.Plan(b.problems, prec)
+        plan.set_schedule(2, 4, graph=True, persistent=True)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        out = torch.empty(len(b), dtype=torch.float64, device="cuda")
+        eager = plan.execute(params).clone()   # default stream: direct launch of the queue kernel
+        for rep in range(4):                   # capture, then replays with host work between them
+            out.fill_(float("nan"))
+            s.wait_stream(torch.cuda.current_stream())
+            plan.execute(params, out, stream=s)
+            s.synchronize()
+            assert torch.equal(out, eager), (prec, rep)
+            got = out.cpu().numpy()
+            assert np.max(np.abs(got - ref) / _scale(b, ref)) <= tol, (prec, rep)
+        plan.close()
