@@ -30,8 +30,44 @@ VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 PAIR_EVAL_FLOPS = 8.0   # one centred node-pair evaluation = one quarter-rate transcendental slot
 
 
+# HBM traffic of one forward launch on the 4096-integrand batch, from two
+# rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE per dispatch) scaled by
+# what the same counters read for a device copy of known size (bench.py
+# --copy-probe-mb), keyed by precision and by a hash of the kernel sources
+# the counters were taken on; any other source hash reports null.
+MEASURED_TRAFFIC = {
+    ("fp32c", "3ab94742f6551173"): 8664411.0,
+    ("fp32e", "3ab94742f6551173"): 8616607.0,
+}
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2210_14313_amd", "csrc")
+    for f in ("sg_device.hpp", "sg_internal.hpp", "sg_fwd0.hip", "sg_fwd1.hip", "sg_fwd2.hip", "sg_rules.cpp",
+              "gen_tables.cpp"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def copy_probe(mb: int) -> None:
+    """Calibration workload for the traffic counters: five device-to-device
+    copies of `mb` MiB (each reads and writes mb MiB)."""
+    import torch
+    n = mb * (1 << 20) // 8
+    x = torch.empty(n, dtype=torch.float64, device="cuda:0").uniform_()
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 8, "copies": 5}))
 
 
 def algorithmic_flops(info) -> float:
@@ -77,7 +113,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--cpu-points", type=float, default=1.5e9)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="only run the traffic-counter calibration copy of this many MiB")
     args = ap.parse_args()
+    if args.copy_probe_mb > 0:
+        copy_probe(args.copy_probe_mb)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -169,7 +210,9 @@ def main():
                    "integrands": args.n, "precision": args.precision,
                    "effective_points_per_step": eff, "parallelism": "single-gpu"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / VALU_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / VALU_PEAK_TFLOPS,
+                     "traffic": MEASURED_TRAFFIC.get((args.precision, kernel_source_hash()))
+                     if args.n == 4096 else None,
                      "kernel_ms": main_run["kernel_ms"], "algorithmic_flops_per_launch": flops},
         "accuracy": {"max_rel_err_vs_oracle": max_err, "all_within_stated_bound": bound_ok,
                      "max_stated_rel_bound": float(np.max(main_run["bound"] / scale))},
