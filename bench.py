@@ -113,6 +113,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--cpu-points", type=float, default=1.5e9)
+    ap.add_argument("--scaling-mults", default="16,64",
+                    help="extra batch sizes (multiples of --n) for the scaling series")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="only run the traffic-counter calibration copy of this many MiB")
     args = ap.parse_args()
@@ -314,6 +316,39 @@ def main():
                          "max_rel_err_vs_oracle_grad": float(np.max(errs))}
             plan.close()
         extras["adjoint_gradient_osc_d200_n256"] = adj
+
+        # scaling series: the same recipe with more integrands per launch
+        scal = {str(args.n): {"kernel_ms": main_run["kernel_ms"], "grid_blocks": info["grid_blocks"],
+                              "points_per_s_kernel": eff / (main_run["kernel_ms"] / 1e3),
+                              "roofline_frac": achieved / VALU_PEAK_TFLOPS}}
+        for mult in [int(m) for m in args.scaling_mults.split(",") if m]:
+            nb = W.batched_uneven(n=args.n * mult)
+            log(f"scaling series: {len(nb)} integrands ...")
+            bp = api.params_tensor(nb, dev)
+            plan = native.Plan(nb.problems, args.precision)
+            o = torch.empty(len(nb), dtype=torch.float64, device=dev)
+            bd = torch.empty_like(o)
+            plan.autotune(bp, o, stream=s)
+            for _ in range(3):
+                plan.execute(bp, o, bd, stream=s)
+            torch.cuda.synchronize()
+            reps = 20
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            for _ in range(reps):
+                plan.execute(bp, o, bd, stream=s)
+            e1.record(s)
+            torch.cuda.synchronize()
+            kms = e0.elapsed_time(e1) / reps
+            ni = plan.info()
+            fl = algorithmic_flops(ni)
+            scal[str(len(nb))] = {"kernel_ms": kms, "grid_blocks": ni["grid_blocks"],
+                                  "coords_per_lane": ni["coords_per_lane"],
+                                  "points_per_s_kernel": float(ni["effective_points"]) / (kms / 1e3),
+                                  "roofline_frac": fl / (kms / 1e3) / 1e12 / VALU_PEAK_TFLOPS}
+            plan.close()
+            del bp, o, bd
+        extras["scaling_" + args.precision] = scal
         result["extras"] = extras
 
     if not args.no_cpu_baseline:

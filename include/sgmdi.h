@@ -236,7 +236,7 @@ sg_status sg_plan_get_info(const sg_plan *plan, sg_plan_info *info);
 /* Time candidate schedules for this plan on `stream` with HIP events and
  * keep the fastest (stored in the context; later plans with the same shape
  * class reuse it): the integrand-to-wave schedule (coordinates per lane
- * 1, 2, 3, 4, 8 times waves per integrand 1, 2, 4; see sg_plan_info),
+ * 1, 2, 3, 4, 8, 16 times waves per integrand 1, 2, 4; see sg_plan_info),
  * hardware dispatch versus the persistent work-queue kernel and, on a
  * non-default stream, graph replay versus direct launch.  Runs the forward
  * launch repeatedly on params_dev/out_dev (their contents are overwritten).

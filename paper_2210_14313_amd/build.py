@@ -54,21 +54,34 @@ def generate_tables(objdir: str, verbose: bool = False) -> None:
     if r.returncode != 0:
         sys.stderr.write(r.stderr)
         raise RuntimeError("gen_tables failed")
-    tmp = os.path.join(objdir, "sg_tables.inc.tmp")
+    dst = os.path.join(objdir, "sg_tables.inc")
+    if os.path.exists(dst) and open(dst).read() == r.stdout:
+        return   # unchanged: keep its timestamp
+    tmp = dst + ".tmp"
     with open(tmp, "w") as f:
         f.write(r.stdout)
-    os.replace(tmp, os.path.join(objdir, "sg_tables.inc"))
+    os.replace(tmp, dst)
 
 
-def build(verbose: bool = False, extra_flags=None) -> str:
-    """Compile every source and link libsgmdi.so next to this file."""
+def build(verbose: bool = False, extra_flags=None, incremental: bool = False) -> str:
+    """Compile every source and link libsgmdi.so next to this file.
+
+    incremental=True skips objects newer than their source and every header
+    (a development shortcut; the default always compiles everything)."""
     objdir = os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)
     generate_tables(objdir, verbose)
+    headers = [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith((".hpp", ".h"))]
+    headers += [os.path.join(INCLUDE, h) for h in os.listdir(INCLUDE)]
+    headers.append(os.path.join(objdir, "sg_tables.inc"))
 
     def compile_one(src):
         path = os.path.join(CSRC, src)
         obj = os.path.join(objdir, src + ".o")
+        if incremental and os.path.exists(obj):
+            t = os.path.getmtime(obj)
+            if all(os.path.getmtime(f) < t for f in [path] + headers):
+                return obj
         cmd = [hipcc()] + HIP_FLAGS + (extra_flags or []) + ["-I", INCLUDE, "-I", CSRC, "-I", objdir, "-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)

@@ -797,7 +797,7 @@ sg_status sg_plan_autotune(sg_plan* p, const double* params_dev, double* out_dev
     bool best_g = saved_g;
     float best_ms = 1e30f;
     const int reps = 20;
-    const int cpls[5] = {1, 2, 3, 4, 8};
+    const int cpls[6] = {1, 2, 3, 4, 8, 16};
     const int gmaxs[3] = {1, 2, 4};
     sg_status st = SG_OK;
     // candidates: coordinates per lane x waves per problem x (hardware
