@@ -340,15 +340,52 @@ __device__ __forceinline__ void surplus64_const(const CoordParam& cp, double (&d
     eps += et;
 }
 
-// FP32 pair values, two-sum compensated FP32 sums against hi+lo weights.
+// Position of the pair (L, J) among the terms of row e (pairs in level
+// order) and the length of row e.
+template <int RC, int K>
+constexpr int row_index(int e, int L, int J)
+{
+    int n = 0;
+    for (int l = 2; l < L; ++l)
+        if (rc_elo(l) <= e && e <= rc_ehi(RC, K, l)) n += rc_pairs(RC, l);
+    return n + J;
+}
+template <int RC, int K>
+constexpr int row_length(int e)
+{
+    int n = 0;
+    for (int l = 2; l <= K + 1; ++l)
+        if (rc_elo(l) <= e && e <= rc_ehi(RC, K, l)) n += rc_pairs(RC, l);
+    return n;
+}
+
+// Terms per block of the blocked two-sum below.
+constexpr int kSumBlock = 4;
+
+// hi + lo += b with the rounding error of the addition kept exactly (two-sum).
+__device__ __forceinline__ void two_sum_into(float& hi, float& lo, float b)
+{
+    const float t = hi + b;
+    const float bp = t - hi;
+    const float err = (hi - (t - bp)) + (b - bp);
+    hi = t;
+    lo += err;
+}
+
+// FP32 pair values, compensated FP32 sums against hi+lo weights: the high
+// weight parts are summed by an FMA chain over blocks of kSumBlock
+// consecutive terms of a row, the block sums enter the row's (hi, lo) pair by
+// two-sum, and the low weight parts go to lo by FMA.  Per term 2 + 6/kSumBlock
+// instructions; the rounding of a block's chain (at most kSumBlock roundings
+// of partial sums of its terms) is what the error bound charges per term.
 template <int RULE, int K, int FAM>
 __device__ __forceinline__ void surplus32_const(const CoordParam& cp, double (&del)[MAXK + 1], double& eps)
 {
     constexpr int RC = rule_class_of(RULE);
     using R = tab::Rec<RULE, K>;
-    float hi[MAXK + 1], lo[MAXK + 1];
+    float hi[MAXK + 1], lo[MAXK + 1], part[MAXK + 1];
 #pragma unroll
-    for (int e = 0; e <= MAXK; ++e) { hi[e] = 0.0f; lo[e] = 0.0f; }
+    for (int e = 0; e <= MAXK; ++e) { hi[e] = 0.0f; lo[e] = 0.0f; part[e] = 0.0f; }
     float epsf = 0.0f;
     const float c32 = (float)cp.p0;
     static_for<2, K + 2>([&](auto Lc) {
@@ -371,11 +408,15 @@ __device__ __forceinline__ void surplus32_const(const CoordParam& cp, double (&d
                 constexpr int E = decltype(Ec)::value;
                 constexpr float wh = R::r32[off32 + J * rl32 + 2 * (E - elo)];
                 constexpr float wl = R::r32[off32 + J * rl32 + 2 * (E - elo) + 1];
-                if constexpr (first_level<RC, K>(E) == L && J == 0) {
-                    hi[E] = wh * sv;
-                    lo[E] = wl * sv;
-                } else {
-                    acc2(hi[E], lo[E], wh, wl, sv);
+                constexpr int k = row_index<RC, K>(E, L, J), n = row_length<RC, K>(E);
+                constexpr bool block_end = (k % kSumBlock == kSumBlock - 1) || (k == n - 1);
+                if constexpr (k % kSumBlock == 0) part[E] = wh * sv;
+                else part[E] = fmaf(wh, sv, part[E]);
+                if constexpr (k == 0) lo[E] = wl * sv;
+                else lo[E] = fmaf(wl, sv, lo[E]);
+                if constexpr (block_end) {
+                    if constexpr (k < kSumBlock) hi[E] = part[E];
+                    else two_sum_into(hi[E], lo[E], part[E]);
                 }
             });
             constexpr float wa = (float)R::r64[off + J * rl + rl - 1];
@@ -575,11 +616,14 @@ __device__ void readout(const Acc& x, int d, int out_index, const double* __rest
     const double ls_err = u64 * (double)d * x.lsabs;   // rounding of the affine sum
     // relative error of one surplus term: pair value (8 roundings) plus the
     // within-rule sum (FP64: a plain FMA chain over at most rl_pairs terms;
-    // FP32 compensated: one rounding of the product, compensated
-    // accumulation; FP32 values with FP64 sums: the FP32 value's error, the
-    // FP64 chain adding a negligible rl_pairs * 2^-53)
+    // FP32 compensated: the FMA chain of the term's block, at most
+    // kSumBlock roundings, blocks joined exactly; FP32 values with FP64
+    // sums: the FP32 value's error, the FP64 chain adding a negligible
+    // rl_pairs * 2^-53)
     const double rel = PREC == SG_PREC_FP64 ? u64 * (8.0 + (double)rl_pairs)
-                                            : 5.9604644775390625e-08 * 10.0 + u64 * (double)rl_pairs;
+                       : PREC == SG_PREC_FP32_COMPENSATED
+                           ? 5.9604644775390625e-08 * (9.0 + kSumBlock) + u64 * (double)rl_pairs
+                           : 5.9604644775390625e-08 * 10.0 + u64 * (double)rl_pairs;
     // products of the sweep: (K+2) roundings per level of the product tree
     // (depth: the caller's bound on the tree depth)
     const double levels = (double)depth;
