@@ -150,22 +150,28 @@ __device__ __forceinline__ float pair32(const CoordParam& cp, double y)
     return (float)pair64<FAM>(cp, y);
 }
 
-// Pair values on the compiled-table path, |c| <= 2 so |v| <= 1: the node
-// is split as y = yh + yl (two FP32 constants), v = c32 * y in FP32.
+// Pair values on the compiled-table path, |c| <= 2 so |v| <= 1.  The series
+// only needs z = +-(c y)^2, formed as (+-c^2) * y^2 with the per-coordinate
+// factor c2s = +-c^2 rounded once and y^2 a per-pair constant (split into two
+// FP32 constants in FP32, so no systematic per-node rounding enters).
 template <int FAM, bool SPLIT>
-__device__ __forceinline__ float pair32_series(float c32, float yh, float yl)
+__device__ __forceinline__ float pair32_z(float c2s, float y2h, float y2l)
 {
-    const float v = SPLIT ? fmaf(c32, yh, c32 * yl) : c32 * yh;
-    const float z = FAM == FAM_EXP ? v * v : -(v * v);
+    const float z = SPLIT ? fmaf(c2s, y2h, c2s * y2l) : c2s * y2h;
     return z * series32w(z);
 }
 
-template <int FAM>
-__device__ __forceinline__ double pair64_series(double c, double y)
+__device__ __forceinline__ double pair64_z(double c2s, double y2)
 {
-    const double v = c * y;
-    const double z = FAM == FAM_EXP ? v * v : -(v * v);
+    const double z = c2s * y2;
     return z * series64w(z);
+}
+
+// +-c^2 for the series argument z (exp-sum: +, oscillatory: -).
+template <int FAM>
+__device__ __forceinline__ double signed_c2(double c)
+{
+    return FAM == FAM_EXP ? c * c : -(c * c);
 }
 
 // Compensated FP32 accumulation of w*s with w = wh + wl: two-sum of the
@@ -305,6 +311,37 @@ constexpr int first_level(int e)
     return -1;
 }
 
+// The pair with the largest y (level, index) and the sum of |dW| over all
+// pairs and rows of a (rule, K) table.  For the exp-sum and oscillatory
+// families |s(y)| grows with y on the series range, so
+// sum_p (sum_e |dW[e][p]|) |s_p| <= total_wabs * |s(y_max)|: the bound's
+// per-coordinate term costs one multiply instead of one per pair.
+template <int RULE, int K>
+struct TableFacts {
+    static constexpr int RC = rule_class_of(RULE);
+    using R = tab::Rec<RULE, K>;
+    static constexpr int max_pair()
+    {
+        int best = -1;
+        double by = -1.0;
+        int p = 0;
+        for (int L = 2; L <= K + 1; ++L)
+            for (int J = 0; J < rc_pairs(RC, L); ++J, ++p) {
+                const double y = R::r64[rc_off64(RC, K, L) + J * rc_rec64(RC, K, L)];
+                if (y > by) { by = y; best = p; }
+            }
+        return best;
+    }
+    static constexpr double total_wabs()
+    {
+        double w = 0.0;
+        for (int L = 2; L <= K + 1; ++L)
+            for (int J = 0; J < rc_pairs(RC, L); ++J)
+                w += R::r64[rc_off64(RC, K, L) + J * rc_rec64(RC, K, L) + rc_rec64(RC, K, L) - 1];
+        return w * (1.0 + 1.0 / 1048576.0);   // margin for the rounding of the sum and of s(y_max)
+    }
+};
+
 // FP64: delta_t[e] = sum_p dW[e][p] s_p with every (y, dW, sum|dW|) a
 // compile-time constant.  `fast` lanes (|c| <= 2, and every product-peak
 // lane) use the series / rational forms; the caller sends other lanes to
@@ -317,6 +354,7 @@ __device__ __forceinline__ void surplus64_const(const CoordParam& cp, double (&d
 #pragma unroll
     for (int e = 0; e <= MAXK; ++e) del[e] = 0.0;
     double et = 0.0;
+    const double c2s = signed_c2<FAM>(cp.p0);
     static_for<2, K + 2>([&](auto Lc) {
         constexpr int L = decltype(Lc)::value;
         constexpr int off = rc_off64(RC, K, L), rl = rc_rec64(RC, K, L);
@@ -326,15 +364,19 @@ __device__ __forceinline__ void surplus64_const(const CoordParam& cp, double (&d
             constexpr double y = R::r64[off + J * rl];
             double sv;
             if constexpr (FAM == FAM_PEAK) sv = pair64<FAM_PEAK>(cp, y);
-            else sv = pair64_series<FAM>(cp.p0, y);
+            else sv = pair64_z(c2s, y * y);
             static_for<lo, hi + 1>([&](auto Ec) {
                 constexpr int E = decltype(Ec)::value;
                 constexpr double w = R::r64[off + J * rl + 1 + E - lo];
                 if constexpr (first_level<RC, K>(E) == L && J == 0) del[E] = w * sv;
                 else del[E] = fma(w, sv, del[E]);
             });
-            constexpr double wa = R::r64[off + J * rl + rl - 1];
-            et = fma(wa, fabs(sv), et);
+            if constexpr (FAM == FAM_PEAK) {
+                constexpr double wa = R::r64[off + J * rl + rl - 1];
+                et = fma(wa, fabs(sv), et);
+            } else if constexpr (pair_base<RC>(L) + J == TableFacts<RULE, K>::max_pair()) {
+                et = TableFacts<RULE, K>::total_wabs() * fabs(sv);
+            }
         });
     });
     eps += et;
@@ -387,7 +429,7 @@ __device__ __forceinline__ void surplus32_const(const CoordParam& cp, double (&d
 #pragma unroll
     for (int e = 0; e <= MAXK; ++e) { hi[e] = 0.0f; lo[e] = 0.0f; part[e] = 0.0f; }
     float epsf = 0.0f;
-    const float c32 = (float)cp.p0;
+    const float c2s = (float)signed_c2<FAM>(cp.p0);
     static_for<2, K + 2>([&](auto Lc) {
         constexpr int L = decltype(Lc)::value;
         constexpr int off = rc_off64(RC, K, L), rl = rc_rec64(RC, K, L);
@@ -400,9 +442,10 @@ __device__ __forceinline__ void surplus32_const(const CoordParam& cp, double (&d
             if constexpr (FAM == FAM_PEAK) {
                 sv = (float)pair64<FAM_PEAK>(cp, y);
             } else {
-                constexpr float yh = (float)y;
-                constexpr float yl = (float)(y - (double)yh);
-                sv = pair32_series<FAM, yl != 0.0f>(c32, yh, yl);
+                constexpr double y2 = y * y;
+                constexpr float y2h = (float)y2;
+                constexpr float y2l = (float)(y2 - (double)y2h);
+                sv = pair32_z<FAM, y2l != 0.0f>(c2s, y2h, y2l);
             }
             static_for<elo, ehi + 1>([&](auto Ec) {
                 constexpr int E = decltype(Ec)::value;
@@ -419,11 +462,13 @@ __device__ __forceinline__ void surplus32_const(const CoordParam& cp, double (&d
                     else two_sum_into(hi[E], lo[E], part[E]);
                 }
             });
-            constexpr float wa = (float)R::r64[off + J * rl + rl - 1];
-            // exp-sum pair values are >= 0 and oscillatory ones <= 0
-            if constexpr (FAM == FAM_EXP) epsf = fmaf(wa, sv, epsf);
-            else if constexpr (FAM == FAM_OSC) epsf = fmaf(-wa, sv, epsf);
-            else epsf = fmaf(wa, fabsf(sv), epsf);
+            if constexpr (FAM == FAM_PEAK) {
+                constexpr float wa = (float)R::r64[off + J * rl + rl - 1];
+                epsf = fmaf(wa, fabsf(sv), epsf);
+            } else if constexpr (pair_base<RC>(L) + J == TableFacts<RULE, K>::max_pair()) {
+                constexpr float wt = (float)TableFacts<RULE, K>::total_wabs();
+                epsf = wt * fabsf(sv);
+            }
         });
     });
 #pragma unroll
@@ -442,7 +487,7 @@ __device__ __forceinline__ void surplus32e_const(const CoordParam& cp, double (&
 #pragma unroll
     for (int e = 0; e <= MAXK; ++e) del[e] = 0.0;
     float epsf = 0.0f;
-    const float c32 = (float)cp.p0;
+    const float c2s = (float)signed_c2<FAM>(cp.p0);
     static_for<2, K + 2>([&](auto Lc) {
         constexpr int L = decltype(Lc)::value;
         constexpr int off = rc_off64(RC, K, L), rl = rc_rec64(RC, K, L);
@@ -454,9 +499,10 @@ __device__ __forceinline__ void surplus32e_const(const CoordParam& cp, double (&
             if constexpr (FAM == FAM_PEAK) {
                 sv = (float)pair64<FAM_PEAK>(cp, y);
             } else {
-                constexpr float yh = (float)y;
-                constexpr float yl = (float)(y - (double)yh);
-                sv = pair32_series<FAM, yl != 0.0f>(c32, yh, yl);
+                constexpr double y2 = y * y;
+                constexpr float y2h = (float)y2;
+                constexpr float y2l = (float)(y2 - (double)y2h);
+                sv = pair32_z<FAM, y2l != 0.0f>(c2s, y2h, y2l);
             }
             const double sd = (double)sv;
             static_for<lo, hi + 1>([&](auto Ec) {
@@ -465,10 +511,13 @@ __device__ __forceinline__ void surplus32e_const(const CoordParam& cp, double (&
                 if constexpr (first_level<RC, K>(E) == L && J == 0) del[E] = w * sd;
                 else del[E] = fma(w, sd, del[E]);
             });
-            constexpr float wa = (float)R::r64[off + J * rl + rl - 1];
-            if constexpr (FAM == FAM_EXP) epsf = fmaf(wa, sv, epsf);
-            else if constexpr (FAM == FAM_OSC) epsf = fmaf(-wa, sv, epsf);
-            else epsf = fmaf(wa, fabsf(sv), epsf);
+            if constexpr (FAM == FAM_PEAK) {
+                constexpr float wa = (float)R::r64[off + J * rl + rl - 1];
+                epsf = fmaf(wa, fabsf(sv), epsf);
+            } else if constexpr (pair_base<RC>(L) + J == TableFacts<RULE, K>::max_pair()) {
+                constexpr float wt = (float)TableFacts<RULE, K>::total_wabs();
+                epsf = wt * fabsf(sv);
+            }
         });
     });
     eps += (double)epsf;
@@ -517,13 +566,22 @@ __device__ __forceinline__ void shfl_acc(Acc& o, const Acc& x, int mask, bool wa
 }
 
 // DPP moves of a double (two 32-bit halves).  Lanes whose source is outside
-// the pattern, or whose row is masked off, receive `fill`.
+// the pattern, or whose row is masked off, receive `fill`; with every row
+// enabled (ROW_MASK 0xF) `fill` must be 0.0, which bound_ctrl supplies.
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ double dpp_f64(double v, double fill)
 {
     const long long bv = __double_as_longlong(v), bf = __double_as_longlong(fill);
-    const int lo = __builtin_amdgcn_update_dpp((int)bf, (int)bv, CTRL, ROW_MASK, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp((int)(bf >> 32), (int)(bv >> 32), CTRL, ROW_MASK, 0xF, false);
+    int lo, hi;
+    if constexpr (ROW_MASK == 0xF) {
+        // every row enabled: with bound_ctrl set, a lane whose source lies
+        // outside its row reads 0 (the identity's bits), no fill copy needed
+        lo = __builtin_amdgcn_mov_dpp((int)bv, CTRL, 0xF, 0xF, true);
+        hi = __builtin_amdgcn_mov_dpp((int)(bv >> 32), CTRL, 0xF, 0xF, true);
+    } else {
+        lo = __builtin_amdgcn_update_dpp((int)bf, (int)bv, CTRL, ROW_MASK, 0xF, false);
+        hi = __builtin_amdgcn_update_dpp((int)(bf >> 32), (int)(bv >> 32), CTRL, ROW_MASK, 0xF, false);
+    }
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
