@@ -19,8 +19,14 @@ SOURCES = ["sg_fwd0.hip", "sg_fwd1.hip", "sg_fwd2.hip", "sg_adj0.hip", "sg_adj1.
 # Packed FP32 instructions are disabled for every device pass; contraction of
 # a*b+c into FMAs is off so that compensated (two-sum) sequences keep their
 # rounding; FMAs the kernels want are written explicitly.
+# Machine-level loop-invariant code motion is off: it would hoist the
+# hundreds of rule constants of the unrolled per-coordinate code out of the
+# coordinate and work-queue loops into scalar registers and spill them to
+# vector lanes (measured: 266 VGPRs instead of 100 for the K <= 6 kernel);
+# rematerialising a constant inside the loop is one scalar move.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-mllvm", "-disable-machine-licm",
              "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 
 

@@ -402,7 +402,7 @@ constexpr int row_length(int e)
 }
 
 // Terms per block of the blocked two-sum below.
-constexpr int kSumBlock = 4;
+constexpr int kSumBlock = 8;
 
 // hi + lo += b with the rounding error of the addition kept exactly (two-sum).
 __device__ __forceinline__ void two_sum_into(float& hi, float& lo, float b)
@@ -950,39 +950,34 @@ __device__ __forceinline__ void run_workgroup(const FwdWG* wg, const double* __r
     }
 }
 
-// Hardware-dispatched form: workgroup b runs descriptor b.
+// Forward kernel.  queue == nullptr: hardware dispatch, workgroup b runs
+// descriptor b.  Otherwise the persistent form: a grid sized to the
+// resident capacity pops descriptors (longest first) from a work queue,
+// queue[0] being the next index; every workgroup leaves once the queue is
+// exhausted, and the last one to leave (counted in queue[1]) resets both
+// counters, so the next launch on the stream starts from zero without a
+// memset (graph-safe).  Launches of one queue must not overlap.
 template <int PREC, int KMAXP>
 __global__ void __launch_bounds__(256)
-k_forward(const FwdWG* __restrict__ wgs, const double* __restrict__ pool64, const float* __restrict__ pool32,
+k_forward(const FwdWG* __restrict__ wgs, int nwg, unsigned int* __restrict__ queue,
+          const double* __restrict__ pool64, const float* __restrict__ pool32,
           const double* __restrict__ params, double* __restrict__ out, double* __restrict__ bound)
 {
     __shared__ double lds[4 * ACC_WORDS];
-    run_workgroup<PREC, KMAXP>(wgs + blockIdx.x, pool64, pool32, params, out, bound, lds);
-}
-
-// Persistent form: a grid sized to the resident capacity pops descriptors
-// (longest first) from a work queue, queue[0] being the next index.  Every
-// workgroup leaves once the queue is exhausted; the last one to leave
-// (counted in queue[1]) resets both counters, so the next launch on the
-// stream starts from zero without a memset (graph-safe).  Launches of one
-// queue must not overlap.
-template <int PREC, int KMAXP>
-__global__ void __launch_bounds__(256)
-k_forward_queue(const FwdWG* __restrict__ wgs, int nwg, unsigned int* __restrict__ queue,
-                const double* __restrict__ pool64, const float* __restrict__ pool32,
-                const double* __restrict__ params, double* __restrict__ out, double* __restrict__ bound)
-{
-    __shared__ double lds[4 * ACC_WORDS];
     __shared__ int next;
+    int idx = blockIdx.x;
     for (;;) {
-        if (threadIdx.x == 0) next = (int)atomicAdd(&queue[0], 1u);
-        __syncthreads();
-        const int idx = __builtin_amdgcn_readfirstlane(next);
-        __syncthreads();   // every thread has read `next` before it is overwritten
+        if (queue) {
+            if (threadIdx.x == 0) next = (int)atomicAdd(&queue[0], 1u);
+            __syncthreads();
+            idx = __builtin_amdgcn_readfirstlane(next);
+            __syncthreads();   // every thread has read `next` before it is overwritten
+        }
         if (idx >= nwg) break;
         run_workgroup<PREC, KMAXP>(wgs + idx, pool64, pool32, params, out, bound, lds);
+        if (!queue) break;
     }
-    if (threadIdx.x == 0) {
+    if (queue && threadIdx.x == 0) {
         __threadfence();
         if (atomicAdd(&queue[1], 1u) == gridDim.x - 1) {
             atomicExch(&queue[0], 0u);

@@ -9,28 +9,17 @@ int launch_forward_p0(int kmax, int nwg, const FwdWG* wgs, unsigned int* queue, 
                       const float* pool32, const double* params, double* out, double* bound, void* stream)
 {
     if (nwg <= 0) return 0;
-    const dim3 block(256);
+    const dim3 block(256), grid((unsigned)(queue ? qgrid : nwg));
     hipStream_t s = (hipStream_t)stream;
-    if (queue) {
-        const dim3 grid((unsigned)qgrid);
-        if (kmax <= 4)
-            hipLaunchKernelGGL((dev::k_forward_queue<0, 4>), grid, block, 0, s, wgs, nwg, queue, pool64, pool32, params,
-                               out, bound);
-        else if (kmax <= 6)
-            hipLaunchKernelGGL((dev::k_forward_queue<0, 6>), grid, block, 0, s, wgs, nwg, queue, pool64, pool32, params,
-                               out, bound);
-        else
-            hipLaunchKernelGGL((dev::k_forward_queue<0, 8>), grid, block, 0, s, wgs, nwg, queue, pool64, pool32, params,
-                               out, bound);
-        return (int)hipGetLastError();
-    }
-    const dim3 grid((unsigned)nwg);
     if (kmax <= 4)
-        hipLaunchKernelGGL((dev::k_forward<0, 4>), grid, block, 0, s, wgs, pool64, pool32, params, out, bound);
+        hipLaunchKernelGGL((dev::k_forward<0, 4>), grid, block, 0, s, wgs, nwg, queue, pool64, pool32, params, out,
+                           bound);
     else if (kmax <= 6)
-        hipLaunchKernelGGL((dev::k_forward<0, 6>), grid, block, 0, s, wgs, pool64, pool32, params, out, bound);
+        hipLaunchKernelGGL((dev::k_forward<0, 6>), grid, block, 0, s, wgs, nwg, queue, pool64, pool32, params, out,
+                           bound);
     else
-        hipLaunchKernelGGL((dev::k_forward<0, 8>), grid, block, 0, s, wgs, pool64, pool32, params, out, bound);
+        hipLaunchKernelGGL((dev::k_forward<0, 8>), grid, block, 0, s, wgs, nwg, queue, pool64, pool32, params, out,
+                           bound);
     return (int)hipGetLastError();
 }
 
@@ -38,9 +27,9 @@ int launch_forward_p0(int kmax, int nwg, const FwdWG* wgs, unsigned int* queue, 
 // once (resident capacity), 0 on error.
 int forward_capacity_p0(int kmax)
 {
-    const void* f = kmax <= 4   ? reinterpret_cast<const void*>(&dev::k_forward_queue<0, 4>)
-                    : kmax <= 6 ? reinterpret_cast<const void*>(&dev::k_forward_queue<0, 6>)
-                                : reinterpret_cast<const void*>(&dev::k_forward_queue<0, 8>);
+    const void* f = kmax <= 4   ? reinterpret_cast<const void*>(&dev::k_forward<0, 4>)
+                    : kmax <= 6 ? reinterpret_cast<const void*>(&dev::k_forward<0, 6>)
+                                : reinterpret_cast<const void*>(&dev::k_forward<0, 8>);
     int per_cu = 0, dev = 0, cus = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 256, 0) != hipSuccess) return 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
