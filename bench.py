@@ -179,7 +179,8 @@ def main():
         got = out.cpu().numpy()
         bnd = bound.cpu().numpy()
         info = plan.info()
-        log(f"  {precision}: sched cpl {info['coords_per_lane']} gmax {info['max_group']} persistent {info['persistent']} graph {info['graph']} "
+        log(f"  {precision}: sched cpl {info['coords_per_lane']} gmax {info['max_group']} cost_scaled "
+            f"{info['cost_scaled']} persistent {info['persistent']} graph {info['graph']} "
             f"grid {info['grid_blocks']}, kernel {kern_ms * 1e3:.2f} us, step {(t1 - t0) * 1e6 / steps:.2f} us")
         plan.close()
         return dict(ms_per_step=(t1 - t0) * 1e3 / steps, kernel_ms=float(kern_ms), got=got, bound=bnd, info=info)

@@ -203,12 +203,14 @@ sg_status sg_plan_execute_grad(sg_plan *plan, const double *params_dev, const do
  *                     products of the sweep (K(K-1)/2 multiply-adds and K
  *                     adds per unit, multiply-add counted as 2);
  *   block_threads, grid_blocks: the forward launch shape the plan uses;
- *   coords_per_lane, max_group: the forward schedule.  Each wave runs one
- *   class (K, rule, family) of integrands; an integrand of d coordinates
- *   gets the fewest lanes (a power of two, 4..64) that keep every lane at
- *   <= coords_per_lane coordinates, several integrands sharing a wave, or,
- *   when d > 64 * coords_per_lane, 64 lanes on up to max_group (1, 2, 4)
- *   waves of one workgroup;
+ *   coords_per_lane, max_group, cost_scaled: the forward schedule.  Each
+ *   wave runs one class (K, rule, family) of integrands; an integrand of d
+ *   coordinates gets the fewest lanes (a power of two, 4..64) that keep
+ *   every lane at <= c coordinates, several integrands sharing a wave, or,
+ *   when d > 64 * c, 64 lanes on up to max_group (1, 2, 4) waves of one
+ *   workgroup; c = coords_per_lane, or with cost_scaled = 1,
+ *   floor(coords_per_lane * (largest per-coordinate cost of the plan) /
+ *   (this class's per-coordinate cost)), capped at 64;
  *   graph: 1 if executions on a non-default stream replay a captured graph,
  *   0 if they launch directly;
  *   persistent: 1 if the forward launch is the persistent work-queue kernel
@@ -229,6 +231,8 @@ typedef struct {
     int32_t max_group;
     int32_t graph;
     int32_t persistent;
+    int32_t cost_scaled;
+    int32_t reserved;
 } sg_plan_info;
 
 sg_status sg_plan_get_info(const sg_plan *plan, sg_plan_info *info);
@@ -236,7 +240,8 @@ sg_status sg_plan_get_info(const sg_plan *plan, sg_plan_info *info);
 /* Time candidate schedules for this plan on `stream` with HIP events and
  * keep the fastest (stored in the context; later plans with the same shape
  * class reuse it): the integrand-to-wave schedule (coordinates per lane
- * 1, 2, 3, 4, 8, 16 times waves per integrand 1, 2, 4; see sg_plan_info),
+ * 1, 2, 3, 4, 8, 16, uniform or cost-scaled, times waves per integrand
+ * 1, 2, 4; see sg_plan_info),
  * hardware dispatch versus the persistent work-queue kernel and, on a
  * non-default stream, graph replay versus direct launch.  Runs the forward
  * launch repeatedly on params_dev/out_dev (their contents are overwritten).
@@ -245,11 +250,11 @@ sg_status sg_plan_autotune(sg_plan *plan, const double *params_dev, double *out_
 
 /* Set the forward schedule and launch mode directly (the knobs
  * sg_plan_autotune chooses; see sg_plan_info): coords_per_lane in 1..64,
- * max_group in {1, 2, 4}, persistent 0/1, graph 0 (direct launch) or 1
- * (graph replay on non-default streams).  Re-packs the plan's workgroups;
- * synchronous.  Errors: INVALID_ARGUMENT, OUT_OF_MEMORY, DEVICE. */
+ * max_group in {1, 2, 4}, cost_scaled 0/1, persistent 0/1, graph 0 (direct
+ * launch) or 1 (graph replay on non-default streams).  Re-packs the plan's
+ * workgroups; synchronous.  Errors: INVALID_ARGUMENT, OUT_OF_MEMORY, DEVICE. */
 sg_status sg_plan_set_schedule(sg_plan *plan, int32_t coords_per_lane, int32_t max_group,
-                               int32_t persistent, int32_t graph);
+                               int32_t cost_scaled, int32_t persistent, int32_t graph);
 
 /* Release a plan (NULL accepted). */
 sg_status sg_plan_destroy(sg_plan *plan);

@@ -31,6 +31,7 @@ struct FwdSched {
     int cpl = 2;
     int gmax = 4;
     bool persistent = false;   // work-queue kernel instead of one workgroup per descriptor
+    bool cost_scaled = false;  // cpl applies to the costliest class; cheaper classes get proportionally more
 };
 
 struct Records {
@@ -232,12 +233,6 @@ void fwd_shape(int d, int cpl, int gmax, int& lw, int& group)
     while ((1 << lw) < lanes) ++lw;
 }
 
-// Forward workgroups for a schedule.  Problems are bucketed by class
-// (K, rule, family) and shape; a bucket's single-wave problems (plan order,
-// so longest first) fill waves side by side, multi-wave problems get their
-// own waves.  Wave sets are then placed longest-first (estimated cost:
-// per-lane coordinates times the class's per-coordinate cost) into 4-wave
-// workgroups, first fit; the hardware dispatches workgroups in that order.
 FwdSeg seg_of(const ProbDev& p)
 {
     FwdSeg g;
@@ -247,13 +242,29 @@ FwdSeg seg_of(const ProbDev& p)
     return g;
 }
 
+// Forward workgroups for a schedule.  Problems are bucketed by class
+// (K, rule, family) and shape; a bucket's single-wave problems (plan order,
+// so longest first) fill waves side by side, multi-wave problems get their
+// own waves.  Wave sets are then placed longest-first (estimated cost:
+// per-lane coordinates times the class's per-coordinate cost) into 4-wave
+// workgroups, first fit; the hardware dispatches workgroups in that order.
+// With cost_scaled, the coordinates-per-lane target sc.cpl applies to the
+// costliest class and a class of per-coordinate cost c gets
+// floor(sc.cpl * cmax / c), so waves of cheap and costly classes take
+// similar time.
+
 std::vector<FwdWG> pack_forward(const std::vector<ProbDev>& probs, const std::vector<double>& unit_cost,
                                 const FwdSched& sc)
 {
+    double cmax = 0.0;
+    for (double c : unit_cost) cmax = std::max(cmax, c);
     std::map<std::tuple<int, int, int, int, int>, std::vector<int>> buckets;
     for (size_t k = 0; k < probs.size(); ++k) {
         int lw, group;
-        fwd_shape(probs[k].d, sc.cpl, sc.gmax, lw, group);
+        int cpl = sc.cpl;
+        if (sc.cost_scaled)
+            cpl = (int)std::max(1.0, std::min(64.0, std::floor((double)sc.cpl * cmax / unit_cost[k])));
+        fwd_shape(probs[k].d, cpl, sc.gmax, lw, group);
         buckets[std::make_tuple(probs[k].K, probs[k].rule, probs[k].family, lw, group)].push_back((int)k);
     }
     struct WaveSet {
@@ -639,13 +650,14 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
         p->sched = tk->second.first;
         p->use_graph = tk->second.second;
     }
-    if (const char* fs = std::getenv("SGMDI_SCHED")) {   // profiling override: "cpl,gmax[,persistent]"
-        int c = 0, g = 0, q = 0;
-        const int nf = std::sscanf(fs, "%d,%d,%d", &c, &g, &q);
+    if (const char* fs = std::getenv("SGMDI_SCHED")) {   // profiling override: "cpl,gmax[,persistent[,cost_scaled]]"
+        int c = 0, g = 0, q = 0, cs = 0;
+        const int nf = std::sscanf(fs, "%d,%d,%d,%d", &c, &g, &q, &cs);
         if (nf >= 2 && c >= 1 && c <= 64 && (g == 1 || g == 2 || g == 4)) {
             p->sched.cpl = c;
             p->sched.gmax = g;
-            p->sched.persistent = nf == 3 && q == 1;
+            p->sched.persistent = nf >= 3 && q == 1;
+            p->sched.cost_scaled = nf >= 4 && cs == 1;
         }
     }
     // reverse sweep: one problem per wave slot, cost-threshold schedule
@@ -711,6 +723,7 @@ static sg_status plan_repack(sg_plan* p, const FwdSched& sc)
     p->info.coords_per_lane = sc.cpl;
     p->info.max_group = sc.gmax;
     p->info.persistent = p->sched.persistent ? 1 : 0;
+    p->info.cost_scaled = sc.cost_scaled ? 1 : 0;
     return SG_OK;
 }
 
@@ -800,16 +813,17 @@ sg_status sg_plan_autotune(sg_plan* p, const double* params_dev, double* out_dev
     const int cpls[6] = {1, 2, 3, 4, 8, 16};
     const int gmaxs[3] = {1, 2, 4};
     sg_status st = SG_OK;
-    // candidates: coordinates per lane x waves per problem x (hardware
-    // dispatch | persistent work queue) x (graph replay | direct launch); the
-    // graph variant is only timed on a non-default stream
+    // candidates: coordinates per lane (uniform or cost-scaled) x waves per
+    // problem x (hardware dispatch | persistent work queue) x (graph replay |
+    // direct launch); the graph variant is only timed on a non-default stream
     for (int c : cpls) {
-        for (int gq = 0; gq < 6; ++gq) {
+        for (int gq = 0; gq < 12; ++gq) {
             const int gm = gmaxs[gq % 3];
             FwdSched sc;
             sc.cpl = c;
             sc.gmax = gm;
-            sc.persistent = gq >= 3;
+            sc.persistent = (gq / 3) % 2 == 1;
+            sc.cost_scaled = gq >= 6;
             if ((st = plan_repack(p, sc)) != SG_OK) break;
             destroy_graphs(p);
             for (int g = 0; g < (stream ? 2 : 1); ++g) {
@@ -840,16 +854,17 @@ sg_status sg_plan_autotune(sg_plan* p, const double* params_dev, double* out_dev
     return SG_OK;
 }
 
-sg_status sg_plan_set_schedule(sg_plan* p, int32_t coords_per_lane, int32_t max_group, int32_t persistent,
-                               int32_t graph)
+sg_status sg_plan_set_schedule(sg_plan* p, int32_t coords_per_lane, int32_t max_group, int32_t cost_scaled,
+                               int32_t persistent, int32_t graph)
 {
     if (!p) return SG_ERR_INVALID_ARGUMENT;
     if (coords_per_lane < 1 || coords_per_lane > 64 || (max_group != 1 && max_group != 2 && max_group != 4) ||
-        (persistent != 0 && persistent != 1) || (graph != 0 && graph != 1))
+        (cost_scaled != 0 && cost_scaled != 1) || (persistent != 0 && persistent != 1) || (graph != 0 && graph != 1))
         return fail(p->ctx, SG_ERR_INVALID_ARGUMENT, "schedule out of range");
     FwdSched sc;
     sc.cpl = coords_per_lane;
     sc.gmax = max_group;
+    sc.cost_scaled = cost_scaled == 1;
     sc.persistent = persistent == 1;
     destroy_graphs(p);
     sg_status st = plan_repack(p, sc);

@@ -41,7 +41,8 @@ class SgPlanInfo(ctypes.Structure):
                 ("pair_evals", ctypes.c_uint64), ("macs", ctypes.c_uint64),
                 ("merge_flops", ctypes.c_uint64), ("block_threads", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int32), ("coords_per_lane", ctypes.c_int32),
-                ("max_group", ctypes.c_int32), ("graph", ctypes.c_int32), ("persistent", ctypes.c_int32)]
+                ("max_group", ctypes.c_int32), ("graph", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("cost_scaled", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -77,7 +78,7 @@ def lib():
         "sg_plan_execute_grad": ([vp, vp, vp, vp, vp], i32),
         "sg_plan_get_info": ([vp, P(SgPlanInfo)], i32),
         "sg_plan_autotune": ([vp, vp, vp, vp], i32),
-        "sg_plan_set_schedule": ([vp, i32, i32, i32, i32], i32),
+        "sg_plan_set_schedule": ([vp, i32, i32, i32, i32, i32], i32),
         "sg_plan_destroy": ([vp], i32),
         "sg_integrate": ([vp, P(SgProblem), i32, vp, vp, vp, vp], i32),
     }
@@ -228,9 +229,10 @@ class Plan:
     def autotune(self, params, out, stream=None):
         _check(lib().sg_plan_autotune(self.handle, _ptr(params), _ptr(out), _stream_ptr(stream)), self.ctx.handle)
 
-    def set_schedule(self, coords_per_lane: int, max_group: int, graph: bool = False, persistent: bool = False):
-        _check(lib().sg_plan_set_schedule(self.handle, coords_per_lane, max_group, int(persistent), int(graph)),
-               self.ctx.handle)
+    def set_schedule(self, coords_per_lane: int, max_group: int, graph: bool = False, persistent: bool = False,
+                     cost_scaled: bool = False):
+        _check(lib().sg_plan_set_schedule(self.handle, coords_per_lane, max_group, int(cost_scaled), int(persistent),
+                                          int(graph)), self.ctx.handle)
 
     def close(self):
         if self.handle:

@@ -331,14 +331,15 @@ def test_set_schedule_validation_and_equivalence(api, orc):
     params = api.params_tensor(b)
     say("case set_schedule")
     plan = native.Plan(b.problems, "fp64")
-    for bad in ((0, 4, 0, 0), (65, 4, 0, 0), (2, 3, 0, 0), (2, 4, 2, 0), (2, 4, 0, 2)):
+    for bad in ((0, 4, 0, 0, 0), (65, 4, 0, 0, 0), (2, 3, 0, 0, 0), (2, 4, 2, 0, 0), (2, 4, 0, 2, 0), (2, 4, 0, 0, 2)):
         with pytest.raises(native.SgError) as e:
-            plan.set_schedule(bad[0], bad[1], graph=bad[2], persistent=bad[3])
+            plan.set_schedule(bad[0], bad[1], graph=bad[2], persistent=bad[3], cost_scaled=bad[4])
         assert e.value.status == 1
     ref = _fact_ref(orc, b)
-    for cpl, gm, pq in ((1, 1, 0), (2, 4, 0), (5, 2, 0), (64, 1, 0), (1, 4, 1), (3, 2, 1), (64, 4, 1)):
-        plan.set_schedule(cpl, gm, persistent=bool(pq))
-        assert plan.info()["persistent"] == pq
+    for cpl, gm, pq, cs in ((1, 1, 0, 0), (2, 4, 0, 1), (5, 2, 0, 0), (64, 1, 0, 1), (1, 4, 1, 0), (3, 2, 1, 1),
+                            (64, 4, 1, 0)):
+        plan.set_schedule(cpl, gm, persistent=bool(pq), cost_scaled=bool(cs))
+        assert plan.info()["persistent"] == pq and plan.info()["cost_scaled"] == cs
         for rep in range(3):   # the work queue must come back reset after every launch
             got = plan.execute(params).cpu().numpy()
             assert np.max(np.abs(got - ref) / _scale(b, ref)) <= 1e-12, (cpl, gm, pq, rep)
