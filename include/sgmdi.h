@@ -175,8 +175,10 @@ sg_status sg_plan_create(sg_context *ctx, const sg_problem *problems, int32_t n,
 
 /* Evaluate every integrand of the plan.  params_dev: the batch's float64
  * parameter array (device); out_dev: n float64 results in problem order
- * (device); bound_dev: NULL or n float64 a-priori bounds on |result - exact
- * Smolyak value| (device).  Launched directly by default; when the
+ * (device-accessible: device memory, or the device alias of pinned host
+ * memory from hipHostGetDevicePointer, which lets the host read results
+ * without a copy); bound_dev: NULL or n float64 a-priori bounds on
+ * |result - exact Smolyak value| (device-accessible).  Launched directly by default; when the
  * autotuner found graph replay faster (non-default streams only), the launch
  * is captured into a HIP graph on the first call with a given
  * (params, out, bound, stream) and replayed after.

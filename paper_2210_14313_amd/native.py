@@ -218,6 +218,13 @@ class Plan:
             _check(st, self.ctx.handle)
         return out
 
+    def execute_raw(self, params_ptr: int, out_ptr: int, bound_ptr: Optional[int] = None, stream=None):
+        """sg_plan_execute on raw device-accessible addresses (e.g. the device
+        alias of pinned host memory for the result)."""
+        st = self._exec(self.handle, params_ptr, out_ptr, bound_ptr, _stream_ptr(stream))
+        if st != 0:
+            _check(st, self.ctx.handle)
+
     def execute_grad(self, params, grad_out, grad_params=None, stream=None):
         import torch
         if grad_params is None:
