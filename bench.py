@@ -351,6 +351,36 @@ def main():
             plan.close()
         extras["adjoint_gradient_osc_d200_n256"] = adj
 
+        # literal point-by-point path on the d = 100, q = 105 workload
+        # (2.08e10 points per integrand) against the stored oracle values
+        log("point-by-point path ...")
+        golden = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_full_size.json")))["rows"]
+        pd100 = W.precision_d100()
+        pts = {}
+        for row in [r for r in golden if r["workload"] == "precision_d100"]:
+            one = pd100.subset([row["index"]])
+            p = one.problems[0]
+            pr = api.params_tensor(one, dev)
+            o = torch.empty(1, dtype=torch.float64, device=dev)
+            bd = torch.empty(1, dtype=torch.float64, device=dev)
+            native.integrate_points(p, pr, out=o, bound=bd, stream=s)     # warm
+            torch.cuda.synchronize()
+            reps = 5
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            for _ in range(reps):
+                native.integrate_points(p, pr, out=o, bound=bd, stream=s)
+            e1.record(s)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            npts = float(row["npoints"])
+            ref_pt = row["points_hi"] + row["points_lo"]
+            sc = max(abs(ref_pt), 1.0) if p.family == "oscillatory" else abs(ref_pt)
+            pts[p.family] = {"points": npts, "ms": ms, "points_per_s": npts / (ms / 1e3),
+                             "rel_err_vs_point_oracle": abs(o.item() - ref_pt) / sc,
+                             "stated_bound_rel": bd.item() / sc}
+        extras["points_path_precision_d100"] = pts
+
         # scaling series: the same recipe with more integrands per launch
         scal = {str(args.n): {"kernel_ms": main_run["kernel_ms"], "grid_blocks": info["grid_blocks"],
                               "points_per_s_kernel": eff / (main_run["kernel_ms"] / 1e3),

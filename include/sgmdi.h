@@ -261,6 +261,24 @@ sg_status sg_plan_set_schedule(sg_plan *plan, int32_t coords_per_lane, int32_t m
 /* Release a plan (NULL accepted). */
 sg_status sg_plan_destroy(sg_plan *plan);
 
+/* Literal point-by-point evaluation of (2.6)-(2.7) for one integrand: every
+ * multi-index of the window is unranked on the device (chunks of 64 ranks
+ * per wave), its tensor rule expanded over the points with the
+ * per-coordinate node contributions staged in LDS, and
+ * f(c) + sum coef(|l|) sum w (f(x) - f(c)) accumulated in double-double.
+ * Cost is proportional to n_d^q (sg_counts): the call fails with
+ * UNSUPPORTED when n_d^q > max_points (0 = no limit).  FP64 point values.
+ * params_dev: this integrand's parameters (param_offset ignored);
+ * out_dev: one float64 (device-accessible); bound_dev: NULL or one float64,
+ * an a-priori rounding bound 16 * 2^-53 * (S + |f(c)|), S the sum over
+ * points of |coef w| (|f(x) - f(c)| + |f(x)| |x - c|-weighted partial
+ * quantity) (the terms' cancellation makes this path far less accurate than
+ * the sweep at large d).  The context's workspace is reused by every call: calls on one
+ * context must not overlap in time.
+ * Errors: INVALID_ARGUMENT, UNSUPPORTED, OVERFLOW, OUT_OF_MEMORY, DEVICE. */
+sg_status sg_integrate_points(sg_context *ctx, const sg_problem *problem, const double *params_dev,
+                              double *out_dev, double *bound_dev, uint64_t max_points, void *stream);
+
 /* Plain, plan-free path: one integrand, one launch, no graph, no batching.
  * Same arguments as one problem of a plan (param_offset is ignored: params_dev
  * points at this integrand's parameters).  out_dev/bound_dev: one float64

@@ -25,6 +25,14 @@ struct PlainEntry {
     float* pool32 = nullptr;
 };
 
+// 1-D nodes (x - 1/2) and weights of the levels 1..K+1 of one rule, on the
+// device, for the point-by-point path.
+struct PointsTable {
+    double* y = nullptr;
+    double* w = nullptr;
+    int level_off[kMaxK + 3] = {};
+};
+
 // Forward schedule: target coordinates per lane and the most waves one
 // problem may span.
 struct FwdSched {
@@ -58,6 +66,9 @@ struct sg_context {
     std::map<std::string, std::pair<FwdSched, bool>> tuned;   // plan shape -> (schedule, graph)
     std::map<std::tuple<int, int, int, int>, PlainEntry> plain;
     std::map<std::pair<int, int>, uint64_t*> unrank_tables;
+    std::map<std::pair<int, int>, PointsTable> points_tables;   // (rule, K) -> 1-D nodes of levels 1..K+1
+    double* points_ws = nullptr;                                // per-wave partial sums of the point path
+    size_t points_ws_elems = 0;
     int live_plans = 0;
 };
 
@@ -441,6 +452,11 @@ sg_status sg_context_destroy(sg_context* ctx)
         hipFree(kv.second.pool32);
     }
     for (auto& kv : ctx->unrank_tables) hipFree(kv.second);
+    for (auto& kv : ctx->points_tables) {
+        hipFree(kv.second.y);
+        hipFree(kv.second.w);
+    }
+    hipFree(ctx->points_ws);
     delete ctx;
     return SG_OK;
 }
@@ -500,17 +516,11 @@ sg_status sg_unrank(int32_t d, int32_t q, uint64_t rank, int32_t* coords, int32_
     return unrank(d, q, rank, coords, levels, nnz);
 }
 
-sg_status sg_unrank_device(sg_context* ctx, int32_t d, int32_t q, uint64_t rank0, uint64_t count,
-                           int32_t max_nnz, int32_t* coords_dev, int32_t* levels_dev, int32_t* nnz_dev,
-                           void* stream)
+// Weak-composition counts W[n][parts] (n <= K, parts <= d) on the device
+// (cached per (d, q)) and the window's multi-index count.
+static sg_status window_table(sg_context* ctx, int d, int q, uint64_t** dW, uint64_t* n_multi)
 {
-    if (!ctx) return SG_ERR_INVALID_ARGUMENT;
-    if (d < 1 || q < d || !coords_dev || !levels_dev || !nnz_dev)
-        return fail(ctx, SG_ERR_INVALID_ARGUMENT, "sg_unrank_device: bad d/q or NULL output");
     const int K = q - d;
-    if (K > 60) return fail(ctx, SG_ERR_UNSUPPORTED, "K > 60");
-    if (max_nnz < std::max(1, K)) return fail(ctx, SG_ERR_INVALID_ARGUMENT, "max_nnz < K");
-    // table of weak-composition counts W[n][parts], n <= K, parts <= d
     std::vector<uint64_t> W((size_t)(K + 1) * (d + 1), 0);
     for (int nn = 0; nn <= K; ++nn)
         for (int parts = 0; parts <= d; ++parts) {
@@ -526,20 +536,117 @@ sg_status sg_unrank_device(sg_context* ctx, int32_t d, int32_t q, uint64_t rank0
         if (m > UINT64_MAX - c) return fail(ctx, SG_ERR_OVERFLOW, "window not countable in 64 bits");
         m += c;
     }
-    if (count == 0) return SG_OK;
-    if (rank0 >= m || count > m - rank0) return fail(ctx, SG_ERR_INVALID_ARGUMENT, "rank range beyond the window");
+    *n_multi = m;
     auto key = std::make_pair(d, q);
-    uint64_t* dW = nullptr;
     auto it = ctx->unrank_tables.find(key);
     if (it == ctx->unrank_tables.end()) {
-        sg_status st = upload(ctx, &dW, W.data(), W.size());
+        uint64_t* p = nullptr;
+        sg_status st = upload(ctx, &p, W.data(), W.size());
         if (st != SG_OK) return st;
-        ctx->unrank_tables[key] = dW;
+        ctx->unrank_tables[key] = p;
+        *dW = p;
     } else {
-        dW = it->second;
+        *dW = it->second;
     }
+    return SG_OK;
+}
+
+sg_status sg_unrank_device(sg_context* ctx, int32_t d, int32_t q, uint64_t rank0, uint64_t count,
+                           int32_t max_nnz, int32_t* coords_dev, int32_t* levels_dev, int32_t* nnz_dev,
+                           void* stream)
+{
+    if (!ctx) return SG_ERR_INVALID_ARGUMENT;
+    if (d < 1 || q < d || !coords_dev || !levels_dev || !nnz_dev)
+        return fail(ctx, SG_ERR_INVALID_ARGUMENT, "sg_unrank_device: bad d/q or NULL output");
+    const int K = q - d;
+    if (K > 60) return fail(ctx, SG_ERR_UNSUPPORTED, "K > 60");
+    if (max_nnz < std::max(1, K)) return fail(ctx, SG_ERR_INVALID_ARGUMENT, "max_nnz < K");
+    uint64_t* dW = nullptr;
+    uint64_t m = 0;
+    sg_status st = window_table(ctx, d, q, &dW, &m);
+    if (st != SG_OK) return st;
+    if (count == 0) return SG_OK;
+    if (rank0 >= m || count > m - rank0) return fail(ctx, SG_ERR_INVALID_ARGUMENT, "rank range beyond the window");
     const int rc = launch_unrank(d, q, rank0, count, max_nnz, dW, K + 1, coords_dev, levels_dev, nnz_dev, stream);
     if (rc != 0) return hip_fail(ctx, (hipError_t)rc, "unrank launch");
+    return SG_OK;
+}
+
+sg_status sg_integrate_points(sg_context* ctx, const sg_problem* problem, const double* params_dev,
+                              double* out_dev, double* bound_dev, uint64_t max_points, void* stream)
+{
+    if (!ctx) return SG_ERR_INVALID_ARGUMENT;
+    if (!problem || !params_dev || !out_dev) return fail(ctx, SG_ERR_INVALID_ARGUMENT, "NULL argument");
+    sg_status st = validate_problem(ctx, *problem, 0);
+    if (st != SG_OK) return st;
+    const int d = problem->d, q = problem->q, K = q - d, rule = problem->rule;
+    uint64_t npts = 0;
+    st = counts(d, q, rule, nullptr, &npts, nullptr);
+    if (st != SG_OK) return fail(ctx, st, "point count not representable in 64 bits");
+    if (max_points && npts > max_points)
+        return fail(ctx, SG_ERR_UNSUPPORTED, "more points than max_points (" + std::to_string(npts) + ")");
+    uint64_t* dW = nullptr;
+    uint64_t n_multi = 0;
+    if ((st = window_table(ctx, d, q, &dW, &n_multi)) != SG_OK) return st;
+    // 1-D nodes of levels 1..K+1
+    auto key = std::make_pair(rule, K);
+    auto it = ctx->points_tables.find(key);
+    if (it == ctx->points_tables.end()) {
+        PointsTable pt;
+        std::vector<double> ys, ws;
+        std::vector<long double> x, w;
+        pt.level_off[0] = pt.level_off[1] = 0;
+        for (int l = 1; l <= K + 1; ++l) {
+            if (!rule_nodes(rule, l, x, w)) return fail(ctx, SG_ERR_UNSUPPORTED, "rule construction failed");
+            for (size_t j = 0; j < x.size(); ++j) {
+                ys.push_back((double)(x[j] - 0.5L));
+                ws.push_back((double)w[j]);
+            }
+            pt.level_off[l + 1] = (int)ys.size();
+        }
+        for (int l = K + 2; l < kMaxK + 3; ++l) pt.level_off[l] = (int)ys.size();
+        if ((st = upload(ctx, &pt.y, ys.data(), ys.size())) != SG_OK) return st;
+        if ((st = upload(ctx, &pt.w, ws.data(), ws.size())) != SG_OK) return st;
+        it = ctx->points_tables.emplace(key, pt).first;
+    }
+    // grid: every wave gets at least one chunk of 64 ranks; at most 2048 workgroups
+    const uint64_t nchunks = (n_multi + 63) / 64;
+    const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(2048, (nchunks + 3) / 4));
+    const size_t ws_need = (size_t)grid * 4 * 3;
+    if (ws_need > ctx->points_ws_elems) {
+        hipFree(ctx->points_ws);
+        ctx->points_ws = nullptr;
+        ctx->points_ws_elems = 0;
+        hipError_t e = hipMalloc((void**)&ctx->points_ws, ws_need * sizeof(double));
+        if (e != hipSuccess) return fail(ctx, SG_ERR_OUT_OF_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(e));
+        ctx->points_ws_elems = ws_need;
+    }
+    PointsLaunch L;
+    L.d = d;
+    L.K = K;
+    L.e0 = std::max(0, K - d + 1);
+    L.grid = grid;
+    L.n_multi = n_multi;
+    L.W = dW;
+    L.node_y = it->second.y;
+    L.node_w = it->second.w;
+    for (int i = 0; i < kMaxK + 3; ++i) L.level_off[i] = it->second.level_off[i];
+    for (int e = 0; e <= kMaxK; ++e) {
+        // (-1)^(K-e) C(d-1, K-e), exact in long double up to 2^64, rounded once
+        long double c = 0.0L;
+        if (e <= K && K - e <= d - 1) {
+            c = 1.0L;
+            for (int j = 1; j <= K - e; ++j) c = c * (long double)(d - 1 - (K - e) + j) / (long double)j;
+            if ((K - e) % 2) c = -c;
+        }
+        L.coef[e] = (double)c;
+    }
+    L.params = params_dev;
+    L.partial = ctx->points_ws;
+    L.out = out_dev;
+    L.bound = bound_dev;
+    const int rc = launch_points(problem->family, L, stream);
+    if (rc != 0) return hip_fail(ctx, (hipError_t)rc, "point path launch");
     return SG_OK;
 }
 

@@ -161,6 +161,22 @@ int launch_unrank(int d, int q, uint64_t rank0, uint64_t count, int max_nnz,
                   int32_t* nnz, void* stream);
 const char* device_error_string(int code);
 
+// Literal point-by-point path (sg_points.hip).
+struct PointsLaunch {
+    int d, K, e0, grid;
+    uint64_t n_multi;
+    const uint64_t* W;             // weak-composition counts, (K+1) rows of d+1 (device)
+    const double* node_y;          // nodes - 1/2 of levels 1..K+1, concatenated (device)
+    const double* node_w;          // their weights (device)
+    int level_off[kMaxK + 3];      // level l occupies [level_off[l], level_off[l+1])
+    double coef[kMaxK + 1];        // combination coefficient by excess
+    const double* params;          // the integrand's parameters (device)
+    double* partial;               // 3 * 4 * grid doubles of workspace (device)
+    double* out;                   // one double (device-accessible)
+    double* bound;                 // NULL or one double (device-accessible)
+};
+int launch_points(int family, const PointsLaunch& L, void* stream);
+
 // Record tables (FP64 and FP32 pools) of one (rule, K) in the static layout.
 bool build_records(const DeltaTable& t, std::vector<double>& rec64, std::vector<float>& rec32,
                    std::string& err);

@@ -50,7 +50,7 @@ _lib = None
 EXPORTS = ["sg_context_create", "sg_context_destroy", "sg_status_string", "sg_last_error", "sg_counts",
            "sg_rule_table", "sg_coefficient", "sg_unrank", "sg_unrank_device", "sg_plan_create",
            "sg_plan_execute", "sg_plan_execute_grad", "sg_plan_get_info", "sg_plan_autotune",
-           "sg_plan_set_schedule", "sg_plan_destroy", "sg_integrate"]
+           "sg_plan_set_schedule", "sg_plan_destroy", "sg_integrate", "sg_integrate_points"]
 
 
 def lib():
@@ -81,6 +81,7 @@ def lib():
         "sg_plan_set_schedule": ([vp, i32, i32, i32, i32, i32], i32),
         "sg_plan_destroy": ([vp], i32),
         "sg_integrate": ([vp, P(SgProblem), i32, vp, vp, vp, vp], i32),
+        "sg_integrate_points": ([vp, P(SgProblem), vp, vp, vp, u64, vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -263,6 +264,19 @@ def integrate_one(problem, params, precision: str = "fp64", out=None, bound=None
         out = torch.empty(1, dtype=torch.float64, device=params.device)
     _check(lib().sg_integrate(ctx.handle, ctypes.byref(pr), PRECISIONS[precision], _ptr(params), _ptr(out),
                               _ptr(bound), _stream_ptr(stream)), ctx.handle)
+    return out
+
+
+def integrate_points(problem, params, out=None, bound=None, max_points: int = 0, stream=None,
+                     ctx: Optional[Context] = None):
+    """Literal point-by-point path (sg_integrate_points): one integrand, FP64."""
+    import torch
+    ctx = ctx or default_context()
+    pr = SgProblem(problem.d, problem.q, RULES[problem.rule], FAMILIES[problem.family], 0)
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=params.device)
+    _check(lib().sg_integrate_points(ctx.handle, ctypes.byref(pr), _ptr(params), _ptr(out), _ptr(bound),
+                                     max_points, _stream_ptr(stream)), ctx.handle)
     return out
 
 

@@ -1,0 +1,141 @@
+"""GPU parity of the literal point-by-point path (sg_integrate_points)
+against the CPU oracle's point-by-point sum (2.6)-(2.7), against the stored
+full-size oracle values, and against the factorised GPU sweep.
+
+Tolerance: both sides evaluate the same sum, the GPU in FP64 with
+double-double accumulation, the oracle in x87 extended precision with
+Neumaier accumulation.  Each GPU result must lie within the rounding bound
+the library states for it plus the oracle's own rounding scale
+(8 * 2^-64 * (A + |f(c)|)), and within 1e-12 relative (oscillatory: to
+max(|Q|, 1)) wherever that bound is below it; the terms' cancellation puts
+the bound far above 1e-12 at d = 100.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2210_14313_amd import native
+    native.lib()
+    return torch
+
+
+def _scale(family, ref):
+    return max(abs(ref), 1.0) if family == "oscillatory" else abs(ref)
+
+
+def _points(batch, i, max_points=0, with_bound=False):
+    import torch
+    from paper_2210_14313_amd import native
+    p = batch.problems[i]
+    prm = torch.as_tensor(batch.param_slice(i), dtype=torch.float64).cuda()
+    bound = torch.empty(1, dtype=torch.float64, device="cuda") if with_bound else None
+    out = native.integrate_points(p, prm, bound=bound, max_points=max_points)
+    torch.cuda.synchronize()
+    return (out.item(), bound.item()) if with_bound else out.item()
+
+
+def _check(got, bnd, ref, family, oracle_scale):
+    err = abs(got - ref)
+    tol_oracle = 8 * 2.0 ** -64 * oracle_scale
+    assert err <= bnd + tol_oracle, (got, ref, err, bnd)
+    if bnd + tol_oracle <= 1e-12 * _scale(family, ref):
+        assert err <= 1e-12 * _scale(family, ref), (got, ref, err)
+
+
+@pytest.mark.parametrize("seed", [3, 4, 5])
+def test_points_small_random_vs_point_oracle(torch_dev, orc, seed):
+    from paper_2210_14313_amd import workloads as W
+    b = W.random_small(seed, 40, d_range=(1, 12), k_range=(0, 5))
+    say("case points small random seed", seed)
+    for i, p in enumerate(b.problems):
+        r = orc.smolyak_points(p.d, p.q, p.rule, p.family, b.param_slice(i))
+        got, bnd = _points(b, i, with_bound=True)
+        _check(got, bnd, r["q"], p.family, r["A"] + abs(r["fc"]))
+
+
+@pytest.mark.parametrize("d,K,rule,family", [(1, 8, "cc", "exp_sum"), (2, 8, "gl", "oscillatory"),
+                                             (7, 0, "tr", "product_peak"), (30, 3, "cc", "product_peak"),
+                                             (65, 2, "gl_paper", "oscillatory"), (3, 8, "tr", "product_peak"),
+                                             (200, 2, "cc", "exp_sum")])
+def test_points_edges_vs_point_oracle(torch_dev, orc, d, K, rule, family):
+    from paper_2210_14313_amd import workloads as W
+    rng = np.random.default_rng(1000 * d + K)
+    b = W.single(d, d + K, rule, family, W.draw_params(rng, family, d))
+    say("case points edge", d, K, rule, family)
+    r = orc.smolyak_points(d, d + K, rule, family, b.param_slice(0))
+    got, bnd = _points(b, 0, with_bound=True)
+    _check(got, bnd, r["q"], family, r["A"] + abs(r["fc"]))
+
+
+def test_points_plain_exp_d10(torch_dev, orc):
+    from paper_2210_14313_amd import workloads as W
+    b = W.plain_exp_d10()
+    say("case points plain_exp_d10")
+    r = orc.smolyak_points(10, 14, "cc", "exp_sum", b.param_slice(0))
+    got, bnd = _points(b, 0, with_bound=True)
+    _check(got, bnd, r["q"], "exp_sum", r["A"] + abs(r["fc"]))
+    assert abs(got - r["q"]) <= 1e-12 * abs(r["q"])
+
+
+def _golden_rows():
+    path = os.path.join(GOLDEN, "oracle_full_size.json")
+    if not os.path.exists(path):
+        return []
+    return [r for r in json.load(open(path))["rows"] if r["workload"] == "precision_d100"]
+
+
+@pytest.mark.parametrize("row", _golden_rows(), ids=lambda r: f"{r['workload']}-{r['index']}")
+def test_points_full_size_against_stored_point_oracle(torch_dev, row):
+    # d = 100, q = 105, Clenshaw-Curtis: 2.08e10 points
+    from paper_2210_14313_amd import workloads as W
+    b = W.STANDARD[row["workload"]]().subset([row["index"]])
+    p = b.problems[0]
+    say("case points full size", row["workload"], row["index"], p.family)
+    ref = row["points_hi"] + row["points_lo"]
+    got, bnd = _points(b, 0, with_bound=True)
+    say("  got", got, "oracle", ref, "bound", bnd)
+    _check(got, bnd, ref, p.family, row["points_A"] + abs(row["fc"]))
+
+
+def test_points_agree_with_factorised_sweep(torch_dev):
+    import torch
+    from paper_2210_14313_amd import api, native, workloads as W
+    b = W.random_small(21, 24, d_range=(20, 150), k_range=(1, 4))
+    say("case points vs sweep")
+    vals, vb = api.integrate(b, "fp64", with_bound=True)
+    vals, vb = vals.cpu().numpy(), vb.cpu().numpy()
+    for i, p in enumerate(b.problems):
+        got, bnd = _points(b, i, with_bound=True)
+        assert abs(got - vals[i]) <= bnd + vb[i], (i, p, got, vals[i], bnd, vb[i])
+
+
+def test_points_deterministic_and_limits(torch_dev):
+    import torch
+    from paper_2210_14313_amd import native, workloads as W
+    b = W.random_small(8, 3, d_range=(40, 60), k_range=(3, 4))
+    say("case points determinism")
+    for i in range(len(b)):
+        assert _points(b, i) == _points(b, i)
+    p = b.problems[0]
+    npts = native.counts(p.d, p.q, p.rule)[1]
+    with pytest.raises(native.SgError) as e:
+        _points(b, 0, max_points=npts - 1)
+    assert e.value.status == 2
+    assert _points(b, 0, max_points=npts) == _points(b, 0)
