@@ -32,7 +32,7 @@ LIB_PATH = os.path.join(_HERE, "liboracle.so")
 SRC_PATH = os.path.join(_HERE, "sg_oracle.c")
 
 RULE_IDS = {"tr": 1, "cc": 2, "gl": 4, "gl_paper": 5}
-FAMILY_IDS = {"exp_sum": 0, "oscillatory": 1, "product_peak": 2, "monomial": 3}
+FAMILY_IDS = {"exp_sum": 0, "oscillatory": 1, "product_peak": 2, "monomial": 3, "corner_peak": 4}
 
 
 def build(force: bool = True) -> str:

@@ -40,8 +40,32 @@ def exact_product_peak(b, u):
     return r
 
 
+def exact_corner_peak(a):
+    """Integral of (1 + sum a_i x_i)^-(d+1) over [0,1]^d for a_i > 0: by d
+    successive integrations, (1 / (d! prod a_i)) sum over subsets S of
+    (-1)^|S| / (1 + sum_{i in S} a_i).  The alternating sum cancels heavily,
+    so it is evaluated at the working precision raised with d."""
+    a = [float(x) for x in np.asarray(a, dtype=np.float64)]
+    d = len(a)
+    with mp.workdps(40 + 4 * d):
+        am = [mp.mpf(x) for x in a]
+        tot = mp.mpf(0)
+        for mask in range(1 << d):
+            s = mp.mpf(1)
+            bits = 0
+            for i in range(d):
+                if mask >> i & 1:
+                    s += am[i]
+                    bits += 1
+            tot += (-1) ** bits / s
+        r = tot / (mp.factorial(d) * mp.fprod(am))
+        return +r
+
+
 def exact(family: str, d: int, params):
     params = np.asarray(params, dtype=np.float64)
+    if family == "corner_peak":
+        return exact_corner_peak(params[:d])
     if family == "exp_sum":
         return exact_exp_sum(params[:d])
     if family == "oscillatory":

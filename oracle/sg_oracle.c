@@ -48,7 +48,7 @@ typedef __float128 f128;
 typedef long double fld;
 
 enum { OR_TR = 1, OR_CC = 2, OR_GL = 4, OR_GL_PAPER = 5 };
-enum { OR_EXP = 0, OR_OSC = 1, OR_PEAK = 2, OR_MONO = 3 };
+enum { OR_EXP = 0, OR_OSC = 1, OR_PEAK = 2, OR_MONO = 3, OR_CORNER = 4 };
 
 #define OR_MAX_LEVEL 16
 #define OR_MAX_NODES 40000
@@ -318,6 +318,14 @@ static fld point_value(const pt_problem *P, int m, const int *coords, const fld 
         /* cos(A + t) - cos(A) = -2 sin(t/2) sin(A + t/2) */
         return -2.0L * sinl(0.5L * t) * sinl(P->theta_c + 0.5L * t);
     }
+    if (P->family == OR_CORNER) {
+        /* f(x) = (1 + sum a_i x_i)^-(d+1), a ridge function of s = t_c + t */
+        fld t = 0;
+        for (int k = 0; k < m; ++k) t += (fld)p[coords[k]] * (xs[k] - 0.5L);
+        if (!P->centred) return powl(1.0L + P->theta_c + t, -(fld)(d + 1));
+        /* f(x) - f(c) = f(c) ((1 + t / (1 + t_c))^-(d+1) - 1) */
+        return P->fc * expm1l(-(fld)(d + 1) * log1pl(t / (1.0L + P->theta_c)));
+    }
     if (P->family == OR_MONO) {
         /* every coordinate: inactive ones sit at the level-1 node 1/2 */
         const double s = p[d];
@@ -406,7 +414,8 @@ static void *pt_thread(void *arg)
 /*
  * Point-by-point Smolyak sum (2.6)-(2.7).
  *   rule: 1 trapezoidal, 2 Clenshaw-Curtis, 4 Gauss-Legendre (2l-1), 5 Gauss-Legendre (l)
- *   family: 0 exp-sum (params c[d]), 1 oscillatory (w, a[d]), 2 product-peak (b[d], u[d])
+ *   family: 0 exp-sum (params c[d]), 1 oscillatory (w, a[d]), 2 product-peak (b[d], u[d]),
+ *           4 corner-peak (a[d] >= 0: f = (1 + sum a_i x_i)^-(d+1))
  *   centred: 1 -> sum f(x) - f(c) and add f(c) once (uses that the weights of
  *            the whole rule sum to 1); 0 -> sum f(x) itself.
  * out[0], out[1]: Q as a double-double (hi, lo)
@@ -454,6 +463,11 @@ int or_smolyak_points(int d, int q, int rule, int family, const double *params,
             v /= 1.0L / (bi * bi) + (0.5L - ui) * (0.5L - ui);
         }
         P.fc = v;
+    } else if (family == OR_CORNER) {
+        fld t = 0;
+        for (int i = 0; i < d; ++i) t += (fld)params[i] * 0.5L;
+        P.theta_c = t;
+        P.fc = powl(1.0L + t, -(fld)(d + 1));
     } else if (family == OR_MONO) {
         P.centred = centred = 0;
         P.fc = 0;

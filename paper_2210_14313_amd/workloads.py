@@ -33,7 +33,10 @@ from typing import List, Sequence
 import numpy as np
 
 RULES = ("tr", "cc", "gl", "gl_paper")
+#: families the factorised sweep handles (they factor per coordinate)
 FAMILIES = ("exp_sum", "oscillatory", "product_peak")
+#: families only the point-by-point path handles (ridge functions that do not factor)
+POINT_ONLY_FAMILIES = ("corner_peak",)
 
 #: seeds used for the five standard workloads (workload k uses SEED_BASE + k)
 SEED_BASE = 14313
@@ -47,6 +50,8 @@ def n_params(family: str, d: int) -> int:
         return d + 1
     if family == "product_peak":
         return 2 * d
+    if family == "corner_peak":
+        return d
     raise ValueError(f"unknown family {family!r}")
 
 
@@ -99,7 +104,7 @@ class _Builder:
         self.off = 0
 
     def add(self, d: int, q: int, rule: str, family: str, params: np.ndarray):
-        assert rule in RULES and family in FAMILIES
+        assert rule in RULES and (family in FAMILIES or family in POINT_ONLY_FAMILIES)
         params = np.asarray(params, dtype=np.float64).ravel()
         assert params.size == n_params(family, d)
         self.problems.append(Problem(int(d), int(q), rule, family, self.off))
@@ -117,7 +122,7 @@ def draw_params(rng: np.random.Generator, family: str, d: int,
 
     exp_sum: c_i ~ U(0,1) * exp_scale.  oscillatory: w ~ U(0,1),
     a_i ~ U(0,1) * osc_scale / d.  product_peak: b_i ~ U(0.5, 2),
-    u_i ~ U(0, 1).
+    u_i ~ U(0, 1).  corner_peak: a_i ~ U(0,1), normalised to sum 1.
     """
     if family == "exp_sum":
         return rng.uniform(0.0, 1.0, d) * exp_scale
@@ -129,6 +134,10 @@ def draw_params(rng: np.random.Generator, family: str, d: int,
         b = rng.uniform(0.5, 2.0, d)
         u = rng.uniform(0.0, 1.0, d)
         return np.concatenate([b, u])
+    if family == "corner_peak":
+        # a_i ~ U(0,1) scaled so that sum a_i = 1 (a mild corner)
+        a = rng.uniform(0.0, 1.0, d)
+        return a / a.sum()
     raise ValueError(family)
 
 

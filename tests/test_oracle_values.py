@@ -54,6 +54,8 @@ def _f(family, params, X):
         return np.exp(X @ params[:d])
     if family == "oscillatory":
         return np.cos(2 * np.pi * params[0] + X @ params[1:1 + d])
+    if family == "corner_peak":
+        return (1.0 + X @ params[:d]) ** (-(d + 1))
     b, u = params[:d], params[d:2 * d]
     return np.prod(1.0 / (b ** -2 + (X - u) ** 2), axis=-1)
 
@@ -76,7 +78,8 @@ def brute_smolyak(d, q, rule, family, params):
 
 
 SMALL = [(d, q, r, f) for (d, q) in [(1, 3), (2, 3), (2, 5), (3, 5), (3, 6), (4, 6)]
-         for r in ("tr", "cc", "gl", "gl_paper") for f in ("exp_sum", "oscillatory", "product_peak")]
+         for r in ("tr", "cc", "gl", "gl_paper")
+         for f in ("exp_sum", "oscillatory", "product_peak", "corner_peak")]
 
 
 @pytest.mark.parametrize("d,q,rule,family", SMALL)
@@ -114,12 +117,41 @@ def test_points_match_factorised_medium(orc, d, K, rule, family):
 
 
 def test_centred_and_uncentred_agree(orc):
-    for fam in ("exp_sum", "oscillatory", "product_peak"):
+    for fam in ("exp_sum", "oscillatory", "product_peak", "corner_peak"):
         rng = np.random.default_rng(5)
         params = W.draw_params(rng, fam, 6)
         a = orc.smolyak_points(6, 10, "cc", fam, params, centred=True)["q"]
         b = orc.smolyak_points(6, 10, "cc", fam, params, centred=False)["q"]
         assert abs(a - b) < 1e-14 * abs(a)
+
+
+# ------------------------------------------------------------ corner peak
+def test_corner_peak_closed_form_independent():
+    # the subset formula against d = 1 by hand and d = 2, 3 by quadrature of
+    # the integral with its last coordinate integrated by hand:
+    # int_0^1 (s + a x)^-(d+1) dx = (s^-d - (s + a)^-d) / (d a)
+    a1 = 0.7
+    assert abs(float(R.exact_corner_peak([a1])) - 1.0 / (1.0 + a1)) < 1e-15
+    for a in ([0.3, 0.9], [0.2, 0.5, 0.4]):
+        d = len(a)
+        al = a[-1]
+
+        def f(*x):
+            s = 1 + sum(ai * xi for ai, xi in zip(a[:-1], x))
+            return (s ** -d - (s + al) ** -d) / (d * al)
+        with mp.workdps(20):
+            ref = mp.quad(f, *([[0, 1]] * (d - 1)))
+        assert abs(float(R.exact_corner_peak(a)) - float(ref)) < 1e-14 * float(ref)
+
+
+@pytest.mark.parametrize("d,q", [(1, 12), (2, 12), (3, 11)])
+def test_corner_peak_converges_to_closed_form(orc, d, q):
+    # an analytic integrand: high-level Gauss-Legendre Smolyak sums converge
+    rng = np.random.default_rng(77 + d)
+    a = W.draw_params(rng, "corner_peak", d)
+    got = orc.smolyak_points(d, q, "gl", "corner_peak", a)["q"]
+    ex = float(R.exact_corner_peak(a))
+    assert abs(got - ex) <= 1e-12 * ex, (got, ex)
 
 
 def test_rule_integrates_one_exactly(orc):
