@@ -64,12 +64,17 @@ typedef enum {
  *   EXP_SUM       f(x) = exp(sum_i c_i x_i)                      params c[d]
  *   OSCILLATORY   f(x) = cos(2 pi w + sum_i a_i x_i)              params w, a[d]
  *   PRODUCT_PEAK  f(x) = prod_i 1/(b_i^-2 + (x_i - u_i)^2)        params b[d], u[d]
+ *   CORNER_PEAK   f(x) = (1 + sum_i a_i x_i)^-(d+1), a_i >= 0     params a[d]
  * (PRODUCT_PEAK is the integrand of (4.4)/(5.2) with free widths/centres;
- * EXP_SUM generalises (4.5)/(5.1); OSCILLATORY generalises Table 5.7's.) */
+ * EXP_SUM generalises (4.5)/(5.1); OSCILLATORY generalises Table 5.7's.
+ * CORNER_PEAK is a ridge function that does not factor per coordinate:
+ * only the point-by-point path sg_integrate_points evaluates it; plans and
+ * sg_integrate reject it with UNSUPPORTED.) */
 typedef enum {
     SG_FAMILY_EXP_SUM = 0,
     SG_FAMILY_OSCILLATORY = 1,
-    SG_FAMILY_PRODUCT_PEAK = 2
+    SG_FAMILY_PRODUCT_PEAK = 2,
+    SG_FAMILY_CORNER_PEAK = 3
 } sg_family;
 
 /* Arithmetic of the per-coordinate work (node values and within-rule sums).

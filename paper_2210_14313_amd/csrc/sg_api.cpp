@@ -119,11 +119,18 @@ sg_status hip_fail(sg_context* ctx, hipError_t e, const char* what)
 
 bool family_ok(int f)
 {
-    return f == SG_FAMILY_EXP_SUM || f == SG_FAMILY_OSCILLATORY || f == SG_FAMILY_PRODUCT_PEAK;
+    return f == SG_FAMILY_EXP_SUM || f == SG_FAMILY_OSCILLATORY || f == SG_FAMILY_PRODUCT_PEAK ||
+           f == SG_FAMILY_CORNER_PEAK;
 }
 
-sg_status validate_problem(sg_context* ctx, const sg_problem& p, int idx)
+sg_status validate_problem(sg_context* ctx, const sg_problem& p, int idx, bool point_path = false)
 {
+    if (!point_path && p.family == SG_FAMILY_CORNER_PEAK) {
+        char buf[160];
+        snprintf(buf, sizeof buf,
+                 "problem %d: the corner-peak family does not factor per coordinate; use sg_integrate_points", idx);
+        return fail(ctx, SG_ERR_UNSUPPORTED, buf);
+    }
     char buf[160];
     if (p.d < 1 || p.q < p.d || !rule_is_known(p.rule) || !family_ok(p.family) || p.param_offset < 0) {
         snprintf(buf, sizeof buf, "problem %d: invalid (d=%d q=%d rule=%d family=%d offset=%lld)", idx,
@@ -577,7 +584,7 @@ sg_status sg_integrate_points(sg_context* ctx, const sg_problem* problem, const 
 {
     if (!ctx) return SG_ERR_INVALID_ARGUMENT;
     if (!problem || !params_dev || !out_dev) return fail(ctx, SG_ERR_INVALID_ARGUMENT, "NULL argument");
-    sg_status st = validate_problem(ctx, *problem, 0);
+    sg_status st = validate_problem(ctx, *problem, 0, true);
     if (st != SG_OK) return st;
     const int d = problem->d, q = problem->q, K = q - d, rule = problem->rule;
     uint64_t npts = 0;

@@ -34,6 +34,7 @@ constexpr int KMAXP = kMaxK;
 constexpr int FAM_EXP = SG_FAMILY_EXP_SUM;
 constexpr int FAM_OSC = SG_FAMILY_OSCILLATORY;
 constexpr int FAM_PEAK = SG_FAMILY_PRODUCT_PEAK;
+constexpr int FAM_CORNER = SG_FAMILY_CORNER_PEAK;
 
 constexpr int REC_INTS = 2 + 2 * KMAXP;   // per unranked multi-index: nnz, excess, coords, levels
 
@@ -60,7 +61,7 @@ __device__ __forceinline__ double centre_value(const double* __restrict__ prm, i
     double s = 0.0, sa = 0.0;
     for (int t = lane; t < d; t += 64) {
         double v;
-        if constexpr (FAM == FAM_EXP) v = 0.5 * prm[t];
+        if constexpr (FAM == FAM_EXP || FAM == FAM_CORNER) v = 0.5 * prm[t];
         else if constexpr (FAM == FAM_OSC) v = 0.5 * prm[1 + t];
         else {
             const double b = prm[t], u = prm[d + t];
@@ -85,13 +86,24 @@ __device__ __forceinline__ double centre_value(const double* __restrict__ prm, i
 
 // f(x) - f(c) from the partial quantity of the point: ridge exp-sum
 // e^{t0} (e^delta - 1); oscillatory cos(t0 + delta) - cos(t0) =
-// -2 sin(t0 + delta/2) sin(delta/2); product-peak f(c) (e^delta - 1) with
-// delta = sum of log(g_i(x_i) / g_i(1/2)).
+// -2 sin(t0 + delta/2) sin(delta/2); corner-peak (1 + t0 + delta)^-(d+1) -
+// (1 + t0)^-(d+1) = f(c) (exp(-(d+1) log1p(delta / (1 + t0))) - 1);
+// product-peak f(c) (e^delta - 1) with delta = sum of log(g_i(x_i) / g_i(1/2)).
 template <int FAM>
-__device__ __forceinline__ double centred_value(double base, double fc, double delta)
+__device__ __forceinline__ double centred_value(double base, double fc, double delta, double dp1)
 {
     if constexpr (FAM == FAM_OSC) return -2.0 * sin(base + 0.5 * delta) * sin(0.5 * delta);
+    else if constexpr (FAM == FAM_CORNER) return fc * expm1(-dp1 * log1p(delta / (1.0 + base)));
     else return fc * expm1(delta);
+}
+
+// f at the centre from the centre's argument.
+template <int FAM>
+__device__ __forceinline__ double centre_f(double base, int d)
+{
+    if constexpr (FAM == FAM_OSC) return cos(base);
+    else if constexpr (FAM == FAM_CORNER) return exp(-(double)(d + 1) * log1p(base));
+    else return exp(base);
 }
 
 struct PointsArgs {
@@ -171,7 +183,8 @@ __global__ void __launch_bounds__(256) k_points(PointsArgs A)
     const int d = A.d;
 
     const double base = centre_value<FAM>(prm, d);
-    const double fc = FAM == FAM_EXP || FAM == FAM_PEAK ? exp(base) : cos(base);
+    const double fc = centre_f<FAM>(base, d);
+    const double dp1 = (double)(d + 1);
     int* rec = recs[w];
     double2* fr = front[w];
     double hi = 0.0, lo = 0.0, aabs = 0.0;
@@ -217,7 +230,7 @@ __global__ void __launch_bounds__(256) k_points(PointsArgs A)
                 const int node = A.level_off[lev] + (idx - bb);
                 const double y = A.node_y[node], wt = A.node_w[node];
                 double q;
-                if constexpr (FAM == FAM_EXP) q = prm[coord] * y;
+                if constexpr (FAM == FAM_EXP || FAM == FAM_CORNER) q = prm[coord] * y;
                 else if constexpr (FAM == FAM_OSC) q = prm[1 + coord] * y;
                 else {
                     const double b = prm[coord], u = prm[d + coord];
@@ -245,12 +258,16 @@ __global__ void __launch_bounds__(256) k_points(PointsArgs A)
                         wp *= f.y;
                     }
                 }
-                const double gd = centred_value<FAM>(base, fc, delta);
+                const double gd = centred_value<FAM>(base, fc, delta, dp1);
                 dd_add(hi, lo, wp * gd);
                 // rounding scale of the term: its own size plus the propagated
-                // error of delta (each entry and each addition rounded)
-                const double fx = FAM == FAM_OSC ? 1.0 : fc + gd;
-                aabs += fabs(wp) * (fabs(gd) + fabs(fx) * sd);
+                // error of delta (each entry and each addition rounded), times
+                // |df/d delta| (oscillatory <= 1; corner-peak (d+1) f / (1 + s))
+                double fx;
+                if constexpr (FAM == FAM_OSC) fx = 1.0;
+                else if constexpr (FAM == FAM_CORNER) fx = dp1 * fabs(fc + gd) / (1.0 + base + delta);
+                else fx = fabs(fc + gd);
+                aabs += fabs(wp) * (fabs(gd) + fx * sd);
             }
         }
     }
@@ -315,13 +332,17 @@ __global__ void __launch_bounds__(256) k_points_finish(const double* __restrict_
     if (t < 64) {
         double babs = 0.0;
         const double base = centre_value<FAM>(params, d, &babs);
-        const double fc = FAM == FAM_EXP || FAM == FAM_PEAK ? exp(base) : cos(base);
+        const double fc = centre_f<FAM>(base, d);
         if (t == 0) {
             out[0] = fc + (sh[0] + sl[0]);
             if (bound) {
                 const double u = 1.1102230246251565e-16;
                 const double S = sa[0] * (1.0 + 1e-12);
-                const double ec = u * ((double)(d + 4) * babs + (FAM == FAM_PEAK ? 4.0 * d : 0.0));
+                double ec = u * ((double)(d + 4) * babs + (FAM == FAM_PEAK ? 4.0 * d : 0.0));
+                // corner-peak: f depends on its argument through the power
+                // -(d+1) (components a_i >= 0, so 1 + s >= 1), and f(c) carries
+                // the rounding of (d+1) log1p(t0)
+                if (FAM == FAM_CORNER) ec = (double)(d + 1) * (ec + 4.0 * u * (fabs(log1p(base)) + 1.0));
                 bound[0] = 16.0 * u * (S + fabs(fc)) + ec * (fabs(fc) + 1.0 + S);
             }
         }
@@ -359,9 +380,13 @@ int launch_points(int family, const PointsLaunch& L, void* stream)
         hipLaunchKernelGGL(pts::k_points<pts::FAM_OSC>, grid, block, 0, s, A);
         hipLaunchKernelGGL(pts::k_points_finish<pts::FAM_OSC>, dim3(1), block, 0, s, L.partial, L.grid * 4,
                            L.params, L.d, L.out, L.bound);
-    } else {
+    } else if (family == SG_FAMILY_PRODUCT_PEAK) {
         hipLaunchKernelGGL(pts::k_points<pts::FAM_PEAK>, grid, block, 0, s, A);
         hipLaunchKernelGGL(pts::k_points_finish<pts::FAM_PEAK>, dim3(1), block, 0, s, L.partial, L.grid * 4,
+                           L.params, L.d, L.out, L.bound);
+    } else {
+        hipLaunchKernelGGL(pts::k_points<pts::FAM_CORNER>, grid, block, 0, s, A);
+        hipLaunchKernelGGL(pts::k_points_finish<pts::FAM_CORNER>, dim3(1), block, 0, s, L.partial, L.grid * 4,
                            L.params, L.d, L.out, L.bound);
     }
     return (int)hipGetLastError();

@@ -139,3 +139,35 @@ def test_points_deterministic_and_limits(torch_dev):
         _points(b, 0, max_points=npts - 1)
     assert e.value.status == 2
     assert _points(b, 0, max_points=npts) == _points(b, 0)
+
+
+@pytest.mark.parametrize("d,K,rule", [(1, 8, "gl"), (3, 6, "cc"), (8, 5, "tr"), (12, 4, "gl_paper"), (40, 3, "cc")])
+def test_points_corner_peak_vs_point_oracle(torch_dev, orc, d, K, rule):
+    # a ridge integrand that does not factor: only the point path handles it
+    from paper_2210_14313_amd import workloads as W
+    rng = np.random.default_rng(500 + d)
+    b = W.single(d, d + K, rule, "corner_peak", W.draw_params(rng, "corner_peak", d))
+    say("case points corner peak", d, K, rule)
+    r = orc.smolyak_points(d, d + K, rule, "corner_peak", b.param_slice(0))
+    got, bnd = _points(b, 0, with_bound=True)
+    _check(got, bnd, r["q"], "corner_peak", r["A"] + abs(r["fc"]))
+
+
+def test_points_corner_peak_converges_to_closed_form(torch_dev):
+    from oracle import reference as R
+    from paper_2210_14313_amd import workloads as W
+    rng = np.random.default_rng(9)
+    a = W.draw_params(rng, "corner_peak", 3)
+    b = W.single(3, 11, "gl", "corner_peak", a)
+    say("case points corner peak closed form")
+    got = _points(b, 0)
+    ex = float(R.exact_corner_peak(a))
+    assert abs(got - ex) <= 1e-12 * ex
+
+
+def test_corner_peak_rejected_by_the_sweep(torch_dev):
+    from paper_2210_14313_amd import native, workloads as W
+    b = W.single(4, 6, "cc", "corner_peak", np.full(4, 0.25))
+    with pytest.raises(native.SgError) as e:
+        native.Plan(b.problems, "fp64")
+    assert e.value.status == 2
