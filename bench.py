@@ -96,6 +96,87 @@ def algorithmic_flops(info) -> float:
     return PAIR_EVAL_FLOPS * info["pair_evals"] + 2.0 * info["macs"] + info["merge_flops"]
 
 
+def points_flop_slots(d: int, q: int, rule: str):
+    """Points (with repetition) and algorithmic flop-slots of the literal
+    point-by-point sum over the window of (2.6): per point one transcendental
+    evaluation of f (8 slots, as for a node pair of the sweep), the
+    multiply-add of w * (f(x) - f(c)) into the sum (2) and, over its nnz
+    active coordinates, nnz - 1 additions forming the partial quantity and
+    nnz multiplications forming coefficient times weight.  Exact integers
+    from the per-level node counts by generating functions in z (excess):
+    N(z) = sum_e n_{e+1} z^e, points = sum_window [z^e] N^d,
+    sum of nnz over points = d sum_window [z^e] (N - n_1) N^(d-1)."""
+    from paper_2210_14313_amd import native
+    K = q - d
+    n = [len(native.rule_table(rule, e + 1)[0]) for e in range(K + 1)]
+
+    def mul(a, b):
+        r = [0] * (K + 1)
+        for i, x in enumerate(a):
+            if x:
+                for j in range(K + 1 - i):
+                    r[i + j] += x * b[j]
+        return r
+
+    def power(a, k):
+        r = [1] + [0] * K
+        while k:
+            if k & 1:
+                r = mul(r, a)
+            a = mul(a, a)
+            k >>= 1
+        return r
+
+    Nd1 = power(n, d - 1)
+    Nd = mul(Nd1, n)
+    M = [0] + n[1:]
+    MN = mul(M, Nd1)
+    lo = max(0, K - d + 1)
+    pts = sum(Nd[lo:K + 1])
+    nnz = d * sum(MN[lo:K + 1])
+    return pts, 10 * pts + 2 * nnz - pts
+
+
+def points_leg(dev, s, reps: int = 5):
+    """Time the literal point-by-point path on the d = 100, q = 105
+    Clenshaw-Curtis workload (both families) and check it against the
+    stored full-size oracle values; roofline in flop-slots per launch."""
+    import torch
+    from paper_2210_14313_amd import api, native, workloads as W
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_full_size.json")))["rows"]
+    pd100 = W.precision_d100()
+    pts = {}
+    for row in [r for r in golden if r["workload"] == "precision_d100"]:
+        one = pd100.subset([row["index"]])
+        p = one.problems[0]
+        pr = api.params_tensor(one, dev)
+        o = torch.empty(1, dtype=torch.float64, device=dev)
+        bd = torch.empty(1, dtype=torch.float64, device=dev)
+        native.integrate_points(p, pr, out=o, bound=bd, stream=s)     # warm
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            native.integrate_points(p, pr, out=o, bound=bd, stream=s)
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        npts, slots = points_flop_slots(p.d, p.q, p.rule)
+        assert npts == int(row["npoints"]), (npts, row["npoints"])
+        ref_pt = row["points_hi"] + row["points_lo"]
+        sc = max(abs(ref_pt), 1.0) if p.family == "oscillatory" else abs(ref_pt)
+        achieved = slots / (ms / 1e3) / 1e12
+        pts[p.family] = {"points": float(npts), "ms": ms, "points_per_s": npts / (ms / 1e3),
+                         "rel_err_vs_point_oracle": abs(o.item() - ref_pt) / sc,
+                         "stated_bound_rel": bd.item() / sc,
+                         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TFLOPS,
+                                      "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TFLOPS,
+                                      "flop_slots_per_launch": float(slots)}}
+        log(f"  points {p.family}: {ms:.2f} ms, {npts / (ms / 1e3):.3e} points/s, "
+            f"frac {achieved / VALU_PEAK_TFLOPS:.4f}")
+    return pts
+
+
 def cpu_baseline(batch, target_points: float, threads: int):
     """Time the point-by-point oracle on the first integrands of the batch
     (skipping any with more than 5e8 points) until ~target_points are done."""
@@ -142,6 +223,8 @@ def main():
                     help="extra batch sizes (multiples of --n) for the scaling series")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="only run the traffic-counter calibration copy of this many MiB")
+    ap.add_argument("--points-only", action="store_true",
+                    help="only run the literal point-by-point leg (d = 100, q = 105) and print its JSON")
     args = ap.parse_args()
     if args.copy_probe_mb > 0:
         copy_probe(args.copy_probe_mb)
@@ -158,6 +241,12 @@ def main():
 
     import oracle
     from paper_2210_14313_amd import api, native, workloads as W
+
+    if args.points_only:
+        torch.cuda.set_device(0)
+        sp = torch.cuda.Stream()
+        print(json.dumps({"points_path_precision_d100": points_leg(torch.device("cuda:0"), sp)}), flush=True)
+        return
 
     batch = W.batched_uneven(n=args.n)
     # oracle values first (CPU, binary128) for the accuracy statement
@@ -385,32 +474,7 @@ def main():
         # literal point-by-point path on the d = 100, q = 105 workload
         # (2.08e10 points per integrand) against the stored oracle values
         log("point-by-point path ...")
-        golden = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_full_size.json")))["rows"]
-        pd100 = W.precision_d100()
-        pts = {}
-        for row in [r for r in golden if r["workload"] == "precision_d100"]:
-            one = pd100.subset([row["index"]])
-            p = one.problems[0]
-            pr = api.params_tensor(one, dev)
-            o = torch.empty(1, dtype=torch.float64, device=dev)
-            bd = torch.empty(1, dtype=torch.float64, device=dev)
-            native.integrate_points(p, pr, out=o, bound=bd, stream=s)     # warm
-            torch.cuda.synchronize()
-            reps = 5
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(s)
-            for _ in range(reps):
-                native.integrate_points(p, pr, out=o, bound=bd, stream=s)
-            e1.record(s)
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / reps
-            npts = float(row["npoints"])
-            ref_pt = row["points_hi"] + row["points_lo"]
-            sc = max(abs(ref_pt), 1.0) if p.family == "oscillatory" else abs(ref_pt)
-            pts[p.family] = {"points": npts, "ms": ms, "points_per_s": npts / (ms / 1e3),
-                             "rel_err_vs_point_oracle": abs(o.item() - ref_pt) / sc,
-                             "stated_bound_rel": bd.item() / sc}
-        extras["points_path_precision_d100"] = pts
+        extras["points_path_precision_d100"] = points_leg(dev, s)
 
         # scaling series: the same recipe with more integrands per launch
         scal = {str(args.n): {"kernel_ms": main_run["kernel_ms"], "grid_blocks": info["grid_blocks"],

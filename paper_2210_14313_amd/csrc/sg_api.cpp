@@ -31,6 +31,7 @@ struct PointsTable {
     double* y = nullptr;
     double* w = nullptr;
     int level_off[kMaxK + 3] = {};
+    int emax = 0, cmax = 0;   // frontier capacities (points_frontier_sizes)
 };
 
 // Forward schedule: target coordinates per lane and the most waves one
@@ -612,6 +613,9 @@ sg_status sg_integrate_points(sg_context* ctx, const sg_problem* problem, const 
             pt.level_off[l + 1] = (int)ys.size();
         }
         for (int l = K + 2; l < kMaxK + 3; ++l) pt.level_off[l] = (int)ys.size();
+        int nl[kMaxK + 3] = {};
+        for (int l = 1; l <= K + 1; ++l) nl[l] = pt.level_off[l + 1] - pt.level_off[l];
+        points_frontier_sizes(nl, K, &pt.emax, &pt.cmax);
         if ((st = upload(ctx, &pt.y, ys.data(), ys.size())) != SG_OK) return st;
         if ((st = upload(ctx, &pt.w, ws.data(), ws.size())) != SG_OK) return st;
         it = ctx->points_tables.emplace(key, pt).first;
@@ -638,6 +642,8 @@ sg_status sg_integrate_points(sg_context* ctx, const sg_problem* problem, const 
     L.node_y = it->second.y;
     L.node_w = it->second.w;
     for (int i = 0; i < kMaxK + 3; ++i) L.level_off[i] = it->second.level_off[i];
+    L.emax = it->second.emax;
+    L.cmax = it->second.cmax;
     for (int e = 0; e <= kMaxK; ++e) {
         // (-1)^(K-e) C(d-1, K-e), exact in long double up to 2^64, rounded once
         long double c = 0.0L;

@@ -170,12 +170,20 @@ struct PointsLaunch {
     const double* node_w;          // their weights (device)
     int level_off[kMaxK + 3];      // level l occupies [level_off[l], level_off[l+1])
     double coef[kMaxK + 1];        // combination coefficient by excess
+    int emax;                      // largest sum of n_l over the active coordinates of a multi-index
+    int cmax;                      // largest size of its two combined frontiers (points_frontier_sizes)
     const double* params;          // the integrand's parameters (device)
     double* partial;               // 3 * 4 * grid doubles of workspace (device)
     double* out;                   // one double (device-accessible)
     double* bound;                 // NULL or one double (device-accessible)
 };
 int launch_points(int family, const PointsLaunch& L, void* stream);
+
+// Frontier capacities of the point path for a rule whose level l has n[l]
+// nodes (l = 1..K+1): over every ordered list of active levels (>= 2) with
+// sum(l - 1) <= K, the largest sum of n_l (*emax) and the largest
+// min over splits s of prod_{m<s} n + prod_{m>=s} n (*cmax).
+void points_frontier_sizes(const int* n, int K, int* emax, int* cmax);
 
 // Record tables (FP64 and FP32 pools) of one (rule, K) in the static layout.
 bool build_records(const DeltaTable& t, std::vector<double>& rec64, std::vector<float>& rec32,

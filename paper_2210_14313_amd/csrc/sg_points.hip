@@ -16,14 +16,21 @@
 // "frontier" in LDS: for every active coordinate (level >= 2) and every node
 // of that coordinate's level, the node weight and the node's contribution to
 // the clustered partial quantity (the affine partial sum a_i (x - 1/2) of a
-// ridge integrand, or log(g_i(x)/g_i(1/2)) of a product integrand), so a
-// point costs one LDS read per active coordinate.  Lanes cover the tensor
-// points; f(x) - f(c) is formed without cancellation from the partial
-// quantity; the products are accumulated in double-double (two-sum) per lane,
-// reduced across lanes in a fixed order, and the per-wave partial sums are
-// added in wave order by a second kernel (bitwise reproducible).
+// ridge integrand, or log(g_i(x)/g_i(1/2)) of a product integrand).  The
+// active coordinates are then split into two groups (the split that
+// minimises the sum of the two groups' tensor sizes, at most 258 for K <= 8)
+// and each group's tensor of partial sums, weight products and magnitude
+// sums is staged too, so a point costs two LDS entries whatever its number
+// of active coordinates.  Lanes cover the tensor points; f(x) - f(c) is
+// formed without cancellation from the partial quantity (short Taylor series
+// on small arguments, the library functions otherwise); the products are
+// accumulated in double-double (two-sum) per lane, reduced across lanes in a
+// fixed order, and the per-wave partial sums are added in wave order by a
+// second kernel (bitwise reproducible).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "sg_internal.hpp"
 
@@ -36,7 +43,63 @@ constexpr int FAM_OSC = SG_FAMILY_OSCILLATORY;
 constexpr int FAM_PEAK = SG_FAMILY_PRODUCT_PEAK;
 constexpr int FAM_CORNER = SG_FAMILY_CORNER_PEAK;
 
-constexpr int REC_INTS = 2 + 2 * KMAXP;   // per unranked multi-index: nnz, excess, coords, levels
+// 1/k!, exact factorials (k <= 20) rounded once
+constexpr double inv_fact(int k)
+{
+    double f = 1.0;
+    for (int i = 2; i <= k; ++i) f *= (double)i;
+    return 1.0 / f;
+}
+
+// expm1(x) for |x| <= 1/2: x * sum_{k=1..16} x^(k-1)/k!; the first omitted
+// term is below 2^-64 of the sum, Horner's rule adds about one rounding and
+// the final product one more.
+constexpr double kExpSmall = 0.5;
+__device__ __forceinline__ double expm1_series(double x)
+{
+    double p = inv_fact(16);
+#pragma unroll
+    for (int k = 15; k >= 1; --k) p = fma(p, x, inv_fact(k));
+    return x * p;
+}
+
+// expm1(x) for any x: x itself on |x| <= 1/2; otherwise x = k ln2 + r with
+// k = rint(x / ln2) != 0 and |r| <= 0.35 (ln2 split in two parts, the first
+// with 12 trailing zero bits so that k times it is exact), and
+// expm1(x) = 2^k expm1(r) + (2^k - 1).  The two terms have the same sign
+// except for k = 1, r < 0 and k = -1, r > 0 (x within [0.5, 1.04] in
+// magnitude), where the sum is at least 0.39 and at most 2.1 times smaller
+// than the terms' magnitudes: at most 5 roundings of the result in all cases.
+// No branch: every lane runs the same instructions.
+constexpr double kLn2Hi = 0x1.62e42fefa3000p-1;
+constexpr double kLn2Lo = 0x1.3de6af278ece6p-42;
+constexpr double kLog2e = 1.4426950408889634;
+__device__ __forceinline__ double expm1_any(double x)
+{
+    const double kd = fabs(x) <= kExpSmall ? 0.0 : rint(x * kLog2e);
+    const double r = fma(-kd, kLn2Lo, fma(-kd, kLn2Hi, x));
+    const double e = expm1_series(r);
+    const int k = (int)kd;
+    const double t = ldexp(e, k) + (ldexp(1.0, k) - 1.0);
+    return kd == 0.0 ? e : t;
+}
+
+// sin(h) = h * sum_k (-h^2)^k/(2k+1)! and cos(h) = sum_k (-h^2)^k/(2k)!,
+// k = 0..8, for |h| <= 0.78 (< pi/4): the first omitted terms are below
+// 2^-60 of the values, and each evaluation adds about two roundings.
+constexpr double kTrigSmall = 0.78;
+__device__ __forceinline__ void sincos_series(double h, double& sh, double& ch)
+{
+    const double u = -h * h;
+    double ps = inv_fact(17), pc = inv_fact(16);
+#pragma unroll
+    for (int k = 7; k >= 0; --k) {
+        ps = fma(ps, u, inv_fact(2 * k + 1));
+        pc = fma(pc, u, inv_fact(2 * k));
+    }
+    sh = h * ps;
+    ch = pc;
+}
 
 // double-double accumulation: (hi, lo) += v exactly up to lo's rounding
 __device__ __forceinline__ void dd_add(double& hi, double& lo, double v)
@@ -89,12 +152,30 @@ __device__ __forceinline__ double centre_value(const double* __restrict__ prm, i
 // -2 sin(t0 + delta/2) sin(delta/2); corner-peak (1 + t0 + delta)^-(d+1) -
 // (1 + t0)^-(d+1) = f(c) (exp(-(d+1) log1p(delta / (1 + t0))) - 1);
 // product-peak f(c) (e^delta - 1) with delta = sum of log(g_i(x_i) / g_i(1/2)).
+//
+// Oscillatory, with h = delta/2 and (s0, c0) = (sin t0, cos t0):
+// sin(t0 + h) = s0 cos h + c0 sin h, so the difference is
+// -2 sin h (s0 cos h + c0 sin h).  Its rounding error is at most a few
+// units of |g| plus 10 u |sin h| <= 5 u |delta| (the bracket may cancel,
+// but each of its two products is at most 1 in magnitude).  Exp-sum and
+// product-peak: f(c) expm1(delta), at most 6 roundings of |g|.
 template <int FAM>
-__device__ __forceinline__ double centred_value(double base, double fc, double delta, double dp1)
+__device__ __forceinline__ double centred_value(double base, double fc, double delta, double dp1, double s0,
+                                                double c0)
 {
-    if constexpr (FAM == FAM_OSC) return -2.0 * sin(base + 0.5 * delta) * sin(0.5 * delta);
-    else if constexpr (FAM == FAM_CORNER) return fc * expm1(-dp1 * log1p(delta / (1.0 + base)));
-    else return fc * expm1(delta);
+    if constexpr (FAM == FAM_OSC) {
+        const double h = 0.5 * delta;
+        if (fabs(h) <= kTrigSmall) {
+            double sh, ch;
+            sincos_series(h, sh, ch);
+            return -2.0 * sh * fma(s0, ch, c0 * sh);
+        }
+        return -2.0 * sin(base + h) * sin(h);
+    } else if constexpr (FAM == FAM_CORNER) {
+        return fc * expm1(-dp1 * log1p(delta / (1.0 + base)));
+    } else {
+        return fc * expm1_any(delta);
+    }
 }
 
 // f at the centre from the centre's argument.
@@ -108,6 +189,9 @@ __device__ __forceinline__ double centre_f(double base, int d)
 
 struct PointsArgs {
     int d, K, e0;
+    int ri;                       // ints per unranked record: nnz, excess, K coordinates, K levels
+    int off_f1, off_fc, off_sc;   // byte offsets in a wave's LDS region: 1-D frontier, group tensors, sums
+    int wave_bytes;               // size of a wave's LDS region
     uint64_t n_multi, nchunks;
     const uint64_t* W;            // weak-composition counts, (K+1) rows of d+1
     const double* node_y;         // per level: x - 1/2 of its nodes
@@ -120,8 +204,8 @@ struct PointsArgs {
 };
 
 // Unrank `rank` (see the canonical order above) into this lane's record:
-// rec[0] = number of active coordinates, rec[1] = excess, then the active
-// coordinates (ascending) and their levels.
+// rec[0] = number of active coordinates, rec[1] = excess, then the K slots
+// of the active coordinates (ascending) and the K slots of their levels.
 __device__ __forceinline__ void unrank_into(const PointsArgs& A, uint64_t rank, int* rec)
 {
     const int d = A.d, K = A.K, stride = d + 1;
@@ -134,7 +218,7 @@ __device__ __forceinline__ void unrank_into(const PointsArgs& A, uint64_t rank, 
         r -= c;
     }
     int i = 0, rem = e, k = 0;
-    while (rem > 0 && k < KMAXP) {
+    while (rem > 0 && k < K) {
         const uint64_t total = weak(rem, d - i);
         const uint64_t T = total - r;
         int lo = i, hi = d - 1;
@@ -151,7 +235,7 @@ __device__ __forceinline__ void unrank_into(const PointsArgs& A, uint64_t rank, 
             r -= cnt;
         }
         rec[2 + k] = j;
-        rec[2 + KMAXP + k] = a + 1;
+        rec[2 + K + k] = a + 1;
         ++k;
         rem -= a;
         i = j + 1;
@@ -168,13 +252,10 @@ __device__ __forceinline__ void wave_lds_sync()
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
 }
 
-constexpr int FRONTIER_MAX = 264;   // >= max over multi-indices of the sum of n_l (K <= 8: 257)
-
 template <int FAM>
 __global__ void __launch_bounds__(256) k_points(PointsArgs A)
 {
-    __shared__ int recs[4][64 * REC_INTS];
-    __shared__ double2 front[4][FRONTIER_MAX];
+    extern __shared__ __align__(16) unsigned char smem[];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int gw = blockIdx.x * 4 + w;
@@ -185,38 +266,62 @@ __global__ void __launch_bounds__(256) k_points(PointsArgs A)
     const double base = centre_value<FAM>(prm, d);
     const double fc = centre_f<FAM>(base, d);
     const double dp1 = (double)(d + 1);
-    int* rec = recs[w];
-    double2* fr = front[w];
+    double s0 = 0.0, c0 = 0.0;
+    if constexpr (FAM == FAM_OSC) {
+        s0 = sin(base);
+        c0 = cos(base);
+    }
+    unsigned char* region = smem + (size_t)w * A.wave_bytes;
+    int* rec = (int*)region;
+    double2* f1 = (double2*)(region + A.off_f1);    // per coordinate and node: (contribution, weight)
+    double2* ft = (double2*)(region + A.off_fc);    // group tensors: (partial sum, weight product)
+    double* st = (double*)(region + A.off_sc);      // group tensors: sum of |contributions|
     double hi = 0.0, lo = 0.0, aabs = 0.0;
 
     for (uint64_t c = gw; c < A.nchunks; c += nw) {
         const uint64_t r0 = c * 64;
         const int cnt = (int)min((uint64_t)64, A.n_multi - r0);
         wave_lds_sync();   // earlier reads of rec are done
-        if (lane < cnt) unrank_into(A, r0 + lane, rec + lane * REC_INTS);
+        if (lane < cnt) unrank_into(A, r0 + lane, rec + lane * A.ri);
         wave_lds_sync();
         for (int j = 0; j < cnt; ++j) {
-            const int* rj = rec + j * REC_INTS;
+            const int* rj = rec + j * A.ri;
             const int nnz = __builtin_amdgcn_readfirstlane(rj[0]);
             if (nnz == 0) continue;                       // the centre: f(x) - f(c) = 0
             const int e = __builtin_amdgcn_readfirstlane(rj[1]);
             const double cw = A.coef[e];
-            // stage the frontier: nodes of every active coordinate
-            int nm[KMAXP], bm[KMAXP], cm[KMAXP], lm[KMAXP];
-            int E = 0, P = 1;
+            // active coordinates: coordinate, level, node count, offset in f1;
+            // pre[m] / suf[m]: tensor sizes of coordinates [0, m) / [m, nnz)
+            int nm[KMAXP], bm[KMAXP], cm[KMAXP], lm[KMAXP], pre[KMAXP + 1], suf[KMAXP + 1];
+            int E = 0;
+            pre[0] = 1;
 #pragma unroll
             for (int m = 0; m < KMAXP; ++m) {
                 if (m < nnz) {
                     cm[m] = __builtin_amdgcn_readfirstlane(rj[2 + m]);
-                    lm[m] = __builtin_amdgcn_readfirstlane(rj[2 + KMAXP + m]);
+                    lm[m] = __builtin_amdgcn_readfirstlane(rj[2 + A.K + m]);
                     nm[m] = A.level_off[lm[m] + 1] - A.level_off[lm[m]];
-                    bm[m] = E;
-                    E += nm[m];
-                    P *= nm[m];
                 } else {
-                    cm[m] = 0; lm[m] = 1; nm[m] = 1; bm[m] = E;
+                    cm[m] = 0; lm[m] = 1; nm[m] = 1;
                 }
+                bm[m] = E;
+                E += nm[m] * (m < nnz);
+                pre[m + 1] = pre[m] * nm[m];
             }
+            suf[KMAXP] = 1;
+#pragma unroll
+            for (int m = KMAXP - 1; m >= 0; --m) suf[m] = suf[m + 1] * nm[m];
+            const int P = pre[KMAXP];
+            // group A = coordinates [0, s) (the fast index), group B = [s, nnz)
+            int s = 0, best = 1 + P;
+#pragma unroll
+            for (int m = 1; m <= KMAXP; ++m)
+                if (m <= nnz && pre[m] + suf[m] < best) { best = pre[m] + suf[m]; s = m; }
+            int PA = pre[0], PB = suf[0];
+#pragma unroll
+            for (int m = 1; m <= KMAXP; ++m)
+                if (m == s) { PA = pre[m]; PB = suf[m]; }
+
             wave_lds_sync();   // earlier frontier reads are done
             for (int idx = lane; idx < E; idx += 64) {
                 int m = 0;
@@ -239,26 +344,44 @@ __global__ void __launch_bounds__(256) k_points(PointsArgs A)
                     // g(1/2 + y) / g(1/2) - 1 = -y (2 hv + y) / (beta + (hv + y)^2)
                     q = log1p(-y * (2.0 * hv + y) / fma(yp, yp, beta));
                 }
-                fr[idx] = make_double2(q, wt);
+                f1[idx] = make_double2(q, wt);
             }
             wave_lds_sync();
-            for (int p = lane; p < P; p += 64) {
-                int rem = p;
-                double delta = 0.0, sd = 0.0, wp = cw;
+            // the two group tensors: entries [0, PA) over group A (carrying
+            // the coefficient), [PA, PA + PB) over group B
+            for (int idx = lane; idx < PA + PB; idx += 64) {
+                const bool inA = idx < PA;
+                int rem = inA ? idx : idx - PA;
+                const int m0 = inA ? 0 : s, m1 = inA ? s : nnz;
+                double q = 0.0, sa = 0.0, wt = inA ? cw : 1.0;
 #pragma unroll
                 for (int m = 0; m < KMAXP; ++m) {
-                    if (m < nnz) {
-                        // rem = qt * n + k; P < 2^13, so the single-precision quotient is exact
+                    if (m >= m0 && m < m1) {
+                        // rem = qt * n + k; rem < 2^13, so the single-precision quotient is exact
                         const int qt = (int)(((float)rem + 0.5f) * A.rinv[lm[m]]);
                         const int k = rem - qt * nm[m];
                         rem = qt;
-                        const double2 f = fr[bm[m] + k];
-                        delta += f.x;
-                        sd += fabs(f.x);
-                        wp *= f.y;
+                        const double2 f = f1[bm[m] + k];
+                        q += f.x;
+                        sa += fabs(f.x);
+                        wt *= f.y;
                     }
                 }
-                const double gd = centred_value<FAM>(base, fc, delta, dp1);
+                ft[idx] = make_double2(q, wt);
+                st[idx] = sa;
+            }
+            wave_lds_sync();
+            // p = ib * PA + ia; p < 2^13, so the single-precision quotient
+            // (reciprocal within a few ulps) is exact after truncation
+            const float rpa = 1.0f / (float)PA;
+            for (int p = lane; p < P; p += 64) {
+                const int ib = (int)(((float)p + 0.5f) * rpa);
+                const int ia = p - ib * PA;
+                const double2 a = ft[ia], b = ft[PA + ib];
+                const double delta = a.x + b.x;
+                const double wp = a.y * b.y;
+                const double sd = st[ia] + st[PA + ib];
+                const double gd = centred_value<FAM>(base, fc, delta, dp1, s0, c0);
                 dd_add(hi, lo, wp * gd);
                 // rounding scale of the term: its own size plus the propagated
                 // error of delta (each entry and each addition rounded), times
@@ -292,11 +415,11 @@ __global__ void __launch_bounds__(256) k_points(PointsArgs A)
 // a-priori rounding bound
 //   16 u (S + |f(c)|) + e_c (|f(c)| + 1 + S),   u = 2^-53:
 // a term w * g carries at most 10 roundings relative to |w g| (up to 8
-// weight products, the coefficient, the product) plus g's error, at most 4
-// roundings of |g| and |f(x)| times the error of the partial quantity delta
-// (each of its at most 8 entries and additions, at most 6 roundings each,
-// relative to the sum of the entries' magnitudes); S accumulates
-// |w| (|g| + |f(x)| sum |entry|).  e_c bounds the error of the centre's
+// weight products, the coefficient, the product) plus g's error, at most 6
+// roundings of |g| (oscillatory: 3, plus 5 u |delta|, within the next term)
+// and |f(x)| times the error of the partial quantity delta (each of its at
+// most 8 entries and additions, at most 6 roundings each, relative to the
+// sum of the entries' magnitudes); S accumulates |w| (|g| + |f(x)| sum |entry|).  e_c bounds the error of the centre's
 // argument (log-amplitude or phase: a d-term sum, u (d + 4) times the sum
 // of its components' magnitudes, plus 4u per logarithm); the value and every
 // term move by at most |f(c)| + 1 + S per unit of it.  The double-double sum
@@ -351,12 +474,55 @@ __global__ void __launch_bounds__(256) k_points_finish(const double* __restrict_
 
 }  // namespace pts
 
+void points_frontier_sizes(const int* n, int K, int* emax, int* cmax)
+{
+    // ordered lists of active levels, depth-first; sizes fit in int (P <= 6561 for K <= 8)
+    int best_e = 0, best_c = 0;
+    int lev[kMaxK];
+    auto visit = [&](int len) {
+        int E = 0, P = 1;
+        for (int m = 0; m < len; ++m) {
+            E += n[lev[m]];
+            P *= n[lev[m]];
+        }
+        int c = 1 + P, pre = 1;
+        for (int m = 1; m <= len; ++m) {
+            pre *= n[lev[m - 1]];
+            c = std::min(c, pre + P / pre);
+        }
+        best_e = std::max(best_e, E);
+        best_c = std::max(best_c, c);
+    };
+    struct Rec {
+        static void go(int len, int budget, int K, int* lev, const decltype(visit)& f)
+        {
+            if (len > 0) f(len);
+            if (len == K) return;
+            for (int l = 2; l - 1 <= budget; ++l) {
+                lev[len] = l;
+                go(len + 1, budget - (l - 1), K, lev, f);
+            }
+        }
+    };
+    Rec::go(0, K, K, lev, visit);
+    *emax = best_e;
+    *cmax = best_c;
+}
+
 int launch_points(int family, const PointsLaunch& L, void* stream)
 {
     pts::PointsArgs A;
     A.d = L.d;
     A.K = L.K;
     A.e0 = L.e0;
+    auto align16 = [](int b) { return (b + 15) & ~15; };
+    A.ri = 2 + 2 * L.K;
+    A.off_f1 = align16(64 * A.ri * (int)sizeof(int));
+    A.off_fc = A.off_f1 + 16 * std::max(1, L.emax);
+    A.off_sc = A.off_fc + 16 * std::max(1, L.cmax);
+    A.wave_bytes = A.off_sc + align16(8 * std::max(1, L.cmax));
+    const size_t shmem = 4 * (size_t)A.wave_bytes;
+    if (shmem > 65536) return (int)hipErrorInvalidValue;
     A.n_multi = L.n_multi;
     A.nchunks = (L.n_multi + 63) / 64;
     A.W = L.W;
@@ -373,19 +539,19 @@ int launch_points(int family, const PointsLaunch& L, void* stream)
     const dim3 grid((unsigned)L.grid), block(256);
     hipStream_t s = (hipStream_t)stream;
     if (family == SG_FAMILY_EXP_SUM) {
-        hipLaunchKernelGGL(pts::k_points<pts::FAM_EXP>, grid, block, 0, s, A);
+        hipLaunchKernelGGL(pts::k_points<pts::FAM_EXP>, grid, block, shmem, s, A);
         hipLaunchKernelGGL(pts::k_points_finish<pts::FAM_EXP>, dim3(1), block, 0, s, L.partial, L.grid * 4,
                            L.params, L.d, L.out, L.bound);
     } else if (family == SG_FAMILY_OSCILLATORY) {
-        hipLaunchKernelGGL(pts::k_points<pts::FAM_OSC>, grid, block, 0, s, A);
+        hipLaunchKernelGGL(pts::k_points<pts::FAM_OSC>, grid, block, shmem, s, A);
         hipLaunchKernelGGL(pts::k_points_finish<pts::FAM_OSC>, dim3(1), block, 0, s, L.partial, L.grid * 4,
                            L.params, L.d, L.out, L.bound);
     } else if (family == SG_FAMILY_PRODUCT_PEAK) {
-        hipLaunchKernelGGL(pts::k_points<pts::FAM_PEAK>, grid, block, 0, s, A);
+        hipLaunchKernelGGL(pts::k_points<pts::FAM_PEAK>, grid, block, shmem, s, A);
         hipLaunchKernelGGL(pts::k_points_finish<pts::FAM_PEAK>, dim3(1), block, 0, s, L.partial, L.grid * 4,
                            L.params, L.d, L.out, L.bound);
     } else {
-        hipLaunchKernelGGL(pts::k_points<pts::FAM_CORNER>, grid, block, 0, s, A);
+        hipLaunchKernelGGL(pts::k_points<pts::FAM_CORNER>, grid, block, shmem, s, A);
         hipLaunchKernelGGL(pts::k_points_finish<pts::FAM_CORNER>, dim3(1), block, 0, s, L.partial, L.grid * 4,
                            L.params, L.d, L.out, L.bound);
     }

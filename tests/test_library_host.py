@@ -122,3 +122,24 @@ def test_rule_tables_match_oracle(orc, rule):
         xo, wo = orc.rule(rule, level)
         np.testing.assert_allclose(x, xo, rtol=0, atol=2e-16)
         np.testing.assert_allclose(w, wo, rtol=4e-16, atol=1e-18)
+
+
+@pytest.mark.parametrize("d,q,rule", [(3, 8, "gl"), (4, 7, "cc"), (2, 5, "tr"), (1, 6, "gl_paper"), (5, 5, "cc")])
+def test_point_path_work_count_by_brute_force(d, q, rule):
+    # the benchmark's flop-slot count of the point-by-point sum: points of
+    # the window of (2.6) and the number of active coordinates over them
+    import itertools
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    K = q - d
+    n = [len(native.rule_table(rule, l)[0]) for l in range(1, K + 2)]
+    P = S = 0
+    for l in itertools.product(range(1, K + 2), repeat=d):
+        if not (max(d, q - d + 1) <= sum(l) <= q):
+            continue
+        pp = int(np.prod([n[x - 1] for x in l]))
+        P += pp
+        S += pp * sum(1 for x in l if x >= 2)
+    assert bench.points_flop_slots(d, q, rule) == (P, 9 * P + 2 * S)
+    assert P == OC.counts_by_generating_function(d, q, rule)["n_points_rep"]
