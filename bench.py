@@ -177,6 +177,90 @@ def points_leg(dev, s, reps: int = 5):
     return pts
 
 
+def blocked_leg(dev, s, batch, precision: str, m: int = 10, reps: int = 50, check: int = 256):
+    """Block (tensor-product) variant of the rule, Algorithm 3.3 with step m:
+    the batch in blocks of m coordinates (block gather, forward over the
+    blocks, ordered combine; timed with events, roofline over the forward
+    work of the blocks, accuracy against the oracle's block rule on the
+    first `check` integrands), and the m = 10 setting of Table 4.9
+    (Gauss-Legendre with n_l = l, [-1,1]^d mapped to the unit cube; excess
+    K = 8, the largest this library builds, where the table uses 9): time
+    to integral and relative error against the exact integral."""
+    import mpmath as mp
+    import numpy as np
+    import torch
+    from oracle import blocked as OB
+    from oracle import reference as R
+    from paper_2210_14313_amd import api, native, workloads as W
+    res = {}
+    params = api.params_tensor(batch, dev)
+    plan = native.Plan(batch.problems, precision, block_dims=m)
+    out = torch.empty(len(batch), dtype=torch.float64, device=dev)
+    bound = torch.empty_like(out)
+    plan.autotune(params, out, stream=s)      # the blocks form a different batch shape
+    for _ in range(5):
+        plan.execute(params, out, bound, stream=s)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        plan.execute(params, out, bound, stream=s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    info = plan.info()
+    plan.close()
+    got, bnd = out.cpu().numpy(), bound.cpu().numpy()
+    idx = list(range(min(check, len(batch))))
+    ref = np.array([OB.smolyak_blocked(batch.problems[i].d, batch.problems[i].q, batch.problems[i].rule,
+                                       batch.problems[i].family, batch.param_slice(i), m) for i in idx])
+    fam = np.array([batch.problems[i].family for i in idx])
+    sc = np.where(fam == "oscillatory", np.maximum(np.abs(ref), 1.0), np.abs(ref))
+    achieved = algorithmic_flops(info) / (ms / 1e3) / 1e12
+    res[f"batched_uneven_{len(batch)}_m{m}"] = {
+        "precision": precision, "ms_per_launch": ms, "block_subproblems_units": info["units"],
+        "schedule": {k: info[k] for k in ("coords_per_lane", "max_group", "cost_scaled", "persistent", "graph",
+                                          "grid_blocks")},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / VALU_PEAK_TFLOPS, "flop_slots_per_launch": algorithmic_flops(info)},
+        "max_rel_err_vs_block_oracle": float(np.max(np.abs(got[idx] - ref) / sc)),
+        "all_within_stated_bound": bool(np.all(np.abs(got[idx] - ref) <= bnd[idx])),
+        "checked_integrands": len(idx)}
+    log(f"  blocked m={m} {precision}: {ms * 1e3:.2f} us per launch, frac {achieved / VALU_PEAK_TFLOPS:.4f}")
+    K = 8
+    paper = {}
+    # exp(sum (-1)^(i+1) x_i) at d = 1000; prod 1/(0.9^2 + (x_i - 0.6)^2) at
+    # d = 300 (on the unit cube its value exceeds the double range at d = 1000)
+    for name, fam, d in (("exp_alt_d1000", "exp_sum", 1000), ("peak_06_d300", "product_peak", 300)):
+        prm = (np.array([2.0 * (-1) ** i for i in range(d)]) if fam == "exp_sum"
+               else np.concatenate([np.full(d, 1 / 0.45), np.full(d, 0.8)]))
+        one = W.single(d, d + K, "gl_paper", fam, prm)
+        pr = api.params_tensor(one, dev)
+        row = {}
+        for prec in ("fp64", "fp32c"):
+            plan = native.Plan(one.problems, prec, block_dims=10)
+            o = torch.empty(1, dtype=torch.float64, device=dev)
+            bo = torch.empty(1, dtype=torch.float64, device=dev)
+            ts = []
+            with torch.cuda.stream(s):
+                for k in range(31):
+                    t0 = time.perf_counter()
+                    plan.execute(pr, o, bo, stream=s)
+                    v = o.item()
+                    ts.append(time.perf_counter() - t0)
+            plan.close()
+            ex = R.exact(fam, d, prm)
+            orc_v = OB.smolyak_blocked(d, d + K, "gl_paper", fam, prm, 10)
+            row[prec] = {"value": v, "stated_bound": bo.item(), "time_to_integral_median_s": statistics.median(ts[1:]),
+                         "rel_err_vs_exact": float(abs((mp.mpf(v) - ex) / ex)),
+                         "rel_diff_vs_block_oracle": abs(v - orc_v) / abs(orc_v)}
+        paper[name] = row
+        log(f"  blocked m=10 {name}: rel err vs exact {row['fp64']['rel_err_vs_exact']:.4e}, "
+            f"{row['fp64']['time_to_integral_median_s'] * 1e6:.1f} us")
+    res["table_4_9_setting_m10_gl_K8"] = paper
+    return res
+
+
 def cpu_baseline(batch, target_points: float, threads: int):
     """Time the point-by-point oracle on the first integrands of the batch
     (skipping any with more than 5e8 points) until ~target_points are done."""
@@ -223,6 +307,8 @@ def main():
                     help="extra batch sizes (multiples of --n) for the scaling series")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="only run the traffic-counter calibration copy of this many MiB")
+    ap.add_argument("--blocked-only", action="store_true",
+                    help="only run the block-variant leg (m = 10) and print its JSON")
     ap.add_argument("--points-only", action="store_true",
                     help="only run the literal point-by-point leg (d = 100, q = 105) and print its JSON")
     args = ap.parse_args()
@@ -249,6 +335,11 @@ def main():
         return
 
     batch = W.batched_uneven(n=args.n)
+    if args.blocked_only:
+        torch.cuda.set_device(0)
+        sb = torch.cuda.Stream()
+        print(json.dumps({"blocked_m10": blocked_leg(torch.device("cuda:0"), sb, batch, args.precision)}), flush=True)
+        return
     # oracle values first (CPU, binary128) for the accuracy statement
     log("oracle reference (binary128, threaded) ...")
     t0 = time.perf_counter()
@@ -431,6 +522,9 @@ def main():
                 tti[f"{p.rule}_{prec}"] = {"median_s": statistics.median(ts), "cold_s": cold, "value": v,
                                            "rel_err_vs_oracle": abs(v - ex) / abs(ex), "pinned_result": pinned}
         extras["time_to_integral_d1000"] = tti
+        # block (tensor-product) variant, Algorithm 3.3 with step m = 10
+        log("block variant (m = 10) ...")
+        extras["blocked_m10"] = blocked_leg(dev, s, batch, args.precision)
         # reverse sweep on the gradient workload (256 oscillatory, d = 200, q = 205)
         gb = W.gradient_osc_d200()
         gref = np.zeros_like(gb.params)

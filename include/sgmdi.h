@@ -178,6 +178,30 @@ sg_status sg_unrank_device(sg_context *ctx, int32_t d, int32_t q, uint64_t rank0
 sg_status sg_plan_create(sg_context *ctx, const sg_problem *problems, int32_t n,
                          int32_t precision, sg_plan **plan);
 
+/* Block (tensor-product) variant of the rule, Algorithm 3.3 with step
+ * m = block_dims > 1 ((3.8)-(3.11)): the coordinates of every integrand are
+ * cut into consecutive blocks of block_dims (the last block shorter when it
+ * does not divide d), each block gets its own sparse grid of level
+ * d_b + (q - d) (the integrand's excess budget), and the rule is the tensor
+ * product of the block rules -- the reading under which the paper's errors
+ * grow in proportion to d/m (Tables 4.7-4.9, 5.1-5.4).  block_dims >= d is
+ * the plain rule.  The integrand must factor over the blocks (exp-sum,
+ * oscillatory, product-peak).  The returned plan is used like any other
+ * (sg_plan_execute, _autotune, _set_schedule, _get_info, _destroy) with the
+ * same parameter layout and outputs.  Execution is three launches (block
+ * parameter gather, forward over the blocks, ordered combine), launched
+ * directly, or -- when sg_plan_set_schedule's graph flag is set or the
+ * autotuner found it faster, on non-default streams only -- captured into
+ * one HIP graph per (params, out, bound, stream) binding and replayed.
+ * bound_dev receives a bound on
+ * |result - exact value of the block rule| propagated from the blocks'
+ * bounds.  sg_plan_execute_grad is not available (UNSUPPORTED).
+ * effective_points counts the tensor product's points (saturating).
+ * Errors: INVALID_ARGUMENT (block_dims < 1, as sg_plan_create), UNSUPPORTED
+ * (corner-peak, K > SG_MAX_K), OUT_OF_MEMORY, DEVICE. */
+sg_status sg_plan_create_blocked(sg_context *ctx, const sg_problem *problems, int32_t n,
+                                 int32_t precision, int32_t block_dims, sg_plan **plan);
+
 /* Evaluate every integrand of the plan.  params_dev: the batch's float64
  * parameter array (device); out_dev: n float64 results in problem order
  * (device-accessible: device memory, or the device alias of pinned host

@@ -11,16 +11,19 @@ def params_tensor(batch, device="cuda") -> torch.Tensor:
     return torch.as_tensor(batch.params, dtype=torch.float64).to(device).contiguous()
 
 
-def integrate(batch, precision: str = "fp64", params=None, with_bound: bool = False, plan=None):
+def integrate(batch, precision: str = "fp64", params=None, with_bound: bool = False, plan=None,
+              block_dims: int = 0):
     """Smolyak values (2.6) of every integrand of ``batch`` on the GPU.
 
     Returns (values, bounds or None) as float64 device tensors in problem
     order.  ``params`` overrides the batch's parameters (a device tensor).
+    ``block_dims`` > 0 selects the block (tensor-product) variant of the
+    rule with blocks of that many coordinates (Algorithm 3.3, step m).
     """
     if params is None:
         params = params_tensor(batch)
     own = plan is None
-    plan = plan or native.Plan(batch.problems, precision)
+    plan = plan or native.Plan(batch.problems, precision, block_dims=block_dims)
     try:
         out = torch.empty(len(batch), dtype=torch.float64, device=params.device)
         bound = torch.empty_like(out) if with_bound else None

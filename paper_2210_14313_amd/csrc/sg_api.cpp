@@ -73,6 +73,19 @@ struct sg_context {
     int live_plans = 0;
 };
 
+// Block (tensor-product) variant: an inner plan over the blocks, and the
+// gather / combine records around it.
+struct BlockedPart {
+    int m = 0;                       // coordinates per block
+    sg_plan* inner = nullptr;        // plan over the block sub-problems
+    BlockSub* d_subs = nullptr;      // per block sub-problem (device)
+    int nsub = 0;
+    BlockProb* d_bprobs = nullptr;   // per integrand (device)
+    double* d_params = nullptr;      // block parameters (device)
+    double* d_out = nullptr;         // block values (device)
+    double* d_bound = nullptr;       // block bounds (device)
+};
+
 struct sg_plan {
     sg_context* ctx = nullptr;
     int precision = 0;
@@ -102,6 +115,7 @@ struct sg_plan {
     sg_plan_info info{};
     std::string tune_key;
     std::vector<GraphEntry> graphs;
+    BlockedPart* blocked = nullptr;  // set for the block variant (sg_plan_create_blocked)
 };
 
 namespace {
@@ -847,11 +861,17 @@ static sg_status plan_repack(sg_plan* p, const FwdSched& sc)
     return SG_OK;
 }
 
-sg_status sg_plan_execute(sg_plan* p, const double* params_dev, double* out_dev, double* bound_dev, void* stream)
+static sg_status blocked_execute(sg_plan* p, const double* params_dev, double* out_dev, double* bound_dev,
+                                 void* stream);
+
+// Launch the plan's work on `stream`: directly, or, when the plan replays
+// graphs (non-default streams only), through a HIP graph captured on the
+// first call with a given (params, out, bound, stream) binding.
+extern "C++" template <class Launch>
+static sg_status graph_or_direct(sg_plan* p, const double* params_dev, double* out_dev, double* bound_dev,
+                                 void* stream, Launch launch)
 {
-    if (!p) return SG_ERR_INVALID_ARGUMENT;
-    if (!params_dev || !out_dev) return fail(p->ctx, SG_ERR_INVALID_ARGUMENT, "NULL params or out");
-    if (!stream || !p->use_graph || !graphs_enabled()) return plan_launch(p, params_dev, out_dev, bound_dev, stream);
+    if (!stream || !p->use_graph || !graphs_enabled()) return launch(stream);
     for (GraphEntry& g : p->graphs) {
         if (g.params == params_dev && g.out == out_dev && g.bound == bound_dev && g.stream == stream) {
             hipError_t e = hipGraphLaunch(g.exec, (hipStream_t)stream);
@@ -859,17 +879,17 @@ sg_status sg_plan_execute(sg_plan* p, const double* params_dev, double* out_dev,
             return SG_OK;
         }
     }
-    // first call with this binding: capture the launch into a graph
+    // first call with this binding: capture the launches into a graph
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return fail(p->ctx, SG_ERR_CAPTURE, std::string("begin capture: ") + hipGetErrorString(e));
-    const int rc = launch_forward(p->precision, p->kmax, p->nfwg, p->d_fwd, p->sched.persistent ? p->d_queue : nullptr,
-                                  p->qgrid, p->d_pool64, p->d_pool32, params_dev, out_dev, bound_dev, stream);
+    const sg_status st = launch(stream);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(s, &graph);
-    if (rc != 0 || e != hipSuccess || !graph) {
+    if (st != SG_OK || e != hipSuccess || !graph) {
         if (graph) hipGraphDestroy(graph);
-        return fail(p->ctx, SG_ERR_CAPTURE, std::string("capture: ") + hipGetErrorString(rc ? (hipError_t)rc : e));
+        if (st != SG_OK) return st;
+        return fail(p->ctx, SG_ERR_CAPTURE, std::string("capture: ") + hipGetErrorString(e));
     }
     hipGraphExec_t exec = nullptr;
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -888,12 +908,125 @@ sg_status sg_plan_execute(sg_plan* p, const double* params_dev, double* out_dev,
     return SG_OK;
 }
 
+sg_status sg_plan_execute(sg_plan* p, const double* params_dev, double* out_dev, double* bound_dev, void* stream)
+{
+    if (!p) return SG_ERR_INVALID_ARGUMENT;
+    if (!params_dev || !out_dev) return fail(p->ctx, SG_ERR_INVALID_ARGUMENT, "NULL params or out");
+    if (p->blocked) return blocked_execute(p, params_dev, out_dev, bound_dev, stream);
+    return graph_or_direct(p, params_dev, out_dev, bound_dev, stream,
+                           [&](void* st) { return plan_launch(p, params_dev, out_dev, bound_dev, st); });
+}
+
+// The block variant's three launches (gather, forward over the blocks,
+// combine), as one graph when the plan replays graphs.
+static sg_status blocked_execute(sg_plan* p, const double* params_dev, double* out_dev, double* bound_dev,
+                                 void* stream)
+{
+    BlockedPart& B = *p->blocked;
+    return graph_or_direct(p, params_dev, out_dev, bound_dev, stream, [&](void* st) {
+        int rc = launch_block_gather(B.d_subs, B.nsub, params_dev, B.d_params, st);
+        if (rc != 0) return hip_fail(p->ctx, (hipError_t)rc, "block gather launch");
+        sg_status s2 = plan_launch(B.inner, B.d_params, B.d_out, B.d_bound, st);
+        if (s2 != SG_OK) return s2;
+        rc = launch_block_combine(B.d_bprobs, p->n, B.d_out, B.d_bound, params_dev, out_dev, bound_dev, st);
+        if (rc != 0) return hip_fail(p->ctx, (hipError_t)rc, "block combine launch");
+        return SG_OK;
+    });
+}
+
+sg_status sg_plan_create_blocked(sg_context* ctx, const sg_problem* problems, int32_t n, int32_t precision,
+                                 int32_t block_dims, sg_plan** plan)
+{
+    if (!ctx || !plan) return SG_ERR_INVALID_ARGUMENT;
+    *plan = nullptr;
+    if (!problems || n < 1) return fail(ctx, SG_ERR_INVALID_ARGUMENT, "empty problem list");
+    if (block_dims < 1) return fail(ctx, SG_ERR_INVALID_ARGUMENT, "block_dims must be >= 1");
+    for (int i = 0; i < n; ++i) {
+        sg_status st = validate_problem(ctx, problems[i], i);
+        if (st != SG_OK) return st;
+    }
+    // block sub-problems in integrand order, blocks in coordinate order
+    // (oscillatory: real part, then imaginary part); their parameters are
+    // laid out contiguously in the plan's block array
+    std::vector<sg_problem> sub;
+    std::vector<BlockSub> gs;
+    std::vector<BlockProb> bp(n);
+    int64_t off = 0;
+    uint64_t eff = 0;
+    for (int i = 0; i < n; ++i) {
+        const sg_problem& P = problems[i];
+        const int K = P.q - P.d;
+        const int nb = (P.d + block_dims - 1) / block_dims;
+        const bool osc = P.family == SG_FAMILY_OSCILLATORY;
+        if (sub.size() + (size_t)nb * (osc ? 2 : 1) > (size_t)INT32_MAX)
+            return fail(ctx, SG_ERR_UNSUPPORTED, "too many blocks");
+        bp[i].param_offset = P.param_offset;
+        bp[i].first_sub = (int32_t)sub.size();
+        bp[i].nblocks = nb;
+        bp[i].family = P.family;
+        bp[i].out_index = i;
+        uint64_t pts = 1;
+        for (int b = 0; b < nb; ++b) {
+            const int start = b * block_dims, len = std::min(block_dims, P.d - start);
+            uint64_t nrep = 0;
+            sg_status st = counts(len, len + K, P.rule, nullptr, &nrep, nullptr);
+            pts = sat_mul(pts, st == SG_OK ? nrep : UINT64_MAX);
+            for (int part = osc ? 1 : 0; part <= (osc ? 2 : 0); ++part) {
+                BlockSub g{};
+                g.src_off = P.param_offset;
+                g.dst_off = off;
+                g.start = start;
+                g.len = len;
+                g.d = P.d;
+                g.family = P.family;
+                g.part = part;
+                gs.push_back(g);
+                sub.push_back(sg_problem{len, len + K, P.rule, P.family, off});
+                off += osc ? 1 + len : P.family == SG_FAMILY_PRODUCT_PEAK ? 2 * (int64_t)len : len;
+            }
+        }
+        eff = sat_add(eff, pts);
+    }
+    sg_plan* inner = nullptr;
+    sg_status st = sg_plan_create(ctx, sub.data(), (int32_t)sub.size(), precision, &inner);
+    if (st != SG_OK) return st;
+    std::unique_ptr<sg_plan> p(new sg_plan());
+    p->ctx = ctx;
+    p->precision = precision;
+    p->n = n;
+    p->problems.assign(problems, problems + n);
+    p->blocked = new BlockedPart();
+    BlockedPart& B = *p->blocked;
+    B.m = block_dims;
+    B.inner = inner;
+    B.nsub = (int)sub.size();
+    p->info = inner->info;
+    p->info.effective_points = eff;
+    inner->use_graph = false;      // graphs, when chosen, hold all three launches
+    inner->info.graph = 0;
+    p->use_graph = false;
+    p->info.graph = 0;
+    ctx->live_plans++;
+    if ((st = upload(ctx, &B.d_subs, gs.data(), gs.size())) != SG_OK) { sg_plan_destroy(p.release()); return st; }
+    if ((st = upload(ctx, &B.d_bprobs, bp.data(), bp.size())) != SG_OK) { sg_plan_destroy(p.release()); return st; }
+    hipError_t e = hipMalloc((void**)&B.d_params, std::max<int64_t>(1, off) * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&B.d_out, (size_t)B.nsub * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&B.d_bound, (size_t)B.nsub * sizeof(double));
+    if (e != hipSuccess) {
+        sg_plan_destroy(p.release());
+        return fail(ctx, SG_ERR_OUT_OF_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    *plan = p.release();
+    return SG_OK;
+}
+
 sg_status sg_plan_execute_grad(sg_plan* p, const double* params_dev, const double* grad_out_dev,
                                double* grad_params_dev, void* stream)
 {
     if (!p) return SG_ERR_INVALID_ARGUMENT;
     if (!params_dev || !grad_out_dev || !grad_params_dev)
         return fail(p->ctx, SG_ERR_INVALID_ARGUMENT, "NULL params, grad_out or grad_params");
+    if (p->blocked) return fail(p->ctx, SG_ERR_UNSUPPORTED, "the block variant has no reverse sweep");
     if (!p->params_disjoint)
         return fail(p->ctx, SG_ERR_INVALID_ARGUMENT,
                     "problems share parameters: the reverse sweep needs disjoint parameter ranges");
@@ -917,9 +1050,54 @@ sg_status sg_plan_get_info(const sg_plan* p, sg_plan_info* info)
     return SG_OK;
 }
 
+// After the inner plan's schedule changed: the outer plan keeps the graph
+// choice (its graphs hold the inner launch, so they are rebuilt).
+static void blocked_sync_info(sg_plan* p, bool graph)
+{
+    sg_plan* in = p->blocked->inner;
+    in->use_graph = false;
+    in->info.graph = 0;
+    destroy_graphs(in);
+    destroy_graphs(p);
+    p->use_graph = graph;
+    p->info.graph = graph ? 1 : 0;
+    p->info.grid_blocks = in->info.grid_blocks;
+    p->info.coords_per_lane = in->info.coords_per_lane;
+    p->info.max_group = in->info.max_group;
+    p->info.persistent = in->info.persistent;
+    p->info.cost_scaled = in->info.cost_scaled;
+}
+
 sg_status sg_plan_autotune(sg_plan* p, const double* params_dev, double* out_dev, void* stream)
 {
     if (!p || !params_dev || !out_dev) return SG_ERR_INVALID_ARGUMENT;
+    if (p->blocked) {
+        BlockedPart& B = *p->blocked;
+        const int rc = launch_block_gather(B.d_subs, B.nsub, params_dev, B.d_params, stream);
+        if (rc != 0) return hip_fail(p->ctx, (hipError_t)rc, "block gather launch");
+        sg_status st = sg_plan_autotune(B.inner, B.d_params, B.d_out, stream);
+        blocked_sync_info(p, false);
+        if (st != SG_OK || !stream) return st;
+        // direct launches or one graph of the three: keep the faster
+        hipEvent_t e0, e1;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+            return fail(p->ctx, SG_ERR_DEVICE, "hipEventCreate");
+        float ms[2] = {0.f, 0.f};
+        for (int g = 0; g < 2 && st == SG_OK; ++g) {
+            p->use_graph = g == 1;
+            if ((st = sg_plan_execute(p, params_dev, out_dev, nullptr, stream)) != SG_OK) break;   // warm / capture
+            hipEventRecord(e0, (hipStream_t)stream);
+            for (int r = 0; r < 20; ++r) sg_plan_execute(p, params_dev, out_dev, nullptr, stream);
+            hipEventRecord(e1, (hipStream_t)stream);
+            hipError_t e = hipEventSynchronize(e1);
+            if (e != hipSuccess) { st = hip_fail(p->ctx, e, "autotune sync"); break; }
+            hipEventElapsedTime(&ms[g], e0, e1);
+        }
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        blocked_sync_info(p, st == SG_OK && ms[1] < ms[0]);
+        return st;
+    }
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -981,6 +1159,11 @@ sg_status sg_plan_set_schedule(sg_plan* p, int32_t coords_per_lane, int32_t max_
     if (coords_per_lane < 1 || coords_per_lane > 64 || (max_group != 1 && max_group != 2 && max_group != 4) ||
         (cost_scaled != 0 && cost_scaled != 1) || (persistent != 0 && persistent != 1) || (graph != 0 && graph != 1))
         return fail(p->ctx, SG_ERR_INVALID_ARGUMENT, "schedule out of range");
+    if (p->blocked) {
+        sg_status st = sg_plan_set_schedule(p->blocked->inner, coords_per_lane, max_group, cost_scaled, persistent, 0);
+        blocked_sync_info(p, graph == 1);
+        return st;
+    }
     FwdSched sc;
     sc.cpl = coords_per_lane;
     sc.gmax = max_group;
@@ -997,6 +1180,17 @@ sg_status sg_plan_set_schedule(sg_plan* p, int32_t coords_per_lane, int32_t max_
 sg_status sg_plan_destroy(sg_plan* p)
 {
     if (!p) return SG_OK;
+    if (p->blocked) {
+        BlockedPart* B = p->blocked;
+        sg_plan_destroy(B->inner);
+        hipFree(B->d_subs);
+        hipFree(B->d_bprobs);
+        hipFree(B->d_params);
+        hipFree(B->d_out);
+        hipFree(B->d_bound);
+        delete B;
+        p->blocked = nullptr;
+    }
     destroy_graphs(p);
     hipFree(p->d_probs);
     hipFree(p->d_wgs);

@@ -1,0 +1,164 @@
+// Block (tensor-product) variant of the sparse grid: the coordinates of an
+// integrand are cut into consecutive blocks, each block gets its own sparse
+// grid with the integrand's excess budget, and the rule is the tensor
+// product of the block rules (the reading of Algorithm 3.3 with step m > 1,
+// (3.8)-(3.11), under which the error grows in proportion to d/m).  For
+// the product-form families the integrand factors over the blocks, so the
+// value is the product of the block values, each block being an ordinary
+// batched problem of the forward sweep:
+//   exp-sum, product-peak: Q = prod_b Q_b;
+//   oscillatory: Q = Re(e^{2 pi i w} prod_b (R_b + i I_b)), with R_b the
+//   block's oscillatory value at w = 0 and I_b the one at w = -1/4
+//   (cos(theta - pi/2) = sin theta).
+// Two kernels surround the forward launch over the blocks: a gather that
+// lays out the blocks' parameters, and a combine that forms the products in
+// a fixed order and propagates the blocks' error bounds.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sg_internal.hpp"
+
+namespace sg {
+namespace blk {
+
+// One thread per block: copies the block's parameters.
+__global__ void __launch_bounds__(256) k_block_gather(const BlockSub* __restrict__ subs, int nsub,
+                                                      const double* __restrict__ params,
+                                                      double* __restrict__ sub_params)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsub) return;
+    const BlockSub b = subs[s];
+    const double* src = params + b.src_off;
+    double* dst = sub_params + b.dst_off;
+    if (b.family == SG_FAMILY_OSCILLATORY) {
+        dst[0] = b.part == 2 ? -0.25 : 0.0;
+        for (int j = 0; j < b.len; ++j) dst[1 + j] = src[1 + b.start + j];
+    } else if (b.family == SG_FAMILY_PRODUCT_PEAK) {
+        for (int j = 0; j < b.len; ++j) {
+            dst[j] = src[b.start + j];
+            dst[b.len + j] = src[b.d + b.start + j];
+        }
+    } else {
+        for (int j = 0; j < b.len; ++j) dst[j] = src[b.start + j];
+    }
+}
+
+// Partial product of some blocks: value (complex for oscillatory), and for
+// the bound P = prod |v_b| and D = prod (|v_b| + e_b) - prod |v_b|.
+struct Part {
+    double re, im, P, D;
+};
+
+// Joining two parts.  Real and complex products are commutative in floating
+// point, so the result does not depend on which part comes first; D joins
+// without cancellation: D = D1 P2 + D2 P1 + D1 D2.
+__device__ __forceinline__ Part join(const Part& x, const Part& y, bool complex_value)
+{
+    Part r;
+    if (complex_value) {
+        r.re = x.re * y.re - x.im * y.im;
+        r.im = x.re * y.im + x.im * y.re;
+    } else {
+        r.re = x.re * y.re;
+        r.im = 0.0;
+    }
+    r.D = x.D * y.P + y.D * x.P + x.D * y.D;
+    r.P = x.P * y.P;
+    return r;
+}
+
+__device__ __forceinline__ Part shfl_part(const Part& x, int off)
+{
+    Part r;
+    r.re = __shfl_down(x.re, off);
+    r.im = __shfl_down(x.im, off);
+    r.P = __shfl_down(x.P, off);
+    r.D = __shfl_down(x.D, off);
+    return r;
+}
+
+// One wave per integrand: lanes take 64 blocks at a time, a fixed lane tree
+// joins them, lane 0 joins the passes in order (bitwise reproducible).
+//
+// Bound.  With block values v_b, |exact block value - v_b| <= e_b, the
+// tensor rule's value differs from prod v_b by at most D.  Rounding of the
+// k - 1 real products, in any association: at most k u (P + D); of the
+// complex products (each component two products and a sum): at most
+// 4 k u (P + D); of the final rotation by e^{2 pi i w}: at most
+// (2 |2 pi w| + 6) u (P + D).  Every quantity of the bound is a sum or
+// product of non-negative numbers, so its own rounding is covered by the
+// factor 1 + 4 k u.
+__global__ void __launch_bounds__(256) k_block_combine(const BlockProb* __restrict__ probs, int n,
+                                                       const double* __restrict__ sub_out,
+                                                       const double* __restrict__ sub_bound,
+                                                       const double* __restrict__ params,
+                                                       double* __restrict__ out, double* __restrict__ bound)
+{
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= n) return;
+    const BlockProb p = probs[i];
+    const bool osc = p.family == SG_FAMILY_OSCILLATORY;
+    const double u = 1.1102230246251565e-16;
+    Part acc{1.0, 0.0, 1.0, 0.0};
+    for (int base = 0; base < p.nblocks; base += 64) {
+        const int b = base + lane;
+        Part x{1.0, 0.0, 1.0, 0.0};
+        if (b < p.nblocks) {
+            if (osc) {
+                const int s = p.first_sub + 2 * b;
+                x.re = sub_out[s];
+                x.im = sub_out[s + 1];
+                x.P = hypot(x.re, x.im) * (1.0 + 2.0 * u);
+                x.D = sub_bound[s] + sub_bound[s + 1];
+            } else {
+                const int s = p.first_sub + b;
+                x.re = sub_out[s];
+                x.P = fabs(x.re);
+                x.D = sub_bound[s];
+            }
+        }
+        for (int off = 1; off < 64; off <<= 1) {
+            const Part y = shfl_part(x, off);
+            if ((lane & (2 * off - 1)) == 0) x = join(x, y, osc);
+        }
+        if (lane == 0) acc = join(acc, x, osc);
+    }
+    if (lane != 0) return;
+    const double ku = (double)p.nblocks * u;
+    if (osc) {
+        const double phi = 2.0 * 3.141592653589793 * params[p.param_offset];
+        double sp, cp;
+        sincos(phi, &sp, &cp);
+        out[p.out_index] = cp * acc.re - sp * acc.im;
+        if (bound) {
+            const double rnd = 4.0 * ku + (2.0 * fabs(phi) + 6.0) * u;
+            bound[p.out_index] = (acc.D + rnd * (acc.P + acc.D)) * (1.0 + 4.0 * ku);
+        }
+    } else {
+        out[p.out_index] = acc.re;
+        if (bound) bound[p.out_index] = (acc.D + ku * (acc.P + acc.D)) * (1.0 + 4.0 * ku);
+    }
+}
+
+}  // namespace blk
+
+int launch_block_gather(const BlockSub* subs, int nsub, const double* params, double* sub_params, void* stream)
+{
+    if (nsub <= 0) return 0;
+    hipLaunchKernelGGL(blk::k_block_gather, dim3((unsigned)((nsub + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       subs, nsub, params, sub_params);
+    return (int)hipGetLastError();
+}
+
+int launch_block_combine(const BlockProb* probs, int n, const double* sub_out, const double* sub_bound,
+                         const double* params, double* out, double* bound, void* stream)
+{
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(blk::k_block_combine, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, (hipStream_t)stream, probs, n,
+                       sub_out, sub_bound, params, out, bound);
+    return (int)hipGetLastError();
+}
+
+}  // namespace sg

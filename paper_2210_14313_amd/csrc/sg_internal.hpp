@@ -185,6 +185,29 @@ int launch_points(int family, const PointsLaunch& L, void* stream);
 // min over splits s of prod_{m<s} n + prod_{m>=s} n (*cmax).
 void points_frontier_sizes(const int* n, int K, int* emax, int* cmax);
 
+// Block (tensor-product) variant: one record per block sub-problem (gather)
+// and one per integrand (ordered combine).
+struct BlockSub {
+    int64_t src_off;   // integrand's parameter offset in the caller's array
+    int64_t dst_off;   // block's parameter offset in the plan's block array
+    int32_t start;     // first coordinate of the block
+    int32_t len;       // coordinates in the block
+    int32_t d;         // integrand's dimension (product-peak: offset of u)
+    int32_t family;
+    int32_t part;      // oscillatory: 1 = real part (w = 0), 2 = imaginary part (w = -1/4)
+    int32_t pad;
+};
+struct BlockProb {
+    int64_t param_offset;   // integrand's parameter offset (oscillatory: w)
+    int32_t first_sub;      // its first block sub-problem (oscillatory: two per block)
+    int32_t nblocks;
+    int32_t family;
+    int32_t out_index;
+};
+int launch_block_gather(const BlockSub* subs, int nsub, const double* params, double* sub_params, void* stream);
+int launch_block_combine(const BlockProb* probs, int n, const double* sub_out, const double* sub_bound,
+                         const double* params, double* out, double* bound, void* stream);
+
 // Record tables (FP64 and FP32 pools) of one (rule, K) in the static layout.
 bool build_records(const DeltaTable& t, std::vector<double>& rec64, std::vector<float>& rec32,
                    std::string& err);

@@ -50,7 +50,8 @@ _lib = None
 EXPORTS = ["sg_context_create", "sg_context_destroy", "sg_status_string", "sg_last_error", "sg_counts",
            "sg_rule_table", "sg_coefficient", "sg_unrank", "sg_unrank_device", "sg_plan_create",
            "sg_plan_execute", "sg_plan_execute_grad", "sg_plan_get_info", "sg_plan_autotune",
-           "sg_plan_set_schedule", "sg_plan_destroy", "sg_integrate", "sg_integrate_points"]
+           "sg_plan_set_schedule", "sg_plan_destroy", "sg_integrate", "sg_integrate_points",
+           "sg_plan_create_blocked"]
 
 
 def lib():
@@ -74,6 +75,7 @@ def lib():
         "sg_unrank": ([i32, i32, u64, P(i32), P(i32), P(i32)], i32),
         "sg_unrank_device": ([vp, i32, i32, u64, u64, i32, vp, vp, vp, vp], i32),
         "sg_plan_create": ([vp, P(SgProblem), i32, i32, P(vp)], i32),
+        "sg_plan_create_blocked": ([vp, P(SgProblem), i32, i32, i32, P(vp)], i32),
         "sg_plan_execute": ([vp, vp, vp, vp, vp], i32),
         "sg_plan_execute_grad": ([vp, vp, vp, vp, vp], i32),
         "sg_plan_get_info": ([vp, P(SgPlanInfo)], i32),
@@ -184,15 +186,23 @@ def make_problems(problems) -> ctypes.Array:
 class Plan:
     """A compiled batch: sg_plan_create / execute / execute_grad / destroy."""
 
-    def __init__(self, problems: Sequence, precision: str = "fp64", ctx: Optional[Context] = None):
+    def __init__(self, problems: Sequence, precision: str = "fp64", ctx: Optional[Context] = None,
+                 block_dims: int = 0):
+        """block_dims > 0: the block (tensor-product) variant of the rule,
+        sg_plan_create_blocked, with blocks of that many coordinates."""
         self.ctx = ctx or default_context()
         self.n = len(problems)
         self.problems = list(problems)
         self._arr = make_problems(problems)
         self.handle = ctypes.c_void_p()
         self.precision = precision
-        _check(lib().sg_plan_create(self.ctx.handle, self._arr, self.n, PRECISIONS[precision],
-                                    ctypes.byref(self.handle)), self.ctx.handle)
+        self.block_dims = int(block_dims)
+        if self.block_dims > 0:
+            _check(lib().sg_plan_create_blocked(self.ctx.handle, self._arr, self.n, PRECISIONS[precision],
+                                                self.block_dims, ctypes.byref(self.handle)), self.ctx.handle)
+        else:
+            _check(lib().sg_plan_create(self.ctx.handle, self._arr, self.n, PRECISIONS[precision],
+                                        ctypes.byref(self.handle)), self.ctx.handle)
         self._exec = lib().sg_plan_execute
 
     def info(self) -> dict:
