@@ -36,8 +36,8 @@ PAIR_EVAL_FLOPS = 8.0   # one centred node-pair evaluation = one quarter-rate tr
 # --copy-probe-mb), keyed by precision and by a hash of the kernel sources
 # the counters were taken on; any other source hash reports null.
 MEASURED_TRAFFIC = {
-    ("fp32c", "a13da1d0e9ec181d"): 8358966.0,
-    ("fp32e", "a13da1d0e9ec181d"): 8184709.0,
+    ("fp32c", "7bb974a4ac6cacfe"): 8359350.0,
+    ("fp32e", "7bb974a4ac6cacfe"): 8185669.0,
 }
 
 
@@ -94,6 +94,17 @@ def algorithmic_flops(info) -> float:
     """Flop-slots of one forward launch: pair evaluations x 8 + 2 x MACs +
     sweep merge flops (see the plan info fields)."""
     return PAIR_EVAL_FLOPS * info["pair_evals"] + 2.0 * info["macs"] + info["merge_flops"]
+
+
+def adjoint_flop_slots(info, problems) -> float:
+    """Flop-slots of one reverse sweep: the forward surpluses and the
+    derivative surpluses (each as in algorithmic_flops, without the merge),
+    per unit the prefix, suffix and exclusion products of truncated
+    polynomials (3 K^2) and the contraction with the derivative surpluses
+    (2 K)."""
+    surpl = PAIR_EVAL_FLOPS * info["pair_evals"] + 2.0 * info["macs"]
+    per_unit = sum(p.d * (3 * (p.q - p.d) ** 2 + 2 * (p.q - p.d)) for p in problems)
+    return 2.0 * surpl + float(per_unit)
 
 
 def points_flop_slots(d: int, q: int, rule: str):
@@ -560,8 +571,13 @@ def main():
             for i, p in enumerate(gb.problems):
                 sl = slice(p.param_offset, p.param_offset + p.d + 1)
                 errs.append(np.max(np.abs(g[sl] - gref[sl])) / np.max(np.abs(gref[sl])))
-            adj[prec] = {"grad_ms": e0.elapsed_time(e1) / reps, "forward_ms": f0.elapsed_time(f1) / reps,
-                         "max_rel_err_vs_oracle_grad": float(np.max(errs))}
+            gms = e0.elapsed_time(e1) / reps
+            slots = adjoint_flop_slots(plan.info(), gb.problems)
+            ach = slots / (gms / 1e3) / 1e12
+            adj[prec] = {"grad_ms": gms, "forward_ms": f0.elapsed_time(f1) / reps,
+                         "max_rel_err_vs_oracle_grad": float(np.max(errs)),
+                         "roofline": {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                      "frac": ach / VALU_PEAK_TFLOPS, "flop_slots_per_launch": slots}}
             plan.close()
         extras["adjoint_gradient_osc_d200_n256"] = adj
 
