@@ -25,6 +25,11 @@ def n_level(rule: str, level: int) -> int:
         return 2 * level - 1
     if rule == "gl_paper":
         return level
+    if rule == "gp":
+        # Gauss-Patterson, level-to-points map of Section 5.4 (q = 1..10)
+        if level > 10:
+            raise ValueError(level)
+        return (1, 3, 3, 7, 7, 7, 15, 15, 15, 15)[level - 1]
     raise ValueError(rule)
 
 
@@ -77,14 +82,19 @@ def _node_ids(rule: str, level: int) -> List[object]:
 
     Nested rules (trapezoidal, Clenshaw-Curtis) place node j of an n-point
     level at a position fixed by the fraction j/(n-1), so that fraction is the
-    identity.  Gauss-Legendre levels share only the centre (the zero of the odd
+    identity (Gauss-Patterson: (j+1)/(n+1)).  Gauss-Legendre levels share only the centre (the zero of the odd
     Legendre polynomials); any other node is identified by (level, index).
     """
     n = n_level(rule, level)
     if n == 1:
-        return [Fraction(1, 2)] if rule in ("tr", "cc") else ["centre"]
+        return [Fraction(1, 2)] if rule in ("tr", "cc", "gp") else ["centre"]
     if rule in ("tr", "cc"):
         return [Fraction(j, n - 1) for j in range(n)]
+    if rule == "gp":
+        # each Patterson extension interlaces its new nodes with the old
+        # ones, so node j of an n-point level is node 2j+1 of the next:
+        # (j+1)/(n+1) identifies it on every finer level
+        return [Fraction(j + 1, n + 1) for j in range(n)]
     ids: List[object] = []
     for j in range(n):
         if n % 2 == 1 and j == n // 2:
@@ -143,8 +153,9 @@ def counts_by_generating_function(d: int, q: int, rule: str) -> Dict[str, int]:
 def unique_points_by_generating_function(d: int, q: int, rule: str) -> int:
     """Number of distinct points of the sparse grid.
 
-    Nested rules: a point is in the grid iff the levels at which its
-    coordinates first appear sum to at most q, so the count is
+    Nested rules (trapezoidal, Clenshaw-Curtis, Gauss-Patterson): a point
+    is in the grid iff the levels at which its coordinates first appear sum
+    to at most q, so the count is
     sum_{e<=K} [z^e] M(z)^d with M(z) = sum_l (n_l - n_{l-1}) z^(l-1).
 
     Gauss-Legendre: a coordinate either sits at the centre (present at every
@@ -153,7 +164,7 @@ def unique_points_by_generating_function(d: int, q: int, rule: str) -> int:
     some window multi-index reaches it; see the inline conditions.
     """
     K = q - d
-    if rule in ("tr", "cc"):
+    if rule in ("tr", "cc", "gp"):
         M = [n_level(rule, 1)] + [n_level(rule, l) - n_level(rule, l - 1) for l in range(2, K + 2)]
         MP = _poly_pow_trunc(M, d, K)
         return sum(MP[: K + 1])

@@ -47,7 +47,7 @@
 typedef __float128 f128;
 typedef long double fld;
 
-enum { OR_TR = 1, OR_CC = 2, OR_GL = 4, OR_GL_PAPER = 5 };
+enum { OR_TR = 1, OR_CC = 2, OR_GP = 3, OR_GL = 4, OR_GL_PAPER = 5 };
 enum { OR_EXP = 0, OR_OSC = 1, OR_PEAK = 2, OR_MONO = 3, OR_CORNER = 4 };
 
 #define OR_MAX_LEVEL 16
@@ -69,6 +69,12 @@ long or_rule_npoints(int rule, int level)
         return (1L << (level - 1)) + 1;         /* (2.10), (2.11): 2^(l-1)+1 */
     case OR_GL: return 2L * level - 1;           /* 2l-1 points */
     case OR_GL_PAPER: return level;              /* (2.13): n_l = l */
+    case OR_GP: {
+        /* (2.12) with the level-to-points map of Section 5.4:
+         * q = 1..10 <-> N = 1, 3, 3, 7, 7, 7, 15, 15, 15, 15 */
+        static const long map[11] = {0, 1, 3, 3, 7, 7, 7, 15, 15, 15, 15};
+        return level <= 10 ? map[level] : -1;
+    }
     default: return -1;
     }
 }
@@ -84,6 +90,163 @@ static void legendre_q(int n, f128 t, f128 *p, f128 *dp)
     }
     *p = p1;
     *dp = n * (t * p1 - p0) / (t * t - 1);
+}
+
+/* Legendre polynomials P_0..P_m at t (three-term recurrence). */
+static void legendre_all_q(int m, f128 t, f128 *P)
+{
+    P[0] = 1;
+    if (m >= 1) P[1] = t;
+    for (int k = 2; k <= m; ++k) P[k] = ((2 * k - 1) * t * P[k - 1] - (k - 1) * P[k - 2]) / k;
+}
+
+/* Gaussian elimination with partial pivoting on an n x n system (row-major
+ * A, right-hand side b, solution in b).  Returns 0, or -1 if singular. */
+static int solve_q(int n, f128 *A, f128 *b)
+{
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (fabsq(A[r * n + c]) > fabsq(A[piv * n + c])) piv = r;
+        if (A[piv * n + c] == 0) return -1;
+        if (piv != c) {
+            for (int j = 0; j < n; ++j) { f128 t = A[c * n + j]; A[c * n + j] = A[piv * n + j]; A[piv * n + j] = t; }
+            f128 t = b[c]; b[c] = b[piv]; b[piv] = t;
+        }
+        for (int r = c + 1; r < n; ++r) {
+            f128 f = A[r * n + c] / A[c * n + c];
+            for (int j = c; j < n; ++j) A[r * n + j] -= f * A[c * n + j];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int r = n - 1; r >= 0; --r) {
+        f128 s = b[r];
+        for (int j = r + 1; j < n; ++j) s -= A[r * n + j] * b[j];
+        b[r] = s / A[r * n + r];
+    }
+    return 0;
+}
+
+/*
+ * One Kronrod-Patterson extension on [-1,1] (Example 3 of Section 2.2): the
+ * n (odd) symmetric nodes t[] of the previous rule, with node polynomial
+ * pi(t) = prod (t - t_i), gain the n+1 zeros of the polynomial G of degree
+ * n+1 orthogonal to every polynomial of degree <= n with respect to the
+ * weight pi.  G is written in the Legendre basis, G = P_{n+1} + sum c_j P_j;
+ * pi is odd and G even, so only even j and the conditions against odd P_k
+ * remain: (n+1)/2 linear equations, their integrals taken by a Gauss-Legendre
+ * rule exact for the degree.  The new zeros interlace with the old nodes (one
+ * between consecutive positive old nodes, one beyond the last, one below the
+ * first) and are found by bisection.  Returns the new node count, or -1.
+ */
+/* G(u) = P_m(u) + sum_c b[c] P_{2c}(u). */
+static f128 g_at(int m, int h, const f128 *b, f128 u)
+{
+    f128 P[64];
+    legendre_all_q(m, u, P);
+    f128 s = P[m];
+    for (int c = 0; c < h; ++c) s += b[c] * P[2 * c];
+    return s;
+}
+
+static int patterson_extend_q(int n, const f128 *t, f128 *tn)
+{
+    enum { NG = 48 };
+    static __thread f128 gx[NG], gw[NG];
+    static __thread int gl_ready = 0;
+    if (!gl_ready) {
+        f128 xq[NG], wq[NG];
+        for (long i = 1; i <= NG; ++i) {
+            f128 u = cosq(M_PIq * (i - 0.25Q) / (NG + 0.5Q));
+            for (int it = 0; it < 100; ++it) {
+                f128 p, dp;
+                legendre_q(NG, u, &p, &dp);
+                f128 du = p / dp;
+                u -= du;
+                if (fabsq(du) < 1e-33Q) break;
+            }
+            f128 p, dp;
+            legendre_q(NG, u, &p, &dp);
+            xq[i - 1] = u;
+            wq[i - 1] = 2 / ((1 - u * u) * dp * dp);
+        }
+        for (int i = 0; i < NG; ++i) { gx[i] = xq[i]; gw[i] = wq[i]; }
+        gl_ready = 1;
+    }
+    const int m = n + 1, h = (n + 1) / 2;
+    if (3 * n + 1 > 2 * NG - 1 || h > 32) return -1;
+    f128 A[32 * 32], b[32], P[64];
+    for (int r = 0; r < h; ++r) {
+        const int k = 2 * r + 1;                    /* odd P_k */
+        for (int c = 0; c < h; ++c) A[r * h + c] = 0;
+        b[r] = 0;
+        for (int g = 0; g < NG; ++g) {
+            f128 pi = 1;
+            for (int i = 0; i < n; ++i) pi *= gx[g] - t[i];
+            legendre_all_q(m, gx[g], P);
+            const f128 f = gw[g] * pi * P[k];
+            for (int c = 0; c < h; ++c) A[r * h + c] += f * P[2 * c];   /* even P_j, j = 2c < m */
+            b[r] -= f * P[m];
+        }
+    }
+    if (solve_q(h, A, b) != 0) return -1;
+    /* positive old nodes, ascending */
+    f128 pos[32];
+    int np = 0;
+    for (int i = 0; i < n; ++i) if (t[i] > 0) pos[np++] = t[i];
+    for (int i = 1; i < np; ++i) for (int j = i; j > 0 && pos[j] < pos[j - 1]; --j) {
+        f128 tt = pos[j]; pos[j] = pos[j - 1]; pos[j - 1] = tt;
+    }
+    if (np + 1 != h) return -1;
+    int cnt = 0;
+    for (int iv = 0; iv <= np; ++iv) {
+        f128 lo = iv == 0 ? 0 : pos[iv - 1], hi = iv == np ? 1 : pos[iv];
+        f128 glo, ghi;
+        glo = g_at(m, h, b, lo);
+        ghi = g_at(m, h, b, hi);
+        if (glo == 0 || ghi == 0 || (glo > 0) == (ghi > 0)) return -1;   /* no sign change: not interlacing */
+        for (int it = 0; it < 240; ++it) {
+            f128 mid = (lo + hi) / 2, gm;
+            gm = g_at(m, h, b, mid);
+            if ((gm > 0) == (glo > 0)) { lo = mid; glo = gm; } else hi = mid;
+        }
+        tn[cnt++] = (lo + hi) / 2;
+        tn[cnt++] = -(lo + hi) / 2;
+    }
+    return cnt;
+}
+
+/* Gauss-Patterson rule of N = 1, 3, 7 or 15 points on [0,1]: the midpoint,
+ * then Patterson extensions; interpolatory weights from the Legendre moment
+ * equations sum_i w_i P_k(t_i) = 2 [k = 0], k < N (well conditioned). */
+static int patterson_q(long N, f128 *x, f128 *w)
+{
+    f128 t[32], tn[32];
+    int n = 1;
+    t[0] = 0;
+    while (n < N) {
+        int k = patterson_extend_q(n, t, tn);
+        if (k != n + 1) return -1;
+        for (int i = 0; i < k; ++i) t[n + i] = tn[i];
+        n += k;
+    }
+    if (n != N) return -1;
+    for (int i = 1; i < n; ++i) for (int j = i; j > 0 && t[j] < t[j - 1]; --j) {
+        f128 tt = t[j]; t[j] = t[j - 1]; t[j - 1] = tt;
+    }
+    f128 A[32 * 32], b[32], P[32];
+    for (int i = 0; i < n; ++i) {
+        legendre_all_q(n - 1, t[i], P);
+        for (int k = 0; k < n; ++k) A[k * n + i] = P[k];
+    }
+    for (int k = 0; k < n; ++k) b[k] = k == 0 ? 2 : 0;
+    if (solve_q(n, A, b) != 0) return -1;
+    for (int i = 0; i < n; ++i) {
+        x[i] = (1 + t[i]) / 2;
+        w[i] = b[i] / 2;
+    }
+    x[n / 2] = 0.5Q;
+    return n;
 }
 
 /*
@@ -131,6 +294,7 @@ int or_rule_q(int rule, int level, f128 *x, f128 *w)
         }
         return (int)n;
     }
+    if (rule == OR_GP) return patterson_q(n, x, w);
     if (rule == OR_GL || rule == OR_GL_PAPER) {
         /* (2.13): zeros of P_n, Newton iteration from Chebyshev-like guesses;
          * weights 2/((1-t^2) P_n'(t)^2) on [-1,1]. */

@@ -32,7 +32,7 @@ def test_enumeration_is_the_window_in_canonical_order(d, q):
     assert len(set(got)) == len(got)
 
 
-@pytest.mark.parametrize("rule", ["tr", "cc", "gl", "gl_paper"])
+@pytest.mark.parametrize("rule", ["tr", "cc", "gl", "gl_paper", "gp"])
 @pytest.mark.parametrize("d,q", [(1, 1), (1, 5), (2, 4), (2, 7), (3, 6), (3, 8), (4, 7), (5, 9), (6, 8)])
 def test_generating_function_matches_enumeration(rule, d, q):
     gf = C.counts_by_generating_function(d, q, rule)

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 from numpy.polynomial.legendre import leggauss
 
-RULES = ["tr", "cc", "gl", "gl_paper"]
+RULES = ["tr", "cc", "gl", "gl_paper", "gp"]
 
 
 @pytest.mark.parametrize("rule", RULES)
@@ -91,7 +91,7 @@ def test_trapezoid_error_on_square(orc, level):
     assert abs((np.sum(w * x ** 2) - 1 / 3) - h * h / 6) < 1e-15
 
 
-@pytest.mark.parametrize("rule", ["tr", "cc"])
+@pytest.mark.parametrize("rule", ["tr", "cc", "gp"])
 def test_nested_rules_are_nested(orc, rule):
     for level in range(1, 8):
         a, _ = orc.rule(rule, level)
@@ -109,3 +109,34 @@ def test_gauss_legendre_levels_share_only_the_centre(orc, rule):
             close = diff < 1e-9
             for a, b in zip(*np.nonzero(close)):
                 assert abs(xs[i][a] - 0.5) < 1e-15 and abs(xs[j][b] - 0.5) < 1e-15
+
+
+# ------------------------------------------------------ Gauss-Patterson
+def test_gauss_patterson_level_map_of_section_5_4(orc):
+    # Section 5.4 lists, for the Gauss-Patterson rule, q = 1..10 <-> N =
+    # 1, 3, 3, 7, 7, 7, 15, 15, 15, 15
+    assert [orc.rule_npoints("gp", l) for l in range(1, 11)] == [1, 3, 3, 7, 7, 7, 15, 15, 15, 15]
+    assert orc.rule_npoints("gp", 11) == -1
+
+
+def test_gauss_patterson_three_points_is_gauss(orc):
+    # the first Patterson extension of the midpoint is the 3-point Gauss rule
+    x, w = orc.rule("gp", 2)
+    t = np.sqrt(0.6)
+    assert np.max(np.abs(x - np.array([(1 - t) / 2, 0.5, (1 + t) / 2]))) < 1e-16
+    assert np.max(np.abs(w - np.array([5, 8, 5]) / 18.0)) < 1e-16
+
+
+@pytest.mark.parametrize("level,degree", [(2, 5), (4, 11), (7, 23)])
+def test_gauss_patterson_exactness_degree(orc, level, degree):
+    # Kronrod-Patterson extensions: 3 points exact to degree 5, 7 points to
+    # 3*3 + 2 = 11, 15 points to 3*7 + 2 = 23; with the nesting below this
+    # fixes each rule uniquely (the extension of a rule by n + 1 nodes
+    # reaching that degree is unique)
+    x, w = orc.rule("gp", level)
+    for k in range(degree + 1):
+        assert _moment_err(x, w, k) < 5e-16, (level, k)
+    # one degree more (even, centred) is not exact
+    c = np.sum(w * (x - 0.5) ** (degree + 1))
+    exact = 2 * 0.5 ** (degree + 2) / (degree + 2)
+    assert abs(c - exact) > 1e-10 * exact

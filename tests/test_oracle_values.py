@@ -25,12 +25,74 @@ U64 = 2.0 ** -64
 
 
 # ------------------------------------------------------------- brute force
+_GP_CACHE = {}
+
+
+def _mp_patterson(npts):
+    """Gauss-Patterson nodes and weights on [0,1] built without the oracle:
+    each extension's new nodes are the roots (mpmath polyroots, 50 digits)
+    of the monic polynomial of degree n+1 orthogonal, against the previous
+    nodes' polynomial, to every lower degree (monomial basis, exact moments);
+    weights from the monomial moment equations at 50 digits."""
+    if npts in _GP_CACHE:
+        return _GP_CACHE[npts]
+    with mp.workdps(50):
+        mom = lambda k: mp.mpf(2) / (k + 1) if k % 2 == 0 else mp.mpf(0)
+
+        def pmul(a, b):
+            r = [mp.mpf(0)] * (len(a) + len(b) - 1)
+            for i, x in enumerate(a):
+                for j, y in enumerate(b):
+                    r[i + j] += x * y
+            return r
+        nodes = [mp.mpf(0)]
+        while len(nodes) < npts:
+            n = len(nodes)
+            pi = [mp.mpf(1)]
+            for t in nodes:
+                pi = pmul(pi, [-t, mp.mpf(1)])
+            m = n + 1
+            A = mp.matrix(m, m)
+            rhs = mp.matrix(m, 1)
+            for k in range(m):
+                for j in range(m):
+                    A[k, j] = sum(c * mom(i + j + k) for i, c in enumerate(pi))
+                rhs[k] = -sum(c * mom(i + m + k) for i, c in enumerate(pi))
+            # pi is odd and the extension even: keep the non-trivial equations
+            idx = [j for j in range(m) if (j - m) % 2 == 0]
+            rows = [k for k in range(m) if (k + n + m) % 2 == 0]
+            B = mp.matrix(len(rows), len(idx))
+            r = mp.matrix(len(rows), 1)
+            for a_, k in enumerate(rows):
+                for b_, j in enumerate(idx):
+                    B[a_, b_] = A[k, j]
+                r[a_] = rhs[k]
+            cc = mp.lu_solve(B, r)
+            coef = [mp.mpf(0)] * m
+            for b_, j in enumerate(idx):
+                coef[j] = cc[b_]
+            roots = mp.polyroots((coef + [mp.mpf(1)])[::-1], maxsteps=400, extraprec=400)
+            nodes = sorted(nodes + [mp.re(z) for z in roots])
+        V = mp.matrix(npts, npts)
+        b = mp.matrix(npts, 1)
+        for k in range(npts):
+            for i in range(npts):
+                V[k, i] = nodes[i] ** k
+            b[k] = mom(k)
+        w = mp.lu_solve(V, b)
+        res = (np.array([float((1 + t) / 2) for t in nodes]), np.array([float(w[i] / 2) for i in range(npts)]))
+    _GP_CACHE[npts] = res
+    return res
+
+
 def _numpy_rule(rule, level):
     """1-D rules built without the oracle: numpy's Gauss-Legendre, and
     interpolatory weights from Legendre moments for the Clenshaw-Curtis
-    nodes; trapezoid directly."""
+    nodes; trapezoid directly; Gauss-Patterson with mpmath."""
     if level == 1:
         return np.array([0.5]), np.array([1.0])
+    if rule == "gp":
+        return _mp_patterson((1, 3, 3, 7, 7, 7, 15, 15, 15, 15)[level - 1])
     if rule == "gl" or rule == "gl_paper":
         n = 2 * level - 1 if rule == "gl" else level
         t, w = npleg.leggauss(n)
@@ -78,7 +140,7 @@ def brute_smolyak(d, q, rule, family, params):
 
 
 SMALL = [(d, q, r, f) for (d, q) in [(1, 3), (2, 3), (2, 5), (3, 5), (3, 6), (4, 6)]
-         for r in ("tr", "cc", "gl", "gl_paper")
+         for r in ("tr", "cc", "gl", "gl_paper", "gp")
          for f in ("exp_sum", "oscillatory", "product_peak", "corner_peak")]
 
 
@@ -156,7 +218,7 @@ def test_corner_peak_converges_to_closed_form(orc, d, q):
 
 def test_rule_integrates_one_exactly(orc):
     # f = 1 (exp-sum with c = 0): the signed combination weights total 1
-    for rule in ("tr", "cc", "gl", "gl_paper"):
+    for rule in ("tr", "cc", "gl", "gl_paper", "gp"):
         for d, q in [(1, 4), (3, 7), (7, 10), (20, 23)]:
             r = orc.smolyak_points(d, q, rule, "exp_sum", np.zeros(d), centred=False)
             assert abs(r["q"] - 1.0) < 1e-15
@@ -168,6 +230,7 @@ def _level_needed(rule, alpha):
     deg = {"cc": lambda l: 1 if l == 1 else 2 ** (l - 1) + 1,
            "gl": lambda l: 4 * l - 3,
            "gl_paper": lambda l: 2 * l - 1,
+           "gp": lambda l: (1, 5, 5, 11, 11, 11, 23, 23, 23, 23)[l - 1] if l <= 10 else 23,
            "tr": lambda l: 1}[rule]
     e = 0
     while deg(e + 1) < alpha:
@@ -177,7 +240,7 @@ def _level_needed(rule, alpha):
     return e
 
 
-@pytest.mark.parametrize("rule", ["cc", "gl", "gl_paper"])
+@pytest.mark.parametrize("rule", ["cc", "gl", "gl_paper", "gp"])
 def test_polynomial_exactness(orc, rule):
     # Smolyak's rule integrates prod (x_i - s)^alpha_i exactly when the levels
     # that integrate each factor exactly fit into the excess budget K.
@@ -290,7 +353,7 @@ def test_dimension_padding(orc):
 
 
 def test_one_dimension_is_the_1d_rule(orc):
-    for rule in ("tr", "cc", "gl", "gl_paper"):
+    for rule in ("tr", "cc", "gl", "gl_paper", "gp"):
         for q in (1, 3, 6):
             c = np.array([0.7])
             x, w = orc.rule(rule, q)
