@@ -56,6 +56,9 @@ typedef enum {
 typedef enum {
     SG_RULE_TRAPEZOID = 1,           /* (2.10): n_1 = 1, n_l = 2^(l-1)+1, nested */
     SG_RULE_CLENSHAW_CURTIS = 2,     /* (2.11): n_1 = 1, n_l = 2^(l-1)+1, nested */
+    SG_RULE_GAUSS_PATTERSON = 3,     /* (2.12): Patterson extensions, nested, with the level
+                                        map of Section 5.4: levels 1..10 have 1, 3, 3, 7, 7, 7,
+                                        15, 15, 15, 15 points (K <= 8 uses at most 15) */
     SG_RULE_GAUSS_LEGENDRE = 4,      /* Gauss-Legendre with n_l = 2l-1 points */
     SG_RULE_GAUSS_LEGENDRE_PAPER = 5 /* (2.13): Gauss-Legendre with n_l = l points */
 } sg_rule;

@@ -864,12 +864,14 @@ __device__ __forceinline__ void wave_dispatch_k(int rule, int family, const Wave
         if (rule == SG_RULE_CLENSHAW_CURTIS) SG_FAMS(SG_RULE_CLENSHAW_CURTIS);
         else if (rule == SG_RULE_TRAPEZOID) SG_FAMS(SG_RULE_TRAPEZOID);
         else if (rule == SG_RULE_GAUSS_LEGENDRE) SG_FAMS(SG_RULE_GAUSS_LEGENDRE);
+        else if (rule == SG_RULE_GAUSS_PATTERSON) SG_FAMS(SG_RULE_GAUSS_PATTERSON);
         else SG_FAMS(SG_RULE_GAUSS_LEGENDRE_PAPER);
     } else {
         // table-driven only: one instantiation per structure class
         const int rc = rule_class_of(rule);
         if (rc == RC_NESTED) SG_FAMS(SG_RULE_CLENSHAW_CURTIS);
         else if (rc == RC_GL2) SG_FAMS(SG_RULE_GAUSS_LEGENDRE);
+        else if (rc == RC_GP) SG_FAMS(SG_RULE_GAUSS_PATTERSON);
         else SG_FAMS(SG_RULE_GAUSS_LEGENDRE_PAPER);
     }
 #undef SG_FAMS
@@ -895,6 +897,7 @@ __device__ __forceinline__ void group_finish_k(int rule, int family, int group, 
     const int rc = rule_class_of(rule);
     const int np = rc == RC_NESTED ? total_pairs<RC_NESTED, K>()
                    : rc == RC_GL2  ? total_pairs<RC_GL2, K>()
+                   : rc == RC_GP   ? total_pairs<RC_GP, K>()
                                    : total_pairs<RC_GLP, K>();
     const int depth = tree_depth(lp.d, 6, group);
     if (family == FAM_EXP) readout<PREC, K, FAM_EXP>(x, lp.d, lp.out_index, prm, np, depth, out, bound);
@@ -1277,6 +1280,10 @@ __device__ __forceinline__ void adjoint_dispatch_k(const ProbDev& P, int rank, i
         if (P.family == FAM_EXP) SG_ADJ(RC_GL2, FAM_EXP);
         else if (P.family == FAM_OSC) SG_ADJ(RC_GL2, FAM_OSC);
         else SG_ADJ(RC_GL2, FAM_PEAK);
+    } else if (rc == RC_GP) {
+        if (P.family == FAM_EXP) SG_ADJ(RC_GP, FAM_EXP);
+        else if (P.family == FAM_OSC) SG_ADJ(RC_GP, FAM_OSC);
+        else SG_ADJ(RC_GP, FAM_PEAK);
     } else {
         if (P.family == FAM_EXP) SG_ADJ(RC_GLP, FAM_EXP);
         else if (P.family == FAM_OSC) SG_ADJ(RC_GLP, FAM_OSC);

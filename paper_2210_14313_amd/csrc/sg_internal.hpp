@@ -60,19 +60,26 @@ sg_status unrank(int d, int q, uint64_t rank, int32_t* coords, int32_t* levels, 
 // pairs entering at level L and the e-range [elo, ehi] their nodes carry
 // weights in.  The kernels unroll over this structure at compile time; the
 // host writes the tables in exactly this order (and checks the counts).
-enum { RC_NESTED = 0, RC_GL2 = 1, RC_GLP = 2 };
+// RC_GP: Gauss-Patterson with the level map 1, 3, 3, 7, 7, 7, 15, ...: new
+// pairs enter at levels 2 (1), 4 (2) and 7 (4); the repeated levels give
+// difference rules that vanish (their rows hold zero weights).
+enum { RC_NESTED = 0, RC_GL2 = 1, RC_GLP = 2, RC_GP = 3 };
 
 constexpr int rule_class_of(int rule)
 {
     return (rule == SG_RULE_TRAPEZOID || rule == SG_RULE_CLENSHAW_CURTIS) ? RC_NESTED
+           : rule == SG_RULE_GAUSS_PATTERSON ? RC_GP
            : rule == SG_RULE_GAUSS_LEGENDRE ? RC_GL2 : RC_GLP;
 }
 constexpr int rc_pairs(int rc, int L)
 {
-    return L < 2 ? 0 : rc == RC_NESTED ? (L == 2 ? 1 : (1 << (L - 3))) : rc == RC_GL2 ? L - 1 : L / 2;
+    return L < 2 ? 0
+           : rc == RC_NESTED ? (L == 2 ? 1 : (1 << (L - 3)))
+           : rc == RC_GP ? (L == 2 ? 1 : L == 4 ? 2 : L == 7 ? 4 : 0)
+           : rc == RC_GL2 ? L - 1 : L / 2;
 }
 constexpr int rc_elo(int L) { return L - 1; }
-constexpr int rc_ehi(int rc, int K, int L) { return rc == RC_NESTED ? K : (L < K ? L : K); }
+constexpr int rc_ehi(int rc, int K, int L) { return (rc == RC_NESTED || rc == RC_GP) ? K : (L < K ? L : K); }
 // FP64 record of one pair: y, dW[elo..ehi], sum_e |dW|
 constexpr int rc_rec64(int rc, int K, int L) { return rc_ehi(rc, K, L) - rc_elo(L) + 3; }
 // FP32 record of one pair: (dW_hi, dW_lo) for e = elo..ehi

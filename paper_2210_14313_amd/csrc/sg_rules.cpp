@@ -3,7 +3,9 @@
 //
 // Trapezoid (2.10) and Clenshaw-Curtis (2.11) use n_1 = 1, n_l = 2^(l-1)+1
 // and are nested; Gauss-Legendre (2.13) uses n_l = l in the paper, and
-// n_l = 2l-1 (odd, so every level holds the centre) in the default mode.
+// n_l = 2l-1 (odd, so every level holds the centre) in the default mode;
+// Gauss-Patterson (2.12) is nested, with the level-to-points map listed in
+// Section 5.4 (1, 3, 3, 7, 7, 7, 15, 15, 15, 15 for levels 1..10).
 // The paper's formulas degenerate for one point (division by n-1 = 0, or a
 // single end node); level 1 is read as the midpoint with weight 1, which
 // keeps the rules nested and symmetric.
@@ -22,18 +24,22 @@ const long double kPi = 3.141592653589793238462643383279502884L;
 
 bool rule_is_known(int rule)
 {
-    return rule == SG_RULE_TRAPEZOID || rule == SG_RULE_CLENSHAW_CURTIS ||
+    return rule == SG_RULE_TRAPEZOID || rule == SG_RULE_CLENSHAW_CURTIS || rule == SG_RULE_GAUSS_PATTERSON ||
            rule == SG_RULE_GAUSS_LEGENDRE || rule == SG_RULE_GAUSS_LEGENDRE_PAPER;
 }
 
 bool rule_is_nested(int rule)
 {
-    return rule == SG_RULE_TRAPEZOID || rule == SG_RULE_CLENSHAW_CURTIS;
+    return rule == SG_RULE_TRAPEZOID || rule == SG_RULE_CLENSHAW_CURTIS || rule == SG_RULE_GAUSS_PATTERSON;
 }
 
 long rule_npoints(int rule, int level)
 {
     if (level < 1 || !rule_is_known(rule)) return -1;
+    if (rule == SG_RULE_GAUSS_PATTERSON) {
+        static const long kMap[11] = {0, 1, 3, 3, 7, 7, 7, 15, 15, 15, 15};
+        return level <= 10 ? kMap[level] : -1;
+    }
     if (rule_is_nested(rule)) {
         if (level == 1) return 1;
         if (level > 17) return -1;
@@ -128,6 +134,114 @@ static void gauss_legendre(long n, std::vector<long double>& x, std::vector<long
     }
 }
 
+// Gauss-Patterson rules of 1, 3, 7 and 15 points (Example 3 of Section
+// 2.2), on [0,1].  Each step adds to the symmetric n-point rule (n odd,
+// nodes t_i on [-1,1]) the n+1 zeros of the polynomial G of degree n+1 that
+// is orthogonal to all lower degrees with respect to the weight
+// pi(t) = prod (t - t_i).  pi is odd and G even, so with G written in the
+// Chebyshev basis, G = T_{n+1} + sum_{j even} c_j T_j, the conditions are
+//   int_{-1}^{1} pi(t) G(t) T_k(t) dt = 0,   k odd <= n,
+// (n+1)/2 linear equations whose integrals a Gauss-Legendre rule evaluates
+// exactly.  The zeros of G interlace with the old nodes (one between 0 and
+// the first positive node, one between consecutive ones, one above the
+// last) and are found by bisection.  Weights: the integrals of the Lagrange
+// basis polynomials, by a Gauss-Legendre rule exact for their degree.
+static void chebyshev_all(int m, long double t, long double* T)
+{
+    T[0] = 1.0L;
+    if (m >= 1) T[1] = t;
+    for (int k = 2; k <= m; ++k) T[k] = 2.0L * t * T[k - 1] - T[k - 2];
+}
+
+static bool gauss_patterson(long N, std::vector<long double>& x, std::vector<long double>& w)
+{
+    std::vector<long double> gx, gw;
+    gauss_legendre(32, gx, gw);              // on [0,1]; exact for degree 63 >= 3n + 1
+    std::vector<long double> t(1, 0.0L);     // nodes on [-1,1]
+    long n = 1;
+    long double T[64];
+    while (n < N) {
+        const int m = (int)n + 1, h = m / 2;
+        std::vector<long double> A((size_t)h * h, 0.0L), rhs(h, 0.0L);
+        for (size_t g = 0; g < gx.size(); ++g) {
+            const long double u = 2.0L * gx[g] - 1.0L, wg = 2.0L * gw[g];
+            long double pi = 1.0L;
+            for (long double ti : t) pi *= u - ti;
+            chebyshev_all(m, u, T);
+            for (int r = 0; r < h; ++r) {
+                const long double f = wg * pi * T[2 * r + 1];
+                for (int c = 0; c < h; ++c) A[(size_t)r * h + c] += f * T[2 * c];
+                rhs[r] -= f * T[m];
+            }
+        }
+        for (int c = 0; c < h; ++c) {        // elimination with partial pivoting
+            int piv = c;
+            for (int r = c + 1; r < h; ++r)
+                if (std::fabs(A[(size_t)r * h + c]) > std::fabs(A[(size_t)piv * h + c])) piv = r;
+            if (A[(size_t)piv * h + c] == 0.0L) return false;
+            for (int j = 0; j < h; ++j) std::swap(A[(size_t)c * h + j], A[(size_t)piv * h + j]);
+            std::swap(rhs[c], rhs[piv]);
+            for (int r = c + 1; r < h; ++r) {
+                const long double f = A[(size_t)r * h + c] / A[(size_t)c * h + c];
+                for (int j = c; j < h; ++j) A[(size_t)r * h + j] -= f * A[(size_t)c * h + j];
+                rhs[r] -= f * rhs[c];
+            }
+        }
+        std::vector<long double> c(h, 0.0L);
+        for (int r = h - 1; r >= 0; --r) {
+            long double sum = rhs[r];
+            for (int j = r + 1; j < h; ++j) sum -= A[(size_t)r * h + j] * c[j];
+            c[r] = sum / A[(size_t)r * h + r];
+        }
+        auto G = [&](long double u) {
+            chebyshev_all(m, u, T);
+            long double v = T[m];
+            for (int j = 0; j < h; ++j) v += c[j] * T[2 * j];
+            return v;
+        };
+        std::vector<long double> ends(1, 0.0L);
+        for (long double ti : t)
+            if (ti > 0.0L) ends.push_back(ti);
+        std::sort(ends.begin(), ends.end());
+        ends.push_back(1.0L);
+        std::vector<long double> added;
+        for (size_t iv = 0; iv + 1 < ends.size(); ++iv) {
+            long double lo = ends[iv], hi = ends[iv + 1];
+            long double glo = G(lo), ghi = G(hi);
+            if (glo == 0.0L || ghi == 0.0L || (glo > 0.0L) == (ghi > 0.0L)) return false;
+            for (int it = 0; it < 128; ++it) {
+                const long double mid = 0.5L * (lo + hi), gm = G(mid);
+                if ((gm > 0.0L) == (glo > 0.0L)) { lo = mid; glo = gm; } else hi = mid;
+            }
+            added.push_back(0.5L * (lo + hi));
+        }
+        for (long double v : added) {
+            t.push_back(v);
+            t.push_back(-v);
+        }
+        n = (long)t.size();
+    }
+    if (n != N) return false;
+    std::sort(t.begin(), t.end());
+    x.assign(N, 0.5L);
+    for (long i = 0; i < N; ++i) x[i] = i == N / 2 ? 0.5L : 0.5L + 0.5L * t[i];
+    // Lagrange integrals on [0,1] by a Gauss-Legendre rule exact for degree N - 1
+    std::vector<long double> lx, lw;
+    gauss_legendre(N + 1, lx, lw);
+    w.assign(N, 0.0L);
+    for (long i = 0; i < N; ++i) {
+        long double sum = 0.0L;
+        for (size_t k = 0; k < lx.size(); ++k) {
+            long double L = 1.0L;
+            for (long j = 0; j < N; ++j)
+                if (j != i) L *= (lx[k] - x[j]) / (x[i] - x[j]);
+            sum += lw[k] * L;
+        }
+        w[i] = sum;
+    }
+    return true;
+}
+
 bool rule_nodes(int rule, int level, std::vector<long double>& x, std::vector<long double>& w)
 {
     const long n = rule_npoints(rule, level);
@@ -152,14 +266,20 @@ bool rule_nodes(int rule, int level, std::vector<long double>& x, std::vector<lo
         clenshaw_curtis(n, x, w);
         return true;
     }
+    if (rule == SG_RULE_GAUSS_PATTERSON) return gauss_patterson(n, x, w);
     gauss_legendre(n, x, w);
     return true;
 }
 
 // Position of a nested node as an exact integer on the finest grid of the
-// table (index on the level-(K+1) grid of 2^K + 1 points).
-static long nested_slot(long j, long n_level, long n_fine)
+// table (index on the level-(K+1) grid).  Trapezoid and Clenshaw-Curtis:
+// node j of n sits at j (n_fine - 1)/(n - 1).  Gauss-Patterson: each
+// extension interlaces its new nodes with the old ones, so node j of n sits
+// at (j + 1)(n_fine + 1)/(n + 1) - 1.
+static long nested_slot(int rule, long j, long n_level, long n_fine)
 {
+    if (rule == SG_RULE_GAUSS_PATTERSON) return (j + 1) * ((n_fine + 1) / (n_level + 1)) - 1;
+    if (n_level == 1) return (n_fine - 1) / 2;
     return j * ((n_fine - 1) / (n_level - 1));
 }
 
@@ -185,7 +305,7 @@ bool build_delta_table(int rule, int K, DeltaTable& t, std::string& err)
             PairW pw;
             pw.y = 0.5L - x[j];
             pw.w = w[j];
-            pw.key = t.nested ? nested_slot(j, n, n_fine) : (long)l * 100000 + j;
+            pw.key = t.nested ? nested_slot(rule, j, n, n_fine) : (long)l * 100000 + j;
             lev[l].push_back(pw);
         }
     }

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 # SGMDI_LIB: developer override of the library file (kernel variants)
 LIB_PATH = os.environ.get("SGMDI_LIB") or os.path.join(_HERE, "libsgmdi.so")
 
-RULES = {"tr": 1, "cc": 2, "gl": 4, "gl_paper": 5}
+RULES = {"tr": 1, "cc": 2, "gp": 3, "gl": 4, "gl_paper": 5}
 FAMILIES = {"exp_sum": 0, "oscillatory": 1, "product_peak": 2, "corner_peak": 3}
 PRECISIONS = {"fp64": 0, "fp32c": 1, "fp32e": 2}
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "overflow", 4: "out of memory",

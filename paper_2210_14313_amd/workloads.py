@@ -33,6 +33,9 @@ from typing import List, Sequence
 import numpy as np
 
 RULES = ("tr", "cc", "gl", "gl_paper")
+# every rule a problem may name; the default mixes above keep the four
+# original rules so that seeded workloads do not change
+ALL_RULES = RULES + ("gp",)
 #: families the factorised sweep handles (they factor per coordinate)
 FAMILIES = ("exp_sum", "oscillatory", "product_peak")
 #: families only the point-by-point path handles (ridge functions that do not factor)
@@ -104,7 +107,7 @@ class _Builder:
         self.off = 0
 
     def add(self, d: int, q: int, rule: str, family: str, params: np.ndarray):
-        assert rule in RULES and (family in FAMILIES or family in POINT_ONLY_FAMILIES)
+        assert rule in ALL_RULES and (family in FAMILIES or family in POINT_ONLY_FAMILIES)
         params = np.asarray(params, dtype=np.float64).ravel()
         assert params.size == n_params(family, d)
         self.problems.append(Problem(int(d), int(q), rule, family, self.off))

@@ -31,7 +31,7 @@ def test_status_strings(L):
         assert L.sg_status_string(s)
 
 
-CASES = [(d, q, r) for r in ("tr", "cc", "gl", "gl_paper")
+CASES = [(d, q, r) for r in ("tr", "cc", "gl", "gl_paper", "gp")
          for d, q in [(1, 1), (1, 6), (2, 4), (2, 9), (3, 7), (5, 9), (7, 12), (10, 14), (12, 12)]]
 
 
@@ -65,7 +65,7 @@ def test_counts_overflow_is_reported():
         native.counts(3, 2, "cc")
     assert e.value.status == 1
     # an unknown rule id
-    assert native.lib().sg_counts(3, 5, 3, None, None, None) == 1
+    assert native.lib().sg_counts(3, 5, 6, None, None, None) == 1
 
 
 @pytest.mark.parametrize("d,q", [(1, 4), (2, 5), (3, 7), (5, 9), (6, 8), (9, 11)])
@@ -115,7 +115,7 @@ def test_coefficients_match_oracle(d, q):
         assert native.coefficient(d, q, e) == OC.coefficient(d, q, e) * (e in OC.window(d, q))
 
 
-@pytest.mark.parametrize("rule", ["tr", "cc", "gl", "gl_paper"])
+@pytest.mark.parametrize("rule", ["tr", "cc", "gl", "gl_paper", "gp"])
 def test_rule_tables_match_oracle(orc, rule):
     for level in range(1, 9):
         x, w = native.rule_table(rule, level)
