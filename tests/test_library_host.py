@@ -143,3 +143,14 @@ def test_point_path_work_count_by_brute_force(d, q, rule):
         S += pp * sum(1 for x in l if x >= 2)
     assert bench.points_flop_slots(d, q, rule) == (P, 9 * P + 2 * S)
     assert P == OC.counts_by_generating_function(d, q, rule)["n_points_rep"]
+
+
+def test_gauss_patterson_counts_match_the_paper():
+    # distinct points of the Gauss-Patterson sparse grids printed in
+    # Tables 4.1, 4.3 and 4.5 (accuracy level q -> excess q - 1)
+    import json
+    g = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                    "paper_gp_node_counts.json")))
+    for row in g["rows"]:
+        d, q = row["d"], row["q"]
+        assert native.counts(d, d + q - 1, "gp")[2] == row["unique_points"], row

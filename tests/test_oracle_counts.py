@@ -63,6 +63,16 @@ def test_paper_table_5_6_node_counts():
         assert C.unique_points_by_enumeration(d, d + N - 1, g["rule"]) == row["unique_points"]
 
 
+def test_paper_gauss_patterson_node_counts():
+    # Tables 4.1, 4.3, 4.5: the Gauss-Patterson level map and its nesting
+    g = json.load(open(os.path.join(GOLDEN, "paper_gp_node_counts.json")))
+    for row in g["rows"]:
+        d, q = row["d"], row["q"]
+        assert C.unique_points_by_generating_function(d, d + q - 1, g["rule"]) == row["unique_points"], row
+        if d <= 3:
+            assert C.unique_points_by_enumeration(d, d + q - 1, g["rule"]) == row["unique_points"], row
+
+
 def test_small_textbook_counts():
     # d=1: the rule reduces to the single level-q rule
     assert C.counts_by_generating_function(1, 4, "cc") == dict(n_multi=1, n_points_rep=9, n_points_unique=9)
