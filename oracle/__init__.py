@@ -32,7 +32,8 @@ LIB_PATH = os.path.join(_HERE, "liboracle.so")
 SRC_PATH = os.path.join(_HERE, "sg_oracle.c")
 
 RULE_IDS = {"tr": 1, "cc": 2, "gp": 3, "gl": 4, "gl_paper": 5}
-FAMILY_IDS = {"exp_sum": 0, "oscillatory": 1, "product_peak": 2, "monomial": 3, "corner_peak": 4}
+FAMILY_IDS = {"exp_sum": 0, "oscillatory": 1, "product_peak": 2, "monomial": 3, "corner_peak": 4,
+              "gaussian": 5, "oscillatory_quadratic": 6}
 
 
 def build(force: bool = True) -> str:

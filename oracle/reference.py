@@ -1,6 +1,6 @@
 """Closed-form integrals of the test integrands -- TEST INFRASTRUCTURE ONLY.
 
-I_d(f) of (2.1), on the unit cube, for the three families, in mpmath at 40
+I_d(f) of (2.1), on the unit cube, for the test families, in mpmath at 40
 significant digits.  These are the exact integrals, not the Smolyak values:
 they pin the quadrature only where its truncation error is small.
 """
@@ -62,6 +62,33 @@ def exact_corner_peak(a):
         return +r
 
 
+def _quad_exp_1d(k, u):
+    """int_0^1 exp(k (x - u)^2) dx for real or complex k: with s = x - u and
+    r = sqrt(-k), (sqrt(pi) / (2 r)) (erf(r (1 - u)) + erf(r u))."""
+    k = mp.mpc(k)
+    u = mp.mpf(float(u))
+    if k == 0:
+        return mp.mpf(1)
+    r = mp.sqrt(-k)
+    return mp.sqrt(mp.pi) / (2 * r) * (mp.erf(r * (1 - u)) + mp.erf(r * u))
+
+
+def exact_gaussian(c, u):
+    """prod_i int_0^1 exp(c_i (x - u_i)^2) dx (real part: the integral is real)."""
+    r = mp.mpc(1)
+    for ci, ui in zip(np.asarray(c, dtype=np.float64), np.asarray(u, dtype=np.float64)):
+        r *= _quad_exp_1d(mp.mpf(float(ci)), ui)
+    return mp.re(r)
+
+
+def exact_oscillatory_quadratic(w, a, u):
+    """Re( e^{2 pi i w} prod_i int_0^1 exp(i a_i (x - u_i)^2) dx )."""
+    z = mp.expj(2 * mp.pi * mp.mpf(float(w)))
+    for ai, ui in zip(np.asarray(a, dtype=np.float64), np.asarray(u, dtype=np.float64)):
+        z *= _quad_exp_1d(1j * mp.mpf(float(ai)), ui)
+    return mp.re(z)
+
+
 def exact(family: str, d: int, params):
     params = np.asarray(params, dtype=np.float64)
     if family == "corner_peak":
@@ -72,6 +99,10 @@ def exact(family: str, d: int, params):
         return exact_oscillatory(params[0], params[1:1 + d])
     if family == "product_peak":
         return exact_product_peak(params[:d], params[d:2 * d])
+    if family == "gaussian":
+        return exact_gaussian(params[:d], params[d:2 * d])
+    if family == "oscillatory_quadratic":
+        return exact_oscillatory_quadratic(params[0], params[1:1 + d], params[1 + d:1 + 2 * d])
     raise ValueError(family)
 
 

@@ -34,6 +34,11 @@
  *   product-peak  f(x) = prod 1/(b_i^-2 + (x_i - u_i)^2)     ((4.4), (5.2))
  *   monomial      f(x) = prod (x_i - s)^alpha_i   (point path only, never
  *                 centred; params alpha[d], s) -- for polynomial exactness
+ *   corner-peak   f(x) = (1 + sum a_i x_i)^-(d+1)            (params a[d])
+ *   gaussian      f(x) = exp(sum c_i (x_i - u_i)^2)           ((4.1)-(4.3);
+ *                 params c[d], u[d], c of either sign)
+ *   oscillatory-quadratic  f(x) = cos(2 pi w + sum a_i (x_i - u_i)^2)
+ *                 ((4.1), (4.2); params w, a[d], u[d])
  *
  * Build: gcc -O2 -fPIC -shared -ffp-contract=off sg_oracle.c -lquadmath -lpthread -lm
  */
@@ -48,7 +53,7 @@ typedef __float128 f128;
 typedef long double fld;
 
 enum { OR_TR = 1, OR_CC = 2, OR_GP = 3, OR_GL = 4, OR_GL_PAPER = 5 };
-enum { OR_EXP = 0, OR_OSC = 1, OR_PEAK = 2, OR_MONO = 3, OR_CORNER = 4 };
+enum { OR_EXP = 0, OR_OSC = 1, OR_PEAK = 2, OR_MONO = 3, OR_CORNER = 4, OR_GAUSS = 5, OR_OSCQ = 6 };
 
 #define OR_MAX_LEVEL 16
 #define OR_MAX_NODES 40000
@@ -482,6 +487,24 @@ static fld point_value(const pt_problem *P, int m, const int *coords, const fld 
         /* cos(A + t) - cos(A) = -2 sin(t/2) sin(A + t/2) */
         return -2.0L * sinl(0.5L * t) * sinl(P->theta_c + 0.5L * t);
     }
+    if (P->family == OR_GAUSS || P->family == OR_OSCQ) {
+        /* the exponent's change from the centre: with y = x - 1/2,
+         * c (x - u)^2 - c (1/2 - u)^2 = c y (y + 1 - 2u) */
+        const double *cc = P->family == OR_GAUSS ? p : p + 1;
+        const double *uu = cc + d;
+        fld t = 0;
+        for (int k = 0; k < m; ++k) {
+            int i = coords[k];
+            fld y = xs[k] - 0.5L;
+            t += (fld)cc[i] * y * (y + 1.0L - 2.0L * (fld)uu[i]);
+        }
+        if (P->family == OR_GAUSS) {
+            if (!P->centred) return expl(P->theta_c + t);
+            return P->fc * expm1l(t);
+        }
+        if (!P->centred) return cosl(P->theta_c + t);
+        return -2.0L * sinl(0.5L * t) * sinl(P->theta_c + 0.5L * t);
+    }
     if (P->family == OR_CORNER) {
         /* f(x) = (1 + sum a_i x_i)^-(d+1), a ridge function of s = t_c + t */
         fld t = 0;
@@ -632,6 +655,15 @@ int or_smolyak_points(int d, int q, int rule, int family, const double *params,
         for (int i = 0; i < d; ++i) t += (fld)params[i] * 0.5L;
         P.theta_c = t;
         P.fc = powl(1.0L + t, -(fld)(d + 1));
+    } else if (family == OR_GAUSS || family == OR_OSCQ) {
+        const double *cc = family == OR_GAUSS ? params : params + 1;
+        fld t = family == OR_OSCQ ? 2.0L * 3.14159265358979323846264338327950288L * (fld)params[0] : 0.0L;
+        for (int i = 0; i < d; ++i) {
+            fld h = 0.5L - (fld)cc[d + i];
+            t += (fld)cc[i] * h * h;
+        }
+        P.theta_c = t;
+        P.fc = family == OR_GAUSS ? expl(t) : cosl(t);
     } else if (family == OR_MONO) {
         P.centred = centred = 0;
         P.fc = 0;
@@ -697,7 +729,8 @@ static int fq_setup(fq_problem *F, int d, int q, int rule, int family, const dou
 {
     memset(F, 0, sizeof(*F));
     if (d < 1 || q < d || q - d + 1 > OR_MAX_LEVEL) return -1;
-    if (family < 0 || family > 2) return -1;
+    if (!(family == OR_EXP || family == OR_OSC || family == OR_PEAK || family == OR_GAUSS || family == OR_OSCQ))
+        return -1;
     F->d = d; F->K = q - d; F->rule = rule; F->family = family; F->params = params;
     for (int l = 1; l <= F->K + 1; ++l) {
         long n = or_rule_npoints(rule, l);
@@ -716,7 +749,10 @@ static void fq_free(fq_problem *F)
 
 /* g_t(x) and its derivatives with respect to the coordinate's parameters.
  * exp: g = e^{c x}, dg/dc = x g.  osc: g = e^{i a x}, dg/da = i x g.
- * peak: g = 1/(b^-2 + (x-u)^2), dg/db = 2 b^-3 g^2, dg/du = 2 (x-u) g^2. */
+ * peak: g = 1/(b^-2 + (x-u)^2), dg/db = 2 b^-3 g^2, dg/du = 2 (x-u) g^2.
+ * gaussian: g = e^{c (x-u)^2}, dg/dc = (x-u)^2 g, dg/du = -2 c (x-u) g.
+ * oscillatory-quadratic: g = e^{i a (x-u)^2}, dg/da = i (x-u)^2 g,
+ * dg/du = -2 i a (x-u) g. */
 static void fq_factor(const fq_problem *F, int t, f128 x, cq *g, cq *dg1, cq *dg2)
 {
     const double *p = F->params;
@@ -731,6 +767,17 @@ static void fq_factor(const fq_problem *F, int t, f128 x, cq *g, cq *dg1, cq *dg
         f128 a = p[1 + t];
         g->re = cosq(a * x); g->im = sinq(a * x);
         dg1->re = -x * g->im; dg1->im = x * g->re;
+    } else if (F->family == OR_GAUSS) {
+        f128 c = p[t], u = p[F->d + t], v = x - u;
+        f128 e = expq(c * v * v);
+        g->re = e; g->im = 0;
+        dg1->re = v * v * e;
+        dg2->re = -2 * c * v * e;
+    } else if (F->family == OR_OSCQ) {
+        f128 a = p[1 + t], u = p[1 + F->d + t], v = x - u;
+        g->re = cosq(a * v * v); g->im = sinq(a * v * v);
+        dg1->re = -v * v * g->im; dg1->im = v * v * g->re;
+        dg2->re = 2 * a * v * g->im; dg2->im = -2 * a * v * g->re;
     } else {
         f128 b = p[t], u = p[F->d + t];
         f128 D = 1 / (b * b) + (x - u) * (x - u);
@@ -803,7 +850,7 @@ int or_smolyak_factorised(int d, int q, int rule, int family, const double *para
     }
     cq s = fq_combine(&F, P);
     f128 Q;
-    if (family == OR_OSC) {
+    if (family == OR_OSC || family == OR_OSCQ) {
         f128 ph = 2 * M_PIq * (f128)params[0];
         Q = cosq(ph) * s.re - sinq(ph) * s.im;
     } else {
@@ -842,24 +889,27 @@ int or_smolyak_factorised_grad(int d, int q, int rule, int family, const double 
         memcpy(suf + (size_t)t * L, suf + (size_t)(t + 1) * L, sizeof(cq) * L);
         poly_mul_trunc(suf + (size_t)t * L, U + (size_t)t * L, K);
     }
-    f128 ph = family == OR_OSC ? 2 * M_PIq * (f128)params[0] : 0;
+    const int rotated = family == OR_OSC || family == OR_OSCQ;
+    const int two = family == OR_PEAK || family == OR_GAUSS || family == OR_OSCQ;
+    f128 ph = rotated ? 2 * M_PIq * (f128)params[0] : 0;
     cq rot = {cosq(ph), sinq(ph)};
     for (int t = 0; t < d; ++t) {
         cq ex[64];
         memcpy(ex, pre + (size_t)t * L, sizeof(cq) * L);
         poly_mul_trunc(ex, suf + (size_t)(t + 1) * L, K);
-        for (int which = 0; which < (family == OR_PEAK ? 2 : 1); ++which) {
+        for (int which = 0; which < (two ? 2 : 1); ++which) {
             cq P[64];
             memcpy(P, ex, sizeof(cq) * L);
             poly_mul_trunc(P, (which ? dU2 : dU1) + (size_t)t * L, K);
             cq s = fq_combine(&F, P);
-            f128 g = family == OR_OSC ? cq_mul(rot, s).re : s.re;
+            f128 g = rotated ? cq_mul(rot, s).re : s.re;
             if (family == OR_EXP) grad[t] = (double)g;
             else if (family == OR_OSC) grad[1 + t] = (double)g;
+            else if (family == OR_OSCQ) grad[which ? 1 + d + t : 1 + t] = (double)g;
             else grad[which ? d + t : t] = (double)g;
         }
     }
-    if (family == OR_OSC) {
+    if (rotated) {
         /* dQ/dw = Re(2 pi i e^{2 pi i w} S) */
         cq s = fq_combine(&F, pre + (size_t)d * L);
         cq r = cq_mul(rot, s);

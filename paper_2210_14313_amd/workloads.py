@@ -39,7 +39,7 @@ ALL_RULES = RULES + ("gp",)
 #: families the factorised sweep handles (they factor per coordinate)
 FAMILIES = ("exp_sum", "oscillatory", "product_peak")
 #: families only the point-by-point path handles (ridge functions that do not factor)
-POINT_ONLY_FAMILIES = ("corner_peak",)
+POINT_ONLY_FAMILIES = ("corner_peak", "gaussian", "oscillatory_quadratic")
 
 #: seeds used for the five standard workloads (workload k uses SEED_BASE + k)
 SEED_BASE = 14313
@@ -55,6 +55,10 @@ def n_params(family: str, d: int) -> int:
         return 2 * d
     if family == "corner_peak":
         return d
+    if family == "gaussian":
+        return 2 * d
+    if family == "oscillatory_quadratic":
+        return 2 * d + 1
     raise ValueError(f"unknown family {family!r}")
 
 
@@ -126,6 +130,8 @@ def draw_params(rng: np.random.Generator, family: str, d: int,
     exp_sum: c_i ~ U(0,1) * exp_scale.  oscillatory: w ~ U(0,1),
     a_i ~ U(0,1) * osc_scale / d.  product_peak: b_i ~ U(0.5, 2),
     u_i ~ U(0, 1).  corner_peak: a_i ~ U(0,1), normalised to sum 1.
+    gaussian: c_i ~ U(-4, 2) * 4 / d, u_i ~ U(0, 1).  oscillatory_quadratic:
+    w ~ U(0,1), a_i ~ U(-1, 1) * osc_scale / d, u_i ~ U(0, 1).
     """
     if family == "exp_sum":
         return rng.uniform(0.0, 1.0, d) * exp_scale
@@ -141,6 +147,15 @@ def draw_params(rng: np.random.Generator, family: str, d: int,
         # a_i ~ U(0,1) scaled so that sum a_i = 1 (a mild corner)
         a = rng.uniform(0.0, 1.0, d)
         return a / a.sum()
+    if family == "gaussian":
+        c = rng.uniform(-4.0, 2.0, d) * (4.0 / d)
+        u = rng.uniform(0.0, 1.0, d)
+        return np.concatenate([c, u])
+    if family == "oscillatory_quadratic":
+        w = rng.uniform(0.0, 1.0)
+        a = rng.uniform(-1.0, 1.0, d) * (osc_scale / d)
+        u = rng.uniform(0.0, 1.0, d)
+        return np.concatenate([[w], a, u])
     raise ValueError(family)
 
 

@@ -118,6 +118,10 @@ def _f(family, params, X):
         return np.cos(2 * np.pi * params[0] + X @ params[1:1 + d])
     if family == "corner_peak":
         return (1.0 + X @ params[:d]) ** (-(d + 1))
+    if family == "gaussian":
+        return np.exp(((X - params[d:2 * d]) ** 2) @ params[:d])
+    if family == "oscillatory_quadratic":
+        return np.cos(2 * np.pi * params[0] + ((X - params[1 + d:1 + 2 * d]) ** 2) @ params[1:1 + d])
     b, u = params[:d], params[d:2 * d]
     return np.prod(1.0 / (b ** -2 + (X - u) ** 2), axis=-1)
 
@@ -141,7 +145,7 @@ def brute_smolyak(d, q, rule, family, params):
 
 SMALL = [(d, q, r, f) for (d, q) in [(1, 3), (2, 3), (2, 5), (3, 5), (3, 6), (4, 6)]
          for r in ("tr", "cc", "gl", "gl_paper", "gp")
-         for f in ("exp_sum", "oscillatory", "product_peak", "corner_peak")]
+         for f in ("exp_sum", "oscillatory", "product_peak", "corner_peak", "gaussian", "oscillatory_quadratic")]
 
 
 @pytest.mark.parametrize("d,q,rule,family", SMALL)
@@ -380,7 +384,8 @@ def test_two_dimensions_is_the_two_term_formula(orc):
 # -------------------------------------------------------------- gradients
 def test_factorised_gradient_matches_finite_differences(orc):
     rng = np.random.default_rng(21)
-    for fam, rule, d, K in [("oscillatory", "cc", 8, 3), ("exp_sum", "gl", 6, 4), ("product_peak", "cc", 5, 3)]:
+    for fam, rule, d, K in [("oscillatory", "cc", 8, 3), ("exp_sum", "gl", 6, 4), ("product_peak", "cc", 5, 3),
+                            ("gaussian", "gp", 5, 4), ("oscillatory_quadratic", "gl", 4, 3)]:
         params = W.draw_params(rng, fam, d)
         g = orc.smolyak_factorised_grad(d, d + K, rule, fam, params)
         h = 1e-6
@@ -401,3 +406,35 @@ def test_factorised_gradient_matches_closed_form(orc):
         g = orc.smolyak_factorised_grad(p.d, p.q, p.rule, p.family, params)
         ge = R.exact_grad_oscillatory(params[0], params[1:])
         np.testing.assert_allclose(g, ge, rtol=1e-12, atol=1e-14 * np.max(np.abs(ge)))
+
+
+# ------------------------------------------------ quadratic exponentials
+@pytest.mark.parametrize("family", ["gaussian", "oscillatory_quadratic"])
+def test_quadratic_families_converge_to_closed_form(orc, family):
+    # entire integrands: high-level Gauss-Legendre sums reach the erf closed
+    # forms (checked against mpmath quadrature in one dimension)
+    rng = np.random.default_rng(31)
+    for d, q in [(1, 9), (2, 11), (3, 11)]:
+        prm = W.draw_params(rng, family, d)
+        got = orc.smolyak_points(d, q, "gl", family, prm)["q"]
+        ex = float(R.exact(family, d, prm))
+        assert abs(got - ex) <= 1e-12 * max(abs(ex), 1e-3 if family == "oscillatory_quadratic" else 0), (d, got, ex)
+    c, u, a, w = 1.7, 0.3, -2.2, 0.4
+    with mp.workdps(30):
+        q1 = mp.quad(lambda x: mp.exp(c * (x - u) ** 2), [0, 1])
+        q2 = mp.quad(lambda x: mp.cos(2 * mp.pi * w + a * (x - u) ** 2), [0, 1])
+    assert abs(float(R.exact_gaussian([c], [u])) - float(q1)) < 1e-15 * float(q1)
+    assert abs(float(R.exact_oscillatory_quadratic(w, [a], [u])) - float(q2)) < 1e-15
+
+
+def test_paper_table_4_1_first_row(orc):
+    g = json.load(open(os.path.join(GOLDEN, "paper_table_4_1.json")))
+    for row in g["rows"]:
+        d, q = row["d"], row["q"]
+        prm = np.array(row["params"], dtype=np.float64)
+        v = orc.smolyak_points(d, d + q - 1, g["rule"], g["family"], prm)["q"]
+        vf = orc.smolyak_factorised(d, d + q - 1, g["rule"], g["family"], prm)
+        ex = R.exact(g["family"], d, prm)
+        for val in (v, vf):
+            rel = float(abs((mp.mpf(val) - ex) / ex))
+            assert _same_to_5_digits(rel, row["rel_err"]), (row, rel)
