@@ -68,16 +68,23 @@ typedef enum {
  *   OSCILLATORY   f(x) = cos(2 pi w + sum_i a_i x_i)              params w, a[d]
  *   PRODUCT_PEAK  f(x) = prod_i 1/(b_i^-2 + (x_i - u_i)^2)        params b[d], u[d]
  *   CORNER_PEAK   f(x) = (1 + sum_i a_i x_i)^-(d+1), a_i >= 0     params a[d]
+ *   GAUSSIAN      f(x) = exp(sum_i c_i (x_i - u_i)^2)             params c[d], u[d]
+ *   OSCILLATORY_QUADRATIC
+ *                 f(x) = cos(2 pi w + sum_i a_i (x_i - u_i)^2)    params w, a[d], u[d]
  * (PRODUCT_PEAK is the integrand of (4.4)/(5.2) with free widths/centres;
- * EXP_SUM generalises (4.5)/(5.1); OSCILLATORY generalises Table 5.7's.
- * CORNER_PEAK is a ridge function that does not factor per coordinate:
- * only the point-by-point path sg_integrate_points evaluates it; plans and
- * sg_integrate reject it with UNSUPPORTED.) */
+ * EXP_SUM generalises (4.5)/(5.1); OSCILLATORY generalises Table 5.7's;
+ * GAUSSIAN covers (4.3) and the exponentials of (4.1)/(4.2) (c of either
+ * sign), OSCILLATORY_QUADRATIC their sines.  CORNER_PEAK is a ridge
+ * function that does not factor per coordinate; it and the two quadratic
+ * families are evaluated by the point-by-point path sg_integrate_points
+ * only; plans and sg_integrate reject them with UNSUPPORTED.) */
 typedef enum {
     SG_FAMILY_EXP_SUM = 0,
     SG_FAMILY_OSCILLATORY = 1,
     SG_FAMILY_PRODUCT_PEAK = 2,
-    SG_FAMILY_CORNER_PEAK = 3
+    SG_FAMILY_CORNER_PEAK = 3,
+    SG_FAMILY_GAUSSIAN = 4,
+    SG_FAMILY_OSCILLATORY_QUADRATIC = 5
 } sg_family;
 
 /* Arithmetic of the per-coordinate work (node values and within-rule sums).
@@ -201,7 +208,7 @@ sg_status sg_plan_create(sg_context *ctx, const sg_problem *problems, int32_t n,
  * bounds.  sg_plan_execute_grad is not available (UNSUPPORTED).
  * effective_points counts the tensor product's points (saturating).
  * Errors: INVALID_ARGUMENT (block_dims < 1, as sg_plan_create), UNSUPPORTED
- * (corner-peak, K > SG_MAX_K), OUT_OF_MEMORY, DEVICE. */
+ * (corner-peak and the quadratic families, K > SG_MAX_K), OUT_OF_MEMORY, DEVICE. */
 sg_status sg_plan_create_blocked(sg_context *ctx, const sg_problem *problems, int32_t n,
                                  int32_t precision, int32_t block_dims, sg_plan **plan);
 

@@ -135,15 +135,22 @@ sg_status hip_fail(sg_context* ctx, hipError_t e, const char* what)
 bool family_ok(int f)
 {
     return f == SG_FAMILY_EXP_SUM || f == SG_FAMILY_OSCILLATORY || f == SG_FAMILY_PRODUCT_PEAK ||
-           f == SG_FAMILY_CORNER_PEAK;
+           f == SG_FAMILY_CORNER_PEAK || f == SG_FAMILY_GAUSSIAN || f == SG_FAMILY_OSCILLATORY_QUADRATIC;
+}
+
+// Families only the point-by-point path evaluates.
+bool family_points_only(int f)
+{
+    return f == SG_FAMILY_CORNER_PEAK || f == SG_FAMILY_GAUSSIAN || f == SG_FAMILY_OSCILLATORY_QUADRATIC;
 }
 
 sg_status validate_problem(sg_context* ctx, const sg_problem& p, int idx, bool point_path = false)
 {
-    if (!point_path && p.family == SG_FAMILY_CORNER_PEAK) {
-        char buf[160];
+    if (!point_path && family_points_only(p.family)) {
+        char buf[200];
         snprintf(buf, sizeof buf,
-                 "problem %d: the corner-peak family does not factor per coordinate; use sg_integrate_points", idx);
+                 "problem %d: family %d is evaluated by the point-by-point path only; use sg_integrate_points",
+                 idx, p.family);
         return fail(ctx, SG_ERR_UNSUPPORTED, buf);
     }
     char buf[160];

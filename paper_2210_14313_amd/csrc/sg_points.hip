@@ -42,6 +42,18 @@ constexpr int FAM_EXP = SG_FAMILY_EXP_SUM;
 constexpr int FAM_OSC = SG_FAMILY_OSCILLATORY;
 constexpr int FAM_PEAK = SG_FAMILY_PRODUCT_PEAK;
 constexpr int FAM_CORNER = SG_FAMILY_CORNER_PEAK;
+constexpr int FAM_GAUSS = SG_FAMILY_GAUSSIAN;
+constexpr int FAM_OSCQ = SG_FAMILY_OSCILLATORY_QUADRATIC;
+
+// Families whose partial quantity is an angle (cosine of a sum).
+template <int FAM>
+constexpr bool is_angle() { return FAM == FAM_OSC || FAM == FAM_OSCQ; }
+// Quadratic families: per coordinate (c, u) with the exponent c (x - u)^2.
+template <int FAM>
+constexpr bool is_quadratic() { return FAM == FAM_GAUSS || FAM == FAM_OSCQ; }
+// Offset of c[0] in the parameters of a quadratic family (u follows at + d).
+template <int FAM>
+constexpr int quad_off() { return FAM == FAM_OSCQ ? 1 : 0; }
 
 // 1/k!, exact factorials (k <= 20) rounded once
 constexpr double inv_fact(int k)
@@ -126,7 +138,10 @@ __device__ __forceinline__ double centre_value(const double* __restrict__ prm, i
         double v;
         if constexpr (FAM == FAM_EXP || FAM == FAM_CORNER) v = 0.5 * prm[t];
         else if constexpr (FAM == FAM_OSC) v = 0.5 * prm[1 + t];
-        else {
+        else if constexpr (is_quadratic<FAM>()) {
+            const double hv = 0.5 - prm[quad_off<FAM>() + d + t];
+            v = prm[quad_off<FAM>() + t] * (hv * hv);
+        } else {
             const double b = prm[t], u = prm[d + t];
             const double hv = 0.5 - u;
             v = -log(fma(hv, hv, 1.0 / (b * b)));
@@ -138,7 +153,7 @@ __device__ __forceinline__ double centre_value(const double* __restrict__ prm, i
         s += __shfl_xor(s, off);
         sa += __shfl_xor(sa, off);
     }
-    if constexpr (FAM == FAM_OSC) {
+    if constexpr (is_angle<FAM>()) {
         const double ph = 2.0 * 3.141592653589793 * prm[0];
         s += ph;
         sa += fabs(ph);
@@ -158,12 +173,15 @@ __device__ __forceinline__ double centre_value(const double* __restrict__ prm, i
 // -2 sin h (s0 cos h + c0 sin h).  Its rounding error is at most a few
 // units of |g| plus 10 u |sin h| <= 5 u |delta| (the bracket may cancel,
 // but each of its two products is at most 1 in magnitude).  Exp-sum and
-// product-peak: f(c) expm1(delta), at most 6 roundings of |g|.
+// product-peak: f(c) expm1(delta), at most 6 roundings of |g|.  The
+// quadratic families take the same forms (gaussian as exp-sum,
+// oscillatory-quadratic as oscillatory) with delta the sum of the active
+// coordinates' changes c y (y + 1 - 2u) of the exponent, y = x - 1/2.
 template <int FAM>
 __device__ __forceinline__ double centred_value(double base, double fc, double delta, double dp1, double s0,
                                                 double c0)
 {
-    if constexpr (FAM == FAM_OSC) {
+    if constexpr (is_angle<FAM>()) {
         const double h = 0.5 * delta;
         if (fabs(h) <= kTrigSmall) {
             double sh, ch;
@@ -182,7 +200,7 @@ __device__ __forceinline__ double centred_value(double base, double fc, double d
 template <int FAM>
 __device__ __forceinline__ double centre_f(double base, int d)
 {
-    if constexpr (FAM == FAM_OSC) return cos(base);
+    if constexpr (is_angle<FAM>()) return cos(base);
     else if constexpr (FAM == FAM_CORNER) return exp(-(double)(d + 1) * log1p(base));
     else return exp(base);
 }
@@ -267,7 +285,7 @@ __global__ void __launch_bounds__(256) k_points(PointsArgs A)
     const double fc = centre_f<FAM>(base, d);
     const double dp1 = (double)(d + 1);
     double s0 = 0.0, c0 = 0.0;
-    if constexpr (FAM == FAM_OSC) {
+    if constexpr (is_angle<FAM>()) {
         s0 = sin(base);
         c0 = cos(base);
     }
@@ -293,14 +311,21 @@ __global__ void __launch_bounds__(256) k_points(PointsArgs A)
             // active coordinates: coordinate, level, node count, offset in f1;
             // pre[m] / suf[m]: tensor sizes of coordinates [0, m) / [m, nnz)
             int nm[KMAXP], bm[KMAXP], cm[KMAXP], lm[KMAXP], pre[KMAXP + 1], suf[KMAXP + 1];
+            // quadratic families: rounding scale of a coordinate's entries,
+            // |c| (1 + |1 - 2u|) (the change c y (y + 1 - 2u) may cancel)
+            double es[KMAXP];
             int E = 0;
             pre[0] = 1;
 #pragma unroll
             for (int m = 0; m < KMAXP; ++m) {
+                es[m] = 0.0;
                 if (m < nnz) {
                     cm[m] = __builtin_amdgcn_readfirstlane(rj[2 + m]);
                     lm[m] = __builtin_amdgcn_readfirstlane(rj[2 + A.K + m]);
                     nm[m] = A.level_off[lm[m] + 1] - A.level_off[lm[m]];
+                    if constexpr (is_quadratic<FAM>())
+                        es[m] = fabs(prm[quad_off<FAM>() + cm[m]]) *
+                                (1.0 + fabs(1.0 - 2.0 * prm[quad_off<FAM>() + d + cm[m]]));
                 } else {
                     cm[m] = 0; lm[m] = 1; nm[m] = 1;
                 }
@@ -337,7 +362,11 @@ __global__ void __launch_bounds__(256) k_points(PointsArgs A)
                 double q;
                 if constexpr (FAM == FAM_EXP || FAM == FAM_CORNER) q = prm[coord] * y;
                 else if constexpr (FAM == FAM_OSC) q = prm[1 + coord] * y;
-                else {
+                else if constexpr (is_quadratic<FAM>()) {
+                    // c (x - u)^2 - c (1/2 - u)^2 = c y (y + 1 - 2u)
+                    const double c = prm[quad_off<FAM>() + coord], u = prm[quad_off<FAM>() + d + coord];
+                    q = c * (y * (y + (1.0 - 2.0 * u)));
+                } else {
                     const double b = prm[coord], u = prm[d + coord];
                     const double beta = 1.0 / (b * b), hv = 0.5 - u;
                     const double yp = y + hv;
@@ -363,7 +392,7 @@ __global__ void __launch_bounds__(256) k_points(PointsArgs A)
                         rem = qt;
                         const double2 f = f1[bm[m] + k];
                         q += f.x;
-                        sa += fabs(f.x);
+                        sa += fabs(f.x) + es[m];
                         wt *= f.y;
                     }
                 }
@@ -387,7 +416,7 @@ __global__ void __launch_bounds__(256) k_points(PointsArgs A)
                 // error of delta (each entry and each addition rounded), times
                 // |df/d delta| (oscillatory <= 1; corner-peak (d+1) f / (1 + s))
                 double fx;
-                if constexpr (FAM == FAM_OSC) fx = 1.0;
+                if constexpr (is_angle<FAM>()) fx = 1.0;
                 else if constexpr (FAM == FAM_CORNER) fx = dp1 * fabs(fc + gd) / (1.0 + base + delta);
                 else fx = fabs(fc + gd);
                 aabs += fabs(wp) * (fabs(gd) + fx * sd);
@@ -419,7 +448,10 @@ __global__ void __launch_bounds__(256) k_points(PointsArgs A)
 // roundings of |g| (oscillatory: 3, plus 5 u |delta|, within the next term)
 // and |f(x)| times the error of the partial quantity delta (each of its at
 // most 8 entries and additions, at most 6 roundings each, relative to the
-// sum of the entries' magnitudes); S accumulates |w| (|g| + |f(x)| sum |entry|).  e_c bounds the error of the centre's
+// sum of the entries' magnitudes; for the quadratic families an entry's
+// magnitude includes |c| (1 + |1 - 2u|), which bounds the rounding of
+// c y (y + 1 - 2u) when it cancels); S accumulates
+// |w| (|g| + |f(x)| sum |entry|).  e_c bounds the error of the centre's
 // argument (log-amplitude or phase: a d-term sum, u (d + 4) times the sum
 // of its components' magnitudes, plus 4u per logarithm); the value and every
 // term move by at most |f(c)| + 1 + S per unit of it.  The double-double sum
@@ -550,9 +582,17 @@ int launch_points(int family, const PointsLaunch& L, void* stream)
         hipLaunchKernelGGL(pts::k_points<pts::FAM_PEAK>, grid, block, shmem, s, A);
         hipLaunchKernelGGL(pts::k_points_finish<pts::FAM_PEAK>, dim3(1), block, 0, s, L.partial, L.grid * 4,
                            L.params, L.d, L.out, L.bound);
-    } else {
+    } else if (family == SG_FAMILY_CORNER_PEAK) {
         hipLaunchKernelGGL(pts::k_points<pts::FAM_CORNER>, grid, block, shmem, s, A);
         hipLaunchKernelGGL(pts::k_points_finish<pts::FAM_CORNER>, dim3(1), block, 0, s, L.partial, L.grid * 4,
+                           L.params, L.d, L.out, L.bound);
+    } else if (family == SG_FAMILY_GAUSSIAN) {
+        hipLaunchKernelGGL(pts::k_points<pts::FAM_GAUSS>, grid, block, shmem, s, A);
+        hipLaunchKernelGGL(pts::k_points_finish<pts::FAM_GAUSS>, dim3(1), block, 0, s, L.partial, L.grid * 4,
+                           L.params, L.d, L.out, L.bound);
+    } else {
+        hipLaunchKernelGGL(pts::k_points<pts::FAM_OSCQ>, grid, block, shmem, s, A);
+        hipLaunchKernelGGL(pts::k_points_finish<pts::FAM_OSCQ>, dim3(1), block, 0, s, L.partial, L.grid * 4,
                            L.params, L.d, L.out, L.bound);
     }
     return (int)hipGetLastError();

@@ -18,7 +18,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("SGMDI_LIB") or os.path.join(_HERE, "libsgmdi.so")
 
 RULES = {"tr": 1, "cc": 2, "gp": 3, "gl": 4, "gl_paper": 5}
-FAMILIES = {"exp_sum": 0, "oscillatory": 1, "product_peak": 2, "corner_peak": 3}
+FAMILIES = {"exp_sum": 0, "oscillatory": 1, "product_peak": 2, "corner_peak": 3, "gaussian": 4,
+            "oscillatory_quadratic": 5}
 PRECISIONS = {"fp64": 0, "fp32c": 1, "fp32e": 2}
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "overflow", 4: "out of memory",
           5: "device error", 6: "capture error"}
