@@ -74,10 +74,11 @@ typedef enum {
  * (PRODUCT_PEAK is the integrand of (4.4)/(5.2) with free widths/centres;
  * EXP_SUM generalises (4.5)/(5.1); OSCILLATORY generalises Table 5.7's;
  * GAUSSIAN covers (4.3) and the exponentials of (4.1)/(4.2) (c of either
- * sign), OSCILLATORY_QUADRATIC their sines.  CORNER_PEAK is a ridge
- * function that does not factor per coordinate; it and the two quadratic
- * families are evaluated by the point-by-point path sg_integrate_points
- * only; plans and sg_integrate reject them with UNSUPPORTED.) */
+ * sign; forward sweep and point path, no reverse sweep), OSCILLATORY_QUADRATIC
+ * their sines.  CORNER_PEAK is a ridge function that does not factor per
+ * coordinate; it and OSCILLATORY_QUADRATIC (whose even parts are complex) are
+ * evaluated by the point-by-point path sg_integrate_points only; plans and
+ * sg_integrate reject them with UNSUPPORTED.) */
 typedef enum {
     SG_FAMILY_EXP_SUM = 0,
     SG_FAMILY_OSCILLATORY = 1,
@@ -208,7 +209,7 @@ sg_status sg_plan_create(sg_context *ctx, const sg_problem *problems, int32_t n,
  * bounds.  sg_plan_execute_grad is not available (UNSUPPORTED).
  * effective_points counts the tensor product's points (saturating).
  * Errors: INVALID_ARGUMENT (block_dims < 1, as sg_plan_create), UNSUPPORTED
- * (corner-peak and the quadratic families, K > SG_MAX_K), OUT_OF_MEMORY, DEVICE. */
+ * (corner-peak, oscillatory-quadratic, K > SG_MAX_K), OUT_OF_MEMORY, DEVICE. */
 sg_status sg_plan_create_blocked(sg_context *ctx, const sg_problem *problems, int32_t n,
                                  int32_t precision, int32_t block_dims, sg_plan **plan);
 
@@ -228,7 +229,8 @@ sg_status sg_plan_execute(sg_plan *plan, const double *params_dev, double *out_d
 /* Gradient of every result with respect to every parameter (reverse sweep):
  * grad_params_dev[k] = grad_out_dev[i] * dQ_i/dparams[k] for the parameters
  * k of problem i, same layout as params.  Parameters not used by any problem
- * are left untouched.  Errors: INVALID_ARGUMENT, DEVICE. */
+ * are left untouched.  Errors: INVALID_ARGUMENT, DEVICE, UNSUPPORTED (a gaussian
+ * problem, or a block-variant plan). */
 sg_status sg_plan_execute_grad(sg_plan *plan, const double *params_dev, const double *grad_out_dev,
                                double *grad_params_dev, void *stream);
 

@@ -16,8 +16,8 @@ product of m-dimensional sparse grids.  This module computes that rule:
 * the rule is the tensor product of the block rules.
 
 For the product-form families the integrand factors over the blocks, so
-the value is the product of the blocks' values: exp-sum, product-peak and
-monomial directly; oscillatory through
+the value is the product of the blocks' values: exp-sum, product-peak,
+gaussian and monomial directly; oscillatory through
 cos(2 pi w + sum_t a_t x_t) = Re(e^{2 pi i w} prod_b e^{i sum_{t in b} a_t x_t}),
 where the block value C_b = A_b(cos theta_b) + i A_b(sin theta_b) and
 A_b(sin theta_b) = A_b(cos(theta_b - pi/2)) is the oscillatory block with
@@ -48,7 +48,7 @@ def block_params(family: str, params, d: int, start: int, length: int, w_overrid
     if family == "oscillatory":
         w = p[0] if w_override is None else w_override
         return np.concatenate([[w], p[1:][sl]])
-    if family == "product_peak":
+    if family in ("product_peak", "gaussian"):
         return np.concatenate([p[:d][sl], p[d:2 * d][sl]])
     if family == "monomial":
         return np.concatenate([p[:d][sl], [p[d]]])

@@ -107,6 +107,7 @@ struct sg_plan {
     int qgrid = 0;                  // persistent kernel: workgroups launched
     bool use_graph = false;         // replay a captured graph (else direct launch)
     bool params_disjoint = true;    // problems' parameter ranges do not overlap
+    bool grad_ok = true;            // every family has a reverse sweep (not the gaussian)
     int kmax = 0;                   // largest K of the plan (kernel instantiation class)
     double* d_ws = nullptr;         // reverse-sweep workspace (sum d*K doubles), lazy
     size_t ws_elems = 0;
@@ -141,7 +142,7 @@ bool family_ok(int f)
 // Families only the point-by-point path evaluates.
 bool family_points_only(int f)
 {
-    return f == SG_FAMILY_CORNER_PEAK || f == SG_FAMILY_GAUSSIAN || f == SG_FAMILY_OSCILLATORY_QUADRATIC;
+    return f == SG_FAMILY_CORNER_PEAK || f == SG_FAMILY_OSCILLATORY_QUADRATIC;
 }
 
 sg_status validate_problem(sg_context* ctx, const sg_problem& p, int idx, bool point_path = false)
@@ -729,6 +730,7 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
     std::vector<double> cost(n);
     sg_plan_info info{};
     int maxd = 1;
+    bool has_gauss = false;
     for (int i = 0; i < n; ++i) {
         const DeltaTable& t = *ptab[i];
         const uint64_t d = (uint64_t)problems[i].d;
@@ -744,7 +746,9 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
         info.merge_flops = sat_add(info.merge_flops, sat_mul(d, K * K));
         maxd = std::max(maxd, problems[i].d);
         p->kmax = std::max(p->kmax, (int)K);
+        if (problems[i].family == SG_FAMILY_GAUSSIAN) has_gauss = true;
     }
+    if (has_gauss) p->kmax = kKmaxGauss;   // the forward kernels built with the gaussian family
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
@@ -773,6 +777,7 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
         // parameter ranges must be disjoint for the reverse sweep to write them
         std::vector<std::pair<int64_t, int64_t>> rg(n);
         for (int i = 0; i < n; ++i) {
+            if (problems[i].family == SG_FAMILY_GAUSSIAN) p->grad_ok = false;
             const int64_t len = problems[i].family == SG_FAMILY_EXP_SUM ? problems[i].d
                                 : problems[i].family == SG_FAMILY_OSCILLATORY ? (int64_t)problems[i].d + 1
                                                                               : 2 * (int64_t)problems[i].d;
@@ -989,7 +994,9 @@ sg_status sg_plan_create_blocked(sg_context* ctx, const sg_problem* problems, in
                 g.part = part;
                 gs.push_back(g);
                 sub.push_back(sg_problem{len, len + K, P.rule, P.family, off});
-                off += osc ? 1 + len : P.family == SG_FAMILY_PRODUCT_PEAK ? 2 * (int64_t)len : len;
+                off += osc ? 1 + len
+                           : (P.family == SG_FAMILY_PRODUCT_PEAK || P.family == SG_FAMILY_GAUSSIAN) ? 2 * (int64_t)len
+                                                                                                    : len;
             }
         }
         eff = sat_add(eff, pts);
@@ -1034,6 +1041,7 @@ sg_status sg_plan_execute_grad(sg_plan* p, const double* params_dev, const doubl
     if (!params_dev || !grad_out_dev || !grad_params_dev)
         return fail(p->ctx, SG_ERR_INVALID_ARGUMENT, "NULL params, grad_out or grad_params");
     if (p->blocked) return fail(p->ctx, SG_ERR_UNSUPPORTED, "the block variant has no reverse sweep");
+    if (!p->grad_ok) return fail(p->ctx, SG_ERR_UNSUPPORTED, "the gaussian family has no reverse sweep");
     if (!p->params_disjoint)
         return fail(p->ctx, SG_ERR_INVALID_ARGUMENT,
                     "problems share parameters: the reverse sweep needs disjoint parameter ranges");
@@ -1249,7 +1257,8 @@ sg_status sg_integrate(sg_context* ctx, const sg_problem* problem, int32_t preci
         if ((st = upload(ctx, &pe.pool32, r->r32.data(), r->r32.size())) != SG_OK) return st;
         it = ctx->plain.emplace(key, pe).first;
     }
-    const int rc = launch_forward(precision, K, it->second.nfwg, it->second.fwd, nullptr, 0, it->second.pool64,
+    const int rc = launch_forward(precision, problem->family == SG_FAMILY_GAUSSIAN ? kKmaxGauss : K,
+                                  it->second.nfwg, it->second.fwd, nullptr, 0, it->second.pool64,
                                   it->second.pool32, params_dev, out_dev, bound_dev, stream);
     if (rc != 0) return hip_fail(ctx, (hipError_t)rc, "forward launch");
     return SG_OK;

@@ -6,7 +6,7 @@
 // the product-form families the integrand factors over the blocks, so the
 // value is the product of the block values, each block being an ordinary
 // batched problem of the forward sweep:
-//   exp-sum, product-peak: Q = prod_b Q_b;
+//   exp-sum, product-peak, gaussian: Q = prod_b Q_b;
 //   oscillatory: Q = Re(e^{2 pi i w} prod_b (R_b + i I_b)), with R_b the
 //   block's oscillatory value at w = 0 and I_b the one at w = -1/4
 //   (cos(theta - pi/2) = sin theta).
@@ -34,7 +34,7 @@ __global__ void __launch_bounds__(256) k_block_gather(const BlockSub* __restrict
     if (b.family == SG_FAMILY_OSCILLATORY) {
         dst[0] = b.part == 2 ? -0.25 : 0.0;
         for (int j = 0; j < b.len; ++j) dst[1 + j] = src[1 + b.start + j];
-    } else if (b.family == SG_FAMILY_PRODUCT_PEAK) {
+    } else if (b.family == SG_FAMILY_PRODUCT_PEAK || b.family == SG_FAMILY_GAUSSIAN) {
         for (int j = 0; j < b.len; ++j) {
             dst[j] = src[b.start + j];
             dst[b.len + j] = src[b.d + b.start + j];

@@ -37,6 +37,7 @@
 #include <type_traits>
 
 #include "sg_internal.hpp"
+#include "sg_math.hpp"
 #include "sg_tables.inc"
 
 namespace sg {
@@ -46,6 +47,7 @@ constexpr int MAXK = kMaxK;
 constexpr int FAM_EXP = SG_FAMILY_EXP_SUM;
 constexpr int FAM_OSC = SG_FAMILY_OSCILLATORY;
 constexpr int FAM_PEAK = SG_FAMILY_PRODUCT_PEAK;
+constexpr int FAM_GAUSS = SG_FAMILY_GAUSSIAN;
 
 // ----------------------------------------------------------------- series
 // P(z) = sum_{k>=0} 2 z^k / (2k+2)!, so that for z = v^2:
@@ -103,9 +105,43 @@ __device__ __forceinline__ float series32w(float z)
 
 // Per-coordinate family parameters, read once per coordinate.
 struct CoordParam {
-    double p0;    // exp: c; osc: a; peak: beta = b^-2
-    double p1;    // peak: (1 - 2u)/2
+    double p0;    // exp: c; osc: a; peak: beta = b^-2; gaussian: c
+    double p1;    // peak: (1 - 2u)/2; gaussian: c (1 - 2u)
 };
+
+// Gaussian exp(c (x - u)^2): with b = 1 - 2u, h(y) = g(1/2 + y)/g(1/2) - 1 =
+// e^{c y (y + b)} - 1 and h(y) + h(-y) = 2 (e^{c y^2} cosh(c b y) - 1) =
+// 2 (E (1 + C) + C), E = expm1(c y^2), C = cosh(c b y) - 1 = F^2 / (2 (1 + F))
+// with F = expm1(|c b y|) (no cancellation).  For c < 0 the two terms have
+// opposite signs and may cancel, so the value's rounding is charged against
+// the magnitude 2 (|E| (1 + C) + C), returned in `mag` (E and F carry at most
+// 5 roundings each, C three more, the combination two more).  Branch-free
+// expm1 keeps the code small: this family takes the table-driven path only.
+__device__ __forceinline__ double pair_gauss64(const CoordParam& cp, double y, double& mag)
+{
+    const double E = expm1_any(cp.p0 * (y * y));
+    const double F = expm1_any(fabs(cp.p1 * y));
+    const double C = 0.5 * (F * (F / (1.0 + F)));
+    mag = 2.0 * fma(fabs(E), 1.0 + C, C);
+    return 2.0 * fma(E, 1.0 + C, C);
+}
+
+// A pair value with the magnitude its rounding is charged against (the
+// Gaussian's); plain values are their own magnitude.
+struct PairVM {
+    double v, m;
+};
+struct PairVMf {
+    float v, m;
+};
+__device__ __forceinline__ double pv_val(double s) { return s; }
+__device__ __forceinline__ double pv_mag(double s) { return fabs(s); }
+__device__ __forceinline__ double pv_val(const PairVM& s) { return s.v; }
+__device__ __forceinline__ double pv_mag(const PairVM& s) { return s.m; }
+__device__ __forceinline__ float pv_val(float s) { return s; }
+__device__ __forceinline__ float pv_mag(float s) { return fabsf(s); }
+__device__ __forceinline__ float pv_val(const PairVMf& s) { return s.v; }
+__device__ __forceinline__ float pv_mag(const PairVMf& s) { return s.m; }
 
 template <int FAM>
 __device__ __forceinline__ double pair64(const CoordParam& cp, double y)
@@ -122,6 +158,9 @@ __device__ __forceinline__ double pair64(const CoordParam& cp, double y)
             const double sn = sin(0.5 * v);        // 2(cos v - 1) = -4 sin^2(v/2)
             return -4.0 * sn * sn;
         }
+    } else if constexpr (FAM == FAM_GAUSS) {
+        double mag;
+        return pair_gauss64(cp, y, mag);
     } else {
         const double beta = cp.p0, hv = cp.p1;
         const double y2 = y * y;
@@ -231,10 +270,11 @@ __device__ __forceinline__ void surplus64g(const double* __restrict__ r64, PF&& 
 #pragma unroll 2
         for (int j = 0; j < np; ++j) {
             const double* r = r64 + off + j * rl;
-            const double s = pf(r[0]);
+            const auto sr = pf(r[0]);
+            const double s = pv_val(sr);
 #pragma unroll
             for (int e = lo; e <= hi; ++e) del[e] = fma(r[1 + e - lo], s, del[e]);
-            if (want_bound) eps = fma(r[rl - 1], fabs(s), eps);
+            if (want_bound) eps = fma(r[rl - 1], pv_mag(sr), eps);
         }
     });
 }
@@ -258,11 +298,12 @@ __device__ __forceinline__ void surplus32g(const double* __restrict__ r64, const
         for (int j = 0; j < np; ++j) {
             const double* r = r64 + off + j * rl;
             const float* w = r32 + off32 + j * rl32;
-            const float s = pf(r[0]);
+            const auto sr = pf(r[0]);
+            const float s = pv_val(sr);
 #pragma unroll
             for (int e = elo; e <= ehi; ++e)
                 acc2(hi[e], lo[e], w[2 * (e - elo)], w[2 * (e - elo) + 1], s);
-            if (want_bound) epsf = fmaf((float)r[rl - 1], fabsf(s), epsf);
+            if (want_bound) epsf = fmaf((float)r[rl - 1], pv_mag(sr), epsf);
         }
     });
 #pragma unroll
@@ -274,7 +315,11 @@ template <int K, int RC, int FAM>
 __device__ __forceinline__ void surplus64(const double* __restrict__ r64, const CoordParam& cp, bool want_bound,
                                           double (&del)[MAXK + 1], double& eps)
 {
-    surplus64g<K, RC>(r64, [&](double y) { return pair64<FAM>(cp, y); }, want_bound, del, eps);
+    if constexpr (FAM == FAM_GAUSS)
+        surplus64g<K, RC>(r64, [&](double y) { PairVM p; p.v = pair_gauss64(cp, y, p.m); return p; }, want_bound,
+                          del, eps);
+    else
+        surplus64g<K, RC>(r64, [&](double y) { return pair64<FAM>(cp, y); }, want_bound, del, eps);
 }
 
 template <int K, int RC, int FAM>
@@ -282,7 +327,17 @@ __device__ __forceinline__ void surplus32(const double* __restrict__ r64, const 
                                           const CoordParam& cp, bool want_bound, double (&del)[MAXK + 1],
                                           double& eps)
 {
-    surplus32g<K, RC>(r64, r32, [&](double y) { return pair32<FAM>(cp, y); }, want_bound, del, eps);
+    if constexpr (FAM == FAM_GAUSS)
+        surplus32g<K, RC>(r64, r32, [&](double y) {
+            double m;
+            const double v = pair_gauss64(cp, y, m);
+            PairVMf p;
+            p.v = (float)v;
+            p.m = (float)m;
+            return p;
+        }, want_bound, del, eps);
+    else
+        surplus32g<K, RC>(r64, r32, [&](double y) { return pair32<FAM>(cp, y); }, want_bound, del, eps);
 }
 
 // ------------------------------------------- compiled-table surpluses
@@ -671,7 +726,10 @@ __device__ void readout(const Acc& x, int d, int out_index, const double* __rest
     s += 1.0;
     const double sabs = want_bound ? abs_product_bound(x.m) : 0.0;
     const double u64 = 1.1102230246251565e-16;
-    const double ls_err = u64 * (double)d * x.lsabs;   // rounding of the affine sum
+    // rounding of the affine sum: d - 1 additions, plus up to 3 roundings
+    // per term where a term is not exact (product-peak log D, gaussian c hv^2)
+    const double ls_err =
+        u64 * (double)(FAM == FAM_EXP || FAM == FAM_OSC ? d : d + 3) * x.lsabs;
     // relative error of one surplus term: pair value (8 roundings) plus the
     // within-rule sum (FP64: a plain FMA chain over at most rl_pairs terms;
     // FP32 compensated: the FMA chain of the term's block, at most
@@ -694,7 +752,7 @@ __device__ void readout(const Acc& x, int d, int out_index, const double* __rest
             bound[out_index] = dsum + fabs(s) * (ls_err + u64 * (fabs(phase) + 4.0)) + fabs(Q) * 4.0 * u64;
         }
     } else {
-        const double A = exp(FAM == FAM_EXP ? x.ls : -x.ls);
+        const double A = exp(FAM == FAM_PEAK ? -x.ls : x.ls);
         Q = A * s;
         if (want_bound) {
             const double dsum = sabs * (rel * x.eps + (K + 2) * levels * u64);
@@ -745,6 +803,11 @@ __device__ __forceinline__ double coord_param(const RawParam& r, CoordParam& cp)
         cp.p0 = r.a;
         cp.p1 = 0.0;
         return 0.5 * cp.p0;                       // exp: log g_t(1/2) = c_t/2; osc: phase a_t/2
+    } else if constexpr (FAM == FAM_GAUSS) {
+        const double hv = 0.5 - r.b;
+        cp.p0 = r.a;
+        cp.p1 = r.a * (2.0 * hv);                 // c (1 - 2u)
+        return r.a * (hv * hv);                   // log g_t(1/2) = c (1/2 - u)^2
     } else {
         cp.p0 = 1.0 / (r.a * r.a);                // beta = b^-2
         cp.p1 = 0.5 - r.b;
@@ -807,7 +870,7 @@ __device__ __forceinline__ void wave_sweep(const WaveInfo& wi, const double* __r
         double del[MAXK + 1];
         double eps_t = 0.0;
         bool done = false;
-        if constexpr (K <= KCONST) {
+        if constexpr (K <= KCONST && FAM != FAM_GAUSS) {
             if (FAM == FAM_PEAK || fabs(cp.p0) <= 2.0) {
                 if constexpr (PREC == SG_PREC_FP64) surplus64_const<RULE, K, FAM>(cp, del, eps_t);
                 else if constexpr (PREC == SG_PREC_FP32_COMPENSATED) surplus32_const<RULE, K, FAM>(cp, del, eps_t);
@@ -848,14 +911,16 @@ __device__ __forceinline__ void wave_sweep(const WaveInfo& wi, const double* __r
     }
 }
 
-template <int PREC, int K>
+template <int PREC, int K, bool GAUSS>
 __device__ __forceinline__ void wave_dispatch_k(int rule, int family, const WaveInfo& wi, const double* params,
                                                 double* out, double* bound, double* lds_slot)
 {
 #define SG_WAVE(RULE, FAM) wave_sweep<PREC, K, RULE, FAM>(wi, params, out, bound, lds_slot)
 #define SG_FAMS(RULE)                                         \
     do {                                                      \
-        if (family == FAM_EXP) SG_WAVE(RULE, FAM_EXP);        \
+        if (GAUSS && family == FAM_GAUSS) {                   \
+            if constexpr (GAUSS) SG_WAVE(RULE, FAM_GAUSS);    \
+        } else if (family == FAM_EXP) SG_WAVE(RULE, FAM_EXP); \
         else if (family == FAM_OSC) SG_WAVE(RULE, FAM_OSC);   \
         else SG_WAVE(RULE, FAM_PEAK);                         \
     } while (0)
@@ -879,7 +944,7 @@ __device__ __forceinline__ void wave_dispatch_k(int rule, int family, const Wave
 }
 
 // Group leader: merge the group's wave states in wave order, read out.
-template <int PREC, int K>
+template <int PREC, int K, bool GAUSS>
 __device__ __forceinline__ void group_finish_k(int rule, int family, int group, const FwdSeg& lp,
                                                const double* lds_first, const double* params, double* out,
                                                double* bound)
@@ -900,6 +965,12 @@ __device__ __forceinline__ void group_finish_k(int rule, int family, int group, 
                    : rc == RC_GP   ? total_pairs<RC_GP, K>()
                                    : total_pairs<RC_GLP, K>();
     const int depth = tree_depth(lp.d, 6, group);
+    if constexpr (GAUSS) {
+        if (family == FAM_GAUSS) {
+            readout<PREC, K, FAM_GAUSS>(x, lp.d, lp.out_index, prm, np, depth, out, bound);
+            return;
+        }
+    }
     if (family == FAM_EXP) readout<PREC, K, FAM_EXP>(x, lp.d, lp.out_index, prm, np, depth, out, bound);
     else if (family == FAM_OSC) readout<PREC, K, FAM_OSC>(x, lp.d, lp.out_index, prm, np, depth, out, bound);
     else readout<PREC, K, FAM_PEAK>(x, lp.d, lp.out_index, prm, np, depth, out, bound);
@@ -918,7 +989,7 @@ __device__ __forceinline__ void switch_k(int K, F&& f)
 // spanning several waves sits in consecutive waves of the workgroup and is
 // merged through LDS by its first wave.  Every thread of the workgroup must
 // call this (it may synchronise the workgroup).
-template <int PREC, int KMAXP>
+template <int PREC, int KMAXP, bool GAUSS>
 __device__ __forceinline__ void run_workgroup(const FwdWG* wg, const double* __restrict__ pool64,
                                               const float* __restrict__ pool32, const double* __restrict__ params,
                                               double* __restrict__ out, double* __restrict__ bound, double* lds)
@@ -939,7 +1010,8 @@ __device__ __forceinline__ void run_workgroup(const FwdWG* wg, const double* __r
     const bool grouped = wg->w[0].group > 1 || wg->w[1].group > 1 || wg->w[2].group > 1 || wg->w[3].group > 1;
     if (wi.nprob > 0) {
         switch_k<KMAXP>(K, [&](auto kc) {
-            wave_dispatch_k<PREC, decltype(kc)::value>(rule, family, wi, params, out, bound, lds + w * ACC_WORDS);
+            wave_dispatch_k<PREC, decltype(kc)::value, GAUSS>(rule, family, wi, params, out, bound,
+                                                              lds + w * ACC_WORDS);
         });
     }
     if (!grouped) return;
@@ -947,7 +1019,7 @@ __device__ __forceinline__ void run_workgroup(const FwdWG* wg, const double* __r
     if (wi.nprob > 0 && wi.group > 1 && wi.rank == 0 && (threadIdx.x & 63) == 0) {
         const FwdSeg lp = wd->seg[0];
         switch_k<KMAXP>(K, [&](auto kc) {
-            group_finish_k<PREC, decltype(kc)::value>(rule, family, wi.group, lp, lds + w * ACC_WORDS, params, out,
+            group_finish_k<PREC, decltype(kc)::value, GAUSS>(rule, family, wi.group, lp, lds + w * ACC_WORDS, params, out,
                                                       bound);
         });
     }
@@ -960,7 +1032,10 @@ __device__ __forceinline__ void run_workgroup(const FwdWG* wg, const double* __r
 // exhausted, and the last one to leave (counted in queue[1]) resets both
 // counters, so the next launch on the stream starts from zero without a
 // memset (graph-safe).  Launches of one queue must not overlap.
-template <int PREC, int KMAXP>
+// GAUSS: the instantiation for plans that hold gaussian problems (it runs
+// every family; kept apart so that the gaussian code does not weigh on the
+// other plans' kernels).
+template <int PREC, int KMAXP, bool GAUSS = false>
 __global__ void __launch_bounds__(256)
 k_forward(const FwdWG* __restrict__ wgs, int nwg, unsigned int* __restrict__ queue,
           const double* __restrict__ pool64, const float* __restrict__ pool32,
@@ -977,7 +1052,7 @@ k_forward(const FwdWG* __restrict__ wgs, int nwg, unsigned int* __restrict__ que
             __syncthreads();   // every thread has read `next` before it is overwritten
         }
         if (idx >= nwg) break;
-        run_workgroup<PREC, KMAXP>(wgs + idx, pool64, pool32, params, out, bound, lds);
+        run_workgroup<PREC, KMAXP, GAUSS>(wgs + idx, pool64, pool32, params, out, bound, lds);
         if (!queue) break;
     }
     if (queue && threadIdx.x == 0) {

@@ -1,6 +1,8 @@
 // Forward-sweep kernels, precision 1: one instantiation per largest
 // excess budget class (K <= 4, <= 6, <= 8); a plan launches the smallest
-// class covering its problems (fewer registers, more waves per SIMD).
+// class covering its problems (fewer registers, more waves per SIMD); a
+// plan holding gaussian problems launches the K <= 8 kernel built with the
+// gaussian family (launch class kKmaxGauss).
 #include "sg_device.hpp"
 
 namespace sg {
@@ -17,9 +19,12 @@ int launch_forward_p1(int kmax, int nwg, const FwdWG* wgs, unsigned int* queue, 
     else if (kmax <= 6)
         hipLaunchKernelGGL((dev::k_forward<1, 6>), grid, block, 0, s, wgs, nwg, queue, pool64, pool32, params, out,
                            bound);
-    else
+    else if (kmax <= 8)
         hipLaunchKernelGGL((dev::k_forward<1, 8>), grid, block, 0, s, wgs, nwg, queue, pool64, pool32, params, out,
                            bound);
+    else   // kKmaxGauss: a plan with gaussian problems
+        hipLaunchKernelGGL((dev::k_forward<1, 8, true>), grid, block, 0, s, wgs, nwg, queue, pool64, pool32, params,
+                           out, bound);
     return (int)hipGetLastError();
 }
 
@@ -29,7 +34,8 @@ int forward_capacity_p1(int kmax)
 {
     const void* f = kmax <= 4   ? reinterpret_cast<const void*>(&dev::k_forward<1, 4>)
                     : kmax <= 6 ? reinterpret_cast<const void*>(&dev::k_forward<1, 6>)
-                                : reinterpret_cast<const void*>(&dev::k_forward<1, 8>);
+                    : kmax <= 8 ? reinterpret_cast<const void*>(&dev::k_forward<1, 8>)
+                                : reinterpret_cast<const void*>(&dev::k_forward<1, 8, true>);
     int per_cu = 0, dev = 0, cus = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 256, 0) != hipSuccess) return 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;

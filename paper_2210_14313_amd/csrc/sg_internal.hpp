@@ -14,6 +14,9 @@
 namespace sg {
 
 constexpr int kMaxK = SG_MAX_K;
+// Launch class of forward plans holding gaussian problems (kernels built
+// for K <= kMaxK with that family).
+constexpr int kKmaxGauss = kMaxK + 1;
 
 // ---------------------------------------------------------------- 1-D rules
 // Number of nodes of the level-l rule (Section 2.2); -1 if unknown/too big.

@@ -39,7 +39,9 @@ ALL_RULES = RULES + ("gp",)
 #: families the factorised sweep handles (they factor per coordinate)
 FAMILIES = ("exp_sum", "oscillatory", "product_peak")
 #: families only the point-by-point path handles (ridge functions that do not factor)
-POINT_ONLY_FAMILIES = ("corner_peak", "gaussian", "oscillatory_quadratic")
+POINT_ONLY_FAMILIES = ("corner_peak", "oscillatory_quadratic")
+#: families the forward sweep handles beyond FAMILIES (no reverse sweep)
+FORWARD_ONLY_FAMILIES = ("gaussian",)
 
 #: seeds used for the five standard workloads (workload k uses SEED_BASE + k)
 SEED_BASE = 14313
@@ -111,7 +113,8 @@ class _Builder:
         self.off = 0
 
     def add(self, d: int, q: int, rule: str, family: str, params: np.ndarray):
-        assert rule in ALL_RULES and (family in FAMILIES or family in POINT_ONLY_FAMILIES)
+        assert rule in ALL_RULES and (family in FAMILIES or family in POINT_ONLY_FAMILIES
+                                      or family in FORWARD_ONLY_FAMILIES)
         params = np.asarray(params, dtype=np.float64).ravel()
         assert params.size == n_params(family, d)
         self.problems.append(Problem(int(d), int(q), rule, family, self.off))

@@ -55,7 +55,7 @@ CASES = [(3, 2, "cc", 1), (4, 2, "gl", 2), (4, 3, "gl_paper", 2), (5, 1, "cc", 2
 
 
 @pytest.mark.parametrize("d,K,rule,m", CASES)
-@pytest.mark.parametrize("family", ["exp_sum", "oscillatory", "product_peak"])
+@pytest.mark.parametrize("family", ["exp_sum", "oscillatory", "product_peak", "gaussian"])
 def test_blocked_equals_the_literal_tensor_product(orc, d, K, rule, m, family):
     rng = np.random.default_rng(100 * d + 10 * K + m)
     params = W.draw_params(rng, family, d)
