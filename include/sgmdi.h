@@ -74,7 +74,7 @@ typedef enum {
  * (PRODUCT_PEAK is the integrand of (4.4)/(5.2) with free widths/centres;
  * EXP_SUM generalises (4.5)/(5.1); OSCILLATORY generalises Table 5.7's;
  * GAUSSIAN covers (4.3) and the exponentials of (4.1)/(4.2) (c of either
- * sign; forward sweep and point path, no reverse sweep), OSCILLATORY_QUADRATIC
+ * sign; forward and reverse sweeps and point path), OSCILLATORY_QUADRATIC
  * their sines.  CORNER_PEAK is a ridge function that does not factor per
  * coordinate; it and OSCILLATORY_QUADRATIC (whose even parts are complex) are
  * evaluated by the point-by-point path sg_integrate_points only; plans and
@@ -229,8 +229,8 @@ sg_status sg_plan_execute(sg_plan *plan, const double *params_dev, double *out_d
 /* Gradient of every result with respect to every parameter (reverse sweep):
  * grad_params_dev[k] = grad_out_dev[i] * dQ_i/dparams[k] for the parameters
  * k of problem i, same layout as params.  Parameters not used by any problem
- * are left untouched.  Errors: INVALID_ARGUMENT, DEVICE, UNSUPPORTED (a gaussian
- * problem, or a block-variant plan). */
+ * are left untouched.  Every family a plan takes has a reverse sweep.
+ * Errors: INVALID_ARGUMENT, DEVICE, UNSUPPORTED (a block-variant plan). */
 sg_status sg_plan_execute_grad(sg_plan *plan, const double *params_dev, const double *grad_out_dev,
                                double *grad_params_dev, void *stream);
 

@@ -107,7 +107,6 @@ struct sg_plan {
     int qgrid = 0;                  // persistent kernel: workgroups launched
     bool use_graph = false;         // replay a captured graph (else direct launch)
     bool params_disjoint = true;    // problems' parameter ranges do not overlap
-    bool grad_ok = true;            // every family has a reverse sweep (not the gaussian)
     int kmax = 0;                   // largest K of the plan (kernel instantiation class)
     double* d_ws = nullptr;         // reverse-sweep workspace (sum d*K doubles), lazy
     size_t ws_elems = 0;
@@ -777,7 +776,6 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
         // parameter ranges must be disjoint for the reverse sweep to write them
         std::vector<std::pair<int64_t, int64_t>> rg(n);
         for (int i = 0; i < n; ++i) {
-            if (problems[i].family == SG_FAMILY_GAUSSIAN) p->grad_ok = false;
             const int64_t len = problems[i].family == SG_FAMILY_EXP_SUM ? problems[i].d
                                 : problems[i].family == SG_FAMILY_OSCILLATORY ? (int64_t)problems[i].d + 1
                                                                               : 2 * (int64_t)problems[i].d;
@@ -1041,7 +1039,6 @@ sg_status sg_plan_execute_grad(sg_plan* p, const double* params_dev, const doubl
     if (!params_dev || !grad_out_dev || !grad_params_dev)
         return fail(p->ctx, SG_ERR_INVALID_ARGUMENT, "NULL params, grad_out or grad_params");
     if (p->blocked) return fail(p->ctx, SG_ERR_UNSUPPORTED, "the block variant has no reverse sweep");
-    if (!p->grad_ok) return fail(p->ctx, SG_ERR_UNSUPPORTED, "the gaussian family has no reverse sweep");
     if (!p->params_disjoint)
         return fail(p->ctx, SG_ERR_INVALID_ARGUMENT,
                     "problems share parameters: the reverse sweep needs disjoint parameter ranges");
@@ -1052,8 +1049,8 @@ sg_status sg_plan_execute_grad(sg_plan* p, const double* params_dev, const doubl
             return fail(p->ctx, SG_ERR_OUT_OF_MEMORY, std::string("workspace: ") + hipGetErrorString(e));
         }
     }
-    const int rc = launch_adjoint(p->precision, p->nwg, p->d_wgs, p->d_probs, p->d_pool64, p->d_pool32, params_dev,
-                                  grad_out_dev, grad_params_dev, p->d_ws, stream);
+    const int rc = launch_adjoint(p->precision, p->kmax == kKmaxGauss, p->nwg, p->d_wgs, p->d_probs, p->d_pool64,
+                                  p->d_pool32, params_dev, grad_out_dev, grad_params_dev, p->d_ws, stream);
     if (rc != 0) return hip_fail(p->ctx, (hipError_t)rc, "adjoint launch");
     return SG_OK;
 }

@@ -1136,6 +1136,24 @@ __device__ __forceinline__ void dpair_peak64(const CoordParam& cp, double y, dou
     ds_dhv = 2.0 * y2 * (6.0 * hv * D - N * (2.0 * dp * Dm - 2.0 * dm * Dp)) * iD2;
 }
 
+// Gaussian: s = 2 (e^{c y^2} cosh(c b y) - 1) with b = 1 - 2u; derivatives
+// in c (at fixed u) and in u (db/du = -2).  The exponentials come from the
+// branch-free expm1 of the forward pass (two per pair instead of the
+// library's exp, cosh and sinh, which cost the kernel its registers):
+// with F = expm1(|v|) >= 0, cosh v = 1 + F^2/(2(1 + F)) and
+// |sinh v| = (F + F/(1 + F))/2, both free of cancellation.
+__device__ __forceinline__ void dpair_gauss64(double c, double b, double y, double& ds_dc, double& ds_du)
+{
+    const double e = 1.0 + expm1_any(c * (y * y));
+    const double v = c * (b * y);
+    const double F = expm1_any(fabs(v));
+    const double r = F / (1.0 + F);
+    const double ch = fma(0.5 * F, r, 1.0);
+    const double sh = copysign(0.5 * (F + r), v);
+    ds_dc = 2.0 * e * fma(y * y, ch, b * y * sh);
+    ds_du = -4.0 * c * y * e * sh;
+}
+
 // Inclusive scans of monic truncated polynomials across the 64 lanes.
 template <int K>
 __device__ __forceinline__ void shfl_poly_up(double (&o)[MAXK + 1], const double (&x)[MAXK + 1], int off)
@@ -1181,6 +1199,11 @@ __device__ __forceinline__ void wave_adjoint(const ProbDev& P, int rank, int gro
             cp.p0 = prm[1 + t];
             cp.p1 = 0.0;
             return 0.5 * cp.p0;
+        } else if constexpr (FAM == FAM_GAUSS) {
+            const double c = prm[t], hv = 0.5 - prm[d + t];
+            cp.p0 = c;
+            cp.p1 = c * (2.0 * hv);
+            return c * (hv * hv);                  // log g_t(1/2)
         } else {
             const double b = prm[t], u = prm[d + t];
             cp.p0 = 1.0 / (b * b);
@@ -1274,7 +1297,7 @@ __device__ __forceinline__ void wave_adjoint(const ProbDev& P, int rank, int gro
         sincos(phase, &sph, &cph);
         if (rank == 0 && lane == 0) grad[P.param_offset] = g * (-2.0 * 3.141592653589793 * sph * s);
     } else {
-        A = exp(FAM == FAM_EXP ? ls : -ls);
+        A = exp(FAM == FAM_PEAK ? -ls : ls);
     }
 
     // pass 2: per coordinate, R_t from prefix, suffix and the lane's other
@@ -1304,7 +1327,20 @@ __device__ __forceinline__ void wave_adjoint(const ProbDev& P, int rank, int gro
         }
         CoordParam cp;
         coord_param(t, cp);
-        if constexpr (FAM == FAM_PEAK) {
+        if constexpr (FAM == FAM_GAUSS) {
+            const double c = prm[t], hv = 0.5 - prm[d + t], b = 2.0 * hv;
+            double dc[MAXK + 1], du[MAXK + 1], eps = 0.0;
+            surplus64g<K, RC>(r64 + opaque, [&](double y) { double a, e; dpair_gauss64(c, b, y, a, e); return a; },
+                              false, dc, eps);
+            surplus64g<K, RC>(r64 + opaque, [&](double y) { double a, e; dpair_gauss64(c, b, y, a, e); return e; },
+                              false, du, eps);
+            double dsc = 0.0, dsu = 0.0;
+#pragma unroll
+            for (int e = 1; e <= K; ++e) { dsc = fma(G[e], dc[e], dsc); dsu = fma(G[e], du[e], dsu); }
+            // Q = A s, A = prod exp(c_t hv_t^2): dA/dc_t = hv_t^2 A, dA/du_t = -2 c_t hv_t A
+            grad[P.param_offset + t] = g * A * fma(s, hv * hv, dsc);
+            grad[P.param_offset + d + t] = g * A * fma(s, -2.0 * c * hv, dsu);
+        } else if constexpr (FAM == FAM_PEAK) {
             double db[MAXK + 1], du[MAXK + 1], eps = 0.0;
             surplus64g<K, RC>(r64 + opaque, [&](double y) { double a, b; dpair_peak64(cp, y, a, b); return a; },
                               false, db, eps);
@@ -1340,36 +1376,34 @@ __device__ __forceinline__ void wave_adjoint(const ProbDev& P, int rank, int gro
     }
 }
 
-template <int PREC, int K>
+template <int PREC, int K, bool GAUSS>
 __device__ __forceinline__ void adjoint_dispatch_k(const ProbDev& P, int rank, int group, bool grouped,
                                                    const double* pool64, const float* pool32, const double* params,
                                                    const double* gout, double* grad, double* ws, double* lds)
 {
 #define SG_ADJ(RC, FAM) wave_adjoint<PREC, K, RC, FAM>(P, rank, group, grouped, pool64, pool32, params, gout, grad, ws, lds)
+#define SG_ADJ_FAMS(RC)                                       \
+    do {                                                      \
+        if (GAUSS && P.family == FAM_GAUSS) {                 \
+            if constexpr (GAUSS) SG_ADJ(RC, FAM_GAUSS);       \
+        } else if (P.family == FAM_EXP) SG_ADJ(RC, FAM_EXP);  \
+        else if (P.family == FAM_OSC) SG_ADJ(RC, FAM_OSC);    \
+        else SG_ADJ(RC, FAM_PEAK);                            \
+    } while (0)
     const int rc = rule_class_of(P.rule);
-    if (rc == RC_NESTED) {
-        if (P.family == FAM_EXP) SG_ADJ(RC_NESTED, FAM_EXP);
-        else if (P.family == FAM_OSC) SG_ADJ(RC_NESTED, FAM_OSC);
-        else SG_ADJ(RC_NESTED, FAM_PEAK);
-    } else if (rc == RC_GL2) {
-        if (P.family == FAM_EXP) SG_ADJ(RC_GL2, FAM_EXP);
-        else if (P.family == FAM_OSC) SG_ADJ(RC_GL2, FAM_OSC);
-        else SG_ADJ(RC_GL2, FAM_PEAK);
-    } else if (rc == RC_GP) {
-        if (P.family == FAM_EXP) SG_ADJ(RC_GP, FAM_EXP);
-        else if (P.family == FAM_OSC) SG_ADJ(RC_GP, FAM_OSC);
-        else SG_ADJ(RC_GP, FAM_PEAK);
-    } else {
-        if (P.family == FAM_EXP) SG_ADJ(RC_GLP, FAM_EXP);
-        else if (P.family == FAM_OSC) SG_ADJ(RC_GLP, FAM_OSC);
-        else SG_ADJ(RC_GLP, FAM_PEAK);
-    }
+    if (rc == RC_NESTED) SG_ADJ_FAMS(RC_NESTED);
+    else if (rc == RC_GL2) SG_ADJ_FAMS(RC_GL2);
+    else if (rc == RC_GP) SG_ADJ_FAMS(RC_GP);
+    else SG_ADJ_FAMS(RC_GLP);
+#undef SG_ADJ_FAMS
 #undef SG_ADJ
 }
 
 // Same workgroup packing as the forward pass.  Every wave of a workgroup
-// that holds a multi-wave problem passes exactly one barrier.
-template <int PREC>
+// that holds a multi-wave problem passes exactly one barrier.  GAUSS: the
+// instantiation for plans that hold gaussian problems (it runs every
+// family), kept apart so that the others' code and registers do not change.
+template <int PREC, bool GAUSS = false>
 __global__ void __launch_bounds__(256)
 k_adjoint(const WGDesc* __restrict__ wgs, const ProbDev* __restrict__ probs, const double* __restrict__ pool64,
           const float* __restrict__ pool32, const double* __restrict__ params, const double* __restrict__ gout,
@@ -1390,8 +1424,8 @@ k_adjoint(const WGDesc* __restrict__ wgs, const ProbDev* __restrict__ probs, con
     }
     const ProbDev P = desc->slot[w].p;
     switch_k<MAXK>(P.K, [&](auto kc) {
-        adjoint_dispatch_k<PREC, decltype(kc)::value>(P, sl.rank, sl.group, grouped, pool64, pool32, params, gout,
-                                                      grad, ws, lds + w * ADJ_WORDS);
+        adjoint_dispatch_k<PREC, decltype(kc)::value, GAUSS>(P, sl.rank, sl.group, grouped, pool64, pool32, params,
+                                                             gout, grad, ws, lds + w * ADJ_WORDS);
     });
 }
 

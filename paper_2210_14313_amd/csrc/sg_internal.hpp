@@ -163,9 +163,11 @@ int launch_forward(int precision, int kmax, int nwg, const FwdWG* wgs, unsigned 
                    double* bound, void* stream);
 // Resident workgroups of the persistent forward kernel on the current device.
 int forward_capacity(int precision, int kmax);
-int launch_adjoint(int precision, int nwg, const WGDesc* wgs, const ProbDev* probs, const double* pool64,
-                   const float* pool32, const double* params, const double* gout, double* grad, double* ws,
-                   void* stream);
+// Reverse sweep; gauss: the plan holds gaussian problems (launches the
+// instantiation built with that family).
+int launch_adjoint(int precision, bool gauss, int nwg, const WGDesc* wgs, const ProbDev* probs,
+                   const double* pool64, const float* pool32, const double* params, const double* gout,
+                   double* grad, double* ws, void* stream);
 int launch_unrank(int d, int q, uint64_t rank0, uint64_t count, int max_nnz,
                   const uint64_t* binom_table, int binom_rows, int32_t* coords, int32_t* levels,
                   int32_t* nnz, void* stream);

@@ -70,10 +70,10 @@ int launch_forward_p2(int, int, const FwdWG*, unsigned int*, int, const double*,
 int forward_capacity_p0(int);
 int forward_capacity_p1(int);
 int forward_capacity_p2(int);
-int launch_adjoint_p0(int, const WGDesc*, const ProbDev*, const double*, const float*, const double*, const double*,
-                      double*, double*, void*);
-int launch_adjoint_p1(int, const WGDesc*, const ProbDev*, const double*, const float*, const double*, const double*,
-                      double*, double*, void*);
+int launch_adjoint_p0(bool, int, const WGDesc*, const ProbDev*, const double*, const float*, const double*,
+                      const double*, double*, double*, void*);
+int launch_adjoint_p1(bool, int, const WGDesc*, const ProbDev*, const double*, const float*, const double*,
+                      const double*, double*, double*, void*);
 
 int launch_forward(int precision, int kmax, int nwg, const FwdWG* wgs, unsigned int* queue, int qgrid,
                    const double* pool64, const float* pool32, const double* params, double* out, double* bound,
@@ -93,13 +93,13 @@ int forward_capacity(int precision, int kmax)
     return forward_capacity_p2(kmax);
 }
 
-int launch_adjoint(int precision, int nwg, const WGDesc* wgs, const ProbDev* probs, const double* pool64,
-                   const float* pool32, const double* params, const double* gout, double* grad, double* ws,
-                   void* stream)
+int launch_adjoint(int precision, bool gauss, int nwg, const WGDesc* wgs, const ProbDev* probs,
+                   const double* pool64, const float* pool32, const double* params, const double* gout,
+                   double* grad, double* ws, void* stream)
 {
     return precision == SG_PREC_FP64
-               ? launch_adjoint_p0(nwg, wgs, probs, pool64, pool32, params, gout, grad, ws, stream)
-               : launch_adjoint_p1(nwg, wgs, probs, pool64, pool32, params, gout, grad, ws, stream);
+               ? launch_adjoint_p0(gauss, nwg, wgs, probs, pool64, pool32, params, gout, grad, ws, stream)
+               : launch_adjoint_p1(gauss, nwg, wgs, probs, pool64, pool32, params, gout, grad, ws, stream);
 }
 
 int launch_unrank(int d, int q, uint64_t rank0, uint64_t count, int max_nnz,

@@ -40,8 +40,8 @@ ALL_RULES = RULES + ("gp",)
 FAMILIES = ("exp_sum", "oscillatory", "product_peak")
 #: families only the point-by-point path handles (ridge functions that do not factor)
 POINT_ONLY_FAMILIES = ("corner_peak", "oscillatory_quadratic")
-#: families the forward sweep handles beyond FAMILIES (no reverse sweep)
-FORWARD_ONLY_FAMILIES = ("gaussian",)
+#: families the sweep handles beyond FAMILIES (kept out of the default mixes)
+EXTRA_SWEEP_FAMILIES = ("gaussian",)
 
 #: seeds used for the five standard workloads (workload k uses SEED_BASE + k)
 SEED_BASE = 14313
@@ -114,7 +114,7 @@ class _Builder:
 
     def add(self, d: int, q: int, rule: str, family: str, params: np.ndarray):
         assert rule in ALL_RULES and (family in FAMILIES or family in POINT_ONLY_FAMILIES
-                                      or family in FORWARD_ONLY_FAMILIES)
+                                      or family in EXTRA_SWEEP_FAMILIES)
         params = np.asarray(params, dtype=np.float64).ravel()
         assert params.size == n_params(family, d)
         self.problems.append(Problem(int(d), int(q), rule, family, self.off))

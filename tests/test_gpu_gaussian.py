@@ -1,12 +1,15 @@
 """GPU parity of the gaussian family exp(sum c_i (x_i - u_i)^2) on the
 forward sweep ((4.1)-(4.3)): batched plans in the three precision modes,
 large and negative c (the growing exp(5 x^2) of (4.1) is c = 20 on the unit
-cube), K up to 8, mixed batches, the block variant, and the refusal of the
-reverse sweep; against the oracle's factorised and point-by-point sums.
+cube), K up to 8, mixed batches, the block variant, and the reverse sweep;
+against the oracle's factorised and point-by-point sums and its binary128
+factorised gradient.
 
 Tolerances: FP64 within 1e-12 relative and within the stated bound; FP32
 modes within the stated bound (their node values are FP64 values rounded
-once, like product-peak's).
+once, like product-peak's).  Gradients: per problem, relative to its
+largest entry, 1e-11 in FP64 and 1e-6 with FP32 forward surpluses, the
+reverse sweep's bars for the other families.
 """
 import sys
 
@@ -94,14 +97,39 @@ def test_gaussian_block_variant(torch_dev, orc):
     _check(got, bnd, ref, "fp64")
 
 
-def test_gaussian_has_no_reverse_sweep(torch_dev):
+def _grad(batch, precision):
     import torch
-    from paper_2210_14313_amd import api, native, workloads as W
-    b = W.single(4, 6, "cc", "gaussian", np.array([1.0, -1.0, 0.5, 2.0, 0.1, 0.5, 0.9, 0.3]))
-    plan = native.Plan(b.problems, "fp64")
+    from paper_2210_14313_amd import api, native
+    params = api.params_tensor(batch)
+    plan = native.Plan(batch.problems, precision)
     try:
-        with pytest.raises(native.SgError) as e:
-            plan.execute_grad(api.params_tensor(b), torch.ones(1, dtype=torch.float64, device="cuda"))
-        assert e.value.status == 2
+        g = plan.execute_grad(params, torch.ones(len(batch), dtype=torch.float64, device="cuda"))
+        torch.cuda.synchronize()
+        return g.cpu().numpy()
     finally:
         plan.close()
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_gaussian_gradient(torch_dev, orc, seed):
+    # gaussian problems of every rule with K up to 8 (compiled and
+    # table-driven levels) in one batch with the other sweep families, so
+    # the gaussian instantiation of the reverse sweep runs all of them;
+    # per problem, error relative to its largest gradient entry
+    from paper_2210_14313_amd import workloads as W
+    b = W.concat([W.random_small(800 + seed, 24, d_range=(1, 80), k_range=(0, 8), families=("gaussian",),
+                                 rules=W.ALL_RULES),
+                  W.random_small(810 + seed, 16, d_range=(1, 80), k_range=(0, 6))])
+    say("case gaussian gradient", seed)
+    ref = np.zeros_like(b.params)
+    for i, p in enumerate(b.problems):
+        ref[p.param_offset:p.param_offset + W.n_params(p.family, p.d)] = \
+            orc.smolyak_factorised_grad(p.d, p.q, p.rule, p.family, b.param_slice(i))
+    for prec, tol in (("fp64", 1e-11), ("fp32c", 1e-6)):
+        got = _grad(b, prec)
+        errs = []
+        for i, p in enumerate(b.problems):
+            sl = slice(p.param_offset, p.param_offset + W.n_params(p.family, p.d))
+            errs.append(np.max(np.abs(got[sl] - ref[sl])) / max(np.max(np.abs(ref[sl])), 1e-300))
+        say(prec, "max per-problem relative gradient error", max(errs))
+        assert max(errs) <= tol, (prec, int(np.argmax(errs)), max(errs))
