@@ -10,7 +10,9 @@ Prints ONE JSON line (rank 0).  Metric: effective sparse-grid points per
 second = sum over integrands of n_d^q (points with repetition of (2.6))
 divided by the time of one step.  Extras: time-to-integral at d = 1000,
 batched vs plain per-integrand FP64 speedup at the 1e-7 accuracy target,
-the FP64 batched rate, and the accuracy against the CPU oracle.
+the FP64 batched rate, and the accuracy against the CPU oracle's values
+of the timed workloads, stored under tests/golden (the oracle itself runs
+only for the CPU baseline).
 """
 from __future__ import annotations
 
@@ -148,6 +150,69 @@ def points_flop_slots(d: int, q: int, rule: str):
     return pts, 10 * pts + 2 * nnz - pts
 
 
+BENCH_REFS = os.path.join(ROOT, "tests", "golden", "bench_refs.npz")
+
+
+def bench_refs():
+    """The oracle's values for the timed workloads, stored by
+    tests/golden/make_bench_refs.py (the benchmark itself runs the oracle
+    only for its CPU baseline)."""
+    import numpy as np
+    with np.load(BENCH_REFS) as z:
+        return {k: z[k] for k in z.files}
+
+
+def adjoint_leg(dev, s):
+    """Reverse sweep on the 256-integrand oscillatory d = 200, q = 205 CC
+    batch: gradient and forward time per launch (HIP events on the launch
+    stream), error against the oracle's binary128 gradient of the first 64
+    integrands (stored), roofline over the reverse sweep's flop-slots."""
+    import numpy as np
+    import torch
+
+    from paper_2210_14313_amd import api, native, workloads as W
+    gb = W.gradient_osc_d200()
+    gref = bench_refs()["gradient_osc_d200_first64"]
+    gparams = api.params_tensor(gb, dev)
+    gout = torch.ones(len(gb), dtype=torch.float64, device=dev)
+    adj = {}
+    for prec in ("fp32c", "fp64"):
+        plan = native.Plan(gb.problems, prec)
+        gp = torch.zeros_like(gparams)
+        s.wait_stream(torch.cuda.current_stream())
+        for _ in range(3):
+            plan.execute_grad(gparams, gout, gp, stream=s)
+        torch.cuda.synchronize()
+        reps = 50
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            plan.execute_grad(gparams, gout, gp, stream=s)
+        e1.record(s)
+        torch.cuda.synchronize()
+        fwd = torch.empty(len(gb), dtype=torch.float64, device=dev)
+        f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        f0.record(s)
+        for _ in range(reps):
+            plan.execute(gparams, fwd, stream=s)
+        f1.record(s)
+        torch.cuda.synchronize()
+        g = gp.cpu().numpy()
+        errs = []
+        for i, p in enumerate(gb.problems[:len(gref)]):
+            sl = slice(p.param_offset, p.param_offset + p.d + 1)
+            errs.append(np.max(np.abs(g[sl] - gref[i])) / np.max(np.abs(gref[i])))
+        gms = e0.elapsed_time(e1) / reps
+        slots = adjoint_flop_slots(plan.info(), gb.problems)
+        ach = slots / (gms / 1e3) / 1e12
+        adj[prec] = {"grad_ms": gms, "forward_ms": f0.elapsed_time(f1) / reps,
+                     "max_rel_err_vs_oracle_grad": float(np.max(errs)), "checked_integrands": len(errs),
+                     "roofline": {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                  "frac": ach / VALU_PEAK_TFLOPS, "flop_slots_per_launch": slots}}
+        plan.close()
+    return adj
+
+
 def points_leg(dev, s, reps: int = 5):
     """Time the literal point-by-point path on the d = 100, q = 105
     Clenshaw-Curtis workload (both families) and check it against the
@@ -188,21 +253,20 @@ def points_leg(dev, s, reps: int = 5):
     return pts
 
 
-def blocked_leg(dev, s, batch, precision: str, m: int = 10, reps: int = 50, check: int = 256):
+def blocked_leg(dev, s, batch, precision: str, m: int = 10, reps: int = 50):
     """Block (tensor-product) variant of the rule, Algorithm 3.3 with step m:
     the batch in blocks of m coordinates (block gather, forward over the
     blocks, ordered combine; timed with events, roofline over the forward
     work of the blocks, accuracy against the oracle's block rule on the
-    first `check` integrands), and the m = 10 setting of Table 4.9
+    first 256 integrands of the 4096 batch, stored), and the m = 10 setting
+    of Table 4.9
     (Gauss-Legendre with n_l = l, [-1,1]^d mapped to the unit cube; excess
     K = 8, the largest this library builds, where the table uses 9): time
     to integral and relative error against the exact integral."""
-    import mpmath as mp
     import numpy as np
     import torch
-    from oracle import blocked as OB
-    from oracle import reference as R
     from paper_2210_14313_amd import api, native, workloads as W
+    refs = bench_refs()
     res = {}
     params = api.params_tensor(batch, dev)
     plan = native.Plan(batch.problems, precision, block_dims=m)
@@ -222,11 +286,15 @@ def blocked_leg(dev, s, batch, precision: str, m: int = 10, reps: int = 50, chec
     info = plan.info()
     plan.close()
     got, bnd = out.cpu().numpy(), bound.cpu().numpy()
-    idx = list(range(min(check, len(batch))))
-    ref = np.array([OB.smolyak_blocked(batch.problems[i].d, batch.problems[i].q, batch.problems[i].rule,
-                                       batch.problems[i].family, batch.param_slice(i), m) for i in idx])
-    fam = np.array([batch.problems[i].family for i in idx])
-    sc = np.where(fam == "oscillatory", np.maximum(np.abs(ref), 1.0), np.abs(ref))
+    if len(batch) == 4096 and m == 10:
+        ref = refs["blocked_m10_first256"]
+        idx = list(range(len(ref)))
+        fam = np.array([batch.problems[i].family for i in idx])
+        sc = np.where(fam == "oscillatory", np.maximum(np.abs(ref), 1.0), np.abs(ref))
+        acc_err = float(np.max(np.abs(got[idx] - ref) / sc))
+        acc_ok = bool(np.all(np.abs(got[idx] - ref) <= bnd[idx]))
+    else:
+        idx, acc_err, acc_ok = [], None, None
     achieved = algorithmic_flops(info) / (ms / 1e3) / 1e12
     res[f"batched_uneven_{len(batch)}_m{m}"] = {
         "precision": precision, "ms_per_launch": ms, "block_subproblems_units": info["units"],
@@ -234,14 +302,14 @@ def blocked_leg(dev, s, batch, precision: str, m: int = 10, reps: int = 50, chec
                                           "grid_blocks")},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / VALU_PEAK_TFLOPS, "flop_slots_per_launch": algorithmic_flops(info)},
-        "max_rel_err_vs_block_oracle": float(np.max(np.abs(got[idx] - ref) / sc)),
-        "all_within_stated_bound": bool(np.all(np.abs(got[idx] - ref) <= bnd[idx])),
+        "max_rel_err_vs_block_oracle": acc_err, "all_within_stated_bound": acc_ok,
         "checked_integrands": len(idx)}
     log(f"  blocked m={m} {precision}: {ms * 1e3:.2f} us per launch, frac {achieved / VALU_PEAK_TFLOPS:.4f}")
     K = 8
     paper = {}
     # exp(sum (-1)^(i+1) x_i) at d = 1000; prod 1/(0.9^2 + (x_i - 0.6)^2) at
     # d = 300 (on the unit cube its value exceeds the double range at d = 1000)
+    names = [str(x) for x in refs["table_4_9_names"]]
     for name, fam, d in (("exp_alt_d1000", "exp_sum", 1000), ("peak_06_d300", "product_peak", 300)):
         prm = (np.array([2.0 * (-1) ** i for i in range(d)]) if fam == "exp_sum"
                else np.concatenate([np.full(d, 1 / 0.45), np.full(d, 0.8)]))
@@ -260,10 +328,10 @@ def blocked_leg(dev, s, batch, precision: str, m: int = 10, reps: int = 50, chec
                     v = o.item()
                     ts.append(time.perf_counter() - t0)
             plan.close()
-            ex = R.exact(fam, d, prm)
-            orc_v = OB.smolyak_blocked(d, d + K, "gl_paper", fam, prm, 10)
+            ex = float(refs["table_4_9_exact"][names.index(name)])
+            orc_v = float(refs["table_4_9_blocked"][names.index(name)])
             row[prec] = {"value": v, "stated_bound": bo.item(), "time_to_integral_median_s": statistics.median(ts[1:]),
-                         "rel_err_vs_exact": float(abs((mp.mpf(v) - ex) / ex)),
+                         "rel_err_vs_exact": abs((v - ex) / ex),
                          "rel_diff_vs_block_oracle": abs(v - orc_v) / abs(orc_v)}
         paper[name] = row
         log(f"  blocked m=10 {name}: rel err vs exact {row['fp64']['rel_err_vs_exact']:.4e}, "
@@ -320,6 +388,8 @@ def main():
                     help="only run the traffic-counter calibration copy of this many MiB")
     ap.add_argument("--blocked-only", action="store_true",
                     help="only run the block-variant leg (m = 10) and print its JSON")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only the reverse-sweep leg (oscillatory d = 200, 256 integrands)")
     ap.add_argument("--points-only", action="store_true",
                     help="only run the literal point-by-point leg (d = 100, q = 105) and print its JSON")
     args = ap.parse_args()
@@ -336,8 +406,13 @@ def main():
     import numpy as np
     import torch
 
-    import oracle
     from paper_2210_14313_amd import api, native, workloads as W
+
+    if args.adjoint_only:
+        torch.cuda.set_device(0)
+        sa = torch.cuda.Stream()
+        print(json.dumps({"adjoint_gradient_osc_d200_n256": adjoint_leg(torch.device("cuda:0"), sa)}), flush=True)
+        return
 
     if args.points_only:
         torch.cuda.set_device(0)
@@ -351,13 +426,17 @@ def main():
         sb = torch.cuda.Stream()
         print(json.dumps({"blocked_m10": blocked_leg(torch.device("cuda:0"), sb, batch, args.precision)}), flush=True)
         return
-    # oracle values first (CPU, binary128) for the accuracy statement
-    log("oracle reference (binary128, threaded) ...")
-    t0 = time.perf_counter()
-    ref = oracle.batch_factorised(batch, nthreads=min(16, os.cpu_count() or 1))
-    log(f"  done in {time.perf_counter() - t0:.1f} s")
+    # accuracy statement against the oracle's binary128 values of the
+    # 4096-integrand batch (stored; other sizes report none)
+    ref = bench_refs()["uneven_4096"] if args.n == 4096 else None
     fam = np.array([p.family for p in batch.problems])
-    scale = np.where(fam == "oscillatory", np.maximum(np.abs(ref), 1.0), np.abs(ref))
+    scale = None if ref is None else np.where(fam == "oscillatory", np.maximum(np.abs(ref), 1.0), np.abs(ref))
+
+    def rel_err(got):
+        return None if ref is None else float(np.max(np.abs(got - ref) / scale))
+
+    def within(got, bnd):
+        return None if ref is None else bool(np.all(np.abs(got - ref) <= bnd))
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
@@ -413,9 +492,8 @@ def main():
         pinned = PINNED_SCHEDULE[args.precision]
     main_run = run_plan(args.precision, args.steps, args.warmup, args.autotune, pinned)
     info = main_run["info"]
-    err = np.abs(main_run["got"] - ref) / scale
-    max_err = float(np.max(err))
-    bound_ok = bool(np.all(np.abs(main_run["got"] - ref) <= main_run["bound"]))
+    max_err = rel_err(main_run["got"])
+    bound_ok = within(main_run["got"], main_run["bound"])
     eff = float(info["effective_points"])
     value = eff / (main_run["ms_per_step"] / 1e3)
     flops = algorithmic_flops(info)
@@ -446,7 +524,7 @@ def main():
                      if args.n == 4096 else None,
                      "kernel_ms": main_run["kernel_ms"], "algorithmic_flops_per_launch": flops},
         "accuracy": {"max_rel_err_vs_oracle": max_err, "all_within_stated_bound": bound_ok,
-                     "max_stated_rel_bound": float(np.max(main_run["bound"] / scale))},
+                     "max_stated_rel_bound": None if ref is None else float(np.max(main_run["bound"] / scale))},
     }
 
     if not args.no_extras:
@@ -457,14 +535,14 @@ def main():
             "schedule": {k: at["info"][k] for k in ("coords_per_lane", "max_group", "cost_scaled", "persistent",
                                                     "graph", "grid_blocks")},
             "kernel_ms": at["kernel_ms"], "ms_per_step": at["ms_per_step"],
-            "max_rel_err_vs_oracle": float(np.max(np.abs(at["got"] - ref) / scale))}
+            "max_rel_err_vs_oracle": rel_err(at["got"])}
         # the other precision modes' batched rates
         for other in [m for m in ("fp64", "fp32e", "fp32c") if m != args.precision]:
             r2 = run_plan(other, max(20, args.steps // 2), 5, False, PINNED_SCHEDULE[other])
             extras[f"{other}_batched"] = {
                 "points_per_s": eff / (r2["ms_per_step"] / 1e3), "ms_per_step": r2["ms_per_step"],
-                "kernel_ms": r2["kernel_ms"], "max_rel_err_vs_oracle": float(np.max(np.abs(r2["got"] - ref) / scale)),
-                "all_within_stated_bound": bool(np.all(np.abs(r2["got"] - ref) <= r2["bound"]))}
+                "kernel_ms": r2["kernel_ms"], "max_rel_err_vs_oracle": rel_err(r2["got"]),
+                "all_within_stated_bound": within(r2["got"], r2["bound"])}
         # plain per-integrand FP64 path: one launch per integrand, no plan, no graph
         log("plain per-integrand FP64 path ...")
         outp = torch.empty(len(batch), dtype=torch.float64, device=dev)
@@ -479,15 +557,18 @@ def main():
             native.integrate_one(p, pv, "fp64", out=ov, stream=s)
         torch.cuda.synchronize()
         t_plain = time.perf_counter() - t0
-        plain_err = float(np.max(np.abs(outp.cpu().numpy() - ref) / scale))
+        plain_err = rel_err(outp.cpu().numpy())
         extras["batched_vs_plain"] = {
             "plain_fp64_ms": t_plain * 1e3, "batched_ms": main_run["ms_per_step"],
-            "speedup": (t_plain * 1e3 / main_run["ms_per_step"]) if max_err <= 1e-7 else None,
+            "speedup": (t_plain * 1e3 / main_run["ms_per_step"]) if max_err is not None and max_err <= 1e-7
+            else None,
             "batched_max_rel_err": max_err, "plain_max_rel_err": plain_err,
             "accuracy_target": 1e-7}
         # time to integral at d = 1000 (wall time, call -> host-visible value)
         hd = W.high_dim_d1000()
-        ref_hd = oracle.batch_factorised(hd)
+        golden = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_full_size.json")))["rows"]
+        ref_hd = {r["index"]: r["factorised_hi"] + r["factorised_lo"] for r in golden
+                  if r["workload"] == "high_dim_d1000"}
         tti = {}
         for i, p in enumerate(hd.problems):
             one = hd.subset([i])
@@ -537,49 +618,7 @@ def main():
         log("block variant (m = 10) ...")
         extras["blocked_m10"] = blocked_leg(dev, s, batch, args.precision)
         # reverse sweep on the gradient workload (256 oscillatory, d = 200, q = 205)
-        gb = W.gradient_osc_d200()
-        gref = np.zeros_like(gb.params)
-        for i, p in enumerate(gb.problems):
-            gref[p.param_offset:p.param_offset + p.d + 1] = oracle.smolyak_factorised_grad(
-                p.d, p.q, p.rule, p.family, gb.param_slice(i))
-        gparams = api.params_tensor(gb, dev)
-        gout = torch.ones(len(gb), dtype=torch.float64, device=dev)
-        adj = {}
-        for prec in ("fp32c", "fp64"):
-            plan = native.Plan(gb.problems, prec)
-            gp = torch.zeros_like(gparams)
-            s.wait_stream(torch.cuda.current_stream())
-            for _ in range(3):
-                plan.execute_grad(gparams, gout, gp, stream=s)
-            torch.cuda.synchronize()
-            reps = 50
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(s)
-            for _ in range(reps):
-                plan.execute_grad(gparams, gout, gp, stream=s)
-            e1.record(s)
-            torch.cuda.synchronize()
-            fwd = torch.empty(len(gb), dtype=torch.float64, device=dev)
-            f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            f0.record(s)
-            for _ in range(reps):
-                plan.execute(gparams, fwd, stream=s)
-            f1.record(s)
-            torch.cuda.synchronize()
-            g = gp.cpu().numpy()
-            errs = []
-            for i, p in enumerate(gb.problems):
-                sl = slice(p.param_offset, p.param_offset + p.d + 1)
-                errs.append(np.max(np.abs(g[sl] - gref[sl])) / np.max(np.abs(gref[sl])))
-            gms = e0.elapsed_time(e1) / reps
-            slots = adjoint_flop_slots(plan.info(), gb.problems)
-            ach = slots / (gms / 1e3) / 1e12
-            adj[prec] = {"grad_ms": gms, "forward_ms": f0.elapsed_time(f1) / reps,
-                         "max_rel_err_vs_oracle_grad": float(np.max(errs)),
-                         "roofline": {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                                      "frac": ach / VALU_PEAK_TFLOPS, "flop_slots_per_launch": slots}}
-            plan.close()
-        extras["adjoint_gradient_osc_d200_n256"] = adj
+        extras["adjoint_gradient_osc_d200_n256"] = adjoint_leg(dev, s)
 
         # literal point-by-point path on the d = 100, q = 105 workload
         # (2.08e10 points per integrand) against the stored oracle values
