@@ -76,9 +76,10 @@ typedef enum {
  * GAUSSIAN covers (4.3) and the exponentials of (4.1)/(4.2) (c of either
  * sign; forward and reverse sweeps and point path), OSCILLATORY_QUADRATIC
  * their sines.  CORNER_PEAK is a ridge function that does not factor per
- * coordinate; it and OSCILLATORY_QUADRATIC (whose even parts are complex) are
- * evaluated by the point-by-point path sg_integrate_points only; plans and
- * sg_integrate reject them with UNSUPPORTED.) */
+ * coordinate: the point-by-point path sg_integrate_points only.
+ * OSCILLATORY_QUADRATIC factors with complex per-coordinate surpluses: the
+ * point path, and sg_integrate in FP64 (a sweep with complex truncated
+ * products); plans reject both with UNSUPPORTED.) */
 typedef enum {
     SG_FAMILY_EXP_SUM = 0,
     SG_FAMILY_OSCILLATORY = 1,
@@ -323,7 +324,10 @@ sg_status sg_integrate_points(sg_context *ctx, const sg_problem *problem, const 
 /* Plain, plan-free path: one integrand, one launch, no graph, no batching.
  * Same arguments as one problem of a plan (param_offset is ignored: params_dev
  * points at this integrand's parameters).  out_dev/bound_dev: one float64
- * each (bound may be NULL). */
+ * each (bound may be NULL).  Also takes OSCILLATORY_QUADRATIC (FP64 only;
+ * the FP32 modes fail with UNSUPPORTED): the sweep of Section 3 with the
+ * complex surpluses of e^{i a (x - u)^2} and the bound of the real sweep
+ * (complex moduli in place of absolute values). */
 sg_status sg_integrate(sg_context *ctx, const sg_problem *problem, int32_t precision,
                        const double *params_dev, double *out_dev, double *bound_dev, void *stream);
 

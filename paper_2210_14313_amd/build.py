@@ -14,7 +14,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsgmdi.so")
 
 SOURCES = ["sg_fwd0.hip", "sg_fwd1.hip", "sg_fwd2.hip", "sg_adj0.hip", "sg_adj1.hip", "sg_unrank.hip", "sg_points.hip",
-           "sg_blocked.hip", "sg_rules.cpp", "sg_counts.cpp", "sg_api.cpp"]
+           "sg_blocked.hip", "sg_oscq.hip", "sg_rules.cpp", "sg_counts.cpp", "sg_api.cpp"]
 
 # Packed FP32 instructions are disabled for every device pass; contraction of
 # a*b+c into FMAs is off so that compensated (two-sum) sequences keep their

@@ -14,6 +14,15 @@
 
 #include "sg_internal.hpp"
 
+namespace sg {
+// Oscillatory-quadratic sweep (sg_oscq.hip; complex truncated products,
+// FP64): one integrand of dimension d, excess K, rule; pool64: the (rule, K)
+// FP64 record table; params: w, a[d], u[d]; out, bound (NULL: none): one
+// double each.
+int launch_oscq(int d, int K, int rule, const double* pool64, const double* params, double* out, double* bound,
+                void* stream);
+}  // namespace sg
+
 using namespace sg;
 
 namespace {
@@ -1223,9 +1232,29 @@ sg_status sg_integrate(sg_context* ctx, const sg_problem* problem, int32_t preci
     if (!problem || !params_dev || !out_dev) return fail(ctx, SG_ERR_INVALID_ARGUMENT, "NULL argument");
     if (precision != SG_PREC_FP64 && precision != SG_PREC_FP32_COMPENSATED && precision != SG_PREC_FP32_FP64_SUM)
         return fail(ctx, SG_ERR_INVALID_ARGUMENT, "unknown precision");
-    sg_status st = validate_problem(ctx, *problem, 0);
+    // the oscillatory quadratic (complex surpluses) has a sweep of its own,
+    // here only: FP64, one integrand
+    const bool oscq = problem->family == SG_FAMILY_OSCILLATORY_QUADRATIC;
+    sg_status st = validate_problem(ctx, *problem, 0, oscq);
     if (st != SG_OK) return st;
+    if (oscq && precision != SG_PREC_FP64)
+        return fail(ctx, SG_ERR_UNSUPPORTED, "the oscillatory-quadratic sweep computes in FP64 only");
     const int K = problem->q - problem->d;
+    if (oscq) {
+        auto key = std::make_tuple(problem->rule, K, problem->family, 0);
+        auto it = ctx->plain.find(key);
+        if (it == ctx->plain.end()) {
+            const Records* r = get_records(ctx, problem->rule, K, st);
+            if (!r) return st;
+            PlainEntry pe;
+            if ((st = upload(ctx, &pe.pool64, r->r64.data(), r->r64.size())) != SG_OK) return st;
+            it = ctx->plain.emplace(key, pe).first;
+        }
+        const int rc = launch_oscq(problem->d, K, problem->rule, it->second.pool64, params_dev, out_dev, bound_dev,
+                                   stream);
+        if (rc != 0) return hip_fail(ctx, (hipError_t)rc, "oscillatory-quadratic launch");
+        return SG_OK;
+    }
     auto key = std::make_tuple(problem->rule, K, problem->family, problem->d);
     auto it = ctx->plain.find(key);
     if (it == ctx->plain.end()) {
