@@ -213,6 +213,66 @@ def adjoint_leg(dev, s):
     return adj
 
 
+def oscq_leg(dev, s, reps: int = 50):
+    """Oscillatory quadratic cos(2 pi w + sum a_i (x_i - u_i)^2) on the sweep
+    with complex surpluses (sg_integrate, FP64), d = 1000, q = 1004,
+    Gauss-Patterson: time per call (HIP events on the launch stream),
+    accuracy against the oracle's stored binary128 value, and the roofline
+    over its flop-slots (two sincos per node pair, 16; 4 per complex
+    multiply-add of a surplus; 4 K^2 per coordinate for the complex
+    truncated products).  One integrand is one workgroup: the launch is
+    latency-bound by construction."""
+    import torch
+    from paper_2210_14313_amd import api, native, workloads as W
+    b = W.oscillatory_quadratic_d1000()
+    p = b.problems[0]
+    K = p.q - p.d
+    pr = api.params_tensor(b, dev)
+    o = torch.empty(1, dtype=torch.float64, device=dev)
+    bd = torch.empty_like(o)
+    s.wait_stream(torch.cuda.current_stream())
+    for _ in range(3):
+        native.integrate_one(p, pr, "fp64", out=o, bound=bd, stream=s)
+    torch.cuda.synchronize()
+    # through the Python binding: the host's per-call cost sets the pace
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        native.integrate_one(p, pr, "fp64", out=o, bound=bd, stream=s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms_binding = e0.elapsed_time(e1) / reps
+    # the C entry point with its arguments marshalled once: the launches
+    # queue faster than they run, so the events time the kernel
+    import ctypes
+    lib, ctx = native.lib(), native.default_context()
+    cp = native.SgProblem(p.d, p.q, native.RULES[p.rule], native.FAMILIES[p.family], 0)
+    args = (ctx.handle, ctypes.byref(cp), native.PRECISIONS["fp64"], ctypes.c_void_p(pr.data_ptr()),
+            ctypes.c_void_p(o.data_ptr()), ctypes.c_void_p(bd.data_ptr()), ctypes.c_void_p(s.cuda_stream))
+    torch.cuda.synchronize()
+    e0.record(s)
+    bad = sum(1 for _ in range(reps) if lib.sg_integrate(*args) != 0)
+    e1.record(s)
+    torch.cuda.synchronize()
+    assert bad == 0, "sg_integrate failed"
+    ms = e0.elapsed_time(e1) / reps
+    ref = float(bench_refs()["oscq_d1000"][0])
+    # the same rule tables as a real family of the same shape: its plan's counts
+    plan = native.Plan([W.Problem(p.d, p.q, p.rule, "oscillatory", 0)], "fp64")
+    info = plan.info()
+    plan.close()
+    slots = 2 * PAIR_EVAL_FLOPS * info["pair_evals"] + 4.0 * info["macs"] + 4.0 * K * K * p.d
+    ach = slots / (ms / 1e3) / 1e12
+    sc = max(abs(ref), 1.0)
+    res = {"d": p.d, "q": p.q, "rule": p.rule, "us_per_call": ms * 1e3, "us_per_call_python_binding": ms_binding * 1e3,
+           "points_per_s": float(info["effective_points"]) / (ms / 1e3),
+           "value": o.item(), "rel_err_vs_oracle": abs(o.item() - ref) / sc, "stated_bound_rel": bd.item() / sc,
+           "roofline": {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": ach / VALU_PEAK_TFLOPS, "flop_slots_per_launch": slots}}
+    log(f"  oscillatory quadratic d={p.d}: {ms * 1e3:.2f} us per call, err {res['rel_err_vs_oracle']:.2e}")
+    return res
+
+
 def points_leg(dev, s, reps: int = 5):
     """Time the literal point-by-point path on the d = 100, q = 105
     Clenshaw-Curtis workload (both families) and check it against the
@@ -388,6 +448,8 @@ def main():
                     help="only run the traffic-counter calibration copy of this many MiB")
     ap.add_argument("--blocked-only", action="store_true",
                     help="only run the block-variant leg (m = 10) and print its JSON")
+    ap.add_argument("--oscq-only", action="store_true",
+                    help="only the oscillatory-quadratic sweep leg (d = 1000)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only the reverse-sweep leg (oscillatory d = 200, 256 integrands)")
     ap.add_argument("--points-only", action="store_true",
@@ -407,6 +469,12 @@ def main():
     import torch
 
     from paper_2210_14313_amd import api, native, workloads as W
+
+    if args.oscq_only:
+        torch.cuda.set_device(0)
+        so = torch.cuda.Stream()
+        print(json.dumps({"oscillatory_quadratic_d1000": oscq_leg(torch.device("cuda:0"), so)}), flush=True)
+        return
 
     if args.adjoint_only:
         torch.cuda.set_device(0)
@@ -619,6 +687,8 @@ def main():
         extras["blocked_m10"] = blocked_leg(dev, s, batch, args.precision)
         # reverse sweep on the gradient workload (256 oscillatory, d = 200, q = 205)
         extras["adjoint_gradient_osc_d200_n256"] = adjoint_leg(dev, s)
+        # oscillatory quadratic on the complex sweep (one integrand, d = 1000)
+        extras["oscillatory_quadratic_d1000"] = oscq_leg(dev, s)
 
         # literal point-by-point path on the d = 100, q = 105 workload
         # (2.08e10 points per integrand) against the stored oracle values

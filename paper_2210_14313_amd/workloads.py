@@ -227,6 +227,13 @@ def gradient_osc_d200(n: int = 256, seed: int = SEED_BASE + 5, d: int = 200, K: 
     return b.build()
 
 
+def oscillatory_quadratic_d1000(seed: int = SEED_BASE + 10, d: int = 1000, K: int = 4, rule: str = "gp") -> Batch:
+    """One oscillatory-quadratic integrand cos(2 pi w + sum a_i (x_i - u_i)^2)
+    (the sines of (4.1)/(4.2) in d dimensions), q = d + K, standard draws."""
+    rng = np.random.default_rng(seed)
+    return single(d, d + K, rule, "oscillatory_quadratic", draw_params(rng, "oscillatory_quadratic", d))
+
+
 def random_small(seed: int, n: int, d_range=(1, 6), k_range=(0, 4),
                  rules: Sequence[str] = RULES, families: Sequence[str] = FAMILIES,
                  osc_scale: float = 9.0, exp_scale: float = 1.0) -> Batch:

@@ -15,7 +15,10 @@ that bench.py states its accuracy without running the oracle itself:
   prod 1/(0.9^2 + (x_i - 0.6)^2) on [-1,1]^300, mapped to the unit cube;
 * gradient_osc_d200_first64: binary128 factorised gradients of the first
   64 integrands of the 256-integrand oscillatory d = 200, q = 205
-  Clenshaw-Curtis batch (row i: dQ_i/dw, dQ_i/da_1..a_200).
+  Clenshaw-Curtis batch (row i: dQ_i/dw, dQ_i/da_1..a_200);
+* oscq_d1000: binary128 factorised value of the oscillatory quadratic
+  cos(2 pi w + sum a_i (x_i - u_i)^2), d = 1000, q = 1004, Gauss-Patterson
+  (workloads.oscillatory_quadratic_d1000).
 
 Run from the repository root:  python tests/golden/make_bench_refs.py
 """
@@ -64,7 +67,9 @@ def main():
     grads = np.stack([oracle.smolyak_factorised_grad(p.d, p.q, p.rule, p.family, gb.param_slice(i))
                       for i, p in enumerate(gb.problems[:GRAD_CHECK])])
     print("gradient_osc_d200_first64 done", flush=True)
-    np.savez(OUT, uneven_4096=uneven, blocked_m10_first256=blocked,
+    oscq = oracle.batch_factorised(W.oscillatory_quadratic_d1000())
+    print("oscq_d1000 done", flush=True)
+    np.savez(OUT, uneven_4096=uneven, blocked_m10_first256=blocked, oscq_d1000=oscq,
              table_4_9_names=np.array([t[0] for t in TABLE_4_9]),
              table_4_9_exact=np.array(t_exact), table_4_9_blocked=np.array(t_blk),
              gradient_osc_d200_first64=grads)

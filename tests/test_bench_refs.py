@@ -53,3 +53,7 @@ def test_gradient_rows(orc, refs):
         p = gb.problems[i]
         np.testing.assert_array_equal(orc.smolyak_factorised_grad(p.d, p.q, p.rule, p.family, gb.param_slice(i)),
                                       g[i])
+
+
+def test_oscillatory_quadratic_value(orc, refs):
+    np.testing.assert_array_equal(orc.batch_factorised(W.oscillatory_quadratic_d1000()), refs["oscq_d1000"])
