@@ -78,8 +78,10 @@ typedef enum {
  * their sines.  CORNER_PEAK is a ridge function that does not factor per
  * coordinate: the point-by-point path sg_integrate_points only.
  * OSCILLATORY_QUADRATIC factors with complex per-coordinate surpluses: the
- * point path, and sg_integrate in FP64 (a sweep with complex truncated
- * products); plans reject both with UNSUPPORTED.) */
+ * point path, sg_integrate in FP64, and plans, which compute it in FP64 in
+ * every precision mode (a sweep with complex truncated products, one
+ * workgroup per integrand beside the forward kernel); it has no reverse
+ * sweep and no block variant.  Plans reject CORNER_PEAK with UNSUPPORTED.) */
 typedef enum {
     SG_FAMILY_EXP_SUM = 0,
     SG_FAMILY_OSCILLATORY = 1,
@@ -230,8 +232,9 @@ sg_status sg_plan_execute(sg_plan *plan, const double *params_dev, double *out_d
 /* Gradient of every result with respect to every parameter (reverse sweep):
  * grad_params_dev[k] = grad_out_dev[i] * dQ_i/dparams[k] for the parameters
  * k of problem i, same layout as params.  Parameters not used by any problem
- * are left untouched.  Every family a plan takes has a reverse sweep.
- * Errors: INVALID_ARGUMENT, DEVICE, UNSUPPORTED (a block-variant plan). */
+ * are left untouched.
+ * Errors: INVALID_ARGUMENT, DEVICE, UNSUPPORTED (a block-variant plan, or a
+ * plan holding OSCILLATORY_QUADRATIC problems). */
 sg_status sg_plan_execute_grad(sg_plan *plan, const double *params_dev, const double *grad_out_dev,
                                double *grad_params_dev, void *stream);
 

@@ -13,15 +13,7 @@
 #include <vector>
 
 #include "sg_internal.hpp"
-
-namespace sg {
-// Oscillatory-quadratic sweep (sg_oscq.hip; complex truncated products,
-// FP64): one integrand of dimension d, excess K, rule; pool64: the (rule, K)
-// FP64 record table; params: w, a[d], u[d]; out, bound (NULL: none): one
-// double each.
-int launch_oscq(int d, int K, int rule, const double* pool64, const double* params, double* out, double* bound,
-                void* stream);
-}  // namespace sg
+#include "sg_oscq.hpp"
 
 using namespace sg;
 
@@ -121,6 +113,8 @@ struct sg_plan {
     size_t ws_elems = 0;
     int nwg = 0;
     size_t wg_capacity = 0;
+    OscqDesc* d_oscq = nullptr;     // oscillatory-quadratic integrands (complex sweep, FP64)
+    int noscq = 0;
     sg_plan_info info{};
     std::string tune_key;
     std::vector<GraphEntry> graphs;
@@ -704,7 +698,7 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
     if (precision != SG_PREC_FP64 && precision != SG_PREC_FP32_COMPENSATED && precision != SG_PREC_FP32_FP64_SUM)
         return fail(ctx, SG_ERR_INVALID_ARGUMENT, "unknown precision");
     for (int i = 0; i < n; ++i) {
-        sg_status st = validate_problem(ctx, problems[i], i);
+        sg_status st = validate_problem(ctx, problems[i], i, problems[i].family == SG_FAMILY_OSCILLATORY_QUADRATIC);
         if (st != SG_OK) return st;
     }
     std::unique_ptr<sg_plan> p(new sg_plan());
@@ -753,16 +747,34 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
         info.macs = sat_add(info.macs, sat_mul(d, macs));
         info.merge_flops = sat_add(info.merge_flops, sat_mul(d, K * K));
         maxd = std::max(maxd, problems[i].d);
+        if (problems[i].family == SG_FAMILY_OSCILLATORY_QUADRATIC) continue;   // its own kernel
         p->kmax = std::max(p->kmax, (int)K);
         if (problems[i].family == SG_FAMILY_GAUSSIAN) has_gauss = true;
     }
     if (has_gauss) p->kmax = kKmaxGauss;   // the forward kernels built with the gaussian family
-    std::vector<int> order(n);
-    for (int i = 0; i < n; ++i) order[i] = i;
+    // the sweep kernels' problems in longest-first order; the oscillatory
+    // quadratic (complex surpluses) to its own kernel, one workgroup each
+    std::vector<int> order;
+    std::vector<OscqDesc> oscq;
+    for (int i = 0; i < n; ++i) {
+        if (problems[i].family != SG_FAMILY_OSCILLATORY_QUADRATIC) {
+            order.push_back(i);
+            continue;
+        }
+        OscqDesc q;
+        q.off64 = toff[std::make_pair(problems[i].rule, problems[i].q - problems[i].d)].first;
+        q.param_offset = problems[i].param_offset;
+        q.d = problems[i].d;
+        q.K = problems[i].q - problems[i].d;
+        q.rule = problems[i].rule;
+        q.out_index = i;
+        oscq.push_back(q);
+    }
+    const int nr = (int)order.size();
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-    p->probs.resize(n);
-    p->unit_cost.resize(n);
-    for (int k = 0; k < n; ++k) {
+    p->probs.resize(nr);
+    p->unit_cost.resize(nr);
+    for (int k = 0; k < nr; ++k) {
         const int i = order[k];
         p->unit_cost[k] = cost[i] / (double)problems[i].d;
         p->cmax = std::max(p->cmax, p->unit_cost[k]);
@@ -785,9 +797,11 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
         // parameter ranges must be disjoint for the reverse sweep to write them
         std::vector<std::pair<int64_t, int64_t>> rg(n);
         for (int i = 0; i < n; ++i) {
-            const int64_t len = problems[i].family == SG_FAMILY_EXP_SUM ? problems[i].d
-                                : problems[i].family == SG_FAMILY_OSCILLATORY ? (int64_t)problems[i].d + 1
-                                                                              : 2 * (int64_t)problems[i].d;
+            const int f = problems[i].family;
+            const int64_t d = problems[i].d;
+            const int64_t len = f == SG_FAMILY_EXP_SUM ? d
+                                : f == SG_FAMILY_OSCILLATORY ? d + 1
+                                : f == SG_FAMILY_OSCILLATORY_QUADRATIC ? 2 * d + 1 : 2 * d;
             rg[i] = std::make_pair(problems[i].param_offset, problems[i].param_offset + len);
         }
         std::sort(rg.begin(), rg.end());
@@ -814,10 +828,10 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
         }
     }
     // reverse sweep: one problem per wave slot, cost-threshold schedule
-    std::vector<int> wv(n);
-    for (int k = 0; k < n; ++k) wv[k] = waves_for(p->probs[k].d, p->unit_cost[k], p->wmax, p->cmax);
+    std::vector<int> wv(nr);
+    for (int k = 0; k < nr; ++k) wv[k] = waves_for(p->probs[k].d, p->unit_cost[k], p->wmax, p->cmax);
     std::vector<WGDesc> wgs = pack_workgroups(p->probs, wv);
-    for (int k = 0; k < n; ++k) p->probs[k].waves = wv[k];
+    for (int k = 0; k < nr; ++k) p->probs[k].waves = wv[k];
     p->nwg = (int)wgs.size();
     info.block_threads = 256;
     info.graph = p->use_graph ? 1 : 0;
@@ -835,6 +849,10 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
     if ((st = plan_repack(p.get(), p->sched)) != SG_OK) return st;
     if ((st = upload(ctx, &p->d_pool64, p64.data(), p64.size())) != SG_OK) return st;
     if ((st = upload(ctx, &p->d_pool32, p32.data(), p32.size())) != SG_OK) return st;
+    if (!oscq.empty()) {
+        if ((st = upload(ctx, &p->d_oscq, oscq.data(), oscq.size())) != SG_OK) return st;
+        p->noscq = (int)oscq.size();
+    }
     ctx->live_plans++;
     *plan = p.release();
     return SG_OK;
@@ -845,6 +863,10 @@ static sg_status plan_launch(sg_plan* p, const double* params, double* out, doub
     const int rc = launch_forward(p->precision, p->kmax, p->nfwg, p->d_fwd, p->sched.persistent ? p->d_queue : nullptr,
                                   p->qgrid, p->d_pool64, p->d_pool32, params, out, bound, stream);
     if (rc != 0) return hip_fail(p->ctx, (hipError_t)rc, "forward launch");
+    if (p->noscq) {
+        const int rq = launch_oscq_batch(p->noscq, p->d_oscq, p->d_pool64, params, out, bound, stream);
+        if (rq != 0) return hip_fail(p->ctx, (hipError_t)rq, "oscillatory-quadratic launch");
+    }
     return SG_OK;
 }
 
@@ -961,6 +983,8 @@ sg_status sg_plan_create_blocked(sg_context* ctx, const sg_problem* problems, in
     if (!problems || n < 1) return fail(ctx, SG_ERR_INVALID_ARGUMENT, "empty problem list");
     if (block_dims < 1) return fail(ctx, SG_ERR_INVALID_ARGUMENT, "block_dims must be >= 1");
     for (int i = 0; i < n; ++i) {
+        if (problems[i].family == SG_FAMILY_OSCILLATORY_QUADRATIC)
+            return fail(ctx, SG_ERR_UNSUPPORTED, "the block variant does not take the oscillatory quadratic");
         sg_status st = validate_problem(ctx, problems[i], i);
         if (st != SG_OK) return st;
     }
@@ -1048,6 +1072,7 @@ sg_status sg_plan_execute_grad(sg_plan* p, const double* params_dev, const doubl
     if (!params_dev || !grad_out_dev || !grad_params_dev)
         return fail(p->ctx, SG_ERR_INVALID_ARGUMENT, "NULL params, grad_out or grad_params");
     if (p->blocked) return fail(p->ctx, SG_ERR_UNSUPPORTED, "the block variant has no reverse sweep");
+    if (p->noscq) return fail(p->ctx, SG_ERR_UNSUPPORTED, "the oscillatory quadratic has no reverse sweep");
     if (!p->params_disjoint)
         return fail(p->ctx, SG_ERR_INVALID_ARGUMENT,
                     "problems share parameters: the reverse sweep needs disjoint parameter ranges");
@@ -1213,6 +1238,7 @@ sg_status sg_plan_destroy(sg_plan* p)
         p->blocked = nullptr;
     }
     destroy_graphs(p);
+    hipFree(p->d_oscq);
     hipFree(p->d_probs);
     hipFree(p->d_wgs);
     hipFree(p->d_fwd);

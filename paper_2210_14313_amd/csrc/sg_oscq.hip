@@ -11,11 +11,13 @@
 // Q = Re(e^{i (2 pi w + sum_t a_t (1/2 - u_t)^2)} sum_{b <= K} [z^b] prod_t D_t(z)),
 // D_t(z) = 1 + sum_e delta_t[e] z^e, with complex truncated products.
 //
-// One workgroup of 256 threads per integrand: each thread sweeps the
+// One workgroup of 256 threads per integrand (a plan launches one per
+// oscillatory-quadratic integrand): each thread sweeps the
 // coordinates t = tid, tid + 256, ..., a wave combines its lanes by an
 // xor butterfly of complex truncated products, and the first thread joins
 // the four waves in wave order and reads out the value and its bound.
 #include "sg_device.hpp"
+#include "sg_oscq.hpp"
 
 namespace sg {
 namespace dev {
@@ -185,19 +187,36 @@ __device__ void oscq_body(int d, const double* __restrict__ r64, const double* _
     }
 }
 
+__device__ __forceinline__ void oscq_dispatch(int d, int K, int rule, const double* r64, const double* prm,
+                                              double* out, double* bound, double* lds)
+{
+    const int rc = rule_class_of(rule);
+    switch_k<MAXK>(K, [&](auto kc) {
+        constexpr int KK = decltype(kc)::value;
+        if (rc == RC_NESTED) oscq_body<KK, RC_NESTED>(d, r64, prm, out, bound, lds);
+        else if (rc == RC_GL2) oscq_body<KK, RC_GL2>(d, r64, prm, out, bound, lds);
+        else if (rc == RC_GP) oscq_body<KK, RC_GP>(d, r64, prm, out, bound, lds);
+        else oscq_body<KK, RC_GLP>(d, r64, prm, out, bound, lds);
+    });
+}
+
 __global__ void __launch_bounds__(256)
 k_oscq(int d, int K, int rule, const double* __restrict__ pool64, const double* __restrict__ params,
        double* __restrict__ out, double* __restrict__ bound)
 {
     __shared__ double lds[4 * OSCQ_WORDS];
-    const int rc = rule_class_of(rule);
-    switch_k<MAXK>(K, [&](auto kc) {
-        constexpr int KK = decltype(kc)::value;
-        if (rc == RC_NESTED) oscq_body<KK, RC_NESTED>(d, pool64, params, out, bound, lds);
-        else if (rc == RC_GL2) oscq_body<KK, RC_GL2>(d, pool64, params, out, bound, lds);
-        else if (rc == RC_GP) oscq_body<KK, RC_GP>(d, pool64, params, out, bound, lds);
-        else oscq_body<KK, RC_GLP>(d, pool64, params, out, bound, lds);
-    });
+    oscq_dispatch(d, K, rule, pool64, params, out, bound, lds);
+}
+
+// Workgroup b runs descriptor b.
+__global__ void __launch_bounds__(256)
+k_oscq_batch(const OscqDesc* __restrict__ descs, const double* __restrict__ pool64,
+             const double* __restrict__ params, double* __restrict__ out, double* __restrict__ bound)
+{
+    __shared__ double lds[4 * OSCQ_WORDS];
+    const OscqDesc q = descs[blockIdx.x];
+    oscq_dispatch(q.d, q.K, q.rule, pool64 + q.off64, params + q.param_offset, out + q.out_index,
+                  bound ? bound + q.out_index : nullptr, lds);
 }
 
 }  // namespace dev
@@ -207,6 +226,15 @@ int launch_oscq(int d, int K, int rule, const double* pool64, const double* para
 {
     hipLaunchKernelGGL(dev::k_oscq, dim3(1), dim3(256), 0, (hipStream_t)stream, d, K, rule, pool64, params, out,
                        bound);
+    return (int)hipGetLastError();
+}
+
+int launch_oscq_batch(int n, const OscqDesc* descs, const double* pool64, const double* params, double* out,
+                      double* bound, void* stream)
+{
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(dev::k_oscq_batch, dim3((unsigned)n), dim3(256), 0, (hipStream_t)stream, descs, pool64,
+                       params, out, bound);
     return (int)hipGetLastError();
 }
 

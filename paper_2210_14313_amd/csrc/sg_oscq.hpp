@@ -1,0 +1,26 @@
+// Oscillatory-quadratic sweep (complex surpluses and truncated products,
+// FP64): descriptors and launchers shared by the kernel file and the API.
+#pragma once
+
+#include <cstdint>
+
+namespace sg {
+
+// One oscillatory-quadratic integrand of a plan.
+struct OscqDesc {
+    int64_t off64;          // its (rule, K) record table in the plan's FP64 pool
+    int64_t param_offset;   // its parameters w, a[d], u[d] in the caller's array
+    int32_t d, K, rule;
+    int32_t out_index;      // its slot in out / bound
+};
+
+// One integrand (the plan-free path): pool64 holds the (rule, K) record
+// table; out and bound (NULL: none) one double each.
+int launch_oscq(int d, int K, int rule, const double* pool64, const double* params, double* out, double* bound,
+                void* stream);
+// n integrands of a plan, one workgroup each; out and bound (NULL: none)
+// indexed by out_index.
+int launch_oscq_batch(int n, const OscqDesc* descs, const double* pool64, const double* params, double* out,
+                      double* bound, void* stream);
+
+}  // namespace sg

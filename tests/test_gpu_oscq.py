@@ -1,9 +1,11 @@
 """GPU parity of the oscillatory-quadratic sweep cos(2 pi w + sum a_i (x_i - u_i)^2)
-(sg_integrate in FP64: the factorised sum with complex surpluses and
-complex truncated products) against the oracle's point-by-point sum (small
-d) and its binary128 factorised sum (any d), with the stated bound; the
-sine of Test 1 ((4.1), on [-1,1]^2 mapped to the unit cube); rejection of
-the FP32 modes and of plans.
+(the factorised sum with complex surpluses and complex truncated products,
+FP64: sg_integrate, and plans, which give each such integrand a workgroup of
+the complex kernel beside the forward sweep of the others) against the
+oracle's point-by-point sum (small d) and its binary128 factorised sum (any
+d), with the stated bound; the sine of Test 1 ((4.1), on [-1,1]^2 mapped to
+the unit cube); rejection of the one-shot FP32 modes, of the block variant
+and of the reverse sweep.
 
 Tolerance: within the stated bound, and within 1e-12 of max(|Q|, 1) (the
 scale the oscillatory family is held to).
@@ -101,3 +103,68 @@ def test_oscq_deterministic_and_fp32_rejected(torch_dev):
         with pytest.raises(native.SgError) as e:
             _one(b.problems[0], prm, prec)
         assert e.value.status == 2
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c", "fp32e"])
+def test_oscq_in_mixed_plans(torch_dev, orc, precision):
+    # plans compute the family in FP64 whatever their precision mode
+    from paper_2210_14313_amd import api, workloads as W
+    b = W.concat([W.random_small(950, 30, d_range=(1, 300), k_range=(0, 6), families=(FAM,), rules=W.ALL_RULES),
+                  W.random_small(951, 40, d_range=(1, 120), k_range=(0, 6)),
+                  W.random_small(952, 10, d_range=(1, 60), k_range=(0, 5), families=("gaussian",))])
+    say("case oscq mixed plan", precision)
+    ref = orc.batch_factorised(b)
+    vals, bnd = api.integrate(b, precision, with_bound=True)
+    got, bnd = vals.cpu().numpy(), bnd.cpu().numpy()
+    assert np.all(np.abs(got - ref) <= bnd), np.max(np.abs(got - ref) / bnd)
+    fam = np.array([p.family for p in b.problems])
+    sel = fam == FAM
+    assert np.max(np.abs(got[sel] - ref[sel]) / np.maximum(np.abs(ref[sel]), 1.0)) <= 1e-12
+    for i in np.flatnonzero(sel)[:5]:                      # the same value as the one-shot path
+        one = b.subset([int(i)])
+        v, _ = _one(one.problems[0], one.param_slice(0))
+        assert v == got[i]
+
+
+def test_oscq_only_plan_autotuned_on_a_stream(torch_dev, orc):
+    import torch
+    from paper_2210_14313_amd import api, native, workloads as W
+    b = W.concat([W.random_small(960, 12, d_range=(200, 1000), k_range=(1, 5), families=(FAM,)),
+                  W.oscillatory_quadratic_d1000()])
+    say("case oscq-only plan")
+    ref = orc.batch_factorised(b)
+    params = api.params_tensor(b)
+    plan = native.Plan(b.problems, "fp64")
+    s = torch.cuda.Stream()
+    try:
+        out = torch.empty(len(b), dtype=torch.float64, device="cuda")
+        bound = torch.empty_like(out)
+        plan.autotune(params, out, stream=s)
+        runs = []
+        for _ in range(3):
+            plan.execute(params, out, bound, stream=s)
+            s.synchronize()
+            runs.append(out.cpu().numpy().copy())
+        bnd = bound.cpu().numpy()
+    finally:
+        plan.close()
+    for r in runs[1:]:
+        assert np.array_equal(r, runs[0])
+    assert np.all(np.abs(runs[0] - ref) <= bnd)
+    assert np.max(np.abs(runs[0] - ref) / np.maximum(np.abs(ref), 1.0)) <= 1e-12
+
+
+def test_oscq_rejected_by_the_block_variant_and_the_reverse_sweep(torch_dev):
+    import torch
+    from paper_2210_14313_amd import api, native, workloads as W
+    b = W.single(20, 24, "cc", FAM, W.draw_params(np.random.default_rng(3), FAM, 20))
+    with pytest.raises(native.SgError) as e:
+        native.Plan(b.problems, "fp64", block_dims=5)
+    assert e.value.status == 2
+    plan = native.Plan(b.problems, "fp64")
+    try:
+        with pytest.raises(native.SgError) as e:
+            plan.execute_grad(api.params_tensor(b), torch.ones(1, dtype=torch.float64, device="cuda"))
+        assert e.value.status == 2
+    finally:
+        plan.close()

@@ -205,7 +205,7 @@ def test_points_paper_table_4_1_first_row(torch_dev):
     assert abs(rel - row["rel_err"]) <= 1.01e-5 * 10 ** np.floor(np.log10(row["rel_err"])) * 10, rel
 
 
-@pytest.mark.parametrize("family", ["oscillatory_quadratic", "corner_peak"])
+@pytest.mark.parametrize("family", ["corner_peak"])
 def test_point_families_rejected_by_plans(torch_dev, family):
     from paper_2210_14313_amd import native, workloads as W
     b = W.single(4, 6, "cc", family, W.draw_params(np.random.default_rng(1), family, 4))
