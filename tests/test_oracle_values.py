@@ -172,6 +172,22 @@ def test_points_match_factorised(orc, case):
     assert abs(pt["q"] - fq) <= tol, (pt, fq, tol)
 
 
+def _quadratic_cases(seed, n):
+    b = W.random_small(seed, n, (1, 8), (0, 6), families=("gaussian", "oscillatory_quadratic"), rules=W.ALL_RULES)
+    return [(p.d, p.q, p.rule, p.family, b.param_slice(i)) for i, p in enumerate(b.problems)]
+
+
+@pytest.mark.parametrize("case", _quadratic_cases(8, 24))
+def test_points_match_factorised_quadratic_families(orc, case):
+    # the factorisation of (2.6) with the quadratic families' factors (the
+    # oscillatory quadratic's complex) against the literal point sum
+    d, q, rule, family, params = case
+    pt = orc.smolyak_points(d, q, rule, family, params)
+    fq = orc.smolyak_factorised(d, q, rule, family, params)
+    tol = 8 * U64 * (pt["A"] + abs(pt["fc"])) + 4e-16 * max(abs(fq), 1.0)
+    assert abs(pt["q"] - fq) <= tol, (pt, fq, tol)
+
+
 @pytest.mark.parametrize("d,K,rule,family", [(30, 3, "cc", "exp_sum"), (25, 3, "gl", "oscillatory"),
                                              (40, 2, "tr", "product_peak"), (12, 5, "cc", "oscillatory")])
 def test_points_match_factorised_medium(orc, d, K, rule, family):
