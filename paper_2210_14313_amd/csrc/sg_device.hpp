@@ -1154,6 +1154,34 @@ __device__ __forceinline__ void dpair_gauss64(double c, double b, double y, doub
     ds_du = -4.0 * c * y * e * sh;
 }
 
+// sum_e G[e] dS[e] and sum_e G[e] dT[e] for the two derivative surpluses dS,
+// dT of one coordinate without forming them: each pair's weights are
+// contracted with G first, then multiplied by its two derivative values
+// (one evaluation per pair, and no surplus arrays held in registers).
+template <int K, int RC, class PF>
+__device__ __forceinline__ void contract_pairs2(const double* __restrict__ r64, const double (&G)[MAXK + 1],
+                                                PF&& pf, double& sa, double& sb)
+{
+    sa = 0.0;
+    sb = 0.0;
+    static_for<2, K + 2>([&](auto Lc) {
+        constexpr int L = decltype(Lc)::value;
+        constexpr int np = rc_pairs(RC, L), lo = rc_elo(L), hi = rc_ehi(RC, K, L);
+        constexpr int rl = rc_rec64(RC, K, L), off = rc_off64(RC, K, L);
+#pragma unroll 2
+        for (int j = 0; j < np; ++j) {
+            const double* r = r64 + off + j * rl;
+            double wg = 0.0;
+#pragma unroll
+            for (int e = lo; e <= hi; ++e) wg = fma(G[e], r[1 + e - lo], wg);
+            double a, b;
+            pf(r[0], a, b);
+            sa = fma(wg, a, sa);
+            sb = fma(wg, b, sb);
+        }
+    });
+}
+
 // Inclusive scans of monic truncated polynomials across the 64 lanes.
 template <int K>
 __device__ __forceinline__ void shfl_poly_up(double (&o)[MAXK + 1], const double (&x)[MAXK + 1], int off)
@@ -1329,14 +1357,9 @@ __device__ __forceinline__ void wave_adjoint(const ProbDev& P, int rank, int gro
         coord_param(t, cp);
         if constexpr (FAM == FAM_GAUSS) {
             const double c = prm[t], hv = 0.5 - prm[d + t], b = 2.0 * hv;
-            double dc[MAXK + 1], du[MAXK + 1], eps = 0.0;
-            surplus64g<K, RC>(r64 + opaque, [&](double y) { double a, e; dpair_gauss64(c, b, y, a, e); return a; },
-                              false, dc, eps);
-            surplus64g<K, RC>(r64 + opaque, [&](double y) { double a, e; dpair_gauss64(c, b, y, a, e); return e; },
-                              false, du, eps);
-            double dsc = 0.0, dsu = 0.0;
-#pragma unroll
-            for (int e = 1; e <= K; ++e) { dsc = fma(G[e], dc[e], dsc); dsu = fma(G[e], du[e], dsu); }
+            double dsc, dsu;
+            contract_pairs2<K, RC>(r64 + opaque, G,
+                                   [&](double y, double& a, double& e) { dpair_gauss64(c, b, y, a, e); }, dsc, dsu);
             // Q = A s, A = prod exp(c_t hv_t^2): dA/dc_t = hv_t^2 A, dA/du_t = -2 c_t hv_t A
             grad[P.param_offset + t] = g * A * fma(s, hv * hv, dsc);
             grad[P.param_offset + d + t] = g * A * fma(s, -2.0 * c * hv, dsu);
