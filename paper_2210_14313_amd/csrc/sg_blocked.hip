@@ -21,26 +21,33 @@
 namespace sg {
 namespace blk {
 
-// One thread per block: copies the block's parameters.
+// kGatherLanes lanes per block: lane j copies the block's coordinates j,
+// j + kGatherLanes, ..., so each block's parameters move as contiguous runs
+// (one thread per block made every lane of a wave walk its own strided
+// run).
+constexpr int kGatherLanes = 16;
+
 __global__ void __launch_bounds__(256) k_block_gather(const BlockSub* __restrict__ subs, int nsub,
                                                       const double* __restrict__ params,
                                                       double* __restrict__ sub_params)
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t s = g / kGatherLanes;
+    const int j0 = (int)(g % kGatherLanes);
     if (s >= nsub) return;
     const BlockSub b = subs[s];
     const double* src = params + b.src_off;
     double* dst = sub_params + b.dst_off;
     if (b.family == SG_FAMILY_OSCILLATORY) {
-        dst[0] = b.part == 2 ? -0.25 : 0.0;
-        for (int j = 0; j < b.len; ++j) dst[1 + j] = src[1 + b.start + j];
+        if (j0 == 0) dst[0] = b.part == 2 ? -0.25 : 0.0;
+        for (int j = j0; j < b.len; j += kGatherLanes) dst[1 + j] = src[1 + b.start + j];
     } else if (b.family == SG_FAMILY_PRODUCT_PEAK || b.family == SG_FAMILY_GAUSSIAN) {
-        for (int j = 0; j < b.len; ++j) {
+        for (int j = j0; j < b.len; j += kGatherLanes) {
             dst[j] = src[b.start + j];
             dst[b.len + j] = src[b.d + b.start + j];
         }
     } else {
-        for (int j = 0; j < b.len; ++j) dst[j] = src[b.start + j];
+        for (int j = j0; j < b.len; j += kGatherLanes) dst[j] = src[b.start + j];
     }
 }
 
@@ -147,8 +154,9 @@ __global__ void __launch_bounds__(256) k_block_combine(const BlockProb* __restri
 int launch_block_gather(const BlockSub* subs, int nsub, const double* params, double* sub_params, void* stream)
 {
     if (nsub <= 0) return 0;
-    hipLaunchKernelGGL(blk::k_block_gather, dim3((unsigned)((nsub + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
-                       subs, nsub, params, sub_params);
+    const int64_t threads = (int64_t)nsub * blk::kGatherLanes;
+    hipLaunchKernelGGL(blk::k_block_gather, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)stream, subs, nsub, params, sub_params);
     return (int)hipGetLastError();
 }
 
