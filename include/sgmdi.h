@@ -187,8 +187,10 @@ sg_status sg_unrank_device(sg_context *ctx, int32_t d, int32_t q, uint64_t rank0
  * validates every problem, builds (or reuses) the rule tables, orders the
  * work longest-first, picks tile/schedule parameters (from the context's
  * autotune results when present) and uploads the plan to the device.
+ * OSCILLATORY_QUADRATIC problems run in FP64 on the complex sweep, one
+ * workgroup each, launched after the forward kernel on the same stream.
  * Errors: INVALID_ARGUMENT (n < 1, NULL, a bad problem), UNSUPPORTED
- * (K > SG_MAX_K), OUT_OF_MEMORY, DEVICE. */
+ * (K > SG_MAX_K, a CORNER_PEAK problem), OUT_OF_MEMORY, DEVICE. */
 sg_status sg_plan_create(sg_context *ctx, const sg_problem *problems, int32_t n,
                          int32_t precision, sg_plan **plan);
 
