@@ -80,8 +80,9 @@ typedef enum {
  * OSCILLATORY_QUADRATIC factors with complex per-coordinate surpluses: the
  * point path, sg_integrate in FP64, and plans, which compute it in FP64 in
  * every precision mode (a sweep with complex truncated products, one
- * workgroup per integrand beside the forward kernel); it has no reverse
- * sweep and no block variant.  Plans reject CORNER_PEAK with UNSUPPORTED.) */
+ * workgroup per integrand beside the forward kernel), block variant
+ * included; it has no reverse sweep.  Plans reject CORNER_PEAK with
+ * UNSUPPORTED.) */
 typedef enum {
     SG_FAMILY_EXP_SUM = 0,
     SG_FAMILY_OSCILLATORY = 1,

@@ -21,7 +21,8 @@ gaussian and monomial directly; oscillatory through
 cos(2 pi w + sum_t a_t x_t) = Re(e^{2 pi i w} prod_b e^{i sum_{t in b} a_t x_t}),
 where the block value C_b = A_b(cos theta_b) + i A_b(sin theta_b) and
 A_b(sin theta_b) = A_b(cos(theta_b - pi/2)) is the oscillatory block with
-w = -1/4.  Each block value comes from the oracle's plain Smolyak sum
+w = -1/4; the oscillatory quadratic the same way, with
+theta_b = sum_{t in b} a_t (x_t - u_t)^2.  Each block value comes from the oracle's plain Smolyak sum
 (point by point, or factorised in binary128), and the product is formed in
 mpmath at 40 digits.
 """
@@ -52,6 +53,9 @@ def block_params(family: str, params, d: int, start: int, length: int, w_overrid
         return np.concatenate([p[:d][sl], p[d:2 * d][sl]])
     if family == "monomial":
         return np.concatenate([p[:d][sl], [p[d]]])
+    if family == "oscillatory_quadratic":
+        w = p[0] if w_override is None else w_override
+        return np.concatenate([[w], p[1:1 + d][sl], p[1 + d:1 + 2 * d][sl]])
     raise ValueError(family)
 
 
@@ -71,7 +75,7 @@ def smolyak_blocked(d: int, q: int, rule: str, family: str, params, m: int, meth
         return smolyak_factorised(db, db + K, rule, family, bp)
 
     with mp.workdps(40):
-        if family == "oscillatory":
+        if family in ("oscillatory", "oscillatory_quadratic"):
             z = mp.mpc(1)
             for s, ln in blocks(d, m):
                 re = block_value(ln, block_params(family, params, d, s, ln, 0.0))

@@ -983,13 +983,13 @@ sg_status sg_plan_create_blocked(sg_context* ctx, const sg_problem* problems, in
     if (!problems || n < 1) return fail(ctx, SG_ERR_INVALID_ARGUMENT, "empty problem list");
     if (block_dims < 1) return fail(ctx, SG_ERR_INVALID_ARGUMENT, "block_dims must be >= 1");
     for (int i = 0; i < n; ++i) {
-        if (problems[i].family == SG_FAMILY_OSCILLATORY_QUADRATIC)
-            return fail(ctx, SG_ERR_UNSUPPORTED, "the block variant does not take the oscillatory quadratic");
-        sg_status st = validate_problem(ctx, problems[i], i);
+        sg_status st = validate_problem(ctx, problems[i], i,
+                                        problems[i].family == SG_FAMILY_OSCILLATORY_QUADRATIC);
         if (st != SG_OK) return st;
     }
     // block sub-problems in integrand order, blocks in coordinate order
-    // (oscillatory: real part, then imaginary part); their parameters are
+    // (oscillatory and oscillatory quadratic: real part, then imaginary
+    // part); their parameters are
     // laid out contiguously in the plan's block array
     std::vector<sg_problem> sub;
     std::vector<BlockSub> gs;
@@ -1000,7 +1000,7 @@ sg_status sg_plan_create_blocked(sg_context* ctx, const sg_problem* problems, in
         const sg_problem& P = problems[i];
         const int K = P.q - P.d;
         const int nb = (P.d + block_dims - 1) / block_dims;
-        const bool osc = P.family == SG_FAMILY_OSCILLATORY;
+        const bool osc = P.family == SG_FAMILY_OSCILLATORY || P.family == SG_FAMILY_OSCILLATORY_QUADRATIC;
         if (sub.size() + (size_t)nb * (osc ? 2 : 1) > (size_t)INT32_MAX)
             return fail(ctx, SG_ERR_UNSUPPORTED, "too many blocks");
         bp[i].param_offset = P.param_offset;
@@ -1025,9 +1025,10 @@ sg_status sg_plan_create_blocked(sg_context* ctx, const sg_problem* problems, in
                 g.part = part;
                 gs.push_back(g);
                 sub.push_back(sg_problem{len, len + K, P.rule, P.family, off});
-                off += osc ? 1 + len
-                           : (P.family == SG_FAMILY_PRODUCT_PEAK || P.family == SG_FAMILY_GAUSSIAN) ? 2 * (int64_t)len
-                                                                                                    : len;
+                off += P.family == SG_FAMILY_OSCILLATORY ? 1 + (int64_t)len
+                       : P.family == SG_FAMILY_OSCILLATORY_QUADRATIC ? 1 + 2 * (int64_t)len
+                       : (P.family == SG_FAMILY_PRODUCT_PEAK || P.family == SG_FAMILY_GAUSSIAN) ? 2 * (int64_t)len
+                                                                                                : len;
             }
         }
         eff = sat_add(eff, pts);

@@ -7,9 +7,9 @@
 // value is the product of the block values, each block being an ordinary
 // batched problem of the forward sweep:
 //   exp-sum, product-peak, gaussian: Q = prod_b Q_b;
-//   oscillatory: Q = Re(e^{2 pi i w} prod_b (R_b + i I_b)), with R_b the
-//   block's oscillatory value at w = 0 and I_b the one at w = -1/4
-//   (cos(theta - pi/2) = sin theta).
+//   oscillatory and oscillatory quadratic: Q = Re(e^{2 pi i w} prod_b
+//   (R_b + i I_b)), with R_b the block's value at w = 0 and I_b the one at
+//   w = -1/4 (cos(theta - pi/2) = sin theta).
 // Two kernels surround the forward launch over the blocks: a gather that
 // lays out the blocks' parameters, and a combine that forms the products in
 // a fixed order and propagates the blocks' error bounds.
@@ -41,6 +41,12 @@ __global__ void __launch_bounds__(256) k_block_gather(const BlockSub* __restrict
     if (b.family == SG_FAMILY_OSCILLATORY) {
         if (j0 == 0) dst[0] = b.part == 2 ? -0.25 : 0.0;
         for (int j = j0; j < b.len; j += kGatherLanes) dst[1 + j] = src[1 + b.start + j];
+    } else if (b.family == SG_FAMILY_OSCILLATORY_QUADRATIC) {
+        if (j0 == 0) dst[0] = b.part == 2 ? -0.25 : 0.0;
+        for (int j = j0; j < b.len; j += kGatherLanes) {
+            dst[1 + j] = src[1 + b.start + j];
+            dst[1 + b.len + j] = src[1 + b.d + b.start + j];
+        }
     } else if (b.family == SG_FAMILY_PRODUCT_PEAK || b.family == SG_FAMILY_GAUSSIAN) {
         for (int j = j0; j < b.len; j += kGatherLanes) {
             dst[j] = src[b.start + j];
@@ -106,7 +112,7 @@ __global__ void __launch_bounds__(256) k_block_combine(const BlockProb* __restri
     const int lane = threadIdx.x & 63;
     if (i >= n) return;
     const BlockProb p = probs[i];
-    const bool osc = p.family == SG_FAMILY_OSCILLATORY;
+    const bool osc = p.family == SG_FAMILY_OSCILLATORY || p.family == SG_FAMILY_OSCILLATORY_QUADRATIC;
     const double u = 1.1102230246251565e-16;
     Part acc{1.0, 0.0, 1.0, 0.0};
     for (int base = 0; base < p.nblocks; base += 64) {
