@@ -185,3 +185,62 @@ def test_oscq_rejected_by_the_reverse_sweep(torch_dev):
         assert e.value.status == 2
     finally:
         plan.close()
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_oscq_plan_graph_replays(torch_dev, orc, persistent):
+    # a plan holding the family, its launches captured into a graph (on a
+    # non-default stream) and replayed with eager work and host
+    # synchronisation between the replays; every replay equals the eager
+    # (direct-launch) result bitwise
+    import torch
+    from paper_2210_14313_amd import api, native, workloads as W
+    b = W.concat([W.random_small(980, 10, d_range=(1, 400), k_range=(0, 6), families=(FAM,)),
+                  W.random_small(981, 30, d_range=(1, 200), k_range=(0, 6))])
+    say("case oscq graph replays", persistent)
+    params = api.params_tensor(b)
+    ref = orc.batch_factorised(b)
+    plan = native.Plan(b.problems, "fp64")
+    try:
+        plan.set_schedule(2, 4, graph=True, persistent=persistent)
+        eager = plan.execute(params).clone()           # default stream: direct launches
+        assert np.max(np.abs(eager.cpu().numpy() - ref) / np.maximum(np.abs(ref), 1.0)) <= 1e-12
+        s = torch.cuda.Stream()
+        out = torch.empty(len(b), dtype=torch.float64, device="cuda")
+        for _ in range(4):                             # capture, then replays
+            out.fill_(float("nan"))
+            torch.cuda.synchronize()
+            s.wait_stream(torch.cuda.current_stream())
+            plan.execute(params, out, stream=s)
+            s.synchronize()
+            assert torch.equal(out, eager)
+            torch.cuda.synchronize()
+    finally:
+        plan.close()
+
+
+def test_oscq_degenerate_and_large_coefficients(torch_dev, orc):
+    # K = 0 (the midpoint rule: cos(2 pi w + sum a (1/2 - u)^2)), d = 1, and
+    # quadratic coefficients a ~ 1e3 (arguments of the sines in the
+    # hundreds): one-shot and in a plan, within the bound
+    from paper_2210_14313_amd import api, workloads as W
+    rng = np.random.default_rng(77)
+    cases = []
+    for d, K, scale in [(1, 0, 1.0), (5, 0, 1.0), (1, 8, 1.0), (1, 8, 300.0), (2, 6, 1000.0), (7, 3, 200.0)]:
+        prm = W.draw_params(rng, FAM, d)
+        prm[1:1 + d] *= scale
+        cases.append(W.single(d, d + K, "cc" if K % 2 else "gl", FAM, prm))
+    b = W.concat(cases)
+    say("case oscq degenerate / large")
+    ref = orc.batch_factorised(b)
+    for i, p in enumerate(b.problems):
+        pt = orc.smolyak_points(p.d, p.q, p.rule, p.family, b.param_slice(i))
+        assert abs(pt["q"] - ref[i]) <= 1e-12 * max(abs(ref[i]), 1.0) + 8 * 2.0 ** -64 * (pt["A"] + abs(pt["fc"]))
+        v, bd = _one(p, b.param_slice(i))
+        assert abs(v - ref[i]) <= bd, (i, v, ref[i], bd)
+        if p.q == p.d:
+            w, a, u = b.param_slice(i)[0], b.param_slice(i)[1:1 + p.d], b.param_slice(i)[1 + p.d:]
+            assert abs(v - np.cos(2 * np.pi * w + np.sum(a * (0.5 - u) ** 2))) <= 1e-14
+    vals, bnd = api.integrate(b, "fp64", with_bound=True)
+    got, bnd = vals.cpu().numpy(), bnd.cpu().numpy()
+    assert np.all(np.abs(got - ref) <= bnd)
