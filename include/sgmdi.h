@@ -330,10 +330,10 @@ sg_status sg_integrate_points(sg_context *ctx, const sg_problem *problem, const 
 /* Plain, plan-free path: one integrand, one launch, no graph, no batching.
  * Same arguments as one problem of a plan (param_offset is ignored: params_dev
  * points at this integrand's parameters).  out_dev/bound_dev: one float64
- * each (bound may be NULL).  Also takes OSCILLATORY_QUADRATIC (FP64 only;
- * the FP32 modes fail with UNSUPPORTED): the sweep of Section 3 with the
- * complex surpluses of e^{i a (x - u)^2} and the bound of the real sweep
- * (complex moduli in place of absolute values). */
+ * each (bound may be NULL).  Also takes OSCILLATORY_QUADRATIC, computed in
+ * FP64 whatever the precision mode: the sweep of Section 3 with the complex
+ * surpluses of e^{i a (x - u)^2} and the bound of the real sweep (complex
+ * moduli in place of absolute values). */
 sg_status sg_integrate(sg_context *ctx, const sg_problem *problem, int32_t precision,
                        const double *params_dev, double *out_dev, double *bound_dev, void *stream);
 

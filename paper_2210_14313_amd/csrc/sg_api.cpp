@@ -1260,12 +1260,10 @@ sg_status sg_integrate(sg_context* ctx, const sg_problem* problem, int32_t preci
     if (precision != SG_PREC_FP64 && precision != SG_PREC_FP32_COMPENSATED && precision != SG_PREC_FP32_FP64_SUM)
         return fail(ctx, SG_ERR_INVALID_ARGUMENT, "unknown precision");
     // the oscillatory quadratic (complex surpluses) has a sweep of its own,
-    // here only: FP64, one integrand
+    // in FP64 whatever the precision mode (as in plans)
     const bool oscq = problem->family == SG_FAMILY_OSCILLATORY_QUADRATIC;
     sg_status st = validate_problem(ctx, *problem, 0, oscq);
     if (st != SG_OK) return st;
-    if (oscq && precision != SG_PREC_FP64)
-        return fail(ctx, SG_ERR_UNSUPPORTED, "the oscillatory-quadratic sweep computes in FP64 only");
     const int K = problem->q - problem->d;
     if (oscq) {
         auto key = std::make_tuple(problem->rule, K, problem->family, 0);
