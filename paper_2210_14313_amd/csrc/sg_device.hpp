@@ -1446,9 +1446,13 @@ k_adjoint(const WGDesc* __restrict__ wgs, const ProbDev* __restrict__ probs, con
         return;
     }
     const ProbDev P = desc->slot[w].p;
-    switch_k<MAXK>(P.K, [&](auto kc) {
-        adjoint_dispatch_k<PREC, decltype(kc)::value, GAUSS>(P, sl.rank, sl.group, grouped, pool64, pool32, params,
-                                                             gout, grad, ws, lds + w * ADJ_WORDS);
+    // the K dispatch with every level forced inline: with the gaussian
+    // family the K = 8 body outgrew the inliner's budget and became a call,
+    // whose convention cost the kernel its whole register file and a stack
+    static_for<0, MAXK + 1>([&](auto kc) __attribute__((always_inline)) {
+        if (P.K == decltype(kc)::value)
+            adjoint_dispatch_k<PREC, decltype(kc)::value, GAUSS>(P, sl.rank, sl.group, grouped, pool64, pool32,
+                                                                 params, gout, grad, ws, lds + w * ADJ_WORDS);
     });
 }
 
