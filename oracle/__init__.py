@@ -207,4 +207,62 @@ def batch_points(batch, nthreads: int | None = None) -> np.ndarray:
     return out
 
 
+#: families of the form cos(2 pi w + phase(x)) with w the first parameter
+OSCILLATORY_FAMILIES = ("oscillatory", "oscillatory_quadratic")
+
+
+class _ParamBatch:
+    """Problems with a flat parameter array (the shape batch_factorised reads)."""
+
+    def __init__(self, problems, params):
+        self.problems = list(problems)
+        self.params = params
+
+    def __len__(self):
+        return len(self.problems)
+
+
+def quarter_shift(batch):
+    """The batch with w replaced by w - 1/4 for every oscillatory integrand
+    (same problems, a copy of the parameters).  Because the rule (2.6) is
+    linear, Q(w) + i Q(w - 1/4) = e^{2 pi i w} S with S the Smolyak sum of
+    the complex integrand e^{i phase(x)}: the shifted values are the
+    imaginary parts of the complex rule."""
+    params = np.array(batch.params, dtype=np.float64, copy=True)
+    for p in batch.problems:
+        if p.family in OSCILLATORY_FAMILIES:
+            params[p.param_offset] -= 0.25
+    return _ParamBatch(batch.problems, params)
+
+
+def accuracy_scale(batch, ref, nthreads: int | None = None) -> np.ndarray:
+    """Scale against which the error of each result is stated.
+
+    Non-oscillatory families: |Q|.  Oscillatory families (the real part of
+    e^{2 pi i w} S for a complex Smolyak sum S, see quarter_shift): the
+    modulus |S| = sqrt(Q(w)^2 + Q(w - 1/4)^2), which does not depend on w.
+    Q(w) itself passes through zero as w varies, so an error relative to
+    |Q(w)| is unbounded near those zeros while the rule's rounding error is
+    proportional to |S|.  ``ref`` holds the oracle's Q(w); the shifted values
+    come from the binary128 factorised sum."""
+    ref = np.asarray(ref, dtype=np.float64)
+    osc = np.array([p.family in OSCILLATORY_FAMILIES for p in batch.problems])
+    scale = np.abs(ref).copy()
+    if osc.any():
+        idx = np.nonzero(osc)[0]
+        shifted = batch_factorised(quarter_shift(_ParamBatch([batch.problems[i] for i in idx], batch.params)),
+                                   nthreads)
+        scale[idx] = np.hypot(ref[idx], shifted)
+    return scale
+
+
+def accuracy_scale_one(d: int, q: int, rule: str, family: str, params, ref: float) -> float:
+    """accuracy_scale for one integrand."""
+    if family not in OSCILLATORY_FAMILIES:
+        return abs(ref)
+    sp = np.array(params, dtype=np.float64, copy=True)
+    sp[0] -= 0.25
+    return float(np.hypot(ref, smolyak_factorised(d, q, rule, family, sp)))
+
+
 from . import counts, reference  # noqa: E402,F401

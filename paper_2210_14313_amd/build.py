@@ -12,6 +12,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsgmdi.so")
+# per-operation VALU ceiling probe (include/sgpeaks.h), a library of its own
+PEAKS_LIB = os.path.join(PKG, "libsgpeaks.so")
+PEAKS_SOURCE = "sg_peaks.hip"
 
 SOURCES = ["sg_fwd0.hip", "sg_fwd1.hip", "sg_fwd2.hip", "sg_adj0.hip", "sg_adj1.hip", "sg_unrank.hip", "sg_points.hip",
            "sg_blocked.hip", "sg_oscq.hip", "sg_rules.cpp", "sg_counts.cpp", "sg_api.cpp"]
@@ -81,12 +84,15 @@ def build(verbose: bool = False, extra_flags=None, incremental: bool = False) ->
     headers += [os.path.join(INCLUDE, h) for h in os.listdir(INCLUDE)]
     headers.append(os.path.join(objdir, "sg_tables.inc"))
 
+    peaks_header = os.path.join(INCLUDE, "sgpeaks.h")
+
     def compile_one(src):
         path = os.path.join(CSRC, src)
         obj = os.path.join(objdir, src + ".o")
+        deps = [peaks_header] if src == PEAKS_SOURCE else [h for h in headers if h != peaks_header]
         if incremental and os.path.exists(obj):
             t = os.path.getmtime(obj)
-            if all(os.path.getmtime(f) < t for f in [path] + headers):
+            if all(os.path.getmtime(f) < t for f in [path] + deps):
                 return obj
         cmd = [hipcc()] + HIP_FLAGS + (extra_flags or []) + ["-I", INCLUDE, "-I", CSRC, "-I", objdir, "-c", path, "-o", obj]
         if verbose:
@@ -98,16 +104,17 @@ def build(verbose: bool = False, extra_flags=None, incremental: bool = False) ->
         return obj
 
     # the kernel units are independent: compile them in parallel
-    workers = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    workers = max(1, min(len(SOURCES) + 1, int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
     with ThreadPoolExecutor(max_workers=workers) as ex:
-        objs = list(ex.map(compile_one, SOURCES))
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("linking libsgmdi.so failed")
-    os.replace(tmp, LIB)
+        objs = list(ex.map(compile_one, SOURCES + [PEAKS_SOURCE]))
+    for lib, lobjs in ((LIB, objs[:-1]), (PEAKS_LIB, objs[-1:])):
+        tmp = lib + ".tmp"
+        cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + lobjs
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError(f"linking {os.path.basename(lib)} failed")
+        os.replace(tmp, lib)
     return LIB
 
 

@@ -18,7 +18,12 @@ that bench.py states its accuracy without running the oracle itself:
   Clenshaw-Curtis batch (row i: dQ_i/dw, dQ_i/da_1..a_200);
 * oscq_d1000: binary128 factorised value of the oscillatory quadratic
   cos(2 pi w + sum a_i (x_i - u_i)^2), d = 1000, q = 1004, Gauss-Patterson
-  (workloads.oscillatory_quadratic_d1000).
+  (workloads.oscillatory_quadratic_d1000);
+* *_scale: the oracle's accuracy scale of each value above (|Q|; for the
+  oscillatory families the modulus sqrt(Q(w)^2 + Q(w - 1/4)^2) of the
+  complex rule, from oracle.accuracy_scale or, for the block rule, the block
+  rule at w - 1/4), and precision_d100_scale for the d = 100, q = 105
+  Clenshaw-Curtis workload of oracle_full_size.json.
 
 Run from the repository root:  python tests/golden/make_bench_refs.py
 """
@@ -67,12 +72,26 @@ def main():
     grads = np.stack([oracle.smolyak_factorised_grad(p.d, p.q, p.rule, p.family, gb.param_slice(i))
                       for i, p in enumerate(gb.problems[:GRAD_CHECK])])
     print("gradient_osc_d200_first64 done", flush=True)
-    oscq = oracle.batch_factorised(W.oscillatory_quadratic_d1000())
+    ob = W.oscillatory_quadratic_d1000()
+    oscq = oracle.batch_factorised(ob)
     print("oscq_d1000 done", flush=True)
+    uneven_scale = oracle.accuracy_scale(batch, uneven, nthreads)
+    blocked_scale = np.abs(blocked)
+    for i in range(BLOCKED_CHECK):
+        p = batch.problems[i]
+        if p.family in oracle.OSCILLATORY_FAMILIES:
+            prm = np.array(batch.param_slice(i), copy=True)
+            prm[0] -= 0.25
+            blocked_scale[i] = np.hypot(blocked[i], OB.smolyak_blocked(p.d, p.q, p.rule, p.family, prm, BLOCK_M))
+    pd = W.precision_d100()
+    pref = oracle.batch_factorised(pd)
+    print("scales done", flush=True)
     np.savez(OUT, uneven_4096=uneven, blocked_m10_first256=blocked, oscq_d1000=oscq,
              table_4_9_names=np.array([t[0] for t in TABLE_4_9]),
              table_4_9_exact=np.array(t_exact), table_4_9_blocked=np.array(t_blk),
-             gradient_osc_d200_first64=grads)
+             gradient_osc_d200_first64=grads,
+             uneven_4096_scale=uneven_scale, blocked_m10_first256_scale=blocked_scale,
+             oscq_d1000_scale=oracle.accuracy_scale(ob, oscq), precision_d100_scale=oracle.accuracy_scale(pd, pref))
 
 
 if __name__ == "__main__":

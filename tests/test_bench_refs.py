@@ -57,3 +57,30 @@ def test_gradient_rows(orc, refs):
 
 def test_oscillatory_quadratic_value(orc, refs):
     np.testing.assert_array_equal(orc.batch_factorised(W.oscillatory_quadratic_d1000()), refs["oscq_d1000"])
+
+
+def test_accuracy_scales(orc, refs):
+    b = W.batched_uneven(4096)
+    idx = list(range(3, 4096, 89))
+    sub = b.subset(idx)
+    np.testing.assert_allclose(orc.accuracy_scale(sub, refs["uneven_4096"][idx]), refs["uneven_4096_scale"][idx],
+                               rtol=1e-15)
+    osc = np.array([p.family == "oscillatory" for p in b.problems])
+    # the modulus is at least |Q|, with equality for the other family
+    s, r = refs["uneven_4096_scale"], refs["uneven_4096"]
+    assert np.all(s[osc] >= np.abs(r[osc])) and np.array_equal(s[~osc], np.abs(r[~osc]))
+    ob = W.oscillatory_quadratic_d1000()
+    np.testing.assert_allclose(orc.accuracy_scale(ob, refs["oscq_d1000"]), refs["oscq_d1000_scale"], rtol=1e-15)
+    pd = W.precision_d100()
+    np.testing.assert_allclose(orc.accuracy_scale(pd, orc.batch_factorised(pd)), refs["precision_d100_scale"],
+                               rtol=1e-15)
+    bs = refs["blocked_m10_first256_scale"]
+    for i in (0, 1, 77, 255):
+        p = b.problems[i]
+        if p.family == "oscillatory":
+            prm = np.array(b.param_slice(i), copy=True)
+            prm[0] -= 0.25
+            exp = np.hypot(refs["blocked_m10_first256"][i], OB.smolyak_blocked(p.d, p.q, p.rule, p.family, prm, 10))
+        else:
+            exp = abs(refs["blocked_m10_first256"][i])
+        assert abs(bs[i] - exp) <= 1e-15 * exp

@@ -2,7 +2,7 @@
 against the oracle's block rule, through the C ABI.
 
 Tolerances as for the plain rule: FP64 within 1e-12 relative (oscillatory:
-relative to max(|Q|, 1)) and within the stated bound; the FP32 modes within
+relative to the modulus of the complex block rule) and within the stated bound; the FP32 modes within
 the stated bound, which the combine step propagates from the blocks' bounds.
 """
 import ctypes
@@ -28,9 +28,19 @@ def torch_dev():
     return torch
 
 
-def _scale(batch, ref):
-    fam = np.array([p.family for p in batch.problems])
-    return np.where(fam == "oscillatory", np.maximum(np.abs(ref), 1.0), np.abs(ref))
+def _scale(batch, ref, m):
+    """|Q|, and for the oscillatory family the modulus of the complex block
+    rule, sqrt(Q(w)^2 + Q(w - 1/4)^2) (the block rule is linear in the
+    integrand, so Q(w - 1/4) is the imaginary part)."""
+    import oracle
+    from oracle import blocked as B
+    sc = np.abs(ref).copy()
+    for i, p in enumerate(batch.problems):
+        if p.family in oracle.OSCILLATORY_FAMILIES:
+            prm = np.array(batch.param_slice(i), copy=True)
+            prm[0] -= 0.25
+            sc[i] = np.hypot(ref[i], B.smolyak_blocked(p.d, p.q, p.rule, p.family, prm, m, "factorised"))
+    return sc
 
 
 def _blocked_ref(batch, m, method):
@@ -64,7 +74,7 @@ def test_small_random_blocked_fp64(torch_dev, orc, seed, m):
     say("case blocked small fp64 seed", seed, "m", m)
     got, bnd, _ = _run(b, "fp64", m)
     ref = _blocked_ref(b, m, "points")
-    err = np.abs(got - ref) / _scale(b, ref)
+    err = np.abs(got - ref) / _scale(b, ref, m)
     assert np.max(err) <= 1e-12, (np.argmax(err), np.max(err))
     assert np.all(np.abs(got - ref) <= bnd + 1e-300)
 
@@ -88,10 +98,14 @@ def test_one_block_matches_the_plain_plan(torch_dev, family):
     say("case blocked one block", family)
     plain, pb = api.integrate(b, "fp64", with_bound=True)
     plain, pb = plain.cpu().numpy(), pb.cpu().numpy()
+    import oracle
+    p = b.problems[0]
+    sc = oracle.accuracy_scale_one(p.d, p.q, p.rule, p.family, b.param_slice(0),
+                                   oracle.smolyak_factorised(p.d, p.q, p.rule, p.family, b.param_slice(0)))
     for m in (40, 64):
         got, bnd, _ = _run(b, "fp64", m)
         assert abs(got[0] - plain[0]) <= bnd[0] + pb[0]
-        assert abs(got[0] - plain[0]) <= 1e-13 * max(abs(plain[0]), 1.0)
+        assert abs(got[0] - plain[0]) <= 1e-13 * sc
 
 
 def test_high_dimension_paper_setting(torch_dev, orc):
@@ -113,7 +127,7 @@ def test_high_dimension_paper_setting(torch_dev, orc):
         got, bnd, info = _run(b, prec, 10)
         assert np.all(np.abs(got - ref) <= bnd), (prec, got, ref, bnd)
         if prec == "fp64":
-            assert np.max(np.abs(got - ref) / _scale(b, ref)) <= 1e-12
+            assert np.max(np.abs(got - ref) / _scale(b, ref, 10)) <= 1e-12
     assert info["effective_points"] == 2 ** 64 - 1     # the tensor product's count saturates
 
 

@@ -5,7 +5,8 @@ the reverse sweep, the point-by-point path and the block variant, against
 the oracle's own Gauss-Patterson construction.
 
 Tolerances as for the other rules: FP64 within 1e-12 relative (oscillatory:
-to max(|Q|, 1)) and within the stated bound; FP32 modes within the bound.
+to the oracle's accuracy scale: the modulus of the complex Smolyak sum) and
+within the stated bound; FP32 modes within the bound.
 """
 import sys
 
@@ -30,8 +31,8 @@ def torch_dev():
 
 
 def _scale(batch, ref):
-    fam = np.array([p.family for p in batch.problems])
-    return np.where(fam == "oscillatory", np.maximum(np.abs(ref), 1.0), np.abs(ref))
+    import oracle
+    return oracle.accuracy_scale(batch, ref)
 
 
 def _run(batch, precision):

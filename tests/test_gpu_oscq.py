@@ -7,8 +7,9 @@ d), with the stated bound; the sine of Test 1 ((4.1), on [-1,1]^2 mapped to
 the unit cube); the block variant; FP64 values in every precision mode;
 rejection of the reverse sweep.
 
-Tolerance: within the stated bound, and within 1e-12 of max(|Q|, 1) (the
-scale the oscillatory family is held to).
+Tolerance: within the stated bound, and within 1e-12 relative to the
+oracle's accuracy scale (the modulus of the complex Smolyak sum,
+sqrt(Q(w)^2 + Q(w - 1/4)^2)).
 """
 import sys
 
@@ -44,9 +45,14 @@ def _one(problem, prm, precision="fp64"):
     return out.item(), bound.item()
 
 
-def _check(got, bnd, ref, extra=0.0):
+def _mod(batch, ref):
+    import oracle
+    return oracle.accuracy_scale(batch, np.atleast_1d(ref))
+
+
+def _check(got, bnd, ref, scale, extra=0.0):
     assert abs(got - ref) <= bnd + extra, (got, ref, bnd)
-    assert abs(got - ref) <= 1e-12 * max(abs(ref), 1.0), (got, ref)
+    assert abs(got - ref) <= 1e-12 * scale, (got, ref)
 
 
 @pytest.mark.parametrize("seed", [1, 2])
@@ -59,7 +65,7 @@ def test_oscq_small_random_vs_point_oracle(torch_dev, orc, seed):
         got, bnd = _one(p, b.param_slice(i))
         # the point oracle's own rounding (extended precision) is below
         # 8 * 2^-64 * (A + |f(c)|)
-        _check(got, bnd, r["q"], 8 * 2.0 ** -64 * (r["A"] + abs(r["fc"])))
+        _check(got, bnd, r["q"], _mod(b.subset([i]), r["q"])[0], 8 * 2.0 ** -64 * (r["A"] + abs(r["fc"])))
 
 
 @pytest.mark.parametrize("d,K,rule,scale", [(1, 8, "gp", 1.0), (3, 5, "cc", 5.0), (64, 4, "tr", 1.0),
@@ -74,7 +80,7 @@ def test_oscq_edges_vs_factorised_oracle(torch_dev, orc, d, K, rule, scale):
     say("case oscq edge", d, K, rule, scale)
     ref = orc.batch_factorised(b)[0]
     got, bnd = _one(b.problems[0], prm)
-    _check(got, bnd, ref)
+    _check(got, bnd, ref, _mod(b, ref)[0])
 
 
 def test_oscq_paper_test_1_sine(torch_dev, orc):
@@ -88,7 +94,7 @@ def test_oscq_paper_test_1_sine(torch_dev, orc):
         say("case oscq test 1", q)
         r = orc.smolyak_points(2, q, "gp", FAM, prm)
         got, bnd = _one(b.problems[0], prm)
-        _check(got, bnd, r["q"], 8 * 2.0 ** -64 * (r["A"] + abs(r["fc"])))
+        _check(got, bnd, r["q"], _mod(b, r["q"])[0], 8 * 2.0 ** -64 * (r["A"] + abs(r["fc"])))
 
 
 def test_oscq_deterministic_and_fp64_in_every_mode(torch_dev):
@@ -117,7 +123,7 @@ def test_oscq_in_mixed_plans(torch_dev, orc, precision):
     assert np.all(np.abs(got - ref) <= bnd), np.max(np.abs(got - ref) / bnd)
     fam = np.array([p.family for p in b.problems])
     sel = fam == FAM
-    assert np.max(np.abs(got[sel] - ref[sel]) / np.maximum(np.abs(ref[sel]), 1.0)) <= 1e-12
+    assert np.max(np.abs(got[sel] - ref[sel]) / _mod(b, ref)[sel]) <= 1e-12
     for i in np.flatnonzero(sel)[:5]:                      # the same value as the one-shot path
         one = b.subset([int(i)])
         v, _ = _one(one.problems[0], one.param_slice(0))
@@ -149,7 +155,7 @@ def test_oscq_only_plan_autotuned_on_a_stream(torch_dev, orc):
     for r in runs[1:]:
         assert np.array_equal(r, runs[0])
     assert np.all(np.abs(runs[0] - ref) <= bnd)
-    assert np.max(np.abs(runs[0] - ref) / np.maximum(np.abs(ref), 1.0)) <= 1e-12
+    assert np.max(np.abs(runs[0] - ref) / _mod(b, ref)) <= 1e-12
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32c"])
@@ -169,7 +175,7 @@ def test_oscq_block_variant(torch_dev, orc, precision):
     assert np.all(np.abs(got - ref) <= bnd), np.max(np.abs(got - ref) / bnd)
     fam = np.array([p.family for p in b.problems])
     sel = fam == FAM
-    assert np.max(np.abs(got[sel] - ref[sel]) / np.maximum(np.abs(ref[sel]), 1.0)) <= 1e-12
+    assert np.max(np.abs(got[sel] - ref[sel]) / _mod(b, ref)[sel]) <= 1e-12
 
 
 def test_oscq_rejected_by_the_reverse_sweep(torch_dev):
@@ -202,7 +208,7 @@ def test_oscq_plan_graph_replays(torch_dev, orc, persistent):
     try:
         plan.set_schedule(2, 4, graph=True, persistent=persistent)
         eager = plan.execute(params).clone()           # default stream: direct launches
-        assert np.max(np.abs(eager.cpu().numpy() - ref) / np.maximum(np.abs(ref), 1.0)) <= 1e-12
+        assert np.max(np.abs(eager.cpu().numpy() - ref) / _mod(b, ref)) <= 1e-12
         s = torch.cuda.Stream()
         out = torch.empty(len(b), dtype=torch.float64, device="cuda")
         for _ in range(4):                             # capture, then replays
@@ -231,9 +237,10 @@ def test_oscq_degenerate_and_large_coefficients(torch_dev, orc):
     b = W.concat(cases)
     say("case oscq degenerate / large")
     ref = orc.batch_factorised(b)
+    mod = _mod(b, ref)
     for i, p in enumerate(b.problems):
         pt = orc.smolyak_points(p.d, p.q, p.rule, p.family, b.param_slice(i))
-        assert abs(pt["q"] - ref[i]) <= 1e-12 * max(abs(ref[i]), 1.0) + 8 * 2.0 ** -64 * (pt["A"] + abs(pt["fc"]))
+        assert abs(pt["q"] - ref[i]) <= 1e-12 * mod[i] + 8 * 2.0 ** -64 * (pt["A"] + abs(pt["fc"]))
         v, bd = _one(p, b.param_slice(i))
         assert abs(v - ref[i]) <= bd, (i, v, ref[i], bd)
         if p.q == p.d:

@@ -6,8 +6,9 @@ Tolerance: both sides evaluate the same sum, the GPU in FP64 with
 double-double accumulation, the oracle in x87 extended precision with
 Neumaier accumulation.  Each GPU result must lie within the rounding bound
 the library states for it plus the oracle's own rounding scale
-(8 * 2^-64 * (A + |f(c)|)), and within 1e-12 relative (oscillatory: to
-max(|Q|, 1)) wherever that bound is below it; the terms' cancellation puts
+(8 * 2^-64 * (A + |f(c)|)), and within 1e-12 relative wherever that bound
+is below it (relative to the oracle's accuracy scale: |Q|, oscillatory
+families the modulus of the complex Smolyak sum); the terms' cancellation puts
 the bound far above 1e-12 at d = 100.
 """
 import json
@@ -36,8 +37,10 @@ def torch_dev():
     return torch
 
 
-def _scale(family, ref):
-    return max(abs(ref), 1.0) if family == "oscillatory" else abs(ref)
+def _acc(batch, i, ref):
+    import oracle
+    p = batch.problems[i]
+    return oracle.accuracy_scale_one(p.d, p.q, p.rule, p.family, batch.param_slice(i), ref)
 
 
 def _points(batch, i, max_points=0, with_bound=False):
@@ -51,12 +54,12 @@ def _points(batch, i, max_points=0, with_bound=False):
     return (out.item(), bound.item()) if with_bound else out.item()
 
 
-def _check(got, bnd, ref, family, oracle_scale):
+def _check(got, bnd, ref, scale, oracle_scale):
     err = abs(got - ref)
     tol_oracle = 8 * 2.0 ** -64 * oracle_scale
     assert err <= bnd + tol_oracle, (got, ref, err, bnd)
-    if bnd + tol_oracle <= 1e-12 * _scale(family, ref):
-        assert err <= 1e-12 * _scale(family, ref), (got, ref, err)
+    if bnd + tol_oracle <= 1e-12 * scale:
+        assert err <= 1e-12 * scale, (got, ref, err)
 
 
 @pytest.mark.parametrize("seed", [3, 4, 5])
@@ -67,7 +70,7 @@ def test_points_small_random_vs_point_oracle(torch_dev, orc, seed):
     for i, p in enumerate(b.problems):
         r = orc.smolyak_points(p.d, p.q, p.rule, p.family, b.param_slice(i))
         got, bnd = _points(b, i, with_bound=True)
-        _check(got, bnd, r["q"], p.family, r["A"] + abs(r["fc"]))
+        _check(got, bnd, r["q"], _acc(b, i, r["q"]), r["A"] + abs(r["fc"]))
 
 
 @pytest.mark.parametrize("d,K,rule,family", [(1, 8, "cc", "exp_sum"), (2, 8, "gl", "oscillatory"),
@@ -81,7 +84,7 @@ def test_points_edges_vs_point_oracle(torch_dev, orc, d, K, rule, family):
     say("case points edge", d, K, rule, family)
     r = orc.smolyak_points(d, d + K, rule, family, b.param_slice(0))
     got, bnd = _points(b, 0, with_bound=True)
-    _check(got, bnd, r["q"], family, r["A"] + abs(r["fc"]))
+    _check(got, bnd, r["q"], _acc(b, 0, r["q"]), r["A"] + abs(r["fc"]))
 
 
 def test_points_plain_exp_d10(torch_dev, orc):
@@ -90,7 +93,7 @@ def test_points_plain_exp_d10(torch_dev, orc):
     say("case points plain_exp_d10")
     r = orc.smolyak_points(10, 14, "cc", "exp_sum", b.param_slice(0))
     got, bnd = _points(b, 0, with_bound=True)
-    _check(got, bnd, r["q"], "exp_sum", r["A"] + abs(r["fc"]))
+    _check(got, bnd, r["q"], _acc(b, 0, r["q"]), r["A"] + abs(r["fc"]))
     assert abs(got - r["q"]) <= 1e-12 * abs(r["q"])
 
 
@@ -111,7 +114,7 @@ def test_points_full_size_against_stored_point_oracle(torch_dev, row):
     ref = row["points_hi"] + row["points_lo"]
     got, bnd = _points(b, 0, with_bound=True)
     say("  got", got, "oracle", ref, "bound", bnd)
-    _check(got, bnd, ref, p.family, row["points_A"] + abs(row["fc"]))
+    _check(got, bnd, ref, _acc(b, 0, ref), row["points_A"] + abs(row["fc"]))
 
 
 def test_points_agree_with_factorised_sweep(torch_dev):
@@ -150,7 +153,7 @@ def test_points_corner_peak_vs_point_oracle(torch_dev, orc, d, K, rule):
     say("case points corner peak", d, K, rule)
     r = orc.smolyak_points(d, d + K, rule, "corner_peak", b.param_slice(0))
     got, bnd = _points(b, 0, with_bound=True)
-    _check(got, bnd, r["q"], "corner_peak", r["A"] + abs(r["fc"]))
+    _check(got, bnd, r["q"], _acc(b, 0, r["q"]), r["A"] + abs(r["fc"]))
 
 
 def test_points_corner_peak_converges_to_closed_form(torch_dev):
@@ -184,8 +187,7 @@ def test_points_quadratic_families_vs_point_oracle(torch_dev, orc, family, d, K,
     say("case points quadratic", family, d, K, rule)
     r = orc.smolyak_points(d, d + K, rule, family, b.param_slice(0))
     got, bnd = _points(b, 0, with_bound=True)
-    _check(got, bnd, r["q"], "oscillatory" if family == "oscillatory_quadratic" else family,
-           r["A"] + abs(r["fc"]))
+    _check(got, bnd, r["q"], _acc(b, 0, r["q"]), r["A"] + abs(r["fc"]))
 
 
 def test_points_paper_table_4_1_first_row(torch_dev):

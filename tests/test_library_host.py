@@ -154,3 +154,28 @@ def test_gauss_patterson_counts_match_the_paper():
     for row in g["rows"]:
         d, q = row["d"], row["q"]
         assert native.counts(d, d + q - 1, "gp")[2] == row["unique_points"], row
+
+
+def test_peaks_library_exports_every_declared_symbol():
+    from paper_2210_14313_amd import peaks
+    hdr = open(os.path.join(ROOT, "include", "sgpeaks.h")).read()
+    declared = set(re.findall(r"^(?:int32_t|const char \*)\s*(sgp_\w+)\s*\(", hdr, flags=re.M))
+    assert declared == set(peaks.EXPORTS), declared ^ set(peaks.EXPORTS)
+    L = peaks.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+    names = [L.sgp_op_name(i).decode() for i in range(len(peaks.OPS))]
+    assert names == list(peaks.OPS), names
+    assert L.sgp_op_name(len(peaks.OPS)) == b""
+
+
+def test_peaks_rejects_bad_arguments_before_launch():
+    import ctypes
+    from paper_2210_14313_amd import peaks
+    L = peaks.lib()
+    sink = ctypes.c_void_p(16)     # never dereferenced: every call below is rejected first
+    assert L.sgp_launch(-1, 1, 1, sink, None, None, None) == 1
+    assert L.sgp_launch(len(peaks.OPS), 1, 1, sink, None, None, None) == 1
+    assert L.sgp_launch(0, 0, 1, sink, None, None, None) == 1
+    assert L.sgp_launch(0, 1, 0, sink, None, None, None) == 1
+    assert L.sgp_launch(0, 1, 1, None, None, None, None) == 1
