@@ -50,18 +50,19 @@ MEASURED_TRAFFIC = {
 }
 
 
-# The schedule the autotuner picks for the 4096-integrand batch (its
-# candidates within ~2% of each other there), pinned so that the headline
-# and its rocprofv3 profile run the same launch shape:
-# (coords_per_lane, max_group, cost_scaled, persistent, graph).
-PINNED_SCHEDULE = {"fp32c": (4, 4, 0, 0, 0), "fp32e": (3, 1, 0, 0, 0), "fp64": (2, 4, 0, 0, 0)}
+# The headline plan's schedule, pinned so that the headline and its
+# rocprofv3 profile run the same launch shape: the balanced schedule with two
+# waves per SIMD (the library's default; the autotuner's choice on this batch
+# lands within a few per cent of it).  A tuple (coords_per_lane, max_group,
+# cost_scaled, persistent, graph) names a coordinates-per-lane schedule.
+PINNED_SCHEDULE = {"fp32c": ("balanced", 2, 0), "fp32e": ("balanced", 2, 0), "fp64": ("balanced", 2, 0)}
 
 
 def kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2210_14313_amd", "csrc")
-    for f in ("sg_device.hpp", "sg_internal.hpp", "sg_fwd0.hip", "sg_fwd1.hip", "sg_fwd2.hip", "sg_rules.cpp",
+    for f in ("sg_device.hpp", "sg_internal.hpp", "sg_fwd_inst.hpp", "sg_fwd_p1_k6.hip", "sg_rules.cpp",
               "gen_tables.cpp"):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
@@ -461,7 +462,7 @@ def blocked_leg(dev, s, batch, precision: str, m: int = 10, reps: int = 50):
     res[f"batched_uneven_{len(batch)}_m{m}"] = {
         "precision": precision, "ms_per_launch": ms, "block_subproblems_units": info["units"],
         "schedule": {k: info[k] for k in ("coords_per_lane", "max_group", "cost_scaled", "persistent", "graph",
-                                          "grid_blocks")},
+                                          "grid_blocks", "balanced")},
         "roofline": roof,
         "max_rel_err_vs_block_oracle": acc_err, "all_within_stated_bound": acc_ok,
         "checked_integrands": len(idx)}
@@ -626,6 +627,8 @@ def main():
     ap.add_argument("--sched", default="",
                     help="headline plan's schedule: coords_per_lane,max_group,cost_scaled,persistent,graph "
                          "(default: the autotuner's usual choice for the 4096 batch, pinned)")
+    ap.add_argument("--balanced", type=int, default=0,
+                    help="headline plan's schedule: the balanced schedule with this many waves per SIMD")
     ap.add_argument("--cpu-points", type=float, default=1.5e9)
     ap.add_argument("--scaling-mults", default="16,64",
                     help="extra batch sizes (multiples of --n) for the scaling series")
@@ -724,7 +727,9 @@ def main():
         plan = native.Plan(batch.problems, precision)
         out = torch.empty(len(batch), dtype=torch.float64, device=dev)
         bound = torch.empty_like(out)
-        if sched:
+        if sched and sched[0] == "balanced":
+            plan.set_balanced(sched[1], graph=bool(sched[2]))
+        elif sched:
             c, g, cs, pq, gr = sched
             plan.set_schedule(c, g, graph=bool(gr), persistent=bool(pq), cost_scaled=bool(cs))
         elif autotune:
@@ -753,13 +758,15 @@ def main():
         bnd = bound.cpu().numpy()
         info = plan.info()
         log(f"  {precision}: sched cpl {info['coords_per_lane']} gmax {info['max_group']} cost_scaled "
-            f"{info['cost_scaled']} persistent {info['persistent']} graph {info['graph']} "
+            f"{info['cost_scaled']} persistent {info['persistent']} graph {info['graph']} balanced {info['balanced']} "
             f"grid {info['grid_blocks']}, kernel {kern_ms * 1e3:.2f} us, step {(t1 - t0) * 1e6 / steps:.2f} us")
         plan.close()
         return dict(ms_per_step=(t1 - t0) * 1e3 / steps, kernel_ms=float(kern_ms), got=got, bound=bnd, info=info)
 
     log(f"timing {args.precision} batched plan: {args.steps} steps after {args.warmup} warmup")
-    if args.sched:
+    if args.balanced:
+        pinned = ("balanced", args.balanced, 0)
+    elif args.sched:
         pinned = tuple(int(v) for v in args.sched.split(","))
     elif args.autotune:
         pinned = None
@@ -804,7 +811,7 @@ def main():
                                f"family~{{oscillatory, exp-sum}}, one launch per step",
                    "integrands": args.n, "precision": args.precision,
                    "schedule": {k: info[k] for k in ("coords_per_lane", "max_group", "cost_scaled", "persistent",
-                                                     "graph", "grid_blocks")},
+                                                     "graph", "grid_blocks", "balanced")},
                    "schedule_source": "pinned" if pinned else "autotuned",
                    "effective_points_per_step": eff, "parallelism": "single-gpu"},
         "roofline": roof,
@@ -816,8 +823,8 @@ def main():
         # the autotuner on the headline batch
         at = run_plan(args.precision, args.steps, 5, True)
         extras["autotuned_" + args.precision] = {
-            "schedule": {k: at["info"][k] for k in ("coords_per_lane", "max_group", "cost_scaled", "persistent",
-                                                    "graph", "grid_blocks")},
+            "schedule": {k: at["info"][k] for k in ("coords_per_lane", "max_group", "cost_scaled", "persistent", "graph",
+                                          "grid_blocks", "balanced")},
             "kernel_ms": at["kernel_ms"], "ms_per_step": at["ms_per_step"],
             "max_rel_err_vs_oracle": rel_err(at["got"])}
         # the other precision modes' batched rates

@@ -268,7 +268,10 @@ sg_status sg_plan_execute_grad(sg_plan *plan, const double *params_dev, const do
  *   descriptors, longest first, from a per-plan queue that each launch
  *   leaves reset; executions of such a plan must not overlap in time), 0 if
  *   the hardware dispatches one workgroup per descriptor (the four knobs are
- *   chosen by sg_plan_autotune). */
+ *   chosen by sg_plan_autotune);
+ *   balanced: 0, or the waves per SIMD of the balanced schedule
+ *   (sg_plan_set_schedule_balanced), which replaces coords_per_lane,
+ *   max_group and cost_scaled. */
 typedef struct {
     uint64_t effective_points;
     uint64_t units;
@@ -282,7 +285,7 @@ typedef struct {
     int32_t graph;
     int32_t persistent;
     int32_t cost_scaled;
-    int32_t reserved;
+    int32_t balanced;
 } sg_plan_info;
 
 sg_status sg_plan_get_info(const sg_plan *plan, sg_plan_info *info);
@@ -291,7 +294,8 @@ sg_status sg_plan_get_info(const sg_plan *plan, sg_plan_info *info);
  * keep the fastest (stored in the context; later plans with the same shape
  * class reuse it): the integrand-to-wave schedule (coordinates per lane
  * 1, 2, 3, 4, 8, 16, uniform or cost-scaled, times waves per integrand
- * 1, 2, 4; see sg_plan_info),
+ * 1, 2, 4; and the balanced schedule with 1..4 waves per SIMD; see
+ * sg_plan_info),
  * hardware dispatch versus the persistent work-queue kernel and, on a
  * non-default stream, graph replay versus direct launch.  Runs the forward
  * launch repeatedly on params_dev/out_dev (their contents are overwritten).
@@ -305,6 +309,23 @@ sg_status sg_plan_autotune(sg_plan *plan, const double *params_dev, double *out_
  * workgroups; synchronous.  Errors: INVALID_ARGUMENT, OUT_OF_MEMORY, DEVICE. */
 sg_status sg_plan_set_schedule(sg_plan *plan, int32_t coords_per_lane, int32_t max_group,
                                int32_t cost_scaled, int32_t persistent, int32_t graph);
+
+/* Balanced forward schedule: every wave of the forward launch gets about
+ * the same estimated cost and the launch has at most waves_per_simd waves
+ * per SIMD of the device.  A cost model of the kernel (per coordinate: node
+ * pairs and weighted terms of the problem's class and precision mode; per
+ * wave: the loads, the reduction across lanes and the read-out) picks the
+ * coordinates per lane of each class for one common target wave cost, the
+ * smallest target whose waves fit; waves form 4-wave workgroups of similar
+ * cost, and the workgroups are ordered so that each compute unit receives
+ * the same load under the hardware's in-order placement (workgroup i on
+ * compute unit i mod the unit count while all are resident).  Uses hardware
+ * dispatch (no persistent queue); graph: as for sg_plan_set_schedule.  Only
+ * the speed depends on the schedule, never the values beyond the order of
+ * the sweep's products.
+ * Errors: INVALID_ARGUMENT (waves_per_simd outside 1..8, graph not 0/1),
+ * OUT_OF_MEMORY, DEVICE. */
+sg_status sg_plan_set_schedule_balanced(sg_plan *plan, int32_t waves_per_simd, int32_t graph);
 
 /* Release a plan (NULL accepted). */
 sg_status sg_plan_destroy(sg_plan *plan);

@@ -16,7 +16,8 @@ LIB = os.path.join(PKG, "libsgmdi.so")
 PEAKS_LIB = os.path.join(PKG, "libsgpeaks.so")
 PEAKS_SOURCE = "sg_peaks.hip"
 
-SOURCES = ["sg_fwd0.hip", "sg_fwd1.hip", "sg_fwd2.hip", "sg_adj0.hip", "sg_adj1.hip", "sg_unrank.hip", "sg_points.hip",
+FORWARD_UNITS = [f"sg_fwd_p{p}_{k}.hip" for p in (0, 1, 2) for k in ("k4", "k6", "k8", "g8")]
+SOURCES = FORWARD_UNITS + ["sg_adj0.hip", "sg_adj1.hip", "sg_unrank.hip", "sg_points.hip",
            "sg_blocked.hip", "sg_oscq.hip", "sg_rules.cpp", "sg_counts.cpp", "sg_api.cpp"]
 
 # Packed FP32 instructions are disabled for every device pass; contraction of

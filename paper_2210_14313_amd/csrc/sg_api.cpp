@@ -3,6 +3,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <cmath>
+#include <functional>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -37,11 +40,14 @@ struct PointsTable {
 
 // Forward schedule: target coordinates per lane and the most waves one
 // problem may span.
+// The default for new plans is the balanced schedule with two waves per
+// SIMD (fastest on the mixed 4096-integrand workload on MI355X).
 struct FwdSched {
-    int cpl = 2;
+    int cpl = 4;
     int gmax = 4;
     bool persistent = false;   // work-queue kernel instead of one workgroup per descriptor
     bool cost_scaled = false;  // cpl applies to the costliest class; cheaper classes get proportionally more
+    int balanced = 2;          // > 0: equal-cost waves, this many per SIMD (pack_forward_balanced)
 };
 
 struct Records {
@@ -98,6 +104,8 @@ struct sg_plan {
     float* d_pool32 = nullptr;
     std::vector<ProbDev> probs;     // plan order (longest first)
     std::vector<double> unit_cost;  // per-coordinate cost estimate, plan order
+    std::vector<double> coord_cost; // per-coordinate cost of the balanced schedule's model, plan order
+    int n_cu = 0;                   // compute units of the plan's device
     double cmax = 1.0;              // largest unit cost of the plan
     int wmax = -1;                  // reverse sweep: > 0 waves cap, < 0 cost threshold (see waves_for)
     FwdSched sched;                 // forward schedule (see pack_forward)
@@ -386,6 +394,224 @@ std::vector<FwdWG> pack_forward(const std::vector<ProbDev>& probs, const std::ve
         if (used[target] == 4) open.erase(std::find(open.begin(), open.end(), target));
     }
     return wgs;
+}
+
+// ------------------------------------------------- balanced forward schedule
+// Cost model of the forward kernel on gfx950, in units of one FP32 VALU
+// instruction issued per wave (FP64 operations weigh 1.65, the ratio of the
+// two issue rates measured on MI355X).  Per coordinate a lane evaluates P
+// node pairs and M weighted terms and multiplies one truncated polynomial;
+// per wave there is a fixed cost (descriptor and parameter loads, the
+// segmented reduction across lanes, the read-out) that is mostly dependency
+// latency.  Calibrated against single-class plans timed on the device
+// (per-coordinate costs within 10 % of the measured ones for K = 2..6,
+// Clenshaw-Curtis and Gauss-Legendre, both real families).
+double fwd_coord_cost(const ProbDev& p, int npairs, uint64_t macs, int precision)
+{
+    const int K = p.K;
+    const bool series = p.family == SG_FAMILY_EXP_SUM || p.family == SG_FAMILY_OSCILLATORY;
+    double pv = p.family == SG_FAMILY_GAUSSIAN ? 90.0 : p.family == SG_FAMILY_PRODUCT_PEAK ? 25.0
+                : precision == SG_PREC_FP64 ? 18.0 : 7.0;
+    const double mac = precision == SG_PREC_FP32_COMPENSATED ? 2.75 : 1.65;
+    double c = (double)npairs * pv + (double)macs * mac + 1.65 * (double)(K * (K - 1) / 2 + K) + 4.0 * K + 31.0;
+    if (p.family == SG_FAMILY_PRODUCT_PEAK) c += 40.0;            // log of the centre value
+    if (K > 6 || !series) c *= 1.5;                                 // table-driven records (loads)
+    return c;
+}
+double fwd_wave_overhead(int K, int family)
+{
+    return 450.0 + 125.0 * K + (family == SG_FAMILY_OSCILLATORY ? 100.0 : 0.0);
+}
+
+// Equal-cost waves, `sc.balanced` per SIMD.  For a target wave cost T every
+// problem gets the most coordinates per lane C with C * cost + overhead <= T,
+// hence 2^lw lanes (or a group of up to 4 waves); problems of one class and
+// shape share waves, longest first.  T is the smallest value whose waves fit
+// in balanced * n_simd.  Waves then form workgroups of four of similar
+// cost (a group stays inside one workgroup), and workgroups are placed so
+// that every compute unit receives the same load: the hardware places
+// workgroup i on compute unit i mod n_cu while all workgroups are resident,
+// and each of a workgroup's four waves on its own SIMD, so a CU's SIMDs each
+// take one wave of each of its workgroups.  Empty descriptors fill the
+// positions no workgroup takes.
+std::vector<FwdWG> pack_forward_balanced(const std::vector<ProbDev>& probs, const std::vector<double>& coord_cost,
+                                         const FwdSched& sc, int n_cu, double* est_max_load)
+{
+    const int n_simd = 4 * n_cu;
+    struct Item {
+        double cost;
+        std::vector<FwdWave> waves;
+    };
+    auto base = [&](const ProbDev& pd, int lw, int group) {
+        FwdWave w;
+        std::memset(&w, 0, sizeof w);
+        w.K = (int16_t)pd.K;
+        w.rule = (int16_t)pd.rule;
+        w.family = (int16_t)pd.family;
+        w.lw = (int16_t)lw;
+        w.group = (int16_t)group;
+        w.off64 = (int32_t)pd.off64;
+        w.off32 = (int32_t)pd.off32;
+        for (int i = 0; i < kWaveProbs; ++i) w.seg[i].out_index = -1;
+        return w;
+    };
+    auto build = [&](double T, std::vector<Item>& items) {
+        items.clear();
+        std::map<std::tuple<int, int, int, int, int>, std::vector<int>> buckets;
+        for (size_t k = 0; k < probs.size(); ++k) {
+            const ProbDev& pd = probs[k];
+            const double o = fwd_wave_overhead(pd.K, pd.family);
+            const int C = (int)std::max(1.0, std::min(4096.0, std::floor((T - o) / coord_cost[k])));
+            const int lanes = (pd.d + C - 1) / C;
+            int lw = 2, group = 1;
+            if (lanes > 64) {
+                lw = 6;
+                group = (lanes + 63) / 64;
+                group = group <= 1 ? 1 : group <= 2 ? 2 : 4;
+                group = std::min(group, sc.gmax);
+            } else {
+                while ((1 << lw) < lanes) ++lw;
+            }
+            buckets[std::make_tuple(pd.K, pd.rule, pd.family, lw, group)].push_back((int)k);
+        }
+        for (auto& kv : buckets) {
+            const int lw = std::get<3>(kv.first), group = std::get<4>(kv.first);
+            std::vector<int> list = kv.second;
+            std::stable_sort(list.begin(), list.end(), [&](int a, int b) { return probs[a].d > probs[b].d; });
+            const ProbDev& p0 = probs[list[0]];
+            const double o = fwd_wave_overhead(p0.K, p0.family);
+            if (group == 1) {
+                const size_t per = (size_t)std::min(kWaveProbs, 64 >> lw);
+                for (size_t i = 0; i < list.size(); i += per) {
+                    FwdWave w = base(probs[list[i]], lw, 1);
+                    int maxd = 0;
+                    for (size_t j = i; j < std::min(list.size(), i + per); ++j) {
+                        w.seg[j - i] = seg_of(probs[list[j]]);
+                        maxd = std::max(maxd, probs[list[j]].d);
+                    }
+                    w.nprob = (int16_t)(std::min(list.size(), i + per) - i);
+                    const int span = 1 << lw;
+                    items.push_back(Item{(double)((maxd + span - 1) / span) * coord_cost[list[i]] + o,
+                                         std::vector<FwdWave>(1, w)});
+                }
+            } else {
+                for (int k : list) {
+                    Item it;
+                    it.cost = (double)((probs[k].d + 64 * group - 1) / (64 * group)) * coord_cost[k] + o +
+                              200.0 * group;
+                    for (int r = 0; r < group; ++r) {
+                        FwdWave w = base(probs[k], lw, group);
+                        w.rank = (int16_t)r;
+                        w.nprob = 1;
+                        w.seg[0] = seg_of(probs[k]);
+                        it.waves.push_back(w);
+                    }
+                    items.push_back(it);
+                }
+            }
+        }
+    };
+    auto nwaves = [](const std::vector<Item>& items) {
+        size_t n = 0;
+        for (const Item& it : items) n += it.waves.size();
+        return n;
+    };
+    // smallest T (bisection on a log scale) whose waves fit
+    std::vector<Item> items;
+    const size_t cap = (size_t)std::max(1, sc.balanced) * (size_t)n_simd;
+    double lo = 1.0, hi = 1.0;
+    for (;;) {
+        build(hi, items);
+        if (nwaves(items) <= cap || hi > 1e12) break;
+        lo = hi;
+        hi *= 2.0;
+    }
+    for (int it = 0; it < 40 && hi > lo * 1.001; ++it) {
+        const double mid = std::sqrt(lo * hi);
+        build(mid, items);
+        if (nwaves(items) <= cap) hi = mid;
+        else lo = mid;
+    }
+    build(hi, items);
+    // workgroups: items longest first, first fit into 4-wave workgroups
+    std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
+    struct WG {
+        FwdWG desc;
+        int used = 0;
+        double cost[4] = {0, 0, 0, 0};
+    };
+    std::vector<WG> wgs;
+    std::vector<int> open;
+    for (const Item& it : items) {
+        const int w = (int)it.waves.size();
+        int target = -1;
+        for (int o : open)
+            if (4 - wgs[o].used >= w) { target = o; break; }
+        if (target < 0) {
+            WG e;
+            std::memset(&e.desc, 0, sizeof e.desc);
+            for (int i = 0; i < 4; ++i) {
+                e.desc.w[i].group = 1;
+                e.desc.w[i].lw = 6;
+                for (int j = 0; j < kWaveProbs; ++j) e.desc.w[i].seg[j].out_index = -1;
+            }
+            wgs.push_back(e);
+            target = (int)wgs.size() - 1;
+            open.push_back(target);
+        }
+        WG& g = wgs[target];
+        for (int r = 0; r < w; ++r) {
+            g.desc.w[g.used + r] = it.waves[r];
+            g.cost[g.used + r] = it.cost;
+        }
+        g.used += w;
+        if (g.used == 4) open.erase(std::find(open.begin(), open.end(), target));
+    }
+    // placement: workgroups longest first, each to the compute unit with the
+    // least load (its SIMDs' loads, the workgroup's costliest wave joining
+    // the least-loaded SIMD) among those with the fewest workgroups
+    std::vector<int> wg_order(wgs.size());
+    for (size_t i = 0; i < wgs.size(); ++i) wg_order[i] = (int)i;
+    auto wg_cost = [&](int i) { return wgs[i].cost[0] + wgs[i].cost[1] + wgs[i].cost[2] + wgs[i].cost[3]; };
+    std::stable_sort(wg_order.begin(), wg_order.end(), [&](int a, int b) { return wg_cost(a) > wg_cost(b); });
+    std::vector<std::array<double, 4>> simd(n_cu, std::array<double, 4>{0, 0, 0, 0});
+    std::vector<int> count(n_cu, 0);
+    std::vector<int> pos(wgs.size(), -1);
+    const int rounds = (int)((wgs.size() + n_cu - 1) / n_cu);
+    for (int i : wg_order) {
+        int best = -1;
+        double bl = 0.0;
+        for (int c = 0; c < n_cu; ++c) {
+            if (count[c] >= rounds) continue;
+            const double l = simd[c][0] + simd[c][1] + simd[c][2] + simd[c][3];
+            if (best < 0 || l < bl) { best = c; bl = l; }
+        }
+        std::array<double, 4> wc{wgs[i].cost[0], wgs[i].cost[1], wgs[i].cost[2], wgs[i].cost[3]};
+        std::sort(wc.begin(), wc.end(), std::greater<double>());
+        std::array<int, 4> idx{0, 1, 2, 3};
+        std::sort(idx.begin(), idx.end(), [&](int a, int b) { return simd[best][a] < simd[best][b]; });
+        for (int k = 0; k < 4; ++k) simd[best][idx[k]] += wc[k];
+        pos[i] = best + n_cu * count[best];
+        count[best]++;
+    }
+    int npos = 0;
+    for (int p : pos) npos = std::max(npos, p + 1);
+    std::vector<FwdWG> out((size_t)npos);
+    for (FwdWG& e : out) {
+        std::memset(&e, 0, sizeof e);
+        for (int i = 0; i < 4; ++i) {
+            e.w[i].group = 1;
+            e.w[i].lw = 6;
+            for (int j = 0; j < kWaveProbs; ++j) e.w[i].seg[j].out_index = -1;
+        }
+    }
+    for (size_t i = 0; i < wgs.size(); ++i) out[(size_t)pos[i]] = wgs[i].desc;
+    if (est_max_load) {
+        double m = 0.0;
+        for (auto& a : simd) m = std::max(m, std::max(std::max(a[0], a[1]), std::max(a[2], a[3])));
+        *est_max_load = m;
+    }
+    return out;
 }
 
 uint64_t macs_of(const DeltaTable& t)
@@ -774,6 +1000,7 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
     p->probs.resize(nr);
     p->unit_cost.resize(nr);
+    p->coord_cost.resize(nr);
     for (int k = 0; k < nr; ++k) {
         const int i = order[k];
         p->unit_cost[k] = cost[i] / (double)problems[i].d;
@@ -790,6 +1017,7 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
         r.off32 = o.second;
         r.out_index = i;
         r.waves = 0;
+        p->coord_cost[k] = fwd_coord_cost(r, ptab[i]->npairs, macs_of(*ptab[i]), precision);
         r.ws_off = (int64_t)p->ws_elems;
         p->ws_elems += (size_t)r.d * (size_t)(K > 0 ? K : 1);
     }
@@ -821,11 +1049,20 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
         int c = 0, g = 0, q = 0, cs = 0;
         const int nf = std::sscanf(fs, "%d,%d,%d,%d", &c, &g, &q, &cs);
         if (nf >= 2 && c >= 1 && c <= 64 && (g == 1 || g == 2 || g == 4)) {
+            p->sched.balanced = 0;
             p->sched.cpl = c;
             p->sched.gmax = g;
             p->sched.persistent = nf >= 3 && q == 1;
             p->sched.cost_scaled = nf >= 4 && cs == 1;
         }
+    }
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            p->n_cu = cus;
+        else
+            p->n_cu = 256;
     }
     // reverse sweep: one problem per wave slot, cost-threshold schedule
     std::vector<int> wv(nr);
@@ -871,9 +1108,12 @@ static sg_status plan_launch(sg_plan* p, const double* params, double* out, doub
 }
 
 // Re-pack the plan's forward workgroups for another schedule.
-static sg_status plan_repack(sg_plan* p, const FwdSched& sc)
+static sg_status plan_repack(sg_plan* p, const FwdSched& sc_in)
 {
-    std::vector<FwdWG> fwd = pack_forward(p->probs, p->unit_cost, sc);
+    FwdSched sc = sc_in;
+    if (sc.balanced > 0) sc.persistent = false;   // placement relies on hardware dispatch order
+    std::vector<FwdWG> fwd = sc.balanced > 0 ? pack_forward_balanced(p->probs, p->coord_cost, sc, p->n_cu, nullptr)
+                                             : pack_forward(p->probs, p->unit_cost, sc);
     if (fwd.size() > p->fwd_capacity) {
         hipFree(p->d_fwd);
         p->d_fwd = nullptr;
@@ -899,6 +1139,7 @@ static sg_status plan_repack(sg_plan* p, const FwdSched& sc)
     p->info.max_group = sc.gmax;
     p->info.persistent = p->sched.persistent ? 1 : 0;
     p->info.cost_scaled = sc.cost_scaled ? 1 : 0;
+    p->info.balanced = sc.balanced;
     return SG_OK;
 }
 
@@ -1113,6 +1354,7 @@ static void blocked_sync_info(sg_plan* p, bool graph)
     p->info.max_group = in->info.max_group;
     p->info.persistent = in->info.persistent;
     p->info.cost_scaled = in->info.cost_scaled;
+    p->info.balanced = in->info.balanced;
 }
 
 sg_status sg_plan_autotune(sg_plan* p, const double* params_dev, double* out_dev, void* stream)
@@ -1165,6 +1407,7 @@ sg_status sg_plan_autotune(sg_plan* p, const double* params_dev, double* out_dev
         for (int gq = 0; gq < 12; ++gq) {
             const int gm = gmaxs[gq % 3];
             FwdSched sc;
+            sc.balanced = 0;
             sc.cpl = c;
             sc.gmax = gm;
             sc.persistent = (gq / 3) % 2 == 1;
@@ -1186,6 +1429,25 @@ sg_status sg_plan_autotune(sg_plan* p, const double* params_dev, double* out_dev
             if (st != SG_OK) break;
         }
         if (st != SG_OK) break;
+    }
+    // balanced schedules: 1..4 equal-cost waves per SIMD
+    for (int m = 1; m <= 4 && st == SG_OK; ++m) {
+        FwdSched sc;
+        sc.balanced = m;
+        if ((st = plan_repack(p, sc)) != SG_OK) break;
+        destroy_graphs(p);
+        for (int g = 0; g < (stream ? 2 : 1); ++g) {
+            p->use_graph = g == 1;
+            if ((st = sg_plan_execute(p, params_dev, out_dev, nullptr, stream)) != SG_OK) break;
+            hipEventRecord(e0, s);
+            for (int r = 0; r < reps; ++r) sg_plan_execute(p, params_dev, out_dev, nullptr, stream);
+            hipEventRecord(e1, s);
+            hipError_t e = hipEventSynchronize(e1);
+            if (e != hipSuccess) { st = hip_fail(p->ctx, e, "autotune sync"); break; }
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best_ms) { best_ms = ms; best = sc; best_g = p->use_graph; }
+        }
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
@@ -1212,10 +1474,31 @@ sg_status sg_plan_set_schedule(sg_plan* p, int32_t coords_per_lane, int32_t max_
         return st;
     }
     FwdSched sc;
+    sc.balanced = 0;
     sc.cpl = coords_per_lane;
     sc.gmax = max_group;
     sc.cost_scaled = cost_scaled == 1;
     sc.persistent = persistent == 1;
+    destroy_graphs(p);
+    sg_status st = plan_repack(p, sc);
+    if (st != SG_OK) return st;
+    p->use_graph = graph == 1;
+    p->info.graph = graph;
+    return SG_OK;
+}
+
+sg_status sg_plan_set_schedule_balanced(sg_plan* p, int32_t waves_per_simd, int32_t graph)
+{
+    if (!p) return SG_ERR_INVALID_ARGUMENT;
+    if (waves_per_simd < 1 || waves_per_simd > 8 || (graph != 0 && graph != 1))
+        return fail(p->ctx, SG_ERR_INVALID_ARGUMENT, "schedule out of range");
+    if (p->blocked) {
+        sg_status st = sg_plan_set_schedule_balanced(p->blocked->inner, waves_per_simd, 0);
+        blocked_sync_info(p, graph == 1);
+        return st;
+    }
+    FwdSched sc;
+    sc.balanced = waves_per_simd;
     destroy_graphs(p);
     sg_status st = plan_repack(p, sc);
     if (st != SG_OK) return st;
@@ -1298,6 +1581,7 @@ sg_status sg_integrate(sg_context* ctx, const sg_problem* problem, int32_t preci
         pd.ws_off = 0;
         // one problem: 64 lanes on up to 4 waves, a few coordinates per lane
         FwdSched sc;
+        sc.balanced = 0;
         sc.cpl = 4;
         sc.gmax = 4;
         std::vector<FwdWG> fwd = pack_forward(pv, std::vector<double>(1, 1.0), sc);

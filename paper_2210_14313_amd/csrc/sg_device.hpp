@@ -213,6 +213,23 @@ __device__ __forceinline__ double signed_c2(double c)
     return FAM == FAM_EXP ? c * c : -(c * c);
 }
 
+// The FP32 series of a coordinate use z = c2s y^2 with c2s the per-coordinate
+// factor +-c^2 rounded once to FP32, i.e. every pair value of the coordinate
+// has its argument off by the same relative amount r = (c2 - c2s) / c2s.
+// With s(z) = z P(z), s(z (1 + r)) = s(z) (1 + r + r z P'(z)/P(z) + O(r^2)),
+// so scaling the coordinate's surpluses by 1 + r removes that error up to a
+// remainder of relative size |r| z / 12 <= 2^-24 / 12 (z <= 1 on this path).
+template <int FAM, int K>
+__device__ __forceinline__ void argument_correction(double c, float c2s, double (&del)[MAXK + 1])
+{
+    // |r| <= 2^-24, so a reciprocal good to a few FP32 units leaves r
+    // accurate far below the FP64 rounding of the surpluses
+    const double c2 = signed_c2<FAM>(c);
+    const double r = c2s != 0.0f ? (c2 - (double)c2s) * (double)__builtin_amdgcn_rcpf(c2s) : 0.0;
+#pragma unroll
+    for (int e = 1; e <= K; ++e) del[e] = fma(del[e], r, del[e]);
+}
+
 // Compensated FP32 accumulation of w*s with w = wh + wl: two-sum of the
 // rounded product into the running sum (its error goes to lo, exactly), and
 // the low weight part w_l*s added to lo.  Each product keeps its own
@@ -528,6 +545,7 @@ __device__ __forceinline__ void surplus32_const(const CoordParam& cp, double (&d
     });
 #pragma unroll
     for (int e = 0; e <= MAXK; ++e) del[e] = (double)hi[e] + (double)lo[e];
+    if constexpr (FAM != FAM_PEAK) argument_correction<FAM, K>(cp.p0, c2s, del);
     eps += (double)epsf;
 }
 
@@ -575,16 +593,21 @@ __device__ __forceinline__ void surplus32e_const(const CoordParam& cp, double (&
             }
         });
     });
+    if constexpr (FAM != FAM_PEAK) argument_correction<FAM, K>(cp.p0, c2s, del);
     eps += (double)epsf;
 }
 
 // ----------------------------------------------------------- merge state
-// Running polynomial a; for the error bound, m = sum_t sum_e |delta_t[e]| and
-// eps = sum_t sum_p sum_e |dW[e][p]| |s_p|; the affine partial sum ls and
-// sum |terms of ls|.
+// Running polynomial a and the affine partial sum ls (FP64); for the error
+// bound, m = sum_t sum_e |delta_t[e]|, eps = sum_t sum_p sum_e |dW[e][p]| |s_p|
+// and lsabs = sum |terms of ls|.  The bound's sums have non-negative terms
+// and are kept in FP32: a sum of n such terms rounded to nearest is at least
+// (1 - n 2^-24) times the exact sum, which the read-out compensates
+// (bound_sum_margin).
 struct Acc {
     double a[MAXK + 1];
-    double m, ls, lsabs, eps;
+    double ls;
+    float m, eps, lsabs;
 };
 
 template <int K>
@@ -592,7 +615,8 @@ __device__ __forceinline__ void acc_identity(Acc& x)
 {
 #pragma unroll
     for (int k = 0; k <= MAXK; ++k) x.a[k] = 0.0;
-    x.m = x.ls = x.lsabs = x.eps = 0.0;
+    x.ls = 0.0;
+    x.m = x.eps = x.lsabs = 0.0f;
 }
 
 template <int K>
@@ -602,22 +626,16 @@ __device__ __forceinline__ void merge(Acc& x, const Acc& y, bool want_bound)
     if (want_bound) {
         x.m += y.m;
         x.eps += y.eps;
+        x.lsabs += y.lsabs;
     }
     x.ls += y.ls;
-    x.lsabs += y.lsabs;
 }
 
-template <int K>
-__device__ __forceinline__ void shfl_acc(Acc& o, const Acc& x, int mask, bool want_bound)
+// Factor that makes an FP32 sum of at most n non-negative terms an upper
+// bound of the exact sum: 1 / (1 - n 2^-24) <= 1 + 2 n 2^-24 for n < 2^22.
+__device__ __forceinline__ double bound_sum_margin(int n)
 {
-#pragma unroll
-    for (int k = 1; k <= K; ++k) o.a[k] = __shfl_xor(x.a[k], mask);
-    if (want_bound) {
-        o.m = __shfl_xor(x.m, mask);
-        o.eps = __shfl_xor(x.eps, mask);
-    }
-    o.ls = __shfl_xor(x.ls, mask);
-    o.lsabs = __shfl_xor(x.lsabs, mask);
+    return 1.0 + (double)(2 * n + 2) * 5.9604644775390625e-08;
 }
 
 // DPP moves of a double (two 32-bit halves).  Lanes whose source is outside
@@ -640,6 +658,16 @@ __device__ __forceinline__ double dpp_f64(double v, double fill)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// DPP move of a float; lanes without a source receive 0.0f (as dpp_f64).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_f32(float v)
+{
+    if constexpr (ROW_MASK == 0xF)
+        return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+    else
+        return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+}
+
 // One reduction step: x <- x (*) (state moved by the DPP pattern); lanes
 // without a source multiply by the identity.
 template <int K, int CTRL, int ROW_MASK>
@@ -649,11 +677,11 @@ __device__ __forceinline__ void dpp_step(Acc& x, bool want_bound)
 #pragma unroll
     for (int k = 1; k <= K; ++k) o.a[k] = dpp_f64<CTRL, ROW_MASK>(x.a[k], 0.0);
     if (want_bound) {
-        o.m = dpp_f64<CTRL, ROW_MASK>(x.m, 0.0);
-        o.eps = dpp_f64<CTRL, ROW_MASK>(x.eps, 0.0);
+        o.m = dpp_f32<CTRL, ROW_MASK>(x.m);
+        o.eps = dpp_f32<CTRL, ROW_MASK>(x.eps);
+        o.lsabs = dpp_f32<CTRL, ROW_MASK>(x.lsabs);
     }
     o.ls = dpp_f64<CTRL, ROW_MASK>(x.ls, 0.0);
-    o.lsabs = dpp_f64<CTRL, ROW_MASK>(x.lsabs, 0.0);
     merge<K>(x, o, want_bound);
 }
 
@@ -685,10 +713,10 @@ __device__ __forceinline__ void acc_store(const Acc& x, double* s)
 {
 #pragma unroll
     for (int k = 1; k <= K; ++k) s[k - 1] = x.a[k];
-    s[MAXK] = x.m;
+    s[MAXK] = (double)x.m;
     s[MAXK + 1] = x.ls;
-    s[MAXK + 2] = x.lsabs;
-    s[MAXK + 3] = x.eps;
+    s[MAXK + 2] = (double)x.lsabs;
+    s[MAXK + 3] = (double)x.eps;
 }
 
 template <int K>
@@ -696,20 +724,27 @@ __device__ __forceinline__ void acc_load(Acc& x, const double* s)
 {
 #pragma unroll
     for (int k = 1; k <= K; ++k) x.a[k] = s[k - 1];
-    x.m = s[MAXK];
+    x.m = (float)s[MAXK];
     x.ls = s[MAXK + 1];
-    x.lsabs = s[MAXK + 2];
-    x.eps = s[MAXK + 3];
+    x.lsabs = (float)s[MAXK + 2];
+    x.eps = (float)s[MAXK + 3];
 }
 
 // Upper bound on every |[z^b] prod_{t in T} delta_t| (any subset T) summed
 // over b <= K: the product of the absolute-value polynomials has
 // non-negative coefficients, 1 + x <= exp(x) coefficient-wise, and a sum of
 // non-negative coefficients is at most the value at z = 1, so the bound is
-// exp(m) with m = sum_t sum_e |delta_t[e]|.
+// exp(m) with m = sum_t sum_e |delta_t[e]| (m given as an upper bound).
+// Formed with the hardware base-2 exponential in FP32: e^m = 2^(m log2 e);
+// the product m log2 e is raised by 2^-20 relative (covering the rounding of
+// the constant, of the product and of m's conversion) plus 2^-20 absolute,
+// and the result by 2^-16 relative (covering the instruction's error of at
+// most a few units in the last place); beyond 2^126 the bound is +inf.
 __device__ __forceinline__ double abs_product_bound(double m)
 {
-    return exp(m) * (1.0 + 1e-13);
+    const float v = (float)m * 1.44269504f * (1.0f + 9.5367431640625e-07f) + 9.5367431640625e-07f;
+    if (!(v < 126.0f)) return __builtin_huge_val();
+    return (double)__builtin_amdgcn_exp2f(v) * (1.0 + 1.52587890625e-05);
 }
 
 // ------------------------------------------------------------ read-out
@@ -724,12 +759,16 @@ __device__ void readout(const Acc& x, int d, int out_index, const double* __rest
 #pragma unroll
     for (int k = K; k >= 1; --k) s += x.a[k];
     s += 1.0;
-    const double sabs = want_bound ? abs_product_bound(x.m) : 0.0;
+    // the bound's FP32 sums (each term rounded once to FP32, then added:
+    // at most 2 (d + depth) roundings) raised to upper bounds
+    const double marg = bound_sum_margin(d + depth + 4);
+    const double m_up = (double)x.m * marg, eps_up = (double)x.eps * marg, lsabs_up = (double)x.lsabs * marg;
+    const double sabs = want_bound ? abs_product_bound(m_up) : 0.0;
     const double u64 = 1.1102230246251565e-16;
     // rounding of the affine sum: d - 1 additions, plus up to 3 roundings
     // per term where a term is not exact (product-peak log D, gaussian c hv^2)
     const double ls_err =
-        u64 * (double)(FAM == FAM_EXP || FAM == FAM_OSC ? d : d + 3) * x.lsabs;
+        u64 * (double)(FAM == FAM_EXP || FAM == FAM_OSC ? d : d + 3) * lsabs_up;
     // relative error of one surplus term: pair value (8 roundings) plus the
     // within-rule sum (FP64: a plain FMA chain over at most rl_pairs terms;
     // FP32 compensated: the FMA chain of the term's block, at most
@@ -748,14 +787,14 @@ __device__ void readout(const Acc& x, int d, int out_index, const double* __rest
         const double phase = 2.0 * 3.141592653589793 * prm[0] + x.ls;
         Q = cos(phase) * s;
         if (want_bound) {
-            const double dsum = sabs * (rel * x.eps + (K + 2) * levels * u64);
+            const double dsum = sabs * (rel * eps_up + (K + 2) * levels * u64);
             bound[out_index] = dsum + fabs(s) * (ls_err + u64 * (fabs(phase) + 4.0)) + fabs(Q) * 4.0 * u64;
         }
     } else {
         const double A = exp(FAM == FAM_PEAK ? -x.ls : x.ls);
         Q = A * s;
         if (want_bound) {
-            const double dsum = sabs * (rel * x.eps + (K + 2) * levels * u64);
+            const double dsum = sabs * (rel * eps_up + (K + 2) * levels * u64);
             bound[out_index] = A * dsum + fabs(Q) * (ls_err + 4.0 * u64 + u64 * fabs(x.ls));
         }
     }
@@ -894,11 +933,11 @@ __device__ __forceinline__ void wave_sweep(const WaveInfo& wi, const double* __r
             double mt = 0.0;
 #pragma unroll
             for (int k = 1; k <= K; ++k) mt += fabs(del[k]);
-            x.m += mt;
-            x.eps += eps_t;
+            x.m += (float)mt;
+            x.eps += (float)eps_t;
+            x.lsabs += (float)fabs(lterm);
         }
         x.ls += lterm;
-        x.lsabs += fabs(lterm);
         t = tn;
     }
     wave_reduce_seg<K>(x, wi.lw, want_bound);

@@ -1,0 +1,6 @@
+// Forward-sweep kernel, precision mode 1 (FP32 values, two-sum compensated FP32 sums), excess budgets K <= 6
+#include "sg_fwd_inst.hpp"
+
+namespace sg {
+SG_FORWARD_INSTANCE(1, 6, false)
+}  // namespace sg

@@ -1,0 +1,6 @@
+// Forward-sweep kernel, precision mode 2 (FP32 values, FP64 sums), excess budgets K <= 4
+#include "sg_fwd_inst.hpp"
+
+namespace sg {
+SG_FORWARD_INSTANCE(2, 4, false)
+}  // namespace sg

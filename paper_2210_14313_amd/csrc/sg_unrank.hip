@@ -61,36 +61,58 @@ k_unrank(int d, int q, uint64_t rank0, uint64_t count, int max_nnz, const uint64
 
 }  // namespace
 
-int launch_forward_p0(int, int, const FwdWG*, unsigned int*, int, const double*, const float*, const double*,
-                      double*, double*, void*);
-int launch_forward_p1(int, int, const FwdWG*, unsigned int*, int, const double*, const float*, const double*,
-                      double*, double*, void*);
-int launch_forward_p2(int, int, const FwdWG*, unsigned int*, int, const double*, const float*, const double*,
-                      double*, double*, void*);
-int forward_capacity_p0(int);
-int forward_capacity_p1(int);
-int forward_capacity_p2(int);
+template <int P, int KM, bool G>
+int launch_forward_inst(int, const FwdWG*, unsigned int*, int, const double*, const float*, const double*, double*,
+                        double*, void*);
+template <int P, int KM, bool G>
+int forward_capacity_inst();
 int launch_adjoint_p0(bool, int, const WGDesc*, const ProbDev*, const double*, const float*, const double*,
                       const double*, double*, double*, void*);
 int launch_adjoint_p1(bool, int, const WGDesc*, const ProbDev*, const double*, const float*, const double*,
                       const double*, double*, double*, void*);
+
+// The instantiation for a precision mode and the plan's launch class: the
+// smallest K class covering the plan's problems (fewer registers, more waves
+// per SIMD), or, for a plan holding gaussian problems (kmax = kKmaxGauss),
+// the K <= 8 kernel built with that family.
+template <int P>
+static int launch_forward_p(int kmax, int nwg, const FwdWG* wgs, unsigned int* queue, int qgrid, const double* pool64,
+                            const float* pool32, const double* params, double* out, double* bound, void* stream)
+{
+    if (kmax <= 4)
+        return launch_forward_inst<P, 4, false>(nwg, wgs, queue, qgrid, pool64, pool32, params, out, bound, stream);
+    if (kmax <= 6)
+        return launch_forward_inst<P, 6, false>(nwg, wgs, queue, qgrid, pool64, pool32, params, out, bound, stream);
+    if (kmax <= kMaxK)
+        return launch_forward_inst<P, 8, false>(nwg, wgs, queue, qgrid, pool64, pool32, params, out, bound, stream);
+    return launch_forward_inst<P, 8, true>(nwg, wgs, queue, qgrid, pool64, pool32, params, out, bound, stream);
+}
+
+template <int P>
+static int forward_capacity_p(int kmax)
+{
+    return kmax <= 4 ? forward_capacity_inst<P, 4, false>()
+           : kmax <= 6 ? forward_capacity_inst<P, 6, false>()
+           : kmax <= kMaxK ? forward_capacity_inst<P, 8, false>()
+                           : forward_capacity_inst<P, 8, true>();
+}
 
 int launch_forward(int precision, int kmax, int nwg, const FwdWG* wgs, unsigned int* queue, int qgrid,
                    const double* pool64, const float* pool32, const double* params, double* out, double* bound,
                    void* stream)
 {
     if (precision == SG_PREC_FP64)
-        return launch_forward_p0(kmax, nwg, wgs, queue, qgrid, pool64, pool32, params, out, bound, stream);
+        return launch_forward_p<0>(kmax, nwg, wgs, queue, qgrid, pool64, pool32, params, out, bound, stream);
     if (precision == SG_PREC_FP32_COMPENSATED)
-        return launch_forward_p1(kmax, nwg, wgs, queue, qgrid, pool64, pool32, params, out, bound, stream);
-    return launch_forward_p2(kmax, nwg, wgs, queue, qgrid, pool64, pool32, params, out, bound, stream);
+        return launch_forward_p<1>(kmax, nwg, wgs, queue, qgrid, pool64, pool32, params, out, bound, stream);
+    return launch_forward_p<2>(kmax, nwg, wgs, queue, qgrid, pool64, pool32, params, out, bound, stream);
 }
 
 int forward_capacity(int precision, int kmax)
 {
-    if (precision == SG_PREC_FP64) return forward_capacity_p0(kmax);
-    if (precision == SG_PREC_FP32_COMPENSATED) return forward_capacity_p1(kmax);
-    return forward_capacity_p2(kmax);
+    if (precision == SG_PREC_FP64) return forward_capacity_p<0>(kmax);
+    if (precision == SG_PREC_FP32_COMPENSATED) return forward_capacity_p<1>(kmax);
+    return forward_capacity_p<2>(kmax);
 }
 
 int launch_adjoint(int precision, bool gauss, int nwg, const WGDesc* wgs, const ProbDev* probs,

@@ -43,7 +43,7 @@ class SgPlanInfo(ctypes.Structure):
                 ("merge_flops", ctypes.c_uint64), ("block_threads", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int32), ("coords_per_lane", ctypes.c_int32),
                 ("max_group", ctypes.c_int32), ("graph", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("cost_scaled", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("cost_scaled", ctypes.c_int32), ("balanced", ctypes.c_int32)]
 
 
 _lib = None
@@ -51,7 +51,7 @@ _lib = None
 EXPORTS = ["sg_context_create", "sg_context_destroy", "sg_status_string", "sg_last_error", "sg_counts",
            "sg_rule_table", "sg_coefficient", "sg_unrank", "sg_unrank_device", "sg_plan_create",
            "sg_plan_execute", "sg_plan_execute_grad", "sg_plan_get_info", "sg_plan_autotune",
-           "sg_plan_set_schedule", "sg_plan_destroy", "sg_integrate", "sg_integrate_points",
+           "sg_plan_set_schedule", "sg_plan_set_schedule_balanced", "sg_plan_destroy", "sg_integrate", "sg_integrate_points",
            "sg_plan_create_blocked"]
 
 
@@ -82,6 +82,7 @@ def lib():
         "sg_plan_get_info": ([vp, P(SgPlanInfo)], i32),
         "sg_plan_autotune": ([vp, vp, vp, vp], i32),
         "sg_plan_set_schedule": ([vp, i32, i32, i32, i32, i32], i32),
+        "sg_plan_set_schedule_balanced": ([vp, i32, i32], i32),
         "sg_plan_destroy": ([vp], i32),
         "sg_integrate": ([vp, P(SgProblem), i32, vp, vp, vp, vp], i32),
         "sg_integrate_points": ([vp, P(SgProblem), vp, vp, vp, u64, vp], i32),
@@ -184,6 +185,35 @@ def make_problems(problems) -> ctypes.Array:
     return arr
 
 
+# Parameters of one integrand by family (include/sgmdi.h, sg_family).
+_PARAMS_PER_FAMILY = {"exp_sum": (1, 0), "oscillatory": (1, 1), "product_peak": (2, 0), "corner_peak": (1, 0),
+                      "gaussian": (2, 0), "oscillatory_quadratic": (2, 1)}
+
+
+def n_params(family: str, d: int) -> int:
+    a, b = _PARAMS_PER_FAMILY[family]
+    return a * d + b
+
+
+def param_extent(problems: Sequence) -> int:
+    """Elements of the parameter array the problems read: the largest
+    param_offset + n_params(family, d)."""
+    return max((int(p.param_offset) + n_params(p.family, p.d) for p in problems), default=0)
+
+
+def check_tensor(name: str, t, min_numel: int):
+    """The C ABI takes raw pointers it cannot bound: every tensor handed to it
+    must be a contiguous float64 device tensor of at least min_numel
+    elements (ValueError otherwise, before anything is launched)."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float64 device tensor")
+    if t.numel() < min_numel:
+        raise ValueError(f"{name} has {t.numel()} elements, needs >= {min_numel}")
+
+
 class Plan:
     """A compiled batch: sg_plan_create / execute / execute_grad / destroy."""
 
@@ -197,6 +227,7 @@ class Plan:
         self._arr = make_problems(problems)
         self.handle = ctypes.c_void_p()
         self.precision = precision
+        self.param_extent = param_extent(self.problems)
         self.block_dims = int(block_dims)
         if self.block_dims > 0:
             _check(lib().sg_plan_create_blocked(self.ctx.handle, self._arr, self.n, PRECISIONS[precision],
@@ -213,17 +244,13 @@ class Plan:
 
     def execute(self, params, out=None, bound=None, stream=None):
         import torch
-        f64 = torch.float64
-        if params.dtype != f64 or not params.is_cuda or not params.is_contiguous():
-            raise ValueError("params must be a contiguous float64 device tensor")
+        check_tensor("params", params, self.param_extent)
         if out is None:
-            out = torch.empty(self.n, dtype=f64, device=params.device)
-        elif out.dtype != f64 or out.numel() < self.n or not out.is_contiguous():
-            raise ValueError(f"out must be a contiguous float64 tensor of >= {self.n} elements")
+            out = torch.empty(self.n, dtype=torch.float64, device=params.device)
+        check_tensor("out", out, self.n)
         bptr = None
         if bound is not None:
-            if bound.dtype != f64 or bound.numel() < self.n or not bound.is_contiguous():
-                raise ValueError(f"bound must be a contiguous float64 tensor of >= {self.n} elements")
+            check_tensor("bound", bound, self.n)
             bptr = bound.data_ptr()
         st = self._exec(self.handle, params.data_ptr(), out.data_ptr(), bptr, _stream_ptr(stream))
         if st != 0:
@@ -239,19 +266,28 @@ class Plan:
 
     def execute_grad(self, params, grad_out, grad_params=None, stream=None):
         import torch
+        check_tensor("params", params, self.param_extent)
+        check_tensor("grad_out", grad_out, self.n)
         if grad_params is None:
             grad_params = torch.zeros_like(params)
+        check_tensor("grad_params", grad_params, self.param_extent)
         _check(lib().sg_plan_execute_grad(self.handle, _ptr(params), _ptr(grad_out), _ptr(grad_params),
                                           _stream_ptr(stream)), self.ctx.handle)
         return grad_params
 
     def autotune(self, params, out, stream=None):
+        check_tensor("params", params, self.param_extent)
+        check_tensor("out", out, self.n)
         _check(lib().sg_plan_autotune(self.handle, _ptr(params), _ptr(out), _stream_ptr(stream)), self.ctx.handle)
 
     def set_schedule(self, coords_per_lane: int, max_group: int, graph: bool = False, persistent: bool = False,
                      cost_scaled: bool = False):
         _check(lib().sg_plan_set_schedule(self.handle, coords_per_lane, max_group, int(cost_scaled), int(persistent),
                                           int(graph)), self.ctx.handle)
+
+    def set_balanced(self, waves_per_simd: int, graph: bool = False):
+        """Balanced forward schedule (sg_plan_set_schedule_balanced)."""
+        _check(lib().sg_plan_set_schedule_balanced(self.handle, int(waves_per_simd), int(graph)), self.ctx.handle)
 
     def close(self):
         if self.handle:
@@ -269,10 +305,14 @@ def integrate_one(problem, params, precision: str = "fp64", out=None, bound=None
                   ctx: Optional[Context] = None):
     """Plain single-integrand path (one launch, no plan, no graph)."""
     import torch
-    ctx = ctx or default_context()
-    pr = SgProblem(problem.d, problem.q, RULES[problem.rule], FAMILIES[problem.family], 0)
+    check_tensor("params", params, n_params(problem.family, problem.d))
     if out is None:
         out = torch.empty(1, dtype=torch.float64, device=params.device)
+    check_tensor("out", out, 1)
+    if bound is not None:
+        check_tensor("bound", bound, 1)
+    ctx = ctx or default_context()
+    pr = SgProblem(problem.d, problem.q, RULES[problem.rule], FAMILIES[problem.family], 0)
     _check(lib().sg_integrate(ctx.handle, ctypes.byref(pr), PRECISIONS[precision], _ptr(params), _ptr(out),
                               _ptr(bound), _stream_ptr(stream)), ctx.handle)
     return out
@@ -282,10 +322,14 @@ def integrate_points(problem, params, out=None, bound=None, max_points: int = 0,
                      ctx: Optional[Context] = None):
     """Literal point-by-point path (sg_integrate_points): one integrand, FP64."""
     import torch
-    ctx = ctx or default_context()
-    pr = SgProblem(problem.d, problem.q, RULES[problem.rule], FAMILIES[problem.family], 0)
+    check_tensor("params", params, n_params(problem.family, problem.d))
     if out is None:
         out = torch.empty(1, dtype=torch.float64, device=params.device)
+    check_tensor("out", out, 1)
+    if bound is not None:
+        check_tensor("bound", bound, 1)
+    ctx = ctx or default_context()
+    pr = SgProblem(problem.d, problem.q, RULES[problem.rule], FAMILIES[problem.family], 0)
     _check(lib().sg_integrate_points(ctx.handle, ctypes.byref(pr), _ptr(params), _ptr(out), _ptr(bound),
                                      max_points, _stream_ptr(stream)), ctx.handle)
     return out

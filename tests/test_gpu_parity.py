@@ -371,3 +371,55 @@ def test_persistent_queue_in_graph_replays(api, orc):
             got = out.cpu().numpy()
             assert np.max(np.abs(got - ref) / _scale(b, ref)) <= tol, (prec, rep)
         plan.close()
+
+
+def test_balanced_schedule(api, orc):
+    """The balanced schedule (equal-cost waves, workgroups placed for equal
+    per-CU load) on mixed batches: every result against the oracle and
+    within its bound, for 1..4 waves per SIMD, in graph replays, on the
+    4096 batch in every precision mode, and its rejections."""
+    import torch
+    from paper_2210_14313_amd import native, workloads as W
+    b = W.random_small(13, 60, d_range=(1, 600), k_range=(0, 8), rules=W.ALL_RULES,
+                       families=("exp_sum", "oscillatory", "product_peak", "gaussian"))
+    params = api.params_tensor(b)
+    ref = _fact_ref(orc, b)
+    say("case balanced schedule small")
+    plan = native.Plan(b.problems, "fp64")
+    for bad in ((0, 0), (9, 0), (2, 2)):
+        with pytest.raises(native.SgError) as e:
+            plan.set_balanced(bad[0], graph=bool(bad[1]) if bad[1] < 2 else 2)
+        assert e.value.status == 1
+    for m in (1, 2, 3, 4):
+        plan.set_balanced(m)
+        inf = plan.info()
+        assert inf["balanced"] == m and inf["persistent"] == 0
+        out = torch.empty(len(b), dtype=torch.float64, device="cuda")
+        bnd = torch.empty_like(out)
+        plan.execute(params, out, bnd)
+        got, bd = out.cpu().numpy(), bnd.cpu().numpy()
+        assert np.max(np.abs(got - ref) / _scale(b, ref)) <= 1e-12, m
+        assert np.all(np.abs(got - ref) <= bd), m
+    plan.close()
+    big = W.batched_uneven()
+    bparams = api.params_tensor(big)
+    bref = _fact_ref(orc, big)
+    bscale = _scale(big, bref)
+    s = torch.cuda.Stream()
+    for prec, tol in (("fp64", 1e-12), ("fp32c", 1e-7), ("fp32e", 1e-7)):
+        say("case balanced schedule batched_uneven", prec)
+        plan = native.Plan(big.problems, prec)
+        plan.set_balanced(2, graph=True)
+        eager = plan.execute(bparams).clone()
+        out = torch.empty(len(big), dtype=torch.float64, device="cuda")
+        bnd = torch.empty_like(out)
+        for rep in range(3):
+            out.fill_(float("nan"))
+            s.wait_stream(torch.cuda.current_stream())
+            plan.execute(bparams, out, bnd, stream=s)
+            s.synchronize()
+            assert torch.equal(out, eager), (prec, rep)
+        got, bd = out.cpu().numpy(), bnd.cpu().numpy()
+        assert np.max(np.abs(got - bref) / bscale) <= tol, prec
+        assert np.all(np.abs(got - bref) <= bd), prec
+        plan.close()
