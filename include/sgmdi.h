@@ -351,10 +351,18 @@ sg_status sg_integrate_points(sg_context *ctx, const sg_problem *problem, const 
 /* Plain, plan-free path: one integrand, one launch, no graph, no batching.
  * Same arguments as one problem of a plan (param_offset is ignored: params_dev
  * points at this integrand's parameters).  out_dev/bound_dev: one float64
- * each (bound may be NULL).  Also takes OSCILLATORY_QUADRATIC, computed in
- * FP64 whatever the precision mode: the sweep of Section 3 with the complex
- * surpluses of e^{i a (x - u)^2} and the bound of the real sweep (complex
- * moduli in place of absolute values). */
+ * each (bound may be NULL).  The launch splits the integrand's coordinates
+ * over ceil(d / 256) workgroups (at most 1024) of 256 lanes, one coordinate
+ * per lane and pass; each workgroup reduces its chunk to a partial truncated
+ * product, and the last workgroup to finish joins the partials in a fixed
+ * order (deterministic) and reads out the value and bound (the associative
+ * product of Section 3, (3.9)-(3.11), split by chunks).  The partials use a
+ * scratch buffer the context allocates on the first call with d > 256
+ * (about 160 KiB, kept until the context is destroyed); calls on one
+ * context must not overlap in time.  Also takes OSCILLATORY_QUADRATIC,
+ * computed in FP64 whatever the precision mode: the sweep of Section 3
+ * with the complex surpluses of e^{i a (x - u)^2} and the bound of the real
+ * sweep (complex moduli in place of absolute values). */
 sg_status sg_integrate(sg_context *ctx, const sg_problem *problem, int32_t precision,
                        const double *params_dev, double *out_dev, double *bound_dev, void *stream);
 

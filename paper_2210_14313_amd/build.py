@@ -17,7 +17,7 @@ PEAKS_LIB = os.path.join(PKG, "libsgpeaks.so")
 PEAKS_SOURCE = "sg_peaks.hip"
 
 FORWARD_UNITS = [f"sg_fwd_p{p}_{k}.hip" for p in (0, 1, 2) for k in ("k4", "k6", "k8", "g8")]
-SOURCES = FORWARD_UNITS + ["sg_adj0.hip", "sg_adj1.hip", "sg_unrank.hip", "sg_points.hip",
+SOURCES = FORWARD_UNITS + ["sg_one_p0.hip", "sg_one_p1.hip", "sg_one_p2.hip", "sg_adj0.hip", "sg_adj1.hip", "sg_unrank.hip", "sg_points.hip",
            "sg_blocked.hip", "sg_oscq.hip", "sg_rules.cpp", "sg_counts.cpp", "sg_api.cpp"]
 
 # Packed FP32 instructions are disabled for every device pass; contraction of
@@ -60,17 +60,18 @@ def generate_tables(objdir: str, verbose: bool = False) -> None:
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("compiling gen_tables failed")
-    r = subprocess.run([exe], capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stderr)
-        raise RuntimeError("gen_tables failed")
-    dst = os.path.join(objdir, "sg_tables.inc")
-    if os.path.exists(dst) and open(dst).read() == r.stdout:
-        return   # unchanged: keep its timestamp
-    tmp = dst + ".tmp"
-    with open(tmp, "w") as f:
-        f.write(r.stdout)
-    os.replace(tmp, dst)
+    for args, name in (([], "sg_tables.inc"), (["device"], "sg_tables_dev.inc")):
+        r = subprocess.run([exe] + args, capture_output=True, text=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stderr)
+            raise RuntimeError("gen_tables failed")
+        dst = os.path.join(objdir, name)
+        if os.path.exists(dst) and open(dst).read() == r.stdout:
+            continue   # unchanged: keep its timestamp
+        tmp = dst + ".tmp"
+        with open(tmp, "w") as f:
+            f.write(r.stdout)
+        os.replace(tmp, dst)
 
 
 def build(verbose: bool = False, extra_flags=None, incremental: bool = False) -> str:
@@ -84,6 +85,7 @@ def build(verbose: bool = False, extra_flags=None, incremental: bool = False) ->
     headers = [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith((".hpp", ".h"))]
     headers += [os.path.join(INCLUDE, h) for h in os.listdir(INCLUDE)]
     headers.append(os.path.join(objdir, "sg_tables.inc"))
+    headers.append(os.path.join(objdir, "sg_tables_dev.inc"))
 
     peaks_header = os.path.join(INCLUDE, "sgpeaks.h")
 

@@ -22,13 +22,6 @@ using namespace sg;
 
 namespace {
 
-struct PlainEntry {
-    FwdWG* fwd = nullptr;
-    int nfwg = 0;
-    double* pool64 = nullptr;
-    float* pool32 = nullptr;
-};
-
 // 1-D nodes (x - 1/2) and weights of the levels 1..K+1 of one rule, on the
 // device, for the point-by-point path.
 struct PointsTable {
@@ -72,7 +65,7 @@ struct sg_context {
     std::map<std::pair<int, int>, std::unique_ptr<DeltaTable>> tables;
     std::map<std::pair<int, int>, std::unique_ptr<Records>> records;
     std::map<std::string, std::pair<FwdSched, bool>> tuned;   // plan shape -> (schedule, graph)
-    std::map<std::tuple<int, int, int, int>, PlainEntry> plain;
+    double* one_ws = nullptr;        // scratch of the plan-free split launches (sg_integrate), counter zero
     std::map<std::pair<int, int>, uint64_t*> unrank_tables;
     std::map<std::pair<int, int>, PointsTable> points_tables;   // (rule, K) -> 1-D nodes of levels 1..K+1
     double* points_ws = nullptr;                                // per-wave partial sums of the point path
@@ -704,11 +697,7 @@ sg_status sg_context_create(sg_context** ctx)
 sg_status sg_context_destroy(sg_context* ctx)
 {
     if (!ctx) return SG_OK;
-    for (auto& kv : ctx->plain) {
-        hipFree(kv.second.fwd);
-        hipFree(kv.second.pool64);
-        hipFree(kv.second.pool32);
-    }
+    hipFree(ctx->one_ws);
     for (auto& kv : ctx->unrank_tables) hipFree(kv.second);
     for (auto& kv : ctx->points_tables) {
         hipFree(kv.second.y);
@@ -1535,67 +1524,42 @@ sg_status sg_plan_destroy(sg_plan* p)
     return SG_OK;
 }
 
+// Arguments of the plan-free path.
+static sg_status check_one(sg_context* ctx, const sg_problem* problem, int32_t precision, const double* params_dev,
+                           const double* out_dev)
+{
+    if (!problem || !params_dev || !out_dev) return fail(ctx, SG_ERR_INVALID_ARGUMENT, "NULL argument");
+    if (precision != SG_PREC_FP64 && precision != SG_PREC_FP32_COMPENSATED && precision != SG_PREC_FP32_FP64_SUM)
+        return fail(ctx, SG_ERR_INVALID_ARGUMENT, "unknown precision");
+    return validate_problem(ctx, *problem, 0, problem->family == SG_FAMILY_OSCILLATORY_QUADRATIC);
+}
+
 sg_status sg_integrate(sg_context* ctx, const sg_problem* problem, int32_t precision, const double* params_dev,
                        double* out_dev, double* bound_dev, void* stream)
 {
     if (!ctx) return SG_ERR_INVALID_ARGUMENT;
-    if (!problem || !params_dev || !out_dev) return fail(ctx, SG_ERR_INVALID_ARGUMENT, "NULL argument");
-    if (precision != SG_PREC_FP64 && precision != SG_PREC_FP32_COMPENSATED && precision != SG_PREC_FP32_FP64_SUM)
-        return fail(ctx, SG_ERR_INVALID_ARGUMENT, "unknown precision");
-    // the oscillatory quadratic (complex surpluses) has a sweep of its own,
-    // in FP64 whatever the precision mode (as in plans)
-    const bool oscq = problem->family == SG_FAMILY_OSCILLATORY_QUADRATIC;
-    sg_status st = validate_problem(ctx, *problem, 0, oscq);
+    sg_status st = check_one(ctx, problem, precision, params_dev, out_dev);
     if (st != SG_OK) return st;
-    const int K = problem->q - problem->d;
-    if (oscq) {
-        auto key = std::make_tuple(problem->rule, K, problem->family, 0);
-        auto it = ctx->plain.find(key);
-        if (it == ctx->plain.end()) {
-            const Records* r = get_records(ctx, problem->rule, K, st);
-            if (!r) return st;
-            PlainEntry pe;
-            if ((st = upload(ctx, &pe.pool64, r->r64.data(), r->r64.size())) != SG_OK) return st;
-            it = ctx->plain.emplace(key, pe).first;
+    const int d = problem->d, K = problem->q - problem->d;
+    const int G = one_workgroups(d);
+    if (G > 1 && !ctx->one_ws) {
+        // the split launches' scratch: allocated once per context, counter
+        // zeroed once; every launch leaves it at zero
+        const size_t words = (size_t)kOneHead + (size_t)kOneMaxG * (size_t)std::max(kOneWords, kOscqWords);
+        hipError_t e = hipMalloc((void**)&ctx->one_ws, words * sizeof(double));
+        if (e != hipSuccess) {
+            ctx->one_ws = nullptr;
+            return fail(ctx, SG_ERR_OUT_OF_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(e));
         }
-        const int rc = launch_oscq(problem->d, K, problem->rule, it->second.pool64, params_dev, out_dev, bound_dev,
-                                   stream);
-        if (rc != 0) return hip_fail(ctx, (hipError_t)rc, "oscillatory-quadratic launch");
-        return SG_OK;
+        e = hipMemset(ctx->one_ws, 0, words * sizeof(double));
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipMemset");
     }
-    auto key = std::make_tuple(problem->rule, K, problem->family, problem->d);
-    auto it = ctx->plain.find(key);
-    if (it == ctx->plain.end()) {
-        const Records* r = get_records(ctx, problem->rule, K, st);
-        if (!r) return st;
-        std::vector<ProbDev> pv(1);
-        ProbDev& pd = pv[0];
-        pd.d = problem->d;
-        pd.K = K;
-        pd.family = problem->family;
-        pd.rule = problem->rule;
-        pd.param_offset = 0;
-        pd.off64 = 0;
-        pd.off32 = 0;
-        pd.out_index = 0;
-        pd.ws_off = 0;
-        // one problem: 64 lanes on up to 4 waves, a few coordinates per lane
-        FwdSched sc;
-        sc.balanced = 0;
-        sc.cpl = 4;
-        sc.gmax = 4;
-        std::vector<FwdWG> fwd = pack_forward(pv, std::vector<double>(1, 1.0), sc);
-        PlainEntry pe;
-        pe.nfwg = (int)fwd.size();
-        if ((st = upload(ctx, &pe.fwd, fwd.data(), fwd.size())) != SG_OK) return st;
-        if ((st = upload(ctx, &pe.pool64, r->r64.data(), r->r64.size())) != SG_OK) return st;
-        if ((st = upload(ctx, &pe.pool32, r->r32.data(), r->r32.size())) != SG_OK) return st;
-        it = ctx->plain.emplace(key, pe).first;
-    }
-    const int rc = launch_forward(precision, problem->family == SG_FAMILY_GAUSSIAN ? kKmaxGauss : K,
-                                  it->second.nfwg, it->second.fwd, nullptr, 0, it->second.pool64,
-                                  it->second.pool32, params_dev, out_dev, bound_dev, stream);
-    if (rc != 0) return hip_fail(ctx, (hipError_t)rc, "forward launch");
+    const int rc = problem->family == SG_FAMILY_OSCILLATORY_QUADRATIC
+                       ? launch_oscq(d, K, problem->rule, G, nullptr, params_dev, out_dev, bound_dev, ctx->one_ws,
+                                     stream)
+                       : launch_one(precision, d, K, problem->rule, problem->family, G, params_dev, out_dev,
+                                    bound_dev, ctx->one_ws, stream);
+    if (rc != 0) return hip_fail(ctx, (hipError_t)rc, "plan-free launch");
     return SG_OK;
 }
 

@@ -173,6 +173,23 @@ int launch_unrank(int d, int q, uint64_t rank0, uint64_t count, int max_nnz,
                   int32_t* nnz, void* stream);
 const char* device_error_string(int code);
 
+// One integrand of the sweep split over G workgroups (sg_one.hpp): G
+// workgroups of 256 threads, precision mode `precision`; scratch (G > 1):
+// kOneHead + G * kOneWords doubles, the first 32-bit word (the arrival
+// counter) zero before the launch and zero after it.
+constexpr int kOneHead = 32;
+constexpr int kOneWords = kMaxK + 4;
+constexpr int kOneMaxG = 1024;   // workgroups of one split launch at most
+int launch_one(int precision, int d, int K, int rule, int family, int G, const double* params, double* out,
+               double* bound, double* scratch, void* stream);
+// Workgroups for an integrand of d coordinates: one coordinate per lane
+// (256 per workgroup), at most kOneMaxG.
+inline int one_workgroups(int d)
+{
+    const int g = (d + 255) / 256;
+    return g < 1 ? 1 : g > kOneMaxG ? kOneMaxG : g;
+}
+
 // Literal point-by-point path (sg_points.hip).
 struct PointsLaunch {
     int d, K, e0, grid;

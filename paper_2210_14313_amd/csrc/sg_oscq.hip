@@ -11,18 +11,21 @@
 // Q = Re(e^{i (2 pi w + sum_t a_t (1/2 - u_t)^2)} sum_{b <= K} [z^b] prod_t D_t(z)),
 // D_t(z) = 1 + sum_e delta_t[e] z^e, with complex truncated products.
 //
-// One workgroup of 256 threads per integrand (a plan launches one per
-// oscillatory-quadratic integrand): each thread sweeps the
-// coordinates t = tid, tid + 256, ..., a wave combines its lanes by an
-// xor butterfly of complex truncated products, and the first thread joins
-// the four waves in wave order and reads out the value and its bound.
+// A plan gives each oscillatory-quadratic integrand one workgroup of 256
+// threads; the plan-free path splits one integrand over G workgroups.  Each
+// thread sweeps the coordinates t = b 256 + tid + j 256 G, a wave combines its
+// lanes by an xor butterfly of complex truncated products, the first thread
+// joins the four waves in wave order, and with G > 1 the workgroups' partials
+// are joined in a fixed order by the last workgroup to finish (oscq_body).
 #include "sg_device.hpp"
 #include "sg_oscq.hpp"
+#include "sg_tables_dev.inc"
 
 namespace sg {
 namespace dev {
 
 constexpr int OSCQ_WORDS = 2 * MAXK + 4;   // doubles per wave in LDS
+static_assert(OSCQ_WORDS == kOscqWords, "partial layout shared with the host");
 
 // a <- a * b for monic complex truncated polynomials (coefficients 1..K).
 template <int K>
@@ -88,81 +91,122 @@ __device__ __forceinline__ void surplus_oscq(const double* __restrict__ r64, dou
     });
 }
 
+// State of a partial complex sweep: the truncated product (real and
+// imaginary coefficients 1..K) and the sums the read-out and bound need.
+struct OscqAcc {
+    double ar[MAXK + 1], ai[MAXK + 1];
+    double m, eps, ph, phabs;
+};
+
+template <int K>
+__device__ __forceinline__ void oscq_identity(OscqAcc& x)
+{
+#pragma unroll
+    for (int k = 0; k <= MAXK; ++k) { x.ar[k] = 0.0; x.ai[k] = 0.0; }
+    x.m = x.eps = x.ph = x.phabs = 0.0;
+}
+
+template <int K>
+__device__ __forceinline__ void oscq_merge(OscqAcc& x, const OscqAcc& y)
+{
+    cpmul<K>(x.ar, x.ai, y.ar, y.ai);
+    x.m += y.m;
+    x.eps += y.eps;
+    x.ph += y.ph;
+    x.phabs += y.phabs;
+}
+
+template <int K>
+__device__ __forceinline__ void oscq_store(const OscqAcc& x, double* s)
+{
+#pragma unroll
+    for (int k = 1; k <= K; ++k) {
+        s[k - 1] = x.ar[k];
+        s[MAXK + k - 1] = x.ai[k];
+    }
+    s[2 * MAXK] = x.m;
+    s[2 * MAXK + 1] = x.eps;
+    s[2 * MAXK + 2] = x.ph;
+    s[2 * MAXK + 3] = x.phabs;
+}
+
+template <int K>
+__device__ __forceinline__ void oscq_load(OscqAcc& x, const double* s)
+{
+#pragma unroll
+    for (int k = 1; k <= K; ++k) {
+        x.ar[k] = s[k - 1];
+        x.ai[k] = s[MAXK + k - 1];
+    }
+    x.m = s[2 * MAXK];
+    x.eps = s[2 * MAXK + 1];
+    x.ph = s[2 * MAXK + 2];
+    x.phabs = s[2 * MAXK + 3];
+}
+
+// Partial sweep of workgroup b of G over the coordinates
+// t = b 256 + tid + j 256 G; thread 0 returns the workgroup's state (its
+// four waves joined in wave order).
 template <int K, int RC>
-__device__ void oscq_body(int d, const double* __restrict__ r64, const double* __restrict__ prm,
-                          double* __restrict__ out, double* __restrict__ bound, double* lds)
+__device__ void oscq_partial(int d, int b, int G, const double* __restrict__ r64, const double* __restrict__ prm,
+                             double* lds, OscqAcc& x)
 {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    double ar[MAXK + 1], ai[MAXK + 1];
-#pragma unroll
-    for (int k = 0; k <= MAXK; ++k) { ar[k] = 0.0; ai[k] = 0.0; }
-    double m = 0.0, eps = 0.0, ph = 0.0, phabs = 0.0;
-    for (int t = tid; t < d; t += 256) {
+    oscq_identity<K>(x);
+    for (int t = b * 256 + tid; t < d; t += 256 * G) {
         const double a = prm[1 + t], hv = 0.5 - prm[1 + d + t];
         double dr[MAXK + 1], di[MAXK + 1], e_t = 0.0;
         int opaque = 0;
         asm volatile("" : "+s"(opaque));
         surplus_oscq<K, RC>(r64 + opaque, a, 2.0 * hv, dr, di, e_t);
-        cpmul<K>(ar, ai, dr, di);
+        cpmul<K>(x.ar, x.ai, dr, di);
         double mt = 0.0;
 #pragma unroll
         for (int k = 1; k <= K; ++k) mt += fabs(dr[k]) + fabs(di[k]);
-        m += mt;
-        eps += e_t;
+        x.m += mt;
+        x.eps += e_t;
         const double term = a * (hv * hv);          // phase of g_t(1/2)
-        ph += term;
-        phabs += fabs(term);
+        x.ph += term;
+        x.phabs += fabs(term);
     }
     for (int off = 32; off >= 1; off >>= 1) {
-        double br[MAXK + 1], bi[MAXK + 1];
+        OscqAcc y;
 #pragma unroll
         for (int k = 1; k <= K; ++k) {
-            br[k] = __shfl_xor(ar[k], off);
-            bi[k] = __shfl_xor(ai[k], off);
+            y.ar[k] = __shfl_xor(x.ar[k], off);
+            y.ai[k] = __shfl_xor(x.ai[k], off);
         }
-        cpmul<K>(ar, ai, br, bi);
-        m += __shfl_xor(m, off);
-        eps += __shfl_xor(eps, off);
-        ph += __shfl_xor(ph, off);
-        phabs += __shfl_xor(phabs, off);
+        y.m = __shfl_xor(x.m, off);
+        y.eps = __shfl_xor(x.eps, off);
+        y.ph = __shfl_xor(x.ph, off);
+        y.phabs = __shfl_xor(x.phabs, off);
+        oscq_merge<K>(x, y);
     }
-    if (lane == 0) {
-        double* s = lds + w * OSCQ_WORDS;
-#pragma unroll
-        for (int k = 1; k <= K; ++k) {
-            s[k - 1] = ar[k];
-            s[MAXK + k - 1] = ai[k];
-        }
-        s[2 * MAXK] = m;
-        s[2 * MAXK + 1] = eps;
-        s[2 * MAXK + 2] = ph;
-        s[2 * MAXK + 3] = phabs;
-    }
+    if (lane == 0) oscq_store<K>(x, lds + w * OSCQ_WORDS);
     __syncthreads();
     if (tid != 0) return;
     for (int v = 1; v < 4; ++v) {
-        const double* s = lds + v * OSCQ_WORDS;
-        double br[MAXK + 1], bi[MAXK + 1];
-#pragma unroll
-        for (int k = 1; k <= K; ++k) {
-            br[k] = s[k - 1];
-            bi[k] = s[MAXK + k - 1];
-        }
-        cpmul<K>(ar, ai, br, bi);
-        m += s[2 * MAXK];
-        eps += s[2 * MAXK + 1];
-        ph += s[2 * MAXK + 2];
-        phabs += s[2 * MAXK + 3];
+        OscqAcc y;
+        oscq_load<K>(y, lds + v * OSCQ_WORDS);
+        oscq_merge<K>(x, y);
     }
+}
+
+// Q = Re(e^{i (2 pi w + ph)} S) and its bound; depth: levels of the product
+// tree behind the joined state.
+template <int K, int RC>
+__device__ void oscq_readout(const OscqAcc& x, int d, int depth, const double* __restrict__ prm,
+                             double* __restrict__ out, double* __restrict__ bound)
+{
     double sr = 0.0, si = 0.0;
 #pragma unroll
     for (int k = K; k >= 1; --k) {
-        sr += ar[k];
-        si += ai[k];
+        sr += x.ar[k];
+        si += x.ai[k];
     }
     sr += 1.0;
     const double wp = 2.0 * 3.141592653589793 * prm[0];
-    const double phase = wp + ph;
+    const double phase = wp + x.ph;
     double sn, cs;
     sincos(phase, &sn, &cs);
     const double Q = fma(cs, sr, -sn * si);
@@ -171,61 +215,127 @@ __device__ void oscq_body(int d, const double* __restrict__ r64, const double* _
         const double u64 = 1.1102230246251565e-16;
         // coefficients of every partial product are bounded in sum by
         // exp(sum_t sum_e |delta_t[e]|) (as for the real sweep)
-        const double sabs = exp(m) * (1.0 + 1e-13);
+        const double sabs = exp(x.m) * (1.0 + 1e-13);
         // pair values: 8 roundings relative to mag; within-rule sums: one
         // FMA chain over the table's pairs
         const double rel = u64 * (8.0 + (double)total_pairs<RC, K>());
-        // product tree: a thread's ceil(d/256) coordinates, 6 butterfly
-        // levels, 3 wave joins; a complex truncated product rounds each
-        // component at most 2K + 2 times
-        const double levels = (double)((d + 255) / 256 + 9);
-        const double dsum = sabs * (rel * eps + (2.0 * K + 4.0) * levels * u64);
+        // product tree: a complex truncated product rounds each component at
+        // most 2K + 2 times per level
+        const double dsum = sabs * (rel * x.eps + (2.0 * K + 4.0) * (double)depth * u64);
         // phase: d - 1 additions of terms rounded twice each, and 2 pi w
-        const double ph_err = u64 * (double)(d + 3) * phabs + 2.0 * u64 * fabs(wp);
+        const double ph_err = u64 * (double)(d + 3) * x.phabs + 2.0 * u64 * fabs(wp);
         const double smag = sqrt(fma(sr, sr, si * si)) + dsum;
         bound[0] = dsum + smag * (ph_err + u64 * (fabs(phase) + 8.0));
     }
 }
 
-__device__ __forceinline__ void oscq_dispatch(int d, int K, int rule, const double* r64, const double* prm,
-                                              double* out, double* bound, double* lds)
+// One integrand on G workgroups: G = 1 reads out directly; otherwise each
+// workgroup writes its partial to scratch (after kOscqHeadWords words whose
+// first 32-bit word is the arrival counter), and the last to arrive joins
+// the G partials (thread i those i, i + 256, ... in order, then a fixed tree
+// over the threads), reads out, and resets the counter.
+constexpr int kOscqHeadWords = 32;
+static_assert(kOscqHeadWords == kOscqScratchHead, "scratch layout shared with the host");
+
+template <int K, int RC>
+__device__ void oscq_body(int d, int b, int G, const double* __restrict__ r64, const double* __restrict__ prm,
+                          double* __restrict__ out, double* __restrict__ bound, double* __restrict__ scratch,
+                          double* lds, int* last)
+{
+    OscqAcc x;
+    oscq_partial<K, RC>(d, b, G, r64, prm, lds, x);
+    // a thread's ceil(d / (256 G)) coordinates, 6 butterfly levels, 3 wave joins
+    const int chain = (d + 256 * G - 1) / (256 * G);
+    if (G == 1) {
+        if (threadIdx.x == 0) oscq_readout<K, RC>(x, d, chain + 9, prm, out, bound);
+        return;
+    }
+    unsigned int* counter = reinterpret_cast<unsigned int*>(scratch);
+    double* partials = scratch + kOscqHeadWords;
+    if (threadIdx.x == 0) {
+        oscq_store<K>(x, partials + (size_t)b * OSCQ_WORDS);
+        __threadfence();
+        *last = atomicAdd(counter, 1u) == (unsigned int)(G - 1);
+    }
+    __syncthreads();
+    if (!*last) return;
+    __threadfence();
+    const int i = threadIdx.x;
+    OscqAcc a, c;
+    oscq_identity<K>(a);
+    for (int j = i; j < G; j += 256) {
+        oscq_load<K>(c, partials + (size_t)j * OSCQ_WORDS);
+        oscq_merge<K>(a, c);
+    }
+    __syncthreads();
+    oscq_store<K>(a, lds + i * OSCQ_WORDS);
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+        if (i < s) {
+            oscq_load<K>(a, lds + i * OSCQ_WORDS);
+            oscq_load<K>(c, lds + (i + s) * OSCQ_WORDS);
+            oscq_merge<K>(a, c);
+            oscq_store<K>(a, lds + i * OSCQ_WORDS);
+        }
+        __syncthreads();
+    }
+    if (i == 0) {
+        oscq_load<K>(a, lds);
+        oscq_readout<K, RC>(a, d, chain + 9 + (G + 255) / 256 + 8, prm, out, bound);
+        atomicExch(counter, 0u);
+    }
+}
+
+// b: this workgroup's index among the G of one integrand.
+__device__ __forceinline__ void oscq_dispatch(int d, int K, int rule, int b, int G, const double* r64,
+                                              const double* prm, double* out, double* bound, double* scratch,
+                                              double* lds, int* last)
 {
     const int rc = rule_class_of(rule);
     switch_k<MAXK>(K, [&](auto kc) {
         constexpr int KK = decltype(kc)::value;
-        if (rc == RC_NESTED) oscq_body<KK, RC_NESTED>(d, r64, prm, out, bound, lds);
-        else if (rc == RC_GL2) oscq_body<KK, RC_GL2>(d, r64, prm, out, bound, lds);
-        else if (rc == RC_GP) oscq_body<KK, RC_GP>(d, r64, prm, out, bound, lds);
-        else oscq_body<KK, RC_GLP>(d, r64, prm, out, bound, lds);
+        if (rc == RC_NESTED) oscq_body<KK, RC_NESTED>(d, b, G, r64, prm, out, bound, scratch, lds, last);
+        else if (rc == RC_GL2) oscq_body<KK, RC_GL2>(d, b, G, r64, prm, out, bound, scratch, lds, last);
+        else if (rc == RC_GP) oscq_body<KK, RC_GP>(d, b, G, r64, prm, out, bound, scratch, lds, last);
+        else oscq_body<KK, RC_GLP>(d, b, G, r64, prm, out, bound, scratch, lds, last);
     });
 }
 
+// One integrand on G workgroups (scratch: see oscq_body; unused for G = 1).
+// pool64 == nullptr: the (rule, K) records compiled into the library.
 __global__ void __launch_bounds__(256)
-k_oscq(int d, int K, int rule, const double* __restrict__ pool64, const double* __restrict__ params,
-       double* __restrict__ out, double* __restrict__ bound)
+k_oscq(int d, int K, int rule, int G, const double* __restrict__ pool64, const double* __restrict__ params,
+       double* __restrict__ out, double* __restrict__ bound, double* __restrict__ scratch)
 {
-    __shared__ double lds[4 * OSCQ_WORDS];
-    oscq_dispatch(d, K, rule, pool64, params, out, bound, lds);
+    __shared__ double lds[256 * OSCQ_WORDS];
+    __shared__ int last;
+    const double* r64 = pool64;
+    if (!r64) {
+        const float* r32;
+        tabd::records(rule, K, &r64, &r32);
+    }
+    oscq_dispatch(d, K, rule, (int)blockIdx.x, G, r64, params, out, bound, scratch, lds, &last);
 }
 
-// Workgroup b runs descriptor b.
+// Workgroup b runs descriptor b (one workgroup per integrand).
 __global__ void __launch_bounds__(256)
 k_oscq_batch(const OscqDesc* __restrict__ descs, const double* __restrict__ pool64,
              const double* __restrict__ params, double* __restrict__ out, double* __restrict__ bound)
 {
     __shared__ double lds[4 * OSCQ_WORDS];
+    __shared__ int last;
     const OscqDesc q = descs[blockIdx.x];
-    oscq_dispatch(q.d, q.K, q.rule, pool64 + q.off64, params + q.param_offset, out + q.out_index,
-                  bound ? bound + q.out_index : nullptr, lds);
+    oscq_dispatch(q.d, q.K, q.rule, 0, 1, pool64 + q.off64, params + q.param_offset, out + q.out_index,
+                  bound ? bound + q.out_index : nullptr, nullptr, lds, &last);
 }
 
 }  // namespace dev
 
-int launch_oscq(int d, int K, int rule, const double* pool64, const double* params, double* out, double* bound,
-                void* stream)
+int launch_oscq(int d, int K, int rule, int G, const double* pool64, const double* params, double* out,
+                double* bound, double* scratch, void* stream)
 {
-    hipLaunchKernelGGL(dev::k_oscq, dim3(1), dim3(256), 0, (hipStream_t)stream, d, K, rule, pool64, params, out,
-                       bound);
+    hipLaunchKernelGGL(dev::k_oscq, dim3((unsigned)G), dim3(256), 0, (hipStream_t)stream, d, K, rule, G, pool64,
+                       params, out, bound, scratch);
     return (int)hipGetLastError();
 }
 

@@ -14,10 +14,15 @@ struct OscqDesc {
     int32_t out_index;      // its slot in out / bound
 };
 
-// One integrand (the plan-free path): pool64 holds the (rule, K) record
-// table; out and bound (NULL: none) one double each.
-int launch_oscq(int d, int K, int rule, const double* pool64, const double* params, double* out, double* bound,
-                void* stream);
+// One integrand (the plan-free path) on G workgroups: pool64 holds the
+// (rule, K) record table, or is NULL for the tables compiled into the
+// library; out and bound (NULL: none) one double each;
+// scratch (G > 1): kOscqScratchHead + G * kOscqWords doubles whose first
+// 32-bit word, the arrival counter, is zero, and is left zero.
+constexpr int kOscqScratchHead = 32;
+constexpr int kOscqWords = 2 * 8 + 4;
+int launch_oscq(int d, int K, int rule, int G, const double* pool64, const double* params, double* out,
+                double* bound, double* scratch, void* stream);
 // n integrands of a plan, one workgroup each; out and bound (NULL: none)
 // indexed by out_index.
 int launch_oscq_batch(int n, const OscqDesc* descs, const double* pool64, const double* params, double* out,

@@ -115,6 +115,20 @@ int forward_capacity(int precision, int kmax)
     return forward_capacity_p<2>(kmax);
 }
 
+template <int P>
+int launch_one_inst(int d, int K, int rule, int family, int G, const double* params, double* out, double* bound,
+                    double* scratch, void* stream);
+
+int launch_one(int precision, int d, int K, int rule, int family, int G, const double* params, double* out,
+               double* bound, double* scratch, void* stream)
+{
+    if (precision == SG_PREC_FP64)
+        return launch_one_inst<0>(d, K, rule, family, G, params, out, bound, scratch, stream);
+    if (precision == SG_PREC_FP32_COMPENSATED)
+        return launch_one_inst<1>(d, K, rule, family, G, params, out, bound, scratch, stream);
+    return launch_one_inst<2>(d, K, rule, family, G, params, out, bound, scratch, stream);
+}
+
 int launch_adjoint(int precision, bool gauss, int nwg, const WGDesc* wgs, const ProbDev* probs,
                    const double* pool64, const float* pool32, const double* params, const double* gout,
                    double* grad, double* ws, void* stream)

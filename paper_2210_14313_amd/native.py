@@ -51,8 +51,8 @@ _lib = None
 EXPORTS = ["sg_context_create", "sg_context_destroy", "sg_status_string", "sg_last_error", "sg_counts",
            "sg_rule_table", "sg_coefficient", "sg_unrank", "sg_unrank_device", "sg_plan_create",
            "sg_plan_execute", "sg_plan_execute_grad", "sg_plan_get_info", "sg_plan_autotune",
-           "sg_plan_set_schedule", "sg_plan_set_schedule_balanced", "sg_plan_destroy", "sg_integrate", "sg_integrate_points",
-           "sg_plan_create_blocked"]
+           "sg_plan_set_schedule", "sg_plan_set_schedule_balanced", "sg_plan_destroy", "sg_integrate",
+           "sg_integrate_points", "sg_plan_create_blocked"]
 
 
 def lib():

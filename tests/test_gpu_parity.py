@@ -423,3 +423,59 @@ def test_balanced_schedule(api, orc):
         assert np.max(np.abs(got - bref) / bscale) <= tol, prec
         assert np.all(np.abs(got - bref) <= bd), prec
         plan.close()
+
+
+@pytest.mark.parametrize("family", ["exp_sum", "oscillatory", "product_peak", "gaussian", "oscillatory_quadratic"])
+def test_plan_free_path_split_over_workgroups(api, orc, family):
+    """sg_integrate splits an integrand over ceil(d / 256) workgroups (at most
+    1024) and joins their partials in a fixed order: FP64 against the
+    oracle at sizes around the split boundaries and beyond the cap, the
+    same value on repeated calls, and graph replays of the split launch
+    (the arrival counter must come back to zero after every launch)."""
+    import torch
+    from paper_2210_14313_amd import native, workloads as W
+    rng = np.random.default_rng(31 + len(family))
+    sizes = [(1, 4, "gl"), (255, 3, "cc"), (256, 2, "gp"), (257, 5, "gl"), (1000, 3, "tr")]
+    if family != "product_peak":     # its value leaves the double range at large d
+        sizes += [(5000, 2, "cc"), (300000, 1, "cc")]
+    for d, K, rule in sizes:
+        prm = W.draw_params(rng, family, d)
+        if family in ("exp_sum", "gaussian"):
+            prm = prm * min(1.0, 30.0 / d)
+        b = W.single(d, d + K, rule, family, prm)
+        p = b.problems[0]
+        pr = torch.as_tensor(prm, dtype=torch.float64).cuda()
+        say("case plan-free split", family, d, K, rule)
+        out = torch.empty(1, dtype=torch.float64, device="cuda")
+        bnd = torch.empty_like(out)
+        native.integrate_one(p, pr, "fp64", out=out, bound=bnd)
+        v1, b1 = out.item(), bnd.item()
+        native.integrate_one(p, pr, "fp64", out=out, bound=bnd)
+        assert (out.item(), bnd.item()) == (v1, b1)
+        ref = orc.smolyak_factorised(p.d, p.q, p.rule, p.family, prm)
+        scale = orc.accuracy_scale_one(p.d, p.q, p.rule, p.family, prm, ref)
+        assert abs(v1 - ref) <= b1, (d, v1, ref, b1)
+        assert abs(v1 - ref) <= 1e-12 * scale, (d, v1, ref)
+    # graph replays of a split launch on a non-default stream
+    d = 3000 if family != "product_peak" else 900
+    prm = W.draw_params(rng, family, d)
+    if family in ("exp_sum", "gaussian"):
+        prm = prm / d
+    p = W.single(d, d + 3, "cc", family, prm).problems[0]
+    pr = torch.as_tensor(prm, dtype=torch.float64).cuda()
+    eager = torch.empty(1, dtype=torch.float64, device="cuda")
+    native.integrate_one(p, pr, "fp64", out=eager)
+    s = torch.cuda.Stream()
+    out = torch.empty(1, dtype=torch.float64, device="cuda")
+    g = torch.cuda.CUDAGraph()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.graph(g, stream=s):
+        native.integrate_one(p, pr, "fp64", out=out, stream=torch.cuda.current_stream())
+    for rep in range(4):
+        out.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert out.item() == eager.item(), (family, rep)
+        native.integrate_one(p, pr, "fp64", out=eager)      # eager work between replays
+        torch.cuda.synchronize()
