@@ -366,6 +366,23 @@ sg_status sg_integrate_points(sg_context *ctx, const sg_problem *problem, const 
 sg_status sg_integrate(sg_context *ctx, const sg_problem *problem, int32_t precision,
                        const double *params_dev, double *out_dev, double *bound_dev, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation, launches and results as sg_integrate, bit for bit, with the
+ * split launches' scratch in a fixed array the library's code object
+ * carries (one per GPU, kept until the process ends; its address is taken
+ * once per device by sg_context_create).  Allocates nothing: no hipMalloc,
+ * hipFree or allocating library routine.  The array holds 1024 partials
+ * (about 160 KiB); problems never need more (the workgroup count is capped
+ * at 1024, more coordinates per lane beyond), and a request that would is
+ * rejected with UNSUPPORTED before launching.  Every call on one GPU shares
+ * the array, so calls that overlap in time on one GPU race (their results
+ * are undefined); calls in sequence on one stream are safe, and each
+ * completed call leaves the array ready for the next.
+ * Errors: as sg_integrate; DEVICE if the context has no array address. */
+sg_status sg_integrate_noalloc(sg_context *ctx, const sg_problem *problem, int32_t precision,
+                               const double *params_dev, double *out_dev, double *bound_dev, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -66,6 +66,7 @@ struct sg_context {
     std::map<std::pair<int, int>, std::unique_ptr<Records>> records;
     std::map<std::string, std::pair<FwdSched, bool>> tuned;   // plan shape -> (schedule, graph)
     double* one_ws = nullptr;        // scratch of the plan-free split launches (sg_integrate), counter zero
+    double* noalloc = nullptr;       // the device's fixed scratch array (sg_integrate_noalloc)
     std::map<std::pair<int, int>, uint64_t*> unrank_tables;
     std::map<std::pair<int, int>, PointsTable> points_tables;   // (rule, K) -> 1-D nodes of levels 1..K+1
     double* points_ws = nullptr;                                // per-wave partial sums of the point path
@@ -690,6 +691,13 @@ sg_status sg_context_create(sg_context** ctx)
     sg_context* c = new (std::nothrow) sg_context();
     if (!c) return SG_ERR_OUT_OF_MEMORY;
     c->device = dev;
+    // set-up of the allocation-free path: the address of this device's fixed
+    // scratch array (looked up once per device)
+    const int rc = noalloc_scratch(&c->noalloc);
+    if (rc != 0) {
+        delete c;
+        return SG_ERR_DEVICE;
+    }
     *ctx = c;
     return SG_OK;
 }
@@ -1524,7 +1532,7 @@ sg_status sg_plan_destroy(sg_plan* p)
     return SG_OK;
 }
 
-// Arguments of the plan-free path.
+// Arguments of the plan-free path (sg_integrate, sg_integrate_noalloc).
 static sg_status check_one(sg_context* ctx, const sg_problem* problem, int32_t precision, const double* params_dev,
                            const double* out_dev)
 {
@@ -1545,7 +1553,7 @@ sg_status sg_integrate(sg_context* ctx, const sg_problem* problem, int32_t preci
     if (G > 1 && !ctx->one_ws) {
         // the split launches' scratch: allocated once per context, counter
         // zeroed once; every launch leaves it at zero
-        const size_t words = (size_t)kOneHead + (size_t)kOneMaxG * (size_t)std::max(kOneWords, kOscqWords);
+        const size_t words = (size_t)noalloc_capacity_words();
         hipError_t e = hipMalloc((void**)&ctx->one_ws, words * sizeof(double));
         if (e != hipSuccess) {
             ctx->one_ws = nullptr;
@@ -1560,6 +1568,20 @@ sg_status sg_integrate(sg_context* ctx, const sg_problem* problem, int32_t preci
                        : launch_one(precision, d, K, problem->rule, problem->family, G, params_dev, out_dev,
                                     bound_dev, ctx->one_ws, stream);
     if (rc != 0) return hip_fail(ctx, (hipError_t)rc, "plan-free launch");
+    return SG_OK;
+}
+
+sg_status sg_integrate_noalloc(sg_context* ctx, const sg_problem* problem, int32_t precision,
+                               const double* params_dev, double* out_dev, double* bound_dev, void* stream)
+{
+    if (!ctx) return SG_ERR_INVALID_ARGUMENT;
+    sg_status st = check_one(ctx, problem, precision, params_dev, out_dev);
+    if (st != SG_OK) return st;
+    if (!ctx->noalloc) return fail(ctx, SG_ERR_DEVICE, "no scratch array on this device");
+    const int rc = noalloc_launch(ctx->noalloc, precision, problem->d, problem->q - problem->d, problem->rule,
+                                  problem->family, params_dev, out_dev, bound_dev, stream);
+    if (rc == -1) return fail(ctx, SG_ERR_UNSUPPORTED, "problem needs more scratch than the fixed array holds");
+    if (rc != 0) return hip_fail(ctx, (hipError_t)rc, "allocation-free launch");
     return SG_OK;
 }
 

@@ -190,6 +190,15 @@ inline int one_workgroups(int d)
     return g < 1 ? 1 : g > kOneMaxG ? kOneMaxG : g;
 }
 
+// Allocation-free path (sg_noalloc.hip): the current device's fixed scratch
+// array (0 or a HIP error code), a split launch on it (0, a HIP error code,
+// or -1 if it would need more scratch than the array holds), and the array's
+// size in doubles (also the size of a context's split-launch scratch).
+int noalloc_scratch(double** ptr);
+int noalloc_launch(double* ptr, int precision, int d, int K, int rule, int family, const double* params,
+                   double* out, double* bound, void* stream);
+long noalloc_capacity_words();
+
 // Literal point-by-point path (sg_points.hip).
 struct PointsLaunch {
     int d, K, e0, grid;

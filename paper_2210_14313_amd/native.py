@@ -52,7 +52,7 @@ EXPORTS = ["sg_context_create", "sg_context_destroy", "sg_status_string", "sg_la
            "sg_rule_table", "sg_coefficient", "sg_unrank", "sg_unrank_device", "sg_plan_create",
            "sg_plan_execute", "sg_plan_execute_grad", "sg_plan_get_info", "sg_plan_autotune",
            "sg_plan_set_schedule", "sg_plan_set_schedule_balanced", "sg_plan_destroy", "sg_integrate",
-           "sg_integrate_points", "sg_plan_create_blocked"]
+           "sg_integrate_noalloc", "sg_integrate_points", "sg_plan_create_blocked"]
 
 
 def lib():
@@ -85,6 +85,7 @@ def lib():
         "sg_plan_set_schedule_balanced": ([vp, i32, i32], i32),
         "sg_plan_destroy": ([vp], i32),
         "sg_integrate": ([vp, P(SgProblem), i32, vp, vp, vp, vp], i32),
+        "sg_integrate_noalloc": ([vp, P(SgProblem), i32, vp, vp, vp, vp], i32),
         "sg_integrate_points": ([vp, P(SgProblem), vp, vp, vp, u64, vp], i32),
     }
     for name, (args, res) in sig.items():
@@ -315,6 +316,23 @@ def integrate_one(problem, params, precision: str = "fp64", out=None, bound=None
     pr = SgProblem(problem.d, problem.q, RULES[problem.rule], FAMILIES[problem.family], 0)
     _check(lib().sg_integrate(ctx.handle, ctypes.byref(pr), PRECISIONS[precision], _ptr(params), _ptr(out),
                               _ptr(bound), _stream_ptr(stream)), ctx.handle)
+    return out
+
+
+def integrate_noalloc(problem, params, precision: str = "fp64", out=None, bound=None, stream=None,
+                      ctx: Optional[Context] = None):
+    """The plan-free path without device allocation (sg_integrate_noalloc):
+    out (and bound) must be given, so nothing is allocated here either."""
+    if out is None:
+        raise ValueError("integrate_noalloc needs an out tensor (it allocates nothing)")
+    check_tensor("params", params, n_params(problem.family, problem.d))
+    check_tensor("out", out, 1)
+    if bound is not None:
+        check_tensor("bound", bound, 1)
+    ctx = ctx or default_context()
+    pr = SgProblem(problem.d, problem.q, RULES[problem.rule], FAMILIES[problem.family], 0)
+    _check(lib().sg_integrate_noalloc(ctx.handle, ctypes.byref(pr), PRECISIONS[precision], _ptr(params), _ptr(out),
+                                      _ptr(bound), _stream_ptr(stream)), ctx.handle)
     return out
 
 
