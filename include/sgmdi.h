@@ -32,6 +32,13 @@
  *   - "stream" is a hipStream_t passed as void* (NULL = default stream);
  *     device work is asynchronous on that stream;
  *   - one context per host thread; contexts and plans are not thread-safe.
+ *
+ * Developer hooks read from the environment (none changes a result):
+ *   SGMDI_SCHED=c,g[,p[,s]]  sg_plan_create: force the forward schedule of
+ *                            new plans (c coordinates per lane, g waves per
+ *                            integrand, p persistent queue 0/1, s
+ *                            cost-scaled 0/1), for profiling;
+ *   SGMDI_NO_GRAPH=1         sg_plan_execute: never replay a graph.
  */
 #ifndef SGMDI_H
 #define SGMDI_H
@@ -106,6 +113,10 @@ typedef enum {
                                      such a plan runs in mode 1) */
 } sg_precision;
 
+/* Version of this library (also the key under which autotune results are
+ * saved: results of another version are not loaded). */
+#define SG_VERSION_STRING "0.2.0"
+
 /* Largest excess budget K = q - d the GPU path accepts. */
 #define SG_MAX_K 8
 
@@ -140,6 +151,25 @@ const char *sg_status_string(sg_status s);
  * valid until the next call on the context.  Never NULL. */
 const char *sg_last_error(const sg_context *ctx);
 
+/* SG_VERSION_STRING of the loaded library. */
+const char *sg_version(void);
+
+/* Autotune results on disk.  A context keeps the schedule sg_plan_autotune
+ * chose for every plan shape it tuned (shape: precision mode, problem count
+ * and the multiset of (d, K, rule, family)); plans created later with the
+ * same shape start from it.  sg_context_save_tuning writes them all to a
+ * JSON file (written to path.tmp, then renamed over path): the library
+ * version, the device's architecture name and compute-unit count, and one
+ * record per shape.  sg_context_load_tuning reads such a file into the
+ * context, replacing records of the same shape; a file written by another
+ * library version, or for another architecture or compute-unit count, loads
+ * nothing (*n_loaded = 0, SG_OK).  n_loaded may be NULL.  Plans that exist
+ * already keep their schedule.
+ * Errors: INVALID_ARGUMENT (NULL, unreadable or unwritable file, malformed
+ * content or an out-of-range record: then nothing is loaded). */
+sg_status sg_context_save_tuning(const sg_context *ctx, const char *path);
+sg_status sg_context_load_tuning(sg_context *ctx, const char *path, int32_t *n_loaded);
+
 /* ------------------------------------------------------- host, exact, sync */
 
 /* Exact counts for (d, q, rule) (Section 2.1):
@@ -148,7 +178,8 @@ const char *sg_last_error(const sg_context *ctx);
  *   n_points_unique distinct points of the sparse grid (the union (2.4)
  *                   over the window).
  * Any output pointer may be NULL.  Errors: INVALID_ARGUMENT (d < 1, q < d,
- * unknown rule), UNSUPPORTED (K > 60), OVERFLOW (a count >= 2^64). */
+ * unknown rule), UNSUPPORTED (K > 60, or a level of the window whose rule
+ * has more than 2^16+1 nodes), OVERFLOW (a count >= 2^64). */
 sg_status sg_counts(int32_t d, int32_t q, int32_t rule,
                     uint64_t *n_multi, uint64_t *n_points_rep, uint64_t *n_points_unique);
 
@@ -202,8 +233,9 @@ sg_status sg_plan_create(sg_context *ctx, const sg_problem *problems, int32_t n,
  * d_b + (q - d) (the integrand's excess budget), and the rule is the tensor
  * product of the block rules -- the reading under which the paper's errors
  * grow in proportion to d/m (Tables 4.7-4.9, 5.1-5.4).  block_dims >= d is
- * the plain rule.  The integrand must factor over the blocks (exp-sum,
- * oscillatory, product-peak).  The returned plan is used like any other
+ * the plain rule.  The integrand must factor over the blocks (every family
+ * but CORNER_PEAK; the oscillatory ones as the real and imaginary parts of
+ * a product of complex block factors).  The returned plan is used like any other
  * (sg_plan_execute, _autotune, _set_schedule, _get_info, _destroy) with the
  * same parameter layout and outputs.  Execution is three launches (block
  * parameter gather, forward over the blocks, ordered combine), launched
@@ -215,7 +247,7 @@ sg_status sg_plan_create(sg_context *ctx, const sg_problem *problems, int32_t n,
  * bounds.  sg_plan_execute_grad is not available (UNSUPPORTED).
  * effective_points counts the tensor product's points (saturating).
  * Errors: INVALID_ARGUMENT (block_dims < 1, as sg_plan_create), UNSUPPORTED
- * (corner-peak, oscillatory-quadratic, K > SG_MAX_K), OUT_OF_MEMORY, DEVICE. */
+ * (corner-peak, K > SG_MAX_K), OUT_OF_MEMORY, DEVICE. */
 sg_status sg_plan_create_blocked(sg_context *ctx, const sg_problem *problems, int32_t n,
                                  int32_t precision, int32_t block_dims, sg_plan **plan);
 
@@ -271,7 +303,10 @@ sg_status sg_plan_execute_grad(sg_plan *plan, const double *params_dev, const do
  *   chosen by sg_plan_autotune);
  *   balanced: 0, or the waves per SIMD of the balanced schedule
  *   (sg_plan_set_schedule_balanced), which replaces coords_per_lane,
- *   max_group and cost_scaled. */
+ *   max_group and cost_scaled;
+ *   fp64_complex: how many of the plan's integrands (OSCILLATORY_QUADRATIC)
+ *   run the FP64 complex sweep whatever the plan's precision mode; their
+ *   values, bounds and time are those of FP64 arithmetic. */
 typedef struct {
     uint64_t effective_points;
     uint64_t units;
@@ -286,6 +321,8 @@ typedef struct {
     int32_t persistent;
     int32_t cost_scaled;
     int32_t balanced;
+    int32_t fp64_complex;
+    int32_t reserved;
 } sg_plan_info;
 
 sg_status sg_plan_get_info(const sg_plan *plan, sg_plan_info *info);

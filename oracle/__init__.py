@@ -41,11 +41,26 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(LIB_PATH):
         tmp = LIB_PATH + ".tmp"
         cmd = ["gcc", "-O2", "-fPIC", "-shared", "-std=gnu11", "-ffp-contract=off",
-               "-Wall", "-Wno-unused-function", SRC_PATH, "-o", tmp,
+               "-Wall", "-Werror", "-Wno-unused-function", SRC_PATH, "-o", tmp,
                "-lquadmath", "-lpthread", "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
+
+
+SAN_LIB_PATH = os.path.join(_HERE, "liboracle_san.so")
+
+
+def build_sanitized() -> str:
+    """The oracle under AddressSanitizer and UndefinedBehaviorSanitizer (for
+    the CPU sanitizer tests; loaded in a process that preloads the runtimes)."""
+    tmp = SAN_LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O1", "-g", "-fPIC", "-shared", "-std=gnu11", "-ffp-contract=off", "-Wall", "-Werror",
+           "-Wno-unused-function", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+           "-fno-omit-frame-pointer", SRC_PATH, "-o", tmp, "-lquadmath", "-lpthread", "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, SAN_LIB_PATH)
+    return SAN_LIB_PATH
 
 
 _lib = None
@@ -56,7 +71,14 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             build()
-        L = ctypes.CDLL(LIB_PATH)
+        _lib = load(LIB_PATH)
+    return _lib
+
+
+def load(path: str):
+    """Open an oracle library file and declare its functions."""
+    if True:
+        L = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int32)
         L.or_rule_npoints.argtypes = [ctypes.c_int, ctypes.c_int]
@@ -78,8 +100,7 @@ def lib():
         L.or_batch_factorised.argtypes = [ctypes.c_int] + [ip] * 4 + [ctypes.POINTER(ctypes.c_int64), dp,
                                                                       ctypes.c_int, dp]
         L.or_batch_factorised.restype = ctypes.c_int
-        _lib = L
-    return _lib
+    return L
 
 
 def _dp(a: np.ndarray):

@@ -18,7 +18,8 @@ PEAKS_SOURCE = "sg_peaks.hip"
 
 FORWARD_UNITS = [f"sg_fwd_p{p}_{k}.hip" for p in (0, 1, 2) for k in ("k4", "k6", "k8", "g8")]
 SOURCES = FORWARD_UNITS + ["sg_one_p0.hip", "sg_one_p1.hip", "sg_one_p2.hip", "sg_adj0.hip", "sg_adj1.hip", "sg_unrank.hip", "sg_points.hip",
-           "sg_blocked.hip", "sg_oscq.hip", "sg_noalloc.hip", "sg_rules.cpp", "sg_counts.cpp", "sg_api.cpp"]
+           "sg_blocked.hip", "sg_oscq.hip", "sg_noalloc.hip", "sg_rules.cpp", "sg_counts.cpp", "sg_tuning.cpp",
+           "sg_api.cpp"]
 
 # Packed FP32 instructions are disabled for every device pass; contraction of
 # a*b+c into FMAs is off so that compensated (two-sum) sequences keep their
@@ -31,7 +32,7 @@ SOURCES = FORWARD_UNITS + ["sg_one_p0.hip", "sg_one_p1.hip", "sg_one_p2.hip", "s
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-mllvm", "-disable-machine-licm",
-             "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
+             "-Wall", "-Werror", "-Wno-unused-function", "-Wno-unused-variable"]
 
 
 def hipcc() -> str:
@@ -52,7 +53,8 @@ def generate_tables(objdir: str, verbose: bool = False) -> None:
     """Write sg_tables.inc: the difference-rule records of every (rule, K)
     as C++ constants, produced by the library's own rule construction."""
     exe = os.path.join(objdir, "gen_tables")
-    cmd = [host_cxx(), "-O2", "-std=c++17", "-I", INCLUDE, "-I", CSRC, os.path.join(CSRC, "gen_tables.cpp"),
+    cmd = [host_cxx(), "-O2", "-std=c++17", "-Wall", "-Werror", "-I", INCLUDE, "-I", CSRC,
+           os.path.join(CSRC, "gen_tables.cpp"),
            os.path.join(CSRC, "sg_rules.cpp"), "-o", exe]
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -119,6 +121,34 @@ def build(verbose: bool = False, extra_flags=None, incremental: bool = False) ->
             raise RuntimeError(f"linking {os.path.basename(lib)} failed")
         os.replace(tmp, lib)
     return LIB
+
+
+HOSTSAN_LIB = os.path.join(PKG, "_build", "libsgmdi_hostsan.so")
+SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer"]
+
+
+def build_host_sanitized(verbose: bool = False) -> str:
+    """The host runtime (C ABI, counts, rules, plans) compiled with the host
+    C++ compiler under AddressSanitizer and UndefinedBehaviorSanitizer,
+    linked against a host stand-in for the HIP runtime calls and launchers
+    that launch nothing (sg_host_stubs.cpp) instead of the HIP runtime.  CPU
+    only; tests load it in a process that preloads the sanitizer runtimes."""
+    objdir = os.path.join(PKG, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    srcs = [os.path.join(CSRC, f) for f in ("sg_api.cpp", "sg_counts.cpp", "sg_rules.cpp", "sg_tuning.cpp",
+                                              "sg_host_stubs.cpp")]
+    tmp = HOSTSAN_LIB + ".tmp"
+    cmd = ([host_cxx(), "-O1", "-g", "-std=c++17", "-fPIC", "-shared", "-Wall", "-Werror", "-Wno-unused-function",
+            "-D__HIP_PLATFORM_AMD__", "-I", INCLUDE, "-I", CSRC, "-I", "/opt/rocm/include"] + SANITIZE + srcs +
+           ["-Wl,--no-undefined", "-o", tmp])
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("compiling the sanitized host runtime failed")
+    os.replace(tmp, HOSTSAN_LIB)
+    return HOSTSAN_LIB
 
 
 if __name__ == "__main__":

@@ -61,6 +61,8 @@ struct GraphEntry {
 
 struct sg_context {
     int device = 0;
+    std::string arch;                // the device's architecture name (gcnArchName)
+    int n_cu = 256;                  // its compute units
     std::string last_error;
     std::map<std::pair<int, int>, std::unique_ptr<DeltaTable>> tables;
     std::map<std::pair<int, int>, std::unique_ptr<Records>> records;
@@ -638,7 +640,11 @@ sg_status upload(sg_context* ctx, T** dst, const T* src, size_t n)
     if (e != hipSuccess) return fail(ctx, SG_ERR_OUT_OF_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(e));
     if (n) {
         e = hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice);
-        if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy");
+        if (e != hipSuccess) {
+            (void)hipFree(*dst);
+            *dst = nullptr;
+            return hip_fail(ctx, e, "hipMemcpy");
+        }
     }
     return SG_OK;
 }
@@ -646,8 +652,8 @@ sg_status upload(sg_context* ctx, T** dst, const T* src, size_t n)
 void destroy_graphs(sg_plan* p)
 {
     for (GraphEntry& g : p->graphs) {
-        hipGraphExecDestroy(g.exec);
-        hipGraphDestroy(g.graph);
+        (void)hipGraphExecDestroy(g.exec);
+        (void)hipGraphDestroy(g.graph);
     }
     p->graphs.clear();
 }
@@ -691,6 +697,15 @@ sg_status sg_context_create(sg_context** ctx)
     sg_context* c = new (std::nothrow) sg_context();
     if (!c) return SG_ERR_OUT_OF_MEMORY;
     c->device = dev;
+    hipDeviceProp_t prop;
+    std::memset(&prop, 0, sizeof prop);
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        delete c;
+        return SG_ERR_DEVICE;
+    }
+    prop.gcnArchName[sizeof prop.gcnArchName - 1] = 0;
+    c->arch = prop.gcnArchName;
+    if (prop.multiProcessorCount > 0) c->n_cu = prop.multiProcessorCount;
     // set-up of the allocation-free path: the address of this device's fixed
     // scratch array (looked up once per device)
     const int rc = noalloc_scratch(&c->noalloc);
@@ -705,13 +720,13 @@ sg_status sg_context_create(sg_context** ctx)
 sg_status sg_context_destroy(sg_context* ctx)
 {
     if (!ctx) return SG_OK;
-    hipFree(ctx->one_ws);
-    for (auto& kv : ctx->unrank_tables) hipFree(kv.second);
+    (void)hipFree(ctx->one_ws);
+    for (auto& kv : ctx->unrank_tables) (void)hipFree(kv.second);
     for (auto& kv : ctx->points_tables) {
-        hipFree(kv.second.y);
-        hipFree(kv.second.w);
+        (void)hipFree(kv.second.y);
+        (void)hipFree(kv.second.w);
     }
-    hipFree(ctx->points_ws);
+    (void)hipFree(ctx->points_ws);
     delete ctx;
     return SG_OK;
 }
@@ -864,7 +879,10 @@ sg_status sg_integrate_points(sg_context* ctx, const sg_problem* problem, const 
         for (int l = 1; l <= K + 1; ++l) nl[l] = pt.level_off[l + 1] - pt.level_off[l];
         points_frontier_sizes(nl, K, &pt.emax, &pt.cmax);
         if ((st = upload(ctx, &pt.y, ys.data(), ys.size())) != SG_OK) return st;
-        if ((st = upload(ctx, &pt.w, ws.data(), ws.size())) != SG_OK) return st;
+        if ((st = upload(ctx, &pt.w, ws.data(), ws.size())) != SG_OK) {
+            (void)hipFree(pt.y);
+            return st;
+        }
         it = ctx->points_tables.emplace(key, pt).first;
     }
     // grid: every wave gets at least one chunk of 64 ranks; at most 2048 workgroups
@@ -872,7 +890,7 @@ sg_status sg_integrate_points(sg_context* ctx, const sg_problem* problem, const 
     const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(2048, (nchunks + 3) / 4));
     const size_t ws_need = (size_t)grid * 4 * 3;
     if (ws_need > ctx->points_ws_elems) {
-        hipFree(ctx->points_ws);
+        (void)hipFree(ctx->points_ws);
         ctx->points_ws = nullptr;
         ctx->points_ws_elems = 0;
         hipError_t e = hipMalloc((void**)&ctx->points_ws, ws_need * sizeof(double));
@@ -911,6 +929,34 @@ sg_status sg_integrate_points(sg_context* ctx, const sg_problem* problem, const 
 }
 
 static sg_status plan_repack(sg_plan* p, const FwdSched& sc);
+static void plan_free(sg_plan* p);
+
+// Autotune key of a plan: precision, problem count and a 64-bit FNV-1a hash
+// of the sorted (d, K, rule, family) list, so that only plans of the same
+// shape share a tuned schedule.
+static std::string tune_key(int precision, const sg_problem* problems, int n)
+{
+    std::vector<std::array<int32_t, 4>> cls((size_t)n);
+    for (int i = 0; i < n; ++i)
+        cls[(size_t)i] = {problems[i].d, problems[i].q - problems[i].d, problems[i].rule, problems[i].family};
+    std::sort(cls.begin(), cls.end());
+    uint64_t h = 1469598103934665603ull;
+    for (const auto& c : cls)
+        for (int32_t v : c)
+            for (int b = 0; b < 4; ++b) {
+                h ^= (uint64_t)(((uint32_t)v >> (8 * b)) & 0xffu);
+                h *= 1099511628211ull;
+            }
+    char key[64];
+    std::snprintf(key, sizeof key, "p%d_n%d_%016llx", precision, n, (unsigned long long)h);
+    return key;
+}
+// Owner of a plan under construction: a failed creation releases whatever
+// it had allocated.
+struct PlanFree {
+    void operator()(sg_plan* p) const { plan_free(p); }
+};
+using PlanOwner = std::unique_ptr<sg_plan, PlanFree>;
 
 sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n, int32_t precision,
                          sg_plan** plan)
@@ -924,7 +970,7 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
         sg_status st = validate_problem(ctx, problems[i], i, problems[i].family == SG_FAMILY_OSCILLATORY_QUADRATIC);
         if (st != SG_OK) return st;
     }
-    std::unique_ptr<sg_plan> p(new sg_plan());
+    PlanOwner p(new sg_plan());
     p->ctx = ctx;
     p->precision = precision;
     p->n = n;
@@ -954,7 +1000,6 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
     // longest-processing-time order
     std::vector<double> cost(n);
     sg_plan_info info{};
-    int maxd = 1;
     bool has_gauss = false;
     for (int i = 0; i < n; ++i) {
         const DeltaTable& t = *ptab[i];
@@ -969,7 +1014,6 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
         info.pair_evals = sat_add(info.pair_evals, sat_mul(d, (uint64_t)t.npairs));
         info.macs = sat_add(info.macs, sat_mul(d, macs));
         info.merge_flops = sat_add(info.merge_flops, sat_mul(d, K * K));
-        maxd = std::max(maxd, problems[i].d);
         if (problems[i].family == SG_FAMILY_OSCILLATORY_QUADRATIC) continue;   // its own kernel
         p->kmax = std::max(p->kmax, (int)K);
         if (problems[i].family == SG_FAMILY_GAUSSIAN) has_gauss = true;
@@ -1034,9 +1078,7 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
             if (rg[i].first < rg[i - 1].second) p->params_disjoint = false;
     }
 
-    char key[128];
-    snprintf(key, sizeof key, "p%d_n%d_maxd%d", precision, n, maxd);
-    p->tune_key = key;
+    p->tune_key = tune_key(precision, problems, n);
     auto tk = ctx->tuned.find(p->tune_key);
     if (tk != ctx->tuned.end()) {
         p->sched = tk->second.first;
@@ -1053,14 +1095,7 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
             p->sched.cost_scaled = nf >= 4 && cs == 1;
         }
     }
-    {
-        int dev = 0, cus = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
-            p->n_cu = cus;
-        else
-            p->n_cu = 256;
-    }
+    p->n_cu = ctx->n_cu;
     // reverse sweep: one problem per wave slot, cost-threshold schedule
     std::vector<int> wv(nr);
     for (int k = 0; k < nr; ++k) wv[k] = waves_for(p->probs[k].d, p->unit_cost[k], p->wmax, p->cmax);
@@ -1086,6 +1121,7 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
     if (!oscq.empty()) {
         if ((st = upload(ctx, &p->d_oscq, oscq.data(), oscq.size())) != SG_OK) return st;
         p->noscq = (int)oscq.size();
+        p->info.fp64_complex = p->noscq;
     }
     ctx->live_plans++;
     *plan = p.release();
@@ -1112,10 +1148,12 @@ static sg_status plan_repack(sg_plan* p, const FwdSched& sc_in)
     std::vector<FwdWG> fwd = sc.balanced > 0 ? pack_forward_balanced(p->probs, p->coord_cost, sc, p->n_cu, nullptr)
                                              : pack_forward(p->probs, p->unit_cost, sc);
     if (fwd.size() > p->fwd_capacity) {
-        hipFree(p->d_fwd);
-        p->d_fwd = nullptr;
-        sg_status st = upload(p->ctx, &p->d_fwd, fwd.data(), fwd.size());
+        // the new buffer first: on failure the plan keeps its schedule
+        FwdWG* grown = nullptr;
+        sg_status st = upload(p->ctx, &grown, fwd.data(), fwd.size());
         if (st != SG_OK) return st;
+        (void)hipFree(p->d_fwd);
+        p->d_fwd = grown;
         p->fwd_capacity = fwd.size();
     } else {
         hipError_t e = hipMemcpy(p->d_fwd, fwd.data(), fwd.size() * sizeof(FwdWG), hipMemcpyHostToDevice);
@@ -1146,7 +1184,8 @@ static sg_status blocked_execute(sg_plan* p, const double* params_dev, double* o
 // Launch the plan's work on `stream`: directly, or, when the plan replays
 // graphs (non-default streams only), through a HIP graph captured on the
 // first call with a given (params, out, bound, stream) binding.
-extern "C++" template <class Launch>
+extern "C++" {
+template <class Launch>
 static sg_status graph_or_direct(sg_plan* p, const double* params_dev, double* out_dev, double* bound_dev,
                                  void* stream, Launch launch)
 {
@@ -1166,19 +1205,19 @@ static sg_status graph_or_direct(sg_plan* p, const double* params_dev, double* o
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(s, &graph);
     if (st != SG_OK || e != hipSuccess || !graph) {
-        if (graph) hipGraphDestroy(graph);
+        if (graph) (void)hipGraphDestroy(graph);
         if (st != SG_OK) return st;
         return fail(p->ctx, SG_ERR_CAPTURE, std::string("capture: ") + hipGetErrorString(e));
     }
     hipGraphExec_t exec = nullptr;
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
-        hipGraphDestroy(graph);
+        (void)hipGraphDestroy(graph);
         return fail(p->ctx, SG_ERR_CAPTURE, std::string("instantiate: ") + hipGetErrorString(e));
     }
     if (p->graphs.size() >= 8) {   // keep the cache small
-        hipGraphExecDestroy(p->graphs.front().exec);
-        hipGraphDestroy(p->graphs.front().graph);
+        (void)hipGraphExecDestroy(p->graphs.front().exec);
+        (void)hipGraphDestroy(p->graphs.front().graph);
         p->graphs.erase(p->graphs.begin());
     }
     p->graphs.push_back(GraphEntry{params_dev, out_dev, bound_dev, stream, graph, exec});
@@ -1186,6 +1225,7 @@ static sg_status graph_or_direct(sg_plan* p, const double* params_dev, double* o
     if (e != hipSuccess) return hip_fail(p->ctx, e, "hipGraphLaunch");
     return SG_OK;
 }
+}  // extern "C++"
 
 sg_status sg_plan_execute(sg_plan* p, const double* params_dev, double* out_dev, double* bound_dev, void* stream)
 {
@@ -1274,7 +1314,7 @@ sg_status sg_plan_create_blocked(sg_context* ctx, const sg_problem* problems, in
     sg_plan* inner = nullptr;
     sg_status st = sg_plan_create(ctx, sub.data(), (int32_t)sub.size(), precision, &inner);
     if (st != SG_OK) return st;
-    std::unique_ptr<sg_plan> p(new sg_plan());
+    PlanOwner p(new sg_plan());
     p->ctx = ctx;
     p->precision = precision;
     p->n = n;
@@ -1286,6 +1326,9 @@ sg_status sg_plan_create_blocked(sg_context* ctx, const sg_problem* problems, in
     B.nsub = (int)sub.size();
     p->info = inner->info;
     p->info.effective_points = eff;
+    p->info.fp64_complex = 0;
+    for (int i = 0; i < n; ++i)
+        if (problems[i].family == SG_FAMILY_OSCILLATORY_QUADRATIC) p->info.fp64_complex++;
     inner->use_graph = false;      // graphs, when chosen, hold all three launches
     inner->info.graph = 0;
     p->use_graph = false;
@@ -1372,15 +1415,15 @@ sg_status sg_plan_autotune(sg_plan* p, const double* params_dev, double* out_dev
         for (int g = 0; g < 2 && st == SG_OK; ++g) {
             p->use_graph = g == 1;
             if ((st = sg_plan_execute(p, params_dev, out_dev, nullptr, stream)) != SG_OK) break;   // warm / capture
-            hipEventRecord(e0, (hipStream_t)stream);
+            (void)hipEventRecord(e0, (hipStream_t)stream);
             for (int r = 0; r < 20; ++r) sg_plan_execute(p, params_dev, out_dev, nullptr, stream);
-            hipEventRecord(e1, (hipStream_t)stream);
+            (void)hipEventRecord(e1, (hipStream_t)stream);
             hipError_t e = hipEventSynchronize(e1);
             if (e != hipSuccess) { st = hip_fail(p->ctx, e, "autotune sync"); break; }
-            hipEventElapsedTime(&ms[g], e0, e1);
+            (void)hipEventElapsedTime(&ms[g], e0, e1);
         }
-        hipEventDestroy(e0);
-        hipEventDestroy(e1);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
         blocked_sync_info(p, st == SG_OK && ms[1] < ms[0]);
         return st;
     }
@@ -1414,13 +1457,13 @@ sg_status sg_plan_autotune(sg_plan* p, const double* params_dev, double* out_dev
             for (int g = 0; g < (stream ? 2 : 1); ++g) {
                 p->use_graph = g == 1;
                 if ((st = sg_plan_execute(p, params_dev, out_dev, nullptr, stream)) != SG_OK) break;   // warm / capture
-                hipEventRecord(e0, s);
+                (void)hipEventRecord(e0, s);
                 for (int r = 0; r < reps; ++r) sg_plan_execute(p, params_dev, out_dev, nullptr, stream);
-                hipEventRecord(e1, s);
+                (void)hipEventRecord(e1, s);
                 hipError_t e = hipEventSynchronize(e1);
                 if (e != hipSuccess) { st = hip_fail(p->ctx, e, "autotune sync"); break; }
                 float ms = 0.f;
-                hipEventElapsedTime(&ms, e0, e1);
+                (void)hipEventElapsedTime(&ms, e0, e1);
                 if (ms < best_ms) { best_ms = ms; best = sc; best_g = p->use_graph; }
             }
             if (st != SG_OK) break;
@@ -1436,18 +1479,18 @@ sg_status sg_plan_autotune(sg_plan* p, const double* params_dev, double* out_dev
         for (int g = 0; g < (stream ? 2 : 1); ++g) {
             p->use_graph = g == 1;
             if ((st = sg_plan_execute(p, params_dev, out_dev, nullptr, stream)) != SG_OK) break;
-            hipEventRecord(e0, s);
+            (void)hipEventRecord(e0, s);
             for (int r = 0; r < reps; ++r) sg_plan_execute(p, params_dev, out_dev, nullptr, stream);
-            hipEventRecord(e1, s);
+            (void)hipEventRecord(e1, s);
             hipError_t e = hipEventSynchronize(e1);
             if (e != hipSuccess) { st = hip_fail(p->ctx, e, "autotune sync"); break; }
             float ms = 0.f;
-            hipEventElapsedTime(&ms, e0, e1);
+            (void)hipEventElapsedTime(&ms, e0, e1);
             if (ms < best_ms) { best_ms = ms; best = sc; best_g = p->use_graph; }
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     destroy_graphs(p);
     sg_status st2 = plan_repack(p, st == SG_OK ? best : saved);
     p->use_graph = st == SG_OK ? best_g : saved_g;
@@ -1507,29 +1550,35 @@ sg_status sg_plan_set_schedule_balanced(sg_plan* p, int32_t waves_per_simd, int3
 sg_status sg_plan_destroy(sg_plan* p)
 {
     if (!p) return SG_OK;
+    if (p->ctx) p->ctx->live_plans--;
+    plan_free(p);
+    return SG_OK;
+}
+
+// Release a plan's device buffers, graphs, block part and the plan itself.
+static void plan_free(sg_plan* p)
+{
     if (p->blocked) {
         BlockedPart* B = p->blocked;
         sg_plan_destroy(B->inner);
-        hipFree(B->d_subs);
-        hipFree(B->d_bprobs);
-        hipFree(B->d_params);
-        hipFree(B->d_out);
-        hipFree(B->d_bound);
+        (void)hipFree(B->d_subs);
+        (void)hipFree(B->d_bprobs);
+        (void)hipFree(B->d_params);
+        (void)hipFree(B->d_out);
+        (void)hipFree(B->d_bound);
         delete B;
         p->blocked = nullptr;
     }
     destroy_graphs(p);
-    hipFree(p->d_oscq);
-    hipFree(p->d_probs);
-    hipFree(p->d_wgs);
-    hipFree(p->d_fwd);
-    hipFree(p->d_queue);
-    hipFree(p->d_ws);
-    hipFree(p->d_pool64);
-    hipFree(p->d_pool32);
-    if (p->ctx) p->ctx->live_plans--;
+    (void)hipFree(p->d_oscq);
+    (void)hipFree(p->d_probs);
+    (void)hipFree(p->d_wgs);
+    (void)hipFree(p->d_fwd);
+    (void)hipFree(p->d_queue);
+    (void)hipFree(p->d_ws);
+    (void)hipFree(p->d_pool64);
+    (void)hipFree(p->d_pool32);
     delete p;
-    return SG_OK;
 }
 
 // Arguments of the plan-free path (sg_integrate, sg_integrate_noalloc).
@@ -1560,7 +1609,11 @@ sg_status sg_integrate(sg_context* ctx, const sg_problem* problem, int32_t preci
             return fail(ctx, SG_ERR_OUT_OF_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(e));
         }
         e = hipMemset(ctx->one_ws, 0, words * sizeof(double));
-        if (e != hipSuccess) return hip_fail(ctx, e, "hipMemset");
+        if (e != hipSuccess) {
+            (void)hipFree(ctx->one_ws);
+            ctx->one_ws = nullptr;
+            return hip_fail(ctx, e, "hipMemset");
+        }
     }
     const int rc = problem->family == SG_FAMILY_OSCILLATORY_QUADRATIC
                        ? launch_oscq(d, K, problem->rule, G, nullptr, params_dev, out_dev, bound_dev, ctx->one_ws,
@@ -1586,3 +1639,76 @@ sg_status sg_integrate_noalloc(sg_context* ctx, const sg_problem* problem, int32
 }
 
 }  // extern "C"
+
+const char* sg_version(void) { return SG_VERSION_STRING; }
+
+sg_status sg_context_save_tuning(const sg_context* ctx, const char* path)
+{
+    if (!ctx || !path) return SG_ERR_INVALID_ARGUMENT;
+    sg_context* c = const_cast<sg_context*>(ctx);
+    TuneFile f;
+    f.version = SG_VERSION_STRING;
+    f.arch = ctx->arch;
+    f.compute_units = ctx->n_cu;
+    for (const auto& kv : ctx->tuned) {
+        TuneRecord r;
+        r.key = kv.first;
+        const FwdSched& sc = kv.second.first;
+        r.cpl = sc.cpl;
+        r.gmax = sc.gmax;
+        r.cost_scaled = sc.cost_scaled ? 1 : 0;
+        r.persistent = sc.persistent ? 1 : 0;
+        r.balanced = sc.balanced;
+        r.graph = kv.second.second ? 1 : 0;
+        f.entries.push_back(r);
+    }
+    const std::string text = tune_file_write(f);
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* fp = std::fopen(tmp.c_str(), "wb");
+    if (!fp) return fail(c, SG_ERR_INVALID_ARGUMENT, std::string("cannot write ") + tmp);
+    const bool ok = std::fwrite(text.data(), 1, text.size(), fp) == text.size();
+    if (std::fclose(fp) != 0 || !ok) {
+        std::remove(tmp.c_str());
+        return fail(c, SG_ERR_INVALID_ARGUMENT, std::string("cannot write ") + tmp);
+    }
+    if (std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        return fail(c, SG_ERR_INVALID_ARGUMENT, std::string("cannot replace ") + path);
+    }
+    return SG_OK;
+}
+
+sg_status sg_context_load_tuning(sg_context* ctx, const char* path, int32_t* n_loaded)
+{
+    if (!ctx || !path) return SG_ERR_INVALID_ARGUMENT;
+    if (n_loaded) *n_loaded = 0;
+    FILE* fp = std::fopen(path, "rb");
+    if (!fp) return fail(ctx, SG_ERR_INVALID_ARGUMENT, std::string("cannot open ") + path);
+    std::string text;
+    char buf[4096];
+    size_t got = 0;
+    while ((got = std::fread(buf, 1, sizeof buf, fp)) > 0) {
+        text.append(buf, got);
+        if (text.size() > ((size_t)1 << 24)) {
+            std::fclose(fp);
+            return fail(ctx, SG_ERR_INVALID_ARGUMENT, "autotune file larger than 16 MiB");
+        }
+    }
+    std::fclose(fp);
+    TuneFile f;
+    std::string err;
+    if (!tune_file_read(text, f, err)) return fail(ctx, SG_ERR_INVALID_ARGUMENT, "autotune file: " + err);
+    // results of another build or device do not apply: load nothing
+    if (f.version != SG_VERSION_STRING || f.arch != ctx->arch || f.compute_units != ctx->n_cu) return SG_OK;
+    for (const TuneRecord& r : f.entries) {
+        FwdSched sc;
+        sc.cpl = r.cpl;
+        sc.gmax = r.gmax;
+        sc.cost_scaled = r.cost_scaled == 1;
+        sc.persistent = r.persistent == 1;
+        sc.balanced = r.balanced;
+        ctx->tuned[r.key] = std::make_pair(sc, r.graph == 1);
+    }
+    if (n_loaded) *n_loaded = (int32_t)f.entries.size();
+    return SG_OK;
+}

@@ -246,4 +246,42 @@ sg_status unrank(int d, int q, uint64_t rank, int32_t* coords, int32_t* levels, 
     return SG_OK;
 }
 
+// Frontier capacities of the point path (declared in sg_internal.hpp): over
+// every ordered list of active levels (>= 2) whose excesses sum to at most K,
+// the largest sum of node counts and the largest smallest two-group size.
+void points_frontier_sizes(const int* n, int K, int* emax, int* cmax)
+{
+    // ordered lists of active levels, depth-first; sizes fit in int (P <= 6561 for K <= 8)
+    int best_e = 0, best_c = 0;
+    int lev[kMaxK];
+    auto visit = [&](int len) {
+        int E = 0, P = 1;
+        for (int m = 0; m < len; ++m) {
+            E += n[lev[m]];
+            P *= n[lev[m]];
+        }
+        int c = 1 + P, pre = 1;
+        for (int m = 1; m <= len; ++m) {
+            pre *= n[lev[m - 1]];
+            c = std::min(c, pre + P / pre);
+        }
+        best_e = std::max(best_e, E);
+        best_c = std::max(best_c, c);
+    };
+    struct Rec {
+        static void go(int len, int budget, int K, int* lev, const decltype(visit)& f)
+        {
+            if (len > 0) f(len);
+            if (len == K) return;
+            for (int l = 2; l - 1 <= budget; ++l) {
+                lev[len] = l;
+                go(len + 1, budget - (l - 1), K, lev, f);
+            }
+        }
+    };
+    Rec::go(0, K, K, lev, visit);
+    *emax = best_e;
+    *cmax = best_c;
+}
+
 }  // namespace sg

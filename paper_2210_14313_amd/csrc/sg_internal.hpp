@@ -250,4 +250,22 @@ int launch_block_combine(const BlockProb* probs, int n, const double* sub_out, c
 bool build_records(const DeltaTable& t, std::vector<double>& rec64, std::vector<float>& rec32,
                    std::string& err);
 
+// Autotune results on disk (sg_context_save_tuning / _load_tuning): one
+// record per tuned plan shape.
+constexpr const char* kTuneFormat = "sgmdi-autotune-1";
+struct TuneRecord {
+    std::string key;   // plan shape: precision, count and a hash of the sorted (d, K, rule, family) list
+    int cpl = 4, gmax = 4, cost_scaled = 0, persistent = 0, balanced = 0, graph = 0;
+};
+struct TuneFile {
+    std::string version;    // SG_VERSION_STRING of the writer
+    std::string arch;       // the device's architecture name
+    int compute_units = 0;
+    std::vector<TuneRecord> entries;
+};
+std::string tune_file_write(const TuneFile& f);
+// Parse a document written by tune_file_write; false (with err) if it is
+// malformed or any record is out of range.
+bool tune_file_read(const std::string& text, TuneFile& f, std::string& err);
+
 }  // namespace sg

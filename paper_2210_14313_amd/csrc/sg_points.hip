@@ -466,40 +466,6 @@ __global__ void __launch_bounds__(256) k_points_finish(const double* __restrict_
 
 }  // namespace pts
 
-void points_frontier_sizes(const int* n, int K, int* emax, int* cmax)
-{
-    // ordered lists of active levels, depth-first; sizes fit in int (P <= 6561 for K <= 8)
-    int best_e = 0, best_c = 0;
-    int lev[kMaxK];
-    auto visit = [&](int len) {
-        int E = 0, P = 1;
-        for (int m = 0; m < len; ++m) {
-            E += n[lev[m]];
-            P *= n[lev[m]];
-        }
-        int c = 1 + P, pre = 1;
-        for (int m = 1; m <= len; ++m) {
-            pre *= n[lev[m - 1]];
-            c = std::min(c, pre + P / pre);
-        }
-        best_e = std::max(best_e, E);
-        best_c = std::max(best_c, c);
-    };
-    struct Rec {
-        static void go(int len, int budget, int K, int* lev, const decltype(visit)& f)
-        {
-            if (len > 0) f(len);
-            if (len == K) return;
-            for (int l = 2; l - 1 <= budget; ++l) {
-                lev[len] = l;
-                go(len + 1, budget - (l - 1), K, lev, f);
-            }
-        }
-    };
-    Rec::go(0, K, K, lev, visit);
-    *emax = best_e;
-    *cmax = best_c;
-}
 
 int launch_points(int family, const PointsLaunch& L, void* stream)
 {

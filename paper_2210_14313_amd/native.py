@@ -43,7 +43,8 @@ class SgPlanInfo(ctypes.Structure):
                 ("merge_flops", ctypes.c_uint64), ("block_threads", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int32), ("coords_per_lane", ctypes.c_int32),
                 ("max_group", ctypes.c_int32), ("graph", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("cost_scaled", ctypes.c_int32), ("balanced", ctypes.c_int32)]
+                ("cost_scaled", ctypes.c_int32), ("balanced", ctypes.c_int32),
+                ("fp64_complex", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -52,7 +53,8 @@ EXPORTS = ["sg_context_create", "sg_context_destroy", "sg_status_string", "sg_la
            "sg_rule_table", "sg_coefficient", "sg_unrank", "sg_unrank_device", "sg_plan_create",
            "sg_plan_execute", "sg_plan_execute_grad", "sg_plan_get_info", "sg_plan_autotune",
            "sg_plan_set_schedule", "sg_plan_set_schedule_balanced", "sg_plan_destroy", "sg_integrate",
-           "sg_integrate_noalloc", "sg_integrate_points", "sg_plan_create_blocked"]
+           "sg_integrate_noalloc", "sg_integrate_points", "sg_plan_create_blocked", "sg_version",
+           "sg_context_save_tuning", "sg_context_load_tuning"]
 
 
 def lib():
@@ -87,6 +89,9 @@ def lib():
         "sg_integrate": ([vp, P(SgProblem), i32, vp, vp, vp, vp], i32),
         "sg_integrate_noalloc": ([vp, P(SgProblem), i32, vp, vp, vp, vp], i32),
         "sg_integrate_points": ([vp, P(SgProblem), vp, vp, vp, u64, vp], i32),
+        "sg_version": ([], ctypes.c_char_p),
+        "sg_context_save_tuning": ([vp, ctypes.c_char_p], i32),
+        "sg_context_load_tuning": ([vp, ctypes.c_char_p, P(i32)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -105,6 +110,10 @@ def _check(st: int, ctx=None):
 
 
 # ------------------------------------------------------------- host calls
+def version() -> str:
+    return lib().sg_version().decode()
+
+
 def counts(d: int, q: int, rule: str):
     """(n_multi, n_points_rep, n_points_unique) of the window of (2.6)."""
     a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
@@ -160,6 +169,17 @@ class Context:
         if self.handle:
             lib().sg_context_destroy(self.handle)
             self.handle = ctypes.c_void_p()
+
+    def save_tuning(self, path: str) -> None:
+        """Write the context's autotune results (sg_context_save_tuning)."""
+        _check(lib().sg_context_save_tuning(self.handle, os.fsencode(path)), self.handle)
+
+    def load_tuning(self, path: str) -> int:
+        """Read autotune results; returns how many records were loaded (0 for
+        a file of another library version or device)."""
+        n = ctypes.c_int32(0)
+        _check(lib().sg_context_load_tuning(self.handle, os.fsencode(path), ctypes.byref(n)), self.handle)
+        return n.value
 
     def __del__(self):
         try:

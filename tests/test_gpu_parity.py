@@ -425,6 +425,42 @@ def test_balanced_schedule(api, orc):
         plan.close()
 
 
+def test_autotune_records_saved_and_loaded(api, orc, tmp_path):
+    """Autotune on the device, save the records, load them into a new
+    context: a plan of the same shape starts from the tuned schedule and
+    still matches the oracle; the file names this device."""
+    import torch
+    from paper_2210_14313_amd import native, workloads as W
+    b = W.random_small(21, 48, d_range=(1, 300), k_range=(0, 6))
+    params = api.params_tensor(b)
+    ref = _fact_ref(orc, b)
+    say("case autotune records")
+    ctx = native.Context()
+    plan = native.Plan(b.problems, "fp64", ctx=ctx)
+    out = torch.empty(len(b), dtype=torch.float64, device="cuda")
+    plan.autotune(params, out)
+    tuned = {k: v for k, v in plan.info().items() if k in ("coords_per_lane", "max_group", "persistent",
+                                                         "cost_scaled", "balanced")}
+    plan.close()
+    path = str(tmp_path / "tune.json")
+    ctx.save_tuning(path)
+    doc = json.load(open(path))
+    props = torch.cuda.get_device_properties(0)
+    assert doc["compute_units"] == props.multi_processor_count
+    assert doc["arch"].split(":")[0] == props.gcnArchName.split(":")[0]
+    assert doc["version"] == native.version() and len(doc["entries"]) == 1
+    ctx.close()
+    ctx2 = native.Context()
+    assert ctx2.load_tuning(path) == 1
+    plan = native.Plan(b.problems, "fp64", ctx=ctx2)
+    got_sched = {k: v for k, v in plan.info().items() if k in tuned}
+    assert got_sched == tuned
+    got = plan.execute(params).cpu().numpy()
+    assert np.max(np.abs(got - ref) / _scale(b, ref)) <= 1e-12
+    plan.close()
+    ctx2.close()
+
+
 @pytest.mark.parametrize("family", ["exp_sum", "oscillatory", "product_peak", "gaussian", "oscillatory_quadratic"])
 def test_plan_free_path_split_over_workgroups(api, orc, family):
     """sg_integrate splits an integrand over ceil(d / 256) workgroups (at most
