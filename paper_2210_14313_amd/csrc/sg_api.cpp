@@ -412,11 +412,16 @@ double fwd_coord_cost(const ProbDev& p, int npairs, uint64_t macs, int precision
     double c = (double)npairs * pv + (double)macs * mac + 1.65 * (double)(K * (K - 1) / 2 + K) + 4.0 * K + 31.0;
     if (p.family == SG_FAMILY_PRODUCT_PEAK) c += 40.0;            // log of the centre value
     if (K > 6 || !series) c *= 1.5;                                 // table-driven records (loads)
-    return c;
+    // latency floor: a coordinate's dependent chain (parameter, series,
+    // sums, product update) takes about this long however little work it
+    // holds, with two waves sharing a SIMD (per-wave timings of the kernel)
+    return c + 100.0;
 }
 double fwd_wave_overhead(int K, int family)
 {
-    return 450.0 + 125.0 * K + (family == SG_FAMILY_OSCILLATORY ? 100.0 : 0.0);
+    // class dispatch, the first parameter load, the lane reduction (growing
+    // with K), the read-out and the stores (per-wave timings of the kernel)
+    return 1800.0 + 40.0 * K + (family == SG_FAMILY_OSCILLATORY ? 60.0 : 0.0);
 }
 
 // Equal-cost waves, `sc.balanced` per SIMD.  For a target wave cost T every
@@ -1147,6 +1152,12 @@ static sg_status plan_repack(sg_plan* p, const FwdSched& sc_in)
     if (sc.balanced > 0) sc.persistent = false;   // placement relies on hardware dispatch order
     std::vector<FwdWG> fwd = sc.balanced > 0 ? pack_forward_balanced(p->probs, p->coord_cost, sc, p->n_cu, nullptr)
                                              : pack_forward(p->probs, p->unit_cost, sc);
+    // the workgroup-level flag the kernel reads instead of the four group sizes
+    for (FwdWG& e : fwd) {
+        e.w[0].grouped = 0;
+        for (int i = 0; i < 4; ++i)
+            if (e.w[i].group > 1) e.w[0].grouped = 1;
+    }
     if (fwd.size() > p->fwd_capacity) {
         // the new buffer first: on failure the plan keeps its schedule
         FwdWG* grown = nullptr;

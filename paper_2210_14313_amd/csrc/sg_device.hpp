@@ -854,12 +854,15 @@ __device__ __forceinline__ double coord_param(const RawParam& r, CoordParam& cp)
     }
 }
 
-// Wave-uniform description of one forward wave (from its descriptor).
+// One forward wave: its class and shape (wave-uniform) and this lane's
+// problem, resolved from the descriptor before the sweep starts.
 struct WaveInfo {
     int lw, rank, group, nprob;
     const double* r64;     // the class's record table (table-driven path)
     const float* r32;
-    const FwdSeg* seg;     // the problems by lane segment
+    int d;                 // this lane's problem: dimension (0: idle lane),
+    int out_index;         // its slot in out / bound,
+    int64_t param_offset;  // its parameters in the caller's array
 };
 
 // Depth of the product tree behind one result: a lane's sequential chain of
@@ -875,7 +878,9 @@ __device__ __forceinline__ int tree_depth(int d, int lw, int group)
 // the segments are reduced and every segment's last lane reads out (group of
 // one wave) or, for a multi-wave problem, leaves the wave's state in LDS for
 // the group leader.  The next coordinate's parameters are loaded before the
-// current coordinate is evaluated, so their latency overlaps the arithmetic.
+// current coordinate is evaluated, so their latency overlaps the arithmetic
+// (loading every coordinate's parameters up front instead makes all waves
+// fetch the whole batch at once and wait for it before computing).
 template <int PREC, int K, int RULE, int FAM>
 __device__ __forceinline__ void wave_sweep(const WaveInfo& wi, const double* __restrict__ params, double* out,
                                            double* bound, double* lds_slot)
@@ -884,15 +889,9 @@ __device__ __forceinline__ void wave_sweep(const WaveInfo& wi, const double* __r
     const bool want_bound = bound != nullptr;
     const int lane = threadIdx.x & 63;
     const int W = 1 << wi.lw;
-    const int sg = lane >> wi.lw, lis = lane & (W - 1);
-    int d = 0, out_index = -1;
-    const double* __restrict__ prm = params;
-    if (sg < wi.nprob) {
-        const FwdSeg rec = wi.seg[sg];
-        d = rec.d;
-        out_index = rec.out_index;
-        prm = params + rec.param_offset;
-    }
+    const int lis = lane & (W - 1);
+    const int d = wi.d, out_index = wi.out_index;
+    const double* __restrict__ prm = params + wi.param_offset;
 
     Acc x;
     acc_identity<K>(x);
@@ -1015,6 +1014,60 @@ __device__ __forceinline__ void group_finish_k(int rule, int family, int group, 
     else readout<PREC, K, FAM_PEAK>(x, lp.d, lp.out_index, prm, np, depth, out, bound);
 }
 
+// Flat dispatch of a forward wave to its class's code: one switch on a
+// class index.  (Nested run-time tests of K, then rule, then family make a
+// failing test jump over a whole class body to the next test, so a wave
+// crosses up to a dozen cold instruction-cache lines before its first
+// useful instruction.)  The compiled-table path (K <= KCONST) has code per
+// rule; the table-driven path per structure class, under the class's
+// representative rule.
+__host__ __device__ __forceinline__ constexpr int fam_slot(int family)
+{
+    return family == FAM_EXP ? 0 : family == FAM_OSC ? 1 : family == FAM_PEAK ? 2 : 3;
+}
+__host__ __device__ __forceinline__ constexpr int representative_rule(int rule)
+{
+    return rule_class_of(rule) == RC_NESTED ? SG_RULE_CLENSHAW_CURTIS
+           : rule_class_of(rule) == RC_GL2  ? SG_RULE_GAUSS_LEGENDRE
+           : rule_class_of(rule) == RC_GP   ? SG_RULE_GAUSS_PATTERSON
+                                            : SG_RULE_GAUSS_LEGENDRE_PAPER;
+}
+__host__ __device__ constexpr int class_slot(int K, int rule, int fslot) { return (K * 8 + rule) * 4 + fslot; }
+__host__ __device__ __forceinline__ constexpr int class_index(int K, int rule, int family)
+{
+    return class_slot(K, K <= KCONST ? rule : representative_rule(rule), fam_slot(family));
+}
+
+template <int PREC, int KMAXP, bool GAUSS, int K, int R, int F>
+__device__ __forceinline__ void wave_case(const WaveInfo& wi, const double* params, double* out, double* bound,
+                                          double* lds_slot)
+{
+    constexpr int FAM = F == 0 ? FAM_EXP : F == 1 ? FAM_OSC : F == 2 ? FAM_PEAK : FAM_GAUSS;
+    if constexpr (K <= KMAXP && (GAUSS || FAM != FAM_GAUSS) && (K <= KCONST || R == representative_rule(R)))
+        wave_sweep<PREC, K, R, FAM>(wi, params, out, bound, lds_slot);
+}
+
+template <int PREC, int KMAXP, bool GAUSS>
+__device__ __forceinline__ void wave_switch(int cls, const WaveInfo& wi, const double* params, double* out,
+                                            double* bound, double* lds_slot)
+{
+    static_assert(KMAXP <= 8, "class index covers K <= 8");
+    switch (cls) {
+#define SG_C(K, R, F)                                                                   \
+    case class_slot(K, R, F):                                                           \
+        wave_case<PREC, KMAXP, GAUSS, K, R, F>(wi, params, out, bound, lds_slot);         \
+        break;
+#define SG_CR(K, R) SG_C(K, R, 0) SG_C(K, R, 1) SG_C(K, R, 2) SG_C(K, R, 3)
+#define SG_CK(K) SG_CR(K, 1) SG_CR(K, 2) SG_CR(K, 3) SG_CR(K, 4) SG_CR(K, 5)
+        SG_CK(0) SG_CK(1) SG_CK(2) SG_CK(3) SG_CK(4) SG_CK(5) SG_CK(6) SG_CK(7) SG_CK(8)
+#undef SG_CK
+#undef SG_CR
+#undef SG_C
+    default:
+        break;
+    }
+}
+
 // Dispatch a runtime K in [0, KMAXP] to a compile-time K.
 template <int KMAXP, class F>
 __device__ __forceinline__ void switch_k(int K, F&& f)
@@ -1028,6 +1081,12 @@ __device__ __forceinline__ void switch_k(int K, F&& f)
 // spanning several waves sits in consecutive waves of the workgroup and is
 // merged through LDS by its first wave.  Every thread of the workgroup must
 // call this (it may synchronise the workgroup).
+// A 32-bit value from another lane of the wave (ds_bpermute).
+__device__ __forceinline__ int lane_read(int v, int src_lane)
+{
+    return __builtin_amdgcn_ds_bpermute(src_lane << 2, v);
+}
+
 template <int PREC, int KMAXP, bool GAUSS>
 __device__ __forceinline__ void run_workgroup(const FwdWG* wg, const double* __restrict__ pool64,
                                               const float* __restrict__ pool32, const double* __restrict__ params,
@@ -1035,6 +1094,11 @@ __device__ __forceinline__ void run_workgroup(const FwdWG* wg, const double* __r
 {
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const FwdWave* wd = &wg->w[w];
+    // lane i fetches segment record i mod kWaveProbs together with the
+    // wave's scalars (no dependence between the two loads); each lane then
+    // takes its own segment's record from the lane that holds it
+    const int lane = threadIdx.x & 63;
+    const FwdSeg cand = wd->seg[lane & (kWaveProbs - 1)];
     const int K = __builtin_amdgcn_readfirstlane(wd->K);
     const int rule = __builtin_amdgcn_readfirstlane(wd->rule);
     const int family = __builtin_amdgcn_readfirstlane(wd->family);
@@ -1045,14 +1109,21 @@ __device__ __forceinline__ void run_workgroup(const FwdWG* wg, const double* __r
     wi.nprob = __builtin_amdgcn_readfirstlane(wd->nprob);
     wi.r64 = pool64 + __builtin_amdgcn_readfirstlane(wd->off64);
     wi.r32 = pool32 + __builtin_amdgcn_readfirstlane(wd->off32);
-    wi.seg = wd->seg;
-    const bool grouped = wg->w[0].group > 1 || wg->w[1].group > 1 || wg->w[2].group > 1 || wg->w[3].group > 1;
-    if (wi.nprob > 0) {
-        switch_k<KMAXP>(K, [&](auto kc) {
-            wave_dispatch_k<PREC, decltype(kc)::value, GAUSS>(rule, family, wi, params, out, bound,
-                                                              lds + w * ACC_WORDS);
-        });
+    {
+        const int sg = lane >> wi.lw;   // lw >= 2: sg < kWaveProbs
+        const int d = lane_read(cand.d, sg);
+        const int oi = lane_read(cand.out_index, sg);
+        const unsigned int plo = (unsigned int)lane_read((int)(cand.param_offset & 0xffffffffll), sg);
+        const int phi = lane_read((int)(cand.param_offset >> 32), sg);
+        const bool live = sg < wi.nprob;
+        wi.d = live ? d : 0;
+        wi.out_index = live ? oi : -1;
+        wi.param_offset = live ? (int64_t)(((uint64_t)(unsigned int)phi << 32) | plo) : 0;
     }
+    const bool grouped = __builtin_amdgcn_readfirstlane(wg->w[0].grouped) != 0;
+    if (wi.nprob > 0)
+        wave_switch<PREC, KMAXP, GAUSS>(__builtin_amdgcn_readfirstlane(class_index(K, rule, family)), wi, params, out,
+                                        bound, lds + w * ACC_WORDS);
     if (!grouped) return;
     __syncthreads();
     if (wi.nprob > 0 && wi.group > 1 && wi.rank == 0 && (threadIdx.x & 63) == 0) {

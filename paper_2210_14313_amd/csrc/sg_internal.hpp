@@ -141,7 +141,8 @@ constexpr int kWaveProbs = 16;
 struct FwdWave {
     int16_t K, rule, family, lw;   // class; lw = log2(lanes per problem), 2..6
     int16_t rank, group;           // wave rank inside its group; group size (1, 2, 4)
-    int16_t nprob, pad;            // problems in this wave (0: idle wave)
+    int16_t nprob;                 // problems in this wave (0: idle wave)
+    int16_t grouped;               // in w[0] only: 1 if any wave of the workgroup has group > 1
     int32_t off64, off32;          // the class's record table in the pools
     int32_t pad2[2];
     FwdSeg seg[kWaveProbs];        // the problems, by lane segment

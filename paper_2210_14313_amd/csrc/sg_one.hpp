@@ -53,7 +53,7 @@ __device__ __forceinline__ void one_readout(int rule, int family, const Acc& x, 
 // workgroup's partial in `x`.
 template <int PREC, int K, bool GAUSS>
 __device__ __forceinline__ void one_workgroup(int d, int rule, int family, int G, const double* params,
-                                              double* out, double* bound, double* lds, const FwdSeg* seg, Acc& x)
+                                              double* out, double* bound, double* lds, Acc& x)
 {
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     WaveInfo wi;
@@ -62,7 +62,9 @@ __device__ __forceinline__ void one_workgroup(int d, int rule, int family, int G
     wi.group = 4 * G;
     wi.nprob = 1;
     tabd::records(rule, K, &wi.r64, &wi.r32);
-    wi.seg = seg;
+    wi.d = d;
+    wi.out_index = 0;
+    wi.param_offset = 0;
     // every wave stores its product in its LDS slot (group > 1); the bound's
     // sums are kept when a bound is asked for
     wave_dispatch_k<PREC, K, GAUSS>(rule, family, wi, params, out, bound, lds + w * ACC_WORDS);
@@ -81,10 +83,10 @@ __device__ __forceinline__ void one_workgroup(int d, int rule, int family, int G
 
 template <int PREC, int K, bool GAUSS>
 __device__ __forceinline__ void one_body(int d, int rule, int family, int G, const double* params, double* out,
-                                         double* bound, double* scratch, double* lds, const FwdSeg* seg, int* last)
+                                         double* bound, double* scratch, double* lds, int* last)
 {
     Acc x;
-    one_workgroup<PREC, K, GAUSS>(d, rule, family, G, params, out, bound, lds, seg, x);
+    one_workgroup<PREC, K, GAUSS>(d, rule, family, G, params, out, bound, lds, x);
     // product-tree depth behind the result: a lane's chain, the DPP scan, the
     // join of four waves, then (G > 1) a thread's run of partials and the tree
     const int chain = (d + 256 * G - 1) / (256 * G);
@@ -140,18 +142,10 @@ k_one(int d, int K, int rule, int family, int G, const double* __restrict__ para
       double* __restrict__ bound, double* __restrict__ scratch)
 {
     __shared__ double lds[kOneTree * ACC_WORDS];
-    __shared__ FwdSeg seg;
     __shared__ int last;
-    if (threadIdx.x == 0) {
-        seg.d = d;
-        seg.out_index = 0;
-        seg.param_offset = 0;
-    }
-    __syncthreads();
     static_for<0, KMAXP + 1>([&](auto kc) __attribute__((always_inline)) {
         if (K == decltype(kc)::value)
-            one_body<PREC, decltype(kc)::value, GAUSS>(d, rule, family, G, params, out, bound, scratch, lds, &seg,
-                                                       &last);
+            one_body<PREC, decltype(kc)::value, GAUSS>(d, rule, family, G, params, out, bound, scratch, lds, &last);
     });
 }
 
