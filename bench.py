@@ -58,13 +58,20 @@ PINNED_SCHEDULE = {"fp32c": ("balanced", 2, 0), "fp32e": ("balanced", 2, 0), "fp
 
 
 def kernel_source_hash() -> str:
+    """Hash of the sources the headline forward kernel is built from: its
+    device code and tables, and the forward descriptor layout (the part of
+    sg_internal.hpp from FwdSeg to FwdWG)."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2210_14313_amd", "csrc")
-    for f in ("sg_device.hpp", "sg_internal.hpp", "sg_fwd_inst.hpp", "sg_fwd_p1_k6.hip", "sg_rules.cpp",
-              "gen_tables.cpp"):
+    for f in ("sg_device.hpp", "sg_fwd_inst.hpp", "sg_fwd_p1_k6.hip", "sg_rules.cpp", "gen_tables.cpp"):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(csrc, "sg_internal.hpp"), "rb") as fh:
+        text = fh.read()
+    a = text.index(b"struct FwdSeg {")
+    b = text.index(b"};", text.index(b"struct FwdWG {")) + 2
+    h.update(text[a:b])
     return h.hexdigest()[:16]
 
 

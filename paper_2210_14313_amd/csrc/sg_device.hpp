@@ -103,6 +103,35 @@ __device__ __forceinline__ float series32w(float z)
     return p;
 }
 
+// sinh(v)/v = sum z^k/(2k+1)! (z = v^2; sin(v)/v with z = -v^2) on |v| <= 1,
+// for the compiled-table reverse sweep: first dropped term relative to 1: 1/21! < 2e-20 (FP64, 10 terms),
+// 1/13! < 2e-10 (FP32, 6 terms).
+__device__ __forceinline__ double series_s64w(double z)
+{
+    double p = 1.0 / 121645100408832000.0;             // 1/19!
+    p = fma(p, z, 1.0 / 355687428096000.0);            // 1/17!
+    p = fma(p, z, 1.0 / 1307674368000.0);              // 1/15!
+    p = fma(p, z, 1.0 / 6227020800.0);                 // 1/13!
+    p = fma(p, z, 1.0 / 39916800.0);                   // 1/11!
+    p = fma(p, z, 1.0 / 362880.0);                     // 1/9!
+    p = fma(p, z, 1.0 / 5040.0);                       // 1/7!
+    p = fma(p, z, 1.0 / 120.0);                        // 1/5!
+    p = fma(p, z, 1.0 / 6.0);                          // 1/3!
+    p = fma(p, z, 1.0);
+    return p;
+}
+
+__device__ __forceinline__ float series_s32w(float z)
+{
+    float p = 1.0f / 39916800.0f;                      // 1/11!
+    p = fmaf(p, z, 1.0f / 362880.0f);
+    p = fmaf(p, z, 1.0f / 5040.0f);
+    p = fmaf(p, z, 1.0f / 120.0f);
+    p = fmaf(p, z, 1.0f / 6.0f);
+    p = fmaf(p, z, 1.0f);
+    return p;
+}
+
 // Per-coordinate family parameters, read once per coordinate.
 struct CoordParam {
     double p0;    // exp: c; osc: a; peak: beta = b^-2; gaussian: c
@@ -447,7 +476,9 @@ __device__ __forceinline__ void surplus64_const(const CoordParam& cp, double (&d
                 constexpr double wa = R::r64[off + J * rl + rl - 1];
                 et = fma(wa, fabs(sv), et);
             } else if constexpr (pair_base<RC>(L) + J == TableFacts<RULE, K>::max_pair()) {
-                et = TableFacts<RULE, K>::total_wabs() * fabs(sv);
+                // (a constexpr variable: the table walk must not run per coordinate)
+                constexpr double wt = TableFacts<RULE, K>::total_wabs();
+                et = wt * fabs(sv);
             }
         });
     });
@@ -597,6 +628,83 @@ __device__ __forceinline__ void surplus32e_const(const CoordParam& cp, double (&
     eps += (double)epsf;
 }
 
+// Derivative surpluses d delta_t[e] / d c_t of the exp-sum (c) and
+// oscillatory (a) families on the compiled-table path (|c| <= 2): per pair
+// ds/dc = +-2 c y^2 S(+-c^2 y^2), S(z) = sinh(v)/v or sin(v)/v, against the
+// compile-time difference weights.  FP64: an FMA chain per row; FP32: the
+// blocked two-sum of the forward sweep against hi+lo weights.
+template <int RULE, int K, int FAM>
+__device__ __forceinline__ void dsurplus64_const(const CoordParam& cp, double (&dd)[MAXK + 1])
+{
+    constexpr int RC = rule_class_of(RULE);
+    using R = tab::Rec<RULE, K>;
+#pragma unroll
+    for (int e = 0; e <= MAXK; ++e) dd[e] = 0.0;
+    const double c2s = signed_c2<FAM>(cp.p0);
+    const double f = (FAM == FAM_EXP ? 2.0 : -2.0) * cp.p0;
+    static_for<2, K + 2>([&](auto Lc) {
+        constexpr int L = decltype(Lc)::value;
+        constexpr int off = rc_off64(RC, K, L), rl = rc_rec64(RC, K, L);
+        constexpr int lo = rc_elo(L), hi = rc_ehi(RC, K, L);
+        static_for<0, rc_pairs(RC, L)>([&](auto Jc) {
+            constexpr int J = decltype(Jc)::value;
+            constexpr double y = R::r64[off + J * rl];
+            constexpr double y2 = y * y;
+            const double dv = (f * y2) * series_s64w(c2s * y2);
+            static_for<lo, hi + 1>([&](auto Ec) {
+                constexpr int E = decltype(Ec)::value;
+                constexpr double w = R::r64[off + J * rl + 1 + E - lo];
+                if constexpr (first_level<RC, K>(E) == L && J == 0) dd[E] = w * dv;
+                else dd[E] = fma(w, dv, dd[E]);
+            });
+        });
+    });
+}
+
+template <int RULE, int K, int FAM>
+__device__ __forceinline__ void dsurplus32_const(const CoordParam& cp, double (&dd)[MAXK + 1])
+{
+    constexpr int RC = rule_class_of(RULE);
+    using R = tab::Rec<RULE, K>;
+    float hi[MAXK + 1], lo[MAXK + 1], part[MAXK + 1];
+#pragma unroll
+    for (int e = 0; e <= MAXK; ++e) { hi[e] = 0.0f; lo[e] = 0.0f; part[e] = 0.0f; }
+    const float c2s = (float)signed_c2<FAM>(cp.p0);
+    const float f = (float)((FAM == FAM_EXP ? 2.0 : -2.0) * cp.p0);
+    static_for<2, K + 2>([&](auto Lc) {
+        constexpr int L = decltype(Lc)::value;
+        constexpr int off = rc_off64(RC, K, L), rl = rc_rec64(RC, K, L);
+        constexpr int off32 = rc_off32(RC, K, L), rl32 = rc_rec32(RC, K, L);
+        constexpr int elo = rc_elo(L), ehi = rc_ehi(RC, K, L);
+        static_for<0, rc_pairs(RC, L)>([&](auto Jc) {
+            constexpr int J = decltype(Jc)::value;
+            constexpr double y = R::r64[off + J * rl];
+            constexpr double y2 = y * y;
+            constexpr float y2h = (float)y2;
+            constexpr float y2l = (float)(y2 - (double)y2h);
+            const float z = y2l != 0.0f ? fmaf(c2s, y2h, c2s * y2l) : c2s * y2h;
+            const float sv = (f * y2h) * series_s32w(z);
+            static_for<elo, ehi + 1>([&](auto Ec) {
+                constexpr int E = decltype(Ec)::value;
+                constexpr float wh = R::r32[off32 + J * rl32 + 2 * (E - elo)];
+                constexpr float wl = R::r32[off32 + J * rl32 + 2 * (E - elo) + 1];
+                constexpr int k = row_index<RC, K>(E, L, J), n = row_length<RC, K>(E);
+                constexpr bool block_end = (k % kSumBlock == kSumBlock - 1) || (k == n - 1);
+                if constexpr (k % kSumBlock == 0) part[E] = wh * sv;
+                else part[E] = fmaf(wh, sv, part[E]);
+                if constexpr (k == 0) lo[E] = wl * sv;
+                else lo[E] = fmaf(wl, sv, lo[E]);
+                if constexpr (block_end) {
+                    if constexpr (k < kSumBlock) hi[E] = part[E];
+                    else two_sum_into(hi[E], lo[E], part[E]);
+                }
+            });
+        });
+    });
+#pragma unroll
+    for (int e = 0; e <= MAXK; ++e) dd[e] = (double)hi[e] + (double)lo[e];
+}
+
 // ----------------------------------------------------------- merge state
 // Running polynomial a and the affine partial sum ls (FP64); for the error
 // bound, m = sum_t sum_e |delta_t[e]|, eps = sum_t sum_p sum_e |dW[e][p]| |s_p|
@@ -704,6 +812,53 @@ __device__ __forceinline__ void wave_reduce_seg(Acc& x, int lw, bool want_bound)
     // lane 15 of each row now holds its row; row 1 takes row 0's total, row 3 row 2's
     if (lw >= 5) dpp_step<K, ROW_BCAST15, 0xA>(x, want_bound);
     if (lw >= 6) dpp_step<K, ROW_BCAST31, 0xC>(x, want_bound);
+}
+
+// Inclusive product scan of a truncated polynomial over the wave's 64 lanes
+// (lane l ends with the product of lanes 0..l), by the DPP steps of
+// wave_reduce_seg on plain polynomials; lanes without a source multiply by
+// the identity.
+template <int K, int CTRL, int ROW_MASK>
+__device__ __forceinline__ void poly_dpp_step(double (&a)[MAXK + 1])
+{
+    double o[MAXK + 1];
+    o[0] = 0.0;
+#pragma unroll
+    for (int k = 1; k <= K; ++k) o[k] = dpp_f64<CTRL, ROW_MASK>(a[k], 0.0);
+    pmul<K>(a, o);
+}
+
+template <int K>
+__device__ __forceinline__ void poly_scan_incl(double (&a)[MAXK + 1])
+{
+    poly_dpp_step<K, 0x111, 0xF>(a);
+    poly_dpp_step<K, 0x112, 0xF>(a);
+    poly_dpp_step<K, 0x114, 0xF>(a);
+    poly_dpp_step<K, 0x118, 0xF>(a);
+    poly_dpp_step<K, 0x142, 0xA>(a);
+    poly_dpp_step<K, 0x143, 0xC>(a);
+}
+
+// Sum over the wave's 64 lanes, returned to every lane.
+__device__ __forceinline__ double wave_sum64(double v)
+{
+    v += dpp_f64<0x111, 0xF>(v, 0.0);
+    v += dpp_f64<0x112, 0xF>(v, 0.0);
+    v += dpp_f64<0x114, 0xF>(v, 0.0);
+    v += dpp_f64<0x118, 0xF>(v, 0.0);
+    v += dpp_f64<0x142, 0xA>(v, 0.0);
+    v += dpp_f64<0x143, 0xC>(v, 0.0);
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, 63), hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double lane_double(double v, int src)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)b);
+    const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
 constexpr int ACC_WORDS = MAXK + 4;   // doubles per wave in LDS
@@ -943,7 +1098,10 @@ __device__ __forceinline__ void wave_sweep(const WaveInfo& wi, const double* __r
     if (lis != W - 1) return;
     if (wi.group == 1) {
         if (out_index >= 0)
-            readout<PREC, K, FAM>(x, d, out_index, prm, total_pairs<RC, K>(), tree_depth(d, wi.lw, 1), out, bound);
+        {
+            constexpr int np = total_pairs<RC, K>();
+            readout<PREC, K, FAM>(x, d, out_index, prm, np, tree_depth(d, wi.lw, 1), out, bound);
+        }
     } else {
         acc_store<K>(x, lds_slot);
     }
@@ -998,10 +1156,9 @@ __device__ __forceinline__ void group_finish_k(int rule, int family, int group, 
     }
     const double* prm = params + lp.param_offset;
     const int rc = rule_class_of(rule);
-    const int np = rc == RC_NESTED ? total_pairs<RC_NESTED, K>()
-                   : rc == RC_GL2  ? total_pairs<RC_GL2, K>()
-                   : rc == RC_GP   ? total_pairs<RC_GP, K>()
-                                   : total_pairs<RC_GLP, K>();
+    constexpr int np_nested = total_pairs<RC_NESTED, K>(), np_gl2 = total_pairs<RC_GL2, K>(),
+                  np_gp = total_pairs<RC_GP, K>(), np_glp = total_pairs<RC_GLP, K>();
+    const int np = rc == RC_NESTED ? np_nested : rc == RC_GL2 ? np_gl2 : rc == RC_GP ? np_gp : np_glp;
     const int depth = tree_depth(lp.d, 6, group);
     if constexpr (GAUSS) {
         if (family == FAM_GAUSS) {
@@ -1314,12 +1471,15 @@ __device__ __forceinline__ void poly_one(double (&x)[MAXK + 1])
 
 constexpr int ADJ_WORDS = MAXK + 2;   // doubles per wave in LDS: wave product + affine sum
 
-template <int PREC, int K, int RC, int FAM>
+template <int PREC, int K, int RULE, int FAM>
 __device__ __forceinline__ void wave_adjoint(const ProbDev& P, int rank, int group, bool grouped,
                                              const double* pool64, const float* pool32,
                                              const double* __restrict__ params, const double* __restrict__ gout,
                                              double* __restrict__ grad, double* __restrict__ ws, double* lds)
 {
+    constexpr int RC = rule_class_of(RULE);
+    // the compiled-table surpluses (series forms, |parameter| <= 2)
+    constexpr bool kConst = K <= KCONST && (FAM == FAM_EXP || FAM == FAM_OSC);
     const int lane = threadIdx.x & 63;
     const int d = P.d;
     const double* __restrict__ r64 = pool64 + P.off64;
@@ -1327,6 +1487,9 @@ __device__ __forceinline__ void wave_adjoint(const ProbDev& P, int rank, int gro
     const double* __restrict__ prm = params + P.param_offset;
     double* __restrict__ wsp = ws + P.ws_off;
     const int stride = 64 * group;
+    // at most one coordinate per lane: its surpluses stay in registers and
+    // the workspace is not touched
+    const bool single = d <= stride;
 
     auto coord_param = [&](int t, CoordParam& cp) -> double {
         if constexpr (FAM == FAM_EXP) {
@@ -1350,44 +1513,72 @@ __device__ __forceinline__ void wave_adjoint(const ProbDev& P, int rank, int gro
         }
     };
 
-    // pass 1: surpluses of this lane's coordinates (kept in the workspace),
-    // the lane's product and affine sum
+    // pass 1: surpluses of this lane's coordinates (in the workspace unless
+    // single), the lane's product and affine sum
     double L[MAXK + 1];
     poly_one<K>(L);
+    double own[MAXK + 1];
+    poly_one<K>(own);
     double ls = 0.0;
     for (int t = rank * 64 + lane; t < d; t += stride) {
-        int opaque = 0;
-        asm volatile("" : "+s"(opaque));
         CoordParam cp;
         ls += coord_param(t, cp);
         double del[MAXK + 1], eps = 0.0;
-        if constexpr (PREC == SG_PREC_FP64) surplus64<K, RC, FAM>(r64 + opaque, cp, false, del, eps);
-        else surplus32<K, RC, FAM>(r64 + opaque, r32 + opaque, cp, false, del, eps);
+        bool done = false;
+        if constexpr (kConst) {
+            if (fabs(cp.p0) <= 2.0) {
+                if constexpr (PREC == SG_PREC_FP64) surplus64_const<RULE, K, FAM>(cp, del, eps);
+                else surplus32_const<RULE, K, FAM>(cp, del, eps);
+                done = true;
+            }
+        }
+        if (!done) {
+            int opaque = 0;
+            asm volatile("" : "+s"(opaque));
+            if constexpr (PREC == SG_PREC_FP64) surplus64<K, RC, FAM>(r64 + opaque, cp, false, del, eps);
+            else surplus32<K, RC, FAM>(r64 + opaque, r32 + opaque, cp, false, del, eps);
+        }
+        if (single) {
 #pragma unroll
-        for (int k = 1; k <= K; ++k) wsp[(size_t)t * K + (k - 1)] = del[k];
+            for (int k = 1; k <= K; ++k) own[k] = del[k];
+        } else {
+#pragma unroll
+            for (int k = 1; k <= K; ++k) wsp[(size_t)t * K + (k - 1)] = del[k];
+        }
         pmul<K>(L, del);
     }
 
-    // exclusive prefix / suffix products across the wave's lanes
-    double pre[MAXK + 1], suf[MAXK + 1], tmp[MAXK + 1];
+    // exclusive prefix and suffix products across the wave's lanes: DPP
+    // scans, the suffix as the prefix scan of the lanes in reverse order
+    double pre[MAXK + 1], suf[MAXK + 1];
 #pragma unroll
-    for (int k = 0; k <= MAXK; ++k) { pre[k] = L[k]; suf[k] = L[k]; }
-    for (int off = 1; off < 64; off <<= 1) {
-        shfl_poly_up<K>(tmp, pre, off);
-        if (lane >= off) pmul<K>(pre, tmp);
-        shfl_poly_down<K>(tmp, suf, off);
-        if (lane + off < 64) pmul<K>(suf, tmp);
-    }
+    for (int k = 0; k <= MAXK; ++k) { pre[k] = L[k]; suf[k] = 0.0; }
+#pragma unroll
+    for (int k = 1; k <= K; ++k) suf[k] = lane_double(L[k], 63 - lane);
+    poly_scan_incl<K>(pre);
+    poly_scan_incl<K>(suf);
     double wave_tot[MAXK + 1];
+    wave_tot[0] = 0.0;
 #pragma unroll
-    for (int k = 1; k <= K; ++k) wave_tot[k] = __shfl(pre[k], 63);
-    shfl_poly_up<K>(tmp, pre, 1);
+    for (int k = 1; k <= K; ++k) {
+        const long long bits = __double_as_longlong(pre[k]);
+        const int lo = __builtin_amdgcn_readlane((int)bits, 63), hi = __builtin_amdgcn_readlane((int)(bits >> 32), 63);
+        wave_tot[k] = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    }
+    {
+        double tmp[MAXK + 1];
 #pragma unroll
-    for (int k = 1; k <= K; ++k) pre[k] = lane == 0 ? 0.0 : tmp[k];
-    shfl_poly_down<K>(tmp, suf, 1);
+        for (int k = 1; k <= K; ++k) {
+            tmp[k] = dpp_f64<0x138, 0xF>(pre[k], 0.0);          // wave_shr:1, lane 0 gets the identity
+            suf[k] = lane_double(suf[k], lane == 63 ? 0 : 62 - lane);
+        }
 #pragma unroll
-    for (int k = 1; k <= K; ++k) suf[k] = lane == 63 ? 0.0 : tmp[k];
-    for (int m = 1; m < 64; m <<= 1) ls += __shfl_xor(ls, m);
+        for (int k = 1; k <= K; ++k) {
+            pre[k] = tmp[k];
+            if (lane == 63) suf[k] = 0.0;
+        }
+    }
+    ls = wave_sum64(ls);
 
     // across the waves of the group: wave products in rank order
     double total[MAXK + 1];
@@ -1441,19 +1632,19 @@ __device__ __forceinline__ void wave_adjoint(const ProbDev& P, int rank, int gro
     // pass 2: per coordinate, R_t from prefix, suffix and the lane's other
     // coordinates; then the contraction with the derivative surpluses
     for (int t = rank * 64 + lane; t < d; t += stride) {
-        int opaque = 0;
-        asm volatile("" : "+s"(opaque));
         double R[MAXK + 1];
 #pragma unroll
         for (int k = 0; k <= MAXK; ++k) R[k] = pre[k];
         pmul<K>(R, suf);
-        for (int t2 = rank * 64 + lane; t2 < d; t2 += stride) {
-            if (t2 == t) continue;
-            double o[MAXK + 1];
-            o[0] = 1.0;
+        if (!single) {
+            for (int t2 = rank * 64 + lane; t2 < d; t2 += stride) {
+                if (t2 == t) continue;
+                double o[MAXK + 1];
+                o[0] = 1.0;
 #pragma unroll
-            for (int k = 1; k <= K; ++k) o[k] = wsp[(size_t)t2 * K + (k - 1)];
-            pmul<K>(R, o);
+                for (int k = 1; k <= K; ++k) o[k] = wsp[(size_t)t2 * K + (k - 1)];
+                pmul<K>(R, o);
+            }
         }
         // G[e] = sum_{j <= K-e} R[j], R[0] = 1
         double G[MAXK + 1];
@@ -1466,6 +1657,8 @@ __device__ __forceinline__ void wave_adjoint(const ProbDev& P, int rank, int gro
         CoordParam cp;
         coord_param(t, cp);
         if constexpr (FAM == FAM_GAUSS) {
+            int opaque = 0;
+            asm volatile("" : "+s"(opaque));
             const double c = prm[t], hv = 0.5 - prm[d + t], b = 2.0 * hv;
             double dsc, dsu;
             contract_pairs2<K, RC>(r64 + opaque, G,
@@ -1474,6 +1667,8 @@ __device__ __forceinline__ void wave_adjoint(const ProbDev& P, int rank, int gro
             grad[P.param_offset + t] = g * A * fma(s, hv * hv, dsc);
             grad[P.param_offset + d + t] = g * A * fma(s, -2.0 * c * hv, dsu);
         } else if constexpr (FAM == FAM_PEAK) {
+            int opaque = 0;
+            asm volatile("" : "+s"(opaque));
             double db[MAXK + 1], du[MAXK + 1], eps = 0.0;
             surplus64g<K, RC>(r64 + opaque, [&](double y) { double a, b; dpair_peak64(cp, y, a, b); return a; },
                               false, db, eps);
@@ -1491,12 +1686,25 @@ __device__ __forceinline__ void wave_adjoint(const ProbDev& P, int rank, int gro
             grad[P.param_offset + t] = g * dQ_dbeta * dbeta_db;
             grad[P.param_offset + d + t] = g * (-dQ_dhv);         // hv = 1/2 - u
         } else {
-            double dd[MAXK + 1], eps = 0.0;
-            if constexpr (PREC == SG_PREC_FP64)
-                surplus64g<K, RC>(r64 + opaque, [&](double y) { return dpair64<FAM>(cp, y); }, false, dd, eps);
-            else
-                surplus32g<K, RC>(r64 + opaque, r32 + opaque, [&](double y) { return dpair32<FAM>(cp, y); }, false,
-                                  dd, eps);
+            double dd[MAXK + 1];
+            bool done = false;
+            if constexpr (kConst) {
+                if (fabs(cp.p0) <= 2.0) {
+                    if constexpr (PREC == SG_PREC_FP64) dsurplus64_const<RULE, K, FAM>(cp, dd);
+                    else dsurplus32_const<RULE, K, FAM>(cp, dd);
+                    done = true;
+                }
+            }
+            if (!done) {
+                int opaque = 0;
+                asm volatile("" : "+s"(opaque));
+                double eps = 0.0;
+                if constexpr (PREC == SG_PREC_FP64)
+                    surplus64g<K, RC>(r64 + opaque, [&](double y) { return dpair64<FAM>(cp, y); }, false, dd, eps);
+                else
+                    surplus32g<K, RC>(r64 + opaque, r32 + opaque, [&](double y) { return dpair32<FAM>(cp, y); },
+                                      false, dd, eps);
+            }
             double ds = 0.0;
 #pragma unroll
             for (int e = 1; e <= K; ++e) ds = fma(G[e], dd[e], ds);
@@ -1509,33 +1717,38 @@ __device__ __forceinline__ void wave_adjoint(const ProbDev& P, int rank, int gro
     }
 }
 
-template <int PREC, int K, bool GAUSS>
-__device__ __forceinline__ void adjoint_dispatch_k(const ProbDev& P, int rank, int group, bool grouped,
-                                                   const double* pool64, const float* pool32, const double* params,
-                                                   const double* gout, double* grad, double* ws, double* lds)
+// Flat dispatch of a reverse-sweep wave (the forward's class index).
+template <int PREC, bool GAUSS, int K, int R, int F>
+__device__ __forceinline__ void adjoint_case(const ProbDev& P, int rank, int group, bool grouped, const double* pool64,
+                                             const float* pool32, const double* params, const double* gout,
+                                             double* grad, double* ws, double* lds)
 {
-#define SG_ADJ(RC, FAM) wave_adjoint<PREC, K, RC, FAM>(P, rank, group, grouped, pool64, pool32, params, gout, grad, ws, lds)
-#define SG_ADJ_FAMS(RC)                                       \
-    do {                                                      \
-        if (GAUSS && P.family == FAM_GAUSS) {                 \
-            if constexpr (GAUSS) SG_ADJ(RC, FAM_GAUSS);       \
-        } else if (P.family == FAM_EXP) SG_ADJ(RC, FAM_EXP);  \
-        else if (P.family == FAM_OSC) SG_ADJ(RC, FAM_OSC);    \
-        else SG_ADJ(RC, FAM_PEAK);                            \
-    } while (0)
-    const int rc = rule_class_of(P.rule);
-    if (rc == RC_NESTED) SG_ADJ_FAMS(RC_NESTED);
-    else if (rc == RC_GL2) SG_ADJ_FAMS(RC_GL2);
-    else if (rc == RC_GP) SG_ADJ_FAMS(RC_GP);
-    else SG_ADJ_FAMS(RC_GLP);
-#undef SG_ADJ_FAMS
-#undef SG_ADJ
+    constexpr int FAM = F == 0 ? FAM_EXP : F == 1 ? FAM_OSC : F == 2 ? FAM_PEAK : FAM_GAUSS;
+    if constexpr ((GAUSS || FAM != FAM_GAUSS) && (K <= KCONST || R == representative_rule(R)))
+        wave_adjoint<PREC, K, R, FAM>(P, rank, group, grouped, pool64, pool32, params, gout, grad, ws, lds);
 }
 
-// Same workgroup packing as the forward pass.  Every wave of a workgroup
-// that holds a multi-wave problem passes exactly one barrier.  GAUSS: the
-// instantiation for plans that hold gaussian problems (it runs every
-// family), kept apart so that the others' code and registers do not change.
+template <int PREC, bool GAUSS>
+__device__ __forceinline__ void adjoint_switch(int cls, const ProbDev& P, int rank, int group, bool grouped,
+                                               const double* pool64, const float* pool32, const double* params,
+                                               const double* gout, double* grad, double* ws, double* lds)
+{
+    switch (cls) {
+#define SG_C(K, R, F)                                                                                   \
+    case class_slot(K, R, F):                                                                           \
+        adjoint_case<PREC, GAUSS, K, R, F>(P, rank, group, grouped, pool64, pool32, params, gout, grad, ws, lds); \
+        break;
+#define SG_CR(K, R) SG_C(K, R, 0) SG_C(K, R, 1) SG_C(K, R, 2) SG_C(K, R, 3)
+#define SG_CK(K) SG_CR(K, 1) SG_CR(K, 2) SG_CR(K, 3) SG_CR(K, 4) SG_CR(K, 5)
+        SG_CK(0) SG_CK(1) SG_CK(2) SG_CK(3) SG_CK(4) SG_CK(5) SG_CK(6) SG_CK(7) SG_CK(8)
+#undef SG_CK
+#undef SG_CR
+#undef SG_C
+    default:
+        break;
+    }
+}
+
 template <int PREC, bool GAUSS = false>
 __global__ void __launch_bounds__(256)
 k_adjoint(const WGDesc* __restrict__ wgs, const ProbDev* __restrict__ probs, const double* __restrict__ pool64,
@@ -1549,21 +1762,20 @@ k_adjoint(const WGDesc* __restrict__ wgs, const ProbDev* __restrict__ probs, con
     sl.prob = __builtin_amdgcn_readfirstlane(desc->slot[w].prob);
     sl.rank = (int16_t)__builtin_amdgcn_readfirstlane(desc->slot[w].rank);
     sl.group = (int16_t)__builtin_amdgcn_readfirstlane(desc->slot[w].group);
-    const bool grouped = desc->slot[0].group > 1 || desc->slot[1].group > 1 || desc->slot[2].group > 1 ||
-                         desc->slot[3].group > 1;
+    // the four group sizes read together (no short-circuit chain of loads)
+    const int g0 = __builtin_amdgcn_readfirstlane(desc->slot[0].group);
+    const int g1 = __builtin_amdgcn_readfirstlane(desc->slot[1].group);
+    const int g2 = __builtin_amdgcn_readfirstlane(desc->slot[2].group);
+    const int g3 = __builtin_amdgcn_readfirstlane(desc->slot[3].group);
+    const bool grouped = ((g0 > 1) | (g1 > 1) | (g2 > 1) | (g3 > 1)) != 0;
     if (sl.prob < 0) {
         if (grouped) __syncthreads();
         return;
     }
     const ProbDev P = desc->slot[w].p;
-    // the K dispatch with every level forced inline: with the gaussian
-    // family the K = 8 body outgrew the inliner's budget and became a call,
-    // whose convention cost the kernel its whole register file and a stack
-    static_for<0, MAXK + 1>([&](auto kc) __attribute__((always_inline)) {
-        if (P.K == decltype(kc)::value)
-            adjoint_dispatch_k<PREC, decltype(kc)::value, GAUSS>(P, sl.rank, sl.group, grouped, pool64, pool32,
-                                                                 params, gout, grad, ws, lds + w * ADJ_WORDS);
-    });
+    const int cls = __builtin_amdgcn_readfirstlane(class_index(P.K, P.rule, P.family));
+    adjoint_switch<PREC, GAUSS>(cls, P, sl.rank, sl.group, grouped, pool64, pool32, params, gout, grad, ws,
+                                lds + w * ADJ_WORDS);
 }
 
 }  // namespace dev

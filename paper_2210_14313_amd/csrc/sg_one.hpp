@@ -34,10 +34,9 @@ __device__ __forceinline__ void one_readout(int rule, int family, const Acc& x, 
                                             double* out, double* bound)
 {
     const int rc = rule_class_of(rule);
-    const int np = rc == RC_NESTED ? total_pairs<RC_NESTED, K>()
-                   : rc == RC_GL2  ? total_pairs<RC_GL2, K>()
-                   : rc == RC_GP   ? total_pairs<RC_GP, K>()
-                                   : total_pairs<RC_GLP, K>();
+    constexpr int np_nested = total_pairs<RC_NESTED, K>(), np_gl2 = total_pairs<RC_GL2, K>(),
+                  np_gp = total_pairs<RC_GP, K>(), np_glp = total_pairs<RC_GLP, K>();
+    const int np = rc == RC_NESTED ? np_nested : rc == RC_GL2 ? np_gl2 : rc == RC_GP ? np_gp : np_glp;
     if constexpr (GAUSS) {
         if (family == FAM_GAUSS) {
             readout<PREC, K, FAM_GAUSS>(x, d, 0, prm, np, depth, out, bound);
