@@ -88,8 +88,8 @@ typedef enum {
  * point path, sg_integrate in FP64, and plans, which compute it in FP64 in
  * every precision mode (a sweep with complex truncated products, one
  * workgroup per integrand beside the forward kernel), block variant
- * included; it has no reverse sweep.  Plans reject CORNER_PEAK with
- * UNSUPPORTED.) */
+ * included, and its reverse sweep (FP64, one workgroup per integrand).
+ * Plans reject CORNER_PEAK with UNSUPPORTED.) */
 typedef enum {
     SG_FAMILY_EXP_SUM = 0,
     SG_FAMILY_OSCILLATORY = 1,
@@ -267,9 +267,11 @@ sg_status sg_plan_execute(sg_plan *plan, const double *params_dev, double *out_d
 /* Gradient of every result with respect to every parameter (reverse sweep):
  * grad_params_dev[k] = grad_out_dev[i] * dQ_i/dparams[k] for the parameters
  * k of problem i, same layout as params.  Parameters not used by any problem
- * are left untouched.
- * Errors: INVALID_ARGUMENT, DEVICE, UNSUPPORTED (a block-variant plan, or a
- * plan holding OSCILLATORY_QUADRATIC problems). */
+ * are left untouched.  OSCILLATORY_QUADRATIC problems take a complex reverse
+ * sweep of their own (FP64 in every mode, one workgroup per integrand,
+ * launched after the real one on the same stream).
+ * Errors: INVALID_ARGUMENT (also: problems whose parameter ranges overlap),
+ * DEVICE, UNSUPPORTED (a block-variant plan). */
 sg_status sg_plan_execute_grad(sg_plan *plan, const double *params_dev, const double *grad_out_dev,
                                double *grad_params_dev, void *stream);
 

@@ -54,7 +54,7 @@ SAN_LIB_PATH = os.path.join(_HERE, "liboracle_san.so")
 def build_sanitized() -> str:
     """The oracle under AddressSanitizer and UndefinedBehaviorSanitizer (for
     the CPU sanitizer tests; loaded in a process that preloads the runtimes)."""
-    tmp = SAN_LIB_PATH + ".tmp"
+    tmp = SAN_LIB_PATH + f".tmp{os.getpid()}"
     cmd = ["gcc", "-O1", "-g", "-fPIC", "-shared", "-std=gnu11", "-ffp-contract=off", "-Wall", "-Werror",
            "-Wno-unused-function", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
            "-fno-omit-frame-pointer", SRC_PATH, "-o", tmp, "-lquadmath", "-lpthread", "-lm"]

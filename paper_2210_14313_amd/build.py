@@ -137,7 +137,7 @@ def build_host_sanitized(verbose: bool = False) -> str:
     os.makedirs(objdir, exist_ok=True)
     srcs = [os.path.join(CSRC, f) for f in ("sg_api.cpp", "sg_counts.cpp", "sg_rules.cpp", "sg_tuning.cpp",
                                               "sg_host_stubs.cpp")]
-    tmp = HOSTSAN_LIB + ".tmp"
+    tmp = HOSTSAN_LIB + f".tmp{os.getpid()}"   # concurrent test workers each build their own
     cmd = ([host_cxx(), "-O1", "-g", "-std=c++17", "-fPIC", "-shared", "-Wall", "-Werror", "-Wno-unused-function",
             "-D__HIP_PLATFORM_AMD__", "-I", INCLUDE, "-I", CSRC, "-I", "/opt/rocm/include"] + SANITIZE + srcs +
            ["-Wl,--no-undefined", "-o", tmp])

@@ -1034,6 +1034,7 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
             continue;
         }
         OscqDesc q;
+        q.ws_off = 0;
         q.off64 = toff[std::make_pair(problems[i].rule, problems[i].q - problems[i].d)].first;
         q.param_offset = problems[i].param_offset;
         q.d = problems[i].d;
@@ -1066,6 +1067,11 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
         p->coord_cost[k] = fwd_coord_cost(r, ptab[i]->npairs, macs_of(*ptab[i]), precision);
         r.ws_off = (int64_t)p->ws_elems;
         p->ws_elems += (size_t)r.d * (size_t)(K > 0 ? K : 1);
+    }
+    // reverse sweep of the oscillatory quadratic: d complex surpluses each
+    for (OscqDesc& q : oscq) {
+        q.ws_off = (int64_t)p->ws_elems;
+        p->ws_elems += (size_t)q.d * (size_t)(2 * (q.K > 0 ? q.K : 1));
     }
     {
         // parameter ranges must be disjoint for the reverse sweep to write them
@@ -1365,7 +1371,6 @@ sg_status sg_plan_execute_grad(sg_plan* p, const double* params_dev, const doubl
     if (!params_dev || !grad_out_dev || !grad_params_dev)
         return fail(p->ctx, SG_ERR_INVALID_ARGUMENT, "NULL params, grad_out or grad_params");
     if (p->blocked) return fail(p->ctx, SG_ERR_UNSUPPORTED, "the block variant has no reverse sweep");
-    if (p->noscq) return fail(p->ctx, SG_ERR_UNSUPPORTED, "the oscillatory quadratic has no reverse sweep");
     if (!p->params_disjoint)
         return fail(p->ctx, SG_ERR_INVALID_ARGUMENT,
                     "problems share parameters: the reverse sweep needs disjoint parameter ranges");
@@ -1379,6 +1384,11 @@ sg_status sg_plan_execute_grad(sg_plan* p, const double* params_dev, const doubl
     const int rc = launch_adjoint(p->precision, p->kmax == kKmaxGauss, p->nwg, p->d_wgs, p->d_probs, p->d_pool64,
                                   p->d_pool32, params_dev, grad_out_dev, grad_params_dev, p->d_ws, stream);
     if (rc != 0) return hip_fail(p->ctx, (hipError_t)rc, "adjoint launch");
+    if (p->noscq) {
+        const int rq = launch_oscq_grad(p->noscq, p->d_oscq, p->d_pool64, params_dev, grad_out_dev, grad_params_dev,
+                                        p->d_ws, stream);
+        if (rq != 0) return hip_fail(p->ctx, (hipError_t)rq, "oscillatory-quadratic reverse sweep launch");
+    }
     return SG_OK;
 }
 

@@ -199,6 +199,10 @@ int launch_block_combine(const BlockProb*, int, const double*, const double*, co
 }
 int launch_oscq(int, int, int, int, const double*, const double*, double*, double*, double*, void*) { return launched(); }
 int launch_oscq_batch(int, const OscqDesc*, const double*, const double*, double*, double*, void*) { return launched(); }
+int launch_oscq_grad(int, const OscqDesc*, const double*, const double*, const double*, double*, double*, void*)
+{
+    return launched();
+}
 
 namespace {
 double g_scratch[1 << 16];

@@ -12,6 +12,7 @@ struct OscqDesc {
     int64_t param_offset;   // its parameters w, a[d], u[d] in the caller's array
     int32_t d, K, rule;
     int32_t out_index;      // its slot in out / bound
+    int64_t ws_off;         // reverse sweep: its d * 2K doubles in the workspace
 };
 
 // One integrand (the plan-free path) on G workgroups: pool64 holds the
@@ -27,5 +28,10 @@ int launch_oscq(int d, int K, int rule, int G, const double* pool64, const doubl
 // indexed by out_index.
 int launch_oscq_batch(int n, const OscqDesc* descs, const double* pool64, const double* params, double* out,
                       double* bound, void* stream);
+// Reverse sweep of n integrands of a plan, one workgroup each: grad (the
+// parameters' layout) receives gout[out_index] times the gradient of each
+// integrand's value; ws: the plan's workspace (OscqDesc::ws_off).
+int launch_oscq_grad(int n, const OscqDesc* descs, const double* pool64, const double* params, const double* gout,
+                     double* grad, double* ws, void* stream);
 
 }  // namespace sg

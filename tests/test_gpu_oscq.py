@@ -178,17 +178,40 @@ def test_oscq_block_variant(torch_dev, orc, precision):
     assert np.max(np.abs(got[sel] - ref[sel]) / _mod(b, ref)[sel]) <= 1e-12
 
 
-def test_oscq_rejected_by_the_reverse_sweep(torch_dev):
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_oscq_reverse_sweep_vs_oracle_gradient(torch_dev, orc, precision):
+    """The complex reverse sweep (FP64 in every mode) against the oracle's
+    binary128 factorised gradient (dQ/dw, dQ/da_t, dQ/du_t), in a plan that
+    mixes it with the real families, including integrands whose threads hold
+    several coordinates (d > 256, the workspace path), with a non-trivial
+    grad_out."""
     import torch
     from paper_2210_14313_amd import api, native, workloads as W
-    b = W.single(20, 24, "cc", FAM, W.draw_params(np.random.default_rng(3), FAM, 20))
-    plan = native.Plan(b.problems, "fp64")
+    rng = np.random.default_rng(41)
+    b = W._Builder("oscq_grad_mix")
+    shapes = [(1, 0, "cc"), (3, 2, "gl"), (20, 4, "cc"), (64, 3, "gp"), (255, 2, "tr"), (256, 5, "gl"),
+              (257, 3, "cc"), (600, 4, "gl"), (1000, 2, "gp")]
+    for d, K, rule in shapes:
+        b.add(d, d + K, rule, FAM, W.draw_params(rng, FAM, d))
+    for d, K, rule, fam in [(40, 3, "cc", "oscillatory"), (70, 4, "gl", "exp_sum"), (33, 2, "gp", "gaussian")]:
+        b.add(d, d + K, rule, fam, W.draw_params(rng, fam, d))
+    b = b.build()
+    say("case oscq reverse sweep", precision)
+    params = api.params_tensor(b)
+    gout = torch.tensor(rng.uniform(0.5, 2.0, len(b)), dtype=torch.float64, device="cuda")
+    plan = native.Plan(b.problems, precision)
     try:
-        with pytest.raises(native.SgError) as e:
-            plan.execute_grad(api.params_tensor(b), torch.ones(1, dtype=torch.float64, device="cuda"))
-        assert e.value.status == 2
+        got = plan.execute_grad(params, gout).cpu().numpy()
     finally:
         plan.close()
+    gw = gout.cpu().numpy()
+    for i, p in enumerate(b.problems):
+        ref = gw[i] * orc.smolyak_factorised_grad(p.d, p.q, p.rule, p.family, b.param_slice(i))
+        sl = slice(p.param_offset, p.param_offset + len(ref))
+        scale = max(np.max(np.abs(ref)), 1e-300)
+        err = np.max(np.abs(got[sl] - ref)) / scale
+        tol = 1e-12 if (p.family == FAM or precision == "fp64") else 1e-6
+        assert err <= tol, (i, p.d, p.q, p.rule, p.family, err)
 
 
 @pytest.mark.parametrize("persistent", [False, True])

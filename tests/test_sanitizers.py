@@ -104,8 +104,8 @@ def test_plan_paths_statuses(run_result):
     assert all(s[-1] == OK for k in ("get_info", "execute", "execute_nobound", "autotune", "autotune_stream",
                                     "execute_after_tune", "destroy", "plan_reuse") for s in by[k])
     assert all(s[-1] == INVALID for s in by["execute_null"])
-    # gradient: unsupported exactly for the batch holding oscillatory-quadratic problems
-    assert all(s[2] == (UNSUPPORTED if s[1] else OK) for s in by["execute_grad"])
+    # gradient: every family, the oscillatory quadratic by its complex reverse sweep
+    assert all(s[2] == OK for s in by["execute_grad"])
     for s in by["set_schedule"]:
         _, cpl, mg, cs, pers, gr, code = s
         valid = 1 <= cpl <= 64 and mg in (1, 2, 4) and cs in (0, 1)
