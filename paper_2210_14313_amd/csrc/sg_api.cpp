@@ -412,6 +412,14 @@ double fwd_coord_cost(const ProbDev& p, int npairs, uint64_t macs, int precision
     double c = (double)npairs * pv + (double)macs * mac + 1.65 * (double)(K * (K - 1) / 2 + K) + 4.0 * K + 31.0;
     if (p.family == SG_FAMILY_PRODUCT_PEAK) c += 40.0;            // log of the centre value
     if (K > 6 || !series) c *= 1.5;                                 // table-driven records (loads)
+    // per-class corrections from per-wave timings of the kernel: the
+    // Gauss-Legendre rules' wider rows at K >= 5, the Clenshaw-Curtis
+    // K = 6 class's longer independent chains, the oscillatory family's
+    // extra phase term
+    const int rc = rule_class_of(p.rule);
+    if (rc == RC_GL2 && K >= 5) c *= 1.08;
+    if (rc == RC_NESTED && K == 6) c *= 0.95;
+    if (p.family == SG_FAMILY_OSCILLATORY) c *= 1.03;
     // latency floor: a coordinate's dependent chain (parameter, series,
     // sums, product update) takes about this long however little work it
     // holds, with two waves sharing a SIMD (per-wave timings of the kernel)
