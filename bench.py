@@ -321,7 +321,8 @@ def adjoint_leg(dev, s):
 
 def oscq_leg(dev, s, reps: int = 50):
     """Oscillatory quadratic cos(2 pi w + sum a_i (x_i - u_i)^2) on the sweep
-    with complex surpluses (sg_integrate, FP64), d = 1000, q = 1004,
+    with complex surpluses (sg_integrate, FP64, and the FP32 modes beside it),
+    d = 1000, q = 1004,
     Gauss-Patterson: time per call (HIP events on the launch stream),
     accuracy against the oracle's stored binary128 value, and the roofline
     over its flop-slots (two sincos per node pair, 16; 4 per complex
@@ -376,7 +377,23 @@ def oscq_leg(dev, s, reps: int = 50):
            "points_per_s": float(info["effective_points"]) / (ms / 1e3),
            "value": o.item(), "rel_err_vs_oracle": abs(o.item() - ref) / sc, "stated_bound_rel": bd.item() / sc,
            "roofline": roof}
-    log(f"  oscillatory quadratic d={p.d}: {ms * 1e3:.2f} us per call, err {res['rel_err_vs_oracle']:.2e}")
+    # the FP32 modes (FP32 node values, FP64 complex products), same entry point
+    for prec in ("fp32c", "fp32e"):
+        args = (ctx.handle, ctypes.byref(cp), native.PRECISIONS[prec], ctypes.c_void_p(pr.data_ptr()),
+                ctypes.c_void_p(o.data_ptr()), ctypes.c_void_p(bd.data_ptr()), ctypes.c_void_p(s.cuda_stream))
+        for _ in range(3):
+            lib.sg_integrate(*args)
+        torch.cuda.synchronize()
+        e0.record(s)
+        bad = sum(1 for _ in range(reps) if lib.sg_integrate(*args) != 0)
+        e1.record(s)
+        torch.cuda.synchronize()
+        assert bad == 0, "sg_integrate failed"
+        m2 = e0.elapsed_time(e1) / reps
+        res[prec] = {"us_per_call": m2 * 1e3, "value": o.item(), "rel_err_vs_oracle": abs(o.item() - ref) / sc,
+                     "stated_bound_rel": bd.item() / sc}
+    log(f"  oscillatory quadratic d={p.d}: {ms * 1e3:.2f} us per call, err {res['rel_err_vs_oracle']:.2e}; "
+        f"fp32c {res['fp32c']['us_per_call']:.2f} us, err {res['fp32c']['rel_err_vs_oracle']:.2e}")
     return res
 
 
@@ -833,6 +850,21 @@ def main():
                                           "grid_blocks", "balanced")},
             "kernel_ms": at["kernel_ms"], "ms_per_step": at["ms_per_step"],
             "max_rel_err_vs_oracle": rel_err(at["got"])}
+        # the same batch in the other launch forms: the balanced schedule
+        # replayed from a captured graph, and the persistent work-queue
+        # kernel (direct and in a graph), beside the headline's direct launch
+        forms = {"balanced_direct": PINNED_SCHEDULE[args.precision]}
+        forms["balanced_graph"] = ("balanced", 2, 1)
+        forms["persistent_queue_direct"] = (4, 4, 0, 1, 0)
+        forms["persistent_queue_graph"] = (4, 4, 0, 1, 1)
+        lf = {}
+        for name, sched in forms.items():
+            r2 = run_plan(args.precision, max(20, args.steps // 2), 5, False, sched)
+            lf[name] = {"schedule": {k: r2["info"][k] for k in ("coords_per_lane", "max_group", "persistent", "graph",
+                                                               "grid_blocks", "balanced")},
+                        "kernel_ms": r2["kernel_ms"], "ms_per_step": r2["ms_per_step"],
+                        "max_rel_err_vs_oracle": rel_err(r2["got"])}
+        extras["launch_forms_" + args.precision] = lf
         # the other precision modes' batched rates
         for other in [m for m in ("fp64", "fp32e", "fp32c") if m != args.precision]:
             r2 = run_plan(other, max(20, args.steps // 2), 5, False, PINNED_SCHEDULE[other])

@@ -85,10 +85,11 @@ typedef enum {
  * their sines.  CORNER_PEAK is a ridge function that does not factor per
  * coordinate: the point-by-point path sg_integrate_points only.
  * OSCILLATORY_QUADRATIC factors with complex per-coordinate surpluses: the
- * point path, sg_integrate in FP64, and plans, which compute it in FP64 in
- * every precision mode (a sweep with complex truncated products, one
- * workgroup per integrand beside the forward kernel), block variant
- * included, and its reverse sweep (FP64, one workgroup per integrand).
+ * point path, sg_integrate, and plans (a sweep with complex truncated
+ * products, one workgroup per integrand beside the forward kernel), block
+ * variant included, in every precision mode (the node values and
+ * within-rule sums follow the mode; products, phase and read-out are FP64),
+ * and its reverse sweep (FP64 in every mode, one workgroup per integrand).
  * Plans reject CORNER_PEAK with UNSUPPORTED.) */
 typedef enum {
     SG_FAMILY_EXP_SUM = 0,
@@ -219,8 +220,9 @@ sg_status sg_unrank_device(sg_context *ctx, int32_t d, int32_t q, uint64_t rank0
  * validates every problem, builds (or reuses) the rule tables, orders the
  * work longest-first, picks tile/schedule parameters (from the context's
  * autotune results when present) and uploads the plan to the device.
- * OSCILLATORY_QUADRATIC problems run in FP64 on the complex sweep, one
- * workgroup each, launched after the forward kernel on the same stream.
+ * OSCILLATORY_QUADRATIC problems run on the complex sweep in the plan's
+ * precision mode, one workgroup each, launched after the forward kernel on
+ * the same stream.
  * Errors: INVALID_ARGUMENT (n < 1, NULL, a bad problem), UNSUPPORTED
  * (K > SG_MAX_K, a CORNER_PEAK problem), OUT_OF_MEMORY, DEVICE. */
 sg_status sg_plan_create(sg_context *ctx, const sg_problem *problems, int32_t n,
@@ -307,8 +309,9 @@ sg_status sg_plan_execute_grad(sg_plan *plan, const double *params_dev, const do
  *   (sg_plan_set_schedule_balanced), which replaces coords_per_lane,
  *   max_group and cost_scaled;
  *   fp64_complex: how many of the plan's integrands (OSCILLATORY_QUADRATIC)
- *   run the FP64 complex sweep whatever the plan's precision mode; their
- *   values, bounds and time are those of FP64 arithmetic. */
+ *   run on the complex sweep, whose forward sweep follows the plan's
+ *   precision mode and whose reverse sweep (sg_plan_execute_grad) is FP64
+ *   whatever the mode. */
 typedef struct {
     uint64_t effective_points;
     uint64_t units;
@@ -398,10 +401,11 @@ sg_status sg_integrate_points(sg_context *ctx, const sg_problem *problem, const 
  * product of Section 3, (3.9)-(3.11), split by chunks).  The partials use a
  * scratch buffer the context allocates on the first call with d > 256
  * (about 160 KiB, kept until the context is destroyed); calls on one
- * context must not overlap in time.  Also takes OSCILLATORY_QUADRATIC,
- * computed in FP64 whatever the precision mode: the sweep of Section 3
- * with the complex surpluses of e^{i a (x - u)^2} and the bound of the real
- * sweep (complex moduli in place of absolute values). */
+ * context must not overlap in time.  Also takes OSCILLATORY_QUADRATIC in
+ * every precision mode: the sweep of Section 3 with the complex surpluses of
+ * e^{i a (x - u)^2} (FP32 node values in the FP32 modes, FP64 complex
+ * products and read-out) and the bound of the real sweep (complex moduli in
+ * place of absolute values). */
 sg_status sg_integrate(sg_context *ctx, const sg_problem *problem, int32_t precision,
                        const double *params_dev, double *out_dev, double *bound_dev, void *stream);
 

@@ -18,7 +18,7 @@ PEAKS_SOURCE = "sg_peaks.hip"
 
 FORWARD_UNITS = [f"sg_fwd_p{p}_{k}.hip" for p in (0, 1, 2) for k in ("k4", "k6", "k8", "g8")]
 SOURCES = FORWARD_UNITS + ["sg_one_p0.hip", "sg_one_p1.hip", "sg_one_p2.hip", "sg_adj0.hip", "sg_adj1.hip", "sg_unrank.hip", "sg_points.hip",
-           "sg_blocked.hip", "sg_oscq.hip", "sg_noalloc.hip", "sg_rules.cpp", "sg_counts.cpp", "sg_tuning.cpp",
+           "sg_blocked.hip", "sg_oscq.hip", "sg_oscq_p1.hip", "sg_oscq_p2.hip", "sg_noalloc.hip", "sg_rules.cpp", "sg_counts.cpp", "sg_tuning.cpp",
            "sg_api.cpp"]
 
 # Packed FP32 instructions are disabled for every device pass; contraction of

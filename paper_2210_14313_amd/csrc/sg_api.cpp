@@ -117,7 +117,7 @@ struct sg_plan {
     size_t ws_elems = 0;
     int nwg = 0;
     size_t wg_capacity = 0;
-    OscqDesc* d_oscq = nullptr;     // oscillatory-quadratic integrands (complex sweep, FP64)
+    OscqDesc* d_oscq = nullptr;     // oscillatory-quadratic integrands (complex sweep)
     int noscq = 0;
     sg_plan_info info{};
     std::string tune_key;
@@ -1043,7 +1043,9 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
         }
         OscqDesc q;
         q.ws_off = 0;
-        q.off64 = toff[std::make_pair(problems[i].rule, problems[i].q - problems[i].d)].first;
+        const auto& qo = toff[std::make_pair(problems[i].rule, problems[i].q - problems[i].d)];
+        q.off64 = qo.first;
+        q.off32 = qo.second;
         q.param_offset = problems[i].param_offset;
         q.d = problems[i].d;
         q.K = problems[i].q - problems[i].d;
@@ -1153,7 +1155,8 @@ static sg_status plan_launch(sg_plan* p, const double* params, double* out, doub
                                   p->qgrid, p->d_pool64, p->d_pool32, params, out, bound, stream);
     if (rc != 0) return hip_fail(p->ctx, (hipError_t)rc, "forward launch");
     if (p->noscq) {
-        const int rq = launch_oscq_batch(p->noscq, p->d_oscq, p->d_pool64, params, out, bound, stream);
+        const int rq = launch_oscq_batch(p->precision, p->noscq, p->d_oscq, p->d_pool64, p->d_pool32, params, out,
+                                         bound, stream);
         if (rq != 0) return hip_fail(p->ctx, (hipError_t)rq, "oscillatory-quadratic launch");
     }
     return SG_OK;
@@ -1645,8 +1648,8 @@ sg_status sg_integrate(sg_context* ctx, const sg_problem* problem, int32_t preci
         }
     }
     const int rc = problem->family == SG_FAMILY_OSCILLATORY_QUADRATIC
-                       ? launch_oscq(d, K, problem->rule, G, nullptr, params_dev, out_dev, bound_dev, ctx->one_ws,
-                                     stream)
+                       ? launch_oscq(precision, d, K, problem->rule, G, nullptr, nullptr, params_dev, out_dev,
+                                     bound_dev, ctx->one_ws, stream)
                        : launch_one(precision, d, K, problem->rule, problem->family, G, params_dev, out_dev,
                                     bound_dev, ctx->one_ws, stream);
     if (rc != 0) return hip_fail(ctx, (hipError_t)rc, "plan-free launch");

@@ -197,8 +197,14 @@ int launch_block_combine(const BlockProb*, int, const double*, const double*, co
 {
     return launched();
 }
-int launch_oscq(int, int, int, int, const double*, const double*, double*, double*, double*, void*) { return launched(); }
-int launch_oscq_batch(int, const OscqDesc*, const double*, const double*, double*, double*, void*) { return launched(); }
+int launch_oscq(int, int, int, int, int, const double*, const float*, const double*, double*, double*, double*, void*)
+{
+    return launched();
+}
+int launch_oscq_batch(int, int, const OscqDesc*, const double*, const float*, const double*, double*, double*, void*)
+{
+    return launched();
+}
 int launch_oscq_grad(int, const OscqDesc*, const double*, const double*, const double*, double*, double*, void*)
 {
     return launched();

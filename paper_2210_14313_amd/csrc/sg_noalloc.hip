@@ -64,7 +64,7 @@ int noalloc_launch(double* ptr, int precision, int d, int K, int rule, int famil
     const bool oscq = family == SG_FAMILY_OSCILLATORY_QUADRATIC;
     const long need = (long)kOneHead + (long)G * (oscq ? kOscqWords : kOneWords);
     if (need > (long)kNoAllocWords) return -1;
-    if (oscq) return launch_oscq(d, K, rule, G, nullptr, params, out, bound, ptr, stream);
+    if (oscq) return launch_oscq(precision, d, K, rule, G, nullptr, nullptr, params, out, bound, ptr, stream);
     return launch_one(precision, d, K, rule, family, G, params, out, bound, ptr, stream);
 }
 
