@@ -33,7 +33,7 @@ SRC_PATH = os.path.join(_HERE, "sg_oracle.c")
 
 RULE_IDS = {"tr": 1, "cc": 2, "gp": 3, "gl": 4, "gl_paper": 5}
 FAMILY_IDS = {"exp_sum": 0, "oscillatory": 1, "product_peak": 2, "monomial": 3, "corner_peak": 4,
-              "gaussian": 5, "oscillatory_quadratic": 6}
+              "gaussian": 5, "oscillatory_quadratic": 6, "oscillatory_quadratic_linear": 7}
 
 
 def build(force: bool = True) -> str:
@@ -229,7 +229,7 @@ def batch_points(batch, nthreads: int | None = None) -> np.ndarray:
 
 
 #: families of the form cos(2 pi w + phase(x)) with w the first parameter
-OSCILLATORY_FAMILIES = ("oscillatory", "oscillatory_quadratic")
+OSCILLATORY_FAMILIES = ("oscillatory", "oscillatory_quadratic", "oscillatory_quadratic_linear")
 
 
 class _ParamBatch:

@@ -22,7 +22,8 @@ cos(2 pi w + sum_t a_t x_t) = Re(e^{2 pi i w} prod_b e^{i sum_{t in b} a_t x_t})
 where the block value C_b = A_b(cos theta_b) + i A_b(sin theta_b) and
 A_b(sin theta_b) = A_b(cos(theta_b - pi/2)) is the oscillatory block with
 w = -1/4; the oscillatory quadratic the same way, with
-theta_b = sum_{t in b} a_t (x_t - u_t)^2.  Each block value comes from the oracle's plain Smolyak sum
+theta_b = sum_{t in b} a_t (x_t - u_t)^2 (plus sum_{t in b} c_t x_t with
+the linear term).  Each block value comes from the oracle's plain Smolyak sum
 (point by point, or factorised in binary128), and the product is formed in
 mpmath at 40 digits.
 """
@@ -56,6 +57,9 @@ def block_params(family: str, params, d: int, start: int, length: int, w_overrid
     if family == "oscillatory_quadratic":
         w = p[0] if w_override is None else w_override
         return np.concatenate([[w], p[1:1 + d][sl], p[1 + d:1 + 2 * d][sl]])
+    if family == "oscillatory_quadratic_linear":
+        w = p[0] if w_override is None else w_override
+        return np.concatenate([[w], p[1:1 + d][sl], p[1 + d:1 + 2 * d][sl], p[1 + 2 * d:1 + 3 * d][sl]])
     raise ValueError(family)
 
 
@@ -75,7 +79,7 @@ def smolyak_blocked(d: int, q: int, rule: str, family: str, params, m: int, meth
         return smolyak_factorised(db, db + K, rule, family, bp)
 
     with mp.workdps(40):
-        if family in ("oscillatory", "oscillatory_quadratic"):
+        if family in ("oscillatory", "oscillatory_quadratic", "oscillatory_quadratic_linear"):
             z = mp.mpc(1)
             for s, ln in blocks(d, m):
                 re = block_value(ln, block_params(family, params, d, s, ln, 0.0))

@@ -89,6 +89,36 @@ def exact_oscillatory_quadratic(w, a, u):
     return mp.re(z)
 
 
+def _quad_linear_1d(a, u, c):
+    """int_0^1 exp(i (a (x - u)^2 + c x)) dx.  a != 0: completing the square,
+    a (x - u)^2 + c x = a (x - v)^2 + c u - c^2 / (4 a) with v = u - c / (2 a),
+    so the integral is e^{i (c u - c^2/(4a))} times _quad_exp_1d(i a, v) (the
+    error functions at 40 + digits, with the working precision raised by
+    the decimal size of v); a = 0: (e^{i c} - 1) / (i c), or 1 at c = 0."""
+    a = mp.mpf(float(a))
+    u = mp.mpf(float(u))
+    c = mp.mpf(float(c))
+    if a == 0:
+        return mp.mpf(1) if c == 0 else (mp.expj(c) - 1) / (1j * c)
+    v = u - c / (2 * a)
+    extra = int(max(0, mp.log10(abs(v) + 1))) * 2 + 10
+    with mp.workdps(mp.mp.dps + extra):
+        k = 1j * a
+        r = mp.sqrt(-k)
+        base = mp.sqrt(mp.pi) / (2 * r) * (mp.erf(r * (1 - v)) + mp.erf(r * v))
+        val = mp.expj(c * u - c * c / (4 * a)) * base
+    return +val
+
+
+def exact_oscillatory_quadratic_linear(w, a, u, c):
+    """Re( e^{2 pi i w} prod_i int_0^1 exp(i (a_i (x - u_i)^2 + c_i x)) dx )."""
+    z = mp.expj(2 * mp.pi * mp.mpf(float(w)))
+    for ai, ui, ci in zip(np.asarray(a, dtype=np.float64), np.asarray(u, dtype=np.float64),
+                          np.asarray(c, dtype=np.float64)):
+        z *= _quad_linear_1d(ai, ui, ci)
+    return mp.re(z)
+
+
 def exact(family: str, d: int, params):
     params = np.asarray(params, dtype=np.float64)
     if family == "corner_peak":
@@ -103,6 +133,9 @@ def exact(family: str, d: int, params):
         return exact_gaussian(params[:d], params[d:2 * d])
     if family == "oscillatory_quadratic":
         return exact_oscillatory_quadratic(params[0], params[1:1 + d], params[1 + d:1 + 2 * d])
+    if family == "oscillatory_quadratic_linear":
+        return exact_oscillatory_quadratic_linear(params[0], params[1:1 + d], params[1 + d:1 + 2 * d],
+                                                  params[1 + 2 * d:1 + 3 * d])
     raise ValueError(family)
 
 

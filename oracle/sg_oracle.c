@@ -39,6 +39,10 @@
  *                 params c[d], u[d], c of either sign)
  *   oscillatory-quadratic  f(x) = cos(2 pi w + sum a_i (x_i - u_i)^2)
  *                 ((4.1), (4.2); params w, a[d], u[d])
+ *   oscillatory-quadratic-linear
+ *                 f(x) = cos(2 pi w + sum a_i (x_i - u_i)^2 + sum c_i x_i)
+ *                 (the sine of (4.2) with its linear term; params w, a[d],
+ *                 u[d], c[d])
  *
  * Build: gcc -O2 -fPIC -shared -ffp-contract=off sg_oracle.c -lquadmath -lpthread -lm
  */
@@ -53,7 +57,7 @@ typedef __float128 f128;
 typedef long double fld;
 
 enum { OR_TR = 1, OR_CC = 2, OR_GP = 3, OR_GL = 4, OR_GL_PAPER = 5 };
-enum { OR_EXP = 0, OR_OSC = 1, OR_PEAK = 2, OR_MONO = 3, OR_CORNER = 4, OR_GAUSS = 5, OR_OSCQ = 6 };
+enum { OR_EXP = 0, OR_OSC = 1, OR_PEAK = 2, OR_MONO = 3, OR_CORNER = 4, OR_GAUSS = 5, OR_OSCQ = 6, OR_OSCQL = 7 };
 
 #define OR_MAX_LEVEL 16
 #define OR_MAX_NODES 40000
@@ -487,9 +491,10 @@ static fld point_value(const pt_problem *P, int m, const int *coords, const fld 
         /* cos(A + t) - cos(A) = -2 sin(t/2) sin(A + t/2) */
         return -2.0L * sinl(0.5L * t) * sinl(P->theta_c + 0.5L * t);
     }
-    if (P->family == OR_GAUSS || P->family == OR_OSCQ) {
+    if (P->family == OR_GAUSS || P->family == OR_OSCQ || P->family == OR_OSCQL) {
         /* the exponent's change from the centre: with y = x - 1/2,
-         * c (x - u)^2 - c (1/2 - u)^2 = c y (y + 1 - 2u) */
+         * c (x - u)^2 - c (1/2 - u)^2 = c y (y + 1 - 2u), plus l y for a
+         * linear term l x */
         const double *cc = P->family == OR_GAUSS ? p : p + 1;
         const double *uu = cc + d;
         fld t = 0;
@@ -497,6 +502,7 @@ static fld point_value(const pt_problem *P, int m, const int *coords, const fld 
             int i = coords[k];
             fld y = xs[k] - 0.5L;
             t += (fld)cc[i] * y * (y + 1.0L - 2.0L * (fld)uu[i]);
+            if (P->family == OR_OSCQL) t += (fld)cc[2 * d + i] * y;
         }
         if (P->family == OR_GAUSS) {
             if (!P->centred) return expl(P->theta_c + t);
@@ -655,12 +661,13 @@ int or_smolyak_points(int d, int q, int rule, int family, const double *params,
         for (int i = 0; i < d; ++i) t += (fld)params[i] * 0.5L;
         P.theta_c = t;
         P.fc = powl(1.0L + t, -(fld)(d + 1));
-    } else if (family == OR_GAUSS || family == OR_OSCQ) {
+    } else if (family == OR_GAUSS || family == OR_OSCQ || family == OR_OSCQL) {
         const double *cc = family == OR_GAUSS ? params : params + 1;
-        fld t = family == OR_OSCQ ? 2.0L * 3.14159265358979323846264338327950288L * (fld)params[0] : 0.0L;
+        fld t = family != OR_GAUSS ? 2.0L * 3.14159265358979323846264338327950288L * (fld)params[0] : 0.0L;
         for (int i = 0; i < d; ++i) {
             fld h = 0.5L - (fld)cc[d + i];
             t += (fld)cc[i] * h * h;
+            if (family == OR_OSCQL) t += (fld)cc[2 * d + i] * 0.5L;
         }
         P.theta_c = t;
         P.fc = family == OR_GAUSS ? expl(t) : cosl(t);
@@ -729,7 +736,8 @@ static int fq_setup(fq_problem *F, int d, int q, int rule, int family, const dou
 {
     memset(F, 0, sizeof(*F));
     if (d < 1 || q < d || q - d + 1 > OR_MAX_LEVEL) return -1;
-    if (!(family == OR_EXP || family == OR_OSC || family == OR_PEAK || family == OR_GAUSS || family == OR_OSCQ))
+    if (!(family == OR_EXP || family == OR_OSC || family == OR_PEAK || family == OR_GAUSS || family == OR_OSCQ ||
+          family == OR_OSCQL))
         return -1;
     F->d = d; F->K = q - d; F->rule = rule; F->family = family; F->params = params;
     for (int l = 1; l <= F->K + 1; ++l) {
@@ -752,12 +760,13 @@ static void fq_free(fq_problem *F)
  * peak: g = 1/(b^-2 + (x-u)^2), dg/db = 2 b^-3 g^2, dg/du = 2 (x-u) g^2.
  * gaussian: g = e^{c (x-u)^2}, dg/dc = (x-u)^2 g, dg/du = -2 c (x-u) g.
  * oscillatory-quadratic: g = e^{i a (x-u)^2}, dg/da = i (x-u)^2 g,
- * dg/du = -2 i a (x-u) g. */
-static void fq_factor(const fq_problem *F, int t, f128 x, cq *g, cq *dg1, cq *dg2)
+ * dg/du = -2 i a (x-u) g; with a linear term, g = e^{i (a (x-u)^2 + c x)},
+ * the same two and dg/dc = i x g. */
+static void fq_factor(const fq_problem *F, int t, f128 x, cq *g, cq *dg1, cq *dg2, cq *dg3)
 {
     const double *p = F->params;
     cq z = {0, 0};
-    *dg1 = z; *dg2 = z;
+    *dg1 = z; *dg2 = z; *dg3 = z;
     if (F->family == OR_EXP) {
         f128 c = p[t];
         f128 v = expq(c * x);
@@ -773,11 +782,14 @@ static void fq_factor(const fq_problem *F, int t, f128 x, cq *g, cq *dg1, cq *dg
         g->re = e; g->im = 0;
         dg1->re = v * v * e;
         dg2->re = -2 * c * v * e;
-    } else if (F->family == OR_OSCQ) {
+    } else if (F->family == OR_OSCQ || F->family == OR_OSCQL) {
         f128 a = p[1 + t], u = p[1 + F->d + t], v = x - u;
-        g->re = cosq(a * v * v); g->im = sinq(a * v * v);
+        f128 ph = a * v * v;
+        if (F->family == OR_OSCQL) ph += (f128)p[1 + 2 * F->d + t] * x;
+        g->re = cosq(ph); g->im = sinq(ph);
         dg1->re = -v * v * g->im; dg1->im = v * v * g->re;
         dg2->re = 2 * a * v * g->im; dg2->im = -2 * a * v * g->re;
+        dg3->re = -x * g->im; dg3->im = x * g->re;
     } else {
         f128 b = p[t], u = p[F->d + t];
         f128 D = 1 / (b * b) + (x - u) * (x - u);
@@ -789,22 +801,24 @@ static void fq_factor(const fq_problem *F, int t, f128 x, cq *g, cq *dg1, cq *dg
 }
 
 /* U_t coefficients k = 0..K (and their parameter derivatives). */
-static void fq_U(const fq_problem *F, int t, cq *U, cq *dU1, cq *dU2)
+static void fq_U(const fq_problem *F, int t, cq *U, cq *dU1, cq *dU2, cq *dU3)
 {
     for (int k = 0; k <= F->K; ++k) {
-        cq s = {0, 0}, s1 = {0, 0}, s2 = {0, 0};
+        cq s = {0, 0}, s1 = {0, 0}, s2 = {0, 0}, s3 = {0, 0};
         int l = k + 1;
         for (int j = 0; j < F->n[l]; ++j) {
-            cq g, g1, g2;
-            fq_factor(F, t, F->x[l][j], &g, &g1, &g2);
+            cq g, g1, g2, g3;
+            fq_factor(F, t, F->x[l][j], &g, &g1, &g2, &g3);
             f128 wj = F->w[l][j];
             s.re += wj * g.re; s.im += wj * g.im;
             s1.re += wj * g1.re; s1.im += wj * g1.im;
             s2.re += wj * g2.re; s2.im += wj * g2.im;
+            s3.re += wj * g3.re; s3.im += wj * g3.im;
         }
         U[k] = s;
         if (dU1) dU1[k] = s1;
         if (dU2) dU2[k] = s2;
+        if (dU3) dU3[k] = s3;
     }
 }
 
@@ -845,12 +859,12 @@ int or_smolyak_factorised(int d, int q, int rule, int family, const double *para
     for (int k = 0; k <= K; ++k) { P[k].re = 0; P[k].im = 0; }
     P[0].re = 1;
     for (int t = 0; t < d; ++t) {
-        fq_U(&F, t, U, NULL, NULL);
+        fq_U(&F, t, U, NULL, NULL, NULL);
         poly_mul_trunc(P, U, K);
     }
     cq s = fq_combine(&F, P);
     f128 Q;
-    if (family == OR_OSC || family == OR_OSCQ) {
+    if (family == OR_OSC || family == OR_OSCQ || family == OR_OSCQL) {
         f128 ph = 2 * M_PIq * (f128)params[0];
         Q = cosq(ph) * s.re - sinq(ph) * s.im;
     } else {
@@ -864,7 +878,9 @@ int or_smolyak_factorised(int d, int q, int rule, int family, const double *para
 
 /*
  * Factorised gradient of Q with respect to every parameter, same layout as
- * params (exp: dc[d]; osc: dw, da[d]; peak: db[d], du[d]).  Differentiates
+ * params (exp: dc[d]; osc: dw, da[d]; peak: db[d], du[d]; gaussian: dc[d],
+ * du[d]; oscillatory-quadratic: dw, da[d], du[d], and with the linear term
+ * dc[d] after them).  Differentiates
  * the factorised sum: dP/dp_t = dU_t(z) * prod_{s != t} U_s(z), with the
  * products excluding t formed from prefix and suffix products.
  */
@@ -874,9 +890,10 @@ int or_smolyak_factorised_grad(int d, int q, int rule, int family, const double 
     if (fq_setup(&F, d, q, rule, family, params)) { fq_free(&F); return -1; }
     int K = F.K, L = K + 1;
     cq *U = malloc(sizeof(cq) * (size_t)d * L), *dU1 = malloc(sizeof(cq) * (size_t)d * L),
-       *dU2 = malloc(sizeof(cq) * (size_t)d * L);
+       *dU2 = malloc(sizeof(cq) * (size_t)d * L), *dU3 = malloc(sizeof(cq) * (size_t)d * L);
     cq *pre = malloc(sizeof(cq) * (size_t)(d + 1) * L), *suf = malloc(sizeof(cq) * (size_t)(d + 1) * L);
-    for (int t = 0; t < d; ++t) fq_U(&F, t, U + (size_t)t * L, dU1 + (size_t)t * L, dU2 + (size_t)t * L);
+    for (int t = 0; t < d; ++t)
+        fq_U(&F, t, U + (size_t)t * L, dU1 + (size_t)t * L, dU2 + (size_t)t * L, dU3 + (size_t)t * L);
     for (int k = 0; k < L; ++k) {
         pre[k].re = suf[(size_t)d * L + k].re = (k == 0);
         pre[k].im = suf[(size_t)d * L + k].im = 0;
@@ -889,23 +906,23 @@ int or_smolyak_factorised_grad(int d, int q, int rule, int family, const double 
         memcpy(suf + (size_t)t * L, suf + (size_t)(t + 1) * L, sizeof(cq) * L);
         poly_mul_trunc(suf + (size_t)t * L, U + (size_t)t * L, K);
     }
-    const int rotated = family == OR_OSC || family == OR_OSCQ;
-    const int two = family == OR_PEAK || family == OR_GAUSS || family == OR_OSCQ;
+    const int rotated = family == OR_OSC || family == OR_OSCQ || family == OR_OSCQL;
+    const int nder = family == OR_OSCQL ? 3 : (family == OR_PEAK || family == OR_GAUSS || family == OR_OSCQ) ? 2 : 1;
     f128 ph = rotated ? 2 * M_PIq * (f128)params[0] : 0;
     cq rot = {cosq(ph), sinq(ph)};
     for (int t = 0; t < d; ++t) {
         cq ex[64];
         memcpy(ex, pre + (size_t)t * L, sizeof(cq) * L);
         poly_mul_trunc(ex, suf + (size_t)(t + 1) * L, K);
-        for (int which = 0; which < (two ? 2 : 1); ++which) {
+        for (int which = 0; which < nder; ++which) {
             cq P[64];
             memcpy(P, ex, sizeof(cq) * L);
-            poly_mul_trunc(P, (which ? dU2 : dU1) + (size_t)t * L, K);
+            poly_mul_trunc(P, (which == 2 ? dU3 : which ? dU2 : dU1) + (size_t)t * L, K);
             cq s = fq_combine(&F, P);
             f128 g = rotated ? cq_mul(rot, s).re : s.re;
             if (family == OR_EXP) grad[t] = (double)g;
             else if (family == OR_OSC) grad[1 + t] = (double)g;
-            else if (family == OR_OSCQ) grad[which ? 1 + d + t : 1 + t] = (double)g;
+            else if (family == OR_OSCQ || family == OR_OSCQL) grad[1 + which * d + t] = (double)g;
             else grad[which ? d + t : t] = (double)g;
         }
     }
@@ -915,7 +932,7 @@ int or_smolyak_factorised_grad(int d, int q, int rule, int family, const double 
         cq r = cq_mul(rot, s);
         grad[0] = (double)(-2 * M_PIq * r.im);
     }
-    free(U); free(dU1); free(dU2); free(pre); free(suf);
+    free(U); free(dU1); free(dU2); free(dU3); free(pre); free(suf);
     fq_free(&F);
     return 0;
 }

@@ -39,9 +39,10 @@ ALL_RULES = RULES + ("gp",)
 #: families the factorised sweep handles (they factor per coordinate)
 FAMILIES = ("exp_sum", "oscillatory", "product_peak")
 #: families only the point-by-point path handles (ridge functions that do not factor)
-POINT_ONLY_FAMILIES = ("corner_peak", "oscillatory_quadratic")
-#: families the sweep handles beyond FAMILIES (kept out of the default mixes)
-EXTRA_SWEEP_FAMILIES = ("gaussian",)
+POINT_ONLY_FAMILIES = ("corner_peak",)
+#: families the sweep handles beyond FAMILIES (kept out of the default mixes;
+#: the oscillatory quadratics on the complex sweep)
+EXTRA_SWEEP_FAMILIES = ("gaussian", "oscillatory_quadratic", "oscillatory_quadratic_linear")
 
 #: seeds used for the five standard workloads (workload k uses SEED_BASE + k)
 SEED_BASE = 14313
@@ -61,6 +62,8 @@ def n_params(family: str, d: int) -> int:
         return 2 * d
     if family == "oscillatory_quadratic":
         return 2 * d + 1
+    if family == "oscillatory_quadratic_linear":
+        return 3 * d + 1
     raise ValueError(f"unknown family {family!r}")
 
 
@@ -135,6 +138,7 @@ def draw_params(rng: np.random.Generator, family: str, d: int,
     u_i ~ U(0, 1).  corner_peak: a_i ~ U(0,1), normalised to sum 1.
     gaussian: c_i ~ U(-4, 2) * 4 / d, u_i ~ U(0, 1).  oscillatory_quadratic:
     w ~ U(0,1), a_i ~ U(-1, 1) * osc_scale / d, u_i ~ U(0, 1).
+    oscillatory_quadratic_linear: the same, then c_i ~ U(-1, 1) * osc_scale / d.
     """
     if family == "exp_sum":
         return rng.uniform(0.0, 1.0, d) * exp_scale
@@ -159,6 +163,12 @@ def draw_params(rng: np.random.Generator, family: str, d: int,
         a = rng.uniform(-1.0, 1.0, d) * (osc_scale / d)
         u = rng.uniform(0.0, 1.0, d)
         return np.concatenate([[w], a, u])
+    if family == "oscillatory_quadratic_linear":
+        w = rng.uniform(0.0, 1.0)
+        a = rng.uniform(-1.0, 1.0, d) * (osc_scale / d)
+        u = rng.uniform(0.0, 1.0, d)
+        c = rng.uniform(-1.0, 1.0, d) * (osc_scale / d)
+        return np.concatenate([[w], a, u, c])
     raise ValueError(family)
 
 

@@ -55,14 +55,15 @@ CASES = [(3, 2, "cc", 1), (4, 2, "gl", 2), (4, 3, "gl_paper", 2), (5, 1, "cc", 2
 
 
 @pytest.mark.parametrize("d,K,rule,m", CASES)
-@pytest.mark.parametrize("family", ["exp_sum", "oscillatory", "product_peak", "gaussian", "oscillatory_quadratic"])
+@pytest.mark.parametrize("family", ["exp_sum", "oscillatory", "product_peak", "gaussian", "oscillatory_quadratic",
+                                    "oscillatory_quadratic_linear"])
 def test_blocked_equals_the_literal_tensor_product(orc, d, K, rule, m, family):
     rng = np.random.default_rng(100 * d + 10 * K + m)
     params = W.draw_params(rng, family, d)
     ref = brute_blocked(d, d + K, rule, family, params, m)
     for method in ("points", "factorised"):
         got = B.smolyak_blocked(d, d + K, rule, family, params, m, method)
-        osc = family in ("oscillatory", "oscillatory_quadratic")
+        osc = family in ("oscillatory", "oscillatory_quadratic", "oscillatory_quadratic_linear")
         assert abs(got - ref) <= 1e-13 * max(abs(ref), 1e-3 if osc else 0.0), (method, got, ref)
 
 

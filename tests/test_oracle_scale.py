@@ -21,7 +21,7 @@ def test_scale_of_non_oscillatory_is_abs(orc):
     assert np.array_equal(orc.accuracy_scale(b, ref), np.abs(ref))
 
 
-@pytest.mark.parametrize("family", ["oscillatory", "oscillatory_quadratic"])
+@pytest.mark.parametrize("family", ["oscillatory", "oscillatory_quadratic", "oscillatory_quadratic_linear"])
 def test_modulus_does_not_depend_on_w(orc, family):
     b = W.random_small(32, 16, d_range=(1, 30), k_range=(0, 5), families=(family,))
     ref = orc.batch_factorised(b)

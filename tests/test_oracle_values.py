@@ -122,6 +122,9 @@ def _f(family, params, X):
         return np.exp(((X - params[d:2 * d]) ** 2) @ params[:d])
     if family == "oscillatory_quadratic":
         return np.cos(2 * np.pi * params[0] + ((X - params[1 + d:1 + 2 * d]) ** 2) @ params[1:1 + d])
+    if family == "oscillatory_quadratic_linear":
+        return np.cos(2 * np.pi * params[0] + ((X - params[1 + d:1 + 2 * d]) ** 2) @ params[1:1 + d]
+                      + X @ params[1 + 2 * d:1 + 3 * d])
     b, u = params[:d], params[d:2 * d]
     return np.prod(1.0 / (b ** -2 + (X - u) ** 2), axis=-1)
 
@@ -145,7 +148,8 @@ def brute_smolyak(d, q, rule, family, params):
 
 SMALL = [(d, q, r, f) for (d, q) in [(1, 3), (2, 3), (2, 5), (3, 5), (3, 6), (4, 6)]
          for r in ("tr", "cc", "gl", "gl_paper", "gp")
-         for f in ("exp_sum", "oscillatory", "product_peak", "corner_peak", "gaussian", "oscillatory_quadratic")]
+         for f in ("exp_sum", "oscillatory", "product_peak", "corner_peak", "gaussian", "oscillatory_quadratic",
+                   "oscillatory_quadratic_linear")]
 
 
 @pytest.mark.parametrize("d,q,rule,family", SMALL)
@@ -173,7 +177,8 @@ def test_points_match_factorised(orc, case):
 
 
 def _quadratic_cases(seed, n):
-    b = W.random_small(seed, n, (1, 8), (0, 6), families=("gaussian", "oscillatory_quadratic"), rules=W.ALL_RULES)
+    b = W.random_small(seed, n, (1, 8), (0, 6), families=("gaussian", "oscillatory_quadratic",
+                                                          "oscillatory_quadratic_linear"), rules=W.ALL_RULES)
     return [(p.d, p.q, p.rule, p.family, b.param_slice(i)) for i, p in enumerate(b.problems)]
 
 
@@ -401,7 +406,8 @@ def test_two_dimensions_is_the_two_term_formula(orc):
 def test_factorised_gradient_matches_finite_differences(orc):
     rng = np.random.default_rng(21)
     for fam, rule, d, K in [("oscillatory", "cc", 8, 3), ("exp_sum", "gl", 6, 4), ("product_peak", "cc", 5, 3),
-                            ("gaussian", "gp", 5, 4), ("oscillatory_quadratic", "gl", 4, 3)]:
+                            ("gaussian", "gp", 5, 4), ("oscillatory_quadratic", "gl", 4, 3),
+                            ("oscillatory_quadratic_linear", "cc", 4, 3)]:
         params = W.draw_params(rng, fam, d)
         g = orc.smolyak_factorised_grad(d, d + K, rule, fam, params)
         h = 1e-6
@@ -425,7 +431,7 @@ def test_factorised_gradient_matches_closed_form(orc):
 
 
 # ------------------------------------------------ quadratic exponentials
-@pytest.mark.parametrize("family", ["gaussian", "oscillatory_quadratic"])
+@pytest.mark.parametrize("family", ["gaussian", "oscillatory_quadratic", "oscillatory_quadratic_linear"])
 def test_quadratic_families_converge_to_closed_form(orc, family):
     # entire integrands: high-level Gauss-Legendre sums reach the erf closed
     # forms (checked against mpmath quadrature in one dimension)
@@ -434,7 +440,7 @@ def test_quadratic_families_converge_to_closed_form(orc, family):
         prm = W.draw_params(rng, family, d)
         got = orc.smolyak_points(d, q, "gl", family, prm)["q"]
         ex = float(R.exact(family, d, prm))
-        assert abs(got - ex) <= 1e-12 * max(abs(ex), 1e-3 if family == "oscillatory_quadratic" else 0), (d, got, ex)
+        assert abs(got - ex) <= 1e-12 * max(abs(ex), 0 if family == "gaussian" else 1e-3), (d, got, ex)
     c, u, a, w = 1.7, 0.3, -2.2, 0.4
     with mp.workdps(30):
         q1 = mp.quad(lambda x: mp.exp(c * (x - u) ** 2), [0, 1])
@@ -454,3 +460,38 @@ def test_paper_table_4_1_first_row(orc):
         for val in (v, vf):
             rel = float(abs((mp.mpf(val) - ex) / ex))
             assert _same_to_5_digits(rel, row["rel_err"]), (row, rel)
+
+
+# ------------------------------------- quadratic phase with a linear term
+def test_linear_term_closed_form_against_quadrature():
+    # the completed-square closed form of int_0^1 e^{i (a (x-u)^2 + c x)} dx
+    # against mpmath's quadrature, including a = 0 (the linear oscillatory
+    # factor) and a small a with a far-off completed centre
+    for a, u, c in [(-2.2, 0.3, 1.1), (3.0, 0.9, -4.0), (0.0, 0.5, 2.5), (1e-3, 0.2, 0.7), (40.0, 0.5, 0.0)]:
+        with mp.workdps(30):
+            qre = mp.quad(lambda x: mp.cos(a * (x - u) ** 2 + c * x), [0, 1])
+            qim = mp.quad(lambda x: mp.sin(a * (x - u) ** 2 + c * x), [0, 1])
+        z = R._quad_linear_1d(a, u, c)
+        assert abs(complex(z) - complex(qre, qim)) < 1e-15, (a, u, c)
+
+
+@pytest.mark.parametrize("rule", ["cc", "gl", "gp"])
+def test_linear_term_reduces_to_the_other_oscillatory_families(orc, rule):
+    # c = 0 is the oscillatory quadratic; a = 0 is the linear oscillatory
+    # family (its own real-surplus code path in the oracle) with c as its
+    # coefficients, u unused
+    rng = np.random.default_rng(61)
+    for d, K in [(1, 4), (3, 3), (6, 2), (20, 4)]:
+        p = W.draw_params(rng, "oscillatory_quadratic_linear", d)
+        w, a, u, c = p[0], p[1:1 + d], p[1 + d:1 + 2 * d], p[1 + 2 * d:]
+        q0 = np.concatenate([[w], a, u, np.zeros(d)])
+        v0 = orc.smolyak_factorised(d, d + K, rule, "oscillatory_quadratic_linear", q0)
+        assert v0 == orc.smolyak_factorised(d, d + K, rule, "oscillatory_quadratic", p[:1 + 2 * d])
+        q1 = np.concatenate([[w], np.zeros(d), u, c])
+        v1 = orc.smolyak_factorised(d, d + K, rule, "oscillatory_quadratic_linear", q1)
+        v2 = orc.smolyak_factorised(d, d + K, rule, "oscillatory", np.concatenate([[w], c]))
+        assert abs(v1 - v2) <= 1e-15 * max(1.0, abs(v2)), (d, K, v1, v2)
+        if d <= 6:
+            pt = orc.smolyak_points(d, d + K, rule, "oscillatory_quadratic_linear", q1)["q"]
+            po = orc.smolyak_points(d, d + K, rule, "oscillatory", np.concatenate([[w], c]))["q"]
+            assert abs(pt - po) <= 1e-15 * max(1.0, abs(po))
