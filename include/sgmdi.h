@@ -78,18 +78,24 @@ typedef enum {
  *   GAUSSIAN      f(x) = exp(sum_i c_i (x_i - u_i)^2)             params c[d], u[d]
  *   OSCILLATORY_QUADRATIC
  *                 f(x) = cos(2 pi w + sum_i a_i (x_i - u_i)^2)    params w, a[d], u[d]
+ *   OSCILLATORY_QUADRATIC_LINEAR
+ *                 f(x) = cos(2 pi w + sum_i (a_i (x_i - u_i)^2 + c_i x_i))
+ *                                                               params w, a[d], u[d], c[d]
  * (PRODUCT_PEAK is the integrand of (4.4)/(5.2) with free widths/centres;
  * EXP_SUM generalises (4.5)/(5.1); OSCILLATORY generalises Table 5.7's;
  * GAUSSIAN covers (4.3) and the exponentials of (4.1)/(4.2) (c of either
  * sign; forward and reverse sweeps and point path), OSCILLATORY_QUADRATIC
- * their sines.  CORNER_PEAK is a ridge function that does not factor per
- * coordinate: the point-by-point path sg_integrate_points only.
- * OSCILLATORY_QUADRATIC factors with complex per-coordinate surpluses: the
- * point path, sg_integrate, and plans (a sweep with complex truncated
- * products, one workgroup per integrand beside the forward kernel), block
- * variant included, in every precision mode (the node values and
- * within-rule sums follow the mode; products, phase and read-out are FP64),
- * and its reverse sweep (FP64 in every mode, one workgroup per integrand).
+ * their sines, and OSCILLATORY_QUADRATIC_LINEAR the sine of (4.2) with its
+ * linear term (a coordinate may be quadratic, linear, both or neither).
+ * CORNER_PEAK is a ridge function that does not factor per coordinate: the
+ * point-by-point path sg_integrate_points only.  The two
+ * OSCILLATORY_QUADRATIC families factor with complex per-coordinate
+ * surpluses: the point path, sg_integrate, and plans (a sweep with complex
+ * truncated products, one workgroup per integrand beside the forward
+ * kernel), block variant included, in every precision mode (the node values
+ * and within-rule sums follow the mode; products, phase and read-out are
+ * FP64), and their reverse sweep (FP64 in every mode, one workgroup per
+ * integrand).
  * Plans reject CORNER_PEAK with UNSUPPORTED.) */
 typedef enum {
     SG_FAMILY_EXP_SUM = 0,
@@ -97,7 +103,8 @@ typedef enum {
     SG_FAMILY_PRODUCT_PEAK = 2,
     SG_FAMILY_CORNER_PEAK = 3,
     SG_FAMILY_GAUSSIAN = 4,
-    SG_FAMILY_OSCILLATORY_QUADRATIC = 5
+    SG_FAMILY_OSCILLATORY_QUADRATIC = 5,
+    SG_FAMILY_OSCILLATORY_QUADRATIC_LINEAR = 6
 } sg_family;
 
 /* Arithmetic of the per-coordinate work (node values and within-rule sums).
@@ -220,7 +227,7 @@ sg_status sg_unrank_device(sg_context *ctx, int32_t d, int32_t q, uint64_t rank0
  * validates every problem, builds (or reuses) the rule tables, orders the
  * work longest-first, picks tile/schedule parameters (from the context's
  * autotune results when present) and uploads the plan to the device.
- * OSCILLATORY_QUADRATIC problems run on the complex sweep in the plan's
+ * OSCILLATORY_QUADRATIC(_LINEAR) problems run on the complex sweep in the plan's
  * precision mode, one workgroup each, launched after the forward kernel on
  * the same stream.
  * Errors: INVALID_ARGUMENT (n < 1, NULL, a bad problem), UNSUPPORTED
@@ -269,7 +276,7 @@ sg_status sg_plan_execute(sg_plan *plan, const double *params_dev, double *out_d
 /* Gradient of every result with respect to every parameter (reverse sweep):
  * grad_params_dev[k] = grad_out_dev[i] * dQ_i/dparams[k] for the parameters
  * k of problem i, same layout as params.  Parameters not used by any problem
- * are left untouched.  OSCILLATORY_QUADRATIC problems take a complex reverse
+ * are left untouched.  OSCILLATORY_QUADRATIC(_LINEAR) problems take a complex reverse
  * sweep of their own (FP64 in every mode, one workgroup per integrand,
  * launched after the real one on the same stream).
  * Errors: INVALID_ARGUMENT (also: problems whose parameter ranges overlap),
@@ -308,7 +315,7 @@ sg_status sg_plan_execute_grad(sg_plan *plan, const double *params_dev, const do
  *   balanced: 0, or the waves per SIMD of the balanced schedule
  *   (sg_plan_set_schedule_balanced), which replaces coords_per_lane,
  *   max_group and cost_scaled;
- *   fp64_complex: how many of the plan's integrands (OSCILLATORY_QUADRATIC)
+ *   fp64_complex: how many of the plan's integrands (OSCILLATORY_QUADRATIC(_LINEAR))
  *   run on the complex sweep, whose forward sweep follows the plan's
  *   precision mode and whose reverse sweep (sg_plan_execute_grad) is FP64
  *   whatever the mode. */
@@ -401,7 +408,7 @@ sg_status sg_integrate_points(sg_context *ctx, const sg_problem *problem, const 
  * product of Section 3, (3.9)-(3.11), split by chunks).  The partials use a
  * scratch buffer the context allocates on the first call with d > 256
  * (about 160 KiB, kept until the context is destroyed); calls on one
- * context must not overlap in time.  Also takes OSCILLATORY_QUADRATIC in
+ * context must not overlap in time.  Also takes OSCILLATORY_QUADRATIC(_LINEAR) in
  * every precision mode: the sweep of Section 3 with the complex surpluses of
  * e^{i a (x - u)^2} (FP32 node values in the FP32 modes, FP64 complex
  * products and read-out) and the bound of the real sweep (complex moduli in

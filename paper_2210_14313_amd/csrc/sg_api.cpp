@@ -142,13 +142,17 @@ sg_status hip_fail(sg_context* ctx, hipError_t e, const char* what)
 bool family_ok(int f)
 {
     return f == SG_FAMILY_EXP_SUM || f == SG_FAMILY_OSCILLATORY || f == SG_FAMILY_PRODUCT_PEAK ||
-           f == SG_FAMILY_CORNER_PEAK || f == SG_FAMILY_GAUSSIAN || f == SG_FAMILY_OSCILLATORY_QUADRATIC;
+           f == SG_FAMILY_CORNER_PEAK || f == SG_FAMILY_GAUSSIAN || f == SG_FAMILY_OSCILLATORY_QUADRATIC ||
+           f == SG_FAMILY_OSCILLATORY_QUADRATIC_LINEAR;
 }
 
 // Families only the point-by-point path evaluates.
-bool family_points_only(int f)
+bool family_points_only(int f) { return f == SG_FAMILY_CORNER_PEAK; }
+
+// Families on the complex sweep (k_oscq).
+bool family_complex(int f)
 {
-    return f == SG_FAMILY_CORNER_PEAK || f == SG_FAMILY_OSCILLATORY_QUADRATIC;
+    return f == SG_FAMILY_OSCILLATORY_QUADRATIC || f == SG_FAMILY_OSCILLATORY_QUADRATIC_LINEAR;
 }
 
 sg_status validate_problem(sg_context* ctx, const sg_problem& p, int idx, bool point_path = false)
@@ -980,7 +984,7 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
     if (precision != SG_PREC_FP64 && precision != SG_PREC_FP32_COMPENSATED && precision != SG_PREC_FP32_FP64_SUM)
         return fail(ctx, SG_ERR_INVALID_ARGUMENT, "unknown precision");
     for (int i = 0; i < n; ++i) {
-        sg_status st = validate_problem(ctx, problems[i], i, problems[i].family == SG_FAMILY_OSCILLATORY_QUADRATIC);
+        sg_status st = validate_problem(ctx, problems[i], i);
         if (st != SG_OK) return st;
     }
     PlanOwner p(new sg_plan());
@@ -1027,7 +1031,7 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
         info.pair_evals = sat_add(info.pair_evals, sat_mul(d, (uint64_t)t.npairs));
         info.macs = sat_add(info.macs, sat_mul(d, macs));
         info.merge_flops = sat_add(info.merge_flops, sat_mul(d, K * K));
-        if (problems[i].family == SG_FAMILY_OSCILLATORY_QUADRATIC) continue;   // its own kernel
+        if (family_complex(problems[i].family)) continue;   // its own kernel
         p->kmax = std::max(p->kmax, (int)K);
         if (problems[i].family == SG_FAMILY_GAUSSIAN) has_gauss = true;
     }
@@ -1037,7 +1041,7 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
     std::vector<int> order;
     std::vector<OscqDesc> oscq;
     for (int i = 0; i < n; ++i) {
-        if (problems[i].family != SG_FAMILY_OSCILLATORY_QUADRATIC) {
+        if (!family_complex(problems[i].family)) {
             order.push_back(i);
             continue;
         }
@@ -1051,6 +1055,8 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
         q.K = problems[i].q - problems[i].d;
         q.rule = problems[i].rule;
         q.out_index = i;
+        q.lin = problems[i].family == SG_FAMILY_OSCILLATORY_QUADRATIC_LINEAR ? 1 : 0;
+        q.reserved = 0;
         oscq.push_back(q);
     }
     const int nr = (int)order.size();
@@ -1091,7 +1097,8 @@ sg_status sg_plan_create(sg_context* ctx, const sg_problem* problems, int32_t n,
             const int64_t d = problems[i].d;
             const int64_t len = f == SG_FAMILY_EXP_SUM ? d
                                 : f == SG_FAMILY_OSCILLATORY ? d + 1
-                                : f == SG_FAMILY_OSCILLATORY_QUADRATIC ? 2 * d + 1 : 2 * d;
+                                : f == SG_FAMILY_OSCILLATORY_QUADRATIC ? 2 * d + 1
+                                : f == SG_FAMILY_OSCILLATORY_QUADRATIC_LINEAR ? 3 * d + 1 : 2 * d;
             rg[i] = std::make_pair(problems[i].param_offset, problems[i].param_offset + len);
         }
         std::sort(rg.begin(), rg.end());
@@ -1289,8 +1296,7 @@ sg_status sg_plan_create_blocked(sg_context* ctx, const sg_problem* problems, in
     if (!problems || n < 1) return fail(ctx, SG_ERR_INVALID_ARGUMENT, "empty problem list");
     if (block_dims < 1) return fail(ctx, SG_ERR_INVALID_ARGUMENT, "block_dims must be >= 1");
     for (int i = 0; i < n; ++i) {
-        sg_status st = validate_problem(ctx, problems[i], i,
-                                        problems[i].family == SG_FAMILY_OSCILLATORY_QUADRATIC);
+        sg_status st = validate_problem(ctx, problems[i], i);
         if (st != SG_OK) return st;
     }
     // block sub-problems in integrand order, blocks in coordinate order
@@ -1306,7 +1312,7 @@ sg_status sg_plan_create_blocked(sg_context* ctx, const sg_problem* problems, in
         const sg_problem& P = problems[i];
         const int K = P.q - P.d;
         const int nb = (P.d + block_dims - 1) / block_dims;
-        const bool osc = P.family == SG_FAMILY_OSCILLATORY || P.family == SG_FAMILY_OSCILLATORY_QUADRATIC;
+        const bool osc = P.family == SG_FAMILY_OSCILLATORY || family_complex(P.family);
         if (sub.size() + (size_t)nb * (osc ? 2 : 1) > (size_t)INT32_MAX)
             return fail(ctx, SG_ERR_UNSUPPORTED, "too many blocks");
         bp[i].param_offset = P.param_offset;
@@ -1333,6 +1339,7 @@ sg_status sg_plan_create_blocked(sg_context* ctx, const sg_problem* problems, in
                 sub.push_back(sg_problem{len, len + K, P.rule, P.family, off});
                 off += P.family == SG_FAMILY_OSCILLATORY ? 1 + (int64_t)len
                        : P.family == SG_FAMILY_OSCILLATORY_QUADRATIC ? 1 + 2 * (int64_t)len
+                       : P.family == SG_FAMILY_OSCILLATORY_QUADRATIC_LINEAR ? 1 + 3 * (int64_t)len
                        : (P.family == SG_FAMILY_PRODUCT_PEAK || P.family == SG_FAMILY_GAUSSIAN) ? 2 * (int64_t)len
                                                                                                 : len;
             }
@@ -1356,7 +1363,7 @@ sg_status sg_plan_create_blocked(sg_context* ctx, const sg_problem* problems, in
     p->info.effective_points = eff;
     p->info.fp64_complex = 0;
     for (int i = 0; i < n; ++i)
-        if (problems[i].family == SG_FAMILY_OSCILLATORY_QUADRATIC) p->info.fp64_complex++;
+        if (family_complex(problems[i].family)) p->info.fp64_complex++;
     inner->use_graph = false;      // graphs, when chosen, hold all three launches
     inner->info.graph = 0;
     p->use_graph = false;
@@ -1620,7 +1627,7 @@ static sg_status check_one(sg_context* ctx, const sg_problem* problem, int32_t p
     if (!problem || !params_dev || !out_dev) return fail(ctx, SG_ERR_INVALID_ARGUMENT, "NULL argument");
     if (precision != SG_PREC_FP64 && precision != SG_PREC_FP32_COMPENSATED && precision != SG_PREC_FP32_FP64_SUM)
         return fail(ctx, SG_ERR_INVALID_ARGUMENT, "unknown precision");
-    return validate_problem(ctx, *problem, 0, problem->family == SG_FAMILY_OSCILLATORY_QUADRATIC);
+    return validate_problem(ctx, *problem, 0);
 }
 
 sg_status sg_integrate(sg_context* ctx, const sg_problem* problem, int32_t precision, const double* params_dev,
@@ -1647,9 +1654,10 @@ sg_status sg_integrate(sg_context* ctx, const sg_problem* problem, int32_t preci
             return hip_fail(ctx, e, "hipMemset");
         }
     }
-    const int rc = problem->family == SG_FAMILY_OSCILLATORY_QUADRATIC
-                       ? launch_oscq(precision, d, K, problem->rule, G, nullptr, nullptr, params_dev, out_dev,
-                                     bound_dev, ctx->one_ws, stream)
+    const int rc = family_complex(problem->family)
+                       ? launch_oscq(precision, d, K, problem->rule, G,
+                                     problem->family == SG_FAMILY_OSCILLATORY_QUADRATIC_LINEAR ? 1 : 0, nullptr,
+                                     nullptr, params_dev, out_dev, bound_dev, ctx->one_ws, stream)
                        : launch_one(precision, d, K, problem->rule, problem->family, G, params_dev, out_dev,
                                     bound_dev, ctx->one_ws, stream);
     if (rc != 0) return hip_fail(ctx, (hipError_t)rc, "plan-free launch");

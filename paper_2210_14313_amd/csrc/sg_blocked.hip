@@ -47,6 +47,13 @@ __global__ void __launch_bounds__(256) k_block_gather(const BlockSub* __restrict
             dst[1 + j] = src[1 + b.start + j];
             dst[1 + b.len + j] = src[1 + b.d + b.start + j];
         }
+    } else if (b.family == SG_FAMILY_OSCILLATORY_QUADRATIC_LINEAR) {
+        if (j0 == 0) dst[0] = b.part == 2 ? -0.25 : 0.0;
+        for (int j = j0; j < b.len; j += kGatherLanes) {
+            dst[1 + j] = src[1 + b.start + j];
+            dst[1 + b.len + j] = src[1 + b.d + b.start + j];
+            dst[1 + 2 * b.len + j] = src[1 + 2 * b.d + b.start + j];
+        }
     } else if (b.family == SG_FAMILY_PRODUCT_PEAK || b.family == SG_FAMILY_GAUSSIAN) {
         for (int j = j0; j < b.len; j += kGatherLanes) {
             dst[j] = src[b.start + j];
@@ -112,7 +119,8 @@ __global__ void __launch_bounds__(256) k_block_combine(const BlockProb* __restri
     const int lane = threadIdx.x & 63;
     if (i >= n) return;
     const BlockProb p = probs[i];
-    const bool osc = p.family == SG_FAMILY_OSCILLATORY || p.family == SG_FAMILY_OSCILLATORY_QUADRATIC;
+    const bool osc = p.family == SG_FAMILY_OSCILLATORY || p.family == SG_FAMILY_OSCILLATORY_QUADRATIC ||
+                     p.family == SG_FAMILY_OSCILLATORY_QUADRATIC_LINEAR;
     const double u = 1.1102230246251565e-16;
     Part acc{1.0, 0.0, 1.0, 0.0};
     for (int base = 0; base < p.nblocks; base += 64) {

@@ -197,7 +197,8 @@ int launch_block_combine(const BlockProb*, int, const double*, const double*, co
 {
     return launched();
 }
-int launch_oscq(int, int, int, int, int, const double*, const float*, const double*, double*, double*, double*, void*)
+int launch_oscq(int, int, int, int, int, int, const double*, const float*, const double*, double*, double*, double*,
+                void*)
 {
     return launched();
 }

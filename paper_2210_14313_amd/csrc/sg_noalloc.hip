@@ -61,10 +61,12 @@ int noalloc_launch(double* ptr, int precision, int d, int K, int rule, int famil
                    double* out, double* bound, void* stream)
 {
     const int G = one_workgroups(d);
-    const bool oscq = family == SG_FAMILY_OSCILLATORY_QUADRATIC;
+    const bool oscq = family == SG_FAMILY_OSCILLATORY_QUADRATIC || family == SG_FAMILY_OSCILLATORY_QUADRATIC_LINEAR;
     const long need = (long)kOneHead + (long)G * (oscq ? kOscqWords : kOneWords);
     if (need > (long)kNoAllocWords) return -1;
-    if (oscq) return launch_oscq(precision, d, K, rule, G, nullptr, nullptr, params, out, bound, ptr, stream);
+    if (oscq)
+        return launch_oscq(precision, d, K, rule, G, family == SG_FAMILY_OSCILLATORY_QUADRATIC_LINEAR ? 1 : 0, nullptr,
+                           nullptr, params, out, bound, ptr, stream);
     return launch_one(precision, d, K, rule, family, G, params, out, bound, ptr, stream);
 }
 

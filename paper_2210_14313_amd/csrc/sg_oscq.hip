@@ -1,13 +1,14 @@
-// Oscillatory-quadratic sweep: the FP64 forward launchers, the dispatch
-// over precision modes, and the complex reverse sweep (FP64 in every mode).
+// Oscillatory-quadratic sweep (with or without the linear term): the FP64
+// forward launchers, the dispatch over precision modes, and the complex
+// reverse sweep (FP64 in every mode).
 #include "sg_oscq_dev.hpp"
 
 namespace sg {
 
 // the FP32 modes' kernels are compiled in their own units
-extern template int launch_oscq_prec<SG_PREC_FP32_COMPENSATED>(int, int, int, int, const double*, const float*,
+extern template int launch_oscq_prec<SG_PREC_FP32_COMPENSATED>(int, int, int, int, int, const double*, const float*,
                                                                const double*, double*, double*, double*, void*);
-extern template int launch_oscq_prec<SG_PREC_FP32_FP64_SUM>(int, int, int, int, const double*, const float*,
+extern template int launch_oscq_prec<SG_PREC_FP32_FP64_SUM>(int, int, int, int, int, const double*, const float*,
                                                             const double*, double*, double*, double*, void*);
 extern template int launch_oscq_batch_prec<SG_PREC_FP32_COMPENSATED>(int, const OscqDesc*, const double*,
                                                                      const float*, const double*, double*, double*,
@@ -15,23 +16,23 @@ extern template int launch_oscq_batch_prec<SG_PREC_FP32_COMPENSATED>(int, const 
 extern template int launch_oscq_batch_prec<SG_PREC_FP32_FP64_SUM>(int, const OscqDesc*, const double*, const float*,
                                                                   const double*, double*, double*, void*);
 
-template int launch_oscq_prec<SG_PREC_FP64>(int, int, int, int, const double*, const float*, const double*, double*,
-                                            double*, double*, void*);
+template int launch_oscq_prec<SG_PREC_FP64>(int, int, int, int, int, const double*, const float*, const double*,
+                                            double*, double*, double*, void*);
 template int launch_oscq_batch_prec<SG_PREC_FP64>(int, const OscqDesc*, const double*, const float*, const double*,
                                                   double*, double*, void*);
 
-int launch_oscq(int precision, int d, int K, int rule, int G, const double* pool64, const float* pool32,
+int launch_oscq(int precision, int d, int K, int rule, int G, int lin, const double* pool64, const float* pool32,
                 const double* params, double* out, double* bound, double* scratch, void* stream)
 {
     switch (precision) {
     case SG_PREC_FP64:
-        return launch_oscq_prec<SG_PREC_FP64>(d, K, rule, G, pool64, pool32, params, out, bound, scratch, stream);
+        return launch_oscq_prec<SG_PREC_FP64>(d, K, rule, G, lin, pool64, pool32, params, out, bound, scratch, stream);
     case SG_PREC_FP32_COMPENSATED:
-        return launch_oscq_prec<SG_PREC_FP32_COMPENSATED>(d, K, rule, G, pool64, pool32, params, out, bound, scratch,
-                                                          stream);
+        return launch_oscq_prec<SG_PREC_FP32_COMPENSATED>(d, K, rule, G, lin, pool64, pool32, params, out, bound,
+                                                          scratch, stream);
     case SG_PREC_FP32_FP64_SUM:
-        return launch_oscq_prec<SG_PREC_FP32_FP64_SUM>(d, K, rule, G, pool64, pool32, params, out, bound, scratch,
-                                                       stream);
+        return launch_oscq_prec<SG_PREC_FP32_FP64_SUM>(d, K, rule, G, lin, pool64, pool32, params, out, bound,
+                                                       scratch, stream);
     default:
         return (int)hipErrorInvalidValue;
     }
@@ -55,24 +56,27 @@ int launch_oscq_batch(int precision, int n, const OscqDesc* descs, const double*
 namespace dev {
 
 // ------------------------------------------------------------ reverse sweep
-// Gradient of Q = Re(E S), E = e^{i Phi}, Phi = 2 pi w + sum_t a_t hv_t^2
+// Gradient of Q = Re(E S), E = e^{i Phi}, Phi = 2 pi w + sum_t (a_t hv_t^2 + c_t / 2)
 // (hv = 1/2 - u), S = sum_{b <= K} [z^b] prod_t D_t(z):
 //   dQ/dw = -2 pi Im(E S);
 //   dQ/dp_t = Re(E (i dPhi/dp_t S + sum_e G_t[e] d delta_t[e]/dp_t)),
 // with G_t[e] = sum_{j <= K-e} [z^j] R_t and R_t = prod_{t' != t} D_t' from
 // exclusive prefix and suffix products (no division), dPhi/da_t = hv_t^2,
-// dPhi/du_t = -2 a_t hv_t, and per pair (t1 = a y^2, t2 = a b y, b = 2 hv)
+// dPhi/du_t = -2 a_t hv_t, dPhi/dc_t = 1/2, and per pair (t1 = a y^2,
+// t2 = beta y, beta = a b + c, b = 2 hv)
 //   d pair/da = 2 e^{i t1} (i y^2 cos t2 - b y sin t2),
-//   d pair/du = 4 a y e^{i t1} sin t2.
+//   d pair/dc = -2 y e^{i t1} sin t2,
+//   d pair/du = -2 a d pair/dc (t2 depends on u through beta only), so the
+// surpluses' u-derivatives are -2 a times their c-derivatives.
 
-// Derivative surpluses of one coordinate with respect to a and u.
+// Derivative surpluses of one coordinate with respect to a and c.
 template <int K, int RC>
-__device__ __forceinline__ void dsurplus_oscq(const double* __restrict__ r64, double a, double b,
+__device__ __forceinline__ void dsurplus_oscq(const double* __restrict__ r64, double a, double b, double beta,
                                               double (&ar)[MAXK + 1], double (&ai)[MAXK + 1],
-                                              double (&ur)[MAXK + 1], double (&ui)[MAXK + 1])
+                                              double (&cr)[MAXK + 1], double (&ci)[MAXK + 1])
 {
 #pragma unroll
-    for (int e = 0; e <= MAXK; ++e) { ar[e] = 0.0; ai[e] = 0.0; ur[e] = 0.0; ui[e] = 0.0; }
+    for (int e = 0; e <= MAXK; ++e) { ar[e] = 0.0; ai[e] = 0.0; cr[e] = 0.0; ci[e] = 0.0; }
     static_for<2, K + 2>([&](auto Lc) {
         constexpr int L = decltype(Lc)::value;
         constexpr int np = rc_pairs(RC, L), lo = rc_elo(L), hi = rc_ehi(RC, K, L);
@@ -83,18 +87,18 @@ __device__ __forceinline__ void dsurplus_oscq(const double* __restrict__ r64, do
             const double y = r[0];
             double s1, c1, s2, c2;
             sincos(a * (y * y), &s1, &c1);
-            sincos(a * (b * y), &s2, &c2);
+            sincos(beta * y, &s2, &c2);
             const double pr = -b * y * s2, pi = y * y * c2;     // i y^2 cos t2 - b y sin t2
             const double dar = 2.0 * (c1 * pr - s1 * pi), dai = 2.0 * (c1 * pi + s1 * pr);
-            const double f = 4.0 * a * y * s2;
-            const double dur = f * c1, dui = f * s1;
+            const double f = -2.0 * y * s2;
+            const double dcr = f * c1, dci = f * s1;
 #pragma unroll
             for (int e = lo; e <= hi; ++e) {
                 const double w = r[1 + e - lo];
                 ar[e] = fma(w, dar, ar[e]);
                 ai[e] = fma(w, dai, ai[e]);
-                ur[e] = fma(w, dur, ur[e]);
-                ui[e] = fma(w, dui, ui[e]);
+                cr[e] = fma(w, dcr, cr[e]);
+                ci[e] = fma(w, dci, ci[e]);
             }
         }
     });
@@ -153,12 +157,15 @@ __device__ void oscq_grad_body(const OscqDesc& q, const double* __restrict__ r64
 #pragma unroll
     for (int k = 0; k <= MAXK; ++k) { Lr[k] = 0.0; Li[k] = 0.0; own_r[k] = 0.0; own_i[k] = 0.0; }
     double ph = 0.0;
+    const bool lin = q.lin != 0;
     for (int t = tid; t < d; t += 256) {
         const double a = prm[1 + t], hv = 0.5 - prm[1 + d + t];
+        const double c = lin ? prm[1 + 2 * d + t] : 0.0;
+        const double ab = a * (2.0 * hv);
         double dr[MAXK + 1], di[MAXK + 1], e_t = 0.0;
         int opaque = 0;
         asm volatile("" : "+s"(opaque));
-        surplus_oscq<K, RC>(r64 + opaque, a, 2.0 * hv, dr, di, e_t);
+        surplus_oscq<K, RC>(r64 + opaque, a, ab + c, fabs(ab) + fabs(c), dr, di, e_t);
         if (single) {
 #pragma unroll
             for (int k = 1; k <= K; ++k) { own_r[k] = dr[k]; own_i[k] = di[k]; }
@@ -170,7 +177,7 @@ __device__ void oscq_grad_body(const OscqDesc& q, const double* __restrict__ r64
             }
         }
         cpmul<K>(Lr, Li, dr, di);
-        ph += a * (hv * hv);
+        ph += fma(0.5, c, a * (hv * hv));
     }
 
     // exclusive prefix and suffix products over the 256 threads: DPP scans in
@@ -289,24 +296,29 @@ __device__ void oscq_grad_body(const OscqDesc& q, const double* __restrict__ r64
             }
         }
         const double a = prm[1 + t], hv = 0.5 - prm[1 + d + t];
-        double ar[MAXK + 1], ai[MAXK + 1], ur[MAXK + 1], ui[MAXK + 1];
+        const double c = lin ? prm[1 + 2 * d + t] : 0.0;
+        double ar[MAXK + 1], ai[MAXK + 1], cr[MAXK + 1], ci[MAXK + 1];
         int opaque = 0;
         asm volatile("" : "+s"(opaque));
-        dsurplus_oscq<K, RC>(r64 + opaque, a, 2.0 * hv, ar, ai, ur, ui);
-        double da_r = 0.0, da_i = 0.0, du_r = 0.0, du_i = 0.0;
+        dsurplus_oscq<K, RC>(r64 + opaque, a, 2.0 * hv, fma(a, 2.0 * hv, c), ar, ai, cr, ci);
+        double da_r = 0.0, da_i = 0.0, dc_r = 0.0, dc_i = 0.0;
 #pragma unroll
         for (int e = 1; e <= K; ++e) {
             da_r = fma(Gr[e], ar[e], fma(-Gi[e], ai[e], da_r));
             da_i = fma(Gr[e], ai[e], fma(Gi[e], ar[e], da_i));
-            du_r = fma(Gr[e], ur[e], fma(-Gi[e], ui[e], du_r));
-            du_i = fma(Gr[e], ui[e], fma(Gi[e], ur[e], du_i));
+            dc_r = fma(Gr[e], cr[e], fma(-Gi[e], ci[e], dc_r));
+            dc_i = fma(Gr[e], ci[e], fma(Gi[e], cr[e], dc_i));
         }
         // Z = i dPhi S + dS; dQ = Re(E Z) = cos Phi Re Z - sin Phi Im Z
-        const double pa = hv * hv, pu = -2.0 * a * hv;
+        const double pa = hv * hv, pu = -2.0 * a * hv, mu = -2.0 * a;
         const double za_r = da_r - pa * s_im, za_i = da_i + pa * s_re;
-        const double zu_r = du_r - pu * s_im, zu_i = du_i + pu * s_re;
+        const double zu_r = fma(mu, dc_r, -pu * s_im), zu_i = fma(mu, dc_i, pu * s_re);
         grad[q.param_offset + 1 + t] = g * fma(cs, za_r, -sn * za_i);
         grad[q.param_offset + 1 + d + t] = g * fma(cs, zu_r, -sn * zu_i);
+        if (lin) {
+            const double zc_r = fma(-0.5, s_im, dc_r), zc_i = fma(0.5, s_re, dc_i);
+            grad[q.param_offset + 1 + 2 * d + t] = g * fma(cs, zc_r, -sn * zc_i);
+        }
     }
 }
 

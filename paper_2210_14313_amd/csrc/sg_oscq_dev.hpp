@@ -1,18 +1,20 @@
-// Factorised sweep for the oscillatory quadratic cos(2 pi w + sum_t a_t (x_t - u_t)^2)
-// (the sines of (4.1)/(4.2) in any dimension): device code of the forward
+// Factorised sweep for the oscillatory quadratic cos(2 pi w + sum_t a_t (x_t - u_t)^2),
+// optionally with a linear term sum_t c_t x_t in the phase (the sines of
+// (4.1)/(4.2) in any dimension): device code of the forward
 // sweep, templated on the precision mode (node values in FP64, or in FP32
 // with compensated FP32 or FP64 within-rule sums; truncated products, phase
 // and read-out in FP64 in every mode), and the helpers the reverse sweep
 // shares.
 //
-// Per coordinate the factor g_t(x) = e^{i a_t (x - u_t)^2}, centred at x = 1/2
-// and written in y = x - 1/2, is g_t(1/2) (1 + h_t(y)) with
-// h_t(y) = e^{i a_t (y^2 + b_t y)} - 1, b_t = 1 - 2 u_t.  The difference rules
-// are symmetric about 1/2, so each sees only the even part, through the pair
-// value h(y) + h(-y) = 2 (e^{i a y^2} cos(a b y) - 1): complex, unlike the
-// linear oscillatory family whose pair values are real.  The surpluses
-// delta_t[e] (e = 1..K) are therefore complex, and the Smolyak sum (2.6) is
-// Q = Re(e^{i (2 pi w + sum_t a_t (1/2 - u_t)^2)} sum_{b <= K} [z^b] prod_t D_t(z)),
+// Per coordinate the factor g_t(x) = e^{i (a_t (x - u_t)^2 + c_t x)}, centred
+// at x = 1/2 and written in y = x - 1/2, is g_t(1/2) (1 + h_t(y)) with
+// h_t(y) = e^{i (a_t y^2 + beta_t y)} - 1, beta_t = a_t (1 - 2 u_t) + c_t
+// (c_t = 0 without the linear term).  The difference rules are symmetric
+// about 1/2, so each sees only the even part, through the pair value
+// h(y) + h(-y) = 2 (e^{i a y^2} cos(beta y) - 1): complex, unlike the linear
+// oscillatory family whose pair values are real.  The surpluses delta_t[e]
+// (e = 1..K) are therefore complex, and the Smolyak sum (2.6) is
+// Q = Re(e^{i (2 pi w + sum_t (a_t (1/2 - u_t)^2 + c_t / 2))} sum_{b <= K} [z^b] prod_t D_t(z)),
 // D_t(z) = 1 + sum_e delta_t[e] z^e, with complex truncated products.
 //
 // A plan gives each oscillatory-quadratic integrand one workgroup of 256
@@ -53,21 +55,24 @@ __device__ __forceinline__ void cpmul(double (&ar)[MAXK + 1], double (&ai)[MAXK 
     }
 }
 
-// Pair value 2 (e^{i t1} cos t2 - 1), t1 = a y^2, t2 = a b y, free of
+// Pair value 2 (e^{i t1} cos t2 - 1), t1 = a y^2, t2 = beta y, free of
 // cancellation: real part -4 (sin^2(t1/2) cos t2 + sin^2(t2/2)), imaginary
 // part 4 sin(t1/2) cos(t1/2) cos t2.  `mag` bounds |re| + |im| plus the
 // arguments' magnitudes, against which the bound charges each pair (the
-// arguments carry a relative rounding, the sines an absolute one).
-__device__ __forceinline__ void pair_oscq(double a, double b, double y, double& re, double& im, double& mag)
+// arguments carry a relative rounding, the sines an absolute one); t2's
+// magnitude is taken as bmag |y| with bmag = |a (1 - 2u)| + |c| >= |beta|,
+// which also covers the rounding of beta's two terms when they cancel.
+__device__ __forceinline__ void pair_oscq(double a, double beta, double bmag, double y, double& re, double& im,
+                                          double& mag)
 {
-    const double t1 = a * (y * y), t2 = a * (b * y);
+    const double t1 = a * (y * y), t2 = beta * y;
     double s1, c1, s2, c2h;
     sincos(0.5 * t1, &s1, &c1);
     sincos(0.5 * t2, &s2, &c2h);
     const double c2 = fma(-2.0 * s2, s2, 1.0);
     re = -4.0 * fma(s1 * s1, c2, s2 * s2);
     im = 4.0 * (s1 * c1) * c2;
-    mag = fabs(re) + fabs(im) + fabs(t1) + fabs(t2);
+    mag = fabs(re) + fabs(im) + fabs(t1) + bmag * fabs(y);
 }
 
 // The same pair value in FP32 (the FP32 precision modes).  With
@@ -81,20 +86,21 @@ __device__ __forceinline__ void pair_oscq(double a, double b, double y, double& 
 // imaginary part 10; the bound charges 14 units of `mag` (which is rounded
 // down by at most one).  Outside the series range the FP64 values are
 // rounded once (their error is below one unit of `mag`).
-__device__ __forceinline__ void pair_oscq32(double a, double b, double y, float& re, float& im, float& mag)
+__device__ __forceinline__ void pair_oscq32(double a, double beta, double bmag, double y, float& re, float& im,
+                                            float& mag)
 {
-    const float t1 = (float)(a * (y * y)), t2 = (float)(a * (b * y));
+    const float t1 = (float)(a * (y * y)), t2 = (float)(beta * y);
     if (fabsf(t1) <= 1.0f && fabsf(t2) <= 1.0f) {
         const float z1 = -(t1 * t1), z2 = -(t2 * t2);
         const float p1 = z1 * series32w(z1), p2 = z2 * series32w(z2);
         const float c2 = fmaf(0.5f, p2, 1.0f);
         re = fmaf(p1, c2, p2);
         im = (2.0f * t1) * (series_s32w(z1) * c2);
-        mag = fabsf(re) + fabsf(im) + fabsf(t1) + fabsf(t2);
+        mag = fabsf(re) + fabsf(im) + fabsf(t1) + (float)(bmag * fabs(y));
         return;
     }
     double r, i, m;
-    pair_oscq(a, b, y, r, i, m);
+    pair_oscq(a, beta, bmag, y, r, i, m);
     re = (float)r;
     im = (float)i;
     mag = (float)m;
@@ -103,7 +109,7 @@ __device__ __forceinline__ void pair_oscq32(double a, double b, double y, float&
 // Complex surpluses of one coordinate from the (rule class, K) record table
 // (per pair: y, dW[elo..ehi], sum_e |dW|); eps accumulates sum_e |dW| * mag.
 template <int K, int RC>
-__device__ __forceinline__ void surplus_oscq(const double* __restrict__ r64, double a, double b,
+__device__ __forceinline__ void surplus_oscq(const double* __restrict__ r64, double a, double beta, double bmag,
                                              double (&dr)[MAXK + 1], double (&di)[MAXK + 1], double& eps)
 {
 #pragma unroll
@@ -116,7 +122,7 @@ __device__ __forceinline__ void surplus_oscq(const double* __restrict__ r64, dou
         for (int j = 0; j < np; ++j) {
             const double* r = r64 + off + j * rl;
             double pr, pi, pm;
-            pair_oscq(a, b, r[0], pr, pi, pm);
+            pair_oscq(a, beta, bmag, r[0], pr, pi, pm);
 #pragma unroll
             for (int e = lo; e <= hi; ++e) {
                 dr[e] = fma(r[1 + e - lo], pr, dr[e]);
@@ -133,8 +139,8 @@ __device__ __forceinline__ void surplus_oscq(const double* __restrict__ r64, dou
 // the FP64 weights; eps as in surplus_oscq.
 template <int PREC, int K, int RC>
 __device__ __forceinline__ void surplus_oscq32(const double* __restrict__ r64, const float* __restrict__ r32,
-                                               double a, double b, double (&dr)[MAXK + 1], double (&di)[MAXK + 1],
-                                               double& eps)
+                                               double a, double beta, double bmag, double (&dr)[MAXK + 1],
+                                               double (&di)[MAXK + 1], double& eps)
 {
     float rh[MAXK + 1], rlo[MAXK + 1], ih[MAXK + 1], ilo[MAXK + 1];
 #pragma unroll
@@ -152,7 +158,7 @@ __device__ __forceinline__ void surplus_oscq32(const double* __restrict__ r64, c
         for (int j = 0; j < np; ++j) {
             const double* r = r64 + off + j * rl;
             float pr, pi, pm;
-            pair_oscq32(a, b, r[0], pr, pi, pm);
+            pair_oscq32(a, beta, bmag, r[0], pr, pi, pm);
             if constexpr (PREC == SG_PREC_FP32_COMPENSATED) {
                 const float* w = r32 + off32 + j * rl32;
 #pragma unroll
@@ -236,27 +242,30 @@ __device__ __forceinline__ void oscq_load(OscqAcc& x, const double* s)
 // t = b 256 + tid + j 256 G; thread 0 returns the workgroup's state (its
 // four waves joined in wave order).
 template <int PREC, int K, int RC>
-__device__ void oscq_partial(int d, int b, int G, const double* __restrict__ r64, const float* __restrict__ r32,
-                             const double* __restrict__ prm, double* lds, OscqAcc& x)
+__device__ void oscq_partial(int d, int b, int G, bool lin, const double* __restrict__ r64,
+                             const float* __restrict__ r32, const double* __restrict__ prm, double* lds, OscqAcc& x)
 {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     oscq_identity<K>(x);
     for (int t = b * 256 + tid; t < d; t += 256 * G) {
         const double a = prm[1 + t], hv = 0.5 - prm[1 + d + t];
+        const double c = lin ? prm[1 + 2 * d + t] : 0.0;
+        const double ab = a * (2.0 * hv);
+        const double beta = ab + c, bmag = fabs(ab) + fabs(c);
         double dr[MAXK + 1], di[MAXK + 1], e_t = 0.0;
         int opaque = 0;
         asm volatile("" : "+s"(opaque));
-        if constexpr (PREC == SG_PREC_FP64) surplus_oscq<K, RC>(r64 + opaque, a, 2.0 * hv, dr, di, e_t);
-        else surplus_oscq32<PREC, K, RC>(r64 + opaque, r32 + opaque, a, 2.0 * hv, dr, di, e_t);
+        if constexpr (PREC == SG_PREC_FP64) surplus_oscq<K, RC>(r64 + opaque, a, beta, bmag, dr, di, e_t);
+        else surplus_oscq32<PREC, K, RC>(r64 + opaque, r32 + opaque, a, beta, bmag, dr, di, e_t);
         cpmul<K>(x.ar, x.ai, dr, di);
         double mt = 0.0;
 #pragma unroll
         for (int k = 1; k <= K; ++k) mt += fabs(dr[k]) + fabs(di[k]);
         x.m += mt;
         x.eps += e_t;
-        const double term = a * (hv * hv);          // phase of g_t(1/2)
-        x.ph += term;
-        x.phabs += fabs(term);
+        const double sq = a * (hv * hv);
+        x.ph += fma(0.5, c, sq);                     // phase of g_t(1/2)
+        x.phabs += fabs(sq) + fabs(0.5 * c);
     }
     for (int off = 32; off >= 1; off >>= 1) {
         OscqAcc y;
@@ -305,21 +314,22 @@ __device__ void oscq_readout(const OscqAcc& x, int d, int depth, const double* _
         // coefficients of every partial product are bounded in sum by
         // exp(sum_t sum_e |delta_t[e]|) (as for the real sweep)
         const double sabs = exp(x.m) * (1.0 + 1e-13);
-        // per pair term, relative to mag: FP64 values 8 roundings and one
+        // per pair term, relative to mag: FP64 values 12 roundings and one
         // FMA chain over the table's pairs; FP32 values 14 units of 2^-24
         // (pair_oscq32) plus, with compensated FP32 sums, one rounding of
         // the product and the second-order 2^-47 per pair of the low-part
         // chain, or, with FP64 sums, the FP64 chain
         const double np = (double)total_pairs<RC, K>();
         const double u32 = 5.9604644775390625e-08;
-        const double rel = PREC == SG_PREC_FP64               ? u64 * (8.0 + np)
+        const double rel = PREC == SG_PREC_FP64               ? u64 * (12.0 + np)
                            : PREC == SG_PREC_FP32_COMPENSATED ? u32 * 16.0 + 7.105427357601002e-15 * np
                                                               : u32 * 15.0 + u64 * (8.0 + np);
         // product tree: a complex truncated product rounds each component at
         // most 2K + 2 times per level
         const double dsum = sabs * (rel * x.eps + (2.0 * K + 4.0) * (double)depth * u64);
-        // phase: d - 1 additions of terms rounded twice each, and 2 pi w
-        const double ph_err = u64 * (double)(d + 3) * x.phabs + 2.0 * u64 * fabs(wp);
+        // phase: d - 1 additions of terms rounded at most three times each,
+        // and 2 pi w
+        const double ph_err = u64 * (double)(d + 4) * x.phabs + 2.0 * u64 * fabs(wp);
         const double smag = sqrt(fma(sr, sr, si * si)) + dsum;
         bound[0] = dsum + smag * (ph_err + u64 * (fabs(phase) + 8.0));
     }
@@ -334,12 +344,12 @@ constexpr int kOscqHeadWords = 32;
 static_assert(kOscqHeadWords == kOscqScratchHead, "scratch layout shared with the host");
 
 template <int PREC, int K, int RC>
-__device__ void oscq_body(int d, int b, int G, const double* __restrict__ r64, const float* __restrict__ r32,
-                          const double* __restrict__ prm, double* __restrict__ out, double* __restrict__ bound,
-                          double* __restrict__ scratch, double* lds, int* last)
+__device__ void oscq_body(int d, int b, int G, bool lin, const double* __restrict__ r64,
+                          const float* __restrict__ r32, const double* __restrict__ prm, double* __restrict__ out,
+                          double* __restrict__ bound, double* __restrict__ scratch, double* lds, int* last)
 {
     OscqAcc x;
-    oscq_partial<PREC, K, RC>(d, b, G, r64, r32, prm, lds, x);
+    oscq_partial<PREC, K, RC>(d, b, G, lin, r64, r32, prm, lds, x);
     // a thread's ceil(d / (256 G)) coordinates, 6 butterfly levels, 3 wave joins
     const int chain = (d + 256 * G - 1) / (256 * G);
     if (G == 1) {
@@ -382,19 +392,24 @@ __device__ void oscq_body(int d, int b, int G, const double* __restrict__ r64, c
     }
 }
 
-// b: this workgroup's index among the G of one integrand.
+// b: this workgroup's index among the G of one integrand; lin: the
+// parameters carry the linear coefficients c[d] after u[d].
 template <int PREC>
-__device__ __forceinline__ void oscq_dispatch(int d, int K, int rule, int b, int G, const double* r64,
+__device__ __forceinline__ void oscq_dispatch(int d, int K, int rule, int b, int G, bool lin, const double* r64,
                                               const float* r32, const double* prm, double* out, double* bound,
                                               double* scratch, double* lds, int* last)
 {
     const int rc = rule_class_of(rule);
     switch_k<MAXK>(K, [&](auto kc) {
         constexpr int KK = decltype(kc)::value;
-        if (rc == RC_NESTED) oscq_body<PREC, KK, RC_NESTED>(d, b, G, r64, r32, prm, out, bound, scratch, lds, last);
-        else if (rc == RC_GL2) oscq_body<PREC, KK, RC_GL2>(d, b, G, r64, r32, prm, out, bound, scratch, lds, last);
-        else if (rc == RC_GP) oscq_body<PREC, KK, RC_GP>(d, b, G, r64, r32, prm, out, bound, scratch, lds, last);
-        else oscq_body<PREC, KK, RC_GLP>(d, b, G, r64, r32, prm, out, bound, scratch, lds, last);
+        if (rc == RC_NESTED)
+            oscq_body<PREC, KK, RC_NESTED>(d, b, G, lin, r64, r32, prm, out, bound, scratch, lds, last);
+        else if (rc == RC_GL2)
+            oscq_body<PREC, KK, RC_GL2>(d, b, G, lin, r64, r32, prm, out, bound, scratch, lds, last);
+        else if (rc == RC_GP)
+            oscq_body<PREC, KK, RC_GP>(d, b, G, lin, r64, r32, prm, out, bound, scratch, lds, last);
+        else
+            oscq_body<PREC, KK, RC_GLP>(d, b, G, lin, r64, r32, prm, out, bound, scratch, lds, last);
     });
 }
 
@@ -402,7 +417,7 @@ __device__ __forceinline__ void oscq_dispatch(int d, int K, int rule, int b, int
 // pool64 == nullptr: the (rule, K) records compiled into the library.
 template <int PREC>
 __global__ void __launch_bounds__(256)
-k_oscq(int d, int K, int rule, int G, const double* __restrict__ pool64, const float* __restrict__ pool32,
+k_oscq(int d, int K, int rule, int G, int lin, const double* __restrict__ pool64, const float* __restrict__ pool32,
        const double* __restrict__ params, double* __restrict__ out, double* __restrict__ bound,
        double* __restrict__ scratch)
 {
@@ -411,7 +426,7 @@ k_oscq(int d, int K, int rule, int G, const double* __restrict__ pool64, const f
     const double* r64 = pool64;
     const float* r32 = pool32;
     if (!r64) tabd::records(rule, K, &r64, &r32);
-    oscq_dispatch<PREC>(d, K, rule, (int)blockIdx.x, G, r64, r32, params, out, bound, scratch, lds, &last);
+    oscq_dispatch<PREC>(d, K, rule, (int)blockIdx.x, G, lin != 0, r64, r32, params, out, bound, scratch, lds, &last);
 }
 
 // Workgroup b runs descriptor b (one workgroup per integrand).
@@ -423,8 +438,9 @@ k_oscq_batch(const OscqDesc* __restrict__ descs, const double* __restrict__ pool
     __shared__ double lds[4 * OSCQ_WORDS];
     __shared__ int last;
     const OscqDesc q = descs[blockIdx.x];
-    oscq_dispatch<PREC>(q.d, q.K, q.rule, 0, 1, pool64 + q.off64, pool32 + q.off32, params + q.param_offset,
-                        out + q.out_index, bound ? bound + q.out_index : nullptr, nullptr, lds, &last);
+    oscq_dispatch<PREC>(q.d, q.K, q.rule, 0, 1, q.lin != 0, pool64 + q.off64, pool32 + q.off32,
+                        params + q.param_offset, out + q.out_index, bound ? bound + q.out_index : nullptr, nullptr,
+                        lds, &last);
 }
 
 }  // namespace dev
@@ -432,11 +448,11 @@ k_oscq_batch(const OscqDesc* __restrict__ descs, const double* __restrict__ pool
 // Launchers of one precision mode (instantiated in sg_oscq.hip for FP64 and
 // in sg_oscq_p1.hip / sg_oscq_p2.hip for the FP32 modes).
 template <int PREC>
-int launch_oscq_prec(int d, int K, int rule, int G, const double* pool64, const float* pool32, const double* params,
-                     double* out, double* bound, double* scratch, void* stream)
+int launch_oscq_prec(int d, int K, int rule, int G, int lin, const double* pool64, const float* pool32,
+                     const double* params, double* out, double* bound, double* scratch, void* stream)
 {
-    hipLaunchKernelGGL(dev::k_oscq<PREC>, dim3((unsigned)G), dim3(256), 0, (hipStream_t)stream, d, K, rule, G, pool64,
-                       pool32, params, out, bound, scratch);
+    hipLaunchKernelGGL(dev::k_oscq<PREC>, dim3((unsigned)G), dim3(256), 0, (hipStream_t)stream, d, K, rule, G, lin,
+                       pool64, pool32, params, out, bound, scratch);
     return (int)hipGetLastError();
 }
 

@@ -4,7 +4,7 @@
 
 namespace sg {
 
-template int launch_oscq_prec<SG_PREC_FP32_FP64_SUM>(int, int, int, int, const double*, const float*,
+template int launch_oscq_prec<SG_PREC_FP32_FP64_SUM>(int, int, int, int, int, const double*, const float*,
                                       const double*, double*, double*, double*, void*);
 template int launch_oscq_batch_prec<SG_PREC_FP32_FP64_SUM>(int, const OscqDesc*, const double*, const float*,
                                             const double*, double*, double*, void*);

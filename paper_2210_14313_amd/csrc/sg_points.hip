@@ -45,16 +45,18 @@ constexpr int FAM_PEAK = SG_FAMILY_PRODUCT_PEAK;
 constexpr int FAM_CORNER = SG_FAMILY_CORNER_PEAK;
 constexpr int FAM_GAUSS = SG_FAMILY_GAUSSIAN;
 constexpr int FAM_OSCQ = SG_FAMILY_OSCILLATORY_QUADRATIC;
+constexpr int FAM_OSCQL = SG_FAMILY_OSCILLATORY_QUADRATIC_LINEAR;
 
 // Families whose partial quantity is an angle (cosine of a sum).
 template <int FAM>
-constexpr bool is_angle() { return FAM == FAM_OSC || FAM == FAM_OSCQ; }
-// Quadratic families: per coordinate (c, u) with the exponent c (x - u)^2.
+constexpr bool is_angle() { return FAM == FAM_OSC || FAM == FAM_OSCQ || FAM == FAM_OSCQL; }
+// Quadratic families: per coordinate (c, u) with the exponent c (x - u)^2
+// (and, for FAM_OSCQL, a linear term l x with l[d] after u[d]).
 template <int FAM>
-constexpr bool is_quadratic() { return FAM == FAM_GAUSS || FAM == FAM_OSCQ; }
+constexpr bool is_quadratic() { return FAM == FAM_GAUSS || FAM == FAM_OSCQ || FAM == FAM_OSCQL; }
 // Offset of c[0] in the parameters of a quadratic family (u follows at + d).
 template <int FAM>
-constexpr int quad_off() { return FAM == FAM_OSCQ ? 1 : 0; }
+constexpr int quad_off() { return FAM == FAM_OSCQ || FAM == FAM_OSCQL ? 1 : 0; }
 
 // sin(h) = h * sum_k (-h^2)^k/(2k+1)! and cos(h) = sum_k (-h^2)^k/(2k)!,
 // k = 0..8, for |h| <= 0.78 (< pi/4): the first omitted terms are below
@@ -101,6 +103,11 @@ __device__ __forceinline__ double centre_value(const double* __restrict__ prm, i
         else if constexpr (is_quadratic<FAM>()) {
             const double hv = 0.5 - prm[quad_off<FAM>() + d + t];
             v = prm[quad_off<FAM>() + t] * (hv * hv);
+            if constexpr (FAM == FAM_OSCQL) {   // the linear term's part l / 2
+                const double lv = 0.5 * prm[1 + 2 * d + t];
+                s += lv;
+                sa += fabs(lv);
+            }
         } else {
             const double b = prm[t], u = prm[d + t];
             const double hv = 0.5 - u;
@@ -272,7 +279,8 @@ __global__ void __launch_bounds__(256) k_points(PointsArgs A)
             // pre[m] / suf[m]: tensor sizes of coordinates [0, m) / [m, nnz)
             int nm[KMAXP], bm[KMAXP], cm[KMAXP], lm[KMAXP], pre[KMAXP + 1], suf[KMAXP + 1];
             // quadratic families: rounding scale of a coordinate's entries,
-            // |c| (1 + |1 - 2u|) (the change c y (y + 1 - 2u) may cancel)
+            // |c| (1 + |1 - 2u|) (the change c y (y + 1 - 2u) may cancel),
+            // plus |l| for a linear term
             double es[KMAXP];
             int E = 0;
             pre[0] = 1;
@@ -286,6 +294,7 @@ __global__ void __launch_bounds__(256) k_points(PointsArgs A)
                     if constexpr (is_quadratic<FAM>())
                         es[m] = fabs(prm[quad_off<FAM>() + cm[m]]) *
                                 (1.0 + fabs(1.0 - 2.0 * prm[quad_off<FAM>() + d + cm[m]]));
+                    if constexpr (FAM == FAM_OSCQL) es[m] += fabs(prm[1 + 2 * d + cm[m]]);
                 } else {
                     cm[m] = 0; lm[m] = 1; nm[m] = 1;
                 }
@@ -326,6 +335,7 @@ __global__ void __launch_bounds__(256) k_points(PointsArgs A)
                     // c (x - u)^2 - c (1/2 - u)^2 = c y (y + 1 - 2u)
                     const double c = prm[quad_off<FAM>() + coord], u = prm[quad_off<FAM>() + d + coord];
                     q = c * (y * (y + (1.0 - 2.0 * u)));
+                    if constexpr (FAM == FAM_OSCQL) q = fma(prm[1 + 2 * d + coord], y, q);
                 } else {
                     const double b = prm[coord], u = prm[d + coord];
                     const double beta = 1.0 / (b * b), hv = 0.5 - u;
@@ -516,9 +526,13 @@ int launch_points(int family, const PointsLaunch& L, void* stream)
         hipLaunchKernelGGL(pts::k_points<pts::FAM_GAUSS>, grid, block, shmem, s, A);
         hipLaunchKernelGGL(pts::k_points_finish<pts::FAM_GAUSS>, dim3(1), block, 0, s, L.partial, L.grid * 4,
                            L.params, L.d, L.out, L.bound);
-    } else {
+    } else if (family == SG_FAMILY_OSCILLATORY_QUADRATIC) {
         hipLaunchKernelGGL(pts::k_points<pts::FAM_OSCQ>, grid, block, shmem, s, A);
         hipLaunchKernelGGL(pts::k_points_finish<pts::FAM_OSCQ>, dim3(1), block, 0, s, L.partial, L.grid * 4,
+                           L.params, L.d, L.out, L.bound);
+    } else {
+        hipLaunchKernelGGL(pts::k_points<pts::FAM_OSCQL>, grid, block, shmem, s, A);
+        hipLaunchKernelGGL(pts::k_points_finish<pts::FAM_OSCQL>, dim3(1), block, 0, s, L.partial, L.grid * 4,
                            L.params, L.d, L.out, L.bound);
     }
     return (int)hipGetLastError();

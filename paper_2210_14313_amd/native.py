@@ -19,7 +19,7 @@ LIB_PATH = os.environ.get("SGMDI_LIB") or os.path.join(_HERE, "libsgmdi.so")
 
 RULES = {"tr": 1, "cc": 2, "gp": 3, "gl": 4, "gl_paper": 5}
 FAMILIES = {"exp_sum": 0, "oscillatory": 1, "product_peak": 2, "corner_peak": 3, "gaussian": 4,
-            "oscillatory_quadratic": 5}
+            "oscillatory_quadratic": 5, "oscillatory_quadratic_linear": 6}
 PRECISIONS = {"fp64": 0, "fp32c": 1, "fp32e": 2}
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "overflow", 4: "out of memory",
           5: "device error", 6: "capture error"}
@@ -208,7 +208,7 @@ def make_problems(problems) -> ctypes.Array:
 
 # Parameters of one integrand by family (include/sgmdi.h, sg_family).
 _PARAMS_PER_FAMILY = {"exp_sum": (1, 0), "oscillatory": (1, 1), "product_peak": (2, 0), "corner_peak": (1, 0),
-                      "gaussian": (2, 0), "oscillatory_quadratic": (2, 1)}
+                      "gaussian": (2, 0), "oscillatory_quadratic": (2, 1), "oscillatory_quadratic_linear": (3, 1)}
 
 
 def n_params(family: str, d: int) -> int:

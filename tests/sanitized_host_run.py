@@ -42,7 +42,7 @@ class PlanInfo(ctypes.Structure):
 
 
 NPARAMS = {0: lambda d: d, 1: lambda d: d + 1, 2: lambda d: 2 * d, 3: lambda d: d, 4: lambda d: 2 * d,
-           5: lambda d: 2 * d + 1}
+           5: lambda d: 2 * d + 1, 6: lambda d: 3 * d + 1}
 
 
 def load(path):
@@ -148,7 +148,7 @@ def mixed_batch(seed, with_oscq=True):
     probs = []
     off = 0
     dims = [1, 2, 3, 7, 63, 64, 65, 257, 1000, 4096, 5000]
-    fams = [0, 1, 2, 4] + ([5] if with_oscq else [])
+    fams = [0, 1, 2, 4] + ([5, 6] if with_oscq else [])
     for i in range(40):
         d = int(dims[i % len(dims)])
         K = int(rng.integers(0, 9))
@@ -187,7 +187,7 @@ def plans(L, ctx, statuses):
                 continue
             info = PlanInfo()
             statuses.append(["get_info", L.sg_plan_get_info(plan, ctypes.byref(info))])
-            statuses.append(["fp64_complex", info.fp64_complex, sum(1 for p in probs if p[3] == 5)])
+            statuses.append(["fp64_complex", info.fp64_complex, sum(1 for p in probs if p[3] in (5, 6))])
             outs = [np.zeros(n) for _ in range(10)]
             bound = np.zeros(n)
             grad = np.zeros(len(params))
@@ -217,7 +217,7 @@ def plans(L, ctx, statuses):
         statuses.append(["plan_reuse", L.sg_plan_create(ctx, arr, n, 0, ctypes.byref(plan))])
         L.sg_plan_destroy(plan)
         # block variant (no oscillatory-quadratic problems)
-        bprobs = [p for p in probs if p[3] != 5]
+        bprobs = [p for p in probs if p[3] not in (5, 6)]
         barr = problems_array(bprobs)
         for m in (1, 2, 3, 10, 10000, 0):
             plan = vp()
@@ -240,7 +240,7 @@ def plans(L, ctx, statuses):
             if st == 0:
                 info = PlanInfo()
                 L.sg_plan_get_info(plan, ctypes.byref(info))
-                statuses.append(["fp64_complex", info.fp64_complex, sum(1 for p in probs if p[3] == 5)])
+                statuses.append(["fp64_complex", info.fp64_complex, sum(1 for p in probs if p[3] in (5, 6))])
                 L.sg_plan_destroy(plan)
     # rejected plans
     for bad in [[(0, 1, 2, 0, 0)], [(3, 2, 2, 0, 0)], [(3, 5, 9, 0, 0)], [(3, 5, 2, 9, 0)], [(3, 12, 2, 0, 0)],
@@ -254,7 +254,7 @@ def plans(L, ctx, statuses):
     # plan-free entry points
     rng = np.random.default_rng(5)
     for d in (1, 255, 256, 257, 4096, 70000, 262144, 300000):
-        for fam in (0, 1, 2, 4, 5):
+        for fam in (0, 1, 2, 4, 5, 6):
             for K in (0, 3, 8, 9):
                 params = rng.uniform(0.05, 0.5, NPARAMS[fam](d))
                 out = np.zeros(1)
@@ -268,7 +268,7 @@ def plans(L, ctx, statuses):
                                      L.sg_integrate_noalloc(ctx, ctypes.byref(pr), prec, ptr(params), ptr(out),
                                                             None, None)])
     for d, K in [(1, 0), (3, 4), (10, 3), (40, 5)]:
-        for fam in range(6):
+        for fam in range(7):
             params = rng.uniform(0.05, 0.5, NPARAMS[fam](d))
             out = np.zeros(1)
             bound = np.zeros(1)
@@ -292,7 +292,7 @@ def fail_malloc_scan(L):
     call: the status, the launches the call made and, after everything is
     destroyed, the allocations still alive."""
     probs, params = mixed_batch(0, True)
-    bprobs = [p for p in probs if p[3] != 5]
+    bprobs = [p for p in probs if p[3] not in (5, 6)]
     p1 = np.full(4096, 0.1)
     out = np.zeros(len(probs))
     rows = []
@@ -466,10 +466,11 @@ def main():
         orc["enumerate"] = [total, int(nnz.sum()), int(levels.sum())]
         rng = np.random.default_rng(3)
         vals = []
-        for fam in ("exp_sum", "oscillatory", "product_peak", "gaussian", "oscillatory_quadratic", "corner_peak"):
+        for fam in ("exp_sum", "oscillatory", "product_peak", "gaussian", "oscillatory_quadratic", "corner_peak",
+                    "oscillatory_quadratic_linear"):
             d = 4
             k = {"exp_sum": d, "oscillatory": d + 1, "product_peak": 2 * d, "gaussian": 2 * d,
-                 "oscillatory_quadratic": 2 * d + 1, "corner_peak": d}[fam]
+                 "oscillatory_quadratic": 2 * d + 1, "corner_peak": d, "oscillatory_quadratic_linear": 3 * d + 1}[fam]
             p = rng.uniform(0.1, 0.6, k)
             vals.append([fam, oracle.smolyak_points(4, 7, "cc", fam, p, nthreads=2)["q"]])
             if fam != "corner_peak":

@@ -304,3 +304,116 @@ def test_oscq_degenerate_and_large_coefficients(torch_dev, orc):
         vals, bnd = api.integrate(b, prec, with_bound=True)
         got, bnd = vals.cpu().numpy(), bnd.cpu().numpy()
         assert np.all(np.abs(got - ref) <= bnd), prec
+
+
+# ------------------------------------------ with a linear term in the phase
+FAML = "oscillatory_quadratic_linear"
+
+
+@pytest.mark.parametrize("precision", MODES)
+@pytest.mark.parametrize("seed", [3, 4])
+def test_oscql_small_random_vs_point_oracle(torch_dev, orc, seed, precision):
+    from paper_2210_14313_amd import workloads as W
+    b = W.random_small(900 + seed, 30, d_range=(1, 10), k_range=(0, 6), families=(FAML,), rules=W.ALL_RULES)
+    say("case oscql small", seed, precision)
+    for i, p in enumerate(b.problems):
+        r = orc.smolyak_points(p.d, p.q, p.rule, p.family, b.param_slice(i))
+        got, bnd = _one(p, b.param_slice(i), precision)
+        _check(got, bnd, r["q"], _mod(b.subset([i]), r["q"])[0], 8 * 2.0 ** -64 * (r["A"] + abs(r["fc"])),
+               precision)
+
+
+@pytest.mark.parametrize("d,K,rule,lin_only", [(1, 8, "gp", False), (3, 5, "cc", True), (64, 4, "tr", False),
+                                               (257, 6, "gl", False), (600, 3, "cc", True), (1000, 4, "gp", False)])
+@pytest.mark.parametrize("precision", MODES)
+def test_oscql_edges_vs_factorised_oracle(torch_dev, orc, d, K, rule, lin_only, precision):
+    # lin_only: every other coordinate purely linear (a = 0), the rest purely
+    # quadratic (c = 0), as in (4.2)
+    from paper_2210_14313_amd import workloads as W
+    rng = np.random.default_rng(d + 100 * K + 7)
+    prm = W.draw_params(rng, FAML, d)
+    if lin_only:
+        prm[1:1 + d:2] = 0.0
+        prm[1 + 2 * d + 1::2] = 0.0
+    b = W.single(d, d + K, rule, FAML, prm)
+    say("case oscql edge", d, K, rule, lin_only, precision)
+    ref = orc.batch_factorised(b)[0]
+    got, bnd = _one(b.problems[0], prm, precision)
+    _check(got, bnd, ref, _mod(b, ref)[0], precision=precision)
+
+
+def _test_2_sine_params():
+    # sin(2 pi + 10 x1^2 + 5 x2^2 + 5 x3) on [-1,1]^3: x = 2t - 1 gives
+    # 10 x1^2 = 40 (t1 - 1/2)^2, 5 x2^2 = 20 (t2 - 1/2)^2, 5 x3 = 10 t3 - 5,
+    # and sin(theta) = cos(theta - pi/2): w = 3/4 - 5 / (2 pi) (mod 1),
+    # a = (40, 20, 0), u = 1/2, c = (0, 0, 10); the mean over the unit cube
+    w = (0.75 - 5.0 / (2.0 * np.pi)) % 1.0
+    return np.array([w, 40.0, 20.0, 0.0, 0.5, 0.5, 0.5, 0.0, 0.0, 10.0])
+
+
+def test_oscql_paper_test_2_sine(torch_dev, orc):
+    import torch
+    from paper_2210_14313_amd import native, workloads as W
+    prm = _test_2_sine_params()
+    for K in range(0, 9):
+        b = W.single(3, 3 + K, "gp", FAML, prm)
+        say("case oscql test 2", K)
+        r = orc.smolyak_points(3, 3 + K, "gp", FAML, prm)
+        for prec in MODES:
+            got, bnd = _one(b.problems[0], prm, prec)
+            _check(got, bnd, r["q"], _mod(b, r["q"])[0], 8 * 2.0 ** -64 * (r["A"] + abs(r["fc"])), prec)
+        pv = native.integrate_points(b.problems[0], torch.as_tensor(prm).cuda()).item()
+        assert abs(pv - r["q"]) <= 1e-12 * _mod(b, r["q"])[0], (K, pv, r["q"])
+
+
+@pytest.mark.parametrize("precision", MODES)
+def test_oscql_in_mixed_plans_with_gradient(torch_dev, orc, precision):
+    # both complex families beside the real ones in one plan: values, the
+    # family count in the plan info, and the reverse sweep against the
+    # oracle's gradient (dw, da, du, dc)
+    import torch
+    from paper_2210_14313_amd import api, native, workloads as W
+    b = W.concat([W.random_small(990, 20, d_range=(1, 400), k_range=(0, 6), families=(FAML,), rules=W.ALL_RULES),
+                  W.random_small(991, 10, d_range=(1, 300), k_range=(0, 6), families=(FAM,)),
+                  W.random_small(992, 20, d_range=(1, 120), k_range=(0, 6))])
+    say("case oscql mixed plan", precision)
+    ref = orc.batch_factorised(b)
+    vals, bnd = api.integrate(b, precision, with_bound=True)
+    got, bnd = vals.cpu().numpy(), bnd.cpu().numpy()
+    assert np.all(np.abs(got - ref) <= bnd), np.max(np.abs(got - ref) / bnd)
+    fam = np.array([p.family for p in b.problems])
+    sel = (fam == FAML) | (fam == FAM)
+    err = np.max(np.abs(got[sel] - ref[sel]) / _mod(b, ref)[sel])
+    say("  max error / accuracy scale", err)
+    assert err <= TOL[precision]
+    assert native_info(b, precision)["fp64_complex"] == int(np.sum(sel))
+    params = api.params_tensor(b)
+    rng = np.random.default_rng(993)
+    gout = torch.tensor(rng.uniform(0.5, 2.0, len(b)), dtype=torch.float64, device="cuda")
+    plan = native.Plan(b.problems, precision)
+    try:
+        g = plan.execute_grad(params, gout).cpu().numpy()
+    finally:
+        plan.close()
+    gw = gout.cpu().numpy()
+    for i, p in enumerate(b.problems):
+        if p.family != FAML:
+            continue
+        gr = gw[i] * orc.smolyak_factorised_grad(p.d, p.q, p.rule, p.family, b.param_slice(i))
+        sl = slice(p.param_offset, p.param_offset + len(gr))
+        e = np.max(np.abs(g[sl] - gr)) / max(np.max(np.abs(gr)), 1e-300)
+        assert e <= 1e-12, (i, p.d, p.q, p.rule, e)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_oscql_block_variant(torch_dev, orc, precision):
+    from oracle import blocked as OB
+    from paper_2210_14313_amd import api, workloads as W
+    b = W.random_small(995, 12, d_range=(3, 40), k_range=(1, 5), families=(FAML,), rules=W.ALL_RULES)
+    say("case oscql blocked", precision)
+    ref = np.array([OB.smolyak_blocked(p.d, p.q, p.rule, p.family, b.param_slice(i), 5)
+                    for i, p in enumerate(b.problems)])
+    vals, bnd = api.integrate(b, precision, with_bound=True, block_dims=5)
+    got, bnd = vals.cpu().numpy(), bnd.cpu().numpy()
+    assert np.all(np.abs(got - ref) <= bnd), np.max(np.abs(got - ref) / bnd)
+    assert np.max(np.abs(got - ref) / _mod(b, ref)) <= TOL[precision]

@@ -461,7 +461,8 @@ def test_autotune_records_saved_and_loaded(api, orc, tmp_path):
     ctx2.close()
 
 
-@pytest.mark.parametrize("family", ["exp_sum", "oscillatory", "product_peak", "gaussian", "oscillatory_quadratic"])
+@pytest.mark.parametrize("family", ["exp_sum", "oscillatory", "product_peak", "gaussian", "oscillatory_quadratic",
+                                    "oscillatory_quadratic_linear"])
 def test_plan_free_path_split_over_workgroups(api, orc, family):
     """sg_integrate splits an integrand over ceil(d / 256) workgroups (at most
     1024) and joins their partials in a fixed order: FP64 against the

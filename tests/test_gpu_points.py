@@ -176,7 +176,7 @@ def test_corner_peak_rejected_by_the_sweep(torch_dev):
     assert e.value.status == 2
 
 
-@pytest.mark.parametrize("family", ["gaussian", "oscillatory_quadratic"])
+@pytest.mark.parametrize("family", ["gaussian", "oscillatory_quadratic", "oscillatory_quadratic_linear"])
 @pytest.mark.parametrize("d,K,rule", [(1, 8, "gp"), (2, 7, "cc"), (5, 5, "gl"), (9, 4, "gp"), (30, 3, "tr"),
                                       (64, 2, "gl_paper")])
 def test_points_quadratic_families_vs_point_oracle(torch_dev, orc, family, d, K, rule):

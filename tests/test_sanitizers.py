@@ -147,9 +147,10 @@ def test_oracle_under_sanitizers(run_result):
         assert wsum == pytest.approx(float(np.sum(oracle.rule(r, lv)[1])), rel=1e-15)
     rng = np.random.default_rng(3)
     vals = iter(orc["values"])
-    for fam in ("exp_sum", "oscillatory", "product_peak", "gaussian", "oscillatory_quadratic", "corner_peak"):
+    for fam in ("exp_sum", "oscillatory", "product_peak", "gaussian", "oscillatory_quadratic", "corner_peak",
+                "oscillatory_quadratic_linear"):
         k = {"exp_sum": 4, "oscillatory": 5, "product_peak": 8, "gaussian": 8, "oscillatory_quadratic": 9,
-             "corner_peak": 4}[fam]
+             "corner_peak": 4, "oscillatory_quadratic_linear": 13}[fam]
         p = rng.uniform(0.1, 0.6, k)
         assert next(vals)[1] == pytest.approx(oracle.smolyak_points(4, 7, "cc", fam, p, nthreads=2)["q"],
                                               rel=1e-15, abs=1e-300)
