@@ -376,7 +376,12 @@ __device__ void oscq_body(int d, int b, int G, bool lin, const double* __restric
     __syncthreads();
     oscq_store<K>(a, lds + i * OSCQ_WORDS);
     __syncthreads();
-    for (int s = 128; s >= 1; s >>= 1) {
+    // tree over the threads holding partials (threads at or above the next
+    // power of two of min(G, 256) hold the identity; skipping their levels
+    // changes no bit, merging with the identity being exact)
+    int top = 1;
+    while (top < G && top < 256) top <<= 1;
+    for (int s = top >> 1; s >= 1; s >>= 1) {
         if (i < s) {
             oscq_load<K>(a, lds + i * OSCQ_WORDS);
             oscq_load<K>(c, lds + (i + s) * OSCQ_WORDS);
