@@ -919,10 +919,54 @@ def main():
                         tp.append(time.perf_counter() - t0)
                         s.synchronize()
                     pinned = {"median_s": statistics.median(tp[1:]), "value": vp}
+                # device time of the plan's launch (events around 50 launches)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(s)
+                for _ in range(50):
+                    plan.execute(pr, o, stream=s)
+                e1.record(s)
+                torch.cuda.synchronize()
+                plan_kernel_us = e0.elapsed_time(e1) / 50 * 1e3
                 plan.close()
+                # the plan-free entry point (sg_integrate: the integrand split
+                # over ceil(d / 256) workgroups joined in a fixed order)
+                import ctypes
+                lib, ctx = native.lib(), native.default_context()
+                cp = native.SgProblem(p.d, p.q, native.RULES[p.rule], native.FAMILIES[p.family], 0)
+                with torch.cuda.stream(s):
+                    to = []
+                    for _ in range(31):
+                        t0 = time.perf_counter()
+                        native.integrate_one(p, pr, prec, out=o, stream=s)
+                        vo = o.item()
+                        to.append(time.perf_counter() - t0)
+                e0.record(s)
+                for _ in range(50):
+                    lib.sg_integrate(ctx.handle, ctypes.byref(cp), native.PRECISIONS[prec], ctypes.c_void_p(pr.data_ptr()),
+                                     ctypes.c_void_p(o.data_ptr()), None, ctypes.c_void_p(s.cuda_stream))
+                e1.record(s)
+                torch.cuda.synchronize()
+                pf = {"median_s": statistics.median(to[1:]), "kernel_us": e0.elapsed_time(e1) / 50 * 1e3,
+                      "value": vo, "pinned_result": None}
+                if dptr is not None:
+                    tp = []
+                    for _ in range(31):
+                        hv[0] = float("nan")
+                        t0 = time.perf_counter()
+                        lib.sg_integrate(ctx.handle, ctypes.byref(cp), native.PRECISIONS[prec],
+                                         ctypes.c_void_p(pr.data_ptr()), ctypes.c_void_p(dptr), None,
+                                         ctypes.c_void_p(s.cuda_stream))
+                        while hv[0] != hv[0] and time.perf_counter() - t0 < 0.1:
+                            pass
+                        vp1 = float(hv[0])
+                        tp.append(time.perf_counter() - t0)
+                        s.synchronize()
+                    pf["pinned_result"] = {"median_s": statistics.median(tp[1:]), "value": vp1}
                 ex = float(ref_hd[i])
+                pf["rel_err_vs_oracle"] = abs(vo - ex) / abs(ex)
                 tti[f"{p.rule}_{prec}"] = {"median_s": statistics.median(ts), "cold_s": cold, "value": v,
-                                           "rel_err_vs_oracle": abs(v - ex) / abs(ex), "pinned_result": pinned}
+                                           "rel_err_vs_oracle": abs(v - ex) / abs(ex), "pinned_result": pinned,
+                                           "kernel_us": plan_kernel_us, "plan_free": pf}
         extras["time_to_integral_d1000"] = tti
         # block (tensor-product) variant, Algorithm 3.3 with step m = 10
         log("block variant (m = 10) ...")

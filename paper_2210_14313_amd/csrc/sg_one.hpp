@@ -115,7 +115,12 @@ __device__ __forceinline__ void one_body(int d, int rule, int family, int G, con
     __syncthreads();   // the workgroup's wave slots are reused below
     acc_store<K>(a, lds + i * ACC_WORDS);
     __syncthreads();
-    for (int s = kOneTree / 2; s >= 1; s >>= 1) {
+    // tree over the threads holding partials (threads at or above the next
+    // power of two of min(G, kOneTree) hold the identity; skipping their
+    // levels changes no bit, merging with the identity being exact)
+    int top = 1;
+    while (top < G && top < kOneTree) top <<= 1;
+    for (int s = top >> 1; s >= 1; s >>= 1) {
         if (i < s) {
             acc_load<K>(a, lds + i * ACC_WORDS);
             acc_load<K>(b, lds + (i + s) * ACC_WORDS);
