@@ -201,7 +201,7 @@ def method_counts(problems):
     for p in problems:
         K = p.q - p.d
         nodes, supp = _rule_facts(p.rule, K)
-        cx = p.family in ("oscillatory", "oscillatory_quadratic")
+        cx = p.family in ("oscillatory", "oscillatory_quadratic", "oscillatory_quadratic_linear")
         nt += p.d * nodes * (2 if cx else 1)
         n32 += p.d * 2 * supp * (2 if cx else 1)
         n64 += p.d * (K + 1) * (K + 2) * (4 if cx else 1)
