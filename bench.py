@@ -736,6 +736,10 @@ def main():
                 "max_plain_rel_err": float(np.max(err[sel] / np.abs(ref[sel]))),
                 "max_stated_rel_bound": float(np.max(bnd[sel] / scale[sel])),
                 "max_bound_over_err": float(np.max(bnd[sel]) / max(float(np.max(err[sel])), 1e-300)),
+                # per integrand (those with a non-zero error): how far each
+                # stated bound is above its own error
+                "median_bound_over_err": float(np.median(bnd[sel][err[sel] > 0] / err[sel][err[sel] > 0]))
+                if np.any(err[sel] > 0) else None,
                 "integrands": int(np.sum(sel))}
         return res
 
