@@ -75,6 +75,21 @@ __device__ __forceinline__ void sincos_series(double h, double& sh, double& ch)
     ch = pc;
 }
 
+// The same on |h| <= 1/8 with k = 0..4 for sin and k = 0..5 for cos: the
+// first omitted terms, h^10/11! and h^12/12! relative, are below 2^-55.
+constexpr double kTrigTiny = 0.125;
+__device__ __forceinline__ void sincos_series_short(double h, double& sh, double& ch)
+{
+    const double u = -h * h;
+    double ps = inv_fact(9), pc = inv_fact(10);
+#pragma unroll
+    for (int k = 3; k >= 0; --k) ps = fma(ps, u, inv_fact(2 * k + 1));
+#pragma unroll
+    for (int k = 4; k >= 0; --k) pc = fma(pc, u, inv_fact(2 * k));
+    sh = h * ps;
+    ch = pc;
+}
+
 // double-double accumulation: (hi, lo) += v exactly up to lo's rounding
 __device__ __forceinline__ void dd_add(double& hi, double& lo, double v)
 {
@@ -150,6 +165,13 @@ __device__ __forceinline__ double centred_value(double base, double fc, double d
 {
     if constexpr (is_angle<FAM>()) {
         const double h = 0.5 * delta;
+        // the shorter series when every lane of the wave can take it (one
+        // path per wave, no divergence)
+        if (__all(fabs(h) <= kTrigTiny)) {
+            double sh, ch;
+            sincos_series_short(h, sh, ch);
+            return -2.0 * sh * fma(s0, ch, c0 * sh);
+        }
         if (fabs(h) <= kTrigSmall) {
             double sh, ch;
             sincos_series(h, sh, ch);
