@@ -886,20 +886,25 @@ __device__ __forceinline__ void acc_load(Acc& x, const double* s)
 }
 
 // Upper bound on every |[z^b] prod_{t in T} delta_t| (any subset T) summed
-// over b <= K: the product of the absolute-value polynomials has
-// non-negative coefficients, 1 + x <= exp(x) coefficient-wise, and a sum of
-// non-negative coefficients is at most the value at z = 1, so the bound is
-// exp(m) with m = sum_t sum_e |delta_t[e]| (m given as an upper bound).
-// Formed with the hardware base-2 exponential in FP32: e^m = 2^(m log2 e);
-// the product m log2 e is raised by 2^-20 relative (covering the rounding of
-// the constant, of the product and of m's conversion) plus 2^-20 absolute,
-// and the result by 2^-16 relative (covering the instruction's error of at
-// most a few units in the last place); beyond 2^126 the bound is +inf.
+// over b <= K.  With M(z) = sum_t sum_e |delta_t[e]| z^e the product of the
+// absolute-value polynomials is at most exp(M(z)) coefficient-wise
+// (1 + x <= exp(x) for non-negative coefficients); M(z)^j starts at degree
+// j and its coefficients sum to m^j (m = M(1)), so the sum over b <= K is at
+// most T_K(m) = sum_{j <= K} m^j / j!, far below exp(m) once m exceeds K.
+// Horner in FP32 over non-negative terms (a short chain at the end of every
+// wave): m is rounded up on its conversion (the product by 1 + 2^-22 covers
+// the conversion's and its own rounding, 2^-24 each), each of the K levels rounds the reciprocal 1/j,
+// the product and the FMA once (at most 3K units of 2^-24 relative in all),
+// covered by the factor 1 + 4 (K + 1) 2^-24; m is given as an upper bound;
+// an overflow gives +inf.
+template <int K>
 __device__ __forceinline__ double abs_product_bound(double m)
 {
-    const float v = (float)m * 1.44269504f * (1.0f + 9.5367431640625e-07f) + 9.5367431640625e-07f;
-    if (!(v < 126.0f)) return __builtin_huge_val();
-    return (double)__builtin_amdgcn_exp2f(v) * (1.0 + 1.52587890625e-05);
+    const float mf = (float)m * (1.0f + 2.384185791015625e-07f);
+    float r = 1.0f;
+#pragma unroll
+    for (int j = K; j >= 1; --j) r = fmaf(mf * (1.0f / (float)j), r, 1.0f);
+    return (double)r * (1.0 + (double)(4 * (K + 1)) * 5.9604644775390625e-08);
 }
 
 // ------------------------------------------------------------ read-out
@@ -918,7 +923,7 @@ __device__ void readout(const Acc& x, int d, int out_index, const double* __rest
     // at most 2 (d + depth) roundings) raised to upper bounds
     const double marg = bound_sum_margin(d + depth + 4);
     const double m_up = (double)x.m * marg, eps_up = (double)x.eps * marg, lsabs_up = (double)x.lsabs * marg;
-    const double sabs = want_bound ? abs_product_bound(m_up) : 0.0;
+    const double sabs = want_bound ? abs_product_bound<K>(m_up) : 0.0;
     const double u64 = 1.1102230246251565e-16;
     // rounding of the affine sum: d - 1 additions, plus up to 3 roundings
     // per term where a term is not exact (product-peak log D, gaussian c hv^2)

@@ -312,8 +312,11 @@ __device__ void oscq_readout(const OscqAcc& x, int d, int depth, const double* _
     if (bound) {
         const double u64 = 1.1102230246251565e-16;
         // coefficients of every partial product are bounded in sum by
-        // exp(sum_t sum_e |delta_t[e]|) (as for the real sweep)
-        const double sabs = exp(x.m) * (1.0 + 1e-13);
+        // T_K(m), m = sum_t sum_e (|Re delta_t[e]| + |Im delta_t[e]|) (as for
+        // the real sweep, moduli in place of absolute values); m's FP64 sum
+        // of non-negative terms, at most d + depth roundings, raised first
+        const double m_up = x.m * (1.0 + (double)(2 * (d + depth + 4)) * u64);
+        const double sabs = abs_product_bound<K>(m_up);
         // per pair term, relative to mag: FP64 values 12 roundings and one
         // FMA chain over the table's pairs; FP32 values 14 units of 2^-24
         // (pair_oscq32) plus, with compensated FP32 sums, one rounding of
