@@ -400,14 +400,16 @@ sg_status sg_integrate_points(sg_context *ctx, const sg_problem *problem, const 
 /* Plain, plan-free path: one integrand, one launch, no graph, no batching.
  * Same arguments as one problem of a plan (param_offset is ignored: params_dev
  * points at this integrand's parameters).  out_dev/bound_dev: one float64
- * each (bound may be NULL).  The launch splits the integrand's coordinates
- * over ceil(d / 256) workgroups (at most 1024) of 256 lanes, one coordinate
- * per lane and pass; each workgroup reduces its chunk to a partial truncated
- * product, and the last workgroup to finish joins the partials in a fixed
- * order (deterministic) and reads out the value and bound (the associative
- * product of Section 3, (3.9)-(3.11), split by chunks).  The partials use a
- * scratch buffer the context allocates on the first call with d > 256
- * (about 160 KiB, kept until the context is destroyed); calls on one
+ * each (bound may be NULL).  Up to d = 2048 (512 for the two
+ * OSCILLATORY_QUADRATIC families) one workgroup of 256 lanes sweeps every
+ * coordinate; larger integrands are split over ceil(d / 256) workgroups (at
+ * most 1024), one coordinate per lane and pass; each workgroup reduces its
+ * chunk to a partial truncated product, and the last workgroup to finish
+ * joins the partials in a fixed order (deterministic) and reads out the
+ * value and bound (the associative product of Section 3, (3.9)-(3.11), split
+ * by chunks).  The partials use a scratch buffer the context allocates on
+ * the first split call (about 160 KiB, kept until the context is
+ * destroyed); calls on one
  * context must not overlap in time.  Also takes OSCILLATORY_QUADRATIC(_LINEAR) in
  * every precision mode: the sweep of Section 3 with the complex surpluses of
  * e^{i a (x - u)^2} (FP32 node values in the FP32 modes, FP64 complex

@@ -1637,7 +1637,7 @@ sg_status sg_integrate(sg_context* ctx, const sg_problem* problem, int32_t preci
     sg_status st = check_one(ctx, problem, precision, params_dev, out_dev);
     if (st != SG_OK) return st;
     const int d = problem->d, K = problem->q - problem->d;
-    const int G = one_workgroups(d);
+    const int G = one_workgroups(d, family_complex(problem->family));
     if (G > 1 && !ctx->one_ws) {
         // the split launches' scratch: allocated once per context, counter
         // zeroed once; every launch leaves it at zero

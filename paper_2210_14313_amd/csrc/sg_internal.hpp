@@ -183,12 +183,20 @@ constexpr int kOneWords = kMaxK + 4;
 constexpr int kOneMaxG = 1024;   // workgroups of one split launch at most
 int launch_one(int precision, int d, int K, int rule, int family, int G, const double* params, double* out,
                double* bound, double* scratch, void* stream);
-// Workgroups for an integrand of d coordinates: one coordinate per lane
-// (256 per workgroup), at most kOneMaxG.
-inline int one_workgroups(int d)
+// Workgroups for an integrand of d coordinates.  One workgroup, its threads
+// holding several coordinates each, up to kOneSingle coordinates (the
+// sweep's families) or kOneSingleComplex (the complex sweep, whose
+// coordinates cost more): below those sizes the longer chains cost less
+// than the cross-workgroup join (measured: d = 1000 in 3.8-4.5 us on one
+// workgroup against 5.6-6.0 us on four).  Above them one coordinate per
+// lane (256 per workgroup), at most kOneMaxG workgroups.
+constexpr int kOneSingle = 2048;
+constexpr int kOneSingleComplex = 512;
+inline int one_workgroups(int d, bool complex_sweep)
 {
+    if (d <= (complex_sweep ? kOneSingleComplex : kOneSingle)) return 1;
     const int g = (d + 255) / 256;
-    return g < 1 ? 1 : g > kOneMaxG ? kOneMaxG : g;
+    return g > kOneMaxG ? kOneMaxG : g;
 }
 
 // Allocation-free path (sg_noalloc.hip): the current device's fixed scratch

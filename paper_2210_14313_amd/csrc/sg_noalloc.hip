@@ -60,8 +60,8 @@ int noalloc_scratch(double** ptr)
 int noalloc_launch(double* ptr, int precision, int d, int K, int rule, int family, const double* params,
                    double* out, double* bound, void* stream)
 {
-    const int G = one_workgroups(d);
     const bool oscq = family == SG_FAMILY_OSCILLATORY_QUADRATIC || family == SG_FAMILY_OSCILLATORY_QUADRATIC_LINEAR;
+    const int G = one_workgroups(d, oscq);
     const long need = (long)kOneHead + (long)G * (oscq ? kOscqWords : kOneWords);
     if (need > (long)kNoAllocWords) return -1;
     if (oscq)

@@ -490,21 +490,27 @@ def test_autotune_records_saved_and_loaded(api, orc, tmp_path):
 @pytest.mark.parametrize("family", ["exp_sum", "oscillatory", "product_peak", "gaussian", "oscillatory_quadratic",
                                     "oscillatory_quadratic_linear"])
 def test_plan_free_path_split_over_workgroups(api, orc, family):
-    """sg_integrate splits an integrand over ceil(d / 256) workgroups (at most
-    1024) and joins their partials in a fixed order: FP64 against the
-    oracle at sizes around the split boundaries and beyond the cap, the
-    same value on repeated calls, and graph replays of the split launch
-    (the arrival counter must come back to zero after every launch)."""
+    """sg_integrate sweeps an integrand on one workgroup up to d = 2048 (512
+    for the complex sweep) and above splits it over ceil(d / 256) workgroups
+    (at most 1024), joining their partials in a fixed order: FP64 against
+    the oracle at sizes around the workgroup and split boundaries and beyond
+    the cap, the same value on repeated calls, and graph replays of the
+    split launch (the arrival counter must come back to zero after every
+    launch)."""
     import torch
     from paper_2210_14313_amd import native, workloads as W
     rng = np.random.default_rng(31 + len(family))
-    sizes = [(1, 4, "gl"), (255, 3, "cc"), (256, 2, "gp"), (257, 5, "gl"), (1000, 3, "tr")]
-    if family != "product_peak":     # its value leaves the double range at large d
+    sizes = [(1, 4, "gl"), (255, 3, "cc"), (256, 2, "gp"), (257, 5, "gl"), (512, 2, "cc"), (513, 3, "gl"),
+             (1000, 3, "tr"), (2048, 2, "gl"), (2049, 2, "cc")]
+    if family != "product_peak":
         sizes += [(5000, 2, "cc"), (300000, 1, "cc")]
     for d, K, rule in sizes:
         prm = W.draw_params(rng, family, d)
         if family in ("exp_sum", "gaussian"):
             prm = prm * min(1.0, 30.0 / d)
+        if family == "product_peak" and d > 1000:
+            # factors 1 / (1 + (x - u)^2) near 1 keep the product in range
+            prm = np.concatenate([np.ones(d), rng.uniform(0.4, 0.6, d)])
         b = W.single(d, d + K, rule, family, prm)
         p = b.problems[0]
         pr = torch.as_tensor(prm, dtype=torch.float64).cuda()
@@ -520,10 +526,12 @@ def test_plan_free_path_split_over_workgroups(api, orc, family):
         assert abs(v1 - ref) <= b1, (d, v1, ref, b1)
         assert abs(v1 - ref) <= 1e-12 * scale, (d, v1, ref)
     # graph replays of a split launch on a non-default stream
-    d = 3000 if family != "product_peak" else 900
+    d = 3000
     prm = W.draw_params(rng, family, d)
     if family in ("exp_sum", "gaussian"):
         prm = prm / d
+    if family == "product_peak":
+        prm = np.concatenate([np.ones(d), rng.uniform(0.4, 0.6, d)])
     p = W.single(d, d + 3, "cc", family, prm).problems[0]
     pr = torch.as_tensor(prm, dtype=torch.float64).cuda()
     eager = torch.empty(1, dtype=torch.float64, device="cuda")
