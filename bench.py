@@ -671,7 +671,7 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(a batch of independent integrands would be split across GPUs by cost, "
               "with no communication); run with --gpus 1", file=sys.stderr)
         sys.exit(2)

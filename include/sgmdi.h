@@ -52,7 +52,7 @@ extern "C" {
 typedef enum {
     SG_OK = 0,
     SG_ERR_INVALID_ARGUMENT = 1, /* bad d, q, rule, family, size or NULL pointer */
-    SG_ERR_UNSUPPORTED = 2,      /* valid but beyond this build (e.g. K > SG_MAX_K) */
+    SG_ERR_UNSUPPORTED = 2,      /* valid but beyond what the library supports (e.g. K > SG_MAX_K) */
     SG_ERR_OVERFLOW = 3,         /* an exact count does not fit in 64 bits */
     SG_ERR_OUT_OF_MEMORY = 4,    /* host or device allocation failed */
     SG_ERR_DEVICE = 5,           /* a HIP call failed; see sg_last_error */

@@ -93,7 +93,7 @@ def test_host_results_match_product_library(run_result):
 
 
 def test_plan_paths_statuses(run_result):
-    """Every plan and plan-free call of the driver returns what the header
+    """Every plan and plan-free call of the sanitized host run returns what the header
     documents, and nothing is left allocated."""
     st = run_result["statuses"]
     assert ["context", OK] in st and ["context_null", INVALID] in st
