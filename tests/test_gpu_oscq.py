@@ -417,3 +417,24 @@ def test_oscql_block_variant(torch_dev, orc, precision):
     got, bnd = vals.cpu().numpy(), bnd.cpu().numpy()
     assert np.all(np.abs(got - ref) <= bnd), np.max(np.abs(got - ref) / bnd)
     assert np.max(np.abs(got - ref) / _mod(b, ref)) <= TOL[precision]
+
+
+def test_box_map_paper_domains_on_the_gpu(torch_dev, orc):
+    """api.integrate_one with box=(-1, 1): (4.2)'s sine on [-1,1]^3 (eight
+    times the unit-cube value of the mapped integrand, against the oracle),
+    and (4.1)'s exp(5 x1^2 + 5 x2^2) on [-1,1]^2 (four times the unit-cube
+    gaussian c = 20, u = 1/2, bitwise)."""
+    import torch
+    from paper_2210_14313_amd import api, native, workloads as W
+    p = np.array([0.75, 10.0, 5.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 5.0])   # sin(theta) = cos(theta - pi/2)
+    for K in (2, 5, 8):
+        v, bnd = api.integrate_one(FAML, p, 3, 3 + K, "gp", box=(-1.0, 1.0), with_bound=True)
+        up = _test_2_sine_params()
+        ref = 8.0 * orc.smolyak_factorised(3, 3 + K, "gp", FAML, up)
+        scale = 8.0 * _mod(W.single(3, 3 + K, "gp", FAML, up), ref / 8.0)[0]
+        assert abs(v - ref) <= 1e-12 * scale, (K, v, ref)
+        assert abs(v - ref) <= bnd + 1e-14 * scale
+    g = api.integrate_one("gaussian", [5.0, 5.0, 0.0, 0.0], 2, 7, "gp", box=(-1.0, 1.0))
+    b = W.single(2, 7, "gp", "gaussian", np.array([20.0, 20.0, 0.5, 0.5]))
+    u = native.integrate_one(b.problems[0], torch.as_tensor(b.params).cuda()).item()
+    assert g == 4.0 * u
