@@ -108,7 +108,7 @@ struct sg_plan {
     FwdWG* d_fwd = nullptr;         // forward workgroup descriptors
     int nfwg = 0;
     size_t fwd_capacity = 0;
-    unsigned int* d_queue = nullptr; // persistent kernel: next-descriptor and exit counters
+    unsigned int* d_queue = nullptr; // persistent kernel: next-descriptor counter (and a spare word)
     int qgrid = 0;                  // persistent kernel: workgroups launched
     bool use_graph = false;         // replay a captured graph (else direct launch)
     bool params_disjoint = true;    // problems' parameter ranges do not overlap

@@ -1298,12 +1298,17 @@ __device__ __forceinline__ void run_workgroup(const FwdWG* wg, const double* __r
 }
 
 // Forward kernel.  queue == nullptr: hardware dispatch, workgroup b runs
-// descriptor b.  Otherwise the persistent form: a grid sized to the
-// resident capacity pops descriptors (longest first) from a work queue,
-// queue[0] being the next index; every workgroup leaves once the queue is
-// exhausted, and the last one to leave (counted in queue[1]) resets both
-// counters, so the next launch on the stream starts from zero without a
-// memset (graph-safe).  Launches of one queue must not overlap.
+// descriptor b.  Otherwise the persistent form: a grid of G workgroups
+// sized to the resident capacity; workgroup b runs descriptor b first (no
+// atomic: every workgroup asking the one counter at once serialises
+// hundreds of atomics), then pops further descriptors (longest first) from
+// the work queue, G + queue[0] being the next index, and leaves at its first
+// index past the end.  A launch makes exactly nwg - G + G = nwg pops
+// (numbered 0 .. nwg - 1 by the counter), so the pop numbered nwg - 1 is
+// the last of all: no workgroup pops again, and that workgroup returns the
+// counter to zero for the next launch on the stream, without a memset or
+// an exit count (graph-safe).  With G >= nwg nothing is popped.  Launches
+// of one queue must not overlap.
 // GAUSS: the instantiation for plans that hold gaussian problems (it runs
 // every family; kept apart so that the gaussian code does not weigh on the
 // other plans' kernels).
@@ -1317,22 +1322,17 @@ k_forward(const FwdWG* __restrict__ wgs, int nwg, unsigned int* __restrict__ que
     __shared__ int next;
     int idx = blockIdx.x;
     for (;;) {
-        if (queue) {
-            if (threadIdx.x == 0) next = (int)atomicAdd(&queue[0], 1u);
-            __syncthreads();
-            idx = __builtin_amdgcn_readfirstlane(next);
-            __syncthreads();   // every thread has read `next` before it is overwritten
-        }
         if (idx >= nwg) break;
         run_workgroup<PREC, KMAXP, GAUSS>(wgs + idx, pool64, pool32, params, out, bound, lds);
-        if (!queue) break;
-    }
-    if (queue && threadIdx.x == 0) {
-        __threadfence();
-        if (atomicAdd(&queue[1], 1u) == gridDim.x - 1) {
-            atomicExch(&queue[0], 0u);
-            atomicExch(&queue[1], 0u);
+        if (!queue || (int)gridDim.x >= nwg) break;   // no descriptor beyond the static ones
+        if (threadIdx.x == 0) {
+            const unsigned int k = atomicAdd(&queue[0], 1u);
+            if (k == (unsigned int)(nwg - 1)) atomicExch(&queue[0], 0u);   // the last pop of the launch
+            next = (int)gridDim.x + (int)k;
         }
+        __syncthreads();
+        idx = __builtin_amdgcn_readfirstlane(next);
+        __syncthreads();   // every thread has read `next` before it is overwritten
     }
 }
 

@@ -399,6 +399,40 @@ def test_persistent_queue_in_graph_replays(api, orc):
         plan.close()
 
 
+def test_persistent_queue_pops_and_resets(api, orc):
+    """The persistent kernel with more descriptors than resident workgroups
+    (one coordinate per lane on the 4096 batch): workgroups pop descriptors
+    from the queue, and the last pop of a launch returns the counter to zero,
+    so back-to-back launches and graph replays each run every descriptor;
+    bitwise equal to the hardware-dispatch launch of the same descriptors."""
+    import torch
+    from paper_2210_14313_amd import native, workloads as W
+    b = W.batched_uneven()
+    params = api.params_tensor(b)
+    say("case persistent queue pops")
+    direct = native.Plan(b.problems, "fp64")
+    direct.set_schedule(1, 4)
+    nfwg = direct.info()["grid_blocks"]
+    want = direct.execute(params).clone()
+    direct.close()
+    ref = _fact_ref(orc, b)
+    assert np.max(np.abs(want.cpu().numpy() - ref) / _scale(b, ref)) <= 1e-12
+    for graph in (False, True):
+        plan = native.Plan(b.problems, "fp64")
+        plan.set_schedule(1, 4, persistent=True, graph=graph)
+        assert plan.info()["grid_blocks"] < nfwg           # the queue is popped
+        s = torch.cuda.Stream()
+        out = torch.empty(len(b), dtype=torch.float64, device="cuda")
+        for rep in range(4):
+            out.fill_(float("nan"))
+            s.wait_stream(torch.cuda.current_stream())
+            plan.execute(params, out, stream=s)
+            plan.execute(params, out, stream=s)            # back to back on the stream
+            s.synchronize()
+            assert torch.equal(out, want), (graph, rep)
+        plan.close()
+
+
 def test_balanced_schedule(api, orc):
     """The balanced schedule (equal-cost waves, workgroups placed for equal
     per-CU load) on mixed batches: every result against the oracle and
