@@ -1300,9 +1300,10 @@ sg_status sg_plan_create_blocked(sg_context* ctx, const sg_problem* problems, in
         if (st != SG_OK) return st;
     }
     // block sub-problems in integrand order, blocks in coordinate order
-    // (oscillatory and oscillatory quadratic: real part, then imaginary
-    // part); their parameters are
-    // laid out contiguously in the plan's block array
+    // (oscillatory quadratic families: real part, then imaginary part;
+    // oscillatory: one sub-problem per block, its phase cancelled, rotated
+    // back by the combine); their parameters are laid out contiguously in
+    // the plan's block array
     std::vector<sg_problem> sub;
     std::vector<BlockSub> gs;
     std::vector<BlockProb> bp(n);
@@ -1312,21 +1313,28 @@ sg_status sg_plan_create_blocked(sg_context* ctx, const sg_problem* problems, in
         const sg_problem& P = problems[i];
         const int K = P.q - P.d;
         const int nb = (P.d + block_dims - 1) / block_dims;
-        const bool osc = P.family == SG_FAMILY_OSCILLATORY || family_complex(P.family);
-        if (sub.size() + (size_t)nb * (osc ? 2 : 1) > (size_t)INT32_MAX)
+        // parts per block: two sweeps for the complex-sweep families (their
+        // block sums are complex), one phase-cancelled sweep for the linear
+        // oscillatory family (its sum is real, the phase a rotation)
+        const bool two_parts = family_complex(P.family);
+        const int part_lo = two_parts ? 1 : P.family == SG_FAMILY_OSCILLATORY ? 3 : 0;
+        const int part_hi = two_parts ? 2 : part_lo;
+        if (sub.size() + (size_t)nb * (two_parts ? 2 : 1) > (size_t)INT32_MAX)
             return fail(ctx, SG_ERR_UNSUPPORTED, "too many blocks");
         bp[i].param_offset = P.param_offset;
         bp[i].first_sub = (int32_t)sub.size();
         bp[i].nblocks = nb;
         bp[i].family = P.family;
         bp[i].out_index = i;
+        bp[i].d = P.d;
+        bp[i].block_dims = block_dims;
         uint64_t pts = 1;
         for (int b = 0; b < nb; ++b) {
             const int start = b * block_dims, len = std::min(block_dims, P.d - start);
             uint64_t nrep = 0;
             sg_status st = counts(len, len + K, P.rule, nullptr, &nrep, nullptr);
             pts = sat_mul(pts, st == SG_OK ? nrep : UINT64_MAX);
-            for (int part = osc ? 1 : 0; part <= (osc ? 2 : 0); ++part) {
+            for (int part = part_lo; part <= part_hi; ++part) {
                 BlockSub g{};
                 g.src_off = P.param_offset;
                 g.dst_off = off;

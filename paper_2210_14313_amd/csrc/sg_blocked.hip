@@ -7,9 +7,14 @@
 // value is the product of the block values, each block being an ordinary
 // batched problem of the forward sweep:
 //   exp-sum, product-peak, gaussian: Q = prod_b Q_b;
-//   oscillatory and oscillatory quadratic: Q = Re(e^{2 pi i w} prod_b
+//   oscillatory quadratic families: Q = Re(e^{2 pi i w} prod_b
 //   (R_b + i I_b)), with R_b the block's value at w = 0 and I_b the one at
-//   w = -1/4 (cos(theta - pi/2) = sin theta).
+//   w = -1/4 (cos(theta - pi/2) = sin theta);
+//   oscillatory: the sweep's sum S_b of a block is real and the block's
+//   complex value is e^{i theta_b} S_b, theta_b = sum of a_t / 2 over the
+//   block (the centre phase), so one sweep per block at w = -theta_b / 2 pi
+//   (phase cancelled: it returns S_b) and the combine rotates it by
+//   e^{i theta_b}; Q = Re(e^{2 pi i w} prod_b e^{i theta_b} S_b).
 // Two kernels surround the forward launch over the blocks: a gather that
 // lays out the blocks' parameters, and a combine that forms the products in
 // a fixed order and propagates the blocks' error bounds.
@@ -39,7 +44,12 @@ __global__ void __launch_bounds__(256) k_block_gather(const BlockSub* __restrict
     const double* src = params + b.src_off;
     double* dst = sub_params + b.dst_off;
     if (b.family == SG_FAMILY_OSCILLATORY) {
-        if (j0 == 0) dst[0] = b.part == 2 ? -0.25 : 0.0;
+        if (j0 == 0) {
+            // w cancelling the block's centre phase theta_b = sum a_t / 2
+            double th = 0.0;
+            for (int j = 0; j < b.len; ++j) th += src[1 + b.start + j];
+            dst[0] = -0.5 * th / (2.0 * 3.141592653589793);
+        }
         for (int j = j0; j < b.len; j += kGatherLanes) dst[1 + j] = src[1 + b.start + j];
     } else if (b.family == SG_FAMILY_OSCILLATORY_QUADRATIC) {
         if (j0 == 0) dst[0] = b.part == 2 ? -0.25 : 0.0;
@@ -119,7 +129,8 @@ __global__ void __launch_bounds__(256) k_block_combine(const BlockProb* __restri
     const int lane = threadIdx.x & 63;
     if (i >= n) return;
     const BlockProb p = probs[i];
-    const bool osc = p.family == SG_FAMILY_OSCILLATORY || p.family == SG_FAMILY_OSCILLATORY_QUADRATIC ||
+    const bool osc_lin = p.family == SG_FAMILY_OSCILLATORY;
+    const bool osc = osc_lin || p.family == SG_FAMILY_OSCILLATORY_QUADRATIC ||
                      p.family == SG_FAMILY_OSCILLATORY_QUADRATIC_LINEAR;
     const double u = 1.1102230246251565e-16;
     Part acc{1.0, 0.0, 1.0, 0.0};
@@ -127,7 +138,34 @@ __global__ void __launch_bounds__(256) k_block_combine(const BlockProb* __restri
         const int b = base + lane;
         Part x{1.0, 0.0, 1.0, 0.0};
         if (b < p.nblocks) {
-            if (osc) {
+            if (osc_lin) {
+                // v_b = e^{i theta_c} q with q the phase-cancelled sweep's value.
+                // Against the exact block value e^{i theta} S_b: theta_c's
+                // rounding (len additions, <= (len + 2) u A, A = sum |a_t| / 2),
+                // sincos and the two products (<= 8 u |q|), q's own bound e_b
+                // (relative to cos(delta) S_b, delta = 2 pi w_b + theta the phase
+                // the cancellation leaves, |delta| <= dmax), and
+                // |S_b| (1 - cos delta) <= dmax^2 (|q| + e_b).
+                const int s = p.first_sub + b;
+                const int start = b * p.block_dims, len = min(p.block_dims, p.d - start);
+                const double* a = params + p.param_offset + 1 + start;
+                double th = 0.0, ab = 0.0;
+                for (int j = 0; j < len; ++j) {
+                    th += a[j];
+                    ab += fabs(a[j]);
+                }
+                th *= 0.5;
+                ab *= 0.5;
+                double sn, cs;
+                sincos(th, &sn, &cs);
+                const double q = sub_out[s], e = sub_bound[s];
+                x.re = cs * q;
+                x.im = sn * q;
+                x.P = fabs(q) * (1.0 + 4.0 * u);
+                const double dth = (double)(len + 2) * u * (ab + 1.0);
+                const double dmax = 2.0 * (double)(len + 8) * u * (ab + 1.0);
+                x.D = e * (1.0 + 4.0 * u) + fabs(q) * (dth + 8.0 * u) + dmax * dmax * (fabs(q) + e);
+            } else if (osc) {
                 const int s = p.first_sub + 2 * b;
                 x.re = sub_out[s];
                 x.im = sub_out[s + 1];

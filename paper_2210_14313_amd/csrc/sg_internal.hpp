@@ -241,15 +241,19 @@ struct BlockSub {
     int32_t len;       // coordinates in the block
     int32_t d;         // integrand's dimension (product-peak: offset of u)
     int32_t family;
-    int32_t part;      // oscillatory: 1 = real part (w = 0), 2 = imaginary part (w = -1/4)
+    int32_t part;      // 0: plain copy; oscillatory quadratic families: 1 = real part (w = 0),
+                       // 2 = imaginary part (w = -1/4); oscillatory: 3 = the block's phase
+                       // cancelled (w = -theta_b / 2 pi, theta_b = sum of a_t / 2 over the block)
     int32_t pad;
 };
 struct BlockProb {
     int64_t param_offset;   // integrand's parameter offset (oscillatory: w)
-    int32_t first_sub;      // its first block sub-problem (oscillatory: two per block)
+    int32_t first_sub;      // its first block sub-problem (oscillatory quadratic: two per block)
     int32_t nblocks;
     int32_t family;
     int32_t out_index;
+    int32_t d;              // integrand's dimension
+    int32_t block_dims;     // coordinates per block (the last block may hold fewer)
 };
 int launch_block_gather(const BlockSub* subs, int nsub, const double* params, double* sub_params, void* stream);
 int launch_block_combine(const BlockProb* probs, int n, const double* sub_out, const double* sub_bound,
