@@ -87,6 +87,7 @@ struct BlockedPart {
     double* d_params = nullptr;      // block parameters (device)
     double* d_out = nullptr;         // block values (device)
     double* d_bound = nullptr;       // block bounds (device)
+    double* d_phase = nullptr;       // per sub-problem: oscillatory blocks' theta_b, sum |a_t| / 2 (device)
 };
 
 struct sg_plan {
@@ -1278,11 +1279,11 @@ static sg_status blocked_execute(sg_plan* p, const double* params_dev, double* o
 {
     BlockedPart& B = *p->blocked;
     return graph_or_direct(p, params_dev, out_dev, bound_dev, stream, [&](void* st) {
-        int rc = launch_block_gather(B.d_subs, B.nsub, params_dev, B.d_params, st);
+        int rc = launch_block_gather(B.d_subs, B.nsub, params_dev, B.d_params, B.d_phase, st);
         if (rc != 0) return hip_fail(p->ctx, (hipError_t)rc, "block gather launch");
         sg_status s2 = plan_launch(B.inner, B.d_params, B.d_out, B.d_bound, st);
         if (s2 != SG_OK) return s2;
-        rc = launch_block_combine(B.d_bprobs, p->n, B.d_out, B.d_bound, params_dev, out_dev, bound_dev, st);
+        rc = launch_block_combine(B.d_bprobs, p->n, B.d_out, B.d_bound, B.d_phase, params_dev, out_dev, bound_dev, st);
         if (rc != 0) return hip_fail(p->ctx, (hipError_t)rc, "block combine launch");
         return SG_OK;
     });
@@ -1382,6 +1383,7 @@ sg_status sg_plan_create_blocked(sg_context* ctx, const sg_problem* problems, in
     hipError_t e = hipMalloc((void**)&B.d_params, std::max<int64_t>(1, off) * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&B.d_out, (size_t)B.nsub * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&B.d_bound, (size_t)B.nsub * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&B.d_phase, 2 * (size_t)B.nsub * sizeof(double));
     if (e != hipSuccess) {
         sg_plan_destroy(p.release());
         return fail(ctx, SG_ERR_OUT_OF_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(e));
@@ -1449,7 +1451,7 @@ sg_status sg_plan_autotune(sg_plan* p, const double* params_dev, double* out_dev
     if (!p || !params_dev || !out_dev) return SG_ERR_INVALID_ARGUMENT;
     if (p->blocked) {
         BlockedPart& B = *p->blocked;
-        const int rc = launch_block_gather(B.d_subs, B.nsub, params_dev, B.d_params, stream);
+        const int rc = launch_block_gather(B.d_subs, B.nsub, params_dev, B.d_params, B.d_phase, stream);
         if (rc != 0) return hip_fail(p->ctx, (hipError_t)rc, "block gather launch");
         sg_status st = sg_plan_autotune(B.inner, B.d_params, B.d_out, stream);
         blocked_sync_info(p, false);
@@ -1613,6 +1615,7 @@ static void plan_free(sg_plan* p)
         (void)hipFree(B->d_params);
         (void)hipFree(B->d_out);
         (void)hipFree(B->d_bound);
+        (void)hipFree(B->d_phase);
         delete B;
         p->blocked = nullptr;
     }

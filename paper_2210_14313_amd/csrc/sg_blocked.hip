@@ -34,7 +34,8 @@ constexpr int kGatherLanes = 16;
 
 __global__ void __launch_bounds__(256) k_block_gather(const BlockSub* __restrict__ subs, int nsub,
                                                       const double* __restrict__ params,
-                                                      double* __restrict__ sub_params)
+                                                      double* __restrict__ sub_params,
+                                                      double* __restrict__ phase)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t s = g / kGatherLanes;
@@ -44,13 +45,27 @@ __global__ void __launch_bounds__(256) k_block_gather(const BlockSub* __restrict
     const double* src = params + b.src_off;
     double* dst = sub_params + b.dst_off;
     if (b.family == SG_FAMILY_OSCILLATORY) {
-        if (j0 == 0) {
-            // w cancelling the block's centre phase theta_b = sum a_t / 2
-            double th = 0.0;
-            for (int j = 0; j < b.len; ++j) th += src[1 + b.start + j];
-            dst[0] = -0.5 * th / (2.0 * 3.141592653589793);
+        double th = 0.0, ab = 0.0;
+        for (int j = j0; j < b.len; j += kGatherLanes) {
+            const double a = src[1 + b.start + j];
+            dst[1 + j] = a;
+            th += a;
+            ab += fabs(a);
         }
-        for (int j = j0; j < b.len; j += kGatherLanes) dst[1 + j] = src[1 + b.start + j];
+        // the block's centre phase theta_b = sum a_t / 2 and sum |a_t| / 2 by
+        // a fixed tree over the block's lanes (a group of kGatherLanes lanes
+        // shares one sub-problem, so the whole group takes this branch); the
+        // sweep runs at the w cancelling theta_b, the combine rotates by it
+        for (int o = kGatherLanes / 2; o >= 1; o >>= 1) {
+            th += __shfl_xor(th, o, kGatherLanes);
+            ab += __shfl_xor(ab, o, kGatherLanes);
+        }
+        if (j0 == 0) {
+            th *= 0.5;
+            dst[0] = -th / (2.0 * 3.141592653589793);
+            phase[2 * s] = th;
+            phase[2 * s + 1] = 0.5 * ab;
+        }
     } else if (b.family == SG_FAMILY_OSCILLATORY_QUADRATIC) {
         if (j0 == 0) dst[0] = b.part == 2 ? -0.25 : 0.0;
         for (int j = j0; j < b.len; j += kGatherLanes) {
@@ -122,6 +137,7 @@ __device__ __forceinline__ Part shfl_part(const Part& x, int off)
 __global__ void __launch_bounds__(256) k_block_combine(const BlockProb* __restrict__ probs, int n,
                                                        const double* __restrict__ sub_out,
                                                        const double* __restrict__ sub_bound,
+                                                       const double* __restrict__ phase,
                                                        const double* __restrict__ params,
                                                        double* __restrict__ out, double* __restrict__ bound)
 {
@@ -139,23 +155,17 @@ __global__ void __launch_bounds__(256) k_block_combine(const BlockProb* __restri
         Part x{1.0, 0.0, 1.0, 0.0};
         if (b < p.nblocks) {
             if (osc_lin) {
-                // v_b = e^{i theta_c} q with q the phase-cancelled sweep's value.
-                // Against the exact block value e^{i theta} S_b: theta_c's
-                // rounding (len additions, <= (len + 2) u A, A = sum |a_t| / 2),
-                // sincos and the two products (<= 8 u |q|), q's own bound e_b
-                // (relative to cos(delta) S_b, delta = 2 pi w_b + theta the phase
-                // the cancellation leaves, |delta| <= dmax), and
+                // v_b = e^{i theta_c} q with q the phase-cancelled sweep's value
+                // and theta_c the gather's sum.  Against the exact block value
+                // e^{i theta} S_b: theta_c's rounding (a summation tree of len
+                // terms, <= (len + 2) u A, A = sum |a_t| / 2), sincos and the two
+                // products (<= 8 u |q|), q's own bound e_b (relative to
+                // cos(delta) S_b, delta = 2 pi w_b + theta the phase the
+                // cancellation leaves, |delta| <= dmax), and
                 // |S_b| (1 - cos delta) <= dmax^2 (|q| + e_b).
                 const int s = p.first_sub + b;
                 const int start = b * p.block_dims, len = min(p.block_dims, p.d - start);
-                const double* a = params + p.param_offset + 1 + start;
-                double th = 0.0, ab = 0.0;
-                for (int j = 0; j < len; ++j) {
-                    th += a[j];
-                    ab += fabs(a[j]);
-                }
-                th *= 0.5;
-                ab *= 0.5;
+                const double th = phase[2 * s], ab = phase[2 * s + 1];
                 double sn, cs;
                 sincos(th, &sn, &cs);
                 const double q = sub_out[s], e = sub_bound[s];
@@ -203,21 +213,22 @@ __global__ void __launch_bounds__(256) k_block_combine(const BlockProb* __restri
 
 }  // namespace blk
 
-int launch_block_gather(const BlockSub* subs, int nsub, const double* params, double* sub_params, void* stream)
+int launch_block_gather(const BlockSub* subs, int nsub, const double* params, double* sub_params, double* phase,
+                        void* stream)
 {
     if (nsub <= 0) return 0;
     const int64_t threads = (int64_t)nsub * blk::kGatherLanes;
     hipLaunchKernelGGL(blk::k_block_gather, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
-                       (hipStream_t)stream, subs, nsub, params, sub_params);
+                       (hipStream_t)stream, subs, nsub, params, sub_params, phase);
     return (int)hipGetLastError();
 }
 
 int launch_block_combine(const BlockProb* probs, int n, const double* sub_out, const double* sub_bound,
-                         const double* params, double* out, double* bound, void* stream)
+                         const double* phase, const double* params, double* out, double* bound, void* stream)
 {
     if (n <= 0) return 0;
     hipLaunchKernelGGL(blk::k_block_combine, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, (hipStream_t)stream, probs, n,
-                       sub_out, sub_bound, params, out, bound);
+                       sub_out, sub_bound, phase, params, out, bound);
     return (int)hipGetLastError();
 }
 

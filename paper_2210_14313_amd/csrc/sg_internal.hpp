@@ -255,9 +255,12 @@ struct BlockProb {
     int32_t d;              // integrand's dimension
     int32_t block_dims;     // coordinates per block (the last block may hold fewer)
 };
-int launch_block_gather(const BlockSub* subs, int nsub, const double* params, double* sub_params, void* stream);
+// phase: two doubles per block sub-problem, written by the gather for
+// oscillatory blocks (theta_b and sum |a_t| / 2) and read by the combine.
+int launch_block_gather(const BlockSub* subs, int nsub, const double* params, double* sub_params, double* phase,
+                        void* stream);
 int launch_block_combine(const BlockProb* probs, int n, const double* sub_out, const double* sub_bound,
-                         const double* params, double* out, double* bound, void* stream);
+                         const double* phase, const double* params, double* out, double* bound, void* stream);
 
 // Record tables (FP64 and FP32 pools) of one (rule, K) in the static layout.
 bool build_records(const DeltaTable& t, std::vector<double>& rec64, std::vector<float>& rec32,
