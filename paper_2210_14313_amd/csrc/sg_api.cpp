@@ -1279,7 +1279,7 @@ static sg_status blocked_execute(sg_plan* p, const double* params_dev, double* o
 {
     BlockedPart& B = *p->blocked;
     return graph_or_direct(p, params_dev, out_dev, bound_dev, stream, [&](void* st) {
-        int rc = launch_block_gather(B.d_subs, B.nsub, params_dev, B.d_params, B.d_phase, st);
+        int rc = launch_block_gather(B.d_subs, B.nsub, B.m, params_dev, B.d_params, B.d_phase, st);
         if (rc != 0) return hip_fail(p->ctx, (hipError_t)rc, "block gather launch");
         sg_status s2 = plan_launch(B.inner, B.d_params, B.d_out, B.d_bound, st);
         if (s2 != SG_OK) return s2;
@@ -1451,7 +1451,7 @@ sg_status sg_plan_autotune(sg_plan* p, const double* params_dev, double* out_dev
     if (!p || !params_dev || !out_dev) return SG_ERR_INVALID_ARGUMENT;
     if (p->blocked) {
         BlockedPart& B = *p->blocked;
-        const int rc = launch_block_gather(B.d_subs, B.nsub, params_dev, B.d_params, B.d_phase, stream);
+        const int rc = launch_block_gather(B.d_subs, B.nsub, B.m, params_dev, B.d_params, B.d_phase, stream);
         if (rc != 0) return hip_fail(p->ctx, (hipError_t)rc, "block gather launch");
         sg_status st = sg_plan_autotune(B.inner, B.d_params, B.d_out, stream);
         blocked_sync_info(p, false);

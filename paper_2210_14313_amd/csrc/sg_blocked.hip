@@ -26,39 +26,47 @@
 namespace sg {
 namespace blk {
 
-// kGatherLanes lanes per block: lane j copies the block's coordinates j,
-// j + kGatherLanes, ..., so each block's parameters move as contiguous runs
-// (one thread per block made every lane of a wave walk its own strided
-// run).
-constexpr int kGatherLanes = 16;
+// `lanes` lanes per block (a power of two, 4..64): lane j copies the block's
+// coordinates j, j + lanes, ..., so each block's parameters move as
+// contiguous runs (one thread per block made every lane of a wave walk its
+// own strided run), and a group of lanes never straddles a wave.  The
+// launcher takes the smallest power of two covering a third of the block
+// size: a few independent loads per lane, and few enough waves that they
+// are all resident at once.
+int gather_lanes(int block_dims)
+{
+    int l = 4;
+    while (l < 64 && 3 * l < block_dims) l *= 2;
+    return l;
+}
 
-__global__ void __launch_bounds__(256) k_block_gather(const BlockSub* __restrict__ subs, int nsub,
+__global__ void __launch_bounds__(256) k_block_gather(const BlockSub* __restrict__ subs, int nsub, int lanes,
                                                       const double* __restrict__ params,
                                                       double* __restrict__ sub_params,
                                                       double* __restrict__ phase)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t s = g / kGatherLanes;
-    const int j0 = (int)(g % kGatherLanes);
+    const int64_t s = g / lanes;
+    const int j0 = (int)(g % lanes);
     if (s >= nsub) return;
     const BlockSub b = subs[s];
     const double* src = params + b.src_off;
     double* dst = sub_params + b.dst_off;
     if (b.family == SG_FAMILY_OSCILLATORY) {
         double th = 0.0, ab = 0.0;
-        for (int j = j0; j < b.len; j += kGatherLanes) {
+        for (int j = j0; j < b.len; j += lanes) {
             const double a = src[1 + b.start + j];
             dst[1 + j] = a;
             th += a;
             ab += fabs(a);
         }
         // the block's centre phase theta_b = sum a_t / 2 and sum |a_t| / 2 by
-        // a fixed tree over the block's lanes (a group of kGatherLanes lanes
+        // a fixed tree over the block's lanes (a group of `lanes` lanes
         // shares one sub-problem, so the whole group takes this branch); the
         // sweep runs at the w cancelling theta_b, the combine rotates by it
-        for (int o = kGatherLanes / 2; o >= 1; o >>= 1) {
-            th += __shfl_xor(th, o, kGatherLanes);
-            ab += __shfl_xor(ab, o, kGatherLanes);
+        for (int o = lanes / 2; o >= 1; o >>= 1) {
+            th += __shfl_xor(th, o, lanes);
+            ab += __shfl_xor(ab, o, lanes);
         }
         if (j0 == 0) {
             th *= 0.5;
@@ -68,24 +76,24 @@ __global__ void __launch_bounds__(256) k_block_gather(const BlockSub* __restrict
         }
     } else if (b.family == SG_FAMILY_OSCILLATORY_QUADRATIC) {
         if (j0 == 0) dst[0] = b.part == 2 ? -0.25 : 0.0;
-        for (int j = j0; j < b.len; j += kGatherLanes) {
+        for (int j = j0; j < b.len; j += lanes) {
             dst[1 + j] = src[1 + b.start + j];
             dst[1 + b.len + j] = src[1 + b.d + b.start + j];
         }
     } else if (b.family == SG_FAMILY_OSCILLATORY_QUADRATIC_LINEAR) {
         if (j0 == 0) dst[0] = b.part == 2 ? -0.25 : 0.0;
-        for (int j = j0; j < b.len; j += kGatherLanes) {
+        for (int j = j0; j < b.len; j += lanes) {
             dst[1 + j] = src[1 + b.start + j];
             dst[1 + b.len + j] = src[1 + b.d + b.start + j];
             dst[1 + 2 * b.len + j] = src[1 + 2 * b.d + b.start + j];
         }
     } else if (b.family == SG_FAMILY_PRODUCT_PEAK || b.family == SG_FAMILY_GAUSSIAN) {
-        for (int j = j0; j < b.len; j += kGatherLanes) {
+        for (int j = j0; j < b.len; j += lanes) {
             dst[j] = src[b.start + j];
             dst[b.len + j] = src[b.d + b.start + j];
         }
     } else {
-        for (int j = j0; j < b.len; j += kGatherLanes) dst[j] = src[b.start + j];
+        for (int j = j0; j < b.len; j += lanes) dst[j] = src[b.start + j];
     }
 }
 
@@ -213,13 +221,14 @@ __global__ void __launch_bounds__(256) k_block_combine(const BlockProb* __restri
 
 }  // namespace blk
 
-int launch_block_gather(const BlockSub* subs, int nsub, const double* params, double* sub_params, double* phase,
-                        void* stream)
+int launch_block_gather(const BlockSub* subs, int nsub, int block_dims, const double* params, double* sub_params,
+                        double* phase, void* stream)
 {
     if (nsub <= 0) return 0;
-    const int64_t threads = (int64_t)nsub * blk::kGatherLanes;
+    const int lanes = blk::gather_lanes(block_dims);
+    const int64_t threads = (int64_t)nsub * lanes;
     hipLaunchKernelGGL(blk::k_block_gather, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
-                       (hipStream_t)stream, subs, nsub, params, sub_params, phase);
+                       (hipStream_t)stream, subs, nsub, lanes, params, sub_params, phase);
     return (int)hipGetLastError();
 }
 

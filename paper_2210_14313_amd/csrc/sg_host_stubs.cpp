@@ -192,7 +192,7 @@ int launch_unrank(int, int, uint64_t, uint64_t, int, const uint64_t*, int, int32
 const char* device_error_string(int) { return "host-only build"; }
 int launch_one(int, int, int, int, int, int, const double*, double*, double*, double*, void*) { return launched(); }
 int launch_points(int, const PointsLaunch&, void*) { return launched(); }
-int launch_block_gather(const BlockSub*, int, const double*, double*, double*, void*) { return launched(); }
+int launch_block_gather(const BlockSub*, int, int, const double*, double*, double*, void*) { return launched(); }
 int launch_block_combine(const BlockProb*, int, const double*, const double*, const double*, const double*, double*, double*, void*)
 {
     return launched();

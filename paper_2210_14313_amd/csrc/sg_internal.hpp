@@ -257,8 +257,8 @@ struct BlockProb {
 };
 // phase: two doubles per block sub-problem, written by the gather for
 // oscillatory blocks (theta_b and sum |a_t| / 2) and read by the combine.
-int launch_block_gather(const BlockSub* subs, int nsub, const double* params, double* sub_params, double* phase,
-                        void* stream);
+int launch_block_gather(const BlockSub* subs, int nsub, int block_dims, const double* params, double* sub_params,
+                        double* phase, void* stream);
 int launch_block_combine(const BlockProb* probs, int n, const double* sub_out, const double* sub_bound,
                          const double* phase, const double* params, double* out, double* bound, void* stream);
 
