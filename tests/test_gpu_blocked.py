@@ -195,3 +195,25 @@ def test_blocked_rejections(torch_dev):
         assert e.value.status == 2
     finally:
         plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32e"])
+def test_oscillatory_blocks_with_large_phases(torch_dev, orc, prec):
+    # oscillatory blocks are swept once with their centre phase cancelled
+    # and rotated back in the combine: phases theta_b = sum a_t / 2 of up to
+    # about 10 rad, coefficients beyond |a| = 2 (the sweep's table-driven
+    # path), and a ragged last block (d = 23, 30 in blocks of 7)
+    from paper_2210_14313_amd import workloads as W
+    rng = np.random.default_rng(707)
+    parts = []
+    for d, rule in ((23, "cc"), (30, "gl"), (23, "tr"), (30, "gp")):
+        prm = np.concatenate([[rng.uniform(0.0, 1.0)], rng.uniform(-3.0, 3.0, d)])
+        parts.append(W.single(d, d + 3, rule, "oscillatory", prm))
+    b = W.concat(parts)
+    say("case blocked oscillatory large phases", prec)
+    ref = _blocked_ref(b, 7, "factorised")
+    got, bnd, _ = _run(b, prec, 7)
+    assert np.all(np.abs(got - ref) <= bnd), np.abs(got - ref) / bnd
+    if prec == "fp64":
+        err = np.abs(got - ref) / _scale(b, ref, 7)
+        assert np.max(err) <= 1e-12, err
