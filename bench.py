@@ -48,6 +48,15 @@ MEASURED_TRAFFIC = {
     ("fp32c", "42138974188eff10"): 8257726.0,
 }
 
+# SQ_ACTIVE_INST_VALU of one forward launch on the same batch (quad-cycles
+# summed over the SIMDs, median dispatch of a rocprofv3 --pmc pass), keyed
+# like MEASURED_TRAFFIC.  With this run's launch time it gives the fraction
+# of the launch's SIMD cycles that issue VALU work (4 cycles per
+# quad-cycle, 4 SIMDs per compute unit, the 2.4 GHz engine clock).
+MEASURED_VALU_ACTIVE = {
+    ("fp32c", "42138974188eff10"): 2824990.0,
+}
+
 
 # The headline plan's schedule, pinned so that the headline and its
 # rocprofv3 profile run the same launch shape: the balanced schedule with two
@@ -77,6 +86,12 @@ def kernel_source_hash() -> str:
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def torch_device_cu_count() -> int:
+    """Compute units of the current device."""
+    import torch
+    return int(torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count)
 
 
 def copy_probe(mb: int) -> None:
@@ -810,8 +825,12 @@ def main():
     ceil = ceilings()
     roof = serial_issue_roofline(counts, ceil, main_run["kernel_ms"] / 1e3)
     roof_pub = serial_issue_roofline(counts, PUBLISHED_PEAKS, main_run["kernel_ms"] / 1e3)
+    valu_active = MEASURED_VALU_ACTIVE.get((args.precision, kernel_source_hash())) if args.n == 4096 else None
+    n_simd = 4 * torch_device_cu_count()
     roof.update({
         "traffic": MEASURED_TRAFFIC.get((args.precision, kernel_source_hash())) if args.n == 4096 else None,
+        "valu_busy_frac": (valu_active * 4.0 / n_simd / (main_run["kernel_ms"] * 1e-3 * 2.4e9)
+                           if valu_active is not None else None),
         "model": "serial issue over operation classes, ceilings measured on this device",
         "counts": counts,
         "ceilings": {k: v for k, v in ceil.items() if k != "probe"},
