@@ -165,11 +165,12 @@ __global__ void __launch_bounds__(256) k_block_combine(const BlockProb* __restri
             if (osc_lin) {
                 // v_b = e^{i theta_c} q with q the phase-cancelled sweep's value
                 // and theta_c the gather's sum.  Against the exact block value
-                // e^{i theta} S_b: theta_c's rounding (a summation tree of len
-                // terms, <= (len + 2) u A, A = sum |a_t| / 2), sincos and the two
-                // products (<= 8 u |q|), q's own bound e_b (relative to
-                // cos(delta) S_b, delta = 2 pi w_b + theta the phase the
-                // cancellation leaves, |delta| <= dmax), and
+                // e^{i theta} S_b: q's own bound e_b (relative to cos(delta) S_b,
+                // delta = 2 pi w_b + theta the phase the cancellation leaves,
+                // |delta| <= dmax; rotated by the computed sincos, |.| <= 1 + 2u),
+                // sincos and the two products (<= 8 u |q|), theta_c's rounding
+                // (a summation tree of len terms, <= dth = (len + 2) u A,
+                // A = sum |a_t| / 2) times |S_b| <= (|q| + e_b) / cos delta, and
                 // |S_b| (1 - cos delta) <= dmax^2 (|q| + e_b).
                 const int s = p.first_sub + b;
                 const int start = b * p.block_dims, len = min(p.block_dims, p.d - start);
@@ -182,7 +183,7 @@ __global__ void __launch_bounds__(256) k_block_combine(const BlockProb* __restri
                 x.P = fabs(q) * (1.0 + 4.0 * u);
                 const double dth = (double)(len + 2) * u * (ab + 1.0);
                 const double dmax = 2.0 * (double)(len + 8) * u * (ab + 1.0);
-                x.D = e * (1.0 + 4.0 * u) + fabs(q) * (dth + 8.0 * u) + dmax * dmax * (fabs(q) + e);
+                x.D = e * (1.0 + 4.0 * u) + fabs(q) * 8.0 * u + (dth + dmax * dmax) * (fabs(q) + e);
             } else if (osc) {
                 const int s = p.first_sub + 2 * b;
                 x.re = sub_out[s];
