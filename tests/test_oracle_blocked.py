@@ -139,3 +139,30 @@ def test_paper_table_5_2_errors_grow_with_the_number_of_blocks(orc):
         assert abs(errs[d] - abs((1 - eta) ** k - 1)) <= 1e-9 * errs[d]     # k equal blocks multiply
         slack = comb(k, 2) * eta ** 2 * 1.01 + k * abs(eta - printed[10]) + 0.5e-4 * p
         assert abs(errs[d] - p) <= slack, (d, errs[d], p, slack)
+
+
+@pytest.mark.parametrize("rule", ["cc", "gl", "tr", "gp"])
+def test_oscillatory_rule_is_a_rotation_of_its_phase_cancelled_value(rule):
+    """For cos(2 pi w + sum a_i x_i) the rule's value is linear in e^{2 pi i w}:
+    with theta = sum a_i / 2 and S its value at w = -theta / 2 pi, the values
+    at w = 0 and w = -1/4 are cos(theta) S and sin(theta) S (the rule is
+    symmetric about the centre, so its sum of e^{i a (x - 1/2)} is real).  The
+    block variant sweeps an oscillatory block once at that w and rotates the
+    result; this pins the identity on the oracle's point-by-point sum."""
+    import oracle
+    rng = np.random.default_rng(23 + len(rule))
+    for d, K in ((1, 3), (4, 2), (6, 3)):
+        a = rng.uniform(-3.0, 3.0, d)
+        th = 0.5 * float(np.sum(a))
+
+        def val(w):
+            return oracle.smolyak_points(d, d + K, rule, "oscillatory", np.concatenate([[w], a]))
+
+        r_s, r_re, r_im = val(-th / (2.0 * np.pi)), val(0.0), val(-0.25)
+        s = r_s["q"]
+        # each sum's rounding (a small multiple of 2^-64 (A + |f(c)|)), the
+        # rounding of w = -theta / 2 pi and of cos, sin and the products
+        tol = sum(2.0 ** -56 * (r["A"] + abs(r["fc"])) for r in (r_s, r_re, r_im)) + 1e-15 * abs(s) * (1.0 + abs(th))
+        assert abs(s) > 1e-3
+        assert abs(r_re["q"] - np.cos(th) * s) <= tol, (rule, d, K, r_re["q"], np.cos(th) * s, tol)
+        assert abs(r_im["q"] - np.sin(th) * s) <= tol, (rule, d, K, r_im["q"], np.sin(th) * s, tol)
