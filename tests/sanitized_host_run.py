@@ -241,6 +241,10 @@ def plans(L, ctx, statuses):
                 info = PlanInfo()
                 L.sg_plan_get_info(plan, ctypes.byref(info))
                 statuses.append(["fp64_complex", info.fp64_complex, sum(1 for p in probs if p[3] in (5, 6))])
+                # block sub-problems: one per block (two for the complex-sweep
+                # families), so the units are sum d, or 2 d for those
+                statuses.append(["blocked_units", int(info.units),
+                                 sum(p[0] * (2 if p[3] in (5, 6) else 1) for p in probs)])
                 L.sg_plan_destroy(plan)
     # rejected plans
     for bad in [[(0, 1, 2, 0, 0)], [(3, 2, 2, 0, 0)], [(3, 5, 9, 0, 0)], [(3, 5, 2, 9, 0)], [(3, 12, 2, 0, 0)],

@@ -135,6 +135,9 @@ def test_plan_paths_statuses(run_result):
     assert len(by["fp64_complex"]) == 7
     assert all(got == want for _, got, want in by["fp64_complex"])
     assert any(want > 0 for _, got, want in by["fp64_complex"])
+    # block plans sweep an oscillatory block once (its phase cancelled), a
+    # complex-sweep block twice
+    assert by["blocked_units"] and all(got == want for _, got, want in by["blocked_units"])
     assert run_result["live"] == 0
 
 
